@@ -1,0 +1,122 @@
+/*
+ * orc.h -- CPU oracle for round-synchronous 2D constrained Delaunay refinement.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct reference that the GPU path is compared against.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product library never links, includes or calls anything here.
+ *
+ * What it computes (Chen, Tan, Ong, "On Designing GPU Algorithms with
+ * Applications to Mesh Refinement"):
+ *   - Line 1 of Algorithm 1 (gDP2d): the constrained Delaunay triangulation of
+ *     the input PSLG (Section 4, definitions of PSLG / subsegment / CDT).
+ *     Cocircular ties are broken by a symbolic perturbation of the lifting
+ *     map, so the CDT is unique and canonical.
+ *   - Lines 2-9 of Algorithm 1 as a deterministic round: collect encroached
+ *     subsegments and bad triangles, compute midpoints / circumcenters,
+ *     prioritize and locate by walking (midpoint replacement when a subsegment
+ *     blocks the walk), grow Bowyer-Watson cavities, resolve overlaps by
+ *     priority marks and the Delaunay-dependency test of Section 5 (gQM3d
+ *     insertion), and insert the winners.
+ * Every arithmetic step is plain: exact signs come from multi-precision
+ * integers, the floating-point formulas are evaluated in one fixed order
+ * (build with -ffp-contract=off).
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0,
+  ORC_E_ARG = -1,
+  ORC_E_INPUT = -2,
+  ORC_E_NOMEM = -3,
+  ORC_E_NOTERM = -5, /* round cap reached with work left; mesh is valid */
+  ORC_E_STALL = -6,  /* a round had candidates but inserted nothing */
+  ORC_E_WALK = -8    /* a locate walk exceeded its step cap */
+};
+
+/* Vertex kinds. */
+enum { ORC_VK_INPUT = 0, ORC_VK_MIDPOINT = 1, ORC_VK_CIRCUMCENTER = 2 };
+
+typedef struct orc_mesh {
+  int32_t nV, nT, nS;          /* live counts */
+  int32_t n_input_v, n_input_s;
+  int32_t capV, capT, capS;
+  int32_t rounds;              /* rounds executed so far */
+  double *x, *y;               /* [capV] */
+  int32_t *vkind;              /* [capV] */
+  int32_t *tv, *tn, *ts;       /* [3*capT]: vertices (CCW), neighbour across edge i,
+                                  subsegment id on edge i (-1 none); edge i = (tv[i], tv[i+1]) */
+  int32_t *sv;                 /* [2*capS]: subsegment endpoints (sv0, sv1) */
+  int32_t *sparent;            /* [capS]: input segment id */
+  uint8_t *spend;              /* [capS]: pending-split flag carried to the next round */
+} orc_mesh;
+
+typedef struct orc_params {
+  int32_t cand_cap_K;     /* 0 = unlimited; else keep the K largest keys per round */
+  int32_t priority_mode;  /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
+  int32_t max_rounds;     /* stop after this many rounds (ORC_E_NOTERM if work left) */
+  int32_t prefilter_f1;   /* must be 0 (not implemented in the oracle yet) */
+  int32_t cavity_approx_n;/* must be 0 (not implemented in the oracle yet) */
+} orc_params;
+
+typedef struct orc_round_stats {
+  int64_t n_enc, n_bad, n_kept_mid, n_kept_cc;
+  int64_t n_blocked, n_coincident, n_enc_reject, n_mid_cand, n_unsplittable;
+  int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
+  int64_t cav_tri_total, cav_max, walk_steps;
+} orc_round_stats;
+
+/* Builds the canonical CDT of the PSLG.  xy: 2*nv doubles; seg: 2*ns vertex ids.
+   On error returns ORC_E_INPUT / ORC_E_ARG and writes a message to err. */
+int orc_cdt_build(int32_t nv, const double *xy, int32_t ns, const int32_t *seg,
+                  orc_mesh **out, char *err, int32_t errlen);
+
+/* Runs refinement rounds in place.  stats (optional) receives one record per
+   executed round, up to stats_cap records; *n_stats gets the count. */
+int orc_refine(orc_mesh *m, double ratio_bound_sq, const orc_params *p,
+               orc_round_stats *stats, int32_t stats_cap, int32_t *n_stats,
+               char *err, int32_t errlen);
+
+orc_mesh *orc_mesh_clone(const orc_mesh *m);
+void orc_mesh_free(orc_mesh *m);
+
+/* Exact predicates on FP64 points (p = {x, y}); return -1, 0 or +1. */
+int orc_orient2d(const double *a, const double *b, const double *c);
+int orc_incircle(const double *a, const double *b, const double *c, const double *d);
+int orc_indiametral(const double *a, const double *b, const double *c);
+/* incircle with the symbolic-perturbation tie-break (vertex ids ia..id). */
+int orc_incircle_sos(const double *a, const double *b, const double *c, const double *d,
+                     int32_t ia, int32_t ib, int32_t ic, int32_t id);
+/* Counts of exact (multi-precision) evaluations since load. */
+void orc_exact_counts(int64_t *orient, int64_t *incircle, int64_t *indiam);
+
+/* Fixed-order FP64 formulas (refinement Line 5 / Line 6). */
+uint32_t orc_perm32(uint32_t x);
+void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq,
+                      double *px, double *py, int32_t *bad, uint64_t *key,
+                      int32_t priority_mode);
+void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t *key,
+                  int32_t priority_mode);
+
+/* Checkers.  Each returns the number of violations found. */
+int64_t orc_check_topology(const orc_mesh *m, char *err, int32_t errlen);
+int64_t orc_check_local_delaunay(const orc_mesh *m);
+int64_t orc_check_quality(const orc_mesh *m, double ratio_bound_sq);
+int64_t orc_check_encroached(const orc_mesh *m);
+int64_t orc_check_cdt_bruteforce(const orc_mesh *m);
+int64_t orc_check_subsegments(const orc_mesh *m, const double *in_xy, const int32_t *in_seg,
+                              char *err, int32_t errlen);
+double orc_area_sum(const orc_mesh *m);
+int32_t orc_hull_vertex_count(const orc_mesh *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,17 @@
+"""Seeded synthetic PSLG generators shared by the oracle tests and the GPU path.
+
+This package holds input generation only: point sets, constraint segments and
+the quality bound. It performs none of the refinement arithmetic.
+"""
+from .generators import (  # noqa: F401
+    PSLG,
+    bare_square,
+    config0,
+    config1,
+    config2,
+    scaled_config1,
+    scaled_config2,
+    near_edge_point,
+    random_small,
+    manifest_hash,
+)
