@@ -477,8 +477,8 @@ int orc_cdt_build(int32_t nv, const double *xy, int32_t ns, const int32_t *seg,
   if (nv < 3 || !xy || ns < 0 || (ns > 0 && !seg)) { seterr(&C, "bad arguments"); return ORC_E_ARG; }
   for (int64_t i = 0; i < 2 * (int64_t)nv; i++) {
     double a = fabs(xy[i]);
-    if (!isfinite(xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-240)) {
-      seterr(&C, "coordinate not finite or outside [2^-240, 2^20] in magnitude");
+    if (!isfinite(xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100)) {
+      seterr(&C, "coordinate not finite, or nonzero with magnitude outside [2^-100, 2^20]");
       return ORC_E_INPUT;
     }
   }
