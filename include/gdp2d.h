@@ -1,0 +1,175 @@
+/*
+ * gdp2d.h -- C ABI of the gfx950 (MI355X) 2D constrained Delaunay refinement
+ * library.
+ *
+ * What it computes (Chen, Tan, Ong, "On Designing GPU Algorithms with
+ * Applications to Mesh Refinement", Section 4, Algorithm 1 gDP2d):
+ *   input  : a planar straight-line graph (PSLG) -- vertices P and
+ *            non-crossing segments E -- and a quality bound;
+ *   output : a constrained Delaunay triangulation of the convex hull of P in
+ *            which every segment is a union of subsegments, no triangle has a
+ *            radius-edge ratio above B (the ratio of Section 5.1, used here in
+ *            2D) and no subsegment is encroached in Ruppert's sense
+ *            (Section 4.2), plus the Steiner vertices that were added.
+ * Line 1 (the initial CDT) runs on the host; Lines 2-9 run as a sequence of
+ * deterministic rounds of HIP kernels on one GPU, where each round collects
+ * encroached subsegments and bad triangles, computes midpoints and
+ * circumcenters, locates them by walking, grows Bowyer-Watson cavities,
+ * resolves overlapping cavities with 64-bit priority marks (atomicMax) and a
+ * Delaunay-dependency test, and inserts the winners.
+ *
+ * Conventions for every call:
+ *   - every function returns gdp_status (GDP_OK == 0; errors are negative);
+ *     no exception or signal crosses the boundary;
+ *   - after an error, gdp_last_error(ctx) describes it; output handles are
+ *     set to NULL;
+ *   - host arrays passed in are read during the call only (copied); the
+ *     caller keeps ownership;
+ *   - a gdp_mesh is owned by the library and lives in device memory until
+ *     gdp_mesh_free;
+ *   - one context is used by one host thread at a time (calls on the same
+ *     context do not run concurrently);
+ *   - vertex ids: input vertices keep their ids 0..n-1; Steiner vertices
+ *     follow in insertion order; triangle vertices are counter-clockwise;
+ *     edge i of triangle t joins vertex i and vertex (i+1) mod 3.
+ */
+#ifndef GDP2D_H
+#define GDP2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GDP_OK = 0,
+  GDP_E_ARG = -1,     /* invalid argument (NULL pointer, bad size, bad parameter) */
+  GDP_E_INPUT = -2,   /* invalid PSLG: non-finite / out-of-range coordinate, duplicate
+                         point, bad or repeated segment, crossing segments, a vertex in
+                         a segment's interior, a hull edge that is not a segment */
+  GDP_E_NOMEM = -3,   /* host or device allocation failed */
+  GDP_E_DEVICE = -4,  /* a HIP call failed */
+  GDP_E_NOTERM = -5,  /* max_rounds reached with work left; the mesh stays valid */
+  GDP_E_STALL = -6,   /* a round had candidates but inserted nothing */
+  GDP_E_BUSY = -7,    /* reserved */
+  GDP_E_WALK = -8,    /* a point-location walk exceeded its step cap */
+  GDP_E_CAVITY = -9   /* a cavity exceeded the cooperative-path capacity */
+} gdp_status;
+
+typedef struct gdp_ctx gdp_ctx;
+typedef struct gdp_mesh gdp_mesh;
+
+/* A PSLG: xy holds 2*n_vertices doubles (x0, y0, x1, y1, ...); seg holds
+   2*n_segments vertex ids.  Every nonzero coordinate must have magnitude in
+   [2^-100, 2^20].  The convex hull boundary must be covered by segments. */
+typedef struct {
+  int32_t n_vertices;
+  const double *xy;
+  int32_t n_segments;
+  const int32_t *seg;
+} gdp_pslg;
+
+/* Refinement parameters.  The first group changes the mesh (semantic); the
+   second only changes speed (every value gives a bit-identical mesh). */
+typedef struct {
+  /* semantic */
+  int32_t cand_cap_K;       /* 0 = unlimited; else keep the K largest priorities per
+                               round (Rule 2 filter as a candidate limit) */
+  int32_t priority_mode;    /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
+  int32_t max_rounds;       /* 0 = no cap; else stop with GDP_E_NOTERM */
+  int32_t prefilter_f1;     /* must be 0 */
+  int32_t cavity_approx_n;  /* must be 0 */
+  /* perf only */
+  int32_t block_size;       /* threads per workgroup for the per-element kernels
+                               (64..1024, multiple of 64; 0 = default 256) */
+  int32_t reserved[6];
+} gdp_params;
+
+typedef struct {
+  int32_t n_vertices, n_triangles, n_subsegments;
+  int32_t n_input_vertices, n_input_segments;
+  int32_t rounds;
+} gdp_mesh_info;
+
+/* Per-round counters (device-side counts copied back after every round). */
+typedef struct {
+  int64_t n_enc, n_bad, n_kept_mid, n_kept_cc;
+  int64_t n_blocked, n_coincident, n_enc_reject, n_mid_cand, n_unsplittable;
+  int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
+  int64_t cav_tri_total, cav_max, n_big_cavities;
+} gdp_round_stats;
+
+/* Fills *p with the defaults (all zero, block_size 256). */
+void gdp_params_default(gdp_params *p);
+
+/* Creates a context on HIP device `device`, issuing work on `hip_stream`
+   (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL means
+   the default stream).  The stream must outlive the context. */
+gdp_status gdp_ctx_create(int device, void *hip_stream, gdp_ctx **out);
+void gdp_ctx_destroy(gdp_ctx *ctx);
+const char *gdp_last_error(const gdp_ctx *ctx);
+const char *gdp_status_str(gdp_status s);
+
+/* Line 1 of Algorithm 1 on the host: builds the canonical constrained
+   Delaunay triangulation of *pslg (cocircular ties broken by a symbolic
+   perturbation in which a smaller vertex id dominates; triangles rotated so
+   the smallest id comes first and sorted lexicographically) and uploads it
+   to the device.  Subsegment k of the result is input segment k. */
+gdp_status gdp_mesh_create(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out);
+
+/* Same CDT, host only (no device needed).  Writes the counts to *n_tri and,
+   when the pointers are non-NULL and cap_tri >= *n_tri, tri/nbr/seg
+   (3 * n_tri int32 each: vertices, neighbour across edge i or -1, segment id
+   on edge i or -1).  Call once with cap_tri = 0 to size the buffers. */
+gdp_status gdp_cdt_host(const gdp_pslg *pslg, int32_t *n_tri, int32_t cap_tri, int32_t *tri,
+                        int32_t *nbr, int32_t *seg, char *err, int32_t err_len);
+
+/* Uploads a mesh given as arrays (e.g. a state saved at a round boundary):
+   xy[2V], vkind[V], tri/nbr/sub_on_edge[3T], sub_v[2S], sub_parent[S],
+   sub_pending[S] (0/1), plus the counts and the round number.  Shapes and
+   index ranges are checked; geometry is not. */
+gdp_status gdp_mesh_upload(gdp_ctx *ctx, int32_t n_v, int32_t n_input_v, const double *xy,
+                           const int32_t *vkind, int32_t n_t, const int32_t *tri,
+                           const int32_t *nbr, const int32_t *sub_on_edge, int32_t n_s,
+                           int32_t n_input_s, const int32_t *sub_v, const int32_t *sub_parent,
+                           const uint8_t *sub_pending, int32_t rounds, gdp_mesh **out);
+
+/* Lines 2-9 of Algorithm 1 on the GPU, in place, until no encroached
+   subsegment or bad triangle remains.  ratio_bound_sq is B^2 passed exactly
+   (B = sqrt(2) -> 2.0): a triangle is bad when its FP64 circumradius^2
+   exceeds ratio_bound_sq times its shortest edge^2.  Blocks until done. */
+gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq,
+                           const gdp_params *params);
+
+/* gdp_mesh_create followed by gdp_mesh_refine. */
+gdp_status gdp_refine(gdp_ctx *ctx, const gdp_pslg *pslg, double ratio_bound_sq,
+                      const gdp_params *params, gdp_mesh **out);
+
+gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info);
+
+/* Copies the mesh to caller buffers sized from gdp_mesh_info_get (any pointer
+   may be NULL to skip that array): xy[2V], vkind[V] (0 input, 1 midpoint,
+   2 circumcenter), tri/nbr/sub_on_edge[3T], sub_v[2S], sub_parent[S] (input
+   segment of each subsegment), sub_pending[S]. */
+gdp_status gdp_mesh_download(gdp_ctx *ctx, const gdp_mesh *mesh, double *xy, int32_t *vkind,
+                             int32_t *tri, int32_t *nbr, int32_t *sub_on_edge, int32_t *sub_v,
+                             int32_t *sub_parent, uint8_t *sub_pending);
+
+/* Copies up to cap per-round records of the last gdp_mesh_refine; *n gets
+   the number of rounds recorded. */
+gdp_status gdp_mesh_round_stats(const gdp_mesh *mesh, gdp_round_stats *stats, int32_t cap,
+                                int32_t *n);
+
+/* Device-resident refinement timing of the last gdp_mesh_refine:
+   *ms = wall time between HIP events recorded before the first and after the
+   last round on the context stream. */
+gdp_status gdp_mesh_last_refine_ms(const gdp_mesh *mesh, double *ms);
+
+void gdp_mesh_free(gdp_mesh *mesh);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,43 @@
+"""Builds the gfx950 shared library libgdp2d.so in place.
+
+    python -m paper_2007_00324_amd.build
+
+One hipcc invocation compiles the kernels, the host driver and the host
+CDT builder.  FP64 formulas must round in the written order, so floating
+point contraction is off; packed FP32 instructions are disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libgdp2d.so")
+SOURCES = ["gdp_kernels.hip", "gdp_api.hip", "gdp_host_cdt.cpp"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("GDP_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc_cmd(out: str) -> list[str]:
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-ffp-contract=off", "-fno-fast-math",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+           "-I", os.path.join(HERE, "..", "include"), "-o", out]
+    return cmd + [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = hipcc_cmd(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

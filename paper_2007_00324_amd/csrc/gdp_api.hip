@@ -1,0 +1,743 @@
+// gdp_api.hip -- C ABI (include/gdp2d.h): contexts, meshes in device memory
+// and the host loop that issues one refinement round after another
+// (Algorithm 1, "repeat ... until L is empty").
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gdp_kernels.h"
+
+using namespace gdp;
+
+struct gdp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+struct gdp_mesh {
+  gdp_ctx *ctx = nullptr;
+  DevMesh m;
+  DevCounters *d_cnt = nullptr;
+  DevCounters *h_cnt = nullptr;  // pinned
+  uint64_t *mark = nullptr;
+  int32_t *sadj = nullptr;
+  uint32_t *mflag = nullptr;
+  CandSet cc{}, mid{};
+  uint32_t *w0_t = nullptr, *w0_s = nullptr, *win_t = nullptr, *win_s = nullptr;
+  int32_t *rank_t = nullptr, *rank_s = nullptr;
+  int32_t *win_ref = nullptr, *fbase = nullptr, *fcount = nullptr, *fan_off = nullptr;
+  int32_t *repl = nullptr;
+  int32_t *pool = nullptr;
+  int32_t pool_cap = 0;
+  FanRec *fan = nullptr;
+  int32_t fan_cap = 0;
+  int32_t *big = nullptr;
+  uint64_t *keys = nullptr;
+  int32_t *hist = nullptr;
+  uint64_t *thresh = nullptr;
+  int32_t *tiles = nullptr;
+  int32_t tiles_cap = 0;
+  int32_t *h_small = nullptr;  // pinned scratch for small reads
+  int32_t wT = 0, wS = 0;      // workspace capacities (triangles, subsegments)
+  std::vector<gdp_round_stats> stats;
+  double last_ms = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_noctx_err;
+
+gdp_status fail(gdp_ctx *ctx, gdp_status s, const std::string &msg) {
+  if (ctx) ctx->err = msg; else g_noctx_err = msg;
+  return s;
+}
+
+#define HIPCHECK(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, GDP_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_));   \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, sizeof(T) * std::max<size_t>(n, 1));
+}
+
+// Grows a device array from old_n to new_n elements, keeping the first keep_n
+// elements and filling the new tail with `fill` bytes.
+template <class T>
+hipError_t dgrow(T **p, size_t old_n, size_t new_n, size_t keep_n, int fill, hipStream_t s) {
+  T *q = nullptr;
+  hipError_t e = hipMalloc((void **)&q, sizeof(T) * std::max<size_t>(new_n, 1));
+  if (e != hipSuccess) return e;
+  if (!*p) keep_n = 0;  // nothing to keep: initialise everything
+  if (*p && keep_n) {
+    e = hipMemcpyAsync(q, *p, sizeof(T) * keep_n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  if (new_n > keep_n) {
+    e = hipMemsetAsync(q + keep_n, fill, sizeof(T) * (new_n - keep_n), s);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (*p) (void)hipFree(*p);
+  *p = q;
+  (void)old_n;
+  return hipSuccess;
+}
+
+inline int words(int n) { return n / 32 + 1; }
+
+gdp_status grow_tri(gdp_mesh *M, int32_t need) {
+  gdp_ctx *ctx = M->ctx;
+  if (need <= M->m.capT) return GDP_OK;
+  hipStream_t s = ctx->stream;
+  int32_t oc = M->m.capT;
+  int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
+  if (nc64 > (1 << 29)) return fail(ctx, GDP_E_NOMEM, "triangle capacity limit exceeded");
+  int32_t nc = (int32_t)nc64;
+  HIPCHECK(dgrow(&M->m.tv, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->m.tn, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->m.ts, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->mark, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.elem, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.key, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.p, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.loc, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.state, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.off, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->cc.len, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->w0_t, words(oc), words(nc), words(oc), 0, s));
+  HIPCHECK(dgrow(&M->win_t, words(oc), words(nc), words(oc), 0, s));
+  HIPCHECK(dgrow(&M->rank_t, words(oc), words(nc), words(oc), 0, s));
+  HIPCHECK(dgrow(&M->repl, 4 * (size_t)oc, 4 * (size_t)nc, 0, 0xff, s));
+  M->m.capT = nc;
+  return GDP_OK;
+}
+
+gdp_status grow_seg(gdp_mesh *M, int32_t need) {
+  gdp_ctx *ctx = M->ctx;
+  if (need <= M->m.capS) return GDP_OK;
+  hipStream_t s = ctx->stream;
+  int32_t oc = M->m.capS;
+  int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
+  if (nc64 > (1 << 28)) return fail(ctx, GDP_E_NOMEM, "subsegment capacity limit exceeded");
+  int32_t nc = (int32_t)nc64;
+  HIPCHECK(dgrow(&M->m.sv, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->m.spar, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->m.spend, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->sadj, 2 * (size_t)oc, 2 * (size_t)nc, 2 * (size_t)oc, 0xff, s));
+  HIPCHECK(dgrow(&M->mflag, oc, nc, oc, 0, s));
+  size_t om = 2 * (size_t)oc, nm = 2 * (size_t)nc;  // a flagged subsegment can appear twice
+  HIPCHECK(dgrow(&M->mid.elem, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.key, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.p, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.loc, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.state, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.off, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->mid.len, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->w0_s, words(oc), words(nc), words(oc), 0, s));
+  HIPCHECK(dgrow(&M->win_s, words(oc), words(nc), words(oc), 0, s));
+  HIPCHECK(dgrow(&M->rank_s, words(oc), words(nc), words(oc), 0, s));
+  M->m.capS = nc;
+  return GDP_OK;
+}
+
+gdp_status grow_vtx(gdp_mesh *M, int32_t need) {
+  gdp_ctx *ctx = M->ctx;
+  if (need <= M->m.capV) return GDP_OK;
+  hipStream_t s = ctx->stream;
+  int32_t oc = M->m.capV;
+  int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
+  if (nc64 > (1 << 29)) return fail(ctx, GDP_E_NOMEM, "vertex capacity limit exceeded");
+  int32_t nc = (int32_t)nc64;
+  HIPCHECK(dgrow(&M->m.vxy, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->m.vkind, oc, nc, oc, 0, s));
+  M->m.capV = nc;
+  return GDP_OK;
+}
+
+// Arrays sized by the candidate count (circumcenters + midpoints).
+gdp_status grow_cand(gdp_mesh *M) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  int64_t need = (int64_t)M->m.capT + 2 * (int64_t)M->m.capS + 2;
+  if (need <= M->wT) return GDP_OK;
+  int64_t nc = std::max<int64_t>(need, (int64_t)M->wT + M->wT / 2);
+  // called between k_winners and k_record: keep what is already written
+  size_t keep = (size_t)M->wT;
+  HIPCHECK(dgrow(&M->win_ref, keep, nc, keep, 0, s));
+  HIPCHECK(dgrow(&M->fbase, keep, nc, keep, 0, s));
+  HIPCHECK(dgrow(&M->fcount, keep, nc, keep, 0, s));
+  HIPCHECK(dgrow(&M->fan_off, keep, nc, keep, 0, s));
+  HIPCHECK(dgrow(&M->big, keep, nc, keep, 0, s));
+  HIPCHECK(dgrow(&M->keys, keep, nc, keep, 0, s));
+  int64_t nt = nc / kScanTileSize + 2;
+  HIPCHECK(dgrow(&M->tiles, 0, nt, 0, 0, s));
+  M->tiles_cap = (int32_t)nt;
+  M->wT = (int32_t)nc;
+  return GDP_OK;
+}
+
+Work make_work(gdp_mesh *M, int pm) {
+  Work w;
+  w.cnt = M->d_cnt;
+  w.mark = M->mark;
+  w.sadj = M->sadj;
+  w.mflag = M->mflag;
+  w.cc = M->cc;
+  w.mid = M->mid;
+  w.w0_t = M->w0_t; w.w0_s = M->w0_s; w.win_t = M->win_t; w.win_s = M->win_s;
+  w.rank_t = M->rank_t; w.rank_s = M->rank_s;
+  w.win_ref = M->win_ref; w.fbase = M->fbase; w.fcount = M->fcount; w.fan_off = M->fan_off;
+  w.repl = M->repl;
+  w.pool = M->pool; w.pool_cap = M->pool_cap;
+  w.fan = M->fan; w.fan_cap = M->fan_cap;
+  w.big = M->big; w.big_cap = M->wT;
+  w.keys = M->keys; w.hist = M->hist; w.thresh = M->thresh;
+  w.pm = pm;
+  return w;
+}
+
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+// Exclusive scan of n entries (mode 0: counts, mode 1: popcounts of words);
+// the total is written to *d_total.
+gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int n, int32_t *d_total, int mode) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  int ntiles = (n + kScanTileSize - 1) / kScanTileSize;
+  if (ntiles < 1) ntiles = 1;
+  if (ntiles > M->tiles_cap) return fail(ctx, GDP_E_NOMEM, "scan tile buffer too small");
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, in, out, n, M->tiles, mode);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, ntiles, d_total);
+  if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, M->tiles);
+  HIPCHECK(hipGetLastError());
+  return GDP_OK;
+}
+
+gdp_status read_counters(gdp_mesh *M) {
+  gdp_ctx *ctx = M->ctx;
+  HIPCHECK(hipMemcpyAsync(M->h_cnt, M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  return GDP_OK;
+}
+
+void free_mesh_arrays(gdp_mesh *M) {
+  void *ptrs[] = {M->m.vxy, M->m.vkind, M->m.tv, M->m.tn, M->m.ts, M->m.sv, M->m.spar, M->m.spend,
+                  M->d_cnt, M->mark, M->sadj, M->mflag,
+                  M->cc.elem, M->cc.key, M->cc.p, M->cc.loc, M->cc.state, M->cc.off, M->cc.len,
+                  M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
+                  M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
+                  M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->hist, M->thresh,
+                  M->tiles};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (M->h_cnt) (void)hipHostFree(M->h_cnt);
+  if (M->h_small) (void)hipHostFree(M->h_small);
+}
+
+// Allocates a device mesh with room for the given counts and uploads it.
+gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const int32_t *vkind,
+                  int32_t nT, const int32_t *tv, const int32_t *tn, const int32_t *ts, int32_t nS,
+                  int32_t nIS, const int32_t *sv, const int32_t *spar, const uint8_t *spend,
+                  int32_t rounds, gdp_mesh **out) {
+  hipStream_t s = ctx->stream;
+  gdp_mesh *M = new gdp_mesh();
+  M->ctx = ctx;
+  auto bail = [&](gdp_status st) {
+    free_mesh_arrays(M);
+    delete M;
+    return st;
+  };
+  M->m.nV = nV; M->m.nT = nT; M->m.nS = nS;
+  M->m.n_input_v = nIV; M->m.n_input_s = nIS; M->m.rounds = rounds;
+  int32_t capV = std::max(1024, nV * 2), capT = std::max(2048, nT * 2), capS = std::max(1024, nS * 2);
+  std::vector<double2> hv(nV);
+  for (int i = 0; i < nV; i++) hv[i] = make_double2(xy[2 * i], xy[2 * i + 1]);
+  std::vector<int4> htv(nT), htn(nT), hts(nT);
+  for (int t = 0; t < nT; t++) {
+    int mask = (ts[3 * t] >= 0 ? 1 : 0) | (ts[3 * t + 1] >= 0 ? 2 : 0) | (ts[3 * t + 2] >= 0 ? 4 : 0);
+    htv[t] = make_int4(tv[3 * t], tv[3 * t + 1], tv[3 * t + 2], mask);
+    htn[t] = make_int4(tn[3 * t], tn[3 * t + 1], tn[3 * t + 2], 0);
+    hts[t] = make_int4(ts[3 * t], ts[3 * t + 1], ts[3 * t + 2], 0);
+  }
+  std::vector<int2> hsv(nS);
+  std::vector<int32_t> hsp(nS), hpend(nS);
+  for (int k = 0; k < nS; k++) {
+    hsv[k] = make_int2(sv[2 * k], sv[2 * k + 1]);
+    hsp[k] = spar[k];
+    hpend[k] = spend ? spend[k] : 0;
+  }
+  std::vector<int32_t> hk(nV, 0);
+  if (vkind) hk.assign(vkind, vkind + nV);
+  M->m.capV = 0; M->m.capT = 0; M->m.capS = 0;
+  gdp_status st;
+  if ((st = grow_vtx(M, capV)) != GDP_OK) return bail(st);
+  if ((st = grow_tri(M, capT)) != GDP_OK) return bail(st);
+  if ((st = grow_seg(M, capS)) != GDP_OK) return bail(st);
+  if ((st = grow_cand(M)) != GDP_OK) return bail(st);
+  auto chk = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess) { fail(ctx, GDP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)); return false; }
+    return true;
+  };
+  if (!chk(hipMemcpyAsync(M->m.vxy, hv.data(), sizeof(double2) * nV, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.vkind, hk.data(), sizeof(int32_t) * nV, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.tv, htv.data(), sizeof(int4) * nT, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.tn, htn.data(), sizeof(int4) * nT, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.ts, hts.data(), sizeof(int4) * nT, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.sv, hsv.data(), sizeof(int2) * nS, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.spar, hsp.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipMemcpyAsync(M->m.spend, hpend.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload"))
+    return bail(GDP_E_DEVICE);
+  if (!chk(dalloc(&M->d_cnt, 1), "alloc") || !chk(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters)), "alloc") ||
+      !chk(hipHostMalloc((void **)&M->h_small, 1024 * sizeof(int32_t)), "alloc") ||
+      !chk(dalloc(&M->hist, 256), "alloc") || !chk(dalloc(&M->thresh, 1), "alloc"))
+    return bail(GDP_E_DEVICE);
+  M->pool_cap = std::max(1 << 16, 8 * capT);
+  if (!chk(dalloc(&M->pool, M->pool_cap), "alloc")) return bail(GDP_E_DEVICE);
+  M->fan_cap = std::max(1 << 16, 2 * capT);
+  if (!chk(dalloc(&M->fan, M->fan_cap), "alloc")) return bail(GDP_E_DEVICE);
+  if (!chk(hipStreamSynchronize(s), "sync")) return bail(GDP_E_DEVICE);
+  *out = M;
+  return GDP_OK;
+}
+
+gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  const int bs = P->block_size;
+  const int pm = P->priority_mode;
+  M->stats.clear();
+  hipEvent_t ev0, ev1;
+  HIPCHECK(hipEventCreate(&ev0));
+  HIPCHECK(hipEventCreate(&ev1));
+  HIPCHECK(hipEventRecord(ev0, s));
+  gdp_status result = GDP_OK;
+  for (;;) {
+    DevMesh &m = M->m;
+    HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
+    Work w = make_work(M, pm);
+    hipLaunchKernelGGL(k_scan, dim3(grid_for(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
+    HIPCHECK(hipGetLastError());
+    gdp_status st = read_counters(M);
+    if (st) return st;
+    int ncc = M->h_cnt->ncc, nmk = M->h_cnt->nmk;
+    gdp_round_stats rs;
+    memset(&rs, 0, sizeof rs);
+    rs.n_bad = ncc;
+    rs.n_enc = nmk;
+    if (ncc == 0 && nmk == 0) break;
+    if (P->max_rounds > 0 && m.rounds >= P->max_rounds) {
+      hipLaunchKernelGGL(k_unflag, dim3(grid_for(nmk, bs)), dim3(bs), 0, s, w, nmk);
+      HIPCHECK(hipGetLastError());
+      result = fail(ctx, GDP_E_NOTERM, "round cap reached");
+      break;
+    }
+    // ---- R3: candidate cap ----
+    bool capped = P->cand_cap_K > 0 && ncc + nmk > P->cand_cap_K;
+    if (capped) {
+      int n = ncc + nmk;
+      hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(n, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm);
+      uint64_t prefix = 0, pmask = 0;
+      int64_t remaining = P->cand_cap_K;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        HIPCHECK(hipMemsetAsync(M->hist, 0, 256 * sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_radix_hist, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, s, w, n,
+                           shift, prefix, pmask);
+        HIPCHECK(hipMemcpyAsync(M->h_small, M->hist, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        int64_t cum = 0;
+        int d = 255;
+        for (; d > 0; d--) {
+          if (cum + M->h_small[d] >= remaining) break;
+          cum += M->h_small[d];
+        }
+        remaining -= cum;
+        prefix |= (uint64_t)d << shift;
+        pmask |= (uint64_t)0xff << shift;
+      }
+      HIPCHECK(hipMemcpyAsync(M->thresh, &prefix, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_apply_cap, dim3(grid_for(n, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      HIPCHECK(hipGetLastError());
+    } else {
+      rs.n_kept_cc = ncc;
+      rs.n_kept_mid = nmk;
+    }
+    // ---- R4: locate ----
+    hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
+    HIPCHECK(hipGetLastError());
+    if ((st = read_counters(M))) return st;
+    DevCounters snap = *M->h_cnt;
+    // ---- R5/R6: cavities (rerun from here if the pool overflows) ----
+    for (int attempt = 0;; attempt++) {
+      hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
+      HIPCHECK(hipGetLastError());
+      if ((st = read_counters(M))) return st;
+      // Midpoint cavities; a large circumcenter cavity handled by the
+      // cooperative kernel may flag more midpoints, so repeat until the
+      // candidate list stops growing.
+      int big_done = 0;
+      for (int pass = 0;; pass++) {
+        nmk = M->h_cnt->nmk;
+        hipLaunchKernelGGL(k_cavity, dim3(grid_for(nmk, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, nmk, 0);
+        HIPCHECK(hipGetLastError());
+        if ((st = read_counters(M))) return st;
+        int nbig = std::min(M->h_cnt->nbig, M->wT);
+        if (nbig > big_done) {
+          hipLaunchKernelGGL(k_cavity_big, dim3(nbig - big_done), dim3(kBigBlockSize), 0, s, m, w, big_done, nbig);
+          HIPCHECK(hipGetLastError());
+          big_done = nbig;
+          if ((st = read_counters(M))) return st;
+        }
+        if (M->h_cnt->nmk == nmk && std::min(M->h_cnt->nbig, M->wT) == big_done) break;
+        if (pass > 64) return fail(ctx, GDP_E_DEVICE, "cavity step did not settle");
+      }
+      DevCounters &c = *M->h_cnt;
+      if (c.err & kErrWalk) { result = fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap"); goto done; }
+      if (c.err & kErrCavity) { result = fail(ctx, GDP_E_CAVITY, "cavity exceeded the cooperative-path capacity"); goto done; }
+      if (c.err & kErrInput) { result = fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment"); goto done; }
+      if (!(c.err & kErrPool)) break;
+      if (attempt > 8) return fail(ctx, GDP_E_NOMEM, "cavity pool keeps overflowing");
+      // grow the pool, forget every cavity of this round and grow them again
+      int64_t ncap = std::max<int64_t>((int64_t)c.pool_used * 2, (int64_t)M->pool_cap * 2);
+      if (ncap > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+      HIPCHECK(dgrow(&M->pool, M->pool_cap, ncap, 0, 0, s));
+      M->pool_cap = (int32_t)ncap;
+      w = make_work(M, pm);
+      std::vector<int32_t> hs;
+      for (int which = 0; which < 2; which++) {
+        int n = which == 0 ? ncc : nmk;
+        int32_t *dst = which == 0 ? M->cc.state : M->mid.state;
+        hs.resize(std::max(n, 1));
+        HIPCHECK(hipMemcpyAsync(hs.data(), dst, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (int i = 0; i < n; i++) hs[i] &= (kStFound | kStSkip);
+        // circumcenters dropped by the walk keep Done
+        if (which == 0)
+          for (int i = 0; i < n; i++)
+            if (!(hs[i] & kStFound)) hs[i] |= kStDone;
+        HIPCHECK(hipMemcpyAsync(dst, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+      }
+      DevCounters r = c;
+      r.pool_used = 0; r.nbig = 0; r.err = 0;
+      r.n_enc_reject = snap.n_enc_reject; r.n_fan_invalid = snap.n_fan_invalid;
+      r.n_unsplittable = snap.n_unsplittable; r.cav_tri_total = snap.cav_tri_total; r.cav_max = snap.cav_max;
+      r.n_mid_cand = snap.n_mid_cand;
+      *M->h_cnt = r;
+      HIPCHECK(hipMemcpyAsync(M->d_cnt, M->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    {
+      int ncand = ncc + nmk;
+      // ---- R8/R9 ----
+      hipLaunchKernelGGL(k_mark, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      hipLaunchKernelGGL(k_own, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      hipLaunchKernelGGL(k_dep, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm, B2);
+      HIPCHECK(hipGetLastError());
+      // ---- R10: ranks ----
+      if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.nS), &M->d_cnt->nwin_mid, 1))) return st;
+      if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.nT), &M->d_cnt->nwin_cc, 1))) return st;
+      if ((st = read_counters(M))) return st;
+      int nwin_mid = M->h_cnt->nwin_mid, nwin_cc = M->h_cnt->nwin_cc, nwin = nwin_mid + nwin_cc;
+      if (nwin == 0) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); goto done; }
+      HIPCHECK(hipMemsetAsync(M->fan_off, 0, sizeof(int32_t) * (nwin + 1), s));
+      hipLaunchKernelGGL(k_winners, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, nwin_mid);
+      if (getenv("GDP_DEBUG")) {
+        if ((st = read_counters(M))) return st;
+        fprintf(stderr, "[gdp] round %d ncc %d nmk %d nwin_mid %d nwin_cc %d win_cands %d dbg_set %d dbg %d %d %d %d pool %d/%d\n",
+                m.rounds + 1, ncc, nmk, nwin_mid, nwin_cc, M->h_cnt->pad[0], M->h_cnt->dbg_set, M->h_cnt->dbg[0],
+                M->h_cnt->dbg[1], M->h_cnt->dbg[2], M->h_cnt->dbg[3], M->h_cnt->pool_used, M->pool_cap);
+      }
+      if ((st = scan(M, M->fcount, M->fbase, nwin, M->fbase + nwin, 0))) return st;
+      HIPCHECK(hipMemcpyAsync(M->h_small, M->fbase + nwin, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      int fresh = M->h_small[0];
+      int pool_used = M->h_cnt->pool_used;
+      // ---- capacity for the new elements ----
+      if ((st = grow_vtx(M, m.nV + nwin))) return st;
+      if ((st = grow_tri(M, m.nT + fresh))) return st;
+      if ((st = grow_seg(M, m.nS + nwin_mid))) return st;
+      if ((st = grow_cand(M))) return st;
+      int64_t need_fan = (int64_t)pool_used + 2 * (int64_t)nwin;
+      if (need_fan > M->fan_cap) {
+        int64_t nc = std::max<int64_t>(need_fan, (int64_t)M->fan_cap * 3 / 2);
+        HIPCHECK(dgrow(&M->fan, M->fan_cap, nc, 0, 0, s));
+        M->fan_cap = (int32_t)nc;
+      }
+      w = make_work(M, pm);
+      hipLaunchKernelGGL(k_record, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
+      hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
+      hipLaunchKernelGGL(k_finish, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk, m.spend);
+      HIPCHECK(hipGetLastError());
+      HIPCHECK(hipMemsetAsync(M->w0_t, 0, sizeof(uint32_t) * words(m.nT), s));
+      HIPCHECK(hipMemsetAsync(M->win_t, 0, sizeof(uint32_t) * words(m.nT), s));
+      HIPCHECK(hipMemsetAsync(M->w0_s, 0, sizeof(uint32_t) * words(m.nS), s));
+      HIPCHECK(hipMemsetAsync(M->win_s, 0, sizeof(uint32_t) * words(m.nS), s));
+      if ((st = read_counters(M))) return st;
+      DevCounters &c = *M->h_cnt;
+      if (c.err & kErrCavity) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "fan boundary mismatch (cc=%d elem=%d cavity=%d expected=%d found=%d state=%d)",
+                 c.dbg[0], c.dbg[1], c.dbg[2], c.dbg[3], c.dbg[4], c.dbg[5]);
+        result = fail(ctx, GDP_E_CAVITY, buf);
+        goto done;
+      }
+      if (capped) {
+        rs.n_kept_cc = c.n_kept_cc;
+        rs.n_kept_mid = c.n_kept_mid;
+      }
+      rs.n_blocked = c.n_blocked;
+      rs.n_coincident = c.n_coincident;
+      rs.n_enc_reject = c.n_enc_reject;
+      rs.n_unsplittable = c.n_unsplittable;
+      rs.n_fan_invalid = c.n_fan_invalid;
+      rs.n_lost_mark = c.n_lost_mark;
+      rs.n_dep_drop = c.n_dep_drop;
+      rs.n_ins_mid = nwin_mid;
+      rs.n_ins_cc = nwin_cc;
+      rs.cav_tri_total = c.cav_tri_total;
+      rs.cav_max = c.cav_max;
+      rs.n_big_cavities = c.nbig;
+      rs.n_mid_cand = c.n_mid_cand;
+      M->stats.push_back(rs);
+      m.nV += nwin;
+      m.nT += fresh;
+      m.nS += nwin_mid;
+      m.rounds += 1;
+    }
+  }
+done:
+  HIPCHECK(hipEventRecord(ev1, s));
+  HIPCHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  M->last_ms = ms;
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gdp_params_default(gdp_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof *p);
+  p->block_size = 256;
+}
+
+const char *gdp_status_str(gdp_status s) {
+  switch (s) {
+    case GDP_OK: return "ok";
+    case GDP_E_ARG: return "invalid argument";
+    case GDP_E_INPUT: return "invalid input PSLG";
+    case GDP_E_NOMEM: return "out of memory";
+    case GDP_E_DEVICE: return "device error";
+    case GDP_E_NOTERM: return "round cap reached";
+    case GDP_E_STALL: return "refinement stalled";
+    case GDP_E_BUSY: return "busy";
+    case GDP_E_WALK: return "walk step cap exceeded";
+    case GDP_E_CAVITY: return "cavity too large";
+  }
+  return "unknown status";
+}
+
+gdp_status gdp_ctx_create(int device, void *hip_stream, gdp_ctx **out) {
+  if (!out) return GDP_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    g_noctx_err = "no such HIP device";
+    return GDP_E_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_noctx_err = "hipSetDevice failed";
+    return GDP_E_DEVICE;
+  }
+  gdp_ctx *c = new gdp_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return GDP_OK;
+}
+
+void gdp_ctx_destroy(gdp_ctx *ctx) { delete ctx; }
+
+const char *gdp_last_error(const gdp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
+
+gdp_status gdp_cdt_host(const gdp_pslg *pslg, int32_t *n_tri, int32_t cap_tri, int32_t *tri, int32_t *nbr,
+                        int32_t *seg, char *err, int32_t err_len) {
+  if (err && err_len > 0) err[0] = 0;
+  if (!pslg || !n_tri) return GDP_E_ARG;
+  HostMesh hm;
+  std::string e;
+  int rc = host_cdt_build(pslg->n_vertices, pslg->xy, pslg->n_segments, pslg->seg, hm, e);
+  if (rc != GDP_OK) {
+    if (err && err_len > 0) snprintf(err, (size_t)err_len, "%s", e.c_str());
+    return (gdp_status)rc;
+  }
+  *n_tri = hm.nT;
+  if (cap_tri >= hm.nT) {
+    if (tri) memcpy(tri, hm.tv.data(), sizeof(int32_t) * 3 * hm.nT);
+    if (nbr) memcpy(nbr, hm.tn.data(), sizeof(int32_t) * 3 * hm.nT);
+    if (seg) memcpy(seg, hm.ts.data(), sizeof(int32_t) * 3 * hm.nT);
+  }
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_create(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out) {
+  if (!ctx || !pslg || !out) return GDP_E_ARG;
+  *out = nullptr;
+  HostMesh hm;
+  std::string e;
+  int rc = host_cdt_build(pslg->n_vertices, pslg->xy, pslg->n_segments, pslg->seg, hm, e);
+  if (rc != GDP_OK) return fail(ctx, (gdp_status)rc, e);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  std::vector<uint8_t> pend(hm.nS, 0);
+  return upload(ctx, hm.nV, hm.nV, hm.xy.data(), nullptr, hm.nT, hm.tv.data(), hm.tn.data(), hm.ts.data(), hm.nS,
+                hm.nS, hm.sv.data(), hm.sparent.data(), pend.data(), 0, out);
+}
+
+gdp_status gdp_mesh_upload(gdp_ctx *ctx, int32_t n_v, int32_t n_input_v, const double *xy, const int32_t *vkind,
+                           int32_t n_t, const int32_t *tri, const int32_t *nbr, const int32_t *sub_on_edge,
+                           int32_t n_s, int32_t n_input_s, const int32_t *sub_v, const int32_t *sub_parent,
+                           const uint8_t *sub_pending, int32_t rounds, gdp_mesh **out) {
+  if (!ctx || !out) return GDP_E_ARG;
+  *out = nullptr;
+  if (n_v < 3 || n_t < 1 || n_s < 0 || !xy || !tri || !nbr || !sub_on_edge || (n_s > 0 && (!sub_v || !sub_parent)) ||
+      n_input_v > n_v || n_input_s > n_s || rounds < 0)
+    return fail(ctx, GDP_E_ARG, "bad mesh arrays");
+  for (int64_t i = 0; i < 3 * (int64_t)n_t; i++) {
+    if (tri[i] < 0 || tri[i] >= n_v || nbr[i] < -1 || nbr[i] >= n_t || sub_on_edge[i] < -1 || sub_on_edge[i] >= n_s)
+      return fail(ctx, GDP_E_ARG, "mesh index out of range");
+  }
+  for (int64_t i = 0; i < 2 * (int64_t)n_s; i++)
+    if (sub_v[i] < 0 || sub_v[i] >= n_v) return fail(ctx, GDP_E_ARG, "subsegment vertex out of range");
+  for (int64_t i = 0; i < 2 * (int64_t)n_v; i++) {
+    double a = fabs(xy[i]);
+    if (!std::isfinite(xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100))
+      return fail(ctx, GDP_E_ARG, "coordinate out of range");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  return upload(ctx, n_v, n_input_v, xy, vkind, n_t, tri, nbr, sub_on_edge, n_s, n_input_s, sub_v, sub_parent,
+                sub_pending, rounds, out);
+}
+
+gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, const gdp_params *params) {
+  if (!ctx || !mesh || mesh->ctx != ctx) return GDP_E_ARG;
+  gdp_params P;
+  if (params) P = *params; else gdp_params_default(&P);
+  if (P.block_size == 0) P.block_size = 256;
+  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(ctx, GDP_E_ARG, "bad ratio bound");
+  if (P.prefilter_f1 != 0 || P.cavity_approx_n != 0) return fail(ctx, GDP_E_ARG, "prefilters are not supported");
+  if (P.cand_cap_K < 0 || P.max_rounds < 0 || (P.priority_mode != 0 && P.priority_mode != 1))
+    return fail(ctx, GDP_E_ARG, "bad parameter");
+  if (P.block_size < 64 || P.block_size > 1024 || P.block_size % 64) return fail(ctx, GDP_E_ARG, "bad block size");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  return refine_loop(mesh, ratio_bound_sq, &P);
+}
+
+gdp_status gdp_refine(gdp_ctx *ctx, const gdp_pslg *pslg, double ratio_bound_sq, const gdp_params *params,
+                      gdp_mesh **out) {
+  if (!out) return GDP_E_ARG;
+  *out = nullptr;
+  gdp_mesh *m = nullptr;
+  gdp_status st = gdp_mesh_create(ctx, pslg, &m);
+  if (st != GDP_OK) return st;
+  st = gdp_mesh_refine(ctx, m, ratio_bound_sq, params);
+  if (st != GDP_OK && st != GDP_E_NOTERM) {
+    gdp_mesh_free(m);
+    return st;
+  }
+  *out = m;
+  return st;
+}
+
+gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info) {
+  if (!mesh || !info) return GDP_E_ARG;
+  info->n_vertices = mesh->m.nV;
+  info->n_triangles = mesh->m.nT;
+  info->n_subsegments = mesh->m.nS;
+  info->n_input_vertices = mesh->m.n_input_v;
+  info->n_input_segments = mesh->m.n_input_s;
+  info->rounds = mesh->m.rounds;
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_download(gdp_ctx *ctx, const gdp_mesh *mesh, double *xy, int32_t *vkind, int32_t *tri,
+                             int32_t *nbr, int32_t *sub_on_edge, int32_t *sub_v, int32_t *sub_parent,
+                             uint8_t *sub_pending) {
+  if (!ctx || !mesh) return GDP_E_ARG;
+  hipStream_t s = ctx->stream;
+  const DevMesh &m = mesh->m;
+  if (xy) {
+    std::vector<double2> h(m.nV);
+    HIPCHECK(hipMemcpyAsync(h.data(), m.vxy, sizeof(double2) * m.nV, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < m.nV; i++) { xy[2 * i] = h[i].x; xy[2 * i + 1] = h[i].y; }
+  }
+  if (vkind) {
+    HIPCHECK(hipMemcpyAsync(vkind, m.vkind, sizeof(int32_t) * m.nV, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  int4 *arrs[3] = {m.tv, m.tn, m.ts};
+  int32_t *outs[3] = {tri, nbr, sub_on_edge};
+  for (int a = 0; a < 3; a++) {
+    if (!outs[a]) continue;
+    std::vector<int4> h(m.nT);
+    HIPCHECK(hipMemcpyAsync(h.data(), arrs[a], sizeof(int4) * m.nT, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int t = 0; t < m.nT; t++) {
+      outs[a][3 * t] = h[t].x;
+      outs[a][3 * t + 1] = h[t].y;
+      outs[a][3 * t + 2] = h[t].z;
+    }
+  }
+  if (sub_v) {
+    HIPCHECK(hipMemcpyAsync(sub_v, m.sv, sizeof(int2) * m.nS, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  if (sub_parent) {
+    HIPCHECK(hipMemcpyAsync(sub_parent, m.spar, sizeof(int32_t) * m.nS, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  if (sub_pending) {
+    std::vector<int32_t> h(m.nS);
+    HIPCHECK(hipMemcpyAsync(h.data(), m.spend, sizeof(int32_t) * m.nS, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < m.nS; k++) sub_pending[k] = (uint8_t)h[k];
+  }
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_round_stats(const gdp_mesh *mesh, gdp_round_stats *stats, int32_t cap, int32_t *n) {
+  if (!mesh || !n) return GDP_E_ARG;
+  int32_t k = (int32_t)mesh->stats.size();
+  *n = k;
+  if (stats)
+    for (int32_t i = 0; i < std::min(k, cap); i++) stats[i] = mesh->stats[i];
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_last_refine_ms(const gdp_mesh *mesh, double *ms) {
+  if (!mesh || !ms) return GDP_E_ARG;
+  *ms = mesh->last_ms;
+  return GDP_OK;
+}
+
+void gdp_mesh_free(gdp_mesh *mesh) {
+  if (!mesh) return;
+  free_mesh_arrays(mesh);
+  delete mesh;
+}
+
+}  // extern "C"

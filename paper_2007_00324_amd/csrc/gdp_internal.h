@@ -1,0 +1,87 @@
+// gdp_internal.h -- shared declarations of the gfx950 refinement library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gdp2d.h"
+#include "gdp_exact.h"
+
+namespace gdp {
+
+// Host-side mesh (canonical CDT output of Line 1).
+struct HostMesh {
+  int32_t nV = 0, nT = 0, nS = 0;
+  std::vector<double> xy;      // 2V
+  std::vector<int32_t> tv;     // 3T
+  std::vector<int32_t> tn;     // 3T
+  std::vector<int32_t> ts;     // 3T
+  std::vector<int32_t> sv;     // 2S
+  std::vector<int32_t> sparent;
+};
+
+int host_cdt_build(int32_t nv, const double *xy, int32_t ns, const int32_t *seg, HostMesh &out,
+                   std::string &err);
+
+// ---- device mesh --------------------------------------------------------------
+// Triangle t: tv[t] = (v0, v1, v2, subsegment-edge mask), tn[t] = (n0, n1, n2, 0),
+// ts[t] = (s0, s1, s2, 0); edge i = (v_i, v_{i+1 mod 3}).
+struct DevMesh {
+  int32_t capV = 0, capT = 0, capS = 0;
+  int32_t nV = 0, nT = 0, nS = 0, n_input_v = 0, n_input_s = 0, rounds = 0;
+  double2 *vxy = nullptr;
+  int32_t *vkind = nullptr;
+  int4 *tv = nullptr, *tn = nullptr, *ts = nullptr;
+  int2 *sv = nullptr;
+  int32_t *spar = nullptr;
+  int32_t *spend = nullptr;
+};
+
+// Device counters of one round.
+struct DevCounters {
+  int32_t ncc;        // circumcenter candidates (bad triangles kept)
+  int32_t nmk;        // midpoint candidates (flagged subsegments)
+  int32_t n_enc;      // subsegments flagged by the scan (pending or encroached apex)
+  int32_t pool_used;  // cavity pool entries allocated
+  int32_t nbig;       // cavities routed to the cooperative path
+  int32_t fan_used;   // fan records allocated
+  int32_t err;        // error bits (kErr*)
+  int32_t nwin_mid, nwin_cc, fresh_total;
+  int32_t n_blocked, n_coincident, n_enc_reject, n_unsplittable, n_fan_invalid;
+  int32_t n_lost_mark, n_dep_drop;
+  int32_t n_kept_mid, n_kept_cc;
+  int32_t cav_max;
+  int64_t cav_tri_total;
+  int32_t n_mid_cand;  // midpoint candidates that reached the cavity step
+  int32_t dbg_set;     // first failing insertion record: set flag
+  int32_t dbg[6];      // class, element, cavity size, expected fan size, found fan size, round-local index
+  int32_t pad[2];
+};
+
+constexpr int kErrWalk = 1;
+constexpr int kErrCavity = 2;
+constexpr int kErrPool = 4;
+constexpr int kErrInput = 8;
+
+// Candidate state bits.
+constexpr int kStFound = 1;     // located (circumcenters) / has seeds (midpoints)
+constexpr int kStAlive = 2;     // cavity grown and valid
+constexpr int kStW0 = 4;        // holds every mark of its cavity
+constexpr int kStWin = 8;       // survives the dependency test
+constexpr int kStBig = 16;      // cavity goes to the cooperative path
+constexpr int kStDone = 32;     // cavity step finished (alive or dropped)
+
+struct CandSet {
+  int32_t *elem;     // triangle slot (circumcenters) or subsegment id (midpoints)
+  uint64_t *key;
+  double2 *p;
+  int32_t *loc;      // located triangle (circumcenters)
+  int32_t *state;
+  int32_t *off;      // cavity pool offset
+  int32_t *len;      // cavity size
+};
+
+}  // namespace gdp

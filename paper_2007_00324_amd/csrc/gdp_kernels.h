@@ -1,0 +1,63 @@
+// gdp_kernels.h -- kernel interface of one refinement round.
+#pragma once
+
+#include "gdp_internal.h"
+
+namespace gdp {
+
+constexpr int kStSkip = 64;  // left out by the candidate cap this round
+
+struct FanRec {
+  int32_t slot, u, v, o, jn, ts;
+};
+
+// Device pointers of the per-round workspace (passed by value to kernels).
+struct Work {
+  DevCounters *cnt;
+  uint64_t *mark;      // [capT] max key of the cavities containing the slot
+  int32_t *sadj;       // [2*capS] t*4+edge of the triangle on each side (-1 none)
+  uint32_t *mflag;     // [capS] subsegment flagged as a midpoint candidate
+  CandSet cc, mid;
+  uint32_t *w0_t, *w0_s, *win_t, *win_s;  // element bitmaps
+  int32_t *rank_t, *rank_s;               // exclusive prefix of bitmap popcounts
+  int32_t *win_ref;    // [nwin] winner -> (class bit 31 set for midpoints) | candidate
+  int32_t *fbase;      // [nwin+1] exclusive prefix of fresh-slot counts
+  int32_t *fcount;     // [nwin] fresh slots per winner (1 or 2)
+  int32_t *fan_off;    // [nwin]
+  int32_t *repl;       // [4*capT] new slot that replaces (old slot, edge)
+  int32_t *pool;
+  int32_t pool_cap;
+  FanRec *fan;
+  int32_t fan_cap;
+  int32_t *big;
+  int32_t big_cap;
+  uint64_t *keys;      // [capT+capS] scratch for the candidate cap
+  int32_t *hist;       // [256]
+  uint64_t *thresh;    // [1]
+  int32_t pm;
+};
+
+__global__ void k_scan(DevMesh m, Work w, double B2, int pm);
+__global__ void k_gather_keys(DevMesh m, Work w, int ncc, int nmk, int pm);
+__global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t pmask);
+__global__ void k_apply_cap(Work w, int ncc, int nmk);
+__global__ void k_locate(DevMesh m, Work w, int ncc);
+__global__ void k_cavity(DevMesh m, Work w, int n, int is_cc);
+__global__ void k_cavity_big(DevMesh m, Work w, int first, int nbig);
+__global__ void k_mark(Work w, int ncc, int nmk);
+__global__ void k_own(Work w, int ncc, int nmk);
+__global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2);
+__global__ void k_scan_tiles(const int32_t *in, int32_t *out, int n, int32_t *tile_sums, int mode);
+__global__ void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total);
+__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums);
+__global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid);
+__global__ void k_record(DevMesh m, Work w, int nwin);
+__global__ void k_write(DevMesh m, Work w, int nwin);
+__global__ void k_unflag(Work w, int nmk);
+__global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend);
+
+constexpr int kCavBlockSize = 128;
+constexpr int kBigBlockSize = 256;
+constexpr int kScanTileSize = 256 * 8;
+
+}  // namespace gdp

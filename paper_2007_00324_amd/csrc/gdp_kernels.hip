@@ -1,0 +1,959 @@
+// gdp_kernels.hip -- gfx950 kernels of one refinement round (Algorithm 1,
+// Lines 3-8 of gDP2d, with cavity insertion as in Section 5.1).
+//
+// Every kernel works on a slot-indexed structure-of-arrays mesh in HBM.  The
+// round is deterministic: candidate lists are built with atomics in any
+// order, but every decision depends only on the mesh at the start of the
+// round, on 64-bit priority keys (unique per element) and on atomicMax,
+// which is order independent; vertex ids, triangle slots and subsegment ids
+// of the inserted points come from prefix sums over element-indexed bitmaps.
+#include "gdp_kernels.h"
+
+namespace gdp {
+
+// ---------------------------------------------------------------------------
+// Priorities (Section 4.3: midpoints before circumcenters, then larger
+// length / area first; the element id, mixed by a fixed bijection, makes
+// every key unique).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t perm32(uint32_t x) {
+  // MurmurHash3 32-bit finalizer applied to id + 1 (never 0)
+  uint32_t h = x + 1u;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__device__ __forceinline__ uint32_t perm32_inv(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x7ed1b41du;  // inverse of 0xc2b2ae35 mod 2^32
+  h ^= (h >> 13) ^ (h >> 26);
+  h *= 0xa5cb9243u;  // inverse of 0x85ebca6b mod 2^32
+  h ^= h >> 16;
+  return h - 1u;
+}
+
+__device__ __forceinline__ uint32_t q31(double x) {
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  return (uint32_t)((b >> 32) & 0x7fffffffu);
+}
+
+__device__ __forceinline__ int comp(const int4 &v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : v.z); }
+
+struct SplitPt {
+  double px, py;
+  uint64_t key;
+  int bad;
+};
+
+// Circumcenter / radius-edge test / key of triangle t, in one fixed FP64
+// operation order (vertices rotated so the smallest id comes first); a
+// needle (non-positive FP64 doubled area, or a circumcenter beyond 2^20)
+// is bad, has measure 0 and splits at the midpoint of its longest edge.
+__device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, int pm) {
+  int v0 = tri.x, v1 = tri.y, v2 = tri.z, ia, ib, ic;
+  if (v0 < v1 && v0 < v2) { ia = v0; ib = v1; ic = v2; }
+  else if (v1 < v2) { ia = v1; ib = v2; ic = v0; }
+  else { ia = v2; ib = v0; ic = v1; }
+  double2 A = m.vxy[ia], B = m.vxy[ib], C = m.vxy[ic];
+  double ax = A.x, ay = A.y;
+  double bx = B.x - ax, by = B.y - ay;
+  double cx = C.x - ax, cy = C.y - ay;
+  double b2 = bx * bx + by * by;
+  double c2 = cx * cx + cy * cy;
+  double d = bx * cy - by * cx;
+  double ex = C.x - B.x, ey = C.y - B.y;
+  double e2 = ex * ex + ey * ey;
+  SplitPt r;
+  uint64_t q = 0;
+  bool needle = true;
+  if (d > 0.0) {
+    double den = d + d;
+    double ux = (cy * b2 - by * c2) / den;
+    double uy = (bx * c2 - cx * b2) / den;
+    double px = ax + ux, py = ay + uy;
+    if (fabs(px) <= 0x1p20 && fabs(py) <= 0x1p20) {
+      needle = false;
+      r.px = px;
+      r.py = py;
+      double r2 = ux * ux + uy * uy;
+      double lmin2 = b2;
+      if (c2 < lmin2) lmin2 = c2;
+      if (e2 < lmin2) lmin2 = e2;
+      r.bad = r2 > B2 * lmin2 ? 1 : 0;
+      q = q31(d);
+    }
+  }
+  if (needle) {
+    double2 U = A, W = B;
+    double best = b2;
+    if (c2 > best) { best = c2; U = A; W = C; }
+    if (e2 > best) { best = e2; U = B; W = C; }
+    r.px = (U.x + W.x) * 0.5;
+    r.py = (U.y + W.y) * 0.5;
+    r.bad = 1;
+    q = 0;
+  }
+  if (pm == 1) q = 0;
+  r.key = (q << 32) | (uint64_t)perm32((uint32_t)t);
+  return r;
+}
+
+__device__ SplitPt seg_split(const DevMesh &m, int k, int pm) {
+  int2 s = m.sv[k];
+  double2 A = m.vxy[s.x], B = m.vxy[s.y];
+  SplitPt r;
+  r.px = (A.x + B.x) * 0.5;
+  r.py = (A.y + B.y) * 0.5;
+  double dx = B.x - A.x, dy = B.y - A.y;
+  double len2 = dx * dx + dy * dy;
+  uint64_t q = pm == 1 ? 0 : (uint64_t)q31(len2);
+  r.key = (1ull << 63) | (q << 32) | (uint64_t)perm32((uint32_t)k);
+  r.bad = 1;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_append(int *counter, bool pred) {
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0) return -1;
+  int lane = __lane_id();
+  int leader = __ffsll((unsigned long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ void flag_mid(const Work &w, int k) {
+  if (atomicOr(&w.mflag[k], 1u) == 0u) {
+    int idx = atomicAdd(&w.cnt->nmk, 1);
+    w.mid.elem[idx] = k;
+    w.mid.state[idx] = 0;
+  }
+}
+
+__device__ __forceinline__ bool bit_get(const uint32_t *bm, int i) { return (bm[i >> 5] >> (i & 31)) & 1u; }
+__device__ __forceinline__ void bit_set(uint32_t *bm, int i) { atomicOr(&bm[i >> 5], 1u << (i & 31)); }
+
+__device__ __forceinline__ int bit_rank(const uint32_t *bm, const int32_t *words_prefix, int i) {
+  uint32_t w = bm[i >> 5];
+  uint32_t below = (i & 31) ? (w & ((1u << (i & 31)) - 1u)) : 0u;
+  return words_prefix[i >> 5] + __popc(below);
+}
+
+__device__ __forceinline__ int orient_pts(double2 a, double2 b, double2 c) {
+  return orient2d(a.x, a.y, b.x, b.y, c.x, c.y);
+}
+
+__device__ __forceinline__ int incircle_tri(const DevMesh &m, int4 tri, double2 p) {
+  double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
+  return incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y);
+}
+
+__device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int v) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int x = a[mid];
+    if (x == v) return true;
+    if (x < v) lo = mid + 1; else hi = mid - 1;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// R1: collect encroached subsegments and bad triangles (Line 3)
+// ---------------------------------------------------------------------------
+__global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  SplitPt r;
+  if (i < m.nT) {
+    int4 tri = m.tv[i];
+    if (tri.w) {
+      int4 s = m.ts[i];
+      for (int e = 0; e < 3; e++) {
+        if (!((tri.w >> e) & 1)) continue;
+        int k = comp(s, e);
+        int u = comp(tri, e), v = comp(tri, (e + 1) % 3), c = comp(tri, (e + 2) % 3);
+        int side = (u == m.sv[k].x) ? 0 : 1;
+        w.sadj[2 * k + side] = i * 4 + e;
+        double2 U = m.vxy[u], V = m.vxy[v], Cc = m.vxy[c];
+        if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0) flag_mid(w, k);
+      }
+    }
+    r = tri_split(m, i, tri, B2, pm);
+    bad = r.bad != 0;
+  }
+  int idx = wave_append(&w.cnt->ncc, bad);
+  if (bad) {
+    w.cc.elem[idx] = i;
+    w.cc.key[idx] = r.key;
+    w.cc.p[idx] = make_double2(r.px, r.py);
+    w.cc.state[idx] = 0;
+  }
+  if (i < m.nS && m.spend[i]) flag_mid(w, i);
+}
+
+// ---------------------------------------------------------------------------
+// R3 (optional): keep the K largest keys.  Keys of both classes are placed in
+// one array; a radix select finds the K-th largest (keys are unique).
+// ---------------------------------------------------------------------------
+__global__ void k_gather_keys(DevMesh m, Work w, int ncc, int nmk, int pm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncc) w.keys[c] = w.cc.key[c];
+  else if (c < ncc + nmk) {
+    int j = c - ncc;
+    SplitPt r = seg_split(m, w.mid.elem[j], pm);
+    w.mid.key[j] = r.key;
+    w.mid.p[j] = make_double2(r.px, r.py);
+    w.keys[c] = r.key;
+  }
+}
+
+// Histogram of 8-bit digit `shift` over keys whose higher digits equal prefix.
+__global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t pmask) {
+  __shared__ int h[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    uint64_t k = w.keys[c];
+    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (h[i]) atomicAdd(&w.hist[i], h[i]);
+}
+
+__global__ void k_apply_cap(Work w, int ncc, int nmk) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t th = *w.thresh;
+  if (c < ncc) {
+    if (w.cc.key[c] < th) w.cc.state[c] = kStDone | kStSkip;
+    else atomicAdd(&w.cnt->n_kept_cc, 1);
+  } else if (c < ncc + nmk) {
+    int j = c - ncc;
+    if (w.mid.key[j] < th) {
+      w.mid.state[j] = kStSkip;
+      w.mflag[w.mid.elem[j]] = 0u;
+    } else {
+      atomicAdd(&w.cnt->n_kept_mid, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R4: locate circumcenters by a visibility walk (Line 6); a walk stopped only
+// by subsegments turns into the midpoint candidate of the first one.
+// ---------------------------------------------------------------------------
+__global__ void k_locate(DevMesh m, Work w, int ncc) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc) return;
+  if (w.cc.state[c] & kStSkip) return;
+  int cur = w.cc.elem[c];
+  double2 p = w.cc.p[c];
+  for (int steps = 1;; steps++) {
+    if (steps > (1 << 20)) {
+      atomicOr(&w.cnt->err, kErrWalk);
+      w.cc.state[c] = kStDone;
+      return;
+    }
+    int4 tri = m.tv[cur];
+    double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
+    int s0 = orient_pts(A, B, p), s1 = orient_pts(B, C, p), s2 = orient_pts(C, A, p);
+    if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
+      int nz = (s0 == 0) + (s1 == 0) + (s2 == 0);
+      if (nz >= 2) {
+        atomicAdd(&w.cnt->n_coincident, 1);
+        w.cc.state[c] = kStDone;
+        return;
+      }
+      w.cc.loc[c] = cur;
+      w.cc.state[c] = kStFound;
+      return;
+    }
+    int4 nb = m.tn[cur];
+    int s[3] = {s0, s1, s2};
+    int first_neg = -1, next = -1;
+    for (int e = 0; e < 3; e++) {
+      if (s[e] >= 0) continue;
+      if (first_neg < 0) first_neg = e;
+      int o = comp(nb, e);
+      if (!((tri.w >> e) & 1) && o >= 0) { next = o; break; }
+    }
+    if (next < 0) {
+      int k = comp(m.ts[cur], first_neg);
+      if (k < 0 || k >= m.nS) {  // a hull edge that is not a subsegment
+        atomicOr(&w.cnt->err, kErrInput);
+        w.cc.state[c] = kStDone;
+        return;
+      }
+      flag_mid(w, k);
+      atomicAdd(&w.cnt->n_blocked, 1);
+      w.cc.state[c] = kStDone;
+      return;
+    }
+    cur = next;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R5 / R6: Bowyer-Watson cavities.  Per-thread growth in an LDS slice; a
+// cavity larger than the slice goes to the cooperative kernel below.
+// ---------------------------------------------------------------------------
+struct CavCheck {
+  int nbnd;
+  bool fan_bad;
+  bool enc;
+};
+
+// Boundary checks of a sorted cavity: encroached boundary subsegments (for
+// circumcenters; all are flagged), fan orientation, boundary count.
+template <typename GetCav>
+__device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, int len, int skip_k,
+                                 bool is_cc, double2 p) {
+  CavCheck r{0, false, false};
+  for (int j = 0; j < len; j++) {
+    int t = cav(j);
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    for (int e = 0; e < 3; e++) {
+      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (skip_k >= 0 && sid == skip_k) continue;
+      int o = comp(nb, e);
+      if (sid < 0 && o >= 0) {
+        // internal iff o is in the cavity (binary search on the sorted list)
+        int lo = 0, hi = len - 1;
+        bool in = false;
+        while (lo <= hi) {
+          int mid = (lo + hi) >> 1;
+          int x = cav(mid);
+          if (x == o) { in = true; break; }
+          if (x < o) lo = mid + 1; else hi = mid - 1;
+        }
+        if (in) continue;
+      }
+      r.nbnd++;
+      double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
+      if (is_cc && sid >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
+        flag_mid(w, sid);
+        r.enc = true;
+      }
+      if (orient_pts(U, V, p) <= 0) r.fan_bad = true;
+    }
+  }
+  return r;
+}
+
+__device__ void finish_cavity(const Work &w, CandSet S, int ci, const CavCheck &ck, int len,
+                              int expect, bool is_cc, const int32_t *src, int stride) {
+  if ((is_cc && ck.enc) || ck.fan_bad || ck.nbnd - len != expect) {
+    atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+    atomicMax(&w.cnt->cav_max, len);
+    atomicAdd((is_cc && ck.enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
+    S.state[ci] |= kStDone;
+    return;
+  }
+  int off = atomicAdd(&w.cnt->pool_used, len);
+  if (off + len > w.pool_cap) {
+    atomicOr(&w.cnt->err, kErrPool);
+    return;  // the host grows the pool and runs the cavity step again
+  }
+  for (int j = 0; j < len; j++) w.pool[off + j] = src[(size_t)j * stride];
+  atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+  atomicMax(&w.cnt->cav_max, len);
+  S.off[ci] = off;
+  S.len[ci] = len;
+  S.state[ci] |= kStDone | kStAlive;
+}
+
+constexpr int kCap = 24;      // per-thread cavity capacity
+constexpr int kCavBlock = 128;
+
+// Grows the cavity of p from the seeds into lds[j * kCavBlock + tid].
+// Returns the size, or -1 if it exceeds kCap.
+__device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *seeds, int nseeds,
+                          double2 p) {
+  int len = 0;
+  for (int s = 0; s < nseeds; s++) {
+    bool dup = false;
+    for (int q = 0; q < len; q++) dup |= lds[q * kCavBlock + tid] == seeds[s];
+    if (!dup) lds[(len++) * kCavBlock + tid] = seeds[s];
+  }
+  for (int h = 0; h < len; h++) {
+    int t = lds[h * kCavBlock + tid];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    for (int e = 0; e < 3; e++) {
+      if ((tri.w >> e) & 1) continue;
+      int o = comp(nb, e);
+      if (o < 0) continue;
+      bool in = false;
+      for (int q = 0; q < len; q++)
+        if (lds[q * kCavBlock + tid] == o) { in = true; break; }
+      if (in) continue;
+      if (incircle_tri(m, m.tv[o], p) > 0) {
+        if (len == kCap) return -1;
+        lds[(len++) * kCavBlock + tid] = o;
+      }
+    }
+  }
+  // insertion sort (ascending slots)
+  for (int a = 1; a < len; a++) {
+    int x = lds[a * kCavBlock + tid];
+    int b = a - 1;
+    while (b >= 0 && lds[b * kCavBlock + tid] > x) {
+      lds[(b + 1) * kCavBlock + tid] = lds[b * kCavBlock + tid];
+      b--;
+    }
+    lds[(b + 1) * kCavBlock + tid] = x;
+  }
+  return len;
+}
+
+__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n, int is_cc) {
+  __shared__ int32_t lds[kCap * kCavBlock];
+  int tid = threadIdx.x;
+  int ci = blockIdx.x * kCavBlock + tid;
+  if (ci >= n) return;
+  CandSet S = is_cc ? w.cc : w.mid;
+  int st = S.state[ci];
+  if (st & (kStDone | kStSkip | kStBig)) return;
+  int seeds[2], nseeds = 0, skip_k = -1, expect = 2;
+  double2 p;
+  if (is_cc) {
+    if (!(st & kStFound)) return;
+    seeds[nseeds++] = S.loc[ci];
+    p = S.p[ci];
+  } else {
+    int k = S.elem[ci];
+    atomicAdd(&w.cnt->n_mid_cand, 1);
+    SplitPt r = seg_split(m, k, w.pm);
+    S.key[ci] = r.key;
+    p = make_double2(r.px, r.py);
+    S.p[ci] = p;
+    int2 sk = m.sv[k];
+    double2 A = m.vxy[sk.x], B = m.vxy[sk.y];
+    if ((p.x == A.x && p.y == A.y) || (p.x == B.x && p.y == B.y)) {
+      atomicAdd(&w.cnt->n_unsplittable, 1);
+      S.state[ci] = st | kStDone;
+      return;
+    }
+    int a0 = w.sadj[2 * k], a1 = w.sadj[2 * k + 1];
+    if (a0 >= 0) seeds[nseeds++] = a0 >> 2;
+    if (a1 >= 0) seeds[nseeds++] = a1 >> 2;
+    skip_k = k;
+    expect = nseeds == 2 ? 2 : 1;
+    S.state[ci] = st | kStFound;
+  }
+  int len = grow_local(m, lds, tid, seeds, nseeds, p);
+  if (len < 0) {
+    S.state[ci] = st | kStBig | kStFound;
+    int q = atomicAdd(&w.cnt->nbig, 1);
+    if (q < w.big_cap) w.big[q] = (is_cc ? 0 : (int)0x80000000) | ci;
+    else atomicOr(&w.cnt->err, kErrCavity);
+    return;
+  }
+  auto cav = [&](int j) { return lds[j * kCavBlock + tid]; };
+  CavCheck ck = check_cavity(m, w, cav, len, skip_k, is_cc != 0, p);
+  finish_cavity(w, S, ci, ck, len, expect, is_cc != 0, lds + tid, kCavBlock);
+}
+
+// Cooperative growth of one large cavity per workgroup (the tuple-parallel
+// ExpandList idea of Section 5.2: the frontier of <point, triangle> tuples
+// is processed in parallel, new tuples are reserved with atomics).
+constexpr int kBigMax = 4096;
+constexpr int kHash = 16384;
+constexpr int kBigBlock = 256;
+
+__device__ __forceinline__ int hash_insert(int32_t *hs, int v, int *ovf) {
+  uint32_t h = ((uint32_t)v * 2654435761u) & (kHash - 1);
+  for (int probe = 0; probe < kHash; probe++) {
+    int old = atomicCAS(&hs[h], -1, v);
+    if (old == -1) return 1;
+    if (old == v) return 0;
+    h = (h + 1) & (kHash - 1);
+  }
+  *ovf = 1;
+  return 0;
+}
+
+__global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int first, int nbig) {
+  __shared__ int32_t cav[kBigMax];
+  __shared__ int32_t hs[kHash];
+  __shared__ int s_n, s_head, s_ovf, s_nbnd, s_fanbad, s_enc, s_off;
+  int b = first + blockIdx.x;
+  if (b >= nbig || b >= w.big_cap) return;
+  int tid = threadIdx.x;
+  int ref = w.big[b];
+  int is_cc = (ref & 0x80000000) ? 0 : 1;
+  int ci = ref & 0x7fffffff;
+  CandSet S = is_cc ? w.cc : w.mid;
+  if (!(S.state[ci] & kStBig) || (S.state[ci] & kStDone)) return;
+  double2 p = S.p[ci];
+  int skip_k = is_cc ? -1 : S.elem[ci];
+  for (int i = tid; i < kHash; i += kBigBlock) hs[i] = -1;
+  __syncthreads();
+  int expect = 2;
+  if (tid == 0) {
+    s_n = 0; s_head = 0; s_ovf = 0; s_nbnd = 0; s_fanbad = 0; s_enc = 0;
+    if (is_cc) {
+      int t = S.loc[ci];
+      hash_insert(hs, t, &s_ovf);
+      cav[s_n++] = t;
+    } else {
+      int a0 = w.sadj[2 * skip_k], a1 = w.sadj[2 * skip_k + 1];
+      if (a0 >= 0 && hash_insert(hs, a0 >> 2, &s_ovf)) cav[s_n++] = a0 >> 2;
+      if (a1 >= 0 && hash_insert(hs, a1 >> 2, &s_ovf)) cav[s_n++] = a1 >> 2;
+    }
+  }
+  if (!is_cc) expect = (w.sadj[2 * skip_k] >= 0 && w.sadj[2 * skip_k + 1] >= 0) ? 2 : 1;
+  __syncthreads();
+  for (;;) {
+    int lo = s_head, hi = s_n < kBigMax ? s_n : kBigMax;
+    int ovf = s_ovf;
+    __syncthreads();
+    if (lo >= hi || ovf) break;
+    if (tid == 0) s_head = hi;
+    for (int idx = lo + tid; idx < hi; idx += kBigBlock) {
+      int t = cav[idx];
+      int4 tri = m.tv[t];
+      int4 nb = m.tn[t];
+      for (int e = 0; e < 3; e++) {
+        if ((tri.w >> e) & 1) continue;
+        int o = comp(nb, e);
+        if (o < 0) continue;
+        if (!hash_insert(hs, o, &s_ovf)) continue;
+        if (incircle_tri(m, m.tv[o], p) > 0) {
+          int pos = atomicAdd(&s_n, 1);
+          if (pos < kBigMax) cav[pos] = o;
+          else s_ovf = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (s_ovf) {
+    if (tid == 0) {
+      atomicOr(&w.cnt->err, kErrCavity);
+      S.state[ci] |= kStDone;
+    }
+    return;
+  }
+  int len = s_n;
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int i = len + tid; i < P; i += kBigBlock) cav[i] = 0x7fffffff;
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = tid; i < P; i += kBigBlock) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool up = (i & size) == 0;
+          int x = cav[i], y = cav[j];
+          if ((x > y) == up) { cav[i] = y; cav[j] = x; }
+        }
+      }
+    }
+  __syncthreads();
+  // boundary checks, in parallel over cavity triangles
+  for (int j = tid; j < len; j += kBigBlock) {
+    int t = cav[j];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    for (int e = 0; e < 3; e++) {
+      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (skip_k >= 0 && sid == skip_k) continue;
+      int o = comp(nb, e);
+      if (sid < 0 && o >= 0 && in_sorted(cav, len, o)) continue;
+      atomicAdd(&s_nbnd, 1);
+      double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
+      if (is_cc && sid >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
+        flag_mid(w, sid);
+        s_enc = 1;
+      }
+      if (orient_pts(U, V, p) <= 0) s_fanbad = 1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_off = -1;
+    bool drop = (is_cc && s_enc) || s_fanbad || s_nbnd - len != expect;
+    if (drop) {
+      atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+      atomicMax(&w.cnt->cav_max, len);
+      atomicAdd((is_cc && s_enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
+      S.state[ci] |= kStDone;
+    } else {
+      int off = atomicAdd(&w.cnt->pool_used, len);
+      if (off + len > w.pool_cap) atomicOr(&w.cnt->err, kErrPool);
+      else {
+        s_off = off;
+        atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+        atomicMax(&w.cnt->cav_max, len);
+      }
+    }
+  }
+  __syncthreads();
+  int off = s_off;
+  if (off >= 0) {
+    for (int j = tid; j < len; j += kBigBlock) w.pool[off + j] = cav[j];
+    if (tid == 0) {
+      S.off[ci] = off;
+      S.len[ci] = len;
+      S.state[ci] |= kStDone | kStAlive;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R8: priority marks and ownership
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool cand_at(const Work &w, int c, int ncc, CandSet &S, int &ci, int &is_cc) {
+  if (c < ncc) { S = w.cc; ci = c; is_cc = 1; return true; }
+  S = w.mid; ci = c - ncc; is_cc = 0; return true;
+}
+
+__global__ void k_mark(Work w, int ncc, int nmk) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc + nmk) return;
+  CandSet S;
+  int ci, is_cc;
+  cand_at(w, c, ncc, S, ci, is_cc);
+  if (!(S.state[ci] & kStAlive)) return;
+  uint64_t key = S.key[ci];
+  int off = S.off[ci], len = S.len[ci];
+  for (int j = 0; j < len; j++) atomicMax((unsigned long long *)&w.mark[w.pool[off + j]], (unsigned long long)key);
+}
+
+__global__ void k_own(Work w, int ncc, int nmk) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc + nmk) return;
+  CandSet S;
+  int ci, is_cc;
+  cand_at(w, c, ncc, S, ci, is_cc);
+  int st = S.state[ci];
+  if (!(st & kStAlive)) return;
+  uint64_t key = S.key[ci];
+  int off = S.off[ci], len = S.len[ci];
+  bool own = true;
+  for (int j = 0; j < len && own; j++) own = w.mark[w.pool[off + j]] == key;
+  if (own) {
+    S.state[ci] = st | kStW0;
+    bit_set(is_cc ? w.w0_t : w.w0_s, S.elem[ci]);
+  } else {
+    atomicAdd(&w.cnt->n_lost_mark, 1);
+  }
+}
+
+// R9: Delaunay dependency across a shared non-subsegment cavity edge.
+__global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc + nmk) return;
+  CandSet S;
+  int ci, is_cc;
+  cand_at(w, c, ncc, S, ci, is_cc);
+  int st = S.state[ci];
+  if (!(st & kStW0)) return;
+  uint64_t key = S.key[ci];
+  double2 p = S.p[ci];
+  int off = S.off[ci], len = S.len[ci];
+  int skip_k = is_cc ? -1 : S.elem[ci];
+  bool drop = false;
+  for (int j = 0; j < len && !drop; j++) {
+    int t = w.pool[off + j];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    for (int e = 0; e < 3 && !drop; e++) {
+      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (sid >= 0) continue;  // subsegment edges (incl. the split one) are not tested
+      int o = comp(nb, e);
+      if (o < 0) continue;
+      uint64_t mo = w.mark[o];
+      if (mo == key || mo == 0) continue;  // inside this cavity, or unclaimed
+      int q_cc = (mo >> 63) ? 0 : 1;
+      int qid = (int)perm32_inv((uint32_t)(mo & 0xffffffffu));
+      if (!bit_get(q_cc ? w.w0_t : w.w0_s, qid)) continue;
+      SplitPt q = q_cc ? tri_split(m, qid, m.tv[qid], B2, pm) : seg_split(m, qid, pm);
+      double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
+      if (key < mo && incircle(U.x, U.y, V.x, V.y, p.x, p.y, q.px, q.py) > 0) drop = true;
+    }
+  }
+  (void)skip_k;
+  if (drop) {
+    atomicAdd(&w.cnt->n_dep_drop, 1);
+  } else {
+    S.state[ci] = st | kStWin;
+    bit_set(is_cc ? w.win_t : w.win_s, S.elem[ci]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prefix sums (block scan + scan of block sums + add)
+// ---------------------------------------------------------------------------
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *total) {
+  __shared__ int warp_sums[kScanBlock / 64];
+  int lane = __lane_id(), wid = threadIdx.x / 64;
+  // inclusive wave scan
+  int x = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) warp_sums[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < kScanBlock / 64; i++) {
+      int s = warp_sums[i];
+      warp_sums[i] = run;
+      run += s;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  int r = x - v + warp_sums[wid];
+  __syncthreads();
+  return r;
+}
+
+// mode 0: in[] are counts; mode 1: in[] are 32-bit words, count = popcount
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, int32_t *out, int n,
+                                                           int32_t *tile_sums, int mode) {
+  __shared__ int s_total;
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+  for (int i = 0; i < kScanItems; i++) {
+    int idx = base + i;
+    int x = idx < n ? in[idx] : 0;
+    if (mode == 1) x = __popc((uint32_t)x);
+    v[i] = x;
+    sum += x;
+  }
+  int excl = block_excl_scan(sum, &s_total);
+  for (int i = 0; i < kScanItems; i++) {
+    int idx = base + i;
+    if (idx < n) out[idx] = excl;
+    excl += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = s_total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total) {
+  __shared__ int s_total;
+  int carry = 0;
+  for (int start = 0; start < ntiles; start += kScanBlock) {
+    int idx = start + threadIdx.x;
+    int x = idx < ntiles ? tile_sums[idx] : 0;
+    int e = block_excl_scan(x, &s_total);
+    if (idx < ntiles) tile_sums[idx] = e + carry;
+    carry += s_total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) out[idx] += tile_sums[idx / kScanTile];
+}
+
+// ---------------------------------------------------------------------------
+// R10: insertion
+// ---------------------------------------------------------------------------
+__global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc + nmk) return;
+  CandSet S;
+  int ci, is_cc;
+  cand_at(w, c, ncc, S, ci, is_cc);
+  if (!(S.state[ci] & kStWin)) return;
+  int e = S.elem[ci];
+  int r, fresh;
+  if (is_cc) {
+    r = nwin_mid + bit_rank(w.win_t, w.rank_t, e);
+    fresh = 2;
+  } else {
+    r = bit_rank(w.win_s, w.rank_s, e);
+    fresh = (w.sadj[2 * e] >= 0 && w.sadj[2 * e + 1] >= 0) ? 2 : 1;
+  }
+  atomicAdd(&w.cnt->pad[0], 1);
+  if (atomicExch(&w.fan_off[r], 1) != 0 && atomicCAS(&w.cnt->dbg_set, 0, 2) == 0) {
+    w.cnt->dbg[0] = is_cc; w.cnt->dbg[1] = e; w.cnt->dbg[2] = r; w.cnt->dbg[3] = ci; w.cnt->dbg[4] = -1;
+  }
+  w.win_ref[r] = (is_cc ? 0 : (int)0x80000000) | ci;
+  w.fcount[r] = fresh;
+}
+
+__device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
+  if (mo == 0) return false;
+  int q_cc = (mo >> 63) ? 0 : 1;
+  int qid = (int)perm32_inv((uint32_t)(mo & 0xffffffffu));
+  return bit_get(q_cc ? w.win_t : w.win_s, qid);
+}
+
+// Fan records of each winner: boundary edges in canonical order (cavity
+// slots ascending, edge index 0..2; the split subsegment is skipped).  The
+// j-th fan triangle takes the j-th cavity slot, then fresh slots.
+__global__ void k_record(DevMesh m, Work w, int nwin) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nwin) return;
+  int ref = w.win_ref[r];
+  int is_cc = (ref & 0x80000000) ? 0 : 1;
+  int ci = ref & 0x7fffffff;
+  CandSet S = is_cc ? w.cc : w.mid;
+  uint64_t key = S.key[ci];
+  int off = S.off[ci], len = S.len[ci];
+  int skip_k = is_cc ? -1 : S.elem[ci];
+  int fresh_base = m.nT + w.fbase[r];
+  int b = len + (w.fbase[r + 1] - w.fbase[r]);
+  int foff = atomicAdd(&w.cnt->fan_used, b);
+  w.fan_off[r] = foff;
+  int j = 0;
+  for (int q = 0; q < len; q++) {
+    int t = w.pool[off + q];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    for (int e = 0; e < 3; e++) {
+      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (skip_k >= 0 && sid == skip_k) continue;
+      int o = comp(nb, e);
+      if (sid < 0 && o >= 0 && w.mark[o] == key) continue;
+      int slot = j < len ? w.pool[off + j] : fresh_base + (j - len);
+      int u = comp(tri, e), v = comp(tri, (e + 1) % 3);
+      int jn = -1;
+      if (o >= 0) {
+        int4 to = m.tv[o];
+        if (to.x == v && to.y == u) jn = 0;
+        else if (to.y == v && to.z == u) jn = 1;
+        else jn = 2;
+      }
+      if (j >= b) {  // cannot happen for a cavity that passed the boundary count check
+        j++;
+        continue;
+      }
+      FanRec f;
+      f.slot = slot; f.u = u; f.v = v; f.o = o; f.jn = jn; f.ts = sid;
+      w.fan[foff + j] = f;
+      w.repl[t * 4 + e] = slot;
+      j++;
+    }
+  }
+  if (j != b) {
+    atomicOr(&w.cnt->err, kErrCavity);
+    if (atomicCAS(&w.cnt->dbg_set, 0, 1) == 0) {
+      w.cnt->dbg[0] = is_cc;
+      w.cnt->dbg[1] = S.elem[ci];
+      w.cnt->dbg[2] = len;
+      w.cnt->dbg[3] = b;
+      w.cnt->dbg[4] = j;
+      w.cnt->dbg[5] = S.state[ci];
+    }
+  }
+}
+
+__global__ void k_write(DevMesh m, Work w, int nwin) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nwin) return;
+  int ref = w.win_ref[r];
+  int is_cc = (ref & 0x80000000) ? 0 : 1;
+  int ci = ref & 0x7fffffff;
+  CandSet S = is_cc ? w.cc : w.mid;
+  int len = S.len[ci];
+  int b = len + (w.fbase[r + 1] - w.fbase[r]);
+  int foff = w.fan_off[r];
+  int pid = m.nV + r;
+  double2 p = S.p[ci];
+  int k = -1, knew = -1, a = -1, bb = -1;
+  if (!is_cc) {
+    k = S.elem[ci];
+    knew = m.nS + r;  // midpoint winners take ranks 0..nwin_mid-1
+    int2 sk = m.sv[k];
+    a = sk.x;
+    bb = sk.y;
+  }
+  for (int j = 0; j < b; j++) {
+    FanRec f = w.fan[foff + j];
+    int s = f.slot;
+    int n0;
+    if (f.o < 0) n0 = -1;
+    else if (owner_wins(w, w.mark[f.o])) n0 = w.repl[f.o * 4 + f.jn];
+    else {
+      n0 = f.o;
+      ((int32_t *)m.tn)[f.o * 4 + f.jn] = s;
+    }
+    int n1 = -1, n2 = -1;
+    for (int g = 0; g < b; g++) {
+      FanRec h = w.fan[foff + g];
+      if (h.u == f.v) n1 = h.slot;
+      if (h.v == f.u) n2 = h.slot;
+    }
+    int s1 = -1, s2 = -1;
+    if (!is_cc) {
+      s1 = f.v == a ? k : (f.v == bb ? knew : -1);
+      s2 = f.u == a ? k : (f.u == bb ? knew : -1);
+    }
+    int mask = (f.ts >= 0 ? 1 : 0) | (s1 >= 0 ? 2 : 0) | (s2 >= 0 ? 4 : 0);
+    m.tv[s] = make_int4(f.u, f.v, pid, mask);
+    m.tn[s] = make_int4(n0, n1, n2, 0);
+    m.ts[s] = make_int4(f.ts, s1, s2, 0);
+  }
+  m.vxy[pid] = p;
+  m.vkind[pid] = is_cc ? 2 : 1;
+  if (!is_cc) {
+    m.sv[k] = make_int2(a, pid);
+    m.sv[knew] = make_int2(pid, bb);
+    m.spar[knew] = m.spar[k];
+    m.spend[knew] = 0;
+    w.sadj[2 * knew] = -1;
+    w.sadj[2 * knew + 1] = -1;
+    w.mflag[knew] = 0u;
+  }
+}
+
+// Leaving the loop right after a scan (round cap): drop this round's flags.
+__global__ void k_unflag(Work w, int nmk) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nmk) w.mflag[w.mid.elem[c]] = 0u;
+}
+
+// R11: clear marks of every grown cavity, update pending flags.
+__global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncc + nmk) return;
+  CandSet S;
+  int ci, is_cc;
+  cand_at(w, c, ncc, S, ci, is_cc);
+  int st = S.state[ci];
+  if (st & kStAlive) {
+    int off = S.off[ci], len = S.len[ci];
+    for (int j = 0; j < len; j++) w.mark[w.pool[off + j]] = 0ull;
+  }
+  if (!is_cc) {
+    // pending := (pending or flagged this round) and not split; an entry the
+    // cap skipped is not "flagged" unless R4/R5 flagged it again (own entry)
+    int k = S.elem[ci];
+    bool split = bit_get(w.win_s, k);
+    if (!(st & kStSkip)) spend[k] = split ? 0 : 1;
+    else if (split) spend[k] = 0;
+    w.mflag[k] = 0u;
+  }
+}
+
+}  // namespace gdp

@@ -1,0 +1,266 @@
+"""Python binding of libgdp2d.so (include/gdp2d.h): argument marshalling only.
+
+Every step of the refinement runs in the library's HIP kernels; this module
+converts numpy arrays to pointers and back.  PyTorch is imported first so the
+library binds to the same HIP runtime as torch, and is used for the stream.
+The binding fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgdp2d.so")
+
+GDP_OK = 0
+STATUS = {0: "GDP_OK", -1: "GDP_E_ARG", -2: "GDP_E_INPUT", -3: "GDP_E_NOMEM", -4: "GDP_E_DEVICE",
+          -5: "GDP_E_NOTERM", -6: "GDP_E_STALL", -7: "GDP_E_BUSY", -8: "GDP_E_WALK", -9: "GDP_E_CAVITY"}
+
+
+class GdpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class gdp_pslg(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xy", C.POINTER(C.c_double)),
+                ("n_segments", C.c_int32), ("seg", C.POINTER(C.c_int32))]
+
+
+class gdp_params(C.Structure):
+    _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
+                ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class gdp_mesh_info(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_subsegments", C.c_int32),
+                ("n_input_vertices", C.c_int32), ("n_input_segments", C.c_int32), ("rounds", C.c_int32)]
+
+
+STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident", "n_enc_reject",
+               "n_mid_cand", "n_unsplittable", "n_fan_invalid", "n_lost_mark", "n_dep_drop", "n_ins_mid",
+               "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities"]
+
+
+class gdp_round_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
+
+
+_lib = None
+_VP = C.c_void_p
+_PI = C.POINTER(C.c_int32)
+_PD = C.POINTER(C.c_double)
+
+
+def load() -> C.CDLL:
+    """Loads libgdp2d.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (binds the HIP runtime torch ships)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2007_00324_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    S = C.c_int
+    sig = {
+        "gdp_params_default": (None, [C.POINTER(gdp_params)]),
+        "gdp_status_str": (C.c_char_p, [S]),
+        "gdp_ctx_create": (S, [C.c_int, _VP, C.POINTER(_VP)]),
+        "gdp_ctx_destroy": (None, [_VP]),
+        "gdp_last_error": (C.c_char_p, [_VP]),
+        "gdp_mesh_create": (S, [_VP, C.POINTER(gdp_pslg), C.POINTER(_VP)]),
+        "gdp_cdt_host": (S, [C.POINTER(gdp_pslg), _PI, C.c_int32, _PI, _PI, _PI, C.c_char_p, C.c_int32]),
+        "gdp_mesh_upload": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.c_int32, _PI, _PI, _PI, C.c_int32,
+                                C.c_int32, _PI, _PI, C.POINTER(C.c_uint8), C.c_int32, C.POINTER(_VP)]),
+        "gdp_mesh_refine": (S, [_VP, _VP, C.c_double, C.POINTER(gdp_params)]),
+        "gdp_refine": (S, [_VP, C.POINTER(gdp_pslg), C.c_double, C.POINTER(gdp_params), C.POINTER(_VP)]),
+        "gdp_mesh_info_get": (S, [_VP, C.POINTER(gdp_mesh_info)]),
+        "gdp_mesh_download": (S, [_VP, _VP, _PD, _PI, _PI, _PI, _PI, _PI, _PI, C.POINTER(C.c_uint8)]),
+        "gdp_mesh_round_stats": (S, [_VP, C.POINTER(gdp_round_stats), C.c_int32, _PI]),
+        "gdp_mesh_last_refine_ms": (S, [_VP, C.POINTER(C.c_double)]),
+        "gdp_mesh_free": (None, [_VP]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
+            "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
+            "gdp_mesh_info_get", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
+            "gdp_mesh_free"]
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _pslg(xy, seg):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    seg = np.ascontiguousarray(seg, dtype=np.int32).reshape(-1, 2)
+    p = gdp_pslg(xy.shape[0], _ptr(xy, C.c_double), seg.shape[0], _ptr(seg, C.c_int32))
+    return p, (xy, seg)
+
+
+def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256) -> gdp_params:
+    p = gdp_params()
+    load().gdp_params_default(C.byref(p))
+    p.cand_cap_K = cand_cap_K
+    p.priority_mode = priority_mode
+    p.max_rounds = max_rounds
+    p.block_size = block_size
+    return p
+
+
+def gdp_cdt_host(xy, seg):
+    """Line 1 on the host: canonical CDT arrays (tri, nbr, seg) of shape (T, 3)."""
+    lib = load()
+    p, keep = _pslg(xy, seg)
+    nt = C.c_int32(0)
+    err = C.create_string_buffer(256)
+    rc = lib.gdp_cdt_host(C.byref(p), C.byref(nt), 0, None, None, None, err, 256)
+    if rc != GDP_OK:
+        raise GdpError(rc, err.value.decode())
+    T = nt.value
+    tri = np.empty((T, 3), np.int32)
+    nbr = np.empty((T, 3), np.int32)
+    sg = np.empty((T, 3), np.int32)
+    rc = lib.gdp_cdt_host(C.byref(p), C.byref(nt), T, _ptr(tri, C.c_int32), _ptr(nbr, C.c_int32),
+                          _ptr(sg, C.c_int32), err, 256)
+    if rc != GDP_OK:
+        raise GdpError(rc, err.value.decode())
+    return tri, nbr, sg
+
+
+class Context:
+    """A device context bound to a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._h = _VP()
+        rc = lib.gdp_ctx_create(device, _VP(stream), C.byref(self._h))
+        if rc != GDP_OK:
+            raise GdpError(rc, lib.gdp_last_error(None).decode())
+        self.device = device
+
+    def check(self, rc: int, ok=(GDP_OK,)):
+        if rc not in ok:
+            raise GdpError(rc, load().gdp_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gdp_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, handle: _VP):
+        self.ctx = ctx
+        self._h = handle
+
+    def free(self):
+        if getattr(self, "_h", None):
+            load().gdp_mesh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = gdp_mesh_info()
+        self.ctx.check(load().gdp_mesh_info_get(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in gdp_mesh_info._fields_}
+
+    def arrays(self) -> dict:
+        lib = load()
+        i = self.info()
+        V, T, S = i["n_vertices"], i["n_triangles"], i["n_subsegments"]
+        xy = np.empty((V, 2), np.float64)
+        vk = np.empty(V, np.int32)
+        tv = np.empty((T, 3), np.int32)
+        tn = np.empty((T, 3), np.int32)
+        ts = np.empty((T, 3), np.int32)
+        sv = np.empty((max(S, 1), 2), np.int32)
+        sp = np.empty(max(S, 1), np.int32)
+        pe = np.empty(max(S, 1), np.uint8)
+        self.ctx.check(lib.gdp_mesh_download(self.ctx._h, self._h, _ptr(xy, C.c_double), _ptr(vk, C.c_int32),
+                                             _ptr(tv, C.c_int32), _ptr(tn, C.c_int32), _ptr(ts, C.c_int32),
+                                             _ptr(sv, C.c_int32), _ptr(sp, C.c_int32), _ptr(pe, C.c_uint8)))
+        return {"xy": xy, "vkind": vk, "tv": tv, "tn": tn, "ts": ts, "sv": sv[:S], "sparent": sp[:S],
+                "spend": pe[:S]}
+
+    def round_stats(self) -> list[dict]:
+        lib = load()
+        n = C.c_int32(0)
+        lib.gdp_mesh_round_stats(self._h, None, 0, C.byref(n))
+        arr = (gdp_round_stats * max(n.value, 1))()
+        lib.gdp_mesh_round_stats(self._h, arr, n.value, C.byref(n))
+        return [{f: getattr(arr[i], f) for f in STAT_FIELDS} for i in range(n.value)]
+
+    def last_refine_ms(self) -> float:
+        ms = C.c_double(0)
+        load().gdp_mesh_last_refine_ms(self._h, C.byref(ms))
+        return ms.value
+
+
+def gdp_mesh_create(ctx: Context, xy, seg) -> Mesh:
+    p, keep = _pslg(xy, seg)
+    h = _VP()
+    ctx.check(load().gdp_mesh_create(ctx._h, C.byref(p), C.byref(h)))
+    return Mesh(ctx, h)
+
+
+def gdp_mesh_upload(ctx: Context, arrays: dict, n_input_v: int, n_input_s: int, rounds: int = 0) -> Mesh:
+    a = {k: np.ascontiguousarray(v) for k, v in arrays.items()}
+    xy = np.ascontiguousarray(a["xy"], np.float64)
+    vk = np.ascontiguousarray(a["vkind"], np.int32)
+    tv = np.ascontiguousarray(a["tv"], np.int32)
+    tn = np.ascontiguousarray(a["tn"], np.int32)
+    ts = np.ascontiguousarray(a["ts"], np.int32)
+    sv = np.ascontiguousarray(a["sv"], np.int32)
+    sp = np.ascontiguousarray(a["sparent"], np.int32)
+    pe = np.ascontiguousarray(a["spend"], np.uint8)
+    h = _VP()
+    ctx.check(load().gdp_mesh_upload(ctx._h, xy.shape[0], n_input_v, _ptr(xy, C.c_double), _ptr(vk, C.c_int32),
+                                     tv.shape[0], _ptr(tv, C.c_int32), _ptr(tn, C.c_int32), _ptr(ts, C.c_int32),
+                                     sv.shape[0], n_input_s, _ptr(sv, C.c_int32), _ptr(sp, C.c_int32),
+                                     _ptr(pe, C.c_uint8), rounds, C.byref(h)))
+    return Mesh(ctx, h)
+
+
+def gdp_mesh_refine(ctx: Context, mesh: Mesh, ratio_bound_sq: float, params: gdp_params | None = None,
+                    allow_noterm: bool = False) -> int:
+    prm = params if params is not None else make_params()
+    rc = load().gdp_mesh_refine(ctx._h, mesh._h, float(ratio_bound_sq), C.byref(prm))
+    return ctx.check(rc, ok=(GDP_OK, -5) if allow_noterm else (GDP_OK,))
+
+
+def gdp_refine(ctx: Context, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> Mesh:
+    p, keep = _pslg(xy, seg)
+    prm = params if params is not None else make_params()
+    h = _VP()
+    ctx.check(load().gdp_refine(ctx._h, C.byref(p), float(ratio_bound_sq), C.byref(prm), C.byref(h)))
+    return Mesh(ctx, h)

@@ -1,0 +1,109 @@
+"""Parity of the HIP refinement path with the oracle: every array of the final
+mesh (vertex coordinates bitwise, triangles, neighbours, subsegment marks,
+subsegments, pending flags) and every per-round counter must be identical.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.parity_util import diff_arrays, diff_stats, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_00324_amd import gdp2d
+    return gdp2d.Context(0)
+
+
+def _check(ctx, p, **kw):
+    print(f"[parity] {p.name} {kw}", flush=True)
+    om, orc_rc = oracle_run(p, **kw)
+    gm, gpu_rc = gpu_run(ctx, p, **kw)
+    assert orc_rc == gpu_rc
+    a, b = om.arrays(), gm.arrays()
+    bad = diff_arrays(a, b)
+    assert not bad, bad
+    sd = diff_stats(om.stats, gm.round_stats())
+    assert not sd, sd
+    assert gm.info()["rounds"] == om.rounds
+    return om, gm
+
+
+SMALL = {
+    "bare_square": lambda: workloads.bare_square(),
+    "near_edge": lambda: workloads.near_edge_point(1e-3),
+    "c0": lambda: workloads.config0(),
+    "rand_60": lambda: workloads.random_small(31, 60, 5),
+    "rand_300": lambda: workloads.random_small(32, 300, 20),
+    "knn_2000": lambda: workloads.random_small(33, 2000, 100, pairing="knn"),
+    "circles_small": lambda: workloads.scaled_config2(6, 40, 100, seed=5),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_parity_small(ctx, name):
+    _check(ctx, SMALL[name]())
+
+
+@pytest.mark.parametrize("B2", [1.6 * 1.6, 4.0])
+def test_parity_other_bounds(ctx, B2):
+    p = workloads.random_small(41, 400, 20, bsq=B2)
+    _check(ctx, p)
+
+
+@pytest.mark.parametrize("K", [1, 7, 64])
+def test_parity_candidate_cap(ctx, K):
+    _check(ctx, workloads.random_small(42, 300, 15), cand_cap_K=K)
+
+
+def test_parity_priority_mode_one(ctx):
+    _check(ctx, workloads.random_small(43, 500, 25), priority_mode=1)
+
+
+def test_parity_round_cap_and_resume(ctx):
+    from paper_2007_00324_amd import gdp2d
+    p = workloads.random_small(44, 800, 40)
+    om, _ = oracle_run(p)
+    gm, rc = gpu_run(ctx, p, max_rounds=4)
+    assert rc == -5 and gm.info()["rounds"] == 4
+    gdp2d.gdp_mesh_refine(ctx, gm, p.ratio_bound_sq, gdp2d.make_params())
+    assert not diff_arrays(om.arrays(), gm.arrays())
+
+
+def test_parity_block_size_invariance(ctx):
+    p = workloads.random_small(45, 600, 30)
+    om, _ = oracle_run(p)
+    for bs in (64, 128, 512, 1024):
+        gm, _ = gpu_run(ctx, p, block_size=bs)
+        assert not diff_arrays(om.arrays(), gm.arrays()), bs
+
+
+def test_parity_from_uploaded_oracle_state(ctx):
+    """Phase entry: the oracle's state after 3 rounds, uploaded, refined on the GPU."""
+    import oracle
+    from paper_2007_00324_amd import gdp2d
+    p = workloads.random_small(46, 700, 35)
+    m3 = oracle.build_cdt(p.xy, p.seg)
+    oracle.refine(m3, 2.0, max_rounds=3)
+    full, _ = oracle_run(p)
+    g = gdp2d.gdp_mesh_upload(ctx, m3.arrays(), p.n_vertices, p.n_segments, rounds=3)
+    gdp2d.gdp_mesh_refine(ctx, g, 2.0, gdp2d.make_params())
+    assert not diff_arrays(full.arrays(), g.arrays())
+
+
+@pytest.mark.parametrize("case", ["c1_100k", "c2_32x200"])
+def test_parity_medium(ctx, case):
+    p = {"c1_100k": lambda: workloads.scaled_config1(100_000, 5_000),
+         "c2_32x200": lambda: workloads.scaled_config2(32, 200, 5_000)}[case]()
+    _check(ctx, p)
+
+
+def test_reruns_identical(ctx):
+    p = workloads.scaled_config1(20_000, 1_000, seed=9)
+    a, _ = gpu_run(ctx, p)
+    b, _ = gpu_run(ctx, p)
+    assert not diff_arrays(a.arrays(), b.arrays())
