@@ -84,8 +84,19 @@ typedef struct {
   /* perf only */
   int32_t block_size;       /* threads per workgroup for the per-element kernels
                                (64..1024, multiple of 64; 0 = default 256) */
-  int32_t reserved[6];
+  int32_t profile_kernels;  /* 1 = time every kernel launch with HIP events (adds
+                               overhead; read with gdp_mesh_kernel_profile) */
+  int32_t reserved[5];
 } gdp_params;
+
+/* Per-kernel totals of the last profiled gdp_mesh_refine. */
+typedef struct {
+  char name[24];
+  int64_t launches;
+  double total_ms;     /* sum of event-timed launch durations */
+  int64_t items;       /* work items over all launches (triangles, candidates, ...) */
+  int64_t alg_bytes;   /* algorithmic HBM bytes (filled for k_scan; 0 otherwise) */
+} gdp_kernel_prof;
 
 typedef struct {
   int32_t n_vertices, n_triangles, n_subsegments;
@@ -166,6 +177,18 @@ gdp_status gdp_mesh_round_stats(const gdp_mesh *mesh, gdp_round_stats *stats, in
    *ms = wall time between HIP events recorded before the first and after the
    last round on the context stream. */
 gdp_status gdp_mesh_last_refine_ms(const gdp_mesh *mesh, double *ms);
+
+/* Kernel timing table of the last refine run with profile_kernels = 1:
+   writes up to cap records, *n gets the number of kernel kinds. */
+gdp_status gdp_mesh_kernel_profile(const gdp_mesh *mesh, gdp_kernel_prof *out, int32_t cap, int32_t *n);
+
+/* Copies the state of src (vertices, triangles, subsegments, counters) into
+   dst on the device, growing dst only if it is too small; both meshes must
+   belong to ctx.  Used to restart refinement from a resident initial CDT. */
+gdp_status gdp_mesh_assign(gdp_ctx *ctx, gdp_mesh *dst, const gdp_mesh *src);
+
+/* New device mesh with the same state and capacities as src. */
+gdp_status gdp_mesh_clone(gdp_ctx *ctx, const gdp_mesh *src, gdp_mesh **out);
 
 void gdp_mesh_free(gdp_mesh *mesh);
 

@@ -46,7 +46,44 @@ struct gdp_mesh {
   int32_t wT = 0, wS = 0;      // workspace capacities (triangles, subsegments)
   std::vector<gdp_round_stats> stats;
   double last_ms = 0.0;
+  // optional per-kernel timing (HIP events around every launch)
+  bool prof = false;
+  struct ProfRec {
+    int id;
+    hipEvent_t a, b;
+    int64_t items, bytes;
+  };
+  std::vector<ProfRec> prof_pending;
+  double prof_ms[16] = {};
+  int64_t prof_launches[16] = {}, prof_items[16] = {}, prof_bytes[16] = {};
 };
+
+namespace {
+enum ProfId {
+  P_SCAN = 0, P_CAP, P_LOCATE, P_CAV_CC, P_CAV_MID, P_CAV_BIG, P_MARK, P_OWN, P_DEP, P_PREFIX,
+  P_WINNERS, P_RECORD, P_WRITE, P_FINISH, P_NUM
+};
+const char *kProfNames[P_NUM] = {"k_scan", "k_cap", "k_locate", "k_cavity_cc", "k_cavity_mid", "k_cavity_big",
+                                  "k_mark", "k_own", "k_dep", "k_prefix_sum", "k_winners", "k_record", "k_write",
+                                  "k_finish"};
+// Records HIP events around the launches issued in its scope (if enabled).
+struct Prof {
+  gdp_mesh *M;
+  int id;
+  hipEvent_t a = nullptr;
+  int64_t items, bytes;
+  Prof(gdp_mesh *M_, int id_, int64_t items_ = 0, int64_t bytes_ = 0) : M(M_), id(id_), items(items_), bytes(bytes_) {
+    if (M->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, M->ctx->stream);
+  }
+  ~Prof() {
+    if (!M->prof || !a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, M->ctx->stream);
+    M->prof_pending.push_back({id, a, b, items, bytes});
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -216,6 +253,7 @@ gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int n, int32_t *d_
   int ntiles = (n + kScanTileSize - 1) / kScanTileSize;
   if (ntiles < 1) ntiles = 1;
   if (ntiles > M->tiles_cap) return fail(ctx, GDP_E_NOMEM, "scan tile buffer too small");
+  Prof pr(M, P_PREFIX, n);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, in, out, n, M->tiles, mode);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, ntiles, d_total);
   if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, M->tiles);
@@ -316,6 +354,9 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   const int bs = P->block_size;
   const int pm = P->priority_mode;
   M->stats.clear();
+  M->prof = P->profile_kernels != 0;
+  for (int i = 0; i < 16; i++) { M->prof_ms[i] = 0; M->prof_launches[i] = M->prof_items[i] = M->prof_bytes[i] = 0; }
+  M->prof_pending.clear();
   hipEvent_t ev0, ev1;
   HIPCHECK(hipEventCreate(&ev0));
   HIPCHECK(hipEventCreate(&ev1));
@@ -325,11 +366,22 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     DevMesh &m = M->m;
     HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
     Work w = make_work(M, pm);
-    hipLaunchKernelGGL(k_scan, dim3(grid_for(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
+    size_t scan_rec = M->prof_pending.size();
+    {
+      Prof pr(M, P_SCAN, m.nT);
+      hipLaunchKernelGGL(k_scan, dim3(grid_for(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
+    }
     HIPCHECK(hipGetLastError());
     gdp_status st = read_counters(M);
     if (st) return st;
     int ncc = M->h_cnt->ncc, nmk = M->h_cnt->nmk;
+    if (M->prof && scan_rec < M->prof_pending.size())
+      // algorithmic bytes of the scan: every triangle record (16 B) and every
+      // vertex (16 B) read once, both records of every subsegment side
+      // (ts 16 B + side slot 4 B per side), the pending flags (4 B), the
+      // bad-triangle records written (elem 4 + key 8 + point 16 + state 4 B)
+      // and the flagged subsegments (flag 4 + list entry 8 B).
+      M->prof_pending[scan_rec].bytes = 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk;
     gdp_round_stats rs;
     memset(&rs, 0, sizeof rs);
     rs.n_bad = ncc;
@@ -345,6 +397,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     bool capped = P->cand_cap_K > 0 && ncc + nmk > P->cand_cap_K;
     if (capped) {
       int n = ncc + nmk;
+      Prof pr(M, P_CAP, n);
       hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(n, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm);
       uint64_t prefix = 0, pmask = 0;
       int64_t remaining = P->cand_cap_K;
@@ -372,13 +425,19 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       rs.n_kept_mid = nmk;
     }
     // ---- R4: locate ----
-    hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
+    {
+      Prof pr(M, P_LOCATE, ncc);
+      hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
+    }
     HIPCHECK(hipGetLastError());
     if ((st = read_counters(M))) return st;
     DevCounters snap = *M->h_cnt;
     // ---- R5/R6: cavities (rerun from here if the pool overflows) ----
     for (int attempt = 0;; attempt++) {
-      hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
+      {
+        Prof pr(M, P_CAV_CC, ncc);
+        hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
+      }
       HIPCHECK(hipGetLastError());
       if ((st = read_counters(M))) return st;
       // Midpoint cavities; a large circumcenter cavity handled by the
@@ -387,12 +446,18 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       int big_done = 0;
       for (int pass = 0;; pass++) {
         nmk = M->h_cnt->nmk;
-        hipLaunchKernelGGL(k_cavity, dim3(grid_for(nmk, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, nmk, 0);
+        {
+          Prof pr(M, P_CAV_MID, nmk);
+          hipLaunchKernelGGL(k_cavity, dim3(grid_for(nmk, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, nmk, 0);
+        }
         HIPCHECK(hipGetLastError());
         if ((st = read_counters(M))) return st;
         int nbig = std::min(M->h_cnt->nbig, M->wT);
         if (nbig > big_done) {
-          hipLaunchKernelGGL(k_cavity_big, dim3(nbig - big_done), dim3(kBigBlockSize), 0, s, m, w, big_done, nbig);
+          {
+            Prof pr(M, P_CAV_BIG, nbig - big_done);
+            hipLaunchKernelGGL(k_cavity_big, dim3(nbig - big_done), dim3(kBigBlockSize), 0, s, m, w, big_done, nbig);
+          }
           HIPCHECK(hipGetLastError());
           big_done = nbig;
           if ((st = read_counters(M))) return st;
@@ -438,9 +503,18 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     {
       int ncand = ncc + nmk;
       // ---- R8/R9 ----
-      hipLaunchKernelGGL(k_mark, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
-      hipLaunchKernelGGL(k_own, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
-      hipLaunchKernelGGL(k_dep, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm, B2);
+      {
+        Prof pr(M, P_MARK, ncand);
+        hipLaunchKernelGGL(k_mark, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      }
+      {
+        Prof pr(M, P_OWN, ncand);
+        hipLaunchKernelGGL(k_own, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      }
+      {
+        Prof pr(M, P_DEP, ncand);
+        hipLaunchKernelGGL(k_dep, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm, B2);
+      }
       HIPCHECK(hipGetLastError());
       // ---- R10: ranks ----
       if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.nS), &M->d_cnt->nwin_mid, 1))) return st;
@@ -449,7 +523,10 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       int nwin_mid = M->h_cnt->nwin_mid, nwin_cc = M->h_cnt->nwin_cc, nwin = nwin_mid + nwin_cc;
       if (nwin == 0) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); goto done; }
       HIPCHECK(hipMemsetAsync(M->fan_off, 0, sizeof(int32_t) * (nwin + 1), s));
-      hipLaunchKernelGGL(k_winners, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, nwin_mid);
+      {
+        Prof pr(M, P_WINNERS, ncand);
+        hipLaunchKernelGGL(k_winners, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, nwin_mid);
+      }
       if (getenv("GDP_DEBUG")) {
         if ((st = read_counters(M))) return st;
         fprintf(stderr, "[gdp] round %d ncc %d nmk %d nwin_mid %d nwin_cc %d win_cands %d dbg_set %d dbg %d %d %d %d pool %d/%d\n",
@@ -473,9 +550,18 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
         M->fan_cap = (int32_t)nc;
       }
       w = make_work(M, pm);
-      hipLaunchKernelGGL(k_record, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
-      hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
-      hipLaunchKernelGGL(k_finish, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk, m.spend);
+      {
+        Prof pr(M, P_RECORD, nwin);
+        hipLaunchKernelGGL(k_record, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
+      }
+      {
+        Prof pr(M, P_WRITE, nwin);
+        hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
+      }
+      {
+        Prof pr(M, P_FINISH, ncand);
+        hipLaunchKernelGGL(k_finish, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk, m.spend);
+      }
       HIPCHECK(hipGetLastError());
       HIPCHECK(hipMemsetAsync(M->w0_t, 0, sizeof(uint32_t) * words(m.nT), s));
       HIPCHECK(hipMemsetAsync(M->win_t, 0, sizeof(uint32_t) * words(m.nT), s));
@@ -520,6 +606,19 @@ done:
   float ms = 0.f;
   HIPCHECK(hipEventElapsedTime(&ms, ev0, ev1));
   M->last_ms = ms;
+  for (auto &r : M->prof_pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      M->prof_ms[r.id] += t;
+      M->prof_launches[r.id] += 1;
+      M->prof_items[r.id] += r.items;
+      M->prof_bytes[r.id] += r.bytes;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  M->prof_pending.clear();
+  M->prof = false;
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   return result;
@@ -731,6 +830,91 @@ gdp_status gdp_mesh_round_stats(const gdp_mesh *mesh, gdp_round_stats *stats, in
 gdp_status gdp_mesh_last_refine_ms(const gdp_mesh *mesh, double *ms) {
   if (!mesh || !ms) return GDP_E_ARG;
   *ms = mesh->last_ms;
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_kernel_profile(const gdp_mesh *mesh, gdp_kernel_prof *out, int32_t cap, int32_t *n) {
+  if (!mesh || !n) return GDP_E_ARG;
+  *n = P_NUM;
+  if (out)
+    for (int i = 0; i < std::min<int>(cap, P_NUM); i++) {
+      memset(&out[i], 0, sizeof out[i]);
+      snprintf(out[i].name, sizeof out[i].name, "%s", kProfNames[i]);
+      out[i].launches = mesh->prof_launches[i];
+      out[i].total_ms = mesh->prof_ms[i];
+      out[i].items = mesh->prof_items[i];
+      out[i].alg_bytes = mesh->prof_bytes[i];
+    }
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_assign(gdp_ctx *ctx, gdp_mesh *dst, const gdp_mesh *src) {
+  if (!ctx || !dst || !src || dst->ctx != ctx || src->ctx != ctx || dst == src) return GDP_E_ARG;
+  gdp_status st;
+  const DevMesh &a = src->m;
+  if ((st = grow_vtx(dst, a.nV))) return st;
+  if ((st = grow_tri(dst, a.nT))) return st;
+  if ((st = grow_seg(dst, a.nS))) return st;
+  if ((st = grow_cand(dst))) return st;
+  DevMesh &b = dst->m;
+  hipStream_t s = ctx->stream;
+  HIPCHECK(hipMemcpyAsync(b.vxy, a.vxy, sizeof(double2) * a.nV, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(hipMemcpyAsync(b.vkind, a.vkind, sizeof(int32_t) * a.nV, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(hipMemcpyAsync(b.tv, a.tv, sizeof(int4) * a.nT, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(hipMemcpyAsync(b.tn, a.tn, sizeof(int4) * a.nT, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(hipMemcpyAsync(b.ts, a.ts, sizeof(int4) * a.nT, hipMemcpyDeviceToDevice, s));
+  if (a.nS) {
+    HIPCHECK(hipMemcpyAsync(b.sv, a.sv, sizeof(int2) * a.nS, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(b.spar, a.spar, sizeof(int32_t) * a.nS, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(b.spend, a.spend, sizeof(int32_t) * a.nS, hipMemcpyDeviceToDevice, s));
+  }
+  // per-round workspace back to its between-rounds state
+  HIPCHECK(hipMemsetAsync(dst->mark, 0, sizeof(uint64_t) * b.capT, s));
+  HIPCHECK(hipMemsetAsync(dst->mflag, 0, sizeof(uint32_t) * b.capS, s));
+  HIPCHECK(hipMemsetAsync(dst->sadj, 0xff, sizeof(int32_t) * 2 * (size_t)b.capS, s));
+  HIPCHECK(hipMemsetAsync(dst->w0_t, 0, sizeof(uint32_t) * words(b.capT), s));
+  HIPCHECK(hipMemsetAsync(dst->win_t, 0, sizeof(uint32_t) * words(b.capT), s));
+  HIPCHECK(hipMemsetAsync(dst->w0_s, 0, sizeof(uint32_t) * words(b.capS), s));
+  HIPCHECK(hipMemsetAsync(dst->win_s, 0, sizeof(uint32_t) * words(b.capS), s));
+  b.nV = a.nV; b.nT = a.nT; b.nS = a.nS;
+  b.n_input_v = a.n_input_v; b.n_input_s = a.n_input_s; b.rounds = a.rounds;
+  HIPCHECK(hipStreamSynchronize(s));
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_clone(gdp_ctx *ctx, const gdp_mesh *src, gdp_mesh **out) {
+  if (!ctx || !src || !out || src->ctx != ctx) return GDP_E_ARG;
+  *out = nullptr;
+  gdp_mesh *M = new gdp_mesh();
+  M->ctx = ctx;
+  gdp_status st;
+  auto chk = [&](hipError_t e) { return e == hipSuccess; };
+  if ((st = grow_vtx(M, src->m.capV)) || (st = grow_tri(M, src->m.capT)) || (st = grow_seg(M, src->m.capS)) ||
+      (st = grow_cand(M))) {
+    free_mesh_arrays(M);
+    delete M;
+    return st;
+  }
+  if (!chk(dalloc(&M->d_cnt, 1)) || !chk(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters))) ||
+      !chk(hipHostMalloc((void **)&M->h_small, 1024 * sizeof(int32_t))) || !chk(dalloc(&M->hist, 256)) ||
+      !chk(dalloc(&M->thresh, 1))) {
+    free_mesh_arrays(M);
+    delete M;
+    return fail(ctx, GDP_E_NOMEM, "allocation failed");
+  }
+  M->pool_cap = src->pool_cap;
+  M->fan_cap = src->fan_cap;
+  if (!chk(dalloc(&M->pool, M->pool_cap)) || !chk(dalloc(&M->fan, M->fan_cap))) {
+    free_mesh_arrays(M);
+    delete M;
+    return fail(ctx, GDP_E_NOMEM, "allocation failed");
+  }
+  if ((st = gdp_mesh_assign(ctx, M, src))) {
+    free_mesh_arrays(M);
+    delete M;
+    return st;
+  }
+  *out = M;
   return GDP_OK;
 }
 

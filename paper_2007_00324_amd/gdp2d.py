@@ -35,7 +35,12 @@ class gdp_pslg(C.Structure):
 class gdp_params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("profile_kernels", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class gdp_kernel_prof(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("items", C.c_int64), ("alg_bytes", C.c_int64)]
 
 
 class gdp_mesh_info(C.Structure):
@@ -84,6 +89,9 @@ def load() -> C.CDLL:
         "gdp_mesh_download": (S, [_VP, _VP, _PD, _PI, _PI, _PI, _PI, _PI, _PI, C.POINTER(C.c_uint8)]),
         "gdp_mesh_round_stats": (S, [_VP, C.POINTER(gdp_round_stats), C.c_int32, _PI]),
         "gdp_mesh_last_refine_ms": (S, [_VP, C.POINTER(C.c_double)]),
+        "gdp_mesh_kernel_profile": (S, [_VP, C.POINTER(gdp_kernel_prof), C.c_int32, _PI]),
+        "gdp_mesh_assign": (S, [_VP, _VP, _VP]),
+        "gdp_mesh_clone": (S, [_VP, _VP, C.POINTER(_VP)]),
         "gdp_mesh_free": (None, [_VP]),
     }
     for name, (res, args) in sig.items():
@@ -98,7 +106,7 @@ def exported_symbols() -> list[str]:
     return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
             "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
             "gdp_mesh_info_get", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
-            "gdp_mesh_free"]
+            "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -112,9 +120,10 @@ def _pslg(xy, seg):
     return p, (xy, seg)
 
 
-def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256) -> gdp_params:
+def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
+    p.profile_kernels = profile_kernels
     p.cand_cap_K = cand_cap_K
     p.priority_mode = priority_mode
     p.max_rounds = max_rounds
@@ -219,6 +228,22 @@ class Mesh:
         arr = (gdp_round_stats * max(n.value, 1))()
         lib.gdp_mesh_round_stats(self._h, arr, n.value, C.byref(n))
         return [{f: getattr(arr[i], f) for f in STAT_FIELDS} for i in range(n.value)]
+
+    def kernel_profile(self) -> list[dict]:
+        lib = load()
+        n = C.c_int32(0)
+        arr = (gdp_kernel_prof * 32)()
+        self.ctx.check(lib.gdp_mesh_kernel_profile(self._h, arr, 32, C.byref(n)))
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                 "items": arr[i].items, "alg_bytes": arr[i].alg_bytes} for i in range(n.value)]
+
+    def assign_from(self, src: "Mesh"):
+        self.ctx.check(load().gdp_mesh_assign(self.ctx._h, self._h, src._h))
+
+    def clone(self) -> "Mesh":
+        h = _VP()
+        self.ctx.check(load().gdp_mesh_clone(self.ctx._h, self._h, C.byref(h)))
+        return Mesh(self.ctx, h)
 
     def last_refine_ms(self) -> float:
         ms = C.c_double(0)
