@@ -60,6 +60,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration) and exit")
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
     ap.add_argument("--segments", type=int, default=50_000, help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -69,6 +71,15 @@ def main() -> int:
         return 2
 
     import torch
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n * 4} bytes three times")
+        return 0
     import workloads
     from paper_2007_00324_amd import gdp2d
 
