@@ -79,8 +79,11 @@ typedef struct {
                                round (Rule 2 filter as a candidate limit) */
   int32_t priority_mode;    /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
   int32_t max_rounds;       /* 0 = no cap; else stop with GDP_E_NOTERM */
-  int32_t prefilter_f1;     /* must be 0 */
-  int32_t cavity_approx_n;  /* must be 0 */
+  int32_t prefilter_f1;     /* 1: keep one circumcenter per located triangle, the
+                               largest key (Line 6 filter, Section 4.3) */
+  int32_t cavity_approx_n;  /* 0 = off; 1..16: drop a circumcenter that does not hold
+                               the largest key on the first n triangles of its
+                               cavity growth order (Line 7 filter, Section 4.3) */
   /* perf only */
   int32_t block_size;       /* threads per workgroup for the per-element kernels
                                (64..1024, multiple of 64; 0 = default 256) */
@@ -110,6 +113,7 @@ typedef struct {
   int64_t n_blocked, n_coincident, n_enc_reject, n_mid_cand, n_unsplittable;
   int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
   int64_t cav_tri_total, cav_max, n_big_cavities;
+  int64_t n_f1_drop, n_f2_drop;
 } gdp_round_stats;
 
 /* Fills *p with the defaults (all zero, block_size 256). */

@@ -33,7 +33,8 @@ class _Params(C.Structure):
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident",
                "n_enc_reject", "n_mid_cand", "n_unsplittable", "n_fan_invalid", "n_lost_mark",
-               "n_dep_drop", "n_ins_mid", "n_ins_cc", "cav_tri_total", "cav_max", "walk_steps"]
+               "n_dep_drop", "n_ins_mid", "n_ins_cc", "cav_tri_total", "cav_max", "walk_steps",
+               "n_f1_drop", "n_f2_drop"]
 
 
 class _Stats(C.Structure):
@@ -212,9 +213,10 @@ def build_cdt(xy: np.ndarray, seg: np.ndarray) -> OracleMesh:
 
 
 def refine(mesh: OracleMesh, ratio_bound_sq: float, cand_cap_K: int = 0, priority_mode: int = 0,
-           max_rounds: int = 0, stats_cap: int = 1 << 16, raise_on_error: bool = True) -> int:
+           max_rounds: int = 0, stats_cap: int = 1 << 16, raise_on_error: bool = True,
+           prefilter_f1: int = 0, cavity_approx_n: int = 0) -> int:
     lib = load()
-    prm = _Params(cand_cap_K, priority_mode, max_rounds, 0, 0)
+    prm = _Params(cand_cap_K, priority_mode, max_rounds, prefilter_f1, cavity_approx_n)
     st = (_Stats * stats_cap)()
     ns = C.c_int32(0)
     err = C.create_string_buffer(256)

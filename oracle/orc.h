@@ -62,8 +62,9 @@ typedef struct orc_params {
   int32_t cand_cap_K;     /* 0 = unlimited; else keep the K largest keys per round */
   int32_t priority_mode;  /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
   int32_t max_rounds;     /* stop after this many rounds (ORC_E_NOTERM if work left) */
-  int32_t prefilter_f1;   /* must be 0 (not implemented in the oracle yet) */
-  int32_t cavity_approx_n;/* must be 0 (not implemented in the oracle yet) */
+  int32_t prefilter_f1;   /* 1: keep one circumcenter per located triangle (max key) */
+  int32_t cavity_approx_n;/* n > 0: drop circumcenters that lose a mark on the first
+                             n triangles of their cavity growth order */
 } orc_params;
 
 typedef struct orc_round_stats {
@@ -71,6 +72,7 @@ typedef struct orc_round_stats {
   int64_t n_blocked, n_coincident, n_enc_reject, n_mid_cand, n_unsplittable;
   int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
   int64_t cav_tri_total, cav_max, walk_steps;
+  int64_t n_f1_drop, n_f2_drop;
 } orc_round_stats;
 
 /* Builds the canonical CDT of the PSLG.  xy: 2*nv doubles; seg: 2*ns vertex ids.

@@ -241,6 +241,33 @@ static int edge_index(const orc_mesh *m, int32_t t, int32_t u, int32_t v) {
   return -1;
 }
 
+/* The first n triangles of the cavity growth order (seed, then breadth
+   first across non-subsegment edges whose far triangle's circumcircle
+   strictly holds p, edges in index order); stops as soon as n are taken. */
+static int32_t approx_cavity(const orc_mesh *m, int32_t seed, const double *p, int32_t n,
+                             int32_t *stamp, int32_t epoch, int32_t *out) {
+  int32_t len = 0;
+  out[len++] = seed;
+  stamp[seed] = epoch;
+  for (int32_t h = 0; h < len && len < n; h++) {
+    int32_t t = out[h];
+    for (int i = 0; i < 3 && len < n; i++) {
+      if (m->ts[3 * t + i] >= 0) continue;
+      int32_t o = m->tn[3 * t + i];
+      if (o < 0 || stamp[o] == epoch) continue;
+      double a[2], b[2], c[2];
+      vxy(m, m->tv[3 * o], a);
+      vxy(m, m->tv[3 * o + 1], b);
+      vxy(m, m->tv[3 * o + 2], c);
+      if (orc_incircle(a, b, c, p) > 0) {
+        stamp[o] = epoch;
+        out[len++] = o;
+      }
+    }
+  }
+  return len;
+}
+
 /* One round.  Returns 1 if the mesh had nothing to refine, 0 after a round,
    <0 on error. */
 static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_stats *st,
@@ -269,6 +296,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
   int32_t *wl = NULL;
   int64_t *foff = NULL;
   uint64_t *keys = NULL;
+  int32_t *tloc = NULL;
   if (!enc || !mflag || !sadj || !bad || !tpx || !tpy || !tkey || !mark || !markc || !stamp) {
     rc = ORC_E_NOMEM;
     goto out;
@@ -331,7 +359,10 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
     }
 
   /* ---- R4: locate circumcenters ---- */
+  tloc = malloc(sizeof(int32_t) * ((size_t)nT + 1));
+  if (!tloc) { rc = ORC_E_NOMEM; goto out; }
   for (int32_t t = 0; t < nT; t++) {
+    tloc[t] = -1;
     if (!bad[t] || tkey[t] < thresh) continue;
     if (st) st->n_kept_cc++;
     double p[2] = {tpx[t], tpy[t]};
@@ -377,7 +408,60 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
       if (st) st->n_blocked++;
       continue;
     }
-    /* ---- R5: circumcenter cavity ---- */
+    tloc[t] = cur;
+  }
+
+  /* ---- F1 (Line 6, optional): one circumcenter per located triangle, the
+     highest priority one ---- */
+  if (prm->prefilter_f1) {
+    for (int32_t t = 0; t < nT; t++)
+      if (tloc[t] >= 0 && tkey[t] > mark[tloc[t]]) mark[tloc[t]] = tkey[t];
+    for (int32_t t = 0; t < nT; t++)
+      if (tloc[t] >= 0 && mark[tloc[t]] != tkey[t]) {
+        tloc[t] = -1;
+        if (st) st->n_f1_drop++;
+      }
+    for (int32_t t = 0; t < nT; t++) mark[t] = 0;
+  }
+
+  /* ---- F2 (Line 7, optional): approximate cavities of n triangles, first
+     n of the growth order; a circumcenter that does not hold the largest key
+     on all of them is dropped ---- */
+  if (prm->cavity_approx_n > 0) {
+    int32_t n = prm->cavity_approx_n;
+    int32_t *ap = malloc(sizeof(int32_t) * (size_t)n);
+    if (!ap) { rc = ORC_E_NOMEM; goto out; }
+    int32_t epoch = 0x40000000;
+    for (int pass = 0; pass < 2; pass++) {
+      for (int32_t t = 0; t < nT; t++) {
+        if (tloc[t] < 0) continue;
+        double p[2] = {tpx[t], tpy[t]};
+        int32_t len = approx_cavity(m, tloc[t], p, n, stamp, epoch++, ap);
+        int own = 1;
+        for (int32_t j = 0; j < len; j++) {
+          if (pass == 0) { if (tkey[t] > mark[ap[j]]) mark[ap[j]] = tkey[t]; }
+          else if (mark[ap[j]] != tkey[t]) own = 0;
+        }
+        if (pass == 1 && !own) {
+          tloc[t] = -2; /* dropped; marks of pass 0 stay until cleared below */
+          if (st) st->n_f2_drop++;
+        }
+      }
+    }
+    free(ap);
+    for (int32_t t = 0; t < nT; t++) {
+      mark[t] = 0;
+      stamp[t] = -1;
+    }
+    for (int32_t t = 0; t < nT; t++)
+      if (tloc[t] == -2) tloc[t] = -1;
+  }
+
+  /* ---- R5: circumcenter cavities ---- */
+  for (int32_t t = 0; t < nT; t++) {
+    if (tloc[t] < 0) continue;
+    double p[2] = {tpx[t], tpy[t]};
+    int32_t cur = tloc[t];
     if (ncand + 1 > capcand) {
       capcand = capcand ? capcand * 2 : 1024;
       cand *a = realloc(cands, sizeof(cand) * (size_t)capcand);
@@ -601,7 +685,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
 out:
   free(enc); free(mflag); free(sadj); free(bad); free(tpx); free(tpy); free(tkey);
   free(mark); free(markc); free(stamp); free(cands); free(pool.a); free(bb); free(fr);
-  free(repl); free(inW); free(wl); free(foff); free(keys);
+  free(repl); free(inW); free(wl); free(foff); free(keys); free(tloc);
   return rc;
 }
 
@@ -610,7 +694,7 @@ int orc_refine(orc_mesh *m, double B2, const orc_params *p, orc_round_stats *sta
   if (err && errlen > 0) err[0] = 0;
   if (n_stats) *n_stats = 0;
   if (!m || !p || !(B2 > 0.0) || !isfinite(B2)) { set_err(err, errlen, "bad arguments"); return ORC_E_ARG; }
-  if (p->prefilter_f1 != 0 || p->cavity_approx_n != 0 || p->cand_cap_K < 0 ||
+  if ((p->prefilter_f1 != 0 && p->prefilter_f1 != 1) || p->cavity_approx_n < 0 || p->cand_cap_K < 0 ||
       (p->priority_mode != 0 && p->priority_mode != 1)) {
     set_err(err, errlen, "unsupported parameter");
     return ORC_E_ARG;

@@ -37,6 +37,12 @@ struct gdp_mesh {
   FanRec *fan = nullptr;
   int32_t fan_cap = 0;
   int32_t *big = nullptr;
+  int32_t *prev_cc_elem = nullptr;
+  uint64_t *prev_cc_key = nullptr;
+  double2 *prev_cc_p = nullptr;
+  int32_t *prev_mid_elem = nullptr;
+  int32_t *tstamp = nullptr;
+  int32_t serial = 0;  // rounds ever executed on this mesh object (slot stamps)
   uint64_t *keys = nullptr;
   int32_t *hist = nullptr;
   uint64_t *thresh = nullptr;
@@ -155,6 +161,10 @@ gdp_status grow_tri(gdp_mesh *M, int32_t need) {
   HIPCHECK(dgrow(&M->win_t, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->rank_t, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->repl, 4 * (size_t)oc, 4 * (size_t)nc, 0, 0xff, s));
+  HIPCHECK(dgrow(&M->prev_cc_elem, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->prev_cc_key, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->prev_cc_p, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->tstamp, oc, nc, oc, 0xff, s));
   M->m.capT = nc;
   return GDP_OK;
 }
@@ -180,6 +190,7 @@ gdp_status grow_seg(gdp_mesh *M, int32_t need) {
   HIPCHECK(dgrow(&M->mid.state, om, nm, om, 0, s));
   HIPCHECK(dgrow(&M->mid.off, om, nm, om, 0, s));
   HIPCHECK(dgrow(&M->mid.len, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->prev_mid_elem, om, nm, om, 0, s));
   HIPCHECK(dgrow(&M->w0_s, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->win_s, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->rank_s, words(oc), words(nc), words(oc), 0, s));
@@ -238,6 +249,8 @@ Work make_work(gdp_mesh *M, int pm) {
   w.pool = M->pool; w.pool_cap = M->pool_cap;
   w.fan = M->fan; w.fan_cap = M->fan_cap;
   w.big = M->big; w.big_cap = M->wT;
+  w.prev_cc_elem = M->prev_cc_elem; w.prev_cc_key = M->prev_cc_key; w.prev_cc_p = M->prev_cc_p;
+  w.prev_mid_elem = M->prev_mid_elem; w.tstamp = M->tstamp;
   w.keys = M->keys; w.hist = M->hist; w.thresh = M->thresh;
   w.pm = pm;
   return w;
@@ -275,7 +288,7 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
                   M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->hist, M->thresh,
-                  M->tiles};
+                  M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
@@ -362,14 +375,23 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   HIPCHECK(hipEventCreate(&ev1));
   HIPCHECK(hipEventRecord(ev0, s));
   gdp_status result = GDP_OK;
+  // The first round of a call tests every element; later rounds carry the
+  // previous bad list over and re-test only the slots the last round wrote.
+  bool full_scan = true;
+  int prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
   for (;;) {
     DevMesh &m = M->m;
     HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
     Work w = make_work(M, pm);
     size_t scan_rec = M->prof_pending.size();
-    {
+    if (full_scan) {
       Prof pr(M, P_SCAN, m.nT);
       hipLaunchKernelGGL(k_scan, dim3(grid_for(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
+    } else {
+      Prof pr(M, P_SCAN, (int64_t)prev_ncc + prev_fan + prev_nmk);
+      hipLaunchKernelGGL(k_carry, dim3(grid_for(prev_ncc, bs)), dim3(bs), 0, s, w, prev_ncc, M->serial - 1);
+      hipLaunchKernelGGL(k_scan_dirty, dim3(grid_for(prev_fan, bs)), dim3(bs), 0, s, m, w, prev_fan, B2, pm);
+      hipLaunchKernelGGL(k_pending, dim3(grid_for(prev_nmk, bs)), dim3(bs), 0, s, m, w, prev_nmk);
     }
     HIPCHECK(hipGetLastError());
     gdp_status st = read_counters(M);
@@ -381,7 +403,12 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       // (ts 16 B + side slot 4 B per side), the pending flags (4 B), the
       // bad-triangle records written (elem 4 + key 8 + point 16 + state 4 B)
       // and the flagged subsegments (flag 4 + list entry 8 B).
-      M->prof_pending[scan_rec].bytes = 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk;
+      M->prof_pending[scan_rec].bytes =
+          full_scan ? 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk
+                    // incremental: carried records (elem 4 + key 8 + point 16 read, the same written, stamp
+                    // 4), each rewritten slot (fan slot 4 + triangle record 16 + three vertices 48) and the
+                    // previous flagged list (4 + pending flag 4), plus the new bad records and flags
+                    : 64LL * prev_ncc + 68LL * prev_fan + 8LL * prev_nmk + 32LL * ncc + 12LL * nmk;
     gdp_round_stats rs;
     memset(&rs, 0, sizeof rs);
     rs.n_bad = ncc;
@@ -430,6 +457,18 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
     }
     HIPCHECK(hipGetLastError());
+    // ---- optional prefilters F1 / F2 on located circumcenters ----
+    if (P->prefilter_f1) {
+      for (int mode = 0; mode < 3; mode++)
+        hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode, 0);
+      HIPCHECK(hipGetLastError());
+    }
+    if (P->cavity_approx_n > 0) {
+      for (int mode = 3; mode < 6; mode++)
+        hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode,
+                           P->cavity_approx_n);
+      HIPCHECK(hipGetLastError());
+    }
     if ((st = read_counters(M))) return st;
     DevCounters snap = *M->h_cnt;
     // ---- R5/R6: cavities (rerun from here if the pool overflows) ----
@@ -556,7 +595,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       }
       {
         Prof pr(M, P_WRITE, nwin);
-        hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
+        hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin, M->serial);
       }
       {
         Prof pr(M, P_FINISH, ncand);
@@ -593,11 +632,23 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       rs.cav_max = c.cav_max;
       rs.n_big_cavities = c.nbig;
       rs.n_mid_cand = c.n_mid_cand;
+      rs.n_f1_drop = c.n_f1_drop;
+      rs.n_f2_drop = c.n_f2_drop;
       M->stats.push_back(rs);
       m.nV += nwin;
       m.nT += fresh;
       m.nS += nwin_mid;
       m.rounds += 1;
+      M->serial += 1;
+      // this round's lists become the previous ones
+      prev_ncc = ncc;
+      prev_nmk = nmk;
+      prev_fan = c.fan_used;
+      std::swap(M->cc.elem, M->prev_cc_elem);
+      std::swap(M->cc.key, M->prev_cc_key);
+      std::swap(M->cc.p, M->prev_cc_p);
+      std::swap(M->mid.elem, M->prev_mid_elem);
+      full_scan = false;
     }
   }
 done:
@@ -737,7 +788,9 @@ gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, 
   if (params) P = *params; else gdp_params_default(&P);
   if (P.block_size == 0) P.block_size = 256;
   if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(ctx, GDP_E_ARG, "bad ratio bound");
-  if (P.prefilter_f1 != 0 || P.cavity_approx_n != 0) return fail(ctx, GDP_E_ARG, "prefilters are not supported");
+  if (P.prefilter_f1 != 0 && P.prefilter_f1 != 1) return fail(ctx, GDP_E_ARG, "prefilter_f1 must be 0 or 1");
+  if (P.cavity_approx_n < 0 || P.cavity_approx_n > kApproxMaxN)
+    return fail(ctx, GDP_E_ARG, "cavity_approx_n must be in [0, 16]");
   if (P.cand_cap_K < 0 || P.max_rounds < 0 || (P.priority_mode != 0 && P.priority_mode != 1))
     return fail(ctx, GDP_E_ARG, "bad parameter");
   if (P.block_size < 64 || P.block_size > 1024 || P.block_size % 64) return fail(ctx, GDP_E_ARG, "bad block size");

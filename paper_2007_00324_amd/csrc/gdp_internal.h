@@ -58,6 +58,7 @@ struct DevCounters {
   int32_t n_mid_cand;  // midpoint candidates that reached the cavity step
   int32_t dbg_set;     // first failing insertion record: set flag
   int32_t dbg[6];      // class, element, cavity size, expected fan size, found fan size, round-local index
+  int32_t n_f1_drop, n_f2_drop;
   int32_t pad[2];
 };
 

@@ -31,6 +31,12 @@ struct Work {
   int32_t fan_cap;
   int32_t *big;
   int32_t big_cap;
+  // previous round's lists (incremental collection) and slot stamps
+  int32_t *prev_cc_elem;
+  uint64_t *prev_cc_key;
+  double2 *prev_cc_p;
+  int32_t *prev_mid_elem;
+  int32_t *tstamp;     // [capT] serial of the round that last wrote the slot
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
   int32_t *hist;       // [256]
   uint64_t *thresh;    // [1]
@@ -38,10 +44,15 @@ struct Work {
 };
 
 __global__ void k_scan(DevMesh m, Work w, double B2, int pm);
+__global__ void k_carry(Work w, int n_prev, int prev_serial);
+__global__ void k_scan_dirty(DevMesh m, Work w, int n_dirty, double B2, int pm);
+__global__ void k_pending(DevMesh m, Work w, int n_prev);
 __global__ void k_gather_keys(DevMesh m, Work w, int ncc, int nmk, int pm);
 __global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t pmask);
 __global__ void k_apply_cap(Work w, int ncc, int nmk);
 __global__ void k_locate(DevMesh m, Work w, int ncc);
+__global__ void k_prefilter(DevMesh m, Work w, int ncc, int mode, int n);
+constexpr int kApproxMaxN = 16;
 __global__ void k_cavity(DevMesh m, Work w, int n, int is_cc);
 __global__ void k_cavity_big(DevMesh m, Work w, int first, int nbig);
 __global__ void k_mark(Work w, int ncc, int nmk);
@@ -52,7 +63,7 @@ __global__ void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total);
 __global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums);
 __global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid);
 __global__ void k_record(DevMesh m, Work w, int nwin);
-__global__ void k_write(DevMesh m, Work w, int nwin);
+__global__ void k_write(DevMesh m, Work w, int nwin, int serial);
 __global__ void k_unflag(Work w, int nmk);
 __global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend);
 

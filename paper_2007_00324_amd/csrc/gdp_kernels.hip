@@ -170,35 +170,103 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int v) {
 // ---------------------------------------------------------------------------
 // R1: collect encroached subsegments and bad triangles (Line 3)
 // ---------------------------------------------------------------------------
-__global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false;
-  SplitPt r;
-  if (i < m.nT) {
-    int4 tri = m.tv[i];
-    if (tri.w) {
-      int4 s = m.ts[i];
-      for (int e = 0; e < 3; e++) {
-        if (!((tri.w >> e) & 1)) continue;
-        int k = comp(s, e);
-        int u = comp(tri, e), v = comp(tri, (e + 1) % 3), c = comp(tri, (e + 2) % 3);
-        int side = (u == m.sv[k].x) ? 0 : 1;
-        w.sadj[2 * k + side] = i * 4 + e;
-        double2 U = m.vxy[u], V = m.vxy[v], Cc = m.vxy[c];
-        if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0) flag_mid(w, k);
-      }
+// Tests one triangle: subsegment sides + encroaching apex, and badness.
+__device__ __forceinline__ bool scan_triangle(const DevMesh &m, const Work &w, int i, double B2, int pm,
+                                              SplitPt &r) {
+  int4 tri = m.tv[i];
+  if (tri.w) {
+    int4 s = m.ts[i];
+    for (int e = 0; e < 3; e++) {
+      if (!((tri.w >> e) & 1)) continue;
+      int k = comp(s, e);
+      int u = comp(tri, e), v = comp(tri, (e + 1) % 3), c = comp(tri, (e + 2) % 3);
+      int side = (u == m.sv[k].x) ? 0 : 1;
+      w.sadj[2 * k + side] = i * 4 + e;
+      double2 U = m.vxy[u], V = m.vxy[v], Cc = m.vxy[c];
+      if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0) flag_mid(w, k);
     }
-    r = tri_split(m, i, tri, B2, pm);
-    bad = r.bad != 0;
   }
+  r = tri_split(m, i, tri, B2, pm);
+  return r.bad != 0;
+}
+
+__device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const SplitPt &r) {
   int idx = wave_append(&w.cnt->ncc, bad);
   if (bad) {
-    w.cc.elem[idx] = i;
+    w.cc.elem[idx] = t;
     w.cc.key[idx] = r.key;
     w.cc.p[idx] = make_double2(r.px, r.py);
     w.cc.state[idx] = 0;
   }
+}
+
+// Full collection over every triangle and subsegment (first round of a call).
+__global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  SplitPt r;
+  if (i < m.nT) bad = scan_triangle(m, w, i, B2, pm, r);
+  append_cc(w, bad, i, r);
   if (i < m.nS && m.spend[i]) flag_mid(w, i);
+}
+
+// Incremental collection, later rounds.  A triangle that no winner rewrote
+// keeps its vertices, so its badness and split point are unchanged: the bad
+// triangles of the previous round that were not rewritten are carried over.
+__global__ void k_carry(Work w, int n_prev, int prev_serial) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  bool keep = false;
+  int t = 0;
+  if (c < n_prev) {
+    t = w.prev_cc_elem[c];
+    keep = w.tstamp[t] != prev_serial;
+  }
+  int idx = wave_append(&w.cnt->ncc, keep);
+  if (keep) {
+    w.cc.elem[idx] = t;
+    w.cc.key[idx] = w.prev_cc_key[c];
+    w.cc.p[idx] = w.prev_cc_p[c];
+    w.cc.state[idx] = 0;
+  }
+}
+
+// ... and every slot written last round (the fan records) is tested afresh;
+// an encroaching apex can only appear on a rewritten triangle.
+__global__ void k_scan_dirty(DevMesh m, Work w, int n_dirty, double B2, int pm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  SplitPt r;
+  int t = 0;
+  if (c < n_dirty) {
+    t = w.fan[c].slot;
+    bad = scan_triangle(m, w, t, B2, pm, r);
+  }
+  append_cc(w, bad, t, r);
+}
+
+// ... and last round's flagged subsegments are tested again: pending, or an
+// apex still inside the diametric circle (a flagged subsegment the candidate
+// cap left out is not pending, and its sides may be unchanged).  The side
+// slots are current: rewritten sides were re-scanned just before.
+__global__ void k_pending(DevMesh m, Work w, int n_prev) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_prev) return;
+  int k = w.prev_mid_elem[c];
+  if (m.spend[k]) {
+    flag_mid(w, k);
+    return;
+  }
+  for (int side = 0; side < 2; side++) {
+    int a = w.sadj[2 * k + side];
+    if (a < 0) continue;
+    int t = a >> 2, e = a & 3;
+    int4 tri = m.tv[t];
+    double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)], C = m.vxy[comp(tri, (e + 2) % 3)];
+    if (indiametral(U.x, U.y, V.x, V.y, C.x, C.y) > 0) {
+      flag_mid(w, k);
+      return;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -300,6 +368,76 @@ __global__ void k_locate(DevMesh m, Work w, int ncc) {
       return;
     }
     cur = next;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Optional semantic prefilters on located circumcenters.
+//   F1 (Line 6): one circumcenter per located triangle, the largest key.
+//   F2 (Line 7): the first n triangles of the cavity growth order (seed, then
+//   breadth first across non-subsegment edges whose far circumcircle strictly
+//   holds the point, edges in index order, stopping as soon as n are taken)
+//   are marked with atomicMax; a point that does not hold all of them is
+//   dropped.  Marks are cleared before the real cavities are grown.
+// mode: 0 F1 mark, 1 F1 filter, 2 F1 clear, 3 F2 mark, 4 F2 filter, 5 F2 clear
+// ---------------------------------------------------------------------------
+constexpr int kApproxMax = 16;
+constexpr int kPreBlock = 128;
+
+__global__ __launch_bounds__(kPreBlock) void k_prefilter(DevMesh m, Work w, int ncc, int mode, int n) {
+  __shared__ int32_t lds[kApproxMax * kPreBlock];
+  int tid = threadIdx.x;
+  int c = blockIdx.x * kPreBlock + tid;
+  if (c >= ncc) return;
+  int st = w.cc.state[c];
+  if (!(st & kStFound)) return;
+  int loc = w.cc.loc[c];
+  uint64_t key = w.cc.key[c];
+  if (mode <= 2) {
+    if (mode == 0) {
+      if (!(st & kStDone)) atomicMax((unsigned long long *)&w.mark[loc], (unsigned long long)key);
+    } else if (mode == 1) {
+      if (!(st & kStDone) && w.mark[loc] != key) {
+        w.cc.state[c] = st | kStDone;
+        atomicAdd(&w.cnt->n_f1_drop, 1);
+      }
+    } else {
+      w.mark[loc] = 0ull;
+    }
+    return;
+  }
+  if (mode != 5 && (st & kStDone)) return;
+  double2 p = w.cc.p[c];
+  int len = 0;
+  lds[tid] = loc;
+  len = 1;
+  for (int h = 0; h < len && len < n; h++) {
+    int t = lds[h * kPreBlock + tid];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    for (int e = 0; e < 3 && len < n; e++) {
+      if ((tri.w >> e) & 1) continue;
+      int o = comp(nb, e);
+      if (o < 0) continue;
+      bool in = false;
+      for (int q = 0; q < len; q++)
+        if (lds[q * kPreBlock + tid] == o) { in = true; break; }
+      if (in) continue;
+      if (incircle_tri(m, m.tv[o], p) > 0) lds[(len++) * kPreBlock + tid] = o;
+    }
+  }
+  if (mode == 3) {
+    for (int j = 0; j < len; j++)
+      atomicMax((unsigned long long *)&w.mark[lds[j * kPreBlock + tid]], (unsigned long long)key);
+  } else if (mode == 4) {
+    bool own = true;
+    for (int j = 0; j < len && own; j++) own = w.mark[lds[j * kPreBlock + tid]] == key;
+    if (!own) {
+      w.cc.state[c] = st | kStDone;
+      atomicAdd(&w.cnt->n_f2_drop, 1);
+    }
+  } else {
+    for (int j = 0; j < len; j++) w.mark[lds[j * kPreBlock + tid]] = 0ull;
   }
 }
 
@@ -868,7 +1006,7 @@ __global__ void k_record(DevMesh m, Work w, int nwin) {
   }
 }
 
-__global__ void k_write(DevMesh m, Work w, int nwin) {
+__global__ void k_write(DevMesh m, Work w, int nwin, int serial) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nwin) return;
   int ref = w.win_ref[r];
@@ -913,6 +1051,7 @@ __global__ void k_write(DevMesh m, Work w, int nwin) {
     m.tv[s] = make_int4(f.u, f.v, pid, mask);
     m.tn[s] = make_int4(n0, n1, n2, 0);
     m.ts[s] = make_int4(f.ts, s1, s2, 0);
+    w.tstamp[s] = serial;
   }
   m.vxy[pid] = p;
   m.vkind[pid] = is_cc ? 2 : 1;

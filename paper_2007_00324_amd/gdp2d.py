@@ -50,7 +50,7 @@ class gdp_mesh_info(C.Structure):
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident", "n_enc_reject",
                "n_mid_cand", "n_unsplittable", "n_fan_invalid", "n_lost_mark", "n_dep_drop", "n_ins_mid",
-               "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities"]
+               "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities", "n_f1_drop", "n_f2_drop"]
 
 
 class gdp_round_stats(C.Structure):
@@ -120,9 +120,12 @@ def _pslg(xy, seg):
     return p, (xy, seg)
 
 
-def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0) -> gdp_params:
+def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
+                prefilter_f1=0, cavity_approx_n=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
+    p.prefilter_f1 = prefilter_f1
+    p.cavity_approx_n = cavity_approx_n
     p.profile_kernels = profile_kernels
     p.cand_cap_K = cand_cap_K
     p.priority_mode = priority_mode

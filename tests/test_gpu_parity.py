@@ -60,6 +60,12 @@ def test_parity_candidate_cap(ctx, K):
     _check(ctx, workloads.random_small(42, 300, 15), cand_cap_K=K)
 
 
+@pytest.mark.parametrize("f1,n", [(1, 0), (0, 1), (0, 4), (1, 8), (0, 16)])
+@pytest.mark.parametrize("case", ["rand_300", "circles_small", "knn_2000"])
+def test_parity_prefilters(ctx, case, f1, n):
+    _check(ctx, SMALL[case](), prefilter_f1=f1, cavity_approx_n=n)
+
+
 def test_parity_priority_mode_one(ctx):
     _check(ctx, workloads.random_small(43, 500, 25), priority_mode=1)
 
