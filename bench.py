@@ -60,6 +60,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--f1", type=int, default=0, help="Line 6 filter: one circumcenter per located triangle")
+    ap.add_argument("--approx-n", type=int, default=0, help="Line 7 filter: n-triangle cavity approximation")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration) and exit")
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
@@ -95,7 +97,7 @@ def main() -> int:
     init = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg)
     log(f"initial CDT (host) + upload: {init.info()['n_triangles']:,} triangles in {time.perf_counter() - t:.1f} s")
     work = init.clone()
-    prm = gdp2d.make_params()
+    prm = gdp2d.make_params(prefilter_f1=args.f1, cavity_approx_n=args.approx_n)
     for i in range(args.warmup):
         work.assign_from(init)
         gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)
@@ -133,6 +135,8 @@ def main() -> int:
             "n_input_vertices": info["n_input_vertices"],
             "n_input_segments": info["n_input_segments"],
             "ratio_bound_sq": p.ratio_bound_sq,
+            "prefilter_f1": args.f1,
+            "cavity_approx_n": args.approx_n,
             "steiner_points": steiner,
             "output_triangles": tris,
             "rounds": info["rounds"],
@@ -143,7 +147,8 @@ def main() -> int:
     }
     if not args.no_profile:
         work.assign_from(init)
-        gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, gdp2d.make_params(profile_kernels=1))
+        gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq,
+                              gdp2d.make_params(profile_kernels=1, prefilter_f1=args.f1, cavity_approx_n=args.approx_n))
         prof = work.kernel_profile()
         for k in sorted(prof, key=lambda r: -r["total_ms"]):
             if k["launches"]:

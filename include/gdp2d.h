@@ -89,7 +89,10 @@ typedef struct {
                                (64..1024, multiple of 64; 0 = default 256) */
   int32_t profile_kernels;  /* 1 = time every kernel launch with HIP events (adds
                                overhead; read with gdp_mesh_kernel_profile) */
-  int32_t reserved[5];
+  int32_t reserve_mode;     /* 0 = grow buffers ahead of each round from the
+                               collection counts; 1 = grow only after a round was
+                               abandoned for lack of room (then it is run again) */
+  int32_t reserved[4];
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */

@@ -42,6 +42,7 @@ struct gdp_mesh {
   double2 *prev_cc_p = nullptr;
   int32_t *prev_mid_elem = nullptr;
   int32_t *tstamp = nullptr;
+  int32_t *cidx_t = nullptr, *cidx_s = nullptr;
   int32_t serial = 0;  // rounds ever executed on this mesh object (slot stamps)
   uint64_t *keys = nullptr;
   int32_t *hist = nullptr;
@@ -165,6 +166,7 @@ gdp_status grow_tri(gdp_mesh *M, int32_t need) {
   HIPCHECK(dgrow(&M->prev_cc_key, oc, nc, oc, 0, s));
   HIPCHECK(dgrow(&M->prev_cc_p, oc, nc, oc, 0, s));
   HIPCHECK(dgrow(&M->tstamp, oc, nc, oc, 0xff, s));
+  HIPCHECK(dgrow(&M->cidx_t, oc, nc, oc, 0, s));
   M->m.capT = nc;
   return GDP_OK;
 }
@@ -191,6 +193,7 @@ gdp_status grow_seg(gdp_mesh *M, int32_t need) {
   HIPCHECK(dgrow(&M->mid.off, om, nm, om, 0, s));
   HIPCHECK(dgrow(&M->mid.len, om, nm, om, 0, s));
   HIPCHECK(dgrow(&M->prev_mid_elem, om, nm, om, 0, s));
+  HIPCHECK(dgrow(&M->cidx_s, oc, nc, oc, 0, s));
   HIPCHECK(dgrow(&M->w0_s, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->win_s, words(oc), words(nc), words(oc), 0, s));
   HIPCHECK(dgrow(&M->rank_s, words(oc), words(nc), words(oc), 0, s));
@@ -245,12 +248,14 @@ Work make_work(gdp_mesh *M, int pm) {
   w.w0_t = M->w0_t; w.w0_s = M->w0_s; w.win_t = M->win_t; w.win_s = M->win_s;
   w.rank_t = M->rank_t; w.rank_s = M->rank_s;
   w.win_ref = M->win_ref; w.fbase = M->fbase; w.fcount = M->fcount; w.fan_off = M->fan_off;
+  w.win_cap = M->wT;
   w.repl = M->repl;
   w.pool = M->pool; w.pool_cap = M->pool_cap;
   w.fan = M->fan; w.fan_cap = M->fan_cap;
   w.big = M->big; w.big_cap = M->wT;
   w.prev_cc_elem = M->prev_cc_elem; w.prev_cc_key = M->prev_cc_key; w.prev_cc_p = M->prev_cc_p;
   w.prev_mid_elem = M->prev_mid_elem; w.tstamp = M->tstamp;
+  w.cidx_t = M->cidx_t; w.cidx_s = M->cidx_s;
   w.keys = M->keys; w.hist = M->hist; w.thresh = M->thresh;
   w.pm = pm;
   return w;
@@ -260,16 +265,21 @@ inline unsigned grid_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>
 
 // Exclusive scan of n entries (mode 0: counts, mode 1: popcounts of words);
 // the total is written to *d_total.
-gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int n, int32_t *d_total, int mode) {
+// Exclusive scan (mode 0: counts, mode 1: popcounts of words).  n is the
+// length, or an upper bound when n_dev points to the length in device memory;
+// the total goes to *d_total.
+gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int n, int32_t *d_total, int mode,
+                const int32_t *n_dev = nullptr) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
   int ntiles = (n + kScanTileSize - 1) / kScanTileSize;
   if (ntiles < 1) ntiles = 1;
   if (ntiles > M->tiles_cap) return fail(ctx, GDP_E_NOMEM, "scan tile buffer too small");
   Prof pr(M, P_PREFIX, n);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, in, out, n, M->tiles, mode);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, ntiles, d_total);
-  if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, M->tiles);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, in, out, n, M->tiles, mode, n_dev);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, ntiles, d_total, n_dev);
+  hipLaunchKernelGGL(k_scan_add, dim3(std::min<unsigned>(grid_for(std::max(n, 1), 256), 4096)), dim3(256), 0, s,
+                     out, n, M->tiles, n_dev);
   HIPCHECK(hipGetLastError());
   return GDP_OK;
 }
@@ -288,7 +298,8 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
                   M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->hist, M->thresh,
-                  M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp};
+                  M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
+                  M->cidx_t, M->cidx_s};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
@@ -361,6 +372,69 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
   return GDP_OK;
 }
 
+// Grid for a grid-stride kernel over at most n items.
+inline unsigned stride_grid(int64_t n, int bs) {
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + bs - 1) / bs), 8192);
+}
+
+// Ensures the buffers a round may need, given the scan's counts (a loose
+// bound; the device-side check abandons the round if it is not enough).
+gdp_status reserve_round(gdp_mesh *M, int ncc, int nmk) {
+  gdp_ctx *ctx = M->ctx;
+  const DevMesh &m = M->m;
+  int64_t wins = (int64_t)ncc + nmk + (ncc >> 3) + 64;
+  gdp_status st;
+  if ((st = grow_vtx(M, (int32_t)std::min<int64_t>(m.nV + wins, 1 << 29)))) return st;
+  if ((st = grow_tri(M, (int32_t)std::min<int64_t>(m.nT + 2 * wins, 1 << 29)))) return st;
+  if ((st = grow_seg(M, (int32_t)std::min<int64_t>(m.nS + nmk + (ncc >> 3) + 64, 1 << 28)))) return st;
+  if ((st = grow_cand(M))) return st;
+  int64_t pool_need = 6 * ((int64_t)ncc + nmk) + 4096;
+  if (pool_need > M->pool_cap) {
+    int64_t nc = std::max<int64_t>(pool_need, (int64_t)M->pool_cap * 3 / 2);
+    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+    HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
+    M->pool_cap = (int32_t)nc;
+  }
+  int64_t fan_need = std::min<int64_t>(M->pool_cap, pool_need) + 2 * wins;
+  if (fan_need > M->fan_cap) {
+    int64_t nc = std::max<int64_t>(fan_need, (int64_t)M->fan_cap * 3 / 2);
+    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "fan buffer limit exceeded");
+    HIPCHECK(dgrow(&M->fan, M->fan_cap, nc, 0, 0, ctx->stream));
+    M->fan_cap = (int32_t)nc;
+  }
+  return GDP_OK;
+}
+
+// After an abandoned round: grow what the device-side check found short.
+// The fan records of the previous round are still needed (they list the
+// slots to re-test), so the first keep_fan records survive a regrowth.
+gdp_status grow_after_abort(gdp_mesh *M, const DevCounters &c, int keep_fan) {
+  gdp_ctx *ctx = M->ctx;
+  const DevMesh &m = M->m;
+  gdp_status st;
+  int nwin = c.nwin;
+  if ((st = grow_vtx(M, m.nV + nwin + 1024))) return st;
+  if ((st = grow_tri(M, m.nT + std::max(c.fresh_total, 2 * nwin) + 2048))) return st;
+  if ((st = grow_seg(M, m.nS + c.nwin_mid + 1024))) return st;
+  if ((st = grow_cand(M))) return st;
+  if (c.err & kErrPool) {
+    int64_t nc = std::max<int64_t>((int64_t)c.pool_used * 2, (int64_t)M->pool_cap * 2);
+    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+    HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
+    M->pool_cap = (int32_t)nc;
+  }
+  int64_t fan_need = (int64_t)std::max(c.pool_used, M->pool_cap) + 2 * (int64_t)nwin + 1024;
+  if (fan_need > M->fan_cap) {
+    if (fan_need > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "fan buffer limit exceeded");
+    HIPCHECK(dgrow(&M->fan, M->fan_cap, fan_need, keep_fan, 0, ctx->stream));
+    M->fan_cap = (int32_t)fan_need;
+  }
+  return GDP_OK;
+}
+
+// One refinement call: rounds until nothing is left (Algorithm 1, "repeat
+// ... until L is empty").  Each round has two host synchronisations: after
+// the collection (termination, capacity, candidate cap) and at its end.
 gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
@@ -379,8 +453,10 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   // previous bad list over and re-test only the slots the last round wrote.
   bool full_scan = true;
   int prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
+  int aborts = 0;
   for (;;) {
     DevMesh &m = M->m;
+    gdp_status st;
     HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
     Work w = make_work(M, pm);
     size_t scan_rec = M->prof_pending.size();
@@ -394,38 +470,40 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       hipLaunchKernelGGL(k_pending, dim3(grid_for(prev_nmk, bs)), dim3(bs), 0, s, m, w, prev_nmk);
     }
     HIPCHECK(hipGetLastError());
-    gdp_status st = read_counters(M);
-    if (st) return st;
-    int ncc = M->h_cnt->ncc, nmk = M->h_cnt->nmk;
+    if ((st = read_counters(M))) return st;  // sync 1
+    const int ncc = M->h_cnt->ncc;
+    const int nmk0 = M->h_cnt->nmk;
     if (M->prof && scan_rec < M->prof_pending.size())
-      // algorithmic bytes of the scan: every triangle record (16 B) and every
-      // vertex (16 B) read once, both records of every subsegment side
-      // (ts 16 B + side slot 4 B per side), the pending flags (4 B), the
-      // bad-triangle records written (elem 4 + key 8 + point 16 + state 4 B)
-      // and the flagged subsegments (flag 4 + list entry 8 B).
+      // algorithmic bytes of the collection.  Full: every triangle record
+      // (16 B) and vertex (16 B) once, both sides of every subsegment (ts
+      // record 16 B + side slot 4 B each), pending flags (4 B), the bad records
+      // written (elem 4 + key 8 + point 16 + state 4 B) and the flagged
+      // subsegments (flag 4 + list entry 8 B).  Incremental: carried records
+      // (elem 4 + key 8 + point 16 read and written, stamp 4), each rewritten
+      // slot (fan slot 4 + record 16 + three vertices 48) and the previous
+      // flagged list (entry 4 + pending flag 4), plus the new records / flags.
       M->prof_pending[scan_rec].bytes =
-          full_scan ? 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk
-                    // incremental: carried records (elem 4 + key 8 + point 16 read, the same written, stamp
-                    // 4), each rewritten slot (fan slot 4 + triangle record 16 + three vertices 48) and the
-                    // previous flagged list (4 + pending flag 4), plus the new bad records and flags
-                    : 64LL * prev_ncc + 68LL * prev_fan + 8LL * prev_nmk + 32LL * ncc + 12LL * nmk;
+          full_scan ? 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk0
+                    : 64LL * prev_ncc + 68LL * prev_fan + 8LL * prev_nmk + 32LL * ncc + 12LL * nmk0;
     gdp_round_stats rs;
     memset(&rs, 0, sizeof rs);
     rs.n_bad = ncc;
-    rs.n_enc = nmk;
-    if (ncc == 0 && nmk == 0) break;
+    rs.n_enc = nmk0;
+    if (ncc == 0 && nmk0 == 0) break;
     if (P->max_rounds > 0 && m.rounds >= P->max_rounds) {
-      hipLaunchKernelGGL(k_unflag, dim3(grid_for(nmk, bs)), dim3(bs), 0, s, w, nmk);
+      hipLaunchKernelGGL(k_unflag, dim3(grid_for(nmk0, bs)), dim3(bs), 0, s, w, nmk0);
       HIPCHECK(hipGetLastError());
       result = fail(ctx, GDP_E_NOTERM, "round cap reached");
       break;
     }
+    if (P->reserve_mode == 0 && (st = reserve_round(M, ncc, nmk0))) return st;
+    w = make_work(M, pm);
     // ---- R3: candidate cap ----
-    bool capped = P->cand_cap_K > 0 && ncc + nmk > P->cand_cap_K;
+    bool capped = P->cand_cap_K > 0 && ncc + nmk0 > P->cand_cap_K;
     if (capped) {
-      int n = ncc + nmk;
+      int n = ncc + nmk0;
       Prof pr(M, P_CAP, n);
-      hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(n, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm);
+      hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(n, bs)), dim3(bs), 0, s, m, w, ncc, nmk0, pm);
       uint64_t prefix = 0, pmask = 0;
       int64_t remaining = P->cand_cap_K;
       for (int shift = 56; shift >= 0; shift -= 8) {
@@ -445,213 +523,141 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
         pmask |= (uint64_t)0xff << shift;
       }
       HIPCHECK(hipMemcpyAsync(M->thresh, &prefix, sizeof(uint64_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_apply_cap, dim3(grid_for(n, bs)), dim3(bs), 0, s, w, ncc, nmk);
+      hipLaunchKernelGGL(k_apply_cap, dim3(grid_for(n, bs)), dim3(bs), 0, s, w, ncc, nmk0);
       HIPCHECK(hipGetLastError());
     } else {
       rs.n_kept_cc = ncc;
-      rs.n_kept_mid = nmk;
+      rs.n_kept_mid = nmk0;
     }
+    // Bound on the midpoint list after R4/R5 (each list entry is a distinct
+    // subsegment, twice at most with the cap).
+    const int nmk_bound = (int)std::min<int64_t>(2LL * m.nS, (int64_t)nmk0 + ncc + (int64_t)m.nS);
+    const int ncand_bound = ncc + nmk_bound;
     // ---- R4: locate ----
     {
       Prof pr(M, P_LOCATE, ncc);
       hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
     }
-    HIPCHECK(hipGetLastError());
     // ---- optional prefilters F1 / F2 on located circumcenters ----
-    if (P->prefilter_f1) {
+    if (P->prefilter_f1)
       for (int mode = 0; mode < 3; mode++)
         hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode, 0);
-      HIPCHECK(hipGetLastError());
-    }
-    if (P->cavity_approx_n > 0) {
+    if (P->cavity_approx_n > 0)
       for (int mode = 3; mode < 6; mode++)
         hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode,
                            P->cavity_approx_n);
-      HIPCHECK(hipGetLastError());
-    }
-    if ((st = read_counters(M))) return st;
-    DevCounters snap = *M->h_cnt;
-    // ---- R5/R6: cavities (rerun from here if the pool overflows) ----
-    for (int attempt = 0;; attempt++) {
-      {
-        Prof pr(M, P_CAV_CC, ncc);
-        hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
-      }
-      HIPCHECK(hipGetLastError());
-      if ((st = read_counters(M))) return st;
-      // Midpoint cavities; a large circumcenter cavity handled by the
-      // cooperative kernel may flag more midpoints, so repeat until the
-      // candidate list stops growing.
-      int big_done = 0;
-      for (int pass = 0;; pass++) {
-        nmk = M->h_cnt->nmk;
-        {
-          Prof pr(M, P_CAV_MID, nmk);
-          hipLaunchKernelGGL(k_cavity, dim3(grid_for(nmk, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, nmk, 0);
-        }
-        HIPCHECK(hipGetLastError());
-        if ((st = read_counters(M))) return st;
-        int nbig = std::min(M->h_cnt->nbig, M->wT);
-        if (nbig > big_done) {
-          {
-            Prof pr(M, P_CAV_BIG, nbig - big_done);
-            hipLaunchKernelGGL(k_cavity_big, dim3(nbig - big_done), dim3(kBigBlockSize), 0, s, m, w, big_done, nbig);
-          }
-          HIPCHECK(hipGetLastError());
-          big_done = nbig;
-          if ((st = read_counters(M))) return st;
-        }
-        if (M->h_cnt->nmk == nmk && std::min(M->h_cnt->nbig, M->wT) == big_done) break;
-        if (pass > 64) return fail(ctx, GDP_E_DEVICE, "cavity step did not settle");
-      }
-      DevCounters &c = *M->h_cnt;
-      if (c.err & kErrWalk) { result = fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap"); goto done; }
-      if (c.err & kErrCavity) { result = fail(ctx, GDP_E_CAVITY, "cavity exceeded the cooperative-path capacity"); goto done; }
-      if (c.err & kErrInput) { result = fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment"); goto done; }
-      if (!(c.err & kErrPool)) break;
-      if (attempt > 8) return fail(ctx, GDP_E_NOMEM, "cavity pool keeps overflowing");
-      // grow the pool, forget every cavity of this round and grow them again
-      int64_t ncap = std::max<int64_t>((int64_t)c.pool_used * 2, (int64_t)M->pool_cap * 2);
-      if (ncap > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
-      HIPCHECK(dgrow(&M->pool, M->pool_cap, ncap, 0, 0, s));
-      M->pool_cap = (int32_t)ncap;
-      w = make_work(M, pm);
-      std::vector<int32_t> hs;
-      for (int which = 0; which < 2; which++) {
-        int n = which == 0 ? ncc : nmk;
-        int32_t *dst = which == 0 ? M->cc.state : M->mid.state;
-        hs.resize(std::max(n, 1));
-        HIPCHECK(hipMemcpyAsync(hs.data(), dst, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        for (int i = 0; i < n; i++) hs[i] &= (kStFound | kStSkip);
-        // circumcenters dropped by the walk keep Done
-        if (which == 0)
-          for (int i = 0; i < n; i++)
-            if (!(hs[i] & kStFound)) hs[i] |= kStDone;
-        HIPCHECK(hipMemcpyAsync(dst, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-      }
-      DevCounters r = c;
-      r.pool_used = 0; r.nbig = 0; r.err = 0;
-      r.n_enc_reject = snap.n_enc_reject; r.n_fan_invalid = snap.n_fan_invalid;
-      r.n_unsplittable = snap.n_unsplittable; r.cav_tri_total = snap.cav_tri_total; r.cav_max = snap.cav_max;
-      r.n_mid_cand = snap.n_mid_cand;
-      *M->h_cnt = r;
-      HIPCHECK(hipMemcpyAsync(M->d_cnt, M->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice, s));
-      HIPCHECK(hipStreamSynchronize(s));
+    // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
+    {
+      Prof pr(M, P_CAV_CC, ncc);
+      hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
     }
     {
-      int ncand = ncc + nmk;
-      // ---- R8/R9 ----
-      {
-        Prof pr(M, P_MARK, ncand);
-        hipLaunchKernelGGL(k_mark, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
-      }
-      {
-        Prof pr(M, P_OWN, ncand);
-        hipLaunchKernelGGL(k_own, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk);
-      }
-      {
-        Prof pr(M, P_DEP, ncand);
-        hipLaunchKernelGGL(k_dep, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, pm, B2);
-      }
-      HIPCHECK(hipGetLastError());
-      // ---- R10: ranks ----
-      if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.nS), &M->d_cnt->nwin_mid, 1))) return st;
-      if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.nT), &M->d_cnt->nwin_cc, 1))) return st;
-      if ((st = read_counters(M))) return st;
-      int nwin_mid = M->h_cnt->nwin_mid, nwin_cc = M->h_cnt->nwin_cc, nwin = nwin_mid + nwin_cc;
-      if (nwin == 0) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); goto done; }
-      HIPCHECK(hipMemsetAsync(M->fan_off, 0, sizeof(int32_t) * (nwin + 1), s));
-      {
-        Prof pr(M, P_WINNERS, ncand);
-        hipLaunchKernelGGL(k_winners, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, m, w, ncc, nmk, nwin_mid);
-      }
-      if (getenv("GDP_DEBUG")) {
-        if ((st = read_counters(M))) return st;
-        fprintf(stderr, "[gdp] round %d ncc %d nmk %d nwin_mid %d nwin_cc %d win_cands %d dbg_set %d dbg %d %d %d %d pool %d/%d\n",
-                m.rounds + 1, ncc, nmk, nwin_mid, nwin_cc, M->h_cnt->pad[0], M->h_cnt->dbg_set, M->h_cnt->dbg[0],
-                M->h_cnt->dbg[1], M->h_cnt->dbg[2], M->h_cnt->dbg[3], M->h_cnt->pool_used, M->pool_cap);
-      }
-      if ((st = scan(M, M->fcount, M->fbase, nwin, M->fbase + nwin, 0))) return st;
-      HIPCHECK(hipMemcpyAsync(M->h_small, M->fbase + nwin, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      int fresh = M->h_small[0];
-      int pool_used = M->h_cnt->pool_used;
-      // ---- capacity for the new elements ----
-      if ((st = grow_vtx(M, m.nV + nwin))) return st;
-      if ((st = grow_tri(M, m.nT + fresh))) return st;
-      if ((st = grow_seg(M, m.nS + nwin_mid))) return st;
-      if ((st = grow_cand(M))) return st;
-      int64_t need_fan = (int64_t)pool_used + 2 * (int64_t)nwin;
-      if (need_fan > M->fan_cap) {
-        int64_t nc = std::max<int64_t>(need_fan, (int64_t)M->fan_cap * 3 / 2);
-        HIPCHECK(dgrow(&M->fan, M->fan_cap, nc, 0, 0, s));
-        M->fan_cap = (int32_t)nc;
-      }
-      w = make_work(M, pm);
-      {
-        Prof pr(M, P_RECORD, nwin);
-        hipLaunchKernelGGL(k_record, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin);
-      }
-      {
-        Prof pr(M, P_WRITE, nwin);
-        hipLaunchKernelGGL(k_write, dim3(grid_for(nwin, bs)), dim3(bs), 0, s, m, w, nwin, M->serial);
-      }
-      {
-        Prof pr(M, P_FINISH, ncand);
-        hipLaunchKernelGGL(k_finish, dim3(grid_for(ncand, bs)), dim3(bs), 0, s, w, ncc, nmk, m.spend);
-      }
-      HIPCHECK(hipGetLastError());
-      HIPCHECK(hipMemsetAsync(M->w0_t, 0, sizeof(uint32_t) * words(m.nT), s));
-      HIPCHECK(hipMemsetAsync(M->win_t, 0, sizeof(uint32_t) * words(m.nT), s));
-      HIPCHECK(hipMemsetAsync(M->w0_s, 0, sizeof(uint32_t) * words(m.nS), s));
-      HIPCHECK(hipMemsetAsync(M->win_s, 0, sizeof(uint32_t) * words(m.nS), s));
-      if ((st = read_counters(M))) return st;
-      DevCounters &c = *M->h_cnt;
-      if (c.err & kErrCavity) {
-        char buf[256];
+      Prof pr(M, P_CAV_BIG, 0);
+      hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 0);
+    }
+    {
+      Prof pr(M, P_CAV_MID, nmk0);
+      hipLaunchKernelGGL(k_cavity, dim3(stride_grid(nmk_bound, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w,
+                         0, 0);
+    }
+    {
+      Prof pr(M, P_CAV_BIG, 0);
+      hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 1);
+    }
+    // ---- R8 ownership, R9 dependency ----
+    {
+      Prof pr(M, P_OWN, ncand_bound);
+      hipLaunchKernelGGL(k_own, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, w, ncc);
+    }
+    {
+      Prof pr(M, P_DEP, ncand_bound);
+      hipLaunchKernelGGL(k_dep, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, ncc);
+    }
+    // ---- R10: ranks, fresh slots, capacity check, insertion ----
+    if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.nS), &M->d_cnt->nwin_mid, 1))) return st;
+    if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.nT), &M->d_cnt->nwin_cc, 1))) return st;
+    hipLaunchKernelGGL(k_nwin, dim3(1), dim3(64), 0, s, w);
+    {
+      Prof pr(M, P_WINNERS, ncand_bound);
+      hipLaunchKernelGGL(k_winners, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, w, ncc);
+    }
+    if ((st = scan(M, M->fcount, M->fbase, ncand_bound + 1, &M->d_cnt->pad[0], 0, &M->d_cnt->nwin1))) return st;
+    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, m, w);
+    {
+      Prof pr(M, P_RECORD, ncand_bound);
+      hipLaunchKernelGGL(k_record, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w);
+    }
+    {
+      Prof pr(M, P_WRITE, ncand_bound);
+      hipLaunchKernelGGL(k_write, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, M->serial);
+    }
+    {
+      Prof pr(M, P_FINISH, ncand_bound);
+      hipLaunchKernelGGL(k_finish, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, ncc);
+    }
+    HIPCHECK(hipGetLastError());
+    if ((st = read_counters(M))) return st;  // sync 2
+    DevCounters &c = *M->h_cnt;
+    if (c.err & kErrWalk) { result = fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap"); break; }
+    if (c.err & kErrInput) {
+      result = fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment");
+      break;
+    }
+    if (c.err & kErrCavity) {
+      char buf[256];
+      if (c.dbg_set)
         snprintf(buf, sizeof buf, "fan boundary mismatch (cc=%d elem=%d cavity=%d expected=%d found=%d state=%d)",
                  c.dbg[0], c.dbg[1], c.dbg[2], c.dbg[3], c.dbg[4], c.dbg[5]);
-        result = fail(ctx, GDP_E_CAVITY, buf);
-        goto done;
-      }
-      if (capped) {
-        rs.n_kept_cc = c.n_kept_cc;
-        rs.n_kept_mid = c.n_kept_mid;
-      }
-      rs.n_blocked = c.n_blocked;
-      rs.n_coincident = c.n_coincident;
-      rs.n_enc_reject = c.n_enc_reject;
-      rs.n_unsplittable = c.n_unsplittable;
-      rs.n_fan_invalid = c.n_fan_invalid;
-      rs.n_lost_mark = c.n_lost_mark;
-      rs.n_dep_drop = c.n_dep_drop;
-      rs.n_ins_mid = nwin_mid;
-      rs.n_ins_cc = nwin_cc;
-      rs.cav_tri_total = c.cav_tri_total;
-      rs.cav_max = c.cav_max;
-      rs.n_big_cavities = c.nbig;
-      rs.n_mid_cand = c.n_mid_cand;
-      rs.n_f1_drop = c.n_f1_drop;
-      rs.n_f2_drop = c.n_f2_drop;
-      M->stats.push_back(rs);
-      m.nV += nwin;
-      m.nT += fresh;
-      m.nS += nwin_mid;
-      m.rounds += 1;
-      M->serial += 1;
-      // this round's lists become the previous ones
-      prev_ncc = ncc;
-      prev_nmk = nmk;
-      prev_fan = c.fan_used;
-      std::swap(M->cc.elem, M->prev_cc_elem);
-      std::swap(M->cc.key, M->prev_cc_key);
-      std::swap(M->cc.p, M->prev_cc_p);
-      std::swap(M->mid.elem, M->prev_mid_elem);
-      full_scan = false;
+      else
+        snprintf(buf, sizeof buf, "cavity exceeded the cooperative-path capacity");
+      result = fail(ctx, GDP_E_CAVITY, buf);
+      break;
     }
+    if (c.abort) {
+      // nothing was written: grow and run the same round again
+      if (++aborts > 16) return fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
+      DevCounters cc = c;
+      if ((st = grow_after_abort(M, cc, full_scan ? 0 : prev_fan))) return st;
+      continue;
+    }
+    aborts = 0;
+    const int nmk = c.nmk, nwin_mid = c.nwin_mid, nwin_cc = c.nwin_cc, nwin = c.nwin, fresh = c.fresh_total;
+    if (nwin == 0) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); break; }
+    if (capped) {
+      rs.n_kept_cc = c.n_kept_cc;
+      rs.n_kept_mid = c.n_kept_mid;
+    }
+    rs.n_blocked = c.n_blocked;
+    rs.n_coincident = c.n_coincident;
+    rs.n_enc_reject = c.n_enc_reject;
+    rs.n_unsplittable = c.n_unsplittable;
+    rs.n_fan_invalid = c.n_fan_invalid;
+    rs.n_lost_mark = c.n_lost_mark;
+    rs.n_dep_drop = c.n_dep_drop;
+    rs.n_ins_mid = nwin_mid;
+    rs.n_ins_cc = nwin_cc;
+    rs.cav_tri_total = c.cav_tri_total;
+    rs.cav_max = c.cav_max;
+    rs.n_big_cavities = c.nbig;
+    rs.n_mid_cand = c.n_mid_cand;
+    rs.n_f1_drop = c.n_f1_drop;
+    rs.n_f2_drop = c.n_f2_drop;
+    M->stats.push_back(rs);
+    m.nV += nwin;
+    m.nT += fresh;
+    m.nS += nwin_mid;
+    m.rounds += 1;
+    M->serial += 1;
+    // this round's lists become the previous ones
+    prev_ncc = ncc;
+    prev_nmk = nmk;
+    prev_fan = c.fan_used;
+    std::swap(M->cc.elem, M->prev_cc_elem);
+    std::swap(M->cc.key, M->prev_cc_key);
+    std::swap(M->cc.p, M->prev_cc_p);
+    std::swap(M->mid.elem, M->prev_mid_elem);
+    full_scan = false;
   }
-done:
   HIPCHECK(hipEventRecord(ev1, s));
   HIPCHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
@@ -794,6 +800,7 @@ gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, 
   if (P.cand_cap_K < 0 || P.max_rounds < 0 || (P.priority_mode != 0 && P.priority_mode != 1))
     return fail(ctx, GDP_E_ARG, "bad parameter");
   if (P.block_size < 64 || P.block_size > 1024 || P.block_size % 64) return fail(ctx, GDP_E_ARG, "bad block size");
+  if (P.reserve_mode != 0 && P.reserve_mode != 1) return fail(ctx, GDP_E_ARG, "bad reserve mode");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
   return refine_loop(mesh, ratio_bound_sq, &P);
 }

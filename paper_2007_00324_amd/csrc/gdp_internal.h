@@ -59,7 +59,9 @@ struct DevCounters {
   int32_t dbg_set;     // first failing insertion record: set flag
   int32_t dbg[6];      // class, element, cavity size, expected fan size, found fan size, round-local index
   int32_t n_f1_drop, n_f2_drop;
-  int32_t pad[2];
+  int32_t nwin, nwin1;  // winners of the round, and nwin + 1 (scan length)
+  int32_t abort;        // the round was abandoned before any mesh write (capacity)
+  int32_t pad[1];
 };
 
 constexpr int kErrWalk = 1;

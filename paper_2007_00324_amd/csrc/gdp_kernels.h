@@ -24,6 +24,7 @@ struct Work {
   int32_t *fbase;      // [nwin+1] exclusive prefix of fresh-slot counts
   int32_t *fcount;     // [nwin] fresh slots per winner (1 or 2)
   int32_t *fan_off;    // [nwin]
+  int32_t win_cap;     // length of win_ref / fbase / fcount / fan_off
   int32_t *repl;       // [4*capT] new slot that replaces (old slot, edge)
   int32_t *pool;
   int32_t pool_cap;
@@ -37,6 +38,8 @@ struct Work {
   double2 *prev_cc_p;
   int32_t *prev_mid_elem;
   int32_t *tstamp;     // [capT] serial of the round that last wrote the slot
+  int32_t *cidx_t;     // [capT] candidate index of a bad triangle in this round's list
+  int32_t *cidx_s;     // [capS] candidate index of a flagged subsegment
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
   int32_t *hist;       // [256]
   uint64_t *thresh;    // [1]
@@ -53,19 +56,21 @@ __global__ void k_apply_cap(Work w, int ncc, int nmk);
 __global__ void k_locate(DevMesh m, Work w, int ncc);
 __global__ void k_prefilter(DevMesh m, Work w, int ncc, int mode, int n);
 constexpr int kApproxMaxN = 16;
-__global__ void k_cavity(DevMesh m, Work w, int n, int is_cc);
-__global__ void k_cavity_big(DevMesh m, Work w, int first, int nbig);
-__global__ void k_mark(Work w, int ncc, int nmk);
-__global__ void k_own(Work w, int ncc, int nmk);
-__global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2);
-__global__ void k_scan_tiles(const int32_t *in, int32_t *out, int n, int32_t *tile_sums, int mode);
-__global__ void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total);
-__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums);
-__global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid);
-__global__ void k_record(DevMesh m, Work w, int nwin);
-__global__ void k_write(DevMesh m, Work w, int nwin, int serial);
+__global__ void k_cavity(DevMesh m, Work w, int n_host, int is_cc);
+__global__ void k_cavity_big(DevMesh m, Work w, int phase);
+__global__ void k_own(Work w, int ncc);
+__global__ void k_dep(DevMesh m, Work w, int ncc);
+__global__ void k_scan_tiles(const int32_t *in, int32_t *out, int n, int32_t *tile_sums, int mode,
+                             const int32_t *n_dev);
+__global__ void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total, const int32_t *n_dev);
+__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums, const int32_t *n_dev);
+__global__ void k_winners(Work w, int ncc);
+__global__ void k_nwin(Work w);
+__global__ void k_check_capacity(DevMesh m, Work w);
+__global__ void k_record(DevMesh m, Work w);
+__global__ void k_write(DevMesh m, Work w, int serial);
 __global__ void k_unflag(Work w, int nmk);
-__global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend);
+__global__ void k_finish(DevMesh m, Work w, int ncc);
 
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;

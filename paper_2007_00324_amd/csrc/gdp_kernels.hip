@@ -135,6 +135,7 @@ __device__ __forceinline__ void flag_mid(const Work &w, int k) {
     int idx = atomicAdd(&w.cnt->nmk, 1);
     w.mid.elem[idx] = k;
     w.mid.state[idx] = 0;
+    w.cidx_s[k] = idx;
   }
 }
 
@@ -197,6 +198,7 @@ __device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const 
     w.cc.key[idx] = r.key;
     w.cc.p[idx] = make_double2(r.px, r.py);
     w.cc.state[idx] = 0;
+    w.cidx_t[t] = idx;
   }
 }
 
@@ -227,6 +229,7 @@ __global__ void k_carry(Work w, int n_prev, int prev_serial) {
     w.cc.key[idx] = w.prev_cc_key[c];
     w.cc.p[idx] = w.prev_cc_p[c];
     w.cc.state[idx] = 0;
+    w.cidx_t[t] = idx;
   }
 }
 
@@ -504,7 +507,14 @@ __device__ void finish_cavity(const Work &w, CandSet S, int ci, const CavCheck &
     atomicOr(&w.cnt->err, kErrPool);
     return;  // the host grows the pool and runs the cavity step again
   }
-  for (int j = 0; j < len; j++) w.pool[off + j] = src[(size_t)j * stride];
+  // R8 marks are placed as soon as the cavity is known to be valid: validity
+  // depends on this cavity alone, and atomicMax does not depend on order.
+  uint64_t key = S.key[ci];
+  for (int j = 0; j < len; j++) {
+    int t = src[(size_t)j * stride];
+    w.pool[off + j] = t;
+    atomicMax((unsigned long long *)&w.mark[t], (unsigned long long)key);
+  }
   atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
   atomicMax(&w.cnt->cav_max, len);
   S.off[ci] = off;
@@ -556,11 +566,7 @@ __device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *se
   return len;
 }
 
-__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n, int is_cc) {
-  __shared__ int32_t lds[kCap * kCavBlock];
-  int tid = threadIdx.x;
-  int ci = blockIdx.x * kCavBlock + tid;
-  if (ci >= n) return;
+__device__ void cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int ci, int is_cc) {
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
   if (st & (kStDone | kStSkip | kStBig)) return;
@@ -604,6 +610,16 @@ __global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n, 
   finish_cavity(w, S, ci, ck, len, expect, is_cc != 0, lds + tid, kCavBlock);
 }
 
+// Per-thread cavities of one class.  The midpoint list is final when this
+// runs for midpoints (they are flagged only by the scan, the walk and the
+// circumcenter cavities), so its length is read from device memory.
+__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n_host, int is_cc) {
+  __shared__ int32_t lds[kCap * kCavBlock];
+  int tid = threadIdx.x;
+  int n = is_cc ? n_host : w.cnt->nmk;
+  for (int ci = blockIdx.x * kCavBlock + tid; ci < n; ci += gridDim.x * kCavBlock) cavity_one(m, w, lds, tid, ci, is_cc);
+}
+
 // Cooperative growth of one large cavity per workgroup (the tuple-parallel
 // ExpandList idea of Section 5.2: the frontier of <point, triangle> tuples
 // is processed in parallel, new tuples are reserved with atomics).
@@ -623,12 +639,18 @@ __device__ __forceinline__ int hash_insert(int32_t *hs, int v, int *ovf) {
   return 0;
 }
 
-__global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int first, int nbig) {
-  __shared__ int32_t cav[kBigMax];
-  __shared__ int32_t hs[kHash];
-  __shared__ int s_n, s_head, s_ovf, s_nbnd, s_fanbad, s_enc, s_off;
-  int b = first + blockIdx.x;
-  if (b >= nbig || b >= w.big_cap) return;
+struct BigShared {
+  int32_t cav[kBigMax];
+  int32_t hs[kHash];
+  int s_n, s_head, s_ovf, s_nbnd, s_fanbad, s_enc, s_off;
+};
+
+// Grows queue entry b (uniform over the workgroup).
+__device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
+  int32_t *cav = sh.cav;
+  int32_t *hs = sh.hs;
+  int &s_n = sh.s_n, &s_head = sh.s_head, &s_ovf = sh.s_ovf, &s_nbnd = sh.s_nbnd, &s_fanbad = sh.s_fanbad,
+      &s_enc = sh.s_enc, &s_off = sh.s_off;
   int tid = threadIdx.x;
   int ref = w.big[b];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
@@ -744,12 +766,30 @@ __global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int
   __syncthreads();
   int off = s_off;
   if (off >= 0) {
-    for (int j = tid; j < len; j += kBigBlock) w.pool[off + j] = cav[j];
+    uint64_t key = S.key[ci];
+    for (int j = tid; j < len; j += kBigBlock) {
+      w.pool[off + j] = cav[j];
+      atomicMax((unsigned long long *)&w.mark[cav[j]], (unsigned long long)key);
+    }
     if (tid == 0) {
       S.off[ci] = off;
       S.len[ci] = len;
       S.state[ci] |= kStDone | kStAlive;
     }
+  }
+}
+
+// Large cavities of one class (phase 0: circumcenters, 1: midpoints); the
+// workgroups stride over the queue.
+__global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int phase) {
+  __shared__ BigShared sh;
+  int nbig = min(w.cnt->nbig, w.big_cap);
+  for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+    int ref = w.big[b];
+    int is_cc = (ref & 0x80000000) ? 0 : 1;
+    if (is_cc != (phase == 0 ? 1 : 0)) continue;
+    big_one(m, w, sh, b);
+    __syncthreads();
   }
 }
 
@@ -761,21 +801,7 @@ __device__ __forceinline__ bool cand_at(const Work &w, int c, int ncc, CandSet &
   S = w.mid; ci = c - ncc; is_cc = 0; return true;
 }
 
-__global__ void k_mark(Work w, int ncc, int nmk) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc + nmk) return;
-  CandSet S;
-  int ci, is_cc;
-  cand_at(w, c, ncc, S, ci, is_cc);
-  if (!(S.state[ci] & kStAlive)) return;
-  uint64_t key = S.key[ci];
-  int off = S.off[ci], len = S.len[ci];
-  for (int j = 0; j < len; j++) atomicMax((unsigned long long *)&w.mark[w.pool[off + j]], (unsigned long long)key);
-}
-
-__global__ void k_own(Work w, int ncc, int nmk) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc + nmk) return;
+__device__ void own_one(const Work &w, int c, int ncc) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -793,10 +819,13 @@ __global__ void k_own(Work w, int ncc, int nmk) {
   }
 }
 
+__global__ void k_own(Work w, int ncc) {
+  int n = ncc + w.cnt->nmk;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) own_one(w, c, ncc);
+}
+
 // R9: Delaunay dependency across a shared non-subsegment cavity edge.
-__global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc + nmk) return;
+__device__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -822,9 +851,10 @@ __global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2) {
       int q_cc = (mo >> 63) ? 0 : 1;
       int qid = (int)perm32_inv((uint32_t)(mo & 0xffffffffu));
       if (!bit_get(q_cc ? w.w0_t : w.w0_s, qid)) continue;
-      SplitPt q = q_cc ? tri_split(m, qid, m.tv[qid], B2, pm) : seg_split(m, qid, pm);
+      if (!(key < mo)) continue;  // only the lower key of a dependent pair drops
+      double2 q = q_cc ? w.cc.p[w.cidx_t[qid]] : w.mid.p[w.cidx_s[qid]];
       double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
-      if (key < mo && incircle(U.x, U.y, V.x, V.y, p.x, p.y, q.px, q.py) > 0) drop = true;
+      if (incircle(U.x, U.y, V.x, V.y, p.x, p.y, q.x, q.y) > 0) drop = true;
     }
   }
   (void)skip_k;
@@ -834,6 +864,11 @@ __global__ void k_dep(DevMesh m, Work w, int ncc, int nmk, int pm, double B2) {
     S.state[ci] = st | kStWin;
     bit_set(is_cc ? w.win_t : w.win_s, S.elem[ci]);
   }
+}
+
+__global__ void k_dep(DevMesh m, Work w, int ncc) {
+  int n = ncc + w.cnt->nmk;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) dep_one(m, w, c, ncc);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,8 +906,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total) {
 
 // mode 0: in[] are counts; mode 1: in[] are 32-bit words, count = popcount
 __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, int32_t *out, int n,
-                                                           int32_t *tile_sums, int mode) {
+                                                           int32_t *tile_sums, int mode, const int32_t *n_dev) {
   __shared__ int s_total;
+  if (n_dev) n = *n_dev;
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
   int sum = 0;
@@ -892,8 +928,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, in
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = s_total;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total,
+                                                          const int32_t *n_dev) {
   __shared__ int s_total;
+  if (n_dev) ntiles = (*n_dev + kScanTile - 1) / kScanTile;
   int carry = 0;
   for (int start = 0; start < ntiles; start += kScanBlock) {
     int idx = start + threadIdx.x;
@@ -906,17 +944,16 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, in
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n) out[idx] += tile_sums[idx / kScanTile];
+__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums, const int32_t *n_dev) {
+  if (n_dev) n = *n_dev;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x)
+    out[idx] += tile_sums[idx / kScanTile];
 }
 
 // ---------------------------------------------------------------------------
 // R10: insertion
 // ---------------------------------------------------------------------------
-__global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc + nmk) return;
+__device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -930,12 +967,41 @@ __global__ void k_winners(DevMesh m, Work w, int ncc, int nmk, int nwin_mid) {
     r = bit_rank(w.win_s, w.rank_s, e);
     fresh = (w.sadj[2 * e] >= 0 && w.sadj[2 * e + 1] >= 0) ? 2 : 1;
   }
-  atomicAdd(&w.cnt->pad[0], 1);
-  if (atomicExch(&w.fan_off[r], 1) != 0 && atomicCAS(&w.cnt->dbg_set, 0, 2) == 0) {
-    w.cnt->dbg[0] = is_cc; w.cnt->dbg[1] = e; w.cnt->dbg[2] = r; w.cnt->dbg[3] = ci; w.cnt->dbg[4] = -1;
-  }
   w.win_ref[r] = (is_cc ? 0 : (int)0x80000000) | ci;
   w.fcount[r] = fresh;
+}
+
+// Winner ranks: midpoints by subsegment id, then circumcenters by slot.
+__global__ void k_winners(Work w, int ncc) {
+  int n = ncc + w.cnt->nmk;
+  int nwin_mid = w.cnt->nwin_mid;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    winner_one(w, c, ncc, nwin_mid);
+}
+
+// nwin, a zero fresh count after the last winner (so the exclusive scan over
+// nwin + 1 entries ends with the total), and the capacity check of this
+// round: if anything would overflow, the round is abandoned before the mesh
+// is written and the host grows the buffers and runs it again.
+__global__ void k_nwin(Work w) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int nwin = w.cnt->nwin_mid + w.cnt->nwin_cc;
+    w.cnt->nwin = nwin;
+    w.cnt->nwin1 = nwin + 1;
+    w.fcount[nwin] = 0;
+  }
+}
+
+__global__ void k_check_capacity(DevMesh m, Work w) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  DevCounters *c = w.cnt;
+  int nwin = c->nwin;
+  int fresh = w.fbase[nwin];
+  c->fresh_total = fresh;
+  int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
+  bool over = (c->err & kErrPool) || (int64_t)m.nV + nwin > m.capV || (int64_t)m.nT + fresh > m.capT ||
+              (int64_t)m.nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
+  c->abort = over ? 1 : 0;
 }
 
 __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
@@ -948,9 +1014,7 @@ __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
 // Fan records of each winner: boundary edges in canonical order (cavity
 // slots ascending, edge index 0..2; the split subsegment is skipped).  The
 // j-th fan triangle takes the j-th cavity slot, then fresh slots.
-__global__ void k_record(DevMesh m, Work w, int nwin) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nwin) return;
+__device__ void record_one(const DevMesh &m, const Work &w, int r) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1006,9 +1070,13 @@ __global__ void k_record(DevMesh m, Work w, int nwin) {
   }
 }
 
-__global__ void k_write(DevMesh m, Work w, int nwin, int serial) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nwin) return;
+__global__ void k_record(DevMesh m, Work w) {
+  if (w.cnt->abort) return;
+  int nwin = w.cnt->nwin;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nwin; r += gridDim.x * blockDim.x) record_one(m, w, r);
+}
+
+__device__ void write_one(const DevMesh &m, const Work &w, int r, int serial) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1066,16 +1134,23 @@ __global__ void k_write(DevMesh m, Work w, int nwin, int serial) {
   }
 }
 
+__global__ void k_write(DevMesh m, Work w, int serial) {
+  if (w.cnt->abort) return;
+  int nwin = w.cnt->nwin;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nwin; r += gridDim.x * blockDim.x)
+    write_one(m, w, r, serial);
+}
+
 // Leaving the loop right after a scan (round cap): drop this round's flags.
 __global__ void k_unflag(Work w, int nmk) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < nmk) w.mflag[w.mid.elem[c]] = 0u;
 }
 
-// R11: clear marks of every grown cavity, update pending flags.
-__global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc + nmk) return;
+// R11: clear marks and bitmap bits of every candidate; pending flags.  A
+// subsegment is split iff its second endpoint is now a new vertex.  After an
+// abandoned round nothing was split and the flags are only released.
+__device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, bool aborted) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1084,15 +1159,27 @@ __global__ void k_finish(Work w, int ncc, int nmk, int32_t *spend) {
     int off = S.off[ci], len = S.len[ci];
     for (int j = 0; j < len; j++) w.mark[w.pool[off + j]] = 0ull;
   }
+  int e = S.elem[ci];
+  uint32_t bit = 1u << (e & 31);
+  if (st & kStW0) atomicAnd(&(is_cc ? w.w0_t : w.w0_s)[e >> 5], ~bit);
+  if (st & kStWin) atomicAnd(&(is_cc ? w.win_t : w.win_s)[e >> 5], ~bit);
   if (!is_cc) {
     // pending := (pending or flagged this round) and not split; an entry the
     // cap skipped is not "flagged" unless R4/R5 flagged it again (own entry)
-    int k = S.elem[ci];
-    bool split = bit_get(w.win_s, k);
-    if (!(st & kStSkip)) spend[k] = split ? 0 : 1;
-    else if (split) spend[k] = 0;
-    w.mflag[k] = 0u;
+    if (!aborted) {
+      bool split = m.sv[e].y >= m.nV;
+      if (!(st & kStSkip)) m.spend[e] = split ? 0 : 1;
+      else if (split) m.spend[e] = 0;
+    }
+    w.mflag[e] = 0u;
   }
+}
+
+__global__ void k_finish(DevMesh m, Work w, int ncc) {
+  int n = ncc + w.cnt->nmk;
+  bool aborted = w.cnt->abort != 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    finish_one(m, w, c, ncc, aborted);
 }
 
 }  // namespace gdp

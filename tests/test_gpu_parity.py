@@ -88,6 +88,16 @@ def test_parity_block_size_invariance(ctx):
         assert not diff_arrays(om.arrays(), gm.arrays()), bs
 
 
+@pytest.mark.parametrize("case", ["c0", "circles_small"])
+def test_parity_grow_on_demand(ctx, case):
+    """Buffers grow only after a round is abandoned for lack of room; the
+    rerun of that round must give the same mesh."""
+    p = SMALL[case]()
+    om, _ = oracle_run(p)
+    gm, _ = gpu_run(ctx, p, reserve_mode=1)
+    assert not diff_arrays(om.arrays(), gm.arrays())
+
+
 def test_parity_from_uploaded_oracle_state(ctx):
     """Phase entry: the oracle's state after 3 rounds, uploaded, refined on the GPU."""
     import oracle

@@ -257,3 +257,19 @@ def test_invalid_inputs_rejected(orc, kind):
     with pytest.raises(orc.OracleError) as e:
         orc.build_cdt(xy, seg)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("f1,n", [(1, 0), (0, 4), (1, 8)])
+def test_prefilters_keep_postconditions(orc, f1, n):
+    """The Line 6 / Line 7 filters only drop candidates: the result still
+    satisfies every post-condition, and the global maximum key of a round is
+    never dropped, so no round stalls."""
+    for p in (workloads.config0(), workloads.scaled_config2(6, 40, 100, seed=5)):
+        m = orc.build_cdt(p.xy, p.seg)
+        orc.refine(m, 2.0, prefilter_f1=f1, cavity_approx_n=n)
+        _full_checks(m, 2.0)
+        assert all(s["n_ins_mid"] + s["n_ins_cc"] > 0 for s in m.stats)
+        if f1:
+            assert sum(s["n_f1_drop"] for s in m.stats) > 0
+        if n:
+            assert sum(s["n_f2_drop"] for s in m.stats) > 0
