@@ -130,6 +130,38 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
   return base + __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Wave-wide reductions and a variable-size allocation (all 64 lanes must
+// take part): one atomic per wave instead of one per lane, which matters for
+// counters every lane updates.
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+  return v;
+}
+
+__device__ __forceinline__ void wave_add(int *counter, int v) {
+  int t = wave_sum(v);
+  if (__lane_id() == 0 && t) atomicAdd(counter, t);
+}
+
+__device__ __forceinline__ int wave_alloc(int *counter, int n) {
+  int lane = __lane_id();
+  int x = n;
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  int total = __shfl(x, 63);
+  int base = 0;
+  if (lane == 63 && total > 0) base = atomicAdd(counter, total);
+  base = __shfl(base, 63);
+  return base + x - n;
+}
+
 __device__ __forceinline__ void flag_mid(const Work &w, int k) {
   if (atomicOr(&w.mflag[k], 1u) == 0u) {
     int idx = atomicAdd(&w.cnt->nmk, 1);
@@ -493,35 +525,6 @@ __device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, in
   return r;
 }
 
-__device__ void finish_cavity(const Work &w, CandSet S, int ci, const CavCheck &ck, int len,
-                              int expect, bool is_cc, const int32_t *src, int stride) {
-  if ((is_cc && ck.enc) || ck.fan_bad || ck.nbnd - len != expect) {
-    atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
-    atomicMax(&w.cnt->cav_max, len);
-    atomicAdd((is_cc && ck.enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
-    S.state[ci] |= kStDone;
-    return;
-  }
-  int off = atomicAdd(&w.cnt->pool_used, len);
-  if (off + len > w.pool_cap) {
-    atomicOr(&w.cnt->err, kErrPool);
-    return;  // the host grows the pool and runs the cavity step again
-  }
-  // R8 marks are placed as soon as the cavity is known to be valid: validity
-  // depends on this cavity alone, and atomicMax does not depend on order.
-  uint64_t key = S.key[ci];
-  for (int j = 0; j < len; j++) {
-    int t = src[(size_t)j * stride];
-    w.pool[off + j] = t;
-    atomicMax((unsigned long long *)&w.mark[t], (unsigned long long)key);
-  }
-  atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
-  atomicMax(&w.cnt->cav_max, len);
-  S.off[ci] = off;
-  S.len[ci] = len;
-  S.state[ci] |= kStDone | kStAlive;
-}
-
 constexpr int kCap = 24;      // per-thread cavity capacity
 constexpr int kCavBlock = 128;
 
@@ -566,19 +569,28 @@ __device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *se
   return len;
 }
 
-__device__ void cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int ci, int is_cc) {
+// Outcome of one per-thread cavity: alive (cavity left in the LDS slice),
+// dropped (with the counter it feeds) or handed to the cooperative kernel.
+struct CavRes {
+  int len;        // cavity size when grown (0 otherwise)
+  int alive;
+  int enc_reject, fan_invalid, unsplittable, mid_cand;
+};
+
+__device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int ci, int is_cc) {
+  CavRes res{0, 0, 0, 0, 0, 0};
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
-  if (st & (kStDone | kStSkip | kStBig)) return;
+  if (st & (kStDone | kStSkip | kStBig)) return res;
   int seeds[2], nseeds = 0, skip_k = -1, expect = 2;
   double2 p;
   if (is_cc) {
-    if (!(st & kStFound)) return;
+    if (!(st & kStFound)) return res;
     seeds[nseeds++] = S.loc[ci];
     p = S.p[ci];
   } else {
     int k = S.elem[ci];
-    atomicAdd(&w.cnt->n_mid_cand, 1);
+    res.mid_cand = 1;
     SplitPt r = seg_split(m, k, w.pm);
     S.key[ci] = r.key;
     p = make_double2(r.px, r.py);
@@ -586,9 +598,9 @@ __device__ void cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ti
     int2 sk = m.sv[k];
     double2 A = m.vxy[sk.x], B = m.vxy[sk.y];
     if ((p.x == A.x && p.y == A.y) || (p.x == B.x && p.y == B.y)) {
-      atomicAdd(&w.cnt->n_unsplittable, 1);
+      res.unsplittable = 1;
       S.state[ci] = st | kStDone;
-      return;
+      return res;
     }
     int a0 = w.sadj[2 * k], a1 = w.sadj[2 * k + 1];
     if (a0 >= 0) seeds[nseeds++] = a0 >> 2;
@@ -603,21 +615,68 @@ __device__ void cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ti
     int q = atomicAdd(&w.cnt->nbig, 1);
     if (q < w.big_cap) w.big[q] = (is_cc ? 0 : (int)0x80000000) | ci;
     else atomicOr(&w.cnt->err, kErrCavity);
-    return;
+    return res;
   }
   auto cav = [&](int j) { return lds[j * kCavBlock + tid]; };
   CavCheck ck = check_cavity(m, w, cav, len, skip_k, is_cc != 0, p);
-  finish_cavity(w, S, ci, ck, len, expect, is_cc != 0, lds + tid, kCavBlock);
+  res.len = len;
+  if (is_cc && ck.enc) {
+    res.enc_reject = 1;
+    S.state[ci] |= kStDone;
+  } else if (ck.fan_bad || ck.nbnd - len != expect) {
+    res.fan_invalid = 1;
+    S.state[ci] |= kStDone;
+  } else {
+    res.alive = 1;
+  }
+  return res;
 }
 
 // Per-thread cavities of one class.  The midpoint list is final when this
 // runs for midpoints (they are flagged only by the scan, the walk and the
-// circumcenter cavities), so its length is read from device memory.
+// circumcenter cavities), so its length is read from device memory.  The
+// loop is uniform over the workgroup so that pool space and statistics are
+// handled once per wave.
 __global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n_host, int is_cc) {
   __shared__ int32_t lds[kCap * kCavBlock];
   int tid = threadIdx.x;
   int n = is_cc ? n_host : w.cnt->nmk;
-  for (int ci = blockIdx.x * kCavBlock + tid; ci < n; ci += gridDim.x * kCavBlock) cavity_one(m, w, lds, tid, ci, is_cc);
+  CandSet S = is_cc ? w.cc : w.mid;
+  for (int base = blockIdx.x * kCavBlock; base < n; base += gridDim.x * kCavBlock) {
+    int ci = base + tid;
+    CavRes r{0, 0, 0, 0, 0, 0};
+    if (ci < n) r = cavity_one(m, w, lds, tid, ci, is_cc);
+    int off = wave_alloc(&w.cnt->pool_used, r.alive ? r.len : 0);
+    bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
+    if (r.alive) {
+      if (off + r.len > w.pool_cap) {
+        atomicOr(&w.cnt->err, kErrPool);  // the round is abandoned and run again
+      } else {
+        // R8 marks are placed as soon as the cavity is known to be valid:
+        // validity depends on this cavity alone, and atomicMax is order free.
+        uint64_t key = S.key[ci];
+        for (int j = 0; j < r.len; j++) {
+          int t = lds[j * kCavBlock + tid];
+          w.pool[off + j] = t;
+          atomicMax((unsigned long long *)&w.mark[t], (unsigned long long)key);
+        }
+        S.off[ci] = off;
+        S.len[ci] = r.len;
+        S.state[ci] |= kStDone | kStAlive;
+        counted = true;
+      }
+    }
+    int lsum = wave_sum(counted ? r.len : 0);
+    int lmax = wave_max(counted ? r.len : 0);
+    if (__lane_id() == 0) {
+      if (lsum) atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)lsum);
+      if (lmax) atomicMax(&w.cnt->cav_max, lmax);
+    }
+    wave_add(&w.cnt->n_enc_reject, r.enc_reject);
+    wave_add(&w.cnt->n_fan_invalid, r.fan_invalid);
+    wave_add(&w.cnt->n_unsplittable, r.unsplittable);
+    wave_add(&w.cnt->n_mid_cand, r.mid_cand);
+  }
 }
 
 // Cooperative growth of one large cavity per workgroup (the tuple-parallel
@@ -801,7 +860,7 @@ __device__ __forceinline__ bool cand_at(const Work &w, int c, int ncc, CandSet &
   S = w.mid; ci = c - ncc; is_cc = 0; return true;
 }
 
-__device__ void own_one(const Work &w, int c, int ncc) {
+__device__ void own_one(const Work &w, int c, int ncc, int &lost) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -815,13 +874,17 @@ __device__ void own_one(const Work &w, int c, int ncc) {
     S.state[ci] = st | kStW0;
     bit_set(is_cc ? w.w0_t : w.w0_s, S.elem[ci]);
   } else {
-    atomicAdd(&w.cnt->n_lost_mark, 1);
+    lost = 1;
   }
 }
 
 __global__ void k_own(Work w, int ncc) {
   int n = ncc + w.cnt->nmk;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) own_one(w, c, ncc);
+  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    int c = base + threadIdx.x, lost = 0;
+    if (c < n) own_one(w, c, ncc, lost);
+    wave_add(&w.cnt->n_lost_mark, lost);
+  }
 }
 
 // R9: Delaunay dependency across a shared non-subsegment cavity edge.
@@ -1014,7 +1077,7 @@ __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
 // Fan records of each winner: boundary edges in canonical order (cavity
 // slots ascending, edge index 0..2; the split subsegment is skipped).  The
 // j-th fan triangle takes the j-th cavity slot, then fresh slots.
-__device__ void record_one(const DevMesh &m, const Work &w, int r) {
+__device__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1024,7 +1087,6 @@ __device__ void record_one(const DevMesh &m, const Work &w, int r) {
   int skip_k = is_cc ? -1 : S.elem[ci];
   int fresh_base = m.nT + w.fbase[r];
   int b = len + (w.fbase[r + 1] - w.fbase[r]);
-  int foff = atomicAdd(&w.cnt->fan_used, b);
   w.fan_off[r] = foff;
   int j = 0;
   for (int q = 0; q < len; q++) {
@@ -1070,10 +1132,21 @@ __device__ void record_one(const DevMesh &m, const Work &w, int r) {
   }
 }
 
+__device__ __forceinline__ int fan_size(const Work &w, int r) {
+  int ref = w.win_ref[r];
+  CandSet S = (ref & 0x80000000) ? w.mid : w.cc;
+  return S.len[ref & 0x7fffffff] + (w.fbase[r + 1] - w.fbase[r]);
+}
+
 __global__ void k_record(DevMesh m, Work w) {
   if (w.cnt->abort) return;
   int nwin = w.cnt->nwin;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nwin; r += gridDim.x * blockDim.x) record_one(m, w, r);
+  for (int base = blockIdx.x * blockDim.x; base < nwin; base += gridDim.x * blockDim.x) {
+    int r = base + threadIdx.x;
+    int b = r < nwin ? fan_size(w, r) : 0;
+    int foff = wave_alloc(&w.cnt->fan_used, b);
+    if (r < nwin) record_one(m, w, r, foff);
+  }
 }
 
 __device__ void write_one(const DevMesh &m, const Work &w, int r, int serial) {
