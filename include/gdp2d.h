@@ -89,10 +89,13 @@ typedef struct {
                                (64..1024, multiple of 64; 0 = default 256) */
   int32_t profile_kernels;  /* 1 = time every kernel launch with HIP events (adds
                                overhead; read with gdp_mesh_kernel_profile) */
-  int32_t reserve_mode;     /* 0 = grow buffers ahead of each round from the
-                               collection counts; 1 = grow only after a round was
+  int32_t reserve_mode;     /* 0 = grow buffers before each group of rounds from the
+                               last counts; 1 = grow only after a round was
                                abandoned for lack of room (then it is run again) */
-  int32_t reserved[4];
+  int32_t rounds_per_sync;  /* rounds queued on the stream between two host
+                               synchronisations (1..64; 0 = automatic: one while
+                               rounds are large, more as they shrink) */
+  int32_t reserved[3];
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */
@@ -101,7 +104,7 @@ typedef struct {
   int64_t launches;
   double total_ms;     /* sum of event-timed launch durations */
   int64_t items;       /* work items over all launches (triangles, candidates, ...) */
-  int64_t alg_bytes;   /* algorithmic HBM bytes (filled for k_scan; 0 otherwise) */
+  int64_t alg_bytes;   /* algorithmic HBM bytes (k_scan and k_cavity_cc; 0 otherwise) */
 } gdp_kernel_prof;
 
 typedef struct {

@@ -43,13 +43,18 @@ struct gdp_mesh {
   int32_t *prev_mid_elem = nullptr;
   int32_t *tstamp = nullptr;
   int32_t *cidx_t = nullptr, *cidx_s = nullptr;
+  // cc.elem/key/p, mid.elem and the prev_* arrays form two list buffers; a
+  // round with an odd serial uses them the other way round
   int32_t serial = 0;  // rounds ever executed on this mesh object (slot stamps)
   uint64_t *keys = nullptr;
-  int32_t *hist = nullptr;
-  uint64_t *thresh = nullptr;
+  int32_t *rhist = nullptr;
+  uint64_t *sel = nullptr;
   int32_t *tiles = nullptr;
   int32_t tiles_cap = 0;
-  int32_t *h_small = nullptr;  // pinned scratch for small reads
+  DevState *d_st = nullptr;
+  DevState *h_st = nullptr;       // pinned
+  DevCounters *d_hist = nullptr;  // counters of the rounds completed since the last sync
+  DevCounters *h_hist = nullptr;  // pinned
   int32_t wT = 0, wS = 0;      // workspace capacities (triangles, subsegments)
   std::vector<gdp_round_stats> stats;
   double last_ms = 0.0;
@@ -58,8 +63,10 @@ struct gdp_mesh {
   struct ProfRec {
     int id;
     hipEvent_t a, b;
+    int round;  // index of the round within its group
     int64_t items, bytes;
   };
+  int cur_round = 0;
   std::vector<ProfRec> prof_pending;
   double prof_ms[16] = {};
   int64_t prof_launches[16] = {}, prof_items[16] = {}, prof_bytes[16] = {};
@@ -73,13 +80,13 @@ enum ProfId {
 const char *kProfNames[P_NUM] = {"k_scan", "k_cap", "k_locate", "k_cavity_cc", "k_cavity_mid", "k_cavity_big",
                                   "k_mark", "k_own", "k_dep", "k_prefix_sum", "k_winners", "k_record", "k_write",
                                   "k_finish"};
-// Records HIP events around the launches issued in its scope (if enabled).
+// Records HIP events around the launches issued in its scope (if enabled);
+// items and algorithmic bytes are filled in once the round's counts are read.
 struct Prof {
   gdp_mesh *M;
   int id;
   hipEvent_t a = nullptr;
-  int64_t items, bytes;
-  Prof(gdp_mesh *M_, int id_, int64_t items_ = 0, int64_t bytes_ = 0) : M(M_), id(id_), items(items_), bytes(bytes_) {
+  Prof(gdp_mesh *M_, int id_) : M(M_), id(id_) {
     if (M->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, M->ctx->stream);
   }
   ~Prof() {
@@ -87,7 +94,7 @@ struct Prof {
     hipEvent_t b = nullptr;
     if (hipEventCreate(&b) != hipSuccess) return;
     (void)hipEventRecord(b, M->ctx->stream);
-    M->prof_pending.push_back({id, a, b, items, bytes});
+    M->prof_pending.push_back({id, a, b, M->cur_round, 0, 0});
   }
 };
 }  // namespace
@@ -237,14 +244,29 @@ gdp_status grow_cand(gdp_mesh *M) {
   return GDP_OK;
 }
 
-Work make_work(gdp_mesh *M, int pm) {
+constexpr int kHistCap = 64;  // rounds queued between two host synchronisations, at most
+
+// Workspace pointers of a round; the two list buffers swap roles with the
+// parity of the round's serial.
+Work make_work(gdp_mesh *M, int pm, int parity) {
   Work w;
+  w.st = M->d_st;
   w.cnt = M->d_cnt;
+  w.hist = M->d_hist;
+  w.hist_cap = kHistCap;
   w.mark = M->mark;
   w.sadj = M->sadj;
   w.mflag = M->mflag;
   w.cc = M->cc;
   w.mid = M->mid;
+  w.prev_cc_elem = M->prev_cc_elem; w.prev_cc_key = M->prev_cc_key; w.prev_cc_p = M->prev_cc_p;
+  w.prev_mid_elem = M->prev_mid_elem;
+  if (parity & 1) {
+    std::swap(w.cc.elem, w.prev_cc_elem);
+    std::swap(w.cc.key, w.prev_cc_key);
+    std::swap(w.cc.p, w.prev_cc_p);
+    std::swap(w.mid.elem, w.prev_mid_elem);
+  }
   w.w0_t = M->w0_t; w.w0_s = M->w0_s; w.win_t = M->win_t; w.win_s = M->win_s;
   w.rank_t = M->rank_t; w.rank_s = M->rank_s;
   w.win_ref = M->win_ref; w.fbase = M->fbase; w.fcount = M->fcount; w.fan_off = M->fan_off;
@@ -253,41 +275,52 @@ Work make_work(gdp_mesh *M, int pm) {
   w.pool = M->pool; w.pool_cap = M->pool_cap;
   w.fan = M->fan; w.fan_cap = M->fan_cap;
   w.big = M->big; w.big_cap = M->wT;
-  w.prev_cc_elem = M->prev_cc_elem; w.prev_cc_key = M->prev_cc_key; w.prev_cc_p = M->prev_cc_p;
-  w.prev_mid_elem = M->prev_mid_elem; w.tstamp = M->tstamp;
+  w.tstamp = M->tstamp;
   w.cidx_t = M->cidx_t; w.cidx_s = M->cidx_s;
-  w.keys = M->keys; w.hist = M->hist; w.thresh = M->thresh;
+  w.keys = M->keys; w.rhist = M->rhist; w.sel = M->sel;
   w.pm = pm;
   return w;
 }
 
 inline unsigned grid_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
-// Exclusive scan of n entries (mode 0: counts, mode 1: popcounts of words);
-// the total is written to *d_total.
-// Exclusive scan (mode 0: counts, mode 1: popcounts of words).  n is the
-// length, or an upper bound when n_dev points to the length in device memory;
-// the total goes to *d_total.
-gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int n, int32_t *d_total, int mode,
-                const int32_t *n_dev = nullptr) {
+// Grid for a grid-stride kernel over about n items.
+inline unsigned stride_grid(int64_t n, int bs) {
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + bs - 1) / bs), 8192);
+}
+
+// Exclusive scan of *n_dev entries (mode 0: counts, mode 1: popcounts of
+// words); n_bound bounds *n_dev and sizes the grid; the total goes to *d_total.
+gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int64_t n_bound, const int32_t *n_dev,
+                int32_t *d_total, int mode) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
-  int ntiles = (n + kScanTileSize - 1) / kScanTileSize;
-  if (ntiles < 1) ntiles = 1;
+  int64_t ntiles = std::max<int64_t>(1, (n_bound + kScanTileSize - 1) / kScanTileSize);
   if (ntiles > M->tiles_cap) return fail(ctx, GDP_E_NOMEM, "scan tile buffer too small");
-  Prof pr(M, P_PREFIX, n);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, in, out, n, M->tiles, mode, n_dev);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, ntiles, d_total, n_dev);
-  hipLaunchKernelGGL(k_scan_add, dim3(std::min<unsigned>(grid_for(std::max(n, 1), 256), 4096)), dim3(256), 0, s,
-                     out, n, M->tiles, n_dev);
+  const int32_t *halt = &M->d_st->halt;
+  Prof pr(M, P_PREFIX);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)std::min<int64_t>(ntiles, 2048)), dim3(256), 0, s, in, out, n_dev,
+                     M->tiles, mode, halt);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, n_dev, d_total, halt);
+  hipLaunchKernelGGL(k_scan_add, dim3(std::min<unsigned>(grid_for(std::max<int64_t>(n_bound, 1), 256), 4096)),
+                     dim3(256), 0, s, out, n_dev, M->tiles, halt);
   HIPCHECK(hipGetLastError());
   return GDP_OK;
 }
 
-gdp_status read_counters(gdp_mesh *M) {
+// Small device buffers and their pinned host mirrors.
+gdp_status alloc_control(gdp_mesh *M) {
   gdp_ctx *ctx = M->ctx;
-  HIPCHECK(hipMemcpyAsync(M->h_cnt, M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  auto ok = [](hipError_t e) { return e == hipSuccess; };
+  if (!ok(dalloc(&M->d_cnt, 1)) || !ok(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters))) ||
+      !ok(dalloc(&M->d_st, 1)) || !ok(hipHostMalloc((void **)&M->h_st, sizeof(DevState))) ||
+      !ok(dalloc(&M->d_hist, kHistCap)) || !ok(hipHostMalloc((void **)&M->h_hist, sizeof(DevCounters) * kHistCap)) ||
+      !ok(dalloc(&M->rhist, 256)) || !ok(dalloc(&M->sel, 4)))
+    return fail(ctx, GDP_E_NOMEM, "allocation failed");
+  HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), ctx->stream));
+  HIPCHECK(hipMemsetAsync(M->d_st, 0, sizeof(DevState), ctx->stream));
+  HIPCHECK(hipMemsetAsync(M->rhist, 0, 256 * sizeof(int32_t), ctx->stream));
+  HIPCHECK(hipMemsetAsync(M->sel, 0, 4 * sizeof(uint64_t), ctx->stream));
   return GDP_OK;
 }
 
@@ -297,13 +330,14 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->cc.elem, M->cc.key, M->cc.p, M->cc.loc, M->cc.state, M->cc.off, M->cc.len,
                   M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
-                  M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->hist, M->thresh,
-                  M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
+                  M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->rhist, M->sel,
+                  M->d_st, M->d_hist, M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
                   M->cidx_t, M->cidx_s};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
-  if (M->h_small) (void)hipHostFree(M->h_small);
+  if (M->h_st) (void)hipHostFree(M->h_st);
+  if (M->h_hist) (void)hipHostFree(M->h_hist);
 }
 
 // Allocates a device mesh with room for the given counts and uploads it.
@@ -359,49 +393,13 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
       !chk(hipMemcpyAsync(M->m.spar, hsp.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload") ||
       !chk(hipMemcpyAsync(M->m.spend, hpend.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload"))
     return bail(GDP_E_DEVICE);
-  if (!chk(dalloc(&M->d_cnt, 1), "alloc") || !chk(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters)), "alloc") ||
-      !chk(hipHostMalloc((void **)&M->h_small, 1024 * sizeof(int32_t)), "alloc") ||
-      !chk(dalloc(&M->hist, 256), "alloc") || !chk(dalloc(&M->thresh, 1), "alloc"))
-    return bail(GDP_E_DEVICE);
+  if ((st = alloc_control(M)) != GDP_OK) return bail(st);
   M->pool_cap = std::max(1 << 16, 8 * capT);
   if (!chk(dalloc(&M->pool, M->pool_cap), "alloc")) return bail(GDP_E_DEVICE);
   M->fan_cap = std::max(1 << 16, 2 * capT);
   if (!chk(dalloc(&M->fan, M->fan_cap), "alloc")) return bail(GDP_E_DEVICE);
   if (!chk(hipStreamSynchronize(s), "sync")) return bail(GDP_E_DEVICE);
   *out = M;
-  return GDP_OK;
-}
-
-// Grid for a grid-stride kernel over at most n items.
-inline unsigned stride_grid(int64_t n, int bs) {
-  return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + bs - 1) / bs), 8192);
-}
-
-// Ensures the buffers a round may need, given the scan's counts (a loose
-// bound; the device-side check abandons the round if it is not enough).
-gdp_status reserve_round(gdp_mesh *M, int ncc, int nmk) {
-  gdp_ctx *ctx = M->ctx;
-  const DevMesh &m = M->m;
-  int64_t wins = (int64_t)ncc + nmk + (ncc >> 3) + 64;
-  gdp_status st;
-  if ((st = grow_vtx(M, (int32_t)std::min<int64_t>(m.nV + wins, 1 << 29)))) return st;
-  if ((st = grow_tri(M, (int32_t)std::min<int64_t>(m.nT + 2 * wins, 1 << 29)))) return st;
-  if ((st = grow_seg(M, (int32_t)std::min<int64_t>(m.nS + nmk + (ncc >> 3) + 64, 1 << 28)))) return st;
-  if ((st = grow_cand(M))) return st;
-  int64_t pool_need = 6 * ((int64_t)ncc + nmk) + 4096;
-  if (pool_need > M->pool_cap) {
-    int64_t nc = std::max<int64_t>(pool_need, (int64_t)M->pool_cap * 3 / 2);
-    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
-    HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
-    M->pool_cap = (int32_t)nc;
-  }
-  int64_t fan_need = std::min<int64_t>(M->pool_cap, pool_need) + 2 * wins;
-  if (fan_need > M->fan_cap) {
-    int64_t nc = std::max<int64_t>(fan_need, (int64_t)M->fan_cap * 3 / 2);
-    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "fan buffer limit exceeded");
-    HIPCHECK(dgrow(&M->fan, M->fan_cap, nc, 0, 0, ctx->stream));
-    M->fan_cap = (int32_t)nc;
-  }
   return GDP_OK;
 }
 
@@ -432,14 +430,217 @@ gdp_status grow_after_abort(gdp_mesh *M, const DevCounters &c, int keep_fan) {
   return GDP_OK;
 }
 
+// Queues one round (Algorithm 1, Lines 3-9) on the stream.  Every length
+// comes from device memory; `est` (an estimate of the candidates) only sizes
+// the grids.  `full` selects the full collection (first round of a call).
+gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full, int parity, int64_t est,
+                         int group_index) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  const DevMesh &m = M->m;
+  const int bs = P->block_size;
+  const int pm = P->priority_mode;
+  Work w = make_work(M, pm, parity);
+  est = std::max<int64_t>(est, 1);
+  M->cur_round = group_index;
+  // ---- R1 collection ----
+  {
+    Prof pr(M, P_SCAN);
+    if (full) {
+      hipLaunchKernelGGL(k_scan, dim3(stride_grid(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
+    } else {
+      hipLaunchKernelGGL(k_carry, dim3(stride_grid(est, bs)), dim3(bs), 0, s, w);
+      hipLaunchKernelGGL(k_scan_dirty, dim3(stride_grid(3 * est, bs)), dim3(bs), 0, s, m, w, B2, pm);
+      hipLaunchKernelGGL(k_pending, dim3(stride_grid(est / 4, bs)), dim3(bs), 0, s, m, w);
+    }
+  }
+  hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, s, w, P->max_rounds);
+  hipLaunchKernelGGL(k_unflag, dim3(stride_grid(est / 4, bs)), dim3(bs), 0, s, w);
+  const int64_t ncand = full ? (int64_t)m.nT + m.nS : 2 * est;
+  // ---- R3: candidate cap ----
+  if (P->cand_cap_K > 0) {
+    Prof pr(M, P_CAP);
+    hipLaunchKernelGGL(k_gather_keys, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w, pm);
+    const unsigned g = std::min<unsigned>(grid_for(ncand, 256), 1024);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(g), dim3(256), 0, s, w, shift);
+      hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(256), 0, s, w, shift, P->cand_cap_K);
+    }
+    hipLaunchKernelGGL(k_apply_cap, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w);
+  }
+  // ---- R4: locate ----
+  {
+    Prof pr(M, P_LOCATE);
+    hipLaunchKernelGGL(k_locate, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+  }
+  // ---- optional prefilters F1 / F2 on located circumcenters ----
+  if (P->prefilter_f1)
+    for (int mode = 0; mode < 3; mode++)
+      hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode, 0);
+  if (P->cavity_approx_n > 0)
+    for (int mode = 3; mode < 6; mode++)
+      hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode,
+                         P->cavity_approx_n);
+  // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
+  {
+    Prof pr(M, P_CAV_CC);
+    hipLaunchKernelGGL(k_cavity, dim3(stride_grid(ncand, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, 1);
+  }
+  {
+    Prof pr(M, P_CAV_BIG);
+    hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 0);
+  }
+  {
+    Prof pr(M, P_CAV_MID);
+    hipLaunchKernelGGL(k_cavity, dim3(stride_grid(ncand / 4, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, 0);
+  }
+  {
+    Prof pr(M, P_CAV_BIG);
+    hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 1);
+  }
+  // ---- R8 ownership, R9 dependency ----
+  {
+    Prof pr(M, P_OWN);
+    hipLaunchKernelGGL(k_own, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w);
+  }
+  {
+    Prof pr(M, P_DEP);
+    hipLaunchKernelGGL(k_dep, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+  }
+  // ---- R10: ranks, fresh slots, capacity check, insertion ----
+  gdp_status st;
+  if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.capS), &M->d_st->wS, &M->d_cnt->nwin_mid, 1)))
+    return st;
+  if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.capT), &M->d_st->wT, &M->d_cnt->nwin_cc, 1)))
+    return st;
+  hipLaunchKernelGGL(k_nwin, dim3(1), dim3(64), 0, s, w);
+  {
+    Prof pr(M, P_WINNERS);
+    hipLaunchKernelGGL(k_winners, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w);
+  }
+  if ((st = scan(M, M->fcount, M->fbase, std::min<int64_t>(ncand + 1, M->wT), &M->d_cnt->nwin1,
+                 &M->d_cnt->fan_total, 0)))
+    return st;
+  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, m, w);
+  {
+    Prof pr(M, P_RECORD);
+    hipLaunchKernelGGL(k_record, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+  }
+  {
+    Prof pr(M, P_WRITE);
+    hipLaunchKernelGGL(k_write, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+  }
+  {
+    Prof pr(M, P_FINISH);
+    hipLaunchKernelGGL(k_finish, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+  }
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, w);
+  HIPCHECK(hipGetLastError());
+  return GDP_OK;
+}
+
+gdp_round_stats round_stats_of(const DevCounters &c, const gdp_params *P) {
+  gdp_round_stats rs;
+  memset(&rs, 0, sizeof rs);
+  rs.n_bad = c.ncc;
+  rs.n_enc = c.nmk0;
+  rs.n_kept_cc = P->cand_cap_K > 0 ? c.n_kept_cc : c.ncc;
+  rs.n_kept_mid = P->cand_cap_K > 0 ? c.n_kept_mid : c.nmk0;
+  rs.n_blocked = c.n_blocked;
+  rs.n_coincident = c.n_coincident;
+  rs.n_enc_reject = c.n_enc_reject;
+  rs.n_unsplittable = c.n_unsplittable;
+  rs.n_fan_invalid = c.n_fan_invalid;
+  rs.n_lost_mark = c.n_lost_mark;
+  rs.n_dep_drop = c.n_dep_drop;
+  rs.n_ins_mid = c.nwin_mid;
+  rs.n_ins_cc = c.nwin_cc;
+  rs.cav_tri_total = c.cav_tri_total;
+  rs.cav_max = c.cav_max;
+  rs.n_big_cavities = c.nbig;
+  rs.n_mid_cand = c.n_mid_cand;
+  rs.n_f1_drop = c.n_f1_drop;
+  rs.n_f2_drop = c.n_f2_drop;
+  return rs;
+}
+
+// Work items of a profiled launch (round counters c; previous round's list
+// lengths pc / pmk / pf; full = full collection over nT slots).
+int64_t prof_items(int id, const DevCounters &c, int64_t nT, int64_t pc, int64_t pmk, int64_t pf, bool full) {
+  switch (id) {
+    case P_SCAN: return full ? nT : pc + pf + pmk;
+    case P_CAP: return (int64_t)c.ncc + c.nmk0;
+    case P_LOCATE: case P_CAV_CC: return c.ncc;
+    case P_CAV_MID: return c.nmk;
+    case P_CAV_BIG: return c.nbig;
+    case P_RECORD: case P_WRITE: return c.nwin;
+    case P_PREFIX: return 0;
+    default: return (int64_t)c.ncc + c.nmk;
+  }
+}
+
+// Algorithmic bytes of a profiled launch (same arguments).
+//   Collection, full: every triangle record (16 B) and vertex (16 B) once,
+//   both sides of every subsegment (ts record 16 B + side slot 4 B each),
+//   pending flags (4 B), the bad records written (elem 4 + key 8 + point 16
+//   + state 4 B) and the flagged subsegments (flag 4 + list entry 8 B).
+//   Incremental: carried records (elem 4 + key 8 + point 16 read and
+//   written, stamp 4), each rewritten slot (fan slot 4 + record 16 + three
+//   vertices 48) and the previous flagged list (entry 4 + pending flag 4),
+//   plus the new records / flags.
+//   Circumcenter cavities: per candidate its state, located triangle, point
+//   and key (32 B) and state / offset / size written (12 B); per cavity
+//   triangle its tv, tn and ts records (48 B), one new vertex (16 B), the
+//   pool entry (4 B) and its mark (8 B); per boundary edge the outside
+//   triangle's tv record (16 B).
+int64_t alg_bytes(int id, const DevCounters &c, int64_t nT, int64_t nV, int64_t nS, int64_t pc, int64_t pmk,
+                  int64_t pf, bool full) {
+  if (id == P_SCAN)
+    return full ? 16 * nT + 16 * nV + 40 * nS + 4 * nS + 32LL * c.ncc + 12LL * c.nmk0
+                : 64 * pc + 68 * pf + 8 * pmk + 32LL * c.ncc + 12LL * c.nmk0;
+  if (id == P_CAV_CC) return 44LL * c.ncc + 76 * c.cav_len[1] + 16 * c.cav_bnd[1];
+  return 0;
+}
+
+// Grows what a group of R rounds may need, from the candidate count of the
+// last round (a loose bound: the device-side check abandons a round that
+// does not fit, and the host grows and runs it again).
+gdp_status reserve_group(gdp_mesh *M, int64_t last_cand, int R) {
+  gdp_ctx *ctx = M->ctx;
+  const DevMesh &m = M->m;
+  int64_t wins = std::min<int64_t>(last_cand * R + 64, 1 << 28);
+  gdp_status st;
+  if ((st = grow_vtx(M, (int32_t)std::min<int64_t>(m.nV + wins, 1 << 29)))) return st;
+  if ((st = grow_tri(M, (int32_t)std::min<int64_t>(m.nT + 2 * wins, 1 << 29)))) return st;
+  if ((st = grow_seg(M, (int32_t)std::min<int64_t>(m.nS + wins, 1 << 28)))) return st;
+  if ((st = grow_cand(M))) return st;
+  int64_t pool_need = 6 * last_cand + 4096;
+  if (pool_need > M->pool_cap) {
+    int64_t nc = std::max<int64_t>(pool_need, (int64_t)M->pool_cap * 3 / 2);
+    if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+    HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
+    M->pool_cap = (int32_t)nc;
+  }
+  return GDP_OK;
+}
+
+// Queues up to this many rounds before the next host synchronisation.
+int rounds_for(const gdp_params *P, int64_t last_cand) {
+  if (P->profile_kernels) return 1;
+  if (P->rounds_per_sync > 0) return std::min(P->rounds_per_sync, kHistCap);
+  if (last_cand > 65536) return 1;
+  if (last_cand > 8192) return 4;
+  return 16;
+}
+
 // One refinement call: rounds until nothing is left (Algorithm 1, "repeat
-// ... until L is empty").  Each round has two host synchronisations: after
-// the collection (termination, capacity, candidate cap) and at its end.
+// ... until L is empty").  Rounds are queued in groups; the host reads the
+// device state once per group.  A round that finds a buffer short writes
+// nothing and halts the group; the host grows the buffers and runs it again.
 gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
-  const int bs = P->block_size;
-  const int pm = P->priority_mode;
+  DevMesh &m = M->m;
   M->stats.clear();
   M->prof = P->profile_kernels != 0;
   for (int i = 0; i < 16; i++) { M->prof_ms[i] = 0; M->prof_launches[i] = M->prof_items[i] = M->prof_bytes[i] = 0; }
@@ -448,162 +649,81 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   HIPCHECK(hipEventCreate(&ev0));
   HIPCHECK(hipEventCreate(&ev1));
   HIPCHECK(hipEventRecord(ev0, s));
+  // device state from the host's copy of the counts
+  DevState &hs = *M->h_st;
+  memset(&hs, 0, sizeof hs);
+  hs.nV = m.nV; hs.nT = m.nT; hs.nS = m.nS;
+  hs.wT = words(m.nT); hs.wS = words(m.nS);
+  hs.rounds = m.rounds;
+  hs.serial = M->serial;
+  HIPCHECK(hipMemcpyAsync(M->d_st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
   gdp_status result = GDP_OK;
   // The first round of a call tests every element; later rounds carry the
   // previous bad list over and re-test only the slots the last round wrote.
-  bool full_scan = true;
-  int prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
+  bool full = true;
+  int64_t last_cand = (int64_t)m.nT + m.nS;
+  int64_t prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
   int aborts = 0;
   for (;;) {
-    DevMesh &m = M->m;
+    const int R = full ? 1 : rounds_for(P, last_cand);
     gdp_status st;
-    HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
-    Work w = make_work(M, pm);
-    size_t scan_rec = M->prof_pending.size();
-    if (full_scan) {
-      Prof pr(M, P_SCAN, m.nT);
-      hipLaunchKernelGGL(k_scan, dim3(grid_for(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
-    } else {
-      Prof pr(M, P_SCAN, (int64_t)prev_ncc + prev_fan + prev_nmk);
-      hipLaunchKernelGGL(k_carry, dim3(grid_for(prev_ncc, bs)), dim3(bs), 0, s, w, prev_ncc, M->serial - 1);
-      hipLaunchKernelGGL(k_scan_dirty, dim3(grid_for(prev_fan, bs)), dim3(bs), 0, s, m, w, prev_fan, B2, pm);
-      hipLaunchKernelGGL(k_pending, dim3(grid_for(prev_nmk, bs)), dim3(bs), 0, s, m, w, prev_nmk);
+    if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, R))) return st;
+    const int serial0 = M->serial;
+    const size_t prof0 = M->prof_pending.size();
+    for (int i = 0; i < R; i++) {
+      if ((st = enqueue_round(M, B2, P, full && i == 0, serial0 + i, full ? (int64_t)m.nT : last_cand, i)))
+        return st;
     }
-    HIPCHECK(hipGetLastError());
-    if ((st = read_counters(M))) return st;  // sync 1
-    const int ncc = M->h_cnt->ncc;
-    const int nmk0 = M->h_cnt->nmk;
-    if (M->prof && scan_rec < M->prof_pending.size())
-      // algorithmic bytes of the collection.  Full: every triangle record
-      // (16 B) and vertex (16 B) once, both sides of every subsegment (ts
-      // record 16 B + side slot 4 B each), pending flags (4 B), the bad records
-      // written (elem 4 + key 8 + point 16 + state 4 B) and the flagged
-      // subsegments (flag 4 + list entry 8 B).  Incremental: carried records
-      // (elem 4 + key 8 + point 16 read and written, stamp 4), each rewritten
-      // slot (fan slot 4 + record 16 + three vertices 48) and the previous
-      // flagged list (entry 4 + pending flag 4), plus the new records / flags.
-      M->prof_pending[scan_rec].bytes =
-          full_scan ? 16LL * m.nT + 16LL * m.nV + 40LL * m.nS + 4LL * m.nS + 32LL * ncc + 12LL * nmk0
-                    : 64LL * prev_ncc + 68LL * prev_fan + 8LL * prev_nmk + 32LL * ncc + 12LL * nmk0;
-    gdp_round_stats rs;
-    memset(&rs, 0, sizeof rs);
-    rs.n_bad = ncc;
-    rs.n_enc = nmk0;
-    if (ncc == 0 && nmk0 == 0) break;
-    if (P->max_rounds > 0 && m.rounds >= P->max_rounds) {
-      hipLaunchKernelGGL(k_unflag, dim3(grid_for(nmk0, bs)), dim3(bs), 0, s, w, nmk0);
-      HIPCHECK(hipGetLastError());
-      result = fail(ctx, GDP_E_NOTERM, "round cap reached");
-      break;
-    }
-    if (P->reserve_mode == 0 && (st = reserve_round(M, ncc, nmk0))) return st;
-    w = make_work(M, pm);
-    // ---- R3: candidate cap ----
-    bool capped = P->cand_cap_K > 0 && ncc + nmk0 > P->cand_cap_K;
-    if (capped) {
-      int n = ncc + nmk0;
-      Prof pr(M, P_CAP, n);
-      hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(n, bs)), dim3(bs), 0, s, m, w, ncc, nmk0, pm);
-      uint64_t prefix = 0, pmask = 0;
-      int64_t remaining = P->cand_cap_K;
-      for (int shift = 56; shift >= 0; shift -= 8) {
-        HIPCHECK(hipMemsetAsync(M->hist, 0, 256 * sizeof(int32_t), s));
-        hipLaunchKernelGGL(k_radix_hist, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, s, w, n,
-                           shift, prefix, pmask);
-        HIPCHECK(hipMemcpyAsync(M->h_small, M->hist, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        int64_t cum = 0;
-        int d = 255;
-        for (; d > 0; d--) {
-          if (cum + M->h_small[d] >= remaining) break;
-          cum += M->h_small[d];
-        }
-        remaining -= cum;
-        prefix |= (uint64_t)d << shift;
-        pmask |= (uint64_t)0xff << shift;
+    HIPCHECK(hipMemcpyAsync(M->h_st, M->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(M->h_hist, M->d_hist, sizeof(DevCounters) * R, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(M->h_cnt, M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const DevState d = *M->h_st;
+    const int done = std::min(d.nhist, R);
+    // profiled launches (one round per group): items and algorithmic bytes
+    for (size_t k = prof0; k < M->prof_pending.size(); k++) {
+      auto &r = M->prof_pending[k];
+      if (r.round < done) {
+        const DevCounters &c = M->h_hist[r.round];
+        bool f = full && r.round == 0;
+        r.items = prof_items(r.id, c, m.nT, prev_ncc, prev_nmk, prev_fan, f);
+        r.bytes = alg_bytes(r.id, c, m.nT, m.nV, m.nS, prev_ncc, prev_nmk, prev_fan, f);
       }
-      HIPCHECK(hipMemcpyAsync(M->thresh, &prefix, sizeof(uint64_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_apply_cap, dim3(grid_for(n, bs)), dim3(bs), 0, s, w, ncc, nmk0);
-      HIPCHECK(hipGetLastError());
-    } else {
-      rs.n_kept_cc = ncc;
-      rs.n_kept_mid = nmk0;
     }
-    // Bound on the midpoint list after R4/R5 (each list entry is a distinct
-    // subsegment, twice at most with the cap).
-    const int nmk_bound = (int)std::min<int64_t>(2LL * m.nS, (int64_t)nmk0 + ncc + (int64_t)m.nS);
-    const int ncand_bound = ncc + nmk_bound;
-    // ---- R4: locate ----
-    {
-      Prof pr(M, P_LOCATE, ncc);
-      hipLaunchKernelGGL(k_locate, dim3(grid_for(ncc, bs)), dim3(bs), 0, s, m, w, ncc);
+    for (int i = 0; i < done; i++) {
+      const DevCounters &c = M->h_hist[i];
+      M->stats.push_back(round_stats_of(c, P));
+      last_cand = (int64_t)c.ncc + c.nmk;
+      prev_ncc = c.ncc;
+      prev_nmk = c.nmk;
+      prev_fan = c.fan_used;
     }
-    // ---- optional prefilters F1 / F2 on located circumcenters ----
-    if (P->prefilter_f1)
-      for (int mode = 0; mode < 3; mode++)
-        hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode, 0);
-    if (P->cavity_approx_n > 0)
-      for (int mode = 3; mode < 6; mode++)
-        hipLaunchKernelGGL(k_prefilter, dim3(grid_for(ncc, 128)), dim3(128), 0, s, m, w, ncc, mode,
-                           P->cavity_approx_n);
-    // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
-    {
-      Prof pr(M, P_CAV_CC, ncc);
-      hipLaunchKernelGGL(k_cavity, dim3(grid_for(ncc, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, ncc, 1);
+    if (M->prof && d.halt && M->prof_pending.size() > prof0) {
+      // keep the collection of a final round (it ran), drop the rest of it
+      std::vector<gdp_mesh::ProfRec> keep(M->prof_pending.begin(), M->prof_pending.begin() + prof0);
+      for (size_t k = prof0; k < M->prof_pending.size(); k++) {
+        auto &r = M->prof_pending[k];
+        if (r.id == P_SCAN || d.halt == kHaltAbort) keep.push_back(r);
+        else { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+      }
+      M->prof_pending.swap(keep);
     }
-    {
-      Prof pr(M, P_CAV_BIG, 0);
-      hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 0);
-    }
-    {
-      Prof pr(M, P_CAV_MID, nmk0);
-      hipLaunchKernelGGL(k_cavity, dim3(stride_grid(nmk_bound, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w,
-                         0, 0);
-    }
-    {
-      Prof pr(M, P_CAV_BIG, 0);
-      hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 1);
-    }
-    // ---- R8 ownership, R9 dependency ----
-    {
-      Prof pr(M, P_OWN, ncand_bound);
-      hipLaunchKernelGGL(k_own, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, w, ncc);
-    }
-    {
-      Prof pr(M, P_DEP, ncand_bound);
-      hipLaunchKernelGGL(k_dep, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, ncc);
-    }
-    // ---- R10: ranks, fresh slots, capacity check, insertion ----
-    if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.nS), &M->d_cnt->nwin_mid, 1))) return st;
-    if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.nT), &M->d_cnt->nwin_cc, 1))) return st;
-    hipLaunchKernelGGL(k_nwin, dim3(1), dim3(64), 0, s, w);
-    {
-      Prof pr(M, P_WINNERS, ncand_bound);
-      hipLaunchKernelGGL(k_winners, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, w, ncc);
-    }
-    if ((st = scan(M, M->fcount, M->fbase, ncand_bound + 1, &M->d_cnt->pad[0], 0, &M->d_cnt->nwin1))) return st;
-    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, m, w);
-    {
-      Prof pr(M, P_RECORD, ncand_bound);
-      hipLaunchKernelGGL(k_record, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w);
-    }
-    {
-      Prof pr(M, P_WRITE, ncand_bound);
-      hipLaunchKernelGGL(k_write, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, M->serial);
-    }
-    {
-      Prof pr(M, P_FINISH, ncand_bound);
-      hipLaunchKernelGGL(k_finish, dim3(stride_grid(ncand_bound, bs)), dim3(bs), 0, s, m, w, ncc);
-    }
-    HIPCHECK(hipGetLastError());
-    if ((st = read_counters(M))) return st;  // sync 2
-    DevCounters &c = *M->h_cnt;
-    if (c.err & kErrWalk) { result = fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap"); break; }
-    if (c.err & kErrInput) {
-      result = fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment");
-      break;
-    }
-    if (c.err & kErrCavity) {
+    m.nV = d.nV; m.nT = d.nT; m.nS = d.nS; m.rounds = d.rounds;
+    M->serial = d.serial;
+    if (done > 0) full = false;
+    // restart the group bookkeeping for the next group
+    HIPCHECK(hipMemsetAsync(&M->d_st->halt, 0, 2 * sizeof(int32_t), s));  // halt, nhist
+    if (d.halt == 0) { aborts = 0; continue; }
+    const DevCounters &c = *M->h_cnt;
+    if (d.halt == kHaltDone) break;
+    if (d.halt == kHaltCap) { result = fail(ctx, GDP_E_NOTERM, "round cap reached"); break; }
+    if (d.halt == kHaltError) {
+      if (c.err & kErrWalk) { result = fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap"); break; }
+      if (c.err & kErrInput) {
+        result = fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment");
+        break;
+      }
       char buf[256];
       if (c.dbg_set)
         snprintf(buf, sizeof buf, "fan boundary mismatch (cc=%d elem=%d cavity=%d expected=%d found=%d state=%d)",
@@ -613,50 +733,11 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       result = fail(ctx, GDP_E_CAVITY, buf);
       break;
     }
-    if (c.abort) {
-      // nothing was written: grow and run the same round again
-      if (++aborts > 16) return fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
-      DevCounters cc = c;
-      if ((st = grow_after_abort(M, cc, full_scan ? 0 : prev_fan))) return st;
-      continue;
-    }
-    aborts = 0;
-    const int nmk = c.nmk, nwin_mid = c.nwin_mid, nwin_cc = c.nwin_cc, nwin = c.nwin, fresh = c.fresh_total;
-    if (nwin == 0) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); break; }
-    if (capped) {
-      rs.n_kept_cc = c.n_kept_cc;
-      rs.n_kept_mid = c.n_kept_mid;
-    }
-    rs.n_blocked = c.n_blocked;
-    rs.n_coincident = c.n_coincident;
-    rs.n_enc_reject = c.n_enc_reject;
-    rs.n_unsplittable = c.n_unsplittable;
-    rs.n_fan_invalid = c.n_fan_invalid;
-    rs.n_lost_mark = c.n_lost_mark;
-    rs.n_dep_drop = c.n_dep_drop;
-    rs.n_ins_mid = nwin_mid;
-    rs.n_ins_cc = nwin_cc;
-    rs.cav_tri_total = c.cav_tri_total;
-    rs.cav_max = c.cav_max;
-    rs.n_big_cavities = c.nbig;
-    rs.n_mid_cand = c.n_mid_cand;
-    rs.n_f1_drop = c.n_f1_drop;
-    rs.n_f2_drop = c.n_f2_drop;
-    M->stats.push_back(rs);
-    m.nV += nwin;
-    m.nT += fresh;
-    m.nS += nwin_mid;
-    m.rounds += 1;
-    M->serial += 1;
-    // this round's lists become the previous ones
-    prev_ncc = ncc;
-    prev_nmk = nmk;
-    prev_fan = c.fan_used;
-    std::swap(M->cc.elem, M->prev_cc_elem);
-    std::swap(M->cc.key, M->prev_cc_key);
-    std::swap(M->cc.p, M->prev_cc_p);
-    std::swap(M->mid.elem, M->prev_mid_elem);
-    full_scan = false;
+    if (d.halt == kHaltStall) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); break; }
+    // kHaltAbort: nothing was written; grow and run the same round again
+    if (++aborts > 16) return fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
+    if ((st = grow_after_abort(M, c, full ? 0 : d.prev_fan))) return st;
+    HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
   }
   HIPCHECK(hipEventRecord(ev1, s));
   HIPCHECK(hipEventSynchronize(ev1));
@@ -801,6 +882,8 @@ gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, 
     return fail(ctx, GDP_E_ARG, "bad parameter");
   if (P.block_size < 64 || P.block_size > 1024 || P.block_size % 64) return fail(ctx, GDP_E_ARG, "bad block size");
   if (P.reserve_mode != 0 && P.reserve_mode != 1) return fail(ctx, GDP_E_ARG, "bad reserve mode");
+  if (P.rounds_per_sync < 0 || P.rounds_per_sync > kHistCap)
+    return fail(ctx, GDP_E_ARG, "rounds_per_sync must be in [0, 64]");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
   return refine_loop(mesh, ratio_bound_sq, &P);
 }
@@ -955,12 +1038,10 @@ gdp_status gdp_mesh_clone(gdp_ctx *ctx, const gdp_mesh *src, gdp_mesh **out) {
     delete M;
     return st;
   }
-  if (!chk(dalloc(&M->d_cnt, 1)) || !chk(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters))) ||
-      !chk(hipHostMalloc((void **)&M->h_small, 1024 * sizeof(int32_t))) || !chk(dalloc(&M->hist, 256)) ||
-      !chk(dalloc(&M->thresh, 1))) {
+  if ((st = alloc_control(M))) {
     free_mesh_arrays(M);
     delete M;
-    return fail(ctx, GDP_E_NOMEM, "allocation failed");
+    return st;
   }
   M->pool_cap = src->pool_cap;
   M->fan_cap = src->fan_cap;

@@ -61,8 +61,33 @@ struct DevCounters {
   int32_t n_f1_drop, n_f2_drop;
   int32_t nwin, nwin1;  // winners of the round, and nwin + 1 (scan length)
   int32_t abort;        // the round was abandoned before any mesh write (capacity)
-  int32_t pad[1];
+  int32_t nmk0;         // midpoint candidates after the collection (R4/R5 add more)
+  int32_t fan_total;    // total of the fresh-count scan (fbase[nwin] is what is used)
+  int32_t pad0;
+  int64_t cav_len[2];   // per-thread cavities [midpoints, circumcenters]: triangles grown
+  int64_t cav_bnd[2];   // ... and their boundary edges
 };
+static_assert(sizeof(DevCounters) % 8 == 0, "DevCounters is copied as 32-bit words");
+
+// Mesh counts and round control in device memory, so that several rounds
+// can be queued without the host looking at any count in between.
+struct DevState {
+  int32_t nV, nT, nS;    // live counts (advanced at the end of every completed round)
+  int32_t wT, wS;        // bitmap words covering nT / nS (nT / 32 + 1)
+  int32_t rounds;        // rounds completed on the mesh
+  int32_t serial;        // slot stamp of the running round
+  int32_t prev_ncc, prev_nmk, prev_fan;  // list lengths of the last completed round
+  int32_t halt;          // kHalt*: nonzero makes every later round kernel return at once
+  int32_t nhist;         // rounds recorded in the history since the host last read it
+  int32_t done_blocks;   // arrival counter of k_finish's workgroups
+  int32_t pad[3];
+};
+
+constexpr int kHaltDone = 1;   // nothing left to refine
+constexpr int kHaltCap = 2;    // round cap reached with work left
+constexpr int kHaltAbort = 3;  // a buffer was short: the round wrote nothing and must run again
+constexpr int kHaltError = 4;  // walk / input / cavity error (bits in the round counters)
+constexpr int kHaltStall = 5;  // candidates but no winner
 
 constexpr int kErrWalk = 1;
 constexpr int kErrCavity = 2;

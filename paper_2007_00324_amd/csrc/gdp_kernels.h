@@ -13,7 +13,10 @@ struct FanRec {
 
 // Device pointers of the per-round workspace (passed by value to kernels).
 struct Work {
-  DevCounters *cnt;
+  DevState *st;        // counts and round control
+  DevCounters *cnt;    // counters of the running round
+  DevCounters *hist;   // [hist_cap] counters of completed rounds, read by the host
+  int32_t hist_cap;
   uint64_t *mark;      // [capT] max key of the cavities containing the slot
   int32_t *sadj;       // [2*capS] t*4+edge of the triangle on each side (-1 none)
   uint32_t *mflag;     // [capS] subsegment flagged as a midpoint candidate
@@ -41,36 +44,41 @@ struct Work {
   int32_t *cidx_t;     // [capT] candidate index of a bad triangle in this round's list
   int32_t *cidx_s;     // [capS] candidate index of a flagged subsegment
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
-  int32_t *hist;       // [256]
-  uint64_t *thresh;    // [1]
+  int32_t *rhist;      // [256] digit histogram of the radix select (zero between uses)
+  uint64_t *sel;       // [3] radix select: key prefix, prefix mask, keys still to take
   int32_t pm;
 };
 
+// Every round kernel returns at once when st->halt is set; lengths come from
+// device memory, and the grids only bound the parallelism (grid-stride loops).
 __global__ void k_scan(DevMesh m, Work w, double B2, int pm);
-__global__ void k_carry(Work w, int n_prev, int prev_serial);
-__global__ void k_scan_dirty(DevMesh m, Work w, int n_dirty, double B2, int pm);
-__global__ void k_pending(DevMesh m, Work w, int n_prev);
-__global__ void k_gather_keys(DevMesh m, Work w, int ncc, int nmk, int pm);
-__global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t pmask);
-__global__ void k_apply_cap(Work w, int ncc, int nmk);
-__global__ void k_locate(DevMesh m, Work w, int ncc);
-__global__ void k_prefilter(DevMesh m, Work w, int ncc, int mode, int n);
+__global__ void k_carry(Work w);
+__global__ void k_scan_dirty(DevMesh m, Work w, double B2, int pm);
+__global__ void k_pending(DevMesh m, Work w);
+__global__ void k_gate(Work w, int max_rounds);
+__global__ void k_unflag(Work w);
+__global__ void k_gather_keys(DevMesh m, Work w, int pm);
+__global__ void k_radix_hist(Work w, int shift);
+__global__ void k_radix_pick(Work w, int shift, int K);
+__global__ void k_apply_cap(Work w);
+__global__ void k_locate(DevMesh m, Work w);
+__global__ void k_prefilter(DevMesh m, Work w, int mode, int n);
 constexpr int kApproxMaxN = 16;
-__global__ void k_cavity(DevMesh m, Work w, int n_host, int is_cc);
+__global__ void k_cavity(DevMesh m, Work w, int is_cc);
 __global__ void k_cavity_big(DevMesh m, Work w, int phase);
-__global__ void k_own(Work w, int ncc);
-__global__ void k_dep(DevMesh m, Work w, int ncc);
-__global__ void k_scan_tiles(const int32_t *in, int32_t *out, int n, int32_t *tile_sums, int mode,
-                             const int32_t *n_dev);
-__global__ void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total, const int32_t *n_dev);
-__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums, const int32_t *n_dev);
-__global__ void k_winners(Work w, int ncc);
+__global__ void k_own(Work w);
+__global__ void k_dep(DevMesh m, Work w);
+__global__ void k_scan_tiles(const int32_t *in, int32_t *out, const int32_t *n_dev, int32_t *tile_sums, int mode,
+                             const int32_t *halt);
+__global__ void k_scan_sums(int32_t *tile_sums, const int32_t *n_dev, int32_t *total, const int32_t *halt);
+__global__ void k_scan_add(int32_t *out, const int32_t *n_dev, const int32_t *tile_sums, const int32_t *halt);
+__global__ void k_winners(Work w);
 __global__ void k_nwin(Work w);
 __global__ void k_check_capacity(DevMesh m, Work w);
 __global__ void k_record(DevMesh m, Work w);
-__global__ void k_write(DevMesh m, Work w, int serial);
-__global__ void k_unflag(Work w, int nmk);
-__global__ void k_finish(DevMesh m, Work w, int ncc);
+__global__ void k_write(DevMesh m, Work w);
+__global__ void k_finish(DevMesh m, Work w);
+__global__ void k_round_end(Work w);
 
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;

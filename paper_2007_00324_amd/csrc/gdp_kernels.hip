@@ -236,57 +236,66 @@ __device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const 
 
 // Full collection over every triangle and subsegment (first round of a call).
 __global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false;
-  SplitPt r;
-  if (i < m.nT) bad = scan_triangle(m, w, i, B2, pm, r);
-  append_cc(w, bad, i, r);
-  if (i < m.nS && m.spend[i]) flag_mid(w, i);
+  if (w.st->halt) return;
+  const int nT = w.st->nT, nS = w.st->nS, n = max(nT, nS);
+  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    int i = base + threadIdx.x;
+    bool bad = false;
+    SplitPt r;
+    if (i < nT) bad = scan_triangle(m, w, i, B2, pm, r);
+    append_cc(w, bad, i, r);
+    if (i < nS && m.spend[i]) flag_mid(w, i);
+  }
 }
 
 // Incremental collection, later rounds.  A triangle that no winner rewrote
 // keeps its vertices, so its badness and split point are unchanged: the bad
 // triangles of the previous round that were not rewritten are carried over.
-__global__ void k_carry(Work w, int n_prev, int prev_serial) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  bool keep = false;
-  int t = 0;
-  if (c < n_prev) {
-    t = w.prev_cc_elem[c];
-    keep = w.tstamp[t] != prev_serial;
-  }
-  int idx = wave_append(&w.cnt->ncc, keep);
-  if (keep) {
-    w.cc.elem[idx] = t;
-    w.cc.key[idx] = w.prev_cc_key[c];
-    w.cc.p[idx] = w.prev_cc_p[c];
-    w.cc.state[idx] = 0;
-    w.cidx_t[t] = idx;
+__global__ void k_carry(Work w) {
+  if (w.st->halt) return;
+  const int n_prev = w.st->prev_ncc, prev_serial = w.st->serial - 1;
+  for (int base = blockIdx.x * blockDim.x; base < n_prev; base += gridDim.x * blockDim.x) {
+    int c = base + threadIdx.x;
+    bool keep = false;
+    int t = 0;
+    if (c < n_prev) {
+      t = w.prev_cc_elem[c];
+      keep = w.tstamp[t] != prev_serial;
+    }
+    int idx = wave_append(&w.cnt->ncc, keep);
+    if (keep) {
+      w.cc.elem[idx] = t;
+      w.cc.key[idx] = w.prev_cc_key[c];
+      w.cc.p[idx] = w.prev_cc_p[c];
+      w.cc.state[idx] = 0;
+      w.cidx_t[t] = idx;
+    }
   }
 }
 
 // ... and every slot written last round (the fan records) is tested afresh;
 // an encroaching apex can only appear on a rewritten triangle.
-__global__ void k_scan_dirty(DevMesh m, Work w, int n_dirty, double B2, int pm) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false;
-  SplitPt r;
-  int t = 0;
-  if (c < n_dirty) {
-    t = w.fan[c].slot;
-    bad = scan_triangle(m, w, t, B2, pm, r);
+__global__ void k_scan_dirty(DevMesh m, Work w, double B2, int pm) {
+  if (w.st->halt) return;
+  const int n_dirty = w.st->prev_fan;
+  for (int base = blockIdx.x * blockDim.x; base < n_dirty; base += gridDim.x * blockDim.x) {
+    int c = base + threadIdx.x;
+    bool bad = false;
+    SplitPt r;
+    int t = 0;
+    if (c < n_dirty) {
+      t = w.fan[c].slot;
+      bad = scan_triangle(m, w, t, B2, pm, r);
+    }
+    append_cc(w, bad, t, r);
   }
-  append_cc(w, bad, t, r);
 }
 
 // ... and last round's flagged subsegments are tested again: pending, or an
 // apex still inside the diametric circle (a flagged subsegment the candidate
 // cap left out is not pending, and its sides may be unchanged).  The side
 // slots are current: rewritten sides were re-scanned just before.
-__global__ void k_pending(DevMesh m, Work w, int n_prev) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_prev) return;
-  int k = w.prev_mid_elem[c];
+__device__ void pending_one(const DevMesh &m, const Work &w, int k) {
   if (m.spend[k]) {
     flag_mid(w, k);
     return;
@@ -304,25 +313,64 @@ __global__ void k_pending(DevMesh m, Work w, int n_prev) {
   }
 }
 
+__global__ void k_pending(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const int n_prev = w.st->prev_nmk;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_prev; c += gridDim.x * blockDim.x)
+    pending_one(m, w, w.prev_mid_elem[c]);
+}
+
+// After the collection: stop if nothing is left (Algorithm 1, the loop ends
+// when L is empty) or if the round cap is reached with work left.
+__global__ void k_gate(Work w, int max_rounds) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  DevState *st = w.st;
+  if (st->halt) return;
+  DevCounters *c = w.cnt;
+  c->nmk0 = c->nmk;
+  if (c->ncc == 0 && c->nmk == 0) st->halt = kHaltDone;
+  else if (max_rounds > 0 && st->rounds >= max_rounds) st->halt = kHaltCap;
+}
+
 // ---------------------------------------------------------------------------
 // R3 (optional): keep the K largest keys.  Keys of both classes are placed in
 // one array; a radix select finds the K-th largest (keys are unique).
 // ---------------------------------------------------------------------------
-__global__ void k_gather_keys(DevMesh m, Work w, int ncc, int nmk, int pm) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncc) w.keys[c] = w.cc.key[c];
-  else if (c < ncc + nmk) {
-    int j = c - ncc;
-    SplitPt r = seg_split(m, w.mid.elem[j], pm);
-    w.mid.key[j] = r.key;
-    w.mid.p[j] = make_double2(r.px, r.py);
-    w.keys[c] = r.key;
+// Round cap reached: this round's flags are dropped before leaving.
+__global__ void k_unflag(Work w) {
+  if (w.st->halt != kHaltCap) return;
+  const int nmk = w.cnt->nmk;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nmk; c += gridDim.x * blockDim.x)
+    w.mflag[w.mid.elem[c]] = 0u;
+}
+
+__global__ void k_gather_keys(DevMesh m, Work w, int pm) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, nmk = w.cnt->nmk;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w.sel[0] = 0;  // prefix
+    w.sel[1] = 0;  // prefix mask
+  }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc + nmk; c += gridDim.x * blockDim.x) {
+    if (c < ncc) {
+      w.keys[c] = w.cc.key[c];
+    } else {
+      int j = c - ncc;
+      SplitPt r = seg_split(m, w.mid.elem[j], pm);
+      w.mid.key[j] = r.key;
+      w.mid.p[j] = make_double2(r.px, r.py);
+      w.keys[c] = r.key;
+    }
   }
 }
 
-// Histogram of 8-bit digit `shift` over keys whose higher digits equal prefix.
-__global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t pmask) {
+// Histogram of 8-bit digit `shift` over keys whose higher digits equal the
+// prefix chosen so far.
+__global__ void k_radix_hist(Work w, int shift) {
   __shared__ int h[256];
+  if (w.st->halt) return;
+  const int n = w.cnt->ncc + w.cnt->nmk;
+  const uint64_t prefix = w.sel[0], pmask = w.sel[1];
   for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
   __syncthreads();
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -331,22 +379,50 @@ __global__ void k_radix_hist(Work w, int n, int shift, uint64_t prefix, uint64_t
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 256; i += blockDim.x)
-    if (h[i]) atomicAdd(&w.hist[i], h[i]);
+    if (h[i]) atomicAdd(&w.rhist[i], h[i]);
 }
 
-__global__ void k_apply_cap(Work w, int ncc, int nmk) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t th = *w.thresh;
-  if (c < ncc) {
-    if (w.cc.key[c] < th) w.cc.state[c] = kStDone | kStSkip;
-    else atomicAdd(&w.cnt->n_kept_cc, 1);
-  } else if (c < ncc + nmk) {
-    int j = c - ncc;
-    if (w.mid.key[j] < th) {
-      w.mid.state[j] = kStSkip;
-      w.mflag[w.mid.elem[j]] = 0u;
+// Picks the digit of the K-th largest key (keys are unique) and clears the
+// histogram for the next digit.  With no more than K keys the threshold is 0
+// and every key is kept.
+__global__ void k_radix_pick(Work w, int shift, int K) {
+  if (w.st->halt) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int n = w.cnt->ncc + w.cnt->nmk;
+    if (shift == 56) w.sel[2] = (uint64_t)K;
+    if (n > K) {
+      int64_t remaining = (int64_t)w.sel[2];
+      int64_t cum = 0;
+      int d = 255;
+      for (; d > 0; d--) {
+        if (cum + w.rhist[d] >= remaining) break;
+        cum += w.rhist[d];
+      }
+      w.sel[2] = (uint64_t)(remaining - cum);
+      w.sel[0] |= (uint64_t)d << shift;
+      w.sel[1] |= (uint64_t)0xff << shift;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) w.rhist[i] = 0;
+}
+
+__global__ void k_apply_cap(Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, nmk = w.cnt->nmk;
+  const uint64_t th = w.sel[0];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc + nmk; c += gridDim.x * blockDim.x) {
+    if (c < ncc) {
+      if (w.cc.key[c] < th) w.cc.state[c] = kStDone | kStSkip;
+      else atomicAdd(&w.cnt->n_kept_cc, 1);
     } else {
-      atomicAdd(&w.cnt->n_kept_mid, 1);
+      int j = c - ncc;
+      if (w.mid.key[j] < th) {
+        w.mid.state[j] = kStSkip;
+        w.mflag[w.mid.elem[j]] = 0u;
+      } else {
+        atomicAdd(&w.cnt->n_kept_mid, 1);
+      }
     }
   }
 }
@@ -355,9 +431,7 @@ __global__ void k_apply_cap(Work w, int ncc, int nmk) {
 // R4: locate circumcenters by a visibility walk (Line 6); a walk stopped only
 // by subsegments turns into the midpoint candidate of the first one.
 // ---------------------------------------------------------------------------
-__global__ void k_locate(DevMesh m, Work w, int ncc) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncc) return;
+__device__ void locate_one(const DevMesh &m, const Work &w, int c, int nS) {
   if (w.cc.state[c] & kStSkip) return;
   int cur = w.cc.elem[c];
   double2 p = w.cc.p[c];
@@ -392,7 +466,7 @@ __global__ void k_locate(DevMesh m, Work w, int ncc) {
     }
     if (next < 0) {
       int k = comp(m.ts[cur], first_neg);
-      if (k < 0 || k >= m.nS) {  // a hull edge that is not a subsegment
+      if (k < 0 || k >= nS) {  // a hull edge that is not a subsegment
         atomicOr(&w.cnt->err, kErrInput);
         w.cc.state[c] = kStDone;
         return;
@@ -404,6 +478,12 @@ __global__ void k_locate(DevMesh m, Work w, int ncc) {
     }
     cur = next;
   }
+}
+
+__global__ void k_locate(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, nS = w.st->nS;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc; c += gridDim.x * blockDim.x) locate_one(m, w, c, nS);
 }
 
 // ---------------------------------------------------------------------------
@@ -419,11 +499,7 @@ __global__ void k_locate(DevMesh m, Work w, int ncc) {
 constexpr int kApproxMax = 16;
 constexpr int kPreBlock = 128;
 
-__global__ __launch_bounds__(kPreBlock) void k_prefilter(DevMesh m, Work w, int ncc, int mode, int n) {
-  __shared__ int32_t lds[kApproxMax * kPreBlock];
-  int tid = threadIdx.x;
-  int c = blockIdx.x * kPreBlock + tid;
-  if (c >= ncc) return;
+__device__ void prefilter_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int c, int mode, int n) {
   int st = w.cc.state[c];
   if (!(st & kStFound)) return;
   int loc = w.cc.loc[c];
@@ -474,6 +550,14 @@ __global__ __launch_bounds__(kPreBlock) void k_prefilter(DevMesh m, Work w, int 
   } else {
     for (int j = 0; j < len; j++) w.mark[lds[j * kPreBlock + tid]] = 0ull;
   }
+}
+
+__global__ __launch_bounds__(kPreBlock) void k_prefilter(DevMesh m, Work w, int mode, int n) {
+  __shared__ int32_t lds[kApproxMax * kPreBlock];
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc;
+  for (int c = blockIdx.x * kPreBlock + threadIdx.x; c < ncc; c += gridDim.x * kPreBlock)
+    prefilter_one(m, w, lds, threadIdx.x, c, mode, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,12 +657,13 @@ __device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *se
 // dropped (with the counter it feeds) or handed to the cooperative kernel.
 struct CavRes {
   int len;        // cavity size when grown (0 otherwise)
+  int bnd;        // its boundary edges
   int alive;
   int enc_reject, fan_invalid, unsplittable, mid_cand;
 };
 
 __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int ci, int is_cc) {
-  CavRes res{0, 0, 0, 0, 0, 0};
+  CavRes res{0, 0, 0, 0, 0, 0, 0};
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
   if (st & (kStDone | kStSkip | kStBig)) return res;
@@ -620,6 +705,7 @@ __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int 
   auto cav = [&](int j) { return lds[j * kCavBlock + tid]; };
   CavCheck ck = check_cavity(m, w, cav, len, skip_k, is_cc != 0, p);
   res.len = len;
+  res.bnd = ck.nbnd;
   if (is_cc && ck.enc) {
     res.enc_reject = 1;
     S.state[ci] |= kStDone;
@@ -637,14 +723,15 @@ __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int 
 // circumcenter cavities), so its length is read from device memory.  The
 // loop is uniform over the workgroup so that pool space and statistics are
 // handled once per wave.
-__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n_host, int is_cc) {
+__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int is_cc) {
   __shared__ int32_t lds[kCap * kCavBlock];
+  if (w.st->halt) return;
   int tid = threadIdx.x;
-  int n = is_cc ? n_host : w.cnt->nmk;
+  const int n = is_cc ? w.cnt->ncc : w.cnt->nmk;
   CandSet S = is_cc ? w.cc : w.mid;
   for (int base = blockIdx.x * kCavBlock; base < n; base += gridDim.x * kCavBlock) {
     int ci = base + tid;
-    CavRes r{0, 0, 0, 0, 0, 0};
+    CavRes r{0, 0, 0, 0, 0, 0, 0};
     if (ci < n) r = cavity_one(m, w, lds, tid, ci, is_cc);
     int off = wave_alloc(&w.cnt->pool_used, r.alive ? r.len : 0);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
@@ -668,9 +755,12 @@ __global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int n_h
     }
     int lsum = wave_sum(counted ? r.len : 0);
     int lmax = wave_max(counted ? r.len : 0);
+    int glen = wave_sum(r.len), gbnd = wave_sum(r.bnd);
     if (__lane_id() == 0) {
       if (lsum) atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)lsum);
       if (lmax) atomicMax(&w.cnt->cav_max, lmax);
+      if (glen) atomicAdd((unsigned long long *)&w.cnt->cav_len[is_cc], (unsigned long long)glen);
+      if (gbnd) atomicAdd((unsigned long long *)&w.cnt->cav_bnd[is_cc], (unsigned long long)gbnd);
     }
     wave_add(&w.cnt->n_enc_reject, r.enc_reject);
     wave_add(&w.cnt->n_fan_invalid, r.fan_invalid);
@@ -842,6 +932,7 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
 // workgroups stride over the queue.
 __global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int phase) {
   __shared__ BigShared sh;
+  if (w.st->halt) return;
   int nbig = min(w.cnt->nbig, w.big_cap);
   for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
     int ref = w.big[b];
@@ -878,8 +969,9 @@ __device__ void own_one(const Work &w, int c, int ncc, int &lost) {
   }
 }
 
-__global__ void k_own(Work w, int ncc) {
-  int n = ncc + w.cnt->nmk;
+__global__ void k_own(Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
   for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     int c = base + threadIdx.x, lost = 0;
     if (c < n) own_one(w, c, ncc, lost);
@@ -929,8 +1021,9 @@ __device__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
   }
 }
 
-__global__ void k_dep(DevMesh m, Work w, int ncc) {
-  int n = ncc + w.cnt->nmk;
+__global__ void k_dep(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) dep_one(m, w, c, ncc);
 }
 
@@ -967,34 +1060,41 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total) {
   return r;
 }
 
-// mode 0: in[] are counts; mode 1: in[] are 32-bit words, count = popcount
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, int32_t *out, int n,
-                                                           int32_t *tile_sums, int mode, const int32_t *n_dev) {
+// Exclusive scan of n = *n_dev entries in three launches (tiles, tile sums,
+// add).  mode 0: in[] are counts; mode 1: in[] are 32-bit words, count =
+// popcount.  The workgroups stride over the tiles.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, int32_t *out, const int32_t *n_dev,
+                                                           int32_t *tile_sums, int mode, const int32_t *halt) {
   __shared__ int s_total;
-  if (n_dev) n = *n_dev;
-  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int sum = 0;
-  for (int i = 0; i < kScanItems; i++) {
-    int idx = base + i;
-    int x = idx < n ? in[idx] : 0;
-    if (mode == 1) x = __popc((uint32_t)x);
-    v[i] = x;
-    sum += x;
+  if (halt && *halt) return;
+  const int n = *n_dev;
+  const int ntiles = (n + kScanTile - 1) / kScanTile;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int base = tile * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int i = 0; i < kScanItems; i++) {
+      int idx = base + i;
+      int x = idx < n ? in[idx] : 0;
+      if (mode == 1) x = __popc((uint32_t)x);
+      v[i] = x;
+      sum += x;
+    }
+    int excl = block_excl_scan(sum, &s_total);
+    for (int i = 0; i < kScanItems; i++) {
+      int idx = base + i;
+      if (idx < n) out[idx] = excl;
+      excl += v[i];
+    }
+    if (threadIdx.x == 0) tile_sums[tile] = s_total;
   }
-  int excl = block_excl_scan(sum, &s_total);
-  for (int i = 0; i < kScanItems; i++) {
-    int idx = base + i;
-    if (idx < n) out[idx] = excl;
-    excl += v[i];
-  }
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = s_total;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, int ntiles, int32_t *total,
-                                                          const int32_t *n_dev) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, const int32_t *n_dev, int32_t *total,
+                                                          const int32_t *halt) {
   __shared__ int s_total;
-  if (n_dev) ntiles = (*n_dev + kScanTile - 1) / kScanTile;
+  if (halt && *halt) return;
+  const int ntiles = (*n_dev + kScanTile - 1) / kScanTile;
   int carry = 0;
   for (int start = 0; start < ntiles; start += kScanBlock) {
     int idx = start + threadIdx.x;
@@ -1007,8 +1107,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, in
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_scan_add(int32_t *out, int n, const int32_t *tile_sums, const int32_t *n_dev) {
-  if (n_dev) n = *n_dev;
+__global__ void k_scan_add(int32_t *out, const int32_t *n_dev, const int32_t *tile_sums, const int32_t *halt) {
+  if (halt && *halt) return;
+  const int n = *n_dev;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x)
     out[idx] += tile_sums[idx / kScanTile];
 }
@@ -1035,8 +1136,9 @@ __device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
 }
 
 // Winner ranks: midpoints by subsegment id, then circumcenters by slot.
-__global__ void k_winners(Work w, int ncc) {
-  int n = ncc + w.cnt->nmk;
+__global__ void k_winners(Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
   int nwin_mid = w.cnt->nwin_mid;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
     winner_one(w, c, ncc, nwin_mid);
@@ -1047,6 +1149,7 @@ __global__ void k_winners(Work w, int ncc) {
 // round: if anything would overflow, the round is abandoned before the mesh
 // is written and the host grows the buffers and runs it again.
 __global__ void k_nwin(Work w) {
+  if (w.st->halt) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     int nwin = w.cnt->nwin_mid + w.cnt->nwin_cc;
     w.cnt->nwin = nwin;
@@ -1057,13 +1160,15 @@ __global__ void k_nwin(Work w) {
 
 __global__ void k_check_capacity(DevMesh m, Work w) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const DevState *st = w.st;
+  if (st->halt) return;
   DevCounters *c = w.cnt;
   int nwin = c->nwin;
   int fresh = w.fbase[nwin];
   c->fresh_total = fresh;
   int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
-  bool over = (c->err & kErrPool) || (int64_t)m.nV + nwin > m.capV || (int64_t)m.nT + fresh > m.capT ||
-              (int64_t)m.nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
+  bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV || (int64_t)st->nT + fresh > m.capT ||
+              (int64_t)st->nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
   c->abort = over ? 1 : 0;
 }
 
@@ -1085,7 +1190,7 @@ __device__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
   uint64_t key = S.key[ci];
   int off = S.off[ci], len = S.len[ci];
   int skip_k = is_cc ? -1 : S.elem[ci];
-  int fresh_base = m.nT + w.fbase[r];
+  int fresh_base = w.st->nT + w.fbase[r];
   int b = len + (w.fbase[r + 1] - w.fbase[r]);
   w.fan_off[r] = foff;
   int j = 0;
@@ -1139,7 +1244,7 @@ __device__ __forceinline__ int fan_size(const Work &w, int r) {
 }
 
 __global__ void k_record(DevMesh m, Work w) {
-  if (w.cnt->abort) return;
+  if (w.st->halt || w.cnt->abort) return;
   int nwin = w.cnt->nwin;
   for (int base = blockIdx.x * blockDim.x; base < nwin; base += gridDim.x * blockDim.x) {
     int r = base + threadIdx.x;
@@ -1149,7 +1254,7 @@ __global__ void k_record(DevMesh m, Work w) {
   }
 }
 
-__device__ void write_one(const DevMesh &m, const Work &w, int r, int serial) {
+__device__ void write_one(const DevMesh &m, const Work &w, int r, int nV, int nS, int serial) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1157,12 +1262,12 @@ __device__ void write_one(const DevMesh &m, const Work &w, int r, int serial) {
   int len = S.len[ci];
   int b = len + (w.fbase[r + 1] - w.fbase[r]);
   int foff = w.fan_off[r];
-  int pid = m.nV + r;
+  int pid = nV + r;
   double2 p = S.p[ci];
   int k = -1, knew = -1, a = -1, bb = -1;
   if (!is_cc) {
     k = S.elem[ci];
-    knew = m.nS + r;  // midpoint winners take ranks 0..nwin_mid-1
+    knew = nS + r;  // midpoint winners take ranks 0..nwin_mid-1
     int2 sk = m.sv[k];
     a = sk.x;
     bb = sk.y;
@@ -1207,23 +1312,17 @@ __device__ void write_one(const DevMesh &m, const Work &w, int r, int serial) {
   }
 }
 
-__global__ void k_write(DevMesh m, Work w, int serial) {
-  if (w.cnt->abort) return;
-  int nwin = w.cnt->nwin;
+__global__ void k_write(DevMesh m, Work w) {
+  if (w.st->halt || w.cnt->abort) return;
+  const int nwin = w.cnt->nwin, nV = w.st->nV, nS = w.st->nS, serial = w.st->serial;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nwin; r += gridDim.x * blockDim.x)
-    write_one(m, w, r, serial);
-}
-
-// Leaving the loop right after a scan (round cap): drop this round's flags.
-__global__ void k_unflag(Work w, int nmk) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < nmk) w.mflag[w.mid.elem[c]] = 0u;
+    write_one(m, w, r, nV, nS, serial);
 }
 
 // R11: clear marks and bitmap bits of every candidate; pending flags.  A
 // subsegment is split iff its second endpoint is now a new vertex.  After an
 // abandoned round nothing was split and the flags are only released.
-__device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, bool aborted) {
+__device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, int nV, bool aborted) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1240,7 +1339,7 @@ __device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, bool
     // pending := (pending or flagged this round) and not split; an entry the
     // cap skipped is not "flagged" unless R4/R5 flagged it again (own entry)
     if (!aborted) {
-      bool split = m.sv[e].y >= m.nV;
+      bool split = m.sv[e].y >= nV;
       if (!(st & kStSkip)) m.spend[e] = split ? 0 : 1;
       else if (split) m.spend[e] = 0;
     }
@@ -1248,11 +1347,56 @@ __device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, bool
   }
 }
 
-__global__ void k_finish(DevMesh m, Work w, int ncc) {
-  int n = ncc + w.cnt->nmk;
+__global__ void k_finish(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
   bool aborted = w.cnt->abort != 0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    finish_one(m, w, c, ncc, aborted);
+    finish_one(m, w, c, ncc, nV, aborted);
+}
+
+// End of a round: a completed round is recorded in the history, the counts
+// advance, this round's lists become the previous ones and the counters are
+// cleared for the next round.  An error, an abandoned round or a round
+// without winners halts instead (the counters stay for the host to read).
+__global__ void k_round_end(Work w) {
+  __shared__ int s_go, s_slot;
+  DevState *st = w.st;
+  DevCounters *c = w.cnt;
+  if (threadIdx.x == 0) {
+    s_go = 0;
+    s_slot = -1;
+    if (st->halt) {
+      // a halted round records nothing
+    } else if (c->err & (kErrWalk | kErrInput | kErrCavity)) st->halt = kHaltError;
+    else if (c->abort) st->halt = kHaltAbort;
+    else if (c->nwin == 0) st->halt = kHaltStall;
+    else {
+      s_go = 1;
+      if (st->nhist < w.hist_cap) s_slot = st->nhist;
+      st->nhist += 1;
+      st->nV += c->nwin;
+      st->nT += c->fresh_total;
+      st->nS += c->nwin_mid;
+      st->wT = st->nT / 32 + 1;
+      st->wS = st->nS / 32 + 1;
+      st->rounds += 1;
+      st->serial += 1;
+      st->prev_ncc = c->ncc;
+      st->prev_nmk = c->nmk;
+      st->prev_fan = c->fan_used;
+    }
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const int nw = (int)(sizeof(DevCounters) / 4);
+  int32_t *src = (int32_t *)c;
+  if (s_slot >= 0) {
+    int32_t *dst = (int32_t *)&w.hist[s_slot];
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) src[i] = 0;
 }
 
 }  // namespace gdp

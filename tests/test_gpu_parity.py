@@ -19,9 +19,12 @@ def ctx():
     return gdp2d.Context(0)
 
 
+PERF_ONLY = ("reserve_mode", "rounds_per_sync", "block_size")
+
+
 def _check(ctx, p, **kw):
     print(f"[parity] {p.name} {kw}", flush=True)
-    om, orc_rc = oracle_run(p, **kw)
+    om, orc_rc = oracle_run(p, **{k: v for k, v in kw.items() if k not in PERF_ONLY})
     gm, gpu_rc = gpu_run(ctx, p, **kw)
     assert orc_rc == gpu_rc
     a, b = om.arrays(), gm.arrays()
@@ -96,6 +99,27 @@ def test_parity_grow_on_demand(ctx, case):
     om, _ = oracle_run(p)
     gm, _ = gpu_run(ctx, p, reserve_mode=1)
     assert not diff_arrays(om.arrays(), gm.arrays())
+
+
+@pytest.mark.parametrize("rps", [1, 3, 64])
+def test_parity_rounds_per_sync(ctx, rps):
+    """Rounds queued in groups between host synchronisations give the same mesh."""
+    _check(ctx, workloads.random_small(47, 900, 45), rounds_per_sync=rps)
+
+
+@pytest.mark.parametrize("kw", [dict(reserve_mode=1, rounds_per_sync=8), dict(cand_cap_K=9, rounds_per_sync=5),
+                                dict(max_rounds=7, rounds_per_sync=4), dict(prefilter_f1=1, cavity_approx_n=3,
+                                                                            rounds_per_sync=16)])
+def test_parity_grouped_rounds_with_options(ctx, kw):
+    """A round abandoned for lack of room, the candidate cap, the round cap and
+    the prefilters inside a group of queued rounds."""
+    p = workloads.scaled_config2(6, 40, 100, seed=5)
+    print(f"[parity] grouped {kw}", flush=True)
+    om, orc_rc = oracle_run(p, **{k: v for k, v in kw.items() if k not in PERF_ONLY})
+    gm, gpu_rc = gpu_run(ctx, p, **kw)
+    assert orc_rc == gpu_rc
+    assert not diff_arrays(om.arrays(), gm.arrays())
+    assert not diff_stats(om.stats, gm.round_stats())
 
 
 def test_parity_from_uploaded_oracle_state(ctx):
