@@ -22,6 +22,15 @@ struct gdp_ctx {
 struct gdp_mesh {
   gdp_ctx *ctx = nullptr;
   DevMesh m;
+  // Two rounds (parity p, then the other) captured as one HIP graph, for
+  // groups of small rounds; rebuilt when a buffer, a parameter or the grid
+  // estimate changes.
+  struct RoundGraph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t key = 0;
+    int64_t est = 0;
+  } graph[2];
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
   DevCounters *d_cnt = nullptr;
   DevCounters *h_cnt = nullptr;  // pinned
   uint64_t *mark = nullptr;
@@ -49,7 +58,7 @@ struct gdp_mesh {
   uint64_t *keys = nullptr;
   int32_t *rhist = nullptr;
   uint64_t *sel = nullptr;
-  int32_t *tiles = nullptr;
+  int32_t *tiles_t = nullptr, *tiles_s = nullptr, *tiles_f = nullptr;  // tile prefixes of the three scans
   int32_t tiles_cap = 0;
   DevState *d_st = nullptr;
   DevState *h_st = nullptr;       // pinned
@@ -238,7 +247,9 @@ gdp_status grow_cand(gdp_mesh *M) {
   HIPCHECK(dgrow(&M->big, keep, nc, keep, 0, s));
   HIPCHECK(dgrow(&M->keys, keep, nc, keep, 0, s));
   int64_t nt = nc / kScanTileSize + 2;
-  HIPCHECK(dgrow(&M->tiles, 0, nt, 0, 0, s));
+  HIPCHECK(dgrow(&M->tiles_t, 0, nt, 0, 0, s));
+  HIPCHECK(dgrow(&M->tiles_s, 0, nt, 0, 0, s));
+  HIPCHECK(dgrow(&M->tiles_f, 0, nt, 0, 0, s));
   M->tiles_cap = (int32_t)nt;
   M->wT = (int32_t)nc;
   return GDP_OK;
@@ -250,6 +261,7 @@ constexpr int kHistCap = 64;  // rounds queued between two host synchronisations
 // parity of the round's serial.
 Work make_work(gdp_mesh *M, int pm, int parity) {
   Work w;
+  memset(&w, 0, sizeof w);  // no stray padding bytes (graph keys hash the struct)
   w.st = M->d_st;
   w.cnt = M->d_cnt;
   w.hist = M->d_hist;
@@ -269,6 +281,7 @@ Work make_work(gdp_mesh *M, int pm, int parity) {
   }
   w.w0_t = M->w0_t; w.w0_s = M->w0_s; w.win_t = M->win_t; w.win_s = M->win_s;
   w.rank_t = M->rank_t; w.rank_s = M->rank_s;
+  w.tiles_t = M->tiles_t; w.tiles_s = M->tiles_s; w.tiles_f = M->tiles_f;
   w.win_ref = M->win_ref; w.fbase = M->fbase; w.fcount = M->fcount; w.fan_off = M->fan_off;
   w.win_cap = M->wT;
   w.repl = M->repl;
@@ -282,6 +295,13 @@ Work make_work(gdp_mesh *M, int pm, int parity) {
   return w;
 }
 
+// FNV-1a over raw bytes.
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = (const unsigned char *)p;
+  for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
 inline unsigned grid_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // Grid for a grid-stride kernel over about n items.
@@ -289,21 +309,18 @@ inline unsigned stride_grid(int64_t n, int bs) {
   return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + bs - 1) / bs), 8192);
 }
 
-// Exclusive scan of *n_dev entries (mode 0: counts, mode 1: popcounts of
-// words); n_bound bounds *n_dev and sizes the grid; the total goes to *d_total.
-gdp_status scan(gdp_mesh *M, const int32_t *in, int32_t *out, int64_t n_bound, const int32_t *n_dev,
-                int32_t *d_total, int mode) {
+// Exclusive scans of one or two jobs (b.in == nullptr: one); n_bound bounds
+// the lengths (in device memory) and sizes the grid.
+gdp_status scan(gdp_mesh *M, const ScanJob &a, const ScanJob &b, int64_t n_bound) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
   int64_t ntiles = std::max<int64_t>(1, (n_bound + kScanTileSize - 1) / kScanTileSize);
   if (ntiles > M->tiles_cap) return fail(ctx, GDP_E_NOMEM, "scan tile buffer too small");
   const int32_t *halt = &M->d_st->halt;
   Prof pr(M, P_PREFIX);
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)std::min<int64_t>(ntiles, 2048)), dim3(256), 0, s, in, out, n_dev,
-                     M->tiles, mode, halt);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, M->tiles, n_dev, d_total, halt);
-  hipLaunchKernelGGL(k_scan_add, dim3(std::min<unsigned>(grid_for(std::max<int64_t>(n_bound, 1), 256), 4096)),
-                     dim3(256), 0, s, out, n_dev, M->tiles, halt);
+  unsigned g = (unsigned)std::min<int64_t>((b.in ? 2 : 1) * ntiles, 2048);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(g), dim3(256), 0, s, a, b, halt);
+  hipLaunchKernelGGL(k_scan_sums, dim3(b.in ? 2 : 1), dim3(256), 0, s, a, b, halt);
   HIPCHECK(hipGetLastError());
   return GDP_OK;
 }
@@ -331,13 +348,16 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
                   M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->rhist, M->sel,
-                  M->d_st, M->d_hist, M->tiles, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
+                  M->d_st, M->d_hist, M->tiles_t, M->tiles_s, M->tiles_f, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
                   M->cidx_t, M->cidx_s};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
   if (M->h_st) (void)hipHostFree(M->h_st);
   if (M->h_hist) (void)hipHostFree(M->h_hist);
+  for (auto &g : M->graph)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
 }
 
 // Allocates a device mesh with room for the given counts and uploads it.
@@ -446,16 +466,14 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   // ---- R1 collection ----
   {
     Prof pr(M, P_SCAN);
-    if (full) {
+    if (full)
       hipLaunchKernelGGL(k_scan, dim3(stride_grid(std::max(m.nT, m.nS), bs)), dim3(bs), 0, s, m, w, B2, pm);
-    } else {
-      hipLaunchKernelGGL(k_carry, dim3(stride_grid(est, bs)), dim3(bs), 0, s, w);
-      hipLaunchKernelGGL(k_scan_dirty, dim3(stride_grid(3 * est, bs)), dim3(bs), 0, s, m, w, B2, pm);
+    else {
+      hipLaunchKernelGGL(k_collect, dim3(stride_grid(3 * est, bs)), dim3(bs), 0, s, m, w, B2, pm);
       hipLaunchKernelGGL(k_pending, dim3(stride_grid(est / 4, bs)), dim3(bs), 0, s, m, w);
     }
   }
-  hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, s, w, P->max_rounds);
-  hipLaunchKernelGGL(k_unflag, dim3(stride_grid(est / 4, bs)), dim3(bs), 0, s, w);
+  hipLaunchKernelGGL(k_gate, dim3(1), dim3(256), 0, s, w, P->max_rounds);
   const int64_t ncand = full ? (int64_t)m.nT + m.nS : 2 * est;
   // ---- R3: candidate cap ----
   if (P->cand_cap_K > 0) {
@@ -509,19 +527,16 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   }
   // ---- R10: ranks, fresh slots, capacity check, insertion ----
   gdp_status st;
-  if ((st = scan(M, (const int32_t *)M->win_s, M->rank_s, words(m.capS), &M->d_st->wS, &M->d_cnt->nwin_mid, 1)))
-    return st;
-  if ((st = scan(M, (const int32_t *)M->win_t, M->rank_t, words(m.capT), &M->d_st->wT, &M->d_cnt->nwin_cc, 1)))
-    return st;
-  hipLaunchKernelGGL(k_nwin, dim3(1), dim3(64), 0, s, w);
+  const ScanJob js{(const int32_t *)M->win_s, M->rank_s, &M->d_st->wS, M->tiles_s, &M->d_cnt->nwin_mid, 1};
+  const ScanJob jt{(const int32_t *)M->win_t, M->rank_t, &M->d_st->wT, M->tiles_t, &M->d_cnt->nwin_cc, 1};
+  const ScanJob jf{M->fcount, M->fbase, &M->d_cnt->nwin1, M->tiles_f, &M->d_cnt->fan_total, 0};
+  const ScanJob none{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+  if ((st = scan(M, js, jt, std::max(words(m.capS), words(m.capT))))) return st;
   {
     Prof pr(M, P_WINNERS);
     hipLaunchKernelGGL(k_winners, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w);
   }
-  if ((st = scan(M, M->fcount, M->fbase, std::min<int64_t>(ncand + 1, M->wT), &M->d_cnt->nwin1,
-                 &M->d_cnt->fan_total, 0)))
-    return st;
-  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, m, w);
+  if ((st = scan(M, jf, none, std::min<int64_t>(ncand + 1, M->wT)))) return st;
   {
     Prof pr(M, P_RECORD);
     hipLaunchKernelGGL(k_record, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
@@ -532,9 +547,9 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   }
   {
     Prof pr(M, P_FINISH);
-    hipLaunchKernelGGL(k_finish, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+    // at most 1024 workgroups: each one arrives on one counter at its end
+    hipLaunchKernelGGL(k_finish, dim3(std::min(stride_grid(ncand, bs), 1024u)), dim3(bs), 0, s, m, w);
   }
-  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, w);
   HIPCHECK(hipGetLastError());
   return GDP_OK;
 }
@@ -624,13 +639,79 @@ gdp_status reserve_group(gdp_mesh *M, int64_t last_cand, int R) {
   return GDP_OK;
 }
 
+// Everything a captured pair of rounds depends on besides device memory.
+uint64_t graph_key(gdp_mesh *M, double B2, const gdp_params *P, int64_t est) {
+  DevMesh m = M->m;
+  m.nV = m.nT = m.nS = m.rounds = 0;  // counts are read from device memory
+  Work w = make_work(M, P->priority_mode, 0);
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, &m, sizeof m);
+  h = fnv(h, &w, sizeof w);
+  h = fnv(h, &B2, sizeof B2);
+  h = fnv(h, P, sizeof *P);
+  h = fnv(h, &est, sizeof est);
+  h = fnv(h, &M->tiles_cap, sizeof M->tiles_cap);
+  return h;
+}
+
+// Queues `pairs` x (round of parity p, round of parity p ^ 1) as replays of
+// a captured graph, capturing it first if needed.
+gdp_status launch_pairs(gdp_mesh *M, double B2, const gdp_params *P, int p, int pairs, int64_t est) {
+  gdp_ctx *ctx = M->ctx;
+  // grids are sized for a power of two at or above the estimate, and kept
+  // while the estimate stays within a factor 64 below it
+  int64_t cap = 256;
+  while (cap < est) cap <<= 1;
+  gdp_mesh::RoundGraph &g = M->graph[p];
+  if (g.exec && (est > g.est || est * 64 < g.est)) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+  int64_t use = g.exec ? g.est : cap;
+  uint64_t key = graph_key(M, B2, P, use);
+  if (g.exec && g.key != key) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    use = cap;
+    key = graph_key(M, B2, P, use);
+  }
+  if (!g.exec) {
+    if (!M->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = ctx->stream;
+    ctx->stream = M->cap_stream;
+    HIPCHECK(hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeThreadLocal));
+    gdp_status st = enqueue_round(M, B2, P, false, p, use, 0);
+    if (st == GDP_OK) st = enqueue_round(M, B2, P, false, p ^ 1, use, 1);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(M->cap_stream, &graph);
+    ctx->stream = user;
+    if (st != GDP_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    HIPCHECK(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(e);
+    g.exec = exec;
+    g.key = key;
+    g.est = use;
+  }
+  for (int i = 0; i < pairs; i++) HIPCHECK(hipGraphLaunch(g.exec, ctx->stream));
+  return GDP_OK;
+}
+
 // Queues up to this many rounds before the next host synchronisation.
+// Groups of two or more rounds are queued as graph replays, in pairs.
 int rounds_for(const gdp_params *P, int64_t last_cand) {
   if (P->profile_kernels) return 1;
-  if (P->rounds_per_sync > 0) return std::min(P->rounds_per_sync, kHistCap);
-  if (last_cand > 65536) return 1;
-  if (last_cand > 8192) return 4;
-  return 16;
+  int r;
+  if (P->rounds_per_sync > 0) r = std::min(P->rounds_per_sync, kHistCap);
+  else if (last_cand > 65536) r = 1;
+  else if (last_cand > 8192) r = 4;
+  else r = 16;
+  return r >= 2 ? r & ~1 : r;
 }
 
 // One refinement call: rounds until nothing is left (Algorithm 1, "repeat
@@ -671,12 +752,18 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, R))) return st;
     const int serial0 = M->serial;
     const size_t prof0 = M->prof_pending.size();
-    for (int i = 0; i < R; i++) {
-      if ((st = enqueue_round(M, B2, P, full && i == 0, serial0 + i, full ? (int64_t)m.nT : last_cand, i)))
-        return st;
+    if (R >= 2 && !full && !M->prof) {
+      // small rounds: replays of a captured pair of rounds
+      if ((st = launch_pairs(M, B2, P, serial0 & 1, R / 2, last_cand))) return st;
+    } else {
+      for (int i = 0; i < R; i++) {
+        if ((st = enqueue_round(M, B2, P, full && i == 0, serial0 + i, full ? (int64_t)m.nT : last_cand, i)))
+          return st;
+      }
     }
     HIPCHECK(hipMemcpyAsync(M->h_st, M->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(M->h_hist, M->d_hist, sizeof(DevCounters) * R, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(M->h_hist, M->d_hist, sizeof(DevCounters) * std::min(R, kHistCap),
+                            hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(M->h_cnt, M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     const DevState d = *M->h_st;

@@ -22,7 +22,8 @@ struct Work {
   uint32_t *mflag;     // [capS] subsegment flagged as a midpoint candidate
   CandSet cc, mid;
   uint32_t *w0_t, *w0_s, *win_t, *win_s;  // element bitmaps
-  int32_t *rank_t, *rank_s;               // exclusive prefix of bitmap popcounts
+  int32_t *rank_t, *rank_s;               // exclusive prefix of bitmap popcounts (per tile)
+  int32_t *tiles_t, *tiles_s, *tiles_f;   // tile prefixes of the three scans
   int32_t *win_ref;    // [nwin] winner -> (class bit 31 set for midpoints) | candidate
   int32_t *fbase;      // [nwin+1] exclusive prefix of fresh-slot counts
   int32_t *fcount;     // [nwin] fresh slots per winner (1 or 2)
@@ -49,14 +50,22 @@ struct Work {
   int32_t pm;
 };
 
+// One exclusive scan (see k_scan_tiles).
+struct ScanJob {
+  const int32_t *in;
+  int32_t *out;
+  const int32_t *n_dev;  // length in device memory
+  int32_t *tiles;        // per-tile totals, then their exclusive prefix
+  int32_t *total;
+  int mode;              // 0: counts, 1: popcounts of 32-bit words
+};
+
 // Every round kernel returns at once when st->halt is set; lengths come from
 // device memory, and the grids only bound the parallelism (grid-stride loops).
 __global__ void k_scan(DevMesh m, Work w, double B2, int pm);
-__global__ void k_carry(Work w);
-__global__ void k_scan_dirty(DevMesh m, Work w, double B2, int pm);
+__global__ void k_collect(DevMesh m, Work w, double B2, int pm);
 __global__ void k_pending(DevMesh m, Work w);
 __global__ void k_gate(Work w, int max_rounds);
-__global__ void k_unflag(Work w);
 __global__ void k_gather_keys(DevMesh m, Work w, int pm);
 __global__ void k_radix_hist(Work w, int shift);
 __global__ void k_radix_pick(Work w, int shift, int K);
@@ -68,17 +77,12 @@ __global__ void k_cavity(DevMesh m, Work w, int is_cc);
 __global__ void k_cavity_big(DevMesh m, Work w, int phase);
 __global__ void k_own(Work w);
 __global__ void k_dep(DevMesh m, Work w);
-__global__ void k_scan_tiles(const int32_t *in, int32_t *out, const int32_t *n_dev, int32_t *tile_sums, int mode,
-                             const int32_t *halt);
-__global__ void k_scan_sums(int32_t *tile_sums, const int32_t *n_dev, int32_t *total, const int32_t *halt);
-__global__ void k_scan_add(int32_t *out, const int32_t *n_dev, const int32_t *tile_sums, const int32_t *halt);
+__global__ void k_scan_tiles(ScanJob a, ScanJob b, const int32_t *halt);
+__global__ void k_scan_sums(ScanJob a, ScanJob b, const int32_t *halt);
 __global__ void k_winners(Work w);
-__global__ void k_nwin(Work w);
-__global__ void k_check_capacity(DevMesh m, Work w);
 __global__ void k_record(DevMesh m, Work w);
 __global__ void k_write(DevMesh m, Work w);
 __global__ void k_finish(DevMesh m, Work w);
-__global__ void k_round_end(Work w);
 
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;

@@ -174,11 +174,16 @@ __device__ __forceinline__ void flag_mid(const Work &w, int k) {
 __device__ __forceinline__ bool bit_get(const uint32_t *bm, int i) { return (bm[i >> 5] >> (i & 31)) & 1u; }
 __device__ __forceinline__ void bit_set(uint32_t *bm, int i) { atomicOr(&bm[i >> 5], 1u << (i & 31)); }
 
-__device__ __forceinline__ int bit_rank(const uint32_t *bm, const int32_t *words_prefix, int i) {
+// Rank of bit i among the set bits of bm: the scanned popcounts of the words
+// before it (word prefix + tile prefix) and the set bits below it in its word.
+__device__ __forceinline__ int bit_rank(const uint32_t *bm, const int32_t *words_prefix, const int32_t *tiles, int i) {
   uint32_t w = bm[i >> 5];
   uint32_t below = (i & 31) ? (w & ((1u << (i & 31)) - 1u)) : 0u;
-  return words_prefix[i >> 5] + __popc(below);
+  return words_prefix[i >> 5] + tiles[(i >> 5) / kScanTileSize] + __popc(below);
 }
+
+// Exclusive prefix of the fresh-slot counts at winner r.
+__device__ __forceinline__ int fbase_at(const Work &w, int r) { return w.fbase[r] + w.tiles_f[r / kScanTileSize]; }
 
 __device__ __forceinline__ int orient_pts(double2 a, double2 b, double2 c) {
   return orient2d(a.x, a.y, b.x, b.y, c.x, c.y);
@@ -251,8 +256,10 @@ __global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
 // Incremental collection, later rounds.  A triangle that no winner rewrote
 // keeps its vertices, so its badness and split point are unchanged: the bad
 // triangles of the previous round that were not rewritten are carried over.
-__global__ void k_carry(Work w) {
-  if (w.st->halt) return;
+// (The carried list and the rewritten slots are collected by one kernel, one
+// grid-stride loop each; each loop is uniform over the grid, as the wave-wide
+// appends require.)
+__device__ void carry_part(const Work &w) {
   const int n_prev = w.st->prev_ncc, prev_serial = w.st->serial - 1;
   for (int base = blockIdx.x * blockDim.x; base < n_prev; base += gridDim.x * blockDim.x) {
     int c = base + threadIdx.x;
@@ -275,8 +282,7 @@ __global__ void k_carry(Work w) {
 
 // ... and every slot written last round (the fan records) is tested afresh;
 // an encroaching apex can only appear on a rewritten triangle.
-__global__ void k_scan_dirty(DevMesh m, Work w, double B2, int pm) {
-  if (w.st->halt) return;
+__device__ void dirty_part(const DevMesh &m, const Work &w, double B2, int pm) {
   const int n_dirty = w.st->prev_fan;
   for (int base = blockIdx.x * blockDim.x; base < n_dirty; base += gridDim.x * blockDim.x) {
     int c = base + threadIdx.x;
@@ -313,6 +319,13 @@ __device__ void pending_one(const DevMesh &m, const Work &w, int k) {
   }
 }
 
+__global__ void k_collect(DevMesh m, Work w, double B2, int pm) {
+  if (w.st->halt) return;
+  carry_part(w);
+  dirty_part(m, w, B2, pm);
+}
+
+// Separate launch: it reads side slots that k_collect rewrites.
 __global__ void k_pending(DevMesh m, Work w) {
   if (w.st->halt) return;
   const int n_prev = w.st->prev_nmk;
@@ -322,28 +335,30 @@ __global__ void k_pending(DevMesh m, Work w) {
 
 // After the collection: stop if nothing is left (Algorithm 1, the loop ends
 // when L is empty) or if the round cap is reached with work left.
+// One workgroup.  At the round cap this round's flags are dropped before
+// leaving.
 __global__ void k_gate(Work w, int max_rounds) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  __shared__ int s_h;
   DevState *st = w.st;
-  if (st->halt) return;
   DevCounters *c = w.cnt;
-  c->nmk0 = c->nmk;
-  if (c->ncc == 0 && c->nmk == 0) st->halt = kHaltDone;
-  else if (max_rounds > 0 && st->rounds >= max_rounds) st->halt = kHaltCap;
+  if (threadIdx.x == 0) {
+    s_h = 0;
+    if (!st->halt) {
+      c->nmk0 = c->nmk;
+      if (c->ncc == 0 && c->nmk == 0) s_h = kHaltDone;
+      else if (max_rounds > 0 && st->rounds >= max_rounds) s_h = kHaltCap;
+      if (s_h) st->halt = s_h;
+    }
+  }
+  __syncthreads();
+  if (s_h == kHaltCap)
+    for (int i = threadIdx.x; i < c->nmk; i += blockDim.x) w.mflag[w.mid.elem[i]] = 0u;
 }
 
 // ---------------------------------------------------------------------------
 // R3 (optional): keep the K largest keys.  Keys of both classes are placed in
 // one array; a radix select finds the K-th largest (keys are unique).
 // ---------------------------------------------------------------------------
-// Round cap reached: this round's flags are dropped before leaving.
-__global__ void k_unflag(Work w) {
-  if (w.st->halt != kHaltCap) return;
-  const int nmk = w.cnt->nmk;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nmk; c += gridDim.x * blockDim.x)
-    w.mflag[w.mid.elem[c]] = 0u;
-}
-
 __global__ void k_gather_keys(DevMesh m, Work w, int pm) {
   if (w.st->halt) return;
   const int ncc = w.cnt->ncc, nmk = w.cnt->nmk;
@@ -1033,6 +1048,7 @@ __global__ void k_dep(DevMesh m, Work w) {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
+static_assert(kScanTile == kScanTileSize, "scan tile size shared with the host and the readers");
 
 __device__ __forceinline__ int block_excl_scan(int v, int *total) {
   __shared__ int warp_sums[kScanBlock / 64];
@@ -1060,58 +1076,58 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total) {
   return r;
 }
 
-// Exclusive scan of n = *n_dev entries in three launches (tiles, tile sums,
-// add).  mode 0: in[] are counts; mode 1: in[] are 32-bit words, count =
-// popcount.  The workgroups stride over the tiles.
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t *in, int32_t *out, const int32_t *n_dev,
-                                                           int32_t *tile_sums, int mode, const int32_t *halt) {
+// Exclusive scans in two launches: per-tile scans (the workgroups stride
+// over the tiles of one or two jobs), then one workgroup per job scans the
+// tile totals in place.  A reader adds the tile prefix itself:
+// value(i) = out[i] + tiles[i / kScanTile].
+__device__ void scan_tile(const ScanJob &j, int n, int tile) {
   __shared__ int s_total;
-  if (halt && *halt) return;
-  const int n = *n_dev;
-  const int ntiles = (n + kScanTile - 1) / kScanTile;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int base = tile * kScanTile + threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int sum = 0;
-    for (int i = 0; i < kScanItems; i++) {
-      int idx = base + i;
-      int x = idx < n ? in[idx] : 0;
-      if (mode == 1) x = __popc((uint32_t)x);
-      v[i] = x;
-      sum += x;
-    }
-    int excl = block_excl_scan(sum, &s_total);
-    for (int i = 0; i < kScanItems; i++) {
-      int idx = base + i;
-      if (idx < n) out[idx] = excl;
-      excl += v[i];
-    }
-    if (threadIdx.x == 0) tile_sums[tile] = s_total;
+  int base = tile * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+  for (int i = 0; i < kScanItems; i++) {
+    int idx = base + i;
+    int x = idx < n ? j.in[idx] : 0;
+    if (j.mode == 1) x = __popc((uint32_t)x);
+    v[i] = x;
+    sum += x;
+  }
+  int excl = block_excl_scan(sum, &s_total);
+  for (int i = 0; i < kScanItems; i++) {
+    int idx = base + i;
+    if (idx < n) j.out[idx] = excl;
+    excl += v[i];
+  }
+  if (threadIdx.x == 0) j.tiles[tile] = s_total;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(ScanJob a, ScanJob b, const int32_t *halt) {
+  if (*halt) return;
+  const int na = *a.n_dev, nb = b.in ? *b.n_dev : 0;
+  const int ta = (na + kScanTile - 1) / kScanTile, tb = (nb + kScanTile - 1) / kScanTile;
+  for (int tile = blockIdx.x; tile < ta + tb; tile += gridDim.x) {
+    if (tile < ta) scan_tile(a, na, tile);
+    else scan_tile(b, nb, tile - ta);
   }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t *tile_sums, const int32_t *n_dev, int32_t *total,
-                                                          const int32_t *halt) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(ScanJob a, ScanJob b, const int32_t *halt) {
   __shared__ int s_total;
-  if (halt && *halt) return;
-  const int ntiles = (*n_dev + kScanTile - 1) / kScanTile;
+  if (*halt) return;
+  const ScanJob &j = blockIdx.x == 0 ? a : b;
+  if (!j.in) return;
+  const int ntiles = (*j.n_dev + kScanTile - 1) / kScanTile;
   int carry = 0;
   for (int start = 0; start < ntiles; start += kScanBlock) {
     int idx = start + threadIdx.x;
-    int x = idx < ntiles ? tile_sums[idx] : 0;
+    int x = idx < ntiles ? j.tiles[idx] : 0;
     int e = block_excl_scan(x, &s_total);
-    if (idx < ntiles) tile_sums[idx] = e + carry;
+    if (idx < ntiles) j.tiles[idx] = e + carry;
     carry += s_total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ void k_scan_add(int32_t *out, const int32_t *n_dev, const int32_t *tile_sums, const int32_t *halt) {
-  if (halt && *halt) return;
-  const int n = *n_dev;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x)
-    out[idx] += tile_sums[idx / kScanTile];
+  if (threadIdx.x == 0) *j.total = carry;
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,10 +1141,10 @@ __device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
   int e = S.elem[ci];
   int r, fresh;
   if (is_cc) {
-    r = nwin_mid + bit_rank(w.win_t, w.rank_t, e);
+    r = nwin_mid + bit_rank(w.win_t, w.rank_t, w.tiles_t, e);
     fresh = 2;
   } else {
-    r = bit_rank(w.win_s, w.rank_s, e);
+    r = bit_rank(w.win_s, w.rank_s, w.tiles_s, e);
     fresh = (w.sadj[2 * e] >= 0 && w.sadj[2 * e + 1] >= 0) ? 2 : 1;
   }
   w.win_ref[r] = (is_cc ? 0 : (int)0x80000000) | ci;
@@ -1136,40 +1152,20 @@ __device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
 }
 
 // Winner ranks: midpoints by subsegment id, then circumcenters by slot.
+// Also sets nwin, and a zero fresh count after the last winner, so that the
+// exclusive scan over nwin + 1 entries ends with the total.
 __global__ void k_winners(Work w) {
   if (w.st->halt) return;
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
-  int nwin_mid = w.cnt->nwin_mid;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    winner_one(w, c, ncc, nwin_mid);
-}
-
-// nwin, a zero fresh count after the last winner (so the exclusive scan over
-// nwin + 1 entries ends with the total), and the capacity check of this
-// round: if anything would overflow, the round is abandoned before the mesh
-// is written and the host grows the buffers and runs it again.
-__global__ void k_nwin(Work w) {
-  if (w.st->halt) return;
+  const int nwin_mid = w.cnt->nwin_mid;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int nwin = w.cnt->nwin_mid + w.cnt->nwin_cc;
+    int nwin = nwin_mid + w.cnt->nwin_cc;
     w.cnt->nwin = nwin;
     w.cnt->nwin1 = nwin + 1;
     w.fcount[nwin] = 0;
   }
-}
-
-__global__ void k_check_capacity(DevMesh m, Work w) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const DevState *st = w.st;
-  if (st->halt) return;
-  DevCounters *c = w.cnt;
-  int nwin = c->nwin;
-  int fresh = w.fbase[nwin];
-  c->fresh_total = fresh;
-  int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
-  bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV || (int64_t)st->nT + fresh > m.capT ||
-              (int64_t)st->nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
-  c->abort = over ? 1 : 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    winner_one(w, c, ncc, nwin_mid);
 }
 
 __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
@@ -1190,8 +1186,8 @@ __device__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
   uint64_t key = S.key[ci];
   int off = S.off[ci], len = S.len[ci];
   int skip_k = is_cc ? -1 : S.elem[ci];
-  int fresh_base = w.st->nT + w.fbase[r];
-  int b = len + (w.fbase[r + 1] - w.fbase[r]);
+  int fresh_base = w.st->nT + fbase_at(w, r);
+  int b = len + (fbase_at(w, r + 1) - fbase_at(w, r));
   w.fan_off[r] = foff;
   int j = 0;
   for (int q = 0; q < len; q++) {
@@ -1240,12 +1236,26 @@ __device__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
 __device__ __forceinline__ int fan_size(const Work &w, int r) {
   int ref = w.win_ref[r];
   CandSet S = (ref & 0x80000000) ? w.mid : w.cc;
-  return S.len[ref & 0x7fffffff] + (w.fbase[r + 1] - w.fbase[r]);
+  return S.len[ref & 0x7fffffff] + (fbase_at(w, r + 1) - fbase_at(w, r));
 }
 
+// The capacity check of the round comes first: every thread evaluates it on
+// the same counts; if anything would overflow, the round is abandoned before
+// the mesh is written and the host grows the buffers and runs it again.
 __global__ void k_record(DevMesh m, Work w) {
-  if (w.st->halt || w.cnt->abort) return;
-  int nwin = w.cnt->nwin;
+  const DevState *st = w.st;
+  if (st->halt) return;
+  DevCounters *c = w.cnt;
+  const int nwin = c->nwin;
+  const int fresh = fbase_at(w, nwin);
+  const int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
+  const bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV || (int64_t)st->nT + fresh > m.capT ||
+                    (int64_t)st->nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->fresh_total = fresh;
+    c->abort = over ? 1 : 0;
+  }
+  if (over) return;
   for (int base = blockIdx.x * blockDim.x; base < nwin; base += gridDim.x * blockDim.x) {
     int r = base + threadIdx.x;
     int b = r < nwin ? fan_size(w, r) : 0;
@@ -1260,7 +1270,7 @@ __device__ void write_one(const DevMesh &m, const Work &w, int r, int nV, int nS
   int ci = ref & 0x7fffffff;
   CandSet S = is_cc ? w.cc : w.mid;
   int len = S.len[ci];
-  int b = len + (w.fbase[r + 1] - w.fbase[r]);
+  int b = len + (fbase_at(w, r + 1) - fbase_at(w, r));
   int foff = w.fan_off[r];
   int pid = nV + r;
   double2 p = S.p[ci];
@@ -1347,28 +1357,19 @@ __device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, int 
   }
 }
 
-__global__ void k_finish(DevMesh m, Work w) {
-  if (w.st->halt) return;
-  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
-  bool aborted = w.cnt->abort != 0;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    finish_one(m, w, c, ncc, nV, aborted);
-}
-
-// End of a round: a completed round is recorded in the history, the counts
-// advance, this round's lists become the previous ones and the counters are
-// cleared for the next round.  An error, an abandoned round or a round
-// without winners halts instead (the counters stay for the host to read).
-__global__ void k_round_end(Work w) {
+// End of a round (run by the last workgroup of k_finish to arrive): a
+// completed round is recorded in the history, the counts advance, this
+// round's lists become the previous ones and the counters are cleared for
+// the next round.  An error, an abandoned round or a round without winners
+// halts instead (the counters stay for the host to read).
+__device__ void round_end(const Work &w) {
   __shared__ int s_go, s_slot;
   DevState *st = w.st;
   DevCounters *c = w.cnt;
   if (threadIdx.x == 0) {
     s_go = 0;
     s_slot = -1;
-    if (st->halt) {
-      // a halted round records nothing
-    } else if (c->err & (kErrWalk | kErrInput | kErrCavity)) st->halt = kHaltError;
+    if (c->err & (kErrWalk | kErrInput | kErrCavity)) st->halt = kHaltError;
     else if (c->abort) st->halt = kHaltAbort;
     else if (c->nwin == 0) st->halt = kHaltStall;
     else {
@@ -1397,6 +1398,26 @@ __global__ void k_round_end(Work w) {
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nw; i += blockDim.x) src[i] = 0;
+}
+
+__global__ void k_finish(DevMesh m, Work w) {
+  __shared__ int s_last;
+  if (w.st->halt) return;
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
+  bool aborted = w.cnt->abort != 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    finish_one(m, w, c, ncc, nV, aborted);
+  // every workgroup has read the counts it needs before it arrives here
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&w.st->done_blocks, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) w.st->done_blocks = 0;
+  round_end(w);
 }
 
 }  // namespace gdp
