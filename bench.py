@@ -62,6 +62,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--f1", type=int, default=0, help="Line 6 filter: one circumcenter per located triangle")
     ap.add_argument("--approx-n", type=int, default=0, help="Line 7 filter: n-triangle cavity approximation")
+    ap.add_argument("--tail-engine-max", type=int, default=0,
+                    help="candidates per round below which rounds run inside one workgroup (0 default, -1 never)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration) and exit")
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
@@ -69,7 +71,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the refinement loop of one PSLG runs on a "
-              "single device, see DESIGN.md for how it would shard.", file=sys.stderr)
+              "single device, it would shard by instance or by spatial blocks.", file=sys.stderr)
         return 2
 
     import torch
@@ -97,7 +99,7 @@ def main() -> int:
     init = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg)
     log(f"initial CDT (host) + upload: {init.info()['n_triangles']:,} triangles in {time.perf_counter() - t:.1f} s")
     work = init.clone()
-    prm = gdp2d.make_params(prefilter_f1=args.f1, cavity_approx_n=args.approx_n)
+    prm = gdp2d.make_params(prefilter_f1=args.f1, cavity_approx_n=args.approx_n, tail_engine_max=args.tail_engine_max)
     for i in range(args.warmup):
         work.assign_from(init)
         gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)

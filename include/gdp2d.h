@@ -95,7 +95,10 @@ typedef struct {
   int32_t rounds_per_sync;  /* rounds queued on the stream between two host
                                synchronisations (1..64; 0 = automatic: one while
                                rounds are large, more as they shrink) */
-  int32_t reserved[3];
+  int32_t tail_engine_max;  /* rounds whose previous round had at most this many
+                               candidates run whole inside one workgroup (0 =
+                               default 1024; negative = never) */
+  int32_t reserved[2];
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */

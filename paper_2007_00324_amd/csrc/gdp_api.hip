@@ -31,6 +31,9 @@ struct gdp_mesh {
     int64_t est = 0;
   } graph[2];
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  EngDesc *d_eng = nullptr;          // descriptor of this mesh for the single-workgroup engine
+  EngDesc *h_eng = nullptr;          // pinned
+  int32_t *d_head = nullptr;         // the engine's queue head
   DevCounters *d_cnt = nullptr;
   DevCounters *h_cnt = nullptr;  // pinned
   uint64_t *mark = nullptr;
@@ -256,6 +259,7 @@ gdp_status grow_cand(gdp_mesh *M) {
 }
 
 constexpr int kHistCap = 64;  // rounds queued between two host synchronisations, at most
+constexpr int64_t kEngineDefaultMax = 1024;  // candidates per round run by the single-workgroup engine
 
 // Workspace pointers of a round; the two list buffers swap roles with the
 // parity of the round's serial.
@@ -357,6 +361,9 @@ void free_mesh_arrays(gdp_mesh *M) {
   if (M->h_hist) (void)hipHostFree(M->h_hist);
   for (auto &g : M->graph)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (M->d_eng) (void)hipFree(M->d_eng);
+  if (M->d_head) (void)hipFree(M->d_head);
+  if (M->h_eng) (void)hipHostFree(M->h_eng);
   if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
 }
 
@@ -702,15 +709,48 @@ gdp_status launch_pairs(gdp_mesh *M, double B2, const gdp_params *P, int p, int 
   return GDP_OK;
 }
 
+// Queues up to `rounds` rounds of the single-workgroup engine.
+gdp_status launch_engine(gdp_mesh *M, double B2, const gdp_params *P, int rounds) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  if (!M->d_eng) {
+    HIPCHECK(dalloc(&M->d_eng, 1));
+    HIPCHECK(dalloc(&M->d_head, 1));
+    HIPCHECK(hipHostMalloc((void **)&M->h_eng, sizeof(EngDesc)));
+  }
+  // the previous launch has finished (the host synchronised since), so the
+  // pinned descriptor can be rewritten
+  EngDesc &d = *M->h_eng;
+  memset(&d, 0, sizeof d);
+  d.m = M->m;
+  d.w[0] = make_work(M, P->priority_mode, 0);
+  d.w[1] = make_work(M, P->priority_mode, 1);
+  d.B2 = B2;
+  d.pm = P->priority_mode;
+  d.K = P->cand_cap_K;
+  d.f1 = P->prefilter_f1;
+  d.approx_n = P->cavity_approx_n;
+  d.max_rounds = P->max_rounds;
+  HIPCHECK(hipMemcpyAsync(M->d_eng, &d, sizeof d, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemsetAsync(M->d_head, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_engine, dim3(1), dim3(kEngBlock), 0, s, M->d_eng, 1, M->d_head, rounds);
+  HIPCHECK(hipGetLastError());
+  return GDP_OK;
+}
+
 // Queues up to this many rounds before the next host synchronisation.
 // Groups of two or more rounds are queued as graph replays, in pairs.
-int rounds_for(const gdp_params *P, int64_t last_cand) {
+int rounds_for(const gdp_params *P, int64_t last_cand, bool engine) {
   if (P->profile_kernels) return 1;
+  if (engine) return kHistCap;
   int r;
   if (P->rounds_per_sync > 0) r = std::min(P->rounds_per_sync, kHistCap);
   else if (last_cand > 65536) r = 1;
   else if (last_cand > 8192) r = 4;
   else r = 16;
+  // close to the engine's threshold: short groups, so that it takes over soon
+  const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
+  if (P->rounds_per_sync == 0 && eng_max > 0 && last_cand <= 4 * eng_max) r = std::min(r, 2);
   return r >= 2 ? r & ~1 : r;
 }
 
@@ -747,12 +787,17 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   int64_t prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
   int aborts = 0;
   for (;;) {
-    const int R = full ? 1 : rounds_for(P, last_cand);
+    // small rounds run in the single-workgroup engine
+    const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
+    const bool engine = !full && !M->prof && eng_max > 0 && last_cand <= eng_max;
+    const int R = full ? 1 : rounds_for(P, last_cand, engine);
     gdp_status st;
-    if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, R))) return st;
+    if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, engine ? 4 : R))) return st;
     const int serial0 = M->serial;
     const size_t prof0 = M->prof_pending.size();
-    if (R >= 2 && !full && !M->prof) {
+    if (engine) {
+      if ((st = launch_engine(M, B2, P, R))) return st;
+    } else if (R >= 2 && !full && !M->prof) {
       // small rounds: replays of a captured pair of rounds
       if ((st = launch_pairs(M, B2, P, serial0 & 1, R / 2, last_cand))) return st;
     } else {

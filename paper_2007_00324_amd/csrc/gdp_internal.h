@@ -80,7 +80,8 @@ struct DevState {
   int32_t halt;          // kHalt*: nonzero makes every later round kernel return at once
   int32_t nhist;         // rounds recorded in the history since the host last read it
   int32_t done_blocks;   // arrival counter of k_finish's workgroups
-  int32_t pad[3];
+  int32_t full;          // the next round collects over the whole mesh (single-workgroup engine)
+  int32_t pad[2];
 };
 
 constexpr int kHaltDone = 1;   // nothing left to refine

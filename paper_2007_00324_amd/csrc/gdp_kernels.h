@@ -84,6 +84,16 @@ __global__ void k_record(DevMesh m, Work w);
 __global__ void k_write(DevMesh m, Work w);
 __global__ void k_finish(DevMesh m, Work w);
 
+// One mesh of the single-workgroup engine.
+struct EngDesc {
+  DevMesh m;
+  Work w[2];  // workspaces of the rounds with an even / odd serial
+  double B2;
+  int32_t pm, K, f1, approx_n, max_rounds, pad;
+};
+constexpr int kEngBlock = 1024;
+__global__ void k_engine(const EngDesc *descs, int n_mesh, int32_t *head, int round_limit);
+
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;
 constexpr int kScanTileSize = 256 * 8;

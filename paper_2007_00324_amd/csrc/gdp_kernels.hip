@@ -205,6 +205,18 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int v) {
   return false;
 }
 
+// Work distribution of a phase: item = base + threadIdx.x for base = base0,
+// base0 + stride, ...  A grid kernel spreads the items over all workgroups;
+// the single-workgroup engine takes them all.  The loops are uniform over a
+// workgroup, as the wave-wide operations require.
+struct Lanes {
+  int base0, stride;
+};
+__device__ __forceinline__ Lanes grid_lanes() { return {(int)(blockIdx.x * blockDim.x), (int)(gridDim.x * blockDim.x)}; }
+__device__ __forceinline__ Lanes block_lanes() { return {0, (int)blockDim.x}; }
+// the first lane of the whole distribution (single writes)
+__device__ __forceinline__ bool first_lane(const Lanes &L) { return L.base0 == 0 && threadIdx.x == 0; }
+
 // ---------------------------------------------------------------------------
 // R1: collect encroached subsegments and bad triangles (Line 3)
 // ---------------------------------------------------------------------------
@@ -240,10 +252,9 @@ __device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const 
 }
 
 // Full collection over every triangle and subsegment (first round of a call).
-__global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void scan_part(const DevMesh &m, const Work &w, double B2, int pm, const Lanes &L) {
   const int nT = w.st->nT, nS = w.st->nS, n = max(nT, nS);
-  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < n; base += L.stride) {
     int i = base + threadIdx.x;
     bool bad = false;
     SplitPt r;
@@ -253,15 +264,20 @@ __global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
   }
 }
 
+__global__ void k_scan(DevMesh m, Work w, double B2, int pm) {
+  if (w.st->halt) return;
+  scan_part(m, w, B2, pm, grid_lanes());
+}
+
 // Incremental collection, later rounds.  A triangle that no winner rewrote
 // keeps its vertices, so its badness and split point are unchanged: the bad
 // triangles of the previous round that were not rewritten are carried over.
 // (The carried list and the rewritten slots are collected by one kernel, one
 // grid-stride loop each; each loop is uniform over the grid, as the wave-wide
 // appends require.)
-__device__ void carry_part(const Work &w) {
+__device__ __forceinline__ void carry_part(const Work &w, const Lanes &L) {
   const int n_prev = w.st->prev_ncc, prev_serial = w.st->serial - 1;
-  for (int base = blockIdx.x * blockDim.x; base < n_prev; base += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < n_prev; base += L.stride) {
     int c = base + threadIdx.x;
     bool keep = false;
     int t = 0;
@@ -282,9 +298,9 @@ __device__ void carry_part(const Work &w) {
 
 // ... and every slot written last round (the fan records) is tested afresh;
 // an encroaching apex can only appear on a rewritten triangle.
-__device__ void dirty_part(const DevMesh &m, const Work &w, double B2, int pm) {
+__device__ __forceinline__ void dirty_part(const DevMesh &m, const Work &w, double B2, int pm, const Lanes &L) {
   const int n_dirty = w.st->prev_fan;
-  for (int base = blockIdx.x * blockDim.x; base < n_dirty; base += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < n_dirty; base += L.stride) {
     int c = base + threadIdx.x;
     bool bad = false;
     SplitPt r;
@@ -301,7 +317,7 @@ __device__ void dirty_part(const DevMesh &m, const Work &w, double B2, int pm) {
 // apex still inside the diametric circle (a flagged subsegment the candidate
 // cap left out is not pending, and its sides may be unchanged).  The side
 // slots are current: rewritten sides were re-scanned just before.
-__device__ void pending_one(const DevMesh &m, const Work &w, int k) {
+__device__ __forceinline__ void pending_one(const DevMesh &m, const Work &w, int k) {
   if (m.spend[k]) {
     flag_mid(w, k);
     return;
@@ -319,54 +335,68 @@ __device__ void pending_one(const DevMesh &m, const Work &w, int k) {
   }
 }
 
+__device__ __forceinline__ void pending_part(const DevMesh &m, const Work &w, const Lanes &L) {
+  const int n_prev = w.st->prev_nmk;
+  for (int base = L.base0; base < n_prev; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < n_prev) pending_one(m, w, w.prev_mid_elem[c]);
+  }
+}
+
 __global__ void k_collect(DevMesh m, Work w, double B2, int pm) {
   if (w.st->halt) return;
-  carry_part(w);
-  dirty_part(m, w, B2, pm);
+  carry_part(w, grid_lanes());
+  dirty_part(m, w, B2, pm, grid_lanes());
 }
 
 // Separate launch: it reads side slots that k_collect rewrites.
 __global__ void k_pending(DevMesh m, Work w) {
   if (w.st->halt) return;
-  const int n_prev = w.st->prev_nmk;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_prev; c += gridDim.x * blockDim.x)
-    pending_one(m, w, w.prev_mid_elem[c]);
+  pending_part(m, w, grid_lanes());
 }
 
 // After the collection: stop if nothing is left (Algorithm 1, the loop ends
 // when L is empty) or if the round cap is reached with work left.
 // One workgroup.  At the round cap this round's flags are dropped before
-// leaving.
-__global__ void k_gate(Work w, int max_rounds) {
+// leaving.  Returns the halt code it set (0: the round goes on).
+__device__ __forceinline__ int gate_part(const Work &w, int max_rounds) {
   __shared__ int s_h;
   DevState *st = w.st;
   DevCounters *c = w.cnt;
   if (threadIdx.x == 0) {
     s_h = 0;
     if (!st->halt) {
-      c->nmk0 = c->nmk;
-      if (c->ncc == 0 && c->nmk == 0) s_h = kHaltDone;
+      const int ncc = c->ncc, nmk = c->nmk;
+      c->nmk0 = nmk;
+      if (ncc == 0 && nmk == 0) s_h = kHaltDone;
       else if (max_rounds > 0 && st->rounds >= max_rounds) s_h = kHaltCap;
       if (s_h) st->halt = s_h;
     }
   }
   __syncthreads();
-  if (s_h == kHaltCap)
-    for (int i = threadIdx.x; i < c->nmk; i += blockDim.x) w.mflag[w.mid.elem[i]] = 0u;
+  const int h = s_h;
+  if (h == kHaltCap) {
+    const int nmk = c->nmk;
+    for (int i = threadIdx.x; i < nmk; i += blockDim.x) w.mflag[w.mid.elem[i]] = 0u;
+  }
+  return h;
 }
+
+__global__ void k_gate(Work w, int max_rounds) { (void)gate_part(w, max_rounds); }
 
 // ---------------------------------------------------------------------------
 // R3 (optional): keep the K largest keys.  Keys of both classes are placed in
 // one array; a radix select finds the K-th largest (keys are unique).
 // ---------------------------------------------------------------------------
-__global__ void k_gather_keys(DevMesh m, Work w, int pm) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void gather_part(const DevMesh &m, const Work &w, int pm, const Lanes &L) {
   const int ncc = w.cnt->ncc, nmk = w.cnt->nmk;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (first_lane(L)) {
     w.sel[0] = 0;  // prefix
     w.sel[1] = 0;  // prefix mask
   }
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc + nmk; c += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < ncc + nmk; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c >= ncc + nmk) break;
     if (c < ncc) {
       w.keys[c] = w.cc.key[c];
     } else {
@@ -377,6 +407,11 @@ __global__ void k_gather_keys(DevMesh m, Work w, int pm) {
       w.keys[c] = r.key;
     }
   }
+}
+
+__global__ void k_gather_keys(DevMesh m, Work w, int pm) {
+  if (w.st->halt) return;
+  gather_part(m, w, pm, grid_lanes());
 }
 
 // Histogram of 8-bit digit `shift` over keys whose higher digits equal the
@@ -422,11 +457,12 @@ __global__ void k_radix_pick(Work w, int shift, int K) {
   for (int i = threadIdx.x; i < 256; i += blockDim.x) w.rhist[i] = 0;
 }
 
-__global__ void k_apply_cap(Work w) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void apply_part(const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, nmk = w.cnt->nmk;
   const uint64_t th = w.sel[0];
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc + nmk; c += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < ncc + nmk; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c >= ncc + nmk) break;
     if (c < ncc) {
       if (w.cc.key[c] < th) w.cc.state[c] = kStDone | kStSkip;
       else atomicAdd(&w.cnt->n_kept_cc, 1);
@@ -442,11 +478,16 @@ __global__ void k_apply_cap(Work w) {
   }
 }
 
+__global__ void k_apply_cap(Work w) {
+  if (w.st->halt) return;
+  apply_part(w, grid_lanes());
+}
+
 // ---------------------------------------------------------------------------
 // R4: locate circumcenters by a visibility walk (Line 6); a walk stopped only
 // by subsegments turns into the midpoint candidate of the first one.
 // ---------------------------------------------------------------------------
-__device__ void locate_one(const DevMesh &m, const Work &w, int c, int nS) {
+__device__ __forceinline__ void locate_one(const DevMesh &m, const Work &w, int c, int nS) {
   if (w.cc.state[c] & kStSkip) return;
   int cur = w.cc.elem[c];
   double2 p = w.cc.p[c];
@@ -495,10 +536,17 @@ __device__ void locate_one(const DevMesh &m, const Work &w, int c, int nS) {
   }
 }
 
+__device__ __forceinline__ void locate_part(const DevMesh &m, const Work &w, const Lanes &L) {
+  const int ncc = w.cnt->ncc, nS = w.st->nS;
+  for (int base = L.base0; base < ncc; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < ncc) locate_one(m, w, c, nS);
+  }
+}
+
 __global__ void k_locate(DevMesh m, Work w) {
   if (w.st->halt) return;
-  const int ncc = w.cnt->ncc, nS = w.st->nS;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc; c += gridDim.x * blockDim.x) locate_one(m, w, c, nS);
+  locate_part(m, w, grid_lanes());
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +562,8 @@ __global__ void k_locate(DevMesh m, Work w) {
 constexpr int kApproxMax = 16;
 constexpr int kPreBlock = 128;
 
-__device__ void prefilter_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int c, int mode, int n) {
+__device__ __forceinline__ void prefilter_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int tid, int c, int mode,
+                              int n) {
   int st = w.cc.state[c];
   if (!(st & kStFound)) return;
   int loc = w.cc.loc[c];
@@ -538,7 +587,7 @@ __device__ void prefilter_one(const DevMesh &m, const Work &w, int32_t *lds, int
   lds[tid] = loc;
   len = 1;
   for (int h = 0; h < len && len < n; h++) {
-    int t = lds[h * kPreBlock + tid];
+    int t = lds[h * ls + tid];
     int4 tri = m.tv[t];
     int4 nb = m.tn[t];
     for (int e = 0; e < 3 && len < n; e++) {
@@ -547,32 +596,39 @@ __device__ void prefilter_one(const DevMesh &m, const Work &w, int32_t *lds, int
       if (o < 0) continue;
       bool in = false;
       for (int q = 0; q < len; q++)
-        if (lds[q * kPreBlock + tid] == o) { in = true; break; }
+        if (lds[q * ls + tid] == o) { in = true; break; }
       if (in) continue;
-      if (incircle_tri(m, m.tv[o], p) > 0) lds[(len++) * kPreBlock + tid] = o;
+      if (incircle_tri(m, m.tv[o], p) > 0) lds[(len++) * ls + tid] = o;
     }
   }
   if (mode == 3) {
     for (int j = 0; j < len; j++)
-      atomicMax((unsigned long long *)&w.mark[lds[j * kPreBlock + tid]], (unsigned long long)key);
+      atomicMax((unsigned long long *)&w.mark[lds[j * ls + tid]], (unsigned long long)key);
   } else if (mode == 4) {
     bool own = true;
-    for (int j = 0; j < len && own; j++) own = w.mark[lds[j * kPreBlock + tid]] == key;
+    for (int j = 0; j < len && own; j++) own = w.mark[lds[j * ls + tid]] == key;
     if (!own) {
       w.cc.state[c] = st | kStDone;
       atomicAdd(&w.cnt->n_f2_drop, 1);
     }
   } else {
-    for (int j = 0; j < len; j++) w.mark[lds[j * kPreBlock + tid]] = 0ull;
+    for (int j = 0; j < len; j++) w.mark[lds[j * ls + tid]] = 0ull;
+  }
+}
+
+// lds: kApproxMax slices of blockDim.x entries
+__device__ __forceinline__ void prefilter_part(const DevMesh &m, const Work &w, int mode, int n, int32_t *lds, const Lanes &L) {
+  const int ncc = w.cnt->ncc;
+  for (int base = L.base0; base < ncc; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < ncc) prefilter_one(m, w, lds, blockDim.x, threadIdx.x, c, mode, n);
   }
 }
 
 __global__ __launch_bounds__(kPreBlock) void k_prefilter(DevMesh m, Work w, int mode, int n) {
   __shared__ int32_t lds[kApproxMax * kPreBlock];
   if (w.st->halt) return;
-  const int ncc = w.cnt->ncc;
-  for (int c = blockIdx.x * kPreBlock + threadIdx.x; c < ncc; c += gridDim.x * kPreBlock)
-    prefilter_one(m, w, lds, threadIdx.x, c, mode, n);
+  prefilter_part(m, w, mode, n, lds, grid_lanes());
 }
 
 // ---------------------------------------------------------------------------
@@ -629,16 +685,16 @@ constexpr int kCavBlock = 128;
 
 // Grows the cavity of p from the seeds into lds[j * kCavBlock + tid].
 // Returns the size, or -1 if it exceeds kCap.
-__device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *seeds, int nseeds,
+__device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls, int tid, const int *seeds, int nseeds,
                           double2 p) {
   int len = 0;
   for (int s = 0; s < nseeds; s++) {
     bool dup = false;
-    for (int q = 0; q < len; q++) dup |= lds[q * kCavBlock + tid] == seeds[s];
-    if (!dup) lds[(len++) * kCavBlock + tid] = seeds[s];
+    for (int q = 0; q < len; q++) dup |= lds[q * ls + tid] == seeds[s];
+    if (!dup) lds[(len++) * ls + tid] = seeds[s];
   }
   for (int h = 0; h < len; h++) {
-    int t = lds[h * kCavBlock + tid];
+    int t = lds[h * ls + tid];
     int4 tri = m.tv[t];
     int4 nb = m.tn[t];
     for (int e = 0; e < 3; e++) {
@@ -647,23 +703,23 @@ __device__ int grow_local(const DevMesh &m, int32_t *lds, int tid, const int *se
       if (o < 0) continue;
       bool in = false;
       for (int q = 0; q < len; q++)
-        if (lds[q * kCavBlock + tid] == o) { in = true; break; }
+        if (lds[q * ls + tid] == o) { in = true; break; }
       if (in) continue;
       if (incircle_tri(m, m.tv[o], p) > 0) {
         if (len == kCap) return -1;
-        lds[(len++) * kCavBlock + tid] = o;
+        lds[(len++) * ls + tid] = o;
       }
     }
   }
   // insertion sort (ascending slots)
   for (int a = 1; a < len; a++) {
-    int x = lds[a * kCavBlock + tid];
+    int x = lds[a * ls + tid];
     int b = a - 1;
-    while (b >= 0 && lds[b * kCavBlock + tid] > x) {
-      lds[(b + 1) * kCavBlock + tid] = lds[b * kCavBlock + tid];
+    while (b >= 0 && lds[b * ls + tid] > x) {
+      lds[(b + 1) * ls + tid] = lds[b * ls + tid];
       b--;
     }
-    lds[(b + 1) * kCavBlock + tid] = x;
+    lds[(b + 1) * ls + tid] = x;
   }
   return len;
 }
@@ -677,7 +733,7 @@ struct CavRes {
   int enc_reject, fan_invalid, unsplittable, mid_cand;
 };
 
-__device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int tid, int ci, int is_cc) {
+__device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int tid, int ci, int is_cc) {
   CavRes res{0, 0, 0, 0, 0, 0, 0};
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
@@ -709,7 +765,7 @@ __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int 
     expect = nseeds == 2 ? 2 : 1;
     S.state[ci] = st | kStFound;
   }
-  int len = grow_local(m, lds, tid, seeds, nseeds, p);
+  int len = grow_local(m, lds, ls, tid, seeds, nseeds, p);
   if (len < 0) {
     S.state[ci] = st | kStBig | kStFound;
     int q = atomicAdd(&w.cnt->nbig, 1);
@@ -717,7 +773,7 @@ __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int 
     else atomicOr(&w.cnt->err, kErrCavity);
     return res;
   }
-  auto cav = [&](int j) { return lds[j * kCavBlock + tid]; };
+  auto cav = [&](int j) { return lds[j * ls + tid]; };
   CavCheck ck = check_cavity(m, w, cav, len, skip_k, is_cc != 0, p);
   res.len = len;
   res.bnd = ck.nbnd;
@@ -733,21 +789,19 @@ __device__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int 
   return res;
 }
 
-// Per-thread cavities of one class.  The midpoint list is final when this
-// runs for midpoints (they are flagged only by the scan, the walk and the
-// circumcenter cavities), so its length is read from device memory.  The
-// loop is uniform over the workgroup so that pool space and statistics are
-// handled once per wave.
-__global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int is_cc) {
-  __shared__ int32_t lds[kCap * kCavBlock];
-  if (w.st->halt) return;
-  int tid = threadIdx.x;
+// Per-thread cavities of one class (lds: kCap slices of blockDim.x entries).
+// The midpoint list is final when this runs for midpoints (they are flagged
+// only by the scan, the walk and the circumcenter cavities), so its length
+// is read from device memory.  The loop is uniform over the workgroup so
+// that pool space and statistics are handled once per wave.
+__device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int is_cc, int32_t *lds, const Lanes &L) {
+  const int tid = threadIdx.x, ls = blockDim.x;
   const int n = is_cc ? w.cnt->ncc : w.cnt->nmk;
   CandSet S = is_cc ? w.cc : w.mid;
-  for (int base = blockIdx.x * kCavBlock; base < n; base += gridDim.x * kCavBlock) {
+  for (int base = L.base0; base < n; base += L.stride) {
     int ci = base + tid;
     CavRes r{0, 0, 0, 0, 0, 0, 0};
-    if (ci < n) r = cavity_one(m, w, lds, tid, ci, is_cc);
+    if (ci < n) r = cavity_one(m, w, lds, ls, tid, ci, is_cc);
     int off = wave_alloc(&w.cnt->pool_used, r.alive ? r.len : 0);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
     if (r.alive) {
@@ -758,7 +812,7 @@ __global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int is_
         // validity depends on this cavity alone, and atomicMax is order free.
         uint64_t key = S.key[ci];
         for (int j = 0; j < r.len; j++) {
-          int t = lds[j * kCavBlock + tid];
+          int t = lds[j * ls + tid];
           w.pool[off + j] = t;
           atomicMax((unsigned long long *)&w.mark[t], (unsigned long long)key);
         }
@@ -782,6 +836,12 @@ __global__ __launch_bounds__(kCavBlock) void k_cavity(DevMesh m, Work w, int is_
     wave_add(&w.cnt->n_unsplittable, r.unsplittable);
     wave_add(&w.cnt->n_mid_cand, r.mid_cand);
   }
+}
+
+__global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w, int is_cc) {
+  __shared__ int32_t lds[kCap * kCavBlock];
+  if (w.st->halt) return;
+  cavity_part(m, w, is_cc, lds, grid_lanes());
 }
 
 // Cooperative growth of one large cavity per workgroup (the tuple-parallel
@@ -810,7 +870,7 @@ struct BigShared {
 };
 
 // Grows queue entry b (uniform over the workgroup).
-__device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
+__device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
   int32_t *cav = sh.cav;
   int32_t *hs = sh.hs;
   int &s_n = sh.s_n, &s_head = sh.s_head, &s_ovf = sh.s_ovf, &s_nbnd = sh.s_nbnd, &s_fanbad = sh.s_fanbad,
@@ -823,7 +883,7 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
   if (!(S.state[ci] & kStBig) || (S.state[ci] & kStDone)) return;
   double2 p = S.p[ci];
   int skip_k = is_cc ? -1 : S.elem[ci];
-  for (int i = tid; i < kHash; i += kBigBlock) hs[i] = -1;
+  for (int i = tid; i < kHash; i += blockDim.x) hs[i] = -1;
   __syncthreads();
   int expect = 2;
   if (tid == 0) {
@@ -846,7 +906,7 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
     __syncthreads();
     if (lo >= hi || ovf) break;
     if (tid == 0) s_head = hi;
-    for (int idx = lo + tid; idx < hi; idx += kBigBlock) {
+    for (int idx = lo + tid; idx < hi; idx += blockDim.x) {
       int t = cav[idx];
       int4 tri = m.tv[t];
       int4 nb = m.tn[t];
@@ -874,11 +934,11 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
   int len = s_n;
   int P = 1;
   while (P < len) P <<= 1;
-  for (int i = len + tid; i < P; i += kBigBlock) cav[i] = 0x7fffffff;
+  for (int i = len + tid; i < P; i += blockDim.x) cav[i] = 0x7fffffff;
   for (int size = 2; size <= P; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       __syncthreads();
-      for (int i = tid; i < P; i += kBigBlock) {
+      for (int i = tid; i < P; i += blockDim.x) {
         int j = i ^ stride;
         if (j > i) {
           bool up = (i & size) == 0;
@@ -889,7 +949,7 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
     }
   __syncthreads();
   // boundary checks, in parallel over cavity triangles
-  for (int j = tid; j < len; j += kBigBlock) {
+  for (int j = tid; j < len; j += blockDim.x) {
     int t = cav[j];
     int4 tri = m.tv[t];
     int4 nb = m.tn[t];
@@ -931,7 +991,7 @@ __device__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
   int off = s_off;
   if (off >= 0) {
     uint64_t key = S.key[ci];
-    for (int j = tid; j < len; j += kBigBlock) {
+    for (int j = tid; j < len; j += blockDim.x) {
       w.pool[off + j] = cav[j];
       atomicMax((unsigned long long *)&w.mark[cav[j]], (unsigned long long)key);
     }
@@ -966,7 +1026,7 @@ __device__ __forceinline__ bool cand_at(const Work &w, int c, int ncc, CandSet &
   S = w.mid; ci = c - ncc; is_cc = 0; return true;
 }
 
-__device__ void own_one(const Work &w, int c, int ncc, int &lost) {
+__device__ __forceinline__ void own_one(const Work &w, int c, int ncc, int &lost) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -984,18 +1044,22 @@ __device__ void own_one(const Work &w, int c, int ncc, int &lost) {
   }
 }
 
-__global__ void k_own(Work w) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void own_part(const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
-  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < n; base += L.stride) {
     int c = base + threadIdx.x, lost = 0;
     if (c < n) own_one(w, c, ncc, lost);
     wave_add(&w.cnt->n_lost_mark, lost);
   }
 }
 
+__global__ void k_own(Work w) {
+  if (w.st->halt) return;
+  own_part(w, grid_lanes());
+}
+
 // R9: Delaunay dependency across a shared non-subsegment cavity edge.
-__device__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
+__device__ __forceinline__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1036,10 +1100,17 @@ __device__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
   }
 }
 
+__device__ __forceinline__ void dep_part(const DevMesh &m, const Work &w, const Lanes &L) {
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  for (int base = L.base0; base < n; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < n) dep_one(m, w, c, ncc);
+  }
+}
+
 __global__ void k_dep(DevMesh m, Work w) {
   if (w.st->halt) return;
-  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) dep_one(m, w, c, ncc);
+  dep_part(m, w, grid_lanes());
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,8 +1121,9 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 static_assert(kScanTile == kScanTileSize, "scan tile size shared with the host and the readers");
 
+// Exclusive scan over a workgroup of up to 1024 threads.
 __device__ __forceinline__ int block_excl_scan(int v, int *total) {
-  __shared__ int warp_sums[kScanBlock / 64];
+  __shared__ int warp_sums[16];
   int lane = __lane_id(), wid = threadIdx.x / 64;
   // inclusive wave scan
   int x = v;
@@ -1063,7 +1135,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int run = 0;
-    for (int i = 0; i < kScanBlock / 64; i++) {
+    for (int i = 0; i < (int)(blockDim.x / 64); i++) {
       int s = warp_sums[i];
       warp_sums[i] = run;
       run += s;
@@ -1133,7 +1205,13 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(ScanJob a, ScanJob b, 
 // ---------------------------------------------------------------------------
 // R10: insertion
 // ---------------------------------------------------------------------------
-__device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
+// Fresh slots of a winner: two, or one for a midpoint on a hull subsegment.
+__device__ __forceinline__ int fresh_of(const Work &w, int is_cc, int e) {
+  if (is_cc) return 2;
+  return (w.sadj[2 * e] >= 0 && w.sadj[2 * e + 1] >= 0) ? 2 : 1;
+}
+
+__device__ __forceinline__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1154,18 +1232,24 @@ __device__ void winner_one(const Work &w, int c, int ncc, int nwin_mid) {
 // Winner ranks: midpoints by subsegment id, then circumcenters by slot.
 // Also sets nwin, and a zero fresh count after the last winner, so that the
 // exclusive scan over nwin + 1 entries ends with the total.
-__global__ void k_winners(Work w) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void winners_part(const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
   const int nwin_mid = w.cnt->nwin_mid;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (first_lane(L)) {
     int nwin = nwin_mid + w.cnt->nwin_cc;
     w.cnt->nwin = nwin;
     w.cnt->nwin1 = nwin + 1;
     w.fcount[nwin] = 0;
   }
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    winner_one(w, c, ncc, nwin_mid);
+  for (int base = L.base0; base < n; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < n) winner_one(w, c, ncc, nwin_mid);
+  }
+}
+
+__global__ void k_winners(Work w) {
+  if (w.st->halt) return;
+  winners_part(w, grid_lanes());
 }
 
 __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
@@ -1178,7 +1262,7 @@ __device__ __forceinline__ bool owner_wins(const Work &w, uint64_t mo) {
 // Fan records of each winner: boundary edges in canonical order (cavity
 // slots ascending, edge index 0..2; the split subsegment is skipped).  The
 // j-th fan triangle takes the j-th cavity slot, then fresh slots.
-__device__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
+__device__ __forceinline__ void record_one(const DevMesh &m, const Work &w, int r, int foff) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1242,21 +1326,21 @@ __device__ __forceinline__ int fan_size(const Work &w, int r) {
 // The capacity check of the round comes first: every thread evaluates it on
 // the same counts; if anything would overflow, the round is abandoned before
 // the mesh is written and the host grows the buffers and runs it again.
-__global__ void k_record(DevMesh m, Work w) {
+__device__ __forceinline__ void record_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const DevState *st = w.st;
-  if (st->halt) return;
   DevCounters *c = w.cnt;
   const int nwin = c->nwin;
   const int fresh = fbase_at(w, nwin);
   const int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
-  const bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV || (int64_t)st->nT + fresh > m.capT ||
-                    (int64_t)st->nS + c->nwin_mid > m.capS || need_fan > w.fan_cap || nwin + 1 > w.win_cap;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV ||
+                    (int64_t)st->nT + fresh > m.capT || (int64_t)st->nS + c->nwin_mid > m.capS ||
+                    need_fan > w.fan_cap || nwin + 1 > w.win_cap;
+  if (first_lane(L)) {
     c->fresh_total = fresh;
     c->abort = over ? 1 : 0;
   }
   if (over) return;
-  for (int base = blockIdx.x * blockDim.x; base < nwin; base += gridDim.x * blockDim.x) {
+  for (int base = L.base0; base < nwin; base += L.stride) {
     int r = base + threadIdx.x;
     int b = r < nwin ? fan_size(w, r) : 0;
     int foff = wave_alloc(&w.cnt->fan_used, b);
@@ -1264,7 +1348,12 @@ __global__ void k_record(DevMesh m, Work w) {
   }
 }
 
-__device__ void write_one(const DevMesh &m, const Work &w, int r, int nV, int nS, int serial) {
+__global__ void k_record(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  record_part(m, w, grid_lanes());
+}
+
+__device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r, int nV, int nS, int serial) {
   int ref = w.win_ref[r];
   int is_cc = (ref & 0x80000000) ? 0 : 1;
   int ci = ref & 0x7fffffff;
@@ -1322,17 +1411,24 @@ __device__ void write_one(const DevMesh &m, const Work &w, int r, int nV, int nS
   }
 }
 
-__global__ void k_write(DevMesh m, Work w) {
-  if (w.st->halt || w.cnt->abort) return;
+__device__ __forceinline__ void write_part(const DevMesh &m, const Work &w, const Lanes &L) {
+  if (w.cnt->abort) return;
   const int nwin = w.cnt->nwin, nV = w.st->nV, nS = w.st->nS, serial = w.st->serial;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nwin; r += gridDim.x * blockDim.x)
-    write_one(m, w, r, nV, nS, serial);
+  for (int base = L.base0; base < nwin; base += L.stride) {
+    int r = base + threadIdx.x;
+    if (r < nwin) write_one(m, w, r, nV, nS, serial);
+  }
+}
+
+__global__ void k_write(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  write_part(m, w, grid_lanes());
 }
 
 // R11: clear marks and bitmap bits of every candidate; pending flags.  A
 // subsegment is split iff its second endpoint is now a new vertex.  After an
 // abandoned round nothing was split and the flags are only released.
-__device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, int nV, bool aborted) {
+__device__ __forceinline__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, int nV, bool aborted) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1357,35 +1453,40 @@ __device__ void finish_one(const DevMesh &m, const Work &w, int c, int ncc, int 
   }
 }
 
-// End of a round (run by the last workgroup of k_finish to arrive): a
+// End of a round (run by the last workgroup of k_finish to arrive, or by the
+// single-workgroup engine): a
 // completed round is recorded in the history, the counts advance, this
 // round's lists become the previous ones and the counters are cleared for
 // the next round.  An error, an abandoned round or a round without winners
 // halts instead (the counters stay for the host to read).
-__device__ void round_end(const Work &w) {
+__device__ __forceinline__ void round_end(const Work &w) {
   __shared__ int s_go, s_slot;
   DevState *st = w.st;
   DevCounters *c = w.cnt;
   if (threadIdx.x == 0) {
     s_go = 0;
     s_slot = -1;
-    if (c->err & (kErrWalk | kErrInput | kErrCavity)) st->halt = kHaltError;
+    const int err = c->err, nwin = c->nwin;
+    if (err & (kErrWalk | kErrInput | kErrCavity)) st->halt = kHaltError;
     else if (c->abort) st->halt = kHaltAbort;
-    else if (c->nwin == 0) st->halt = kHaltStall;
+    else if (nwin == 0) st->halt = kHaltStall;
     else {
       s_go = 1;
-      if (st->nhist < w.hist_cap) s_slot = st->nhist;
-      st->nhist += 1;
-      st->nV += c->nwin;
-      st->nT += c->fresh_total;
-      st->nS += c->nwin_mid;
-      st->wT = st->nT / 32 + 1;
-      st->wS = st->nS / 32 + 1;
-      st->rounds += 1;
-      st->serial += 1;
+      const int nh = st->nhist;
+      if (nh < w.hist_cap) s_slot = nh;
+      st->nhist = nh + 1;
+      const int nT = st->nT + c->fresh_total, nS = st->nS + c->nwin_mid;
+      st->nV = st->nV + nwin;
+      st->nT = nT;
+      st->nS = nS;
+      st->wT = nT / 32 + 1;
+      st->wS = nS / 32 + 1;
+      st->rounds = st->rounds + 1;
+      st->serial = st->serial + 1;
       st->prev_ncc = c->ncc;
       st->prev_nmk = c->nmk;
       st->prev_fan = c->fan_used;
+      st->full = 0;
     }
   }
   __syncthreads();
@@ -1400,13 +1501,19 @@ __device__ void round_end(const Work &w) {
   for (int i = threadIdx.x; i < nw; i += blockDim.x) src[i] = 0;
 }
 
+__device__ __forceinline__ void finish_part(const DevMesh &m, const Work &w, const Lanes &L) {
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
+  bool aborted = w.cnt->abort != 0;
+  for (int base = L.base0; base < n; base += L.stride) {
+    int c = base + threadIdx.x;
+    if (c < n) finish_one(m, w, c, ncc, nV, aborted);
+  }
+}
+
 __global__ void k_finish(DevMesh m, Work w) {
   __shared__ int s_last;
   if (w.st->halt) return;
-  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
-  bool aborted = w.cnt->abort != 0;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    finish_one(m, w, c, ncc, nV, aborted);
+  finish_part(m, w, grid_lanes());
   // every workgroup has read the counts it needs before it arrives here
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1418,6 +1525,255 @@ __global__ void k_finish(DevMesh m, Work w) {
   __threadfence();
   if (threadIdx.x == 0) w.st->done_blocks = 0;
   round_end(w);
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup engine: whole rounds, every phase of Lines 3-9, inside one
+// workgroup, with workgroup barriers between the phases instead of kernel
+// launches.  Used for rounds too small to fill the chip (the end of a
+// refinement, where launch latency dominates) and, one mesh per workgroup,
+// for batches of independent meshes.  The phases are the same functions the
+// grid kernels run, so the result is identical.
+// ---------------------------------------------------------------------------
+// Barrier between two phases.  Every wave of the engine runs on one compute
+// unit, so the workgroup-scope release / acquire of the barrier is enough to
+// make each phase's writes (stores and atomics) visible to the next phase.
+__device__ __forceinline__ void phase_sync() { __syncthreads(); }
+
+// Exclusive scan of *j.n_dev entries by one workgroup: complete prefixes in
+// j.out, zero tile prefixes (so that readers that add them are unchanged).
+__device__ void engine_scan(const ScanJob &j) {
+  __shared__ int s_total;
+  const int n = *j.n_dev;
+  const int chunk = blockDim.x * kScanItems;
+  int carry = 0;
+  for (int start = 0; start < n; start += chunk) {
+    int base = start + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int i = 0; i < kScanItems; i++) {
+      int idx = base + i;
+      int x = idx < n ? j.in[idx] : 0;
+      if (j.mode == 1) x = __popc((uint32_t)x);
+      v[i] = x;
+      sum += x;
+    }
+    int excl = block_excl_scan(sum, &s_total) + carry;
+    for (int i = 0; i < kScanItems; i++) {
+      int idx = base + i;
+      if (idx < n) j.out[idx] = excl;
+      excl += v[i];
+    }
+    carry += s_total;
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t <= n / kScanTile; t += blockDim.x) j.tiles[t] = 0;
+  if (threadIdx.x == 0) *j.total = carry;
+}
+
+// Radix select of the K-th largest key by one workgroup (keys are unique);
+// the threshold goes to w.sel[0] (0 when no more than K keys).
+__device__ void engine_select(const Work &w, int K, int32_t *h) {
+  __shared__ uint64_t s_prefix, s_pmask;
+  __shared__ int64_t s_rem;
+  const int n = w.cnt->ncc + w.cnt->nmk;
+  if (threadIdx.x == 0) {
+    s_prefix = 0;
+    s_pmask = 0;
+    s_rem = K;
+  }
+  __syncthreads();
+  if (n > K) {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+      __syncthreads();
+      const uint64_t prefix = s_prefix, pmask = s_pmask;
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        uint64_t k = w.keys[c];
+        if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t cum = 0;
+        int d = 255;
+        for (; d > 0; d--) {
+          if (cum + h[d] >= s_rem) break;
+          cum += h[d];
+        }
+        s_rem -= cum;
+        s_prefix |= (uint64_t)d << shift;
+        s_pmask |= (uint64_t)0xff << shift;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) w.sel[0] = s_prefix;
+}
+
+// Winner ranks by counting (at most kEngRankMax winners): rank = number of
+// winners with a smaller (class, element) key, midpoints first, which is the
+// order the bitmap ranks give.  Returns false if there are more winners.
+constexpr int kEngRankMax = 2048;
+__device__ bool engine_rank(const Work &w, int32_t *lds) {
+  __shared__ int s_nw, s_nmid;
+  int32_t *key = lds, *ref = lds + kEngRankMax;
+  if (threadIdx.x == 0) {
+    s_nw = 0;
+    s_nmid = 0;
+  }
+  __syncthreads();
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    CandSet S;
+    int ci, is_cc;
+    cand_at(w, c, ncc, S, ci, is_cc);
+    if (!(S.state[ci] & kStWin)) continue;
+    int pos = atomicAdd(&s_nw, 1);
+    if (!is_cc) atomicAdd(&s_nmid, 1);
+    if (pos < kEngRankMax) {
+      key[pos] = (int32_t)(((uint32_t)is_cc << 31) | (uint32_t)S.elem[ci]);
+      ref[pos] = (is_cc ? 0 : (int)0x80000000) | ci;
+    }
+  }
+  __syncthreads();
+  const int nw = s_nw;
+  if (nw > kEngRankMax) return false;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    const uint32_t k = (uint32_t)key[i];
+    int r = 0;
+    for (int j = 0; j < nw; j++) r += (uint32_t)key[j] < k;
+    w.win_ref[r] = ref[i];
+    w.fcount[r] = fresh_of(w, (k >> 31) != 0, (int)(k & 0x7fffffffu));
+  }
+  if (threadIdx.x == 0) {
+    w.cnt->nwin_mid = s_nmid;
+    w.cnt->nwin_cc = nw - s_nmid;
+    w.cnt->nwin = nw;
+    w.cnt->nwin1 = nw + 1;
+    w.fcount[nw] = 0;
+  }
+  return true;
+}
+
+// Large cavities of one class, one after the other, by the whole workgroup.
+__device__ void engine_big(const DevMesh &m, const Work &w, BigShared &sh, int phase) {
+  const int nbig = min(w.cnt->nbig, w.big_cap);
+  for (int b = 0; b < nbig; b++) {
+    int ref = w.big[b];
+    int is_cc = (ref & 0x80000000) ? 0 : 1;
+    if (is_cc != (phase == 0 ? 1 : 0)) continue;
+    big_one(m, w, sh, b);
+    __syncthreads();
+  }
+}
+
+constexpr int kEngLdsWords = (kCap * kEngBlock > (int)(sizeof(BigShared) / 4)) ? kCap * kEngBlock
+                                                                               : (int)(sizeof(BigShared) / 4);
+static_assert(kApproxMax <= kCap, "prefilter slices fit in the cavity slices");
+
+// Rounds of one mesh until it halts or round_limit rounds have completed.
+__device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
+  __shared__ int s_ser, s_full, s_halt;
+  const DevMesh &m = d.m;
+  DevState *st = d.w[0].st;
+  const Lanes L = block_lanes();
+  for (int r = 0; r < round_limit; r++) {
+    phase_sync();
+    if (threadIdx.x == 0) {
+      s_halt = st->halt;
+      s_ser = st->serial;
+      s_full = st->full;
+    }
+    __syncthreads();
+    if (s_halt) break;
+    const Work &w = d.w[s_ser & 1];
+    // R1 collection
+    if (s_full) {
+      scan_part(m, w, d.B2, d.pm, L);
+    } else {
+      carry_part(w, L);
+      dirty_part(m, w, d.B2, d.pm, L);
+      phase_sync();
+      pending_part(m, w, L);
+    }
+    phase_sync();
+    if (gate_part(w, d.max_rounds)) break;
+    phase_sync();
+    // R3 candidate cap
+    if (d.K > 0) {
+      gather_part(m, w, d.pm, L);
+      phase_sync();
+      engine_select(w, d.K, lds);
+      phase_sync();
+      apply_part(w, L);
+      phase_sync();
+    }
+    // R4 locate, optional prefilters
+    locate_part(m, w, L);
+    phase_sync();
+    if (d.f1)
+      for (int mode = 0; mode < 3; mode++) {
+        prefilter_part(m, w, mode, 0, lds, L);
+        phase_sync();
+      }
+    if (d.approx_n > 0)
+      for (int mode = 3; mode < 6; mode++) {
+        prefilter_part(m, w, mode, d.approx_n, lds, L);
+        phase_sync();
+      }
+    // R5/R6 cavities with their marks
+    BigShared &sh = *reinterpret_cast<BigShared *>(lds);
+    cavity_part(m, w, 1, lds, L);
+    phase_sync();
+    engine_big(m, w, sh, 0);
+    phase_sync();
+    cavity_part(m, w, 0, lds, L);
+    phase_sync();
+    engine_big(m, w, sh, 1);
+    phase_sync();
+    // R8 ownership, R9 dependency
+    own_part(w, L);
+    phase_sync();
+    dep_part(m, w, L);
+    phase_sync();
+    // R10 ranks, fresh slots, capacity check, insertion
+    const ScanJob js{(const int32_t *)w.win_s, w.rank_s, &w.st->wS, w.tiles_s, &w.cnt->nwin_mid, 1};
+    const ScanJob jt{(const int32_t *)w.win_t, w.rank_t, &w.st->wT, w.tiles_t, &w.cnt->nwin_cc, 1};
+    const ScanJob jf{w.fcount, w.fbase, &w.cnt->nwin1, w.tiles_f, &w.cnt->fan_total, 0};
+    if (!engine_rank(w, lds)) {  // many winners: bitmap ranks as in the grid kernels
+      phase_sync();
+      engine_scan(js);
+      engine_scan(jt);
+      phase_sync();
+      winners_part(w, L);
+    }
+    phase_sync();
+    engine_scan(jf);
+    phase_sync();
+    record_part(m, w, L);
+    phase_sync();
+    write_part(m, w, L);
+    phase_sync();
+    finish_part(m, w, L);
+    phase_sync();
+    round_end(w);
+  }
+}
+
+// Each workgroup takes meshes from a queue (head counts the taken ones) and
+// runs each for at most round_limit rounds.
+__global__ __launch_bounds__(kEngBlock) void k_engine(const EngDesc *descs, int n_mesh, int32_t *head,
+                                                      int round_limit) {
+  __shared__ int32_t lds[kEngLdsWords];
+  __shared__ int s_i;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_i = atomicAdd(head, 1);
+    __syncthreads();
+    const int i = s_i;
+    if (i >= n_mesh) return;
+    engine_mesh(descs[i], lds, round_limit);
+  }
 }
 
 }  // namespace gdp

@@ -36,7 +36,7 @@ class gdp_params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
                 ("profile_kernels", C.c_int32), ("reserve_mode", C.c_int32), ("rounds_per_sync", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("tail_engine_max", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class gdp_kernel_prof(C.Structure):
@@ -122,11 +122,13 @@ def _pslg(xy, seg):
 
 
 def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
-                prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0) -> gdp_params:
+                prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0,
+                tail_engine_max=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
     p.reserve_mode = reserve_mode
     p.rounds_per_sync = rounds_per_sync
+    p.tail_engine_max = tail_engine_max
     p.prefilter_f1 = prefilter_f1
     p.cavity_approx_n = cavity_approx_n
     p.profile_kernels = profile_kernels

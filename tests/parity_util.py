@@ -18,12 +18,13 @@ def oracle_run(pslg, cand_cap_K=0, priority_mode=0, max_rounds=0, prefilter_f1=0
 
 
 def gpu_run(ctx, pslg, cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, prefilter_f1=0,
-            cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0):
+            cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0, tail_engine_max=0):
     from paper_2007_00324_amd import gdp2d
     mesh = gdp2d.gdp_mesh_create(ctx, pslg.xy, pslg.seg)
     prm = gdp2d.make_params(cand_cap_K=cand_cap_K, priority_mode=priority_mode, max_rounds=max_rounds,
                             block_size=block_size, prefilter_f1=prefilter_f1, cavity_approx_n=cavity_approx_n,
-                            reserve_mode=reserve_mode, rounds_per_sync=rounds_per_sync)
+                            reserve_mode=reserve_mode, rounds_per_sync=rounds_per_sync,
+                            tail_engine_max=tail_engine_max)
     rc = gdp2d.gdp_mesh_refine(ctx, mesh, pslg.ratio_bound_sq, prm, allow_noterm=True)
     return mesh, rc
 

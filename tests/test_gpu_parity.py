@@ -19,7 +19,7 @@ def ctx():
     return gdp2d.Context(0)
 
 
-PERF_ONLY = ("reserve_mode", "rounds_per_sync", "block_size")
+PERF_ONLY = ("reserve_mode", "rounds_per_sync", "block_size", "tail_engine_max")
 
 
 def _check(ctx, p, **kw):
@@ -50,6 +50,23 @@ SMALL = {
 @pytest.mark.parametrize("name", list(SMALL))
 def test_parity_small(ctx, name):
     _check(ctx, SMALL[name]())
+
+
+@pytest.mark.parametrize("name", ["c0", "rand_300", "knn_2000", "circles_small"])
+def test_parity_small_grid_only(ctx, name):
+    """Every round on the multi-workgroup kernels (the single-workgroup engine off)."""
+    _check(ctx, SMALL[name](), tail_engine_max=-1)
+
+
+ENGINE_ALL = 1 << 30  # every round after the first in the single-workgroup engine
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(cand_cap_K=7), dict(prefilter_f1=1, cavity_approx_n=4),
+                                dict(priority_mode=1), dict(reserve_mode=1), dict(max_rounds=6)])
+@pytest.mark.parametrize("case", ["c0", "circles_small", "knn_2000"])
+def test_parity_engine(ctx, case, kw):
+    """Rounds run whole inside one workgroup give the same mesh and counters."""
+    _check(ctx, SMALL[case](), tail_engine_max=ENGINE_ALL, **kw)
 
 
 @pytest.mark.parametrize("B2", [1.6 * 1.6, 4.0])
@@ -135,11 +152,18 @@ def test_parity_from_uploaded_oracle_state(ctx):
     assert not diff_arrays(full.arrays(), g.arrays())
 
 
-@pytest.mark.parametrize("case", ["c1_100k", "c2_32x200"])
+MEDIUM = {"c1_100k": lambda: workloads.scaled_config1(100_000, 5_000),
+          "c2_32x200": lambda: workloads.scaled_config2(32, 200, 5_000)}
+
+
+@pytest.mark.parametrize("case", list(MEDIUM))
 def test_parity_medium(ctx, case):
-    p = {"c1_100k": lambda: workloads.scaled_config1(100_000, 5_000),
-         "c2_32x200": lambda: workloads.scaled_config2(32, 200, 5_000)}[case]()
-    _check(ctx, p)
+    _check(ctx, MEDIUM[case]())
+
+
+@pytest.mark.parametrize("case", list(MEDIUM))
+def test_parity_medium_engine(ctx, case):
+    _check(ctx, MEDIUM[case](), tail_engine_max=ENGINE_ALL)
 
 
 def test_reruns_identical(ctx):
