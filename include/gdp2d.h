@@ -195,6 +195,22 @@ gdp_status gdp_mesh_last_refine_ms(const gdp_mesh *mesh, double *ms);
    writes up to cap records, *n gets the number of kernel kinds. */
 gdp_status gdp_mesh_kernel_profile(const gdp_mesh *mesh, gdp_kernel_prof *out, int32_t cap, int32_t *n);
 
+/* Batched form: refines count independent PSLGs (pslgs[i] with bound
+   ratio_bound_sq[i], the same params for all).  Line 1 runs on the host for
+   every input (in parallel), then every mesh is refined by Lines 2-9 in one
+   persistent launch in which each workgroup takes meshes from a queue,
+   largest first, and runs every round of a mesh by itself.  Each mesh is
+   bit-identical to gdp_refine on the same input.  outs[i] receives the mesh
+   (free with gdp_mesh_free; the meshes of a batch share one device
+   allocation, released with the last of them) or NULL if status[i]
+   (optional, count entries) is an error; status[i] = GDP_E_NOTERM keeps the
+   mesh.  A mesh that outgrows its estimated room is refined again on its
+   own.  *elapsed_ms (optional) receives the device time of the launch.
+   Returns GDP_OK unless the call itself failed. */
+gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *ratio_bound_sq,
+                            const gdp_params *params, int32_t count, gdp_mesh **outs, gdp_status *status,
+                            double *elapsed_ms);
+
 /* Copies the state of src (vertices, triangles, subsegments, counters) into
    dst on the device, growing dst only if it is too small; both meshes must
    belong to ctx.  Used to restart refinement from a resident initial CDT. */

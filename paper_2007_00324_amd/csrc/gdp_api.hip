@@ -2,11 +2,13 @@
 // and the host loop that issues one refinement round after another
 // (Algorithm 1, "repeat ... until L is empty").
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gdp_kernels.h"
@@ -19,8 +21,15 @@ struct gdp_ctx {
   std::string err;
 };
 
+// Device memory shared by the meshes of one batch (freed with the last one).
+struct gdp_arena {
+  void *base = nullptr;
+  int refs = 0;
+};
+
 struct gdp_mesh {
   gdp_ctx *ctx = nullptr;
+  gdp_arena *arena = nullptr;  // non-null: the device arrays below live in a batch arena
   DevMesh m;
   // Two rounds (parity p, then the other) captured as one HIP graph, for
   // groups of small rounds; rebuilt when a buffer, a parameter or the grid
@@ -87,11 +96,11 @@ struct gdp_mesh {
 namespace {
 enum ProfId {
   P_SCAN = 0, P_CAP, P_LOCATE, P_CAV_CC, P_CAV_MID, P_CAV_BIG, P_MARK, P_OWN, P_DEP, P_PREFIX,
-  P_WINNERS, P_RECORD, P_WRITE, P_FINISH, P_NUM
+  P_WINNERS, P_RECORD, P_WRITE, P_FINISH, P_ENGINE, P_NUM
 };
 const char *kProfNames[P_NUM] = {"k_scan", "k_cap", "k_locate", "k_cavity_cc", "k_cavity_mid", "k_cavity_big",
                                   "k_mark", "k_own", "k_dep", "k_prefix_sum", "k_winners", "k_record", "k_write",
-                                  "k_finish"};
+                                  "k_finish", "k_engine"};
 // Records HIP events around the launches issued in its scope (if enabled);
 // items and algorithmic bytes are filled in once the round's counts are read.
 struct Prof {
@@ -345,7 +354,18 @@ gdp_status alloc_control(gdp_mesh *M) {
   return GDP_OK;
 }
 
+void free_extras(gdp_mesh *M);
+
 void free_mesh_arrays(gdp_mesh *M) {
+  if (M->arena) {
+    free_extras(M);
+    if (--M->arena->refs == 0) {
+      (void)hipFree(M->arena->base);
+      delete M->arena;
+    }
+    M->arena = nullptr;
+    return;
+  }
   void *ptrs[] = {M->m.vxy, M->m.vkind, M->m.tv, M->m.tn, M->m.ts, M->m.sv, M->m.spar, M->m.spend,
                   M->d_cnt, M->mark, M->sadj, M->mflag,
                   M->cc.elem, M->cc.key, M->cc.p, M->cc.loc, M->cc.state, M->cc.off, M->cc.len,
@@ -356,6 +376,12 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->cidx_t, M->cidx_s};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  free_extras(M);
+}
+
+// Allocations a mesh owns even inside a batch arena: pinned host mirrors,
+// captured graphs, the engine descriptor.
+void free_extras(gdp_mesh *M) {
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
   if (M->h_st) (void)hipHostFree(M->h_st);
   if (M->h_hist) (void)hipHostFree(M->h_hist);
@@ -509,7 +535,7 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
   {
     Prof pr(M, P_CAV_CC);
-    hipLaunchKernelGGL(k_cavity, dim3(stride_grid(ncand, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, 1);
+    hipLaunchKernelGGL(k_cavity<1>, dim3(stride_grid(ncand, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w);
   }
   {
     Prof pr(M, P_CAV_BIG);
@@ -517,7 +543,7 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   }
   {
     Prof pr(M, P_CAV_MID);
-    hipLaunchKernelGGL(k_cavity, dim3(stride_grid(ncand / 4, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w, 0);
+    hipLaunchKernelGGL(k_cavity<0>, dim3(stride_grid(ncand / 4, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w);
   }
   {
     Prof pr(M, P_CAV_BIG);
@@ -597,6 +623,7 @@ int64_t prof_items(int id, const DevCounters &c, int64_t nT, int64_t pc, int64_t
     case P_CAV_BIG: return c.nbig;
     case P_RECORD: case P_WRITE: return c.nwin;
     case P_PREFIX: return 0;
+    case P_ENGINE: return (int64_t)c.ncc + c.nmk;
     default: return (int64_t)c.ncc + c.nmk;
   }
 }
@@ -733,24 +760,406 @@ gdp_status launch_engine(gdp_mesh *M, double B2, const gdp_params *P, int rounds
   d.max_rounds = P->max_rounds;
   HIPCHECK(hipMemcpyAsync(M->d_eng, &d, sizeof d, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemsetAsync(M->d_head, 0, sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_engine, dim3(1), dim3(kEngBlock), 0, s, M->d_eng, 1, M->d_head, rounds);
+  M->cur_round = 0;
+  {
+    Prof pr(M, P_ENGINE);
+    hipLaunchKernelGGL(k_engine, dim3(1), dim3(kEngBlock), 0, s, M->d_eng, 1, M->d_head, rounds);
+  }
   HIPCHECK(hipGetLastError());
+  return GDP_OK;
+}
+
+
+// ---- batched form: many meshes in one arena, one persistent launch ---------
+struct Caps {
+  int64_t V, T, S, W, tiles, pool, fan;
+};
+
+Caps caps_of(const gdp_mesh *M) {
+  return {M->m.capV, M->m.capT, M->m.capS, M->wT, M->tiles_cap, M->pool_cap, M->fan_cap};
+}
+
+// Every device array of a mesh: f(pointer, element bytes, length, fill byte).
+// The lengths match the grow_* functions for the same capacities.
+template <class F>
+void for_each_array(gdp_mesh *M, const Caps &c, F f) {
+  const int64_t wT = c.T / 32 + 1, wS = c.S / 32 + 1;
+  f((void **)&M->m.vxy, sizeof(double2), c.V, 0);
+  f((void **)&M->m.vkind, 4, c.V, 0);
+  f((void **)&M->m.tv, sizeof(int4), c.T, 0);
+  f((void **)&M->m.tn, sizeof(int4), c.T, 0);
+  f((void **)&M->m.ts, sizeof(int4), c.T, 0);
+  f((void **)&M->m.sv, sizeof(int2), c.S, 0);
+  f((void **)&M->m.spar, 4, c.S, 0);
+  f((void **)&M->m.spend, 4, c.S, 0);
+  f((void **)&M->mark, 8, c.T, 0);
+  f((void **)&M->sadj, 4, 2 * c.S, 0xff);
+  f((void **)&M->mflag, 4, c.S, 0);
+  CandSet *sets[2] = {&M->cc, &M->mid};
+  for (int k = 0; k < 2; k++) {
+    const int64_t n = k == 0 ? c.T : 2 * c.S;
+    CandSet &cs = *sets[k];
+    f((void **)&cs.elem, 4, n, 0);
+    f((void **)&cs.key, 8, n, 0);
+    f((void **)&cs.p, sizeof(double2), n, 0);
+    f((void **)&cs.loc, 4, n, 0);
+    f((void **)&cs.state, 4, n, 0);
+    f((void **)&cs.off, 4, n, 0);
+    f((void **)&cs.len, 4, n, 0);
+  }
+  f((void **)&M->prev_cc_elem, 4, c.T, 0);
+  f((void **)&M->prev_cc_key, 8, c.T, 0);
+  f((void **)&M->prev_cc_p, sizeof(double2), c.T, 0);
+  f((void **)&M->prev_mid_elem, 4, 2 * c.S, 0);
+  f((void **)&M->w0_t, 4, wT, 0);
+  f((void **)&M->win_t, 4, wT, 0);
+  f((void **)&M->rank_t, 4, wT, 0);
+  f((void **)&M->w0_s, 4, wS, 0);
+  f((void **)&M->win_s, 4, wS, 0);
+  f((void **)&M->rank_s, 4, wS, 0);
+  f((void **)&M->repl, 4, 4 * c.T, 0xff);
+  f((void **)&M->tstamp, 4, c.T, 0xff);
+  f((void **)&M->cidx_t, 4, c.T, 0);
+  f((void **)&M->cidx_s, 4, c.S, 0);
+  f((void **)&M->win_ref, 4, c.W, 0);
+  f((void **)&M->fbase, 4, c.W, 0);
+  f((void **)&M->fcount, 4, c.W, 0);
+  f((void **)&M->fan_off, 4, c.W, 0);
+  f((void **)&M->big, 4, c.W, 0);
+  f((void **)&M->keys, 8, c.W, 0);
+  f((void **)&M->tiles_t, 4, c.tiles, 0);
+  f((void **)&M->tiles_s, 4, c.tiles, 0);
+  f((void **)&M->tiles_f, 4, c.tiles, 0);
+  f((void **)&M->pool, 4, c.pool, 0);
+  f((void **)&M->fan, sizeof(FanRec), c.fan, 0);
+  f((void **)&M->d_cnt, sizeof(DevCounters), 1, 0);
+  f((void **)&M->d_st, sizeof(DevState), 1, 0);
+  f((void **)&M->d_hist, sizeof(DevCounters), kHistCap, 0);
+  f((void **)&M->rhist, 4, 256, 0);
+  f((void **)&M->sel, 8, 4, 0);
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Pinned host mirrors of a mesh's control block (a batch member gets them
+// when it is first refined on its own).
+gdp_status alloc_host_mirrors(gdp_mesh *M) {
+  gdp_ctx *ctx = M->ctx;
+  if (!M->h_cnt && hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters)) != hipSuccess)
+    return fail(ctx, GDP_E_NOMEM, "pinned allocation failed");
+  if (!M->h_st && hipHostMalloc((void **)&M->h_st, sizeof(DevState)) != hipSuccess)
+    return fail(ctx, GDP_E_NOMEM, "pinned allocation failed");
+  if (!M->h_hist && hipHostMalloc((void **)&M->h_hist, sizeof(DevCounters) * kHistCap) != hipSuccess)
+    return fail(ctx, GDP_E_NOMEM, "pinned allocation failed");
+  return GDP_OK;
+}
+
+// A batch member that is refined or overwritten on its own first moves its
+// arrays out of the shared arena into allocations of its own.
+gdp_status detach(gdp_mesh *M) {
+  if (!M->arena) return GDP_OK;
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  std::vector<void **> slot;
+  std::vector<size_t> bytes;
+  for_each_array(M, caps_of(M), [&](void **pp, size_t es, int64_t n, int) {
+    slot.push_back(pp);
+    bytes.push_back(es * (size_t)std::max<int64_t>(n, 1));
+  });
+  std::vector<void *> fresh(slot.size(), nullptr);
+  for (size_t i = 0; i < slot.size(); i++) {
+    if (hipMalloc(&fresh[i], bytes[i]) != hipSuccess) {
+      for (void *q : fresh)
+        if (q) (void)hipFree(q);
+      return fail(ctx, GDP_E_NOMEM, "device allocation failed");
+    }
+    HIPCHECK(hipMemcpyAsync(fresh[i], *slot[i], bytes[i], hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  for (size_t i = 0; i < slot.size(); i++) *slot[i] = fresh[i];
+  if (--M->arena->refs == 0) {
+    (void)hipFree(M->arena->base);
+    delete M->arena;
+  }
+  M->arena = nullptr;
+  return alloc_host_mirrors(M);
+}
+
+gdp_status status_of_halt(gdp_ctx *ctx, const DevState &d, const DevCounters &c) {
+  switch (d.halt) {
+    case kHaltDone: return GDP_OK;
+    case kHaltCap: return fail(ctx, GDP_E_NOTERM, "round cap reached");
+    case kHaltStall: return fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing");
+    case kHaltError:
+      if (c.err & kErrWalk) return fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap");
+      if (c.err & kErrInput) return fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment");
+      return fail(ctx, GDP_E_CAVITY, "cavity error");
+    default: return fail(ctx, GDP_E_DEVICE, "mesh did not finish");
+  }
+}
+
+// The batched form (Algorithm 1 for many independent PSLGs): Line 1 on the
+// host for every input (in parallel), one arena holding every mesh and its
+// workspace, then all of Lines 2-9 in one launch of the single-workgroup
+// engine whose workgroups take meshes from a queue, largest first.  A mesh
+// whose estimated room runs out is refined again on its own (same result).
+gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, const gdp_params *P,
+                        int32_t count, gdp_mesh **outs, gdp_status *status, double *elapsed_ms) {
+  hipStream_t s = ctx->stream;
+  for (int32_t i = 0; i < count; i++) {
+    outs[i] = nullptr;
+    if (status) status[i] = GDP_OK;
+  }
+  // Line 1 on the host
+  std::vector<HostMesh> hm(count);
+  std::vector<int> rc(count, GDP_OK);
+  std::vector<std::string> errs(count);
+  {
+    std::atomic<int32_t> next(0);
+    unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16));
+    nth = std::min<unsigned>(nth, (unsigned)std::max(count, 1));
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; t++)
+      pool.emplace_back([&]() {
+        for (int32_t i; (i = next.fetch_add(1)) < count;)
+          rc[i] = host_cdt_build(pslgs[i].n_vertices, pslgs[i].xy, pslgs[i].n_segments, pslgs[i].seg, hm[i], errs[i]);
+      });
+    for (auto &th : pool) th.join();
+  }
+  std::vector<int32_t> ok;
+  for (int32_t i = 0; i < count; i++) {
+    if (rc[i] == GDP_OK) ok.push_back(i);
+    else if (status) status[i] = (gdp_status)rc[i];
+  }
+  if (elapsed_ms) *elapsed_ms = 0.0;
+  if (ok.empty()) return GDP_OK;
+  // capacities: room for the refined mesh (about 2.5x the input vertices at
+  // B = sqrt(2), more for tiny inputs); a mesh that outgrows it falls back
+  const int32_t n = (int32_t)ok.size();
+  std::vector<gdp_mesh *> mesh(n);
+  std::vector<Caps> caps(n);
+  gdp_arena *arena = new gdp_arena();
+  for (int32_t k = 0; k < n; k++) {
+    const HostMesh &h = hm[ok[k]];
+    Caps c;
+    c.V = 3 * (int64_t)h.nV + 256;
+    c.T = std::max<int64_t>(2 * c.V + 256, h.nT);
+    c.S = 16 * (int64_t)h.nS + 64;
+    c.W = c.T + 2 * c.S + 2;
+    c.tiles = c.W / kScanTileSize + 2;
+    c.pool = 2 * c.T + 4096;
+    c.fan = 2 * c.T + 4096;
+    caps[k] = c;
+    gdp_mesh *M = new gdp_mesh();
+    M->ctx = ctx;
+    M->arena = arena;
+    arena->refs++;
+    mesh[k] = M;
+  }
+  // arena: one region per array kind, each mesh's array 256-byte aligned in it
+  std::vector<size_t> region;
+  for (int32_t k = 0; k < n; k++) {
+    size_t j = 0;
+    for_each_array(mesh[k], caps[k], [&](void **, size_t es, int64_t len, int) {
+      if (region.size() <= j) region.push_back(0);
+      region[j++] += align256(es * (size_t)std::max<int64_t>(len, 1));
+    });
+  }
+  std::vector<size_t> region_off(region.size());
+  size_t total = 0;
+  for (size_t j = 0; j < region.size(); j++) {
+    region_off[j] = total;
+    total += region[j];
+  }
+  auto bail = [&](gdp_status st) {
+    for (gdp_mesh *M : mesh) {
+      M->arena = nullptr;
+      delete M;
+    }
+    if (arena->base) (void)hipFree(arena->base);
+    delete arena;
+    return st;
+  };
+  if (hipMalloc(&arena->base, total) != hipSuccess) return bail(fail(ctx, GDP_E_NOMEM, "batch arena allocation failed"));
+  char *base = (char *)arena->base;
+  std::vector<size_t> run(region.size(), 0);
+  std::vector<int> fills(region.size(), 0);
+  std::vector<std::vector<size_t>> off(n, std::vector<size_t>(region.size()));
+  for (int32_t k = 0; k < n; k++) {
+    size_t j = 0;
+    for_each_array(mesh[k], caps[k], [&](void **pp, size_t es, int64_t len, int fill) {
+      off[k][j] = run[j];
+      *pp = base + region_off[j] + run[j];
+      fills[j] = fill;
+      run[j] += align256(es * (size_t)std::max<int64_t>(len, 1));
+      j++;
+    });
+  }
+  if (hipMemsetAsync(base, 0, total, s) != hipSuccess) return bail(fail(ctx, GDP_E_DEVICE, "arena fill failed"));
+  for (size_t j = 0; j < region.size(); j++)
+    if (fills[j] && hipMemsetAsync(base + region_off[j], fills[j], region[j], s) != hipSuccess)
+      return bail(fail(ctx, GDP_E_DEVICE, "arena fill failed"));
+  // initial meshes and device states, staged per region (array indices as in for_each_array)
+  enum { R_VXY = 0, R_TV = 2, R_TN = 3, R_TS = 4, R_SV = 5, R_SPAR = 6 };
+  const int R_ST = (int)region.size() - 4;  // d_st (then d_hist, rhist, sel)
+  auto stage = [&](int j, auto fillfn) -> gdp_status {
+    std::vector<char> h(region[j], 0);
+    for (int32_t k = 0; k < n; k++) fillfn(k, h.data() + off[k][j]);
+    if (hipMemcpy(base + region_off[j], h.data(), region[j], hipMemcpyHostToDevice) != hipSuccess)
+      return fail(ctx, GDP_E_DEVICE, "batch upload failed");
+    return GDP_OK;
+  };
+  gdp_status st = GDP_OK;
+  if ((st = stage(R_VXY, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].xy.data(), sizeof(double) * 2 * hm[ok[k]].nV); })))
+    return bail(st);
+  for (int e = 0; e < 3; e++) {
+    const int j = e == 0 ? R_TV : (e == 1 ? R_TN : R_TS);
+    st = stage(j, [&](int32_t k, char *d) {
+      const HostMesh &h = hm[ok[k]];
+      int4 *q = (int4 *)d;
+      for (int32_t t = 0; t < h.nT; t++) {
+        const int32_t *a = e == 0 ? &h.tv[3 * t] : (e == 1 ? &h.tn[3 * t] : &h.ts[3 * t]);
+        int w = 0;
+        if (e == 0)
+          w = (h.ts[3 * t] >= 0 ? 1 : 0) | (h.ts[3 * t + 1] >= 0 ? 2 : 0) | (h.ts[3 * t + 2] >= 0 ? 4 : 0);
+        q[t] = make_int4(a[0], a[1], a[2], w);
+      }
+    });
+    if (st) return bail(st);
+  }
+  if ((st = stage(R_SV, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].sv.data(), sizeof(int32_t) * 2 * hm[ok[k]].nS); })))
+    return bail(st);
+  if ((st = stage(R_SPAR, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].sparent.data(), sizeof(int32_t) * hm[ok[k]].nS); })))
+    return bail(st);
+  if ((st = stage(R_ST, [&](int32_t k, char *d) {
+         const HostMesh &h = hm[ok[k]];
+         DevState ds;
+         memset(&ds, 0, sizeof ds);
+         ds.nV = h.nV; ds.nT = h.nT; ds.nS = h.nS;
+         ds.wT = words(h.nT); ds.wS = words(h.nS);
+         ds.full = 1;
+         memcpy(d, &ds, sizeof ds);
+       })))
+    return bail(st);
+  for (int32_t k = 0; k < n; k++) {
+    gdp_mesh *M = mesh[k];
+    const HostMesh &h = hm[ok[k]];
+    const Caps &c = caps[k];
+    M->m.capV = (int32_t)c.V; M->m.capT = (int32_t)c.T; M->m.capS = (int32_t)c.S;
+    M->m.nV = h.nV; M->m.nT = h.nT; M->m.nS = h.nS;
+    M->m.n_input_v = h.nV; M->m.n_input_s = h.nS; M->m.rounds = 0;
+    M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
+    M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
+  }
+  // descriptors, largest mesh first (the queue order balances the workgroups)
+  std::vector<int32_t> order(n);
+  for (int32_t k = 0; k < n; k++) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hm[ok[a]].nT > hm[ok[b]].nT; });
+  std::vector<EngDesc> desc(n);
+  for (int32_t q = 0; q < n; q++) {
+    const int32_t k = order[q];
+    EngDesc &d = desc[q];
+    memset(&d, 0, sizeof d);
+    d.m = mesh[k]->m;
+    d.w[0] = make_work(mesh[k], P->priority_mode, 0);
+    d.w[1] = make_work(mesh[k], P->priority_mode, 1);
+    d.B2 = bsq[ok[k]];
+    d.pm = P->priority_mode;
+    d.K = P->cand_cap_K;
+    d.f1 = P->prefilter_f1;
+    d.approx_n = P->cavity_approx_n;
+    d.max_rounds = P->max_rounds;
+  }
+  EngDesc *d_desc = nullptr;
+  int32_t *d_head = nullptr;
+  if (dalloc(&d_desc, n) != hipSuccess || dalloc(&d_head, 1) != hipSuccess) {
+    if (d_desc) (void)hipFree(d_desc);
+    return bail(fail(ctx, GDP_E_NOMEM, "descriptor allocation failed"));
+  }
+  auto free_tmp = [&]() {
+    (void)hipFree(d_desc);
+    (void)hipFree(d_head);
+  };
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool ok_run = hipMemcpy(d_desc, desc.data(), sizeof(EngDesc) * n, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemsetAsync(d_head, 0, sizeof(int32_t), s) == hipSuccess && hipEventCreate(&ev0) == hipSuccess &&
+                hipEventCreate(&ev1) == hipSuccess && hipEventRecord(ev0, s) == hipSuccess;
+  if (ok_run) {
+    hipLaunchKernelGGL(k_engine, dim3((unsigned)std::min(n, cus)), dim3(kEngBlock), 0, s, d_desc, n, d_head,
+                       1 << 30);
+    ok_run = hipGetLastError() == hipSuccess && hipEventRecord(ev1, s) == hipSuccess &&
+             hipEventSynchronize(ev1) == hipSuccess;
+  }
+  float ms = 0.f;
+  if (ok_run) (void)hipEventElapsedTime(&ms, ev0, ev1);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  free_tmp();
+  if (!ok_run) return bail(fail(ctx, GDP_E_DEVICE, "batch launch failed"));
+  if (elapsed_ms) *elapsed_ms = ms;
+  // results: device states, counters and per-round histories
+  const int R_CNT = R_ST - 1;  // d_cnt precedes d_st
+  std::vector<char> hst(region[R_ST]), hcnt(region[R_CNT]), hhist(region[R_ST + 1]);
+  if (hipMemcpy(hst.data(), base + region_off[R_ST], region[R_ST], hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hcnt.data(), base + region_off[R_CNT], region[R_CNT], hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hhist.data(), base + region_off[R_ST + 1], region[R_ST + 1], hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(fail(ctx, GDP_E_DEVICE, "batch download failed"));
+  for (int32_t k = 0; k < n; k++) {
+    gdp_mesh *M = mesh[k];
+    const int32_t i = ok[k];
+    DevState d;
+    DevCounters c;
+    memcpy(&d, hst.data() + off[k][R_ST], sizeof d);
+    memcpy(&c, hcnt.data() + off[k][R_CNT], sizeof c);
+    M->m.nV = d.nV; M->m.nT = d.nT; M->m.nS = d.nS; M->m.rounds = d.rounds;
+    M->serial = d.serial;
+    M->last_ms = ms;
+    const DevCounters *h = (const DevCounters *)(hhist.data() + off[k][R_ST + 1]);
+    for (int r = 0; r < std::min(d.nhist, kHistCap); r++) M->stats.push_back(round_stats_of(h[r], P));
+    if (d.halt == kHaltAbort) {
+      // out of its estimated room: the same refinement on its own
+      gdp_mesh_free(M);
+      mesh[k] = nullptr;
+      gdp_status r = gdp_refine(ctx, &pslgs[i], bsq[i], P, &outs[i]);
+      if (status) status[i] = r;
+      continue;
+    }
+    gdp_status r = status_of_halt(ctx, d, c);
+    if (status) status[i] = r;
+    if (r == GDP_OK || r == GDP_E_NOTERM) {
+      outs[i] = M;
+    } else {
+      gdp_mesh_free(M);
+      mesh[k] = nullptr;
+    }
+  }
   return GDP_OK;
 }
 
 // Queues up to this many rounds before the next host synchronisation.
 // Groups of two or more rounds are queued as graph replays, in pairs.
 int rounds_for(const gdp_params *P, int64_t last_cand, bool engine) {
-  if (P->profile_kernels) return 1;
   if (engine) return kHistCap;
   int r;
   if (P->rounds_per_sync > 0) r = std::min(P->rounds_per_sync, kHistCap);
   else if (last_cand > 65536) r = 1;
   else if (last_cand > 8192) r = 4;
   else r = 16;
-  // close to the engine's threshold: short groups, so that it takes over soon
+  // approaching the engine's threshold: end the group about when the
+  // candidates fall below it (they shrink by roughly a quarter per round at
+  // the end of a refinement), so that the engine takes over in time
   const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
-  if (P->rounds_per_sync == 0 && eng_max > 0 && last_cand <= 4 * eng_max) r = std::min(r, 2);
+  if (P->rounds_per_sync == 0 && eng_max > 0 && r > 2) {
+    int k = 0;
+    for (double c = (double)last_cand; c > (double)eng_max && k < 16; c *= 0.75) k++;
+    r = std::max(2, std::min(r, k));
+  }
   return r >= 2 ? r & ~1 : r;
 }
 
@@ -789,7 +1198,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   for (;;) {
     // small rounds run in the single-workgroup engine
     const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
-    const bool engine = !full && !M->prof && eng_max > 0 && last_cand <= eng_max;
+    const bool engine = !full && eng_max > 0 && last_cand <= eng_max;
     const int R = full ? 1 : rounds_for(P, last_cand, engine);
     gdp_status st;
     if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, engine ? 4 : R))) return st;
@@ -813,14 +1222,24 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     HIPCHECK(hipStreamSynchronize(s));
     const DevState d = *M->h_st;
     const int done = std::min(d.nhist, R);
-    // profiled launches (one round per group): items and algorithmic bytes
+    // profiled launches: items and algorithmic bytes of each completed round
     for (size_t k = prof0; k < M->prof_pending.size(); k++) {
       auto &r = M->prof_pending[k];
-      if (r.round < done) {
+      if (r.id == P_ENGINE) {  // one launch for the whole group
+        for (int i = 0; i < done; i++) r.items += (int64_t)M->h_hist[i].ncc + M->h_hist[i].nmk;
+      } else if (r.round < done) {
         const DevCounters &c = M->h_hist[r.round];
-        bool f = full && r.round == 0;
-        r.items = prof_items(r.id, c, m.nT, prev_ncc, prev_nmk, prev_fan, f);
-        r.bytes = alg_bytes(r.id, c, m.nT, m.nV, m.nS, prev_ncc, prev_nmk, prev_fan, f);
+        const bool f = full && r.round == 0;
+        int64_t pc = prev_ncc, pmk = prev_nmk, pf = prev_fan;
+        if (r.round > 0) {
+          const DevCounters &q = M->h_hist[r.round - 1];
+          pc = q.ncc;
+          pmk = q.nmk;
+          pf = q.fan_used;
+        }
+        // (a full collection is only ever the first round of a group)
+        r.items = prof_items(r.id, c, m.nT, pc, pmk, pf, f);
+        r.bytes = alg_bytes(r.id, c, m.nT, m.nV, m.nS, pc, pmk, pf, f);
       }
     }
     for (int i = 0; i < done; i++) {
@@ -832,11 +1251,15 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       prev_fan = c.fan_used;
     }
     if (M->prof && d.halt && M->prof_pending.size() > prof0) {
-      // keep the collection of a final round (it ran), drop the rest of it
+      // completed rounds stay; of the round that halted, the collection (it
+      // ran) or everything it ran before it was abandoned; later rounds of
+      // the group did nothing
       std::vector<gdp_mesh::ProfRec> keep(M->prof_pending.begin(), M->prof_pending.begin() + prof0);
       for (size_t k = prof0; k < M->prof_pending.size(); k++) {
         auto &r = M->prof_pending[k];
-        if (r.id == P_SCAN || d.halt == kHaltAbort) keep.push_back(r);
+        bool ran = r.id == P_ENGINE || r.round < done ||
+                   (r.round == done && (r.id == P_SCAN || d.halt == kHaltAbort));
+        if (ran) keep.push_back(r);
         else { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
       }
       M->prof_pending.swap(keep);
@@ -1001,12 +1424,9 @@ gdp_status gdp_mesh_upload(gdp_ctx *ctx, int32_t n_v, int32_t n_input_v, const d
                 sub_pending, rounds, out);
 }
 
-gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, const gdp_params *params) {
-  if (!ctx || !mesh || mesh->ctx != ctx) return GDP_E_ARG;
-  gdp_params P;
+static gdp_status check_params(gdp_ctx *ctx, const gdp_params *params, gdp_params &P) {
   if (params) P = *params; else gdp_params_default(&P);
   if (P.block_size == 0) P.block_size = 256;
-  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(ctx, GDP_E_ARG, "bad ratio bound");
   if (P.prefilter_f1 != 0 && P.prefilter_f1 != 1) return fail(ctx, GDP_E_ARG, "prefilter_f1 must be 0 or 1");
   if (P.cavity_approx_n < 0 || P.cavity_approx_n > kApproxMaxN)
     return fail(ctx, GDP_E_ARG, "cavity_approx_n must be in [0, 16]");
@@ -1016,8 +1436,31 @@ gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, 
   if (P.reserve_mode != 0 && P.reserve_mode != 1) return fail(ctx, GDP_E_ARG, "bad reserve mode");
   if (P.rounds_per_sync < 0 || P.rounds_per_sync > kHistCap)
     return fail(ctx, GDP_E_ARG, "rounds_per_sync must be in [0, 64]");
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_refine(gdp_ctx *ctx, gdp_mesh *mesh, double ratio_bound_sq, const gdp_params *params) {
+  if (!ctx || !mesh || mesh->ctx != ctx) return GDP_E_ARG;
+  gdp_params P;
+  gdp_status st;
+  if ((st = check_params(ctx, params, P))) return st;
+  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(ctx, GDP_E_ARG, "bad ratio bound");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  if ((st = detach(mesh))) return st;
   return refine_loop(mesh, ratio_bound_sq, &P);
+}
+
+gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *ratio_bound_sq,
+                            const gdp_params *params, int32_t count, gdp_mesh **outs, gdp_status *status,
+                            double *elapsed_ms) {
+  if (!ctx || count < 0 || (count > 0 && (!pslgs || !ratio_bound_sq || !outs))) return GDP_E_ARG;
+  gdp_params P;
+  gdp_status st;
+  if ((st = check_params(ctx, params, P))) return st;
+  for (int32_t i = 0; i < count; i++)
+    if (!(ratio_bound_sq[i] > 0.0) || !std::isfinite(ratio_bound_sq[i])) return fail(ctx, GDP_E_ARG, "bad ratio bound");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  return refine_batch(ctx, pslgs, ratio_bound_sq, &P, count, outs, status, elapsed_ms);
 }
 
 gdp_status gdp_refine(gdp_ctx *ctx, const gdp_pslg *pslg, double ratio_bound_sq, const gdp_params *params,
@@ -1126,6 +1569,7 @@ gdp_status gdp_mesh_kernel_profile(const gdp_mesh *mesh, gdp_kernel_prof *out, i
 gdp_status gdp_mesh_assign(gdp_ctx *ctx, gdp_mesh *dst, const gdp_mesh *src) {
   if (!ctx || !dst || !src || dst->ctx != ctx || src->ctx != ctx || dst == src) return GDP_E_ARG;
   gdp_status st;
+  if ((st = detach(dst))) return st;
   const DevMesh &a = src->m;
   if ((st = grow_vtx(dst, a.nV))) return st;
   if ((st = grow_tri(dst, a.nT))) return st;

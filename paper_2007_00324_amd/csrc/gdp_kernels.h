@@ -73,7 +73,8 @@ __global__ void k_apply_cap(Work w);
 __global__ void k_locate(DevMesh m, Work w);
 __global__ void k_prefilter(DevMesh m, Work w, int mode, int n);
 constexpr int kApproxMaxN = 16;
-__global__ void k_cavity(DevMesh m, Work w, int is_cc);
+template <int IS_CC>
+__global__ void k_cavity(DevMesh m, Work w);
 __global__ void k_cavity_big(DevMesh m, Work w, int phase);
 __global__ void k_own(Work w);
 __global__ void k_dep(DevMesh m, Work w);

@@ -838,11 +838,16 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
   }
 }
 
-__global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w, int is_cc) {
+// One kernel symbol per class (circumcenters: IS_CC = 1), so that profiles
+// tell them apart.
+template <int IS_CC>
+__global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w) {
   __shared__ int32_t lds[kCap * kCavBlock];
   if (w.st->halt) return;
-  cavity_part(m, w, is_cc, lds, grid_lanes());
+  cavity_part(m, w, IS_CC, lds, grid_lanes());
 }
+template __global__ void k_cavity<0>(DevMesh m, Work w);
+template __global__ void k_cavity<1>(DevMesh m, Work w);
 
 // Cooperative growth of one large cavity per workgroup (the tuple-parallel
 // ExpandList idea of Section 5.2: the frontier of <point, triangle> tuples

@@ -94,6 +94,8 @@ def load() -> C.CDLL:
         "gdp_mesh_assign": (S, [_VP, _VP, _VP]),
         "gdp_mesh_clone": (S, [_VP, _VP, C.POINTER(_VP)]),
         "gdp_mesh_free": (None, [_VP]),
+        "gdp_refine_batch": (S, [_VP, C.POINTER(gdp_pslg), _PD, C.POINTER(gdp_params), C.c_int32, C.POINTER(_VP),
+                                 C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -107,7 +109,7 @@ def exported_symbols() -> list[str]:
     return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
             "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
             "gdp_mesh_info_get", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
-            "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free"]
+            "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -289,6 +291,28 @@ def gdp_mesh_refine(ctx: Context, mesh: Mesh, ratio_bound_sq: float, params: gdp
     prm = params if params is not None else make_params()
     rc = load().gdp_mesh_refine(ctx._h, mesh._h, float(ratio_bound_sq), C.byref(prm))
     return ctx.check(rc, ok=(GDP_OK, -5) if allow_noterm else (GDP_OK,))
+
+
+def gdp_refine_batch(ctx: Context, inputs, ratio_bound_sq, params: gdp_params | None = None):
+    """Batched form: inputs is a list of (xy, seg) pairs, ratio_bound_sq a list
+    of bounds.  Returns (meshes, statuses, elapsed_ms); meshes[i] is None when
+    statuses[i] is an error."""
+    n = len(inputs)
+    keep, arr = [], (gdp_pslg * max(n, 1))()
+    for i, (xy, seg) in enumerate(inputs):
+        p, k = _pslg(xy, seg)
+        arr[i] = p
+        keep.append(k)
+    bsq = np.ascontiguousarray(np.asarray(ratio_bound_sq, dtype=np.float64).reshape(-1))
+    if bsq.shape[0] != n:
+        raise ValueError("one bound per input")
+    prm = params if params is not None else make_params()
+    outs = (_VP * max(n, 1))()
+    st = (C.c_int * max(n, 1))()
+    ms = C.c_double(0.0)
+    ctx.check(load().gdp_refine_batch(ctx._h, arr, _ptr(bsq, C.c_double), C.byref(prm), n, outs, st, C.byref(ms)))
+    meshes = [Mesh(ctx, _VP(outs[i])) if outs[i] else None for i in range(n)]
+    return meshes, [int(st[i]) for i in range(n)], ms.value
 
 
 def gdp_refine(ctx: Context, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> Mesh:

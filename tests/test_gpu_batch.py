@@ -1,0 +1,90 @@
+"""Batched form: many PSLGs refined in one persistent launch.  Each mesh must
+be identical to the oracle's and to the plain per-instance path's."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.parity_util import diff_arrays, diff_stats, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_00324_amd import gdp2d
+    return gdp2d.Context(0)
+
+
+def _batch(ctx, ps, **kw):
+    from paper_2007_00324_amd import gdp2d
+    prm = gdp2d.make_params(**kw)
+    return gdp2d.gdp_refine_batch(ctx, [(p.xy, p.seg) for p in ps], [p.ratio_bound_sq for p in ps], prm)
+
+
+def test_batch_matches_oracle(ctx):
+    ps = workloads.batch_config3(48, seed=11, n_min=100, n_max=3000)
+    print(f"[batch] {len(ps)} instances, {sum(p.n_vertices for p in ps)} vertices", flush=True)
+    meshes, st, ms = _batch(ctx, ps)
+    assert all(s == 0 for s in st), st
+    for p, g in zip(ps, meshes):
+        om, rc = oracle_run(p)
+        assert rc == 0
+        bad = diff_arrays(om.arrays(), g.arrays())
+        assert not bad, (p.name, bad)
+        assert g.info()["rounds"] == om.rounds
+        assert not diff_stats(om.stats[:64], g.round_stats()), p.name
+
+
+@pytest.mark.parametrize("kw", [dict(cand_cap_K=5), dict(prefilter_f1=1, cavity_approx_n=2), dict(priority_mode=1),
+                                dict(max_rounds=5)])
+def test_batch_options_match_oracle(ctx, kw):
+    ps = workloads.batch_config3(12, seed=12, n_min=100, n_max=1500)
+    meshes, st, _ = _batch(ctx, ps, **kw)
+    for p, g, s in zip(ps, meshes, st):
+        om, rc = oracle_run(p, **kw)
+        assert s == rc, (p.name, s, rc)
+        assert not diff_arrays(om.arrays(), g.arrays()), p.name
+
+
+def test_batch_equals_plain_path(ctx):
+    """Each instance alone (plain loop) and in the batch give the same mesh."""
+    from tests.parity_util import gpu_run
+    ps = workloads.batch_config3(24, seed=13, n_min=500, n_max=20000)
+    meshes, st, _ = _batch(ctx, ps)
+    assert all(s == 0 for s in st), st
+    for p, g in zip(ps, meshes):
+        alone, rc = gpu_run(ctx, p)
+        assert rc == 0
+        assert not diff_arrays(alone.arrays(), g.arrays()), p.name
+
+
+def test_batch_member_refined_again(ctx):
+    """A batch mesh can leave the batch (round cap first, then refined on its
+    own to the end), and the others are unaffected."""
+    from paper_2007_00324_amd import gdp2d
+    ps = workloads.batch_config3(6, seed=14, n_min=200, n_max=2000)
+    meshes, st, _ = _batch(ctx, ps, max_rounds=3)
+    assert all(s == -5 for s in st), st
+    gdp2d.gdp_mesh_refine(ctx, meshes[2], ps[2].ratio_bound_sq, gdp2d.make_params())
+    om, _ = oracle_run(ps[2])
+    assert not diff_arrays(om.arrays(), meshes[2].arrays())
+    o3, _ = oracle_run(ps[3], max_rounds=3)
+    assert not diff_arrays(o3.arrays(), meshes[3].arrays())
+    del meshes
+
+
+def test_batch_invalid_member(ctx):
+    """A member with an invalid PSLG gets an error status; the rest refine."""
+    ps = workloads.batch_config3(4, seed=15, n_min=100, n_max=500)
+    bad = workloads.bare_square()
+    xy = np.vstack([bad.xy, [[0.5, 0.5], [0.5, 0.5]]])  # duplicate point
+    from paper_2007_00324_amd import gdp2d
+    inputs = [(p.xy, p.seg) for p in ps] + [(xy, bad.seg)]
+    meshes, st, _ = gdp2d.gdp_refine_batch(ctx, inputs, [p.ratio_bound_sq for p in ps] + [2.0])
+    assert st[-1] != 0 and meshes[-1] is None
+    assert all(s == 0 for s in st[:-1])
+    for p, g in zip(ps, meshes[:-1]):
+        om, _ = oracle_run(p)
+        assert not diff_arrays(om.arrays(), g.arrays())

@@ -14,4 +14,8 @@ from .generators import (  # noqa: F401
     near_edge_point,
     random_small,
     manifest_hash,
+    BATCH_BOUNDS_SQ,
+    batch_plan,
+    batch_instance,
+    batch_config3,
 )

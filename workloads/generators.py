@@ -377,3 +377,42 @@ def config2(seed: int = 2) -> PSLG:
     p = scaled_config2(512, 1000, 100_000, seed)
     p.name = "c2_512_circles"
     return p
+
+
+# ---- batched form (4,096 independent PSLGs) ---------------------------------
+BATCH_BOUNDS_SQ = (2.0, 2.56, 4.0)  # B = sqrt(2), 1.6, 2.0, passed squared as FP64 literals
+
+
+def batch_plan(count: int = 4096, seed: int = 3, n_min: int = 100, n_max: int = 50_000):
+    """Sizes (log-uniform in [n_min, n_max]), bounds and per-instance seeds."""
+    rng = _rng(seed)
+    n = np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=count))).astype(np.int64)
+    bsq = rng.choice(np.array(BATCH_BOUNDS_SQ), size=count)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return n, bsq, seeds
+
+
+def batch_instance(n: int, bsq: float, seed: int) -> PSLG:
+    """One instance: config-0 style uniform points, k-nearest-neighbour
+    segments (5% of the vertices), unit square."""
+    m = max(1, int(round(0.05 * n)))
+    p = random_small(int(seed), int(n), m, float(bsq), pairing="knn")
+    p.name = f"c3_s{int(seed)}_n{int(n)}"
+    return p
+
+
+def _batch_instance_args(args):
+    return batch_instance(*args)
+
+
+def batch_config3(count: int = 4096, seed: int = 3, n_min: int = 100, n_max: int = 50_000,
+                  workers: int = 1) -> list[PSLG]:
+    """The batched workload: count instances of batch_instance (generated in
+    parallel when workers > 1; each instance depends only on its own seed)."""
+    n, bsq, seeds = batch_plan(count, seed, n_min, n_max)
+    args = list(zip(n.tolist(), bsq.tolist(), seeds.tolist()))
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_batch_instance_args, args, chunksize=8)
+    return [batch_instance(*a) for a in args]
