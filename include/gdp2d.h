@@ -211,6 +211,46 @@ gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *r
                             const gdp_params *params, int32_t count, gdp_mesh **outs, gdp_status *status,
                             double *elapsed_ms);
 
+/* ---- Serving form ----------------------------------------------------------
+   A server refines meshing jobs as they arrive, with continuous batching:
+   arrived jobs are admitted while there is a free slot and room in the
+   server's device memory (each job's region is sized from its initial CDT),
+   every admitted job advances a few rounds per launch of the single-workgroup
+   engine alongside the others, and finished jobs leave, freeing their slot.
+   Each result is bit-identical to gdp_refine on the same input.  A job that
+   outgrows its region is refined again on its own.  Latency is measured from
+   arrival (after Line 1, which runs in the caller's thread at prepare). */
+typedef struct gdp_server gdp_server;
+
+typedef struct {
+  double submit_ms;  /* arrival, ms since the server was created */
+  double admit_ms;   /* admission into a slot */
+  double done_ms;    /* completion */
+} gdp_job_times;
+
+/* hbm_budget: bytes of device memory for job regions; max_slots: jobs on the
+   device at once.  A worker thread of the library drives the device. */
+gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out);
+/* Line 1 for a job (host) without letting it arrive; *job identifies it. */
+gdp_status gdp_server_prepare(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq,
+                              const gdp_params *params, uint64_t *job);
+/* The prepared job arrives: it is queued for admission (first come, first served). */
+gdp_status gdp_server_arrive(gdp_server *srv, uint64_t job);
+/* gdp_server_prepare followed by gdp_server_arrive. */
+gdp_status gdp_server_submit(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq,
+                             const gdp_params *params, uint64_t *job);
+/* GDP_E_BUSY while the job is not finished (*out = NULL).  Once finished the
+   job's status is returned, *out receives its mesh (the caller owns it and
+   frees it with gdp_mesh_free; NULL on error) and the job id is released.
+   *times (optional) is filled either way. */
+gdp_status gdp_server_poll(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp_job_times *times);
+/* gdp_server_poll that blocks until the job has finished (a prepared job
+   must still arrive; GDP_E_BUSY if the server is being destroyed first). */
+gdp_status gdp_server_wait(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp_job_times *times);
+/* Finishes every job that has arrived, frees the jobs nobody took, stops the
+   worker.  Meshes already handed out stay valid. */
+void gdp_server_destroy(gdp_server *srv);
+
 /* Copies the state of src (vertices, triangles, subsegments, counters) into
    dst on the device, growing dst only if it is too small; both meshes must
    belong to ctx.  Used to restart refinement from a resident initial CDT. */

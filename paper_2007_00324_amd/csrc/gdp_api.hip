@@ -3,7 +3,13 @@
 // (Algorithm 1, "repeat ... until L is empty").
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,7 +31,15 @@ struct gdp_ctx {
 struct gdp_arena {
   void *base = nullptr;
   int refs = 0;
+  std::function<void()> release;  // set: the memory is a server job region, handed back on release
 };
+
+void arena_release(gdp_arena *a) {
+  if (--a->refs > 0) return;
+  if (a->release) a->release();
+  else if (a->base) (void)hipFree(a->base);
+  delete a;
+}
 
 struct gdp_mesh {
   gdp_ctx *ctx = nullptr;
@@ -167,9 +181,17 @@ hipError_t dgrow(T **p, size_t old_n, size_t new_n, size_t keep_n, int fill, hip
 
 inline int words(int n) { return n / 32 + 1; }
 
+// A mesh whose arrays live in a batch or server region moves them into
+// allocations of its own before any of them grows (defined below).
+gdp_status detach(gdp_mesh *M);
+
 gdp_status grow_tri(gdp_mesh *M, int32_t need) {
   gdp_ctx *ctx = M->ctx;
   if (need <= M->m.capT) return GDP_OK;
+  if (M->arena) {
+    gdp_status d = detach(M);
+    if (d != GDP_OK) return d;
+  }
   hipStream_t s = ctx->stream;
   int32_t oc = M->m.capT;
   int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
@@ -202,6 +224,10 @@ gdp_status grow_tri(gdp_mesh *M, int32_t need) {
 gdp_status grow_seg(gdp_mesh *M, int32_t need) {
   gdp_ctx *ctx = M->ctx;
   if (need <= M->m.capS) return GDP_OK;
+  if (M->arena) {
+    gdp_status d = detach(M);
+    if (d != GDP_OK) return d;
+  }
   hipStream_t s = ctx->stream;
   int32_t oc = M->m.capS;
   int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
@@ -232,6 +258,10 @@ gdp_status grow_seg(gdp_mesh *M, int32_t need) {
 gdp_status grow_vtx(gdp_mesh *M, int32_t need) {
   gdp_ctx *ctx = M->ctx;
   if (need <= M->m.capV) return GDP_OK;
+  if (M->arena) {
+    gdp_status d = detach(M);
+    if (d != GDP_OK) return d;
+  }
   hipStream_t s = ctx->stream;
   int32_t oc = M->m.capV;
   int64_t nc64 = std::max<int64_t>(need, (int64_t)oc + oc / 2 + 1024);
@@ -249,6 +279,10 @@ gdp_status grow_cand(gdp_mesh *M) {
   hipStream_t s = ctx->stream;
   int64_t need = (int64_t)M->m.capT + 2 * (int64_t)M->m.capS + 2;
   if (need <= M->wT) return GDP_OK;
+  if (M->arena) {
+    gdp_status d = detach(M);
+    if (d != GDP_OK) return d;
+  }
   int64_t nc = std::max<int64_t>(need, (int64_t)M->wT + M->wT / 2);
   // called between k_winners and k_record: keep what is already written
   size_t keep = (size_t)M->wT;
@@ -359,10 +393,7 @@ void free_extras(gdp_mesh *M);
 void free_mesh_arrays(gdp_mesh *M) {
   if (M->arena) {
     free_extras(M);
-    if (--M->arena->refs == 0) {
-      (void)hipFree(M->arena->base);
-      delete M->arena;
-    }
+    arena_release(M->arena);
     M->arena = nullptr;
     return;
   }
@@ -408,7 +439,14 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
   };
   M->m.nV = nV; M->m.nT = nT; M->m.nS = nS;
   M->m.n_input_v = nIV; M->m.n_input_s = nIS; M->m.rounds = rounds;
-  int32_t capV = std::max(1024, nV * 2), capT = std::max(2048, nT * 2), capS = std::max(1024, nS * 2);
+  // room for the refined mesh from the start (about 2.5x the input vertices
+  // at B = sqrt(2)): growing later costs allocations, copies and a device
+  // synchronisation per array
+  const int64_t cV = std::max<int64_t>(3 * (int64_t)nV + 1024, nV);
+  const int64_t cT = std::max<int64_t>(2 * cV + 2048, nT);
+  const int64_t cS = std::max<int64_t>(16 * (int64_t)nS + 1024, nS);
+  if (cT > (1 << 29) || cS > (1 << 28)) return fail(ctx, GDP_E_NOMEM, "mesh too large");
+  int32_t capV = (int32_t)cV, capT = (int32_t)cT, capS = (int32_t)cS;
   std::vector<double2> hv(nV);
   for (int i = 0; i < nV; i++) hv[i] = make_double2(xy[2 * i], xy[2 * i + 1]);
   std::vector<int4> htv(nT), htn(nT), hts(nT);
@@ -447,7 +485,7 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
       !chk(hipMemcpyAsync(M->m.spend, hpend.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload"))
     return bail(GDP_E_DEVICE);
   if ((st = alloc_control(M)) != GDP_OK) return bail(st);
-  M->pool_cap = std::max(1 << 16, 8 * capT);
+  M->pool_cap = std::max(1 << 16, 2 * capT + 65536);
   if (!chk(dalloc(&M->pool, M->pool_cap), "alloc")) return bail(GDP_E_DEVICE);
   M->fan_cap = std::max(1 << 16, 2 * capT);
   if (!chk(dalloc(&M->fan, M->fan_cap), "alloc")) return bail(GDP_E_DEVICE);
@@ -471,12 +509,14 @@ gdp_status grow_after_abort(gdp_mesh *M, const DevCounters &c, int keep_fan) {
   if (c.err & kErrPool) {
     int64_t nc = std::max<int64_t>((int64_t)c.pool_used * 2, (int64_t)M->pool_cap * 2);
     if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+    if (M->arena && (st = detach(M))) return st;
     HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
     M->pool_cap = (int32_t)nc;
   }
   int64_t fan_need = (int64_t)std::max(c.pool_used, M->pool_cap) + 2 * (int64_t)nwin + 1024;
   if (fan_need > M->fan_cap) {
     if (fan_need > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "fan buffer limit exceeded");
+    if (M->arena && (st = detach(M))) return st;
     HIPCHECK(dgrow(&M->fan, M->fan_cap, fan_need, keep_fan, 0, ctx->stream));
     M->fan_cap = (int32_t)fan_need;
   }
@@ -667,6 +707,7 @@ gdp_status reserve_group(gdp_mesh *M, int64_t last_cand, int R) {
   if (pool_need > M->pool_cap) {
     int64_t nc = std::max<int64_t>(pool_need, (int64_t)M->pool_cap * 3 / 2);
     if (nc > (1LL << 30)) return fail(ctx, GDP_E_NOMEM, "cavity pool limit exceeded");
+    if (M->arena && (st = detach(M))) return st;
     HIPCHECK(dgrow(&M->pool, M->pool_cap, nc, 0, 0, ctx->stream));
     M->pool_cap = (int32_t)nc;
   }
@@ -877,10 +918,7 @@ gdp_status detach(gdp_mesh *M) {
   }
   HIPCHECK(hipStreamSynchronize(s));
   for (size_t i = 0; i < slot.size(); i++) *slot[i] = fresh[i];
-  if (--M->arena->refs == 0) {
-    (void)hipFree(M->arena->base);
-    delete M->arena;
-  }
+  arena_release(M->arena);
   M->arena = nullptr;
   return alloc_host_mirrors(M);
 }
@@ -1139,6 +1177,274 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
       mesh[k] = nullptr;
     }
   }
+  return GDP_OK;
+}
+
+// ---- serving form: continuous batching over the single-workgroup engine ----
+// Device memory of a server: one allocation split into job regions by a
+// first-fit allocator; it is freed once the server is gone and every region
+// (held by a finished mesh the caller still owns) has come back.
+struct ServerMem {
+  void *base = nullptr;
+  size_t size = 0;
+  std::mutex mu;
+  std::map<size_t, size_t> free_ranges;  // offset -> length
+  int live = 0;
+  bool closed = false;
+
+  bool take(size_t n, size_t *off) {
+    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      size_t rest = it->second - n, o = it->first + n;
+      free_ranges.erase(it);
+      if (rest) free_ranges[o] = rest;
+      live++;
+      return true;
+    }
+    return false;
+  }
+  // returns true when the whole allocation can go
+  bool give(size_t off, size_t n) {
+    auto nx = free_ranges.lower_bound(off);
+    if (nx != free_ranges.end() && off + n == nx->first) {
+      n += nx->second;
+      free_ranges.erase(nx);
+    }
+    auto pv = free_ranges.lower_bound(off);
+    if (pv != free_ranges.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        n += pv->second;
+        free_ranges.erase(pv);
+      }
+    }
+    free_ranges[off] = n;
+    return --live == 0 && closed;
+  }
+};
+
+void server_mem_release(ServerMem *sm, size_t off, size_t n) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> g(sm->mu);
+    last = sm->give(off, n);
+  }
+  if (last) {
+    (void)hipFree(sm->base);
+    delete sm;
+  }
+}
+
+struct Job {
+  uint64_t id = 0;
+  std::vector<double> xy;    // the input, kept for a fallback refinement on its own
+  std::vector<int32_t> seg;
+  HostMesh hm;               // Line 1 output
+  std::vector<int4> tv, tn, ts;
+  double B2 = 2.0;
+  gdp_params P;
+  Caps caps;
+  size_t bytes = 0, off = 0;
+  gdp_mesh *mesh = nullptr;
+  enum { PREPARED, QUEUED, ACTIVE, DONE } state = PREPARED;
+  gdp_status status = GDP_OK;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+// One worker per slot: its own stream (so that the jobs of different slots
+// overlap on the device) and pinned mirrors lent to the mesh it refines.
+struct ServerWorker {
+  gdp_ctx ctx;
+  DevCounters *h_cnt = nullptr;
+  DevState *h_st = nullptr;
+  DevCounters *h_hist = nullptr;
+  std::thread th;
+};
+
+struct gdp_server {
+  gdp_ctx *user = nullptr;  // the caller's context: finished meshes are handed over to it
+  ServerMem *mem = nullptr;
+  int max_slots = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<uint64_t, Job *> jobs;
+  std::deque<Job *> queue;
+  int running = 0;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::vector<ServerWorker *> workers;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+
+// Places a prepared job in its region and uploads its initial mesh.
+gdp_status admit_job(gdp_server *S, Job *J, gdp_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  gdp_mesh *M = new gdp_mesh();
+  M->ctx = ctx;
+  gdp_arena *a = new gdp_arena();
+  ServerMem *sm = S->mem;
+  const size_t off = J->off, n = J->bytes;
+  a->base = (char *)sm->base + off;
+  a->refs = 1;
+  a->release = [sm, off, n]() { server_mem_release(sm, off, n); };
+  M->arena = a;
+  char *p = (char *)a->base;
+  std::vector<std::pair<size_t, std::pair<size_t, int>>> fills;
+  size_t run = 0;
+  for_each_array(M, J->caps, [&](void **pp, size_t es, int64_t len, int fill) {
+    size_t b = align256(es * (size_t)std::max<int64_t>(len, 1));
+    *pp = p + run;
+    if (fill) fills.push_back({run, {b, fill}});
+    run += b;
+  });
+  const HostMesh &h = J->hm;
+  const Caps &c = J->caps;
+  M->m.capV = (int32_t)c.V; M->m.capT = (int32_t)c.T; M->m.capS = (int32_t)c.S;
+  M->m.nV = h.nV; M->m.nT = h.nT; M->m.nS = h.nS;
+  M->m.n_input_v = h.nV; M->m.n_input_s = h.nS;
+  M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
+  M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
+  J->mesh = M;
+  DevState ds;
+  memset(&ds, 0, sizeof ds);
+  ds.nV = h.nV; ds.nT = h.nT; ds.nS = h.nS;
+  ds.wT = words(h.nT); ds.wS = words(h.nS);
+  ds.full = 1;
+  HIPCHECK(hipMemsetAsync(p, 0, run, st));
+  for (auto &f : fills) HIPCHECK(hipMemsetAsync(p + f.first, f.second.second, f.second.first, st));
+  HIPCHECK(hipMemcpyAsync(M->m.vxy, h.xy.data(), sizeof(double) * 2 * h.nV, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(M->m.tv, J->tv.data(), sizeof(int4) * h.nT, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(M->m.tn, J->tn.data(), sizeof(int4) * h.nT, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(M->m.ts, J->ts.data(), sizeof(int4) * h.nT, hipMemcpyHostToDevice, st));
+  if (h.nS) {
+    HIPCHECK(hipMemcpyAsync(M->m.sv, h.sv.data(), sizeof(int32_t) * 2 * h.nS, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(M->m.spar, h.sparent.data(), sizeof(int32_t) * h.nS, hipMemcpyHostToDevice, st));
+  }
+  HIPCHECK(hipMemcpyAsync(M->d_st, &ds, sizeof ds, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));  // the host arrays above are pageable
+  return GDP_OK;
+}
+
+gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P);
+
+void complete_job(gdp_server *S, Job *J, gdp_status st) {
+  std::lock_guard<std::mutex> g(S->mu);
+  J->status = st;
+  J->t_done = ms_since(S->t0);
+  J->state = Job::DONE;
+  S->running--;
+  S->cv.notify_all();
+}
+
+// A worker: takes the oldest arrived job once its region fits, uploads it,
+// refines it to the end on its own stream (the plain refinement, whose
+// small final rounds run in the single-workgroup engine), hands it over.
+void server_worker(gdp_server *S, ServerWorker *W) {
+  (void)hipSetDevice(W->ctx.device);
+  for (;;) {
+    Job *J = nullptr;
+    {
+      std::unique_lock<std::mutex> g(S->mu);
+      for (;;) {
+        if (!S->queue.empty()) {
+          Job *Q = S->queue.front();
+          size_t off;
+          bool got;
+          {
+            std::lock_guard<std::mutex> gm(S->mem->mu);
+            got = S->mem->take(Q->bytes, &off);
+          }
+          if (got) {
+            Q->off = off;
+            S->queue.pop_front();
+            Q->state = Job::ACTIVE;
+            Q->t_admit = ms_since(S->t0);
+            S->running++;
+            J = Q;
+            break;
+          }
+          if (S->stop && S->running == 0) {
+            // closing, and the room is held by meshes the caller owns
+            for (Job *R : S->queue) {
+              R->status = GDP_E_NOMEM;
+              R->t_done = ms_since(S->t0);
+              R->state = Job::DONE;
+            }
+            S->queue.clear();
+            S->cv.notify_all();
+          }
+        }
+        if (S->stop && S->queue.empty()) return;
+        // first come, first served: wait for an arrival or for room
+        S->cv.wait_for(g, std::chrono::milliseconds(2));
+      }
+    }
+    gdp_status st = admit_job(S, J, &W->ctx);
+    gdp_mesh *M = J->mesh;
+    if (st == GDP_OK) {
+      M->h_cnt = W->h_cnt;
+      M->h_st = W->h_st;
+      M->h_hist = W->h_hist;
+      st = refine_loop(M, J->B2, &J->P);
+      M->h_cnt = nullptr;  // give the lent mirrors back; a mesh that left its region gets its own
+      M->h_st = nullptr;
+      M->h_hist = nullptr;
+      if (!M->arena && st == GDP_OK) st = alloc_host_mirrors(M);
+    }
+    if (st != GDP_OK && st != GDP_E_NOTERM && M) {
+      gdp_mesh_free(M);
+      J->mesh = nullptr;
+    }
+    complete_job(S, J, st);
+  }
+}
+
+// Line 1 on the host and everything a job needs before it arrives.
+gdp_status prepare_job(gdp_server *S, const gdp_pslg *pslg, double B2, const gdp_params *P, Job *J) {
+  gdp_ctx *ctx = S->user;
+  J->B2 = B2;
+  J->P = *P;
+  // a host synchronisation per round: the other slots keep the device busy
+  if (J->P.rounds_per_sync == 0) J->P.rounds_per_sync = 1;
+  J->xy.assign(pslg->xy, pslg->xy + 2 * (size_t)pslg->n_vertices);
+  J->seg.assign(pslg->seg, pslg->seg + 2 * (size_t)pslg->n_segments);
+  std::string e;
+  int rc = host_cdt_build(pslg->n_vertices, pslg->xy, pslg->n_segments, pslg->seg, J->hm, e);
+  if (rc != GDP_OK) return fail(ctx, (gdp_status)rc, e);
+  const HostMesh &h = J->hm;
+  J->tv.resize(h.nT);
+  J->tn.resize(h.nT);
+  J->ts.resize(h.nT);
+  for (int32_t t = 0; t < h.nT; t++) {
+    int w = (h.ts[3 * t] >= 0 ? 1 : 0) | (h.ts[3 * t + 1] >= 0 ? 2 : 0) | (h.ts[3 * t + 2] >= 0 ? 4 : 0);
+    J->tv[t] = make_int4(h.tv[3 * t], h.tv[3 * t + 1], h.tv[3 * t + 2], w);
+    J->tn[t] = make_int4(h.tn[3 * t], h.tn[3 * t + 1], h.tn[3 * t + 2], 0);
+    J->ts[t] = make_int4(h.ts[3 * t], h.ts[3 * t + 1], h.ts[3 * t + 2], 0);
+  }
+  Caps c;
+  c.V = 3 * (int64_t)h.nV + 256;
+  c.T = std::max<int64_t>(2 * c.V + 256, h.nT);
+  c.S = 16 * (int64_t)h.nS + 64;
+  c.W = c.T + 2 * c.S + 2;
+  c.tiles = c.W / kScanTileSize + 2;
+  c.pool = 2 * c.T + 4096;
+  c.fan = 2 * c.T + 4096;
+  J->caps = c;
+  gdp_mesh tmp;
+  size_t b = 0;
+  for_each_array(&tmp, c, [&](void **, size_t es, int64_t len, int) { b += align256(es * (size_t)std::max<int64_t>(len, 1)); });
+  J->bytes = b;
+  if (b > S->mem->size) return fail(ctx, GDP_E_NOMEM, "job larger than the server's memory budget");
   return GDP_OK;
 }
 
@@ -1641,4 +1947,148 @@ void gdp_mesh_free(gdp_mesh *mesh) {
   delete mesh;
 }
 
+
+gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out) {
+  if (!ctx || !out || max_slots < 1 || hbm_budget < (1u << 20)) return GDP_E_ARG;
+  *out = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  gdp_server *S = new gdp_server();
+  S->user = ctx;
+  S->max_slots = max_slots;
+  S->t0 = std::chrono::steady_clock::now();
+  S->mem = new ServerMem();
+  S->mem->size = hbm_budget;
+  bool ok = hipMalloc(&S->mem->base, hbm_budget) == hipSuccess;
+  if (ok) S->mem->free_ranges[0] = hbm_budget;
+  for (int i = 0; ok && i < max_slots; i++) {
+    ServerWorker *W = new ServerWorker();
+    W->ctx.device = ctx->device;
+    S->workers.push_back(W);
+    ok = hipStreamCreateWithFlags(&W->ctx.stream, hipStreamNonBlocking) == hipSuccess &&
+         hipHostMalloc((void **)&W->h_cnt, sizeof(DevCounters)) == hipSuccess &&
+         hipHostMalloc((void **)&W->h_st, sizeof(DevState)) == hipSuccess &&
+         hipHostMalloc((void **)&W->h_hist, sizeof(DevCounters) * kHistCap) == hipSuccess;
+  }
+  if (!ok) {
+    for (ServerWorker *W : S->workers) {
+      if (W->ctx.stream) (void)hipStreamDestroy(W->ctx.stream);
+      if (W->h_cnt) (void)hipHostFree(W->h_cnt);
+      if (W->h_st) (void)hipHostFree(W->h_st);
+      if (W->h_hist) (void)hipHostFree(W->h_hist);
+      delete W;
+    }
+    if (S->mem->base) (void)hipFree(S->mem->base);
+    delete S->mem;
+    delete S;
+    return fail(ctx, GDP_E_NOMEM, "server allocation failed");
+  }
+  for (ServerWorker *W : S->workers) W->th = std::thread(server_worker, S, W);
+  *out = S;
+  return GDP_OK;
+}
+
+gdp_status gdp_server_prepare(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq, const gdp_params *params,
+                              uint64_t *job) {
+  if (!srv || !pslg || !job) return GDP_E_ARG;
+  gdp_params P;
+  gdp_status st;
+  if ((st = check_params(srv->user, params, P))) return st;
+  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(srv->user, GDP_E_ARG, "bad ratio bound");
+  Job *J = new Job();
+  if ((st = prepare_job(srv, pslg, ratio_bound_sq, &P, J))) {
+    delete J;
+    return st;
+  }
+  std::lock_guard<std::mutex> g(srv->mu);
+  J->id = srv->next_id++;
+  srv->jobs[J->id] = J;
+  *job = J->id;
+  return GDP_OK;
+}
+
+gdp_status gdp_server_arrive(gdp_server *srv, uint64_t job) {
+  if (!srv) return GDP_E_ARG;
+  std::lock_guard<std::mutex> g(srv->mu);
+  auto it = srv->jobs.find(job);
+  if (it == srv->jobs.end() || it->second->state != Job::PREPARED) return GDP_E_ARG;
+  Job *J = it->second;
+  J->state = Job::QUEUED;
+  J->t_submit = ms_since(srv->t0);
+  srv->queue.push_back(J);
+  srv->cv.notify_all();
+  return GDP_OK;
+}
+
+gdp_status gdp_server_submit(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq, const gdp_params *params,
+                             uint64_t *job) {
+  gdp_status st = gdp_server_prepare(srv, pslg, ratio_bound_sq, params, job);
+  if (st != GDP_OK) return st;
+  return gdp_server_arrive(srv, *job);
+}
+
+static gdp_status server_take(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp_job_times *times, bool wait) {
+  if (!srv) return GDP_E_ARG;
+  if (out) *out = nullptr;
+  std::unique_lock<std::mutex> g(srv->mu);
+  auto it = srv->jobs.find(job);
+  if (it == srv->jobs.end()) return GDP_E_ARG;
+  Job *J = it->second;
+  if (wait) srv->cv.wait(g, [&] { return J->state == Job::DONE || srv->stop; });
+  if (times) {
+    times->submit_ms = J->t_submit;
+    times->admit_ms = J->t_admit;
+    times->done_ms = J->t_done;
+  }
+  if (J->state != Job::DONE) return GDP_E_BUSY;
+  gdp_status st = J->status;
+  if (J->mesh) {
+    J->mesh->ctx = srv->user;
+    if (out) *out = J->mesh;
+    else gdp_mesh_free(J->mesh);
+  }
+  srv->jobs.erase(it);
+  delete J;
+  return st;
+}
+
+gdp_status gdp_server_poll(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp_job_times *times) {
+  return server_take(srv, job, out, times, false);
+}
+
+gdp_status gdp_server_wait(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp_job_times *times) {
+  return server_take(srv, job, out, times, true);
+}
+
+void gdp_server_destroy(gdp_server *srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->stop = true;
+    srv->cv.notify_all();
+  }
+  for (ServerWorker *W : srv->workers) W->th.join();
+  for (auto &kv : srv->jobs) {
+    if (kv.second->mesh) gdp_mesh_free(kv.second->mesh);
+    delete kv.second;
+  }
+  for (ServerWorker *W : srv->workers) {
+    (void)hipStreamDestroy(W->ctx.stream);
+    (void)hipHostFree(W->h_cnt);
+    (void)hipHostFree(W->h_st);
+    (void)hipHostFree(W->h_hist);
+    delete W;
+  }
+  ServerMem *sm = srv->mem;
+  bool last;
+  {
+    std::lock_guard<std::mutex> g(sm->mu);
+    sm->closed = true;
+    last = sm->live == 0;
+  }
+  if (last) {
+    (void)hipFree(sm->base);
+    delete sm;
+  }
+  delete srv;
+}
 }  // extern "C"

@@ -680,13 +680,14 @@ __device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, in
   return r;
 }
 
-constexpr int kCap = 24;      // per-thread cavity capacity
+constexpr int kCap = 24;      // per-thread cavity capacity of the grid kernel
 constexpr int kCavBlock = 128;
 
-// Grows the cavity of p from the seeds into lds[j * kCavBlock + tid].
-// Returns the size, or -1 if it exceeds kCap.
-__device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls, int tid, const int *seeds, int nseeds,
-                          double2 p) {
+// Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
+// cap entries).  Returns the size, or -1 if it exceeds cap (the cavity then
+// goes to the cooperative path; the set of triangles is the same).
+__device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls, int cap, int tid, const int *seeds,
+                                          int nseeds, double2 p) {
   int len = 0;
   for (int s = 0; s < nseeds; s++) {
     bool dup = false;
@@ -706,7 +707,7 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls
         if (lds[q * ls + tid] == o) { in = true; break; }
       if (in) continue;
       if (incircle_tri(m, m.tv[o], p) > 0) {
-        if (len == kCap) return -1;
+        if (len == cap) return -1;
         lds[(len++) * ls + tid] = o;
       }
     }
@@ -733,7 +734,8 @@ struct CavRes {
   int enc_reject, fan_invalid, unsplittable, mid_cand;
 };
 
-__device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int tid, int ci, int is_cc) {
+__device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
+                                             int ci, int is_cc) {
   CavRes res{0, 0, 0, 0, 0, 0, 0};
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
@@ -765,7 +767,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
     expect = nseeds == 2 ? 2 : 1;
     S.state[ci] = st | kStFound;
   }
-  int len = grow_local(m, lds, ls, tid, seeds, nseeds, p);
+  int len = grow_local(m, lds, ls, cap, tid, seeds, nseeds, p);
   if (len < 0) {
     S.state[ci] = st | kStBig | kStFound;
     int q = atomicAdd(&w.cnt->nbig, 1);
@@ -789,19 +791,21 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
   return res;
 }
 
-// Per-thread cavities of one class (lds: kCap slices of blockDim.x entries).
+// Per-thread cavities of one class (lds: cap slices of ls entries; the
+// threads tid < ls take part).
 // The midpoint list is final when this runs for midpoints (they are flagged
 // only by the scan, the walk and the circumcenter cavities), so its length
 // is read from device memory.  The loop is uniform over the workgroup so
 // that pool space and statistics are handled once per wave.
-__device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int is_cc, int32_t *lds, const Lanes &L) {
-  const int tid = threadIdx.x, ls = blockDim.x;
+__device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int is_cc, int32_t *lds, int ls, int cap,
+                                            const Lanes &L) {
+  const int tid = threadIdx.x;
   const int n = is_cc ? w.cnt->ncc : w.cnt->nmk;
   CandSet S = is_cc ? w.cc : w.mid;
   for (int base = L.base0; base < n; base += L.stride) {
     int ci = base + tid;
     CavRes r{0, 0, 0, 0, 0, 0, 0};
-    if (ci < n) r = cavity_one(m, w, lds, ls, tid, ci, is_cc);
+    if (ci < n) r = cavity_one(m, w, lds, ls, cap, tid, ci, is_cc);
     int off = wave_alloc(&w.cnt->pool_used, r.alive ? r.len : 0);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
     if (r.alive) {
@@ -844,7 +848,7 @@ template <int IS_CC>
 __global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w) {
   __shared__ int32_t lds[kCap * kCavBlock];
   if (w.st->halt) return;
-  cavity_part(m, w, IS_CC, lds, grid_lanes());
+  cavity_part(m, w, IS_CC, lds, kCavBlock, kCap, grid_lanes());
 }
 template __global__ void k_cavity<0>(DevMesh m, Work w);
 template __global__ void k_cavity<1>(DevMesh m, Work w);
@@ -1672,9 +1676,15 @@ __device__ void engine_big(const DevMesh &m, const Work &w, BigShared &sh, int p
   }
 }
 
-constexpr int kEngLdsWords = (kCap * kEngBlock > (int)(sizeof(BigShared) / 4)) ? kCap * kEngBlock
-                                                                               : (int)(sizeof(BigShared) / 4);
-static_assert(kApproxMax <= kCap, "prefilter slices fit in the cavity slices");
+// The engine's per-thread cavities: half the workgroup, with slices twice as
+// long as the grid kernel's (large cavities are common in small meshes with
+// clustered points, and the cooperative path runs them one at a time here).
+constexpr int kEngCavThreads = kEngBlock / 2;
+constexpr int kEngCap = 48;
+constexpr int kEngLdsWords = (kEngCap * kEngCavThreads > (int)(sizeof(BigShared) / 4)) ? kEngCap * kEngCavThreads
+                                                                                     : (int)(sizeof(BigShared) / 4);
+static_assert(kApproxMax * kEngBlock <= kEngLdsWords, "prefilter slices fit in the engine's LDS");
+static_assert(2 * kEngRankMax <= kEngLdsWords, "winner keys fit in the engine's LDS");
 
 // Rounds of one mesh until it halts or round_limit rounds have completed.
 __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
@@ -1728,11 +1738,12 @@ __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
       }
     // R5/R6 cavities with their marks
     BigShared &sh = *reinterpret_cast<BigShared *>(lds);
-    cavity_part(m, w, 1, lds, L);
+    const Lanes LC{0, kEngCavThreads};
+    if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 1, lds, kEngCavThreads, kEngCap, LC);
     phase_sync();
     engine_big(m, w, sh, 0);
     phase_sync();
-    cavity_part(m, w, 0, lds, L);
+    if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 0, lds, kEngCavThreads, kEngCap, LC);
     phase_sync();
     engine_big(m, w, sh, 1);
     phase_sync();

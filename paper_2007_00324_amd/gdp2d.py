@@ -32,6 +32,10 @@ class gdp_pslg(C.Structure):
                 ("n_segments", C.c_int32), ("seg", C.POINTER(C.c_int32))]
 
 
+class gdp_job_times(C.Structure):
+    _fields_ = [("submit_ms", C.c_double), ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+
+
 class gdp_params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
@@ -96,6 +100,13 @@ def load() -> C.CDLL:
         "gdp_mesh_free": (None, [_VP]),
         "gdp_refine_batch": (S, [_VP, C.POINTER(gdp_pslg), _PD, C.POINTER(gdp_params), C.c_int32, C.POINTER(_VP),
                                  C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+        "gdp_server_create": (S, [_VP, C.c_size_t, C.c_int32, C.POINTER(_VP)]),
+        "gdp_server_prepare": (S, [_VP, C.POINTER(gdp_pslg), C.c_double, C.POINTER(gdp_params), C.POINTER(C.c_uint64)]),
+        "gdp_server_arrive": (S, [_VP, C.c_uint64]),
+        "gdp_server_submit": (S, [_VP, C.POINTER(gdp_pslg), C.c_double, C.POINTER(gdp_params), C.POINTER(C.c_uint64)]),
+        "gdp_server_poll": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
+        "gdp_server_wait": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
+        "gdp_server_destroy": (None, [_VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -109,7 +120,9 @@ def exported_symbols() -> list[str]:
     return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
             "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
             "gdp_mesh_info_get", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
-            "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch"]
+            "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
+            "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
+            "gdp_server_wait", "gdp_server_destroy"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -313,6 +326,62 @@ def gdp_refine_batch(ctx: Context, inputs, ratio_bound_sq, params: gdp_params | 
     ctx.check(load().gdp_refine_batch(ctx._h, arr, _ptr(bsq, C.c_double), C.byref(prm), n, outs, st, C.byref(ms)))
     meshes = [Mesh(ctx, _VP(outs[i])) if outs[i] else None for i in range(n)]
     return meshes, [int(st[i]) for i in range(n)], ms.value
+
+
+GDP_E_BUSY = -7
+
+
+class Server:
+    """Serving form: jobs arrive while others run; each finished job yields a
+    device-resident Mesh."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int):
+        self.ctx = ctx
+        self._h = _VP()
+        ctx.check(load().gdp_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(self._h)))
+
+    def prepare(self, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> int:
+        p, keep = _pslg(xy, seg)
+        prm = params if params is not None else make_params()
+        job = C.c_uint64(0)
+        self.ctx.check(load().gdp_server_prepare(self._h, C.byref(p), float(ratio_bound_sq), C.byref(prm),
+                                                 C.byref(job)))
+        return job.value
+
+    def arrive(self, job: int) -> None:
+        self.ctx.check(load().gdp_server_arrive(self._h, C.c_uint64(job)))
+
+    def submit(self, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> int:
+        job = self.prepare(xy, seg, ratio_bound_sq, params)
+        self.arrive(job)
+        return job
+
+    def _take(self, fn, job: int):
+        h = _VP()
+        t = gdp_job_times()
+        rc = fn(self._h, C.c_uint64(job), C.byref(h), C.byref(t))
+        times = {"submit_ms": t.submit_ms, "admit_ms": t.admit_ms, "done_ms": t.done_ms}
+        if rc == GDP_E_BUSY:
+            return None, rc, times
+        return (Mesh(self.ctx, h) if h.value else None), rc, times
+
+    def poll(self, job: int):
+        """(mesh or None, status, times); status GDP_E_BUSY while pending."""
+        return self._take(load().gdp_server_poll, job)
+
+    def wait(self, job: int):
+        return self._take(load().gdp_server_wait, job)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gdp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gdp_refine(ctx: Context, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> Mesh:

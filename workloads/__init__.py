@@ -18,4 +18,7 @@ from .generators import (  # noqa: F401
     batch_plan,
     batch_instance,
     batch_config3,
+    serving_plan,
+    serving_job,
+    serving_jobs,
 )

@@ -416,3 +416,35 @@ def batch_config3(count: int = 4096, seed: int = 3, n_min: int = 100, n_max: int
         with mp.get_context("fork").Pool(workers) as pool:
             return pool.map(_batch_instance_args, args, chunksize=8)
     return [batch_instance(*a) for a in args]
+
+
+# ---- serving form (a stream of jobs of mixed sizes) --------------------------
+def serving_plan(count: int, seed: int = 4, n_min: int = 1_000, n_max: int = 200_000):
+    """Sizes (log-uniform), bounds and per-job seeds of a job stream."""
+    rng = _rng(seed)
+    n = np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=count))).astype(np.int64)
+    bsq = rng.choice(np.array(BATCH_BOUNDS_SQ), size=count)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return n, bsq, seeds
+
+
+def serving_job(n: int, bsq: float, seed: int) -> PSLG:
+    """One job: the 1M-point generator scaled to n points, segments 5% of them."""
+    p = scaled_config1(int(n), max(1, int(round(0.05 * n))), seed=int(seed), bsq=float(bsq))
+    p.name = f"c4_s{int(seed)}_n{int(n)}"
+    return p
+
+
+def _serving_job_args(args):
+    return serving_job(*args)
+
+
+def serving_jobs(count: int, seed: int = 4, n_min: int = 1_000, n_max: int = 200_000,
+                 workers: int = 1) -> list[PSLG]:
+    n, bsq, seeds = serving_plan(count, seed, n_min, n_max)
+    args = list(zip(n.tolist(), bsq.tolist(), seeds.tolist()))
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_serving_job_args, args, chunksize=2)
+    return [serving_job(*a) for a in args]
