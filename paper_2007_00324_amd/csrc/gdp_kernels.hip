@@ -648,30 +648,35 @@ __device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, in
                                  bool is_cc, double2 p) {
   CavCheck r{0, false, false};
   for (int j = 0; j < len; j++) {
-    int t = cav(j);
-    int4 tri = m.tv[t];
-    int4 nb = m.tn[t];
-    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    const int t = cav(j);
+    const int4 tri = m.tv[t];
+    const int4 nb = m.tn[t];
+    const int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    bool bnd[3];
+    int sid[3];
     for (int e = 0; e < 3; e++) {
-      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
-      if (skip_k >= 0 && sid == skip_k) continue;
-      int o = comp(nb, e);
-      if (sid < 0 && o >= 0) {
+      sid[e] = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      bnd[e] = !(skip_k >= 0 && sid[e] == skip_k);
+      const int o = comp(nb, e);
+      if (bnd[e] && sid[e] < 0 && o >= 0) {
         // internal iff o is in the cavity (binary search on the sorted list)
         int lo = 0, hi = len - 1;
-        bool in = false;
         while (lo <= hi) {
           int mid = (lo + hi) >> 1;
           int x = cav(mid);
-          if (x == o) { in = true; break; }
+          if (x == o) { bnd[e] = false; break; }
           if (x < o) lo = mid + 1; else hi = mid - 1;
         }
-        if (in) continue;
       }
+    }
+    if (!(bnd[0] || bnd[1] || bnd[2])) continue;
+    const double2 P[3] = {m.vxy[tri.x], m.vxy[tri.y], m.vxy[tri.z]};
+    for (int e = 0; e < 3; e++) {
+      if (!bnd[e]) continue;
       r.nbnd++;
-      double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
-      if (is_cc && sid >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
-        flag_mid(w, sid);
+      const double2 U = P[e], V = P[(e + 1) % 3];
+      if (is_cc && sid[e] >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
+        flag_mid(w, sid[e]);
         r.enc = true;
       }
       if (orient_pts(U, V, p) <= 0) r.fan_bad = true;
@@ -695,20 +700,50 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls
     if (!dup) lds[(len++) * ls + tid] = seeds[s];
   }
   for (int h = 0; h < len; h++) {
-    int t = lds[h * ls + tid];
-    int4 tri = m.tv[t];
-    int4 nb = m.tn[t];
+    const int t = lds[h * ls + tid];
+    const int4 tri = m.tv[t];
+    const int4 nb = m.tn[t];
+    // the three neighbours are distinct triangles, so they can be screened
+    // against the list together and then tested in edge order
+    int o[3];
+    bool c[3];
     for (int e = 0; e < 3; e++) {
-      if ((tri.w >> e) & 1) continue;
-      int o = comp(nb, e);
-      if (o < 0) continue;
-      bool in = false;
-      for (int q = 0; q < len; q++)
-        if (lds[q * ls + tid] == o) { in = true; break; }
-      if (in) continue;
-      if (incircle_tri(m, m.tv[o], p) > 0) {
+      o[e] = comp(nb, e);
+      c[e] = !((tri.w >> e) & 1) && o[e] >= 0;
+    }
+    for (int q = 0; q < len; q++) {
+      const int x = lds[q * ls + tid];
+      c[0] = c[0] && x != o[0];
+      c[1] = c[1] && x != o[1];
+      c[2] = c[2] && x != o[2];
+    }
+    if (!(c[0] || c[1] || c[2])) continue;
+    // independent loads: the neighbours' records and this triangle's
+    // vertices; then only the far vertex of each neighbour
+    int4 to[3];
+    for (int e = 0; e < 3; e++) to[e] = c[e] ? m.tv[o[e]] : make_int4(0, 0, 0, 0);
+    const double2 P[3] = {m.vxy[tri.x], m.vxy[tri.y], m.vxy[tri.z]};
+    double2 F[3];
+    int fv[3];
+    for (int e = 0; e < 3; e++) {
+      fv[e] = -1;
+      if (!c[e]) continue;
+      const int u = comp(tri, e), v = comp(tri, (e + 1) % 3);
+      fv[e] = (to[e].x != u && to[e].x != v) ? to[e].x : ((to[e].y != u && to[e].y != v) ? to[e].y : to[e].z);
+      F[e] = m.vxy[fv[e]];
+    }
+    for (int e = 0; e < 3; e++) {
+      if (!c[e]) continue;
+      const int u = comp(tri, e);
+      const double2 Pu = P[e], Pv = P[(e + 1) % 3];
+      // the neighbour's vertices in its own order (the same arguments as a
+      // direct evaluation on its record)
+      const double2 A = to[e].x == fv[e] ? F[e] : (to[e].x == u ? Pu : Pv);
+      const double2 B = to[e].y == fv[e] ? F[e] : (to[e].y == u ? Pu : Pv);
+      const double2 C = to[e].z == fv[e] ? F[e] : (to[e].z == u ? Pu : Pv);
+      if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y) > 0) {
         if (len == cap) return -1;
-        lds[(len++) * ls + tid] = o;
+        lds[(len++) * ls + tid] = o[e];
       }
     }
   }
