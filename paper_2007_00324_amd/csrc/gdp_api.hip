@@ -59,6 +59,7 @@ struct gdp_mesh {
   int32_t *d_head = nullptr;         // the engine's queue head
   DevCounters *d_cnt = nullptr;
   DevCounters *h_cnt = nullptr;  // pinned
+  StatLine *d_stat = nullptr;    // [kStatStripes] statistics of the running round
   uint64_t *mark = nullptr;
   int32_t *sadj = nullptr;
   uint32_t *mflag = nullptr;
@@ -311,6 +312,7 @@ Work make_work(gdp_mesh *M, int pm, int parity) {
   memset(&w, 0, sizeof w);  // no stray padding bytes (graph keys hash the struct)
   w.st = M->d_st;
   w.cnt = M->d_cnt;
+  w.stat = M->d_stat;
   w.hist = M->d_hist;
   w.hist_cap = kHistCap;
   w.mark = M->mark;
@@ -377,11 +379,13 @@ gdp_status alloc_control(gdp_mesh *M) {
   gdp_ctx *ctx = M->ctx;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   if (!ok(dalloc(&M->d_cnt, 1)) || !ok(hipHostMalloc((void **)&M->h_cnt, sizeof(DevCounters))) ||
+      !ok(dalloc(&M->d_stat, kStatStripes)) ||
       !ok(dalloc(&M->d_st, 1)) || !ok(hipHostMalloc((void **)&M->h_st, sizeof(DevState))) ||
       !ok(dalloc(&M->d_hist, kHistCap)) || !ok(hipHostMalloc((void **)&M->h_hist, sizeof(DevCounters) * kHistCap)) ||
       !ok(dalloc(&M->rhist, 256)) || !ok(dalloc(&M->sel, 4)))
     return fail(ctx, GDP_E_NOMEM, "allocation failed");
   HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), ctx->stream));
+  HIPCHECK(hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, ctx->stream));
   HIPCHECK(hipMemsetAsync(M->d_st, 0, sizeof(DevState), ctx->stream));
   HIPCHECK(hipMemsetAsync(M->rhist, 0, 256 * sizeof(int32_t), ctx->stream));
   HIPCHECK(hipMemsetAsync(M->sel, 0, 4 * sizeof(uint64_t), ctx->stream));
@@ -398,7 +402,7 @@ void free_mesh_arrays(gdp_mesh *M) {
     return;
   }
   void *ptrs[] = {M->m.vxy, M->m.vkind, M->m.tv, M->m.tn, M->m.ts, M->m.sv, M->m.spar, M->m.spend,
-                  M->d_cnt, M->mark, M->sadj, M->mflag,
+                  M->d_cnt, M->d_stat, M->mark, M->sadj, M->mflag,
                   M->cc.elem, M->cc.key, M->cc.p, M->cc.loc, M->cc.state, M->cc.off, M->cc.len,
                   M->mid.elem, M->mid.key, M->mid.p, M->mid.loc, M->mid.state, M->mid.off, M->mid.len,
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
@@ -873,6 +877,7 @@ void for_each_array(gdp_mesh *M, const Caps &c, F f) {
   f((void **)&M->tiles_f, 4, c.tiles, 0);
   f((void **)&M->pool, 4, c.pool, 0);
   f((void **)&M->fan, sizeof(FanRec), c.fan, 0);
+  f((void **)&M->d_stat, sizeof(StatLine), kStatStripes, 0);
   f((void **)&M->d_cnt, sizeof(DevCounters), 1, 0);
   f((void **)&M->d_st, sizeof(DevState), 1, 0);
   f((void **)&M->d_hist, sizeof(DevCounters), kHistCap, 0);
@@ -1494,6 +1499,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   hs.serial = M->serial;
   HIPCHECK(hipMemcpyAsync(M->d_st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
+  HIPCHECK(hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s));
   gdp_status result = GDP_OK;
   // The first round of a call tests every element; later rounds carry the
   // previous bad list over and re-test only the slots the last round wrote.
@@ -1599,6 +1605,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
     if (++aborts > 16) return fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
     if ((st = grow_after_abort(M, c, full ? 0 : d.prev_fan))) return st;
     HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
+    HIPCHECK(hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s));
   }
   HIPCHECK(hipEventRecord(ev1, s));
   HIPCHECK(hipEventSynchronize(ev1));

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -40,26 +41,32 @@ struct DevMesh {
   int32_t *spend = nullptr;
 };
 
-// Device counters of one round.
+// Device counters of one round.  Atomics on one 128-byte line are serialised
+// by the memory side (about 12 ns each on MI355X), so the two append counters
+// of the collection sit on different lines and the statistics are summed in
+// striped lines (StatLine) folded in at the end of the round.
 struct DevCounters {
+  // line 0
   int32_t ncc;        // circumcenter candidates (bad triangles kept)
-  int32_t nmk;        // midpoint candidates (flagged subsegments)
-  int32_t n_enc;      // subsegments flagged by the scan (pending or encroached apex)
   int32_t pool_used;  // cavity pool entries allocated
-  int32_t nbig;       // cavities routed to the cooperative path
   int32_t fan_used;   // fan records allocated
+  int32_t n_enc;      // subsegments flagged by the scan (pending or encroached apex)
+  int32_t nbig;       // cavities routed to the cooperative path
   int32_t err;        // error bits (kErr*)
   int32_t nwin_mid, nwin_cc, fresh_total;
   int32_t n_blocked, n_coincident, n_enc_reject, n_unsplittable, n_fan_invalid;
   int32_t n_lost_mark, n_dep_drop;
   int32_t n_kept_mid, n_kept_cc;
   int32_t cav_max;
-  int64_t cav_tri_total;
   int32_t n_mid_cand;  // midpoint candidates that reached the cavity step
+  int64_t cav_tri_total;
   int32_t dbg_set;     // first failing insertion record: set flag
   int32_t dbg[6];      // class, element, cavity size, expected fan size, found fan size, round-local index
   int32_t n_f1_drop, n_f2_drop;
-  int32_t nwin, nwin1;  // winners of the round, and nwin + 1 (scan length)
+  int32_t nwin;        // winners of the round
+  // line 1
+  int32_t nmk;          // midpoint candidates (flagged subsegments)
+  int32_t nwin1;        // nwin + 1 (scan length)
   int32_t abort;        // the round was abandoned before any mesh write (capacity)
   int32_t nmk0;         // midpoint candidates after the collection (R4/R5 add more)
   int32_t fan_total;    // total of the fresh-count scan (fbase[nwin] is what is used)
@@ -68,6 +75,20 @@ struct DevCounters {
   int64_t cav_bnd[2];   // ... and their boundary edges
 };
 static_assert(sizeof(DevCounters) % 8 == 0, "DevCounters is copied as 32-bit words");
+static_assert(offsetof(DevCounters, nmk) == 128, "the midpoint append counter starts the second line");
+
+// Statistics of a round, summed per wave into one of kStatStripes lines (the
+// wave's global index picks the line) and folded into DevCounters at the end
+// of the round, which also clears the lines.
+enum StatField {
+  kStCavTri, kStCavLen0, kStCavLen1, kStCavBnd0, kStCavBnd1, kStEncReject, kStFanInvalid, kStUnsplittable,
+  kStMidCand, kStLostMark, kStDepDrop, kStBlocked, kStCoincident, kStCavMax, kStFields
+};
+struct StatLine {
+  uint64_t v[16];
+};
+static_assert(kStFields <= 16 && sizeof(StatLine) == 128, "one stat line per cache line");
+constexpr int kStatStripes = 64;
 
 // Mesh counts and round control in device memory, so that several rounds
 // can be queued without the host looking at any count in between.

@@ -46,6 +46,7 @@ struct Work {
   int32_t *cidx_s;     // [capS] candidate index of a flagged subsegment
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
   int32_t *rhist;      // [256] digit histogram of the radix select (zero between uses)
+  StatLine *stat;      // [kStatStripes] statistics of the running round
   uint64_t *sel;       // [3] radix select: key prefix, prefix mask, keys still to take
   int32_t pm;
 };

@@ -119,35 +119,8 @@ __device__ SplitPt seg_split(const DevMesh &m, int k, int pm) {
 // ---------------------------------------------------------------------------
 // Small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int wave_append(int *counter, bool pred) {
-  unsigned long long mask = __ballot(pred);
-  if (mask == 0) return -1;
-  int lane = __lane_id();
-  int leader = __ffsll((unsigned long long)mask) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-  base = __shfl(base, leader);
-  return base + __popcll(mask & ((1ull << lane) - 1ull));
-}
-
-// Wave-wide reductions and a variable-size allocation (all 64 lanes must
-// take part): one atomic per wave instead of one per lane, which matters for
-// counters every lane updates.
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-  for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
-  return v;
-}
-
-__device__ __forceinline__ void wave_add(int *counter, int v) {
-  int t = wave_sum(v);
-  if (__lane_id() == 0 && t) atomicAdd(counter, t);
-}
-
+// A variable-size allocation by one wave (all 64 lanes take part): one
+// atomic per wave instead of one per lane.
 __device__ __forceinline__ int wave_alloc(int *counter, int n) {
   int lane = __lane_id();
   int x = n;
@@ -162,13 +135,33 @@ __device__ __forceinline__ int wave_alloc(int *counter, int n) {
   return base + x - n;
 }
 
+// Entry idx of the midpoint list: subsegment k.
+__device__ __forceinline__ void put_mid(const Work &w, int idx, int k) {
+  w.mid.elem[idx] = k;
+  w.mid.state[idx] = 0;
+  w.cidx_s[k] = idx;
+}
+
+// Flags subsegment k; the first flag of the round appends it to the list.
+// (One lane at a time: used where flags are rare; the collection gathers its
+// flags and appends them per workgroup, see push_mids.)
 __device__ __forceinline__ void flag_mid(const Work &w, int k) {
-  if (atomicOr(&w.mflag[k], 1u) == 0u) {
-    int idx = atomicAdd(&w.cnt->nmk, 1);
-    w.mid.elem[idx] = k;
-    w.mid.state[idx] = 0;
-    w.cidx_s[k] = idx;
-  }
+  if (atomicOr(&w.mflag[k], 1u) == 0u) put_mid(w, atomicAdd(&w.cnt->nmk, 1), k);
+}
+
+// Round statistics: a wave-wide sum (every lane of the wave takes part)
+// added by one lane to the stat line of the wave.
+__device__ __forceinline__ StatLine *stat_line(const Work &w) {
+  const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  return w.stat + (wave & (kStatStripes - 1));
+}
+__device__ __forceinline__ void stat_add(const Work &w, int f, uint64_t v) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  if (__lane_id() == 0 && v) atomicAdd((unsigned long long *)&stat_line(w)->v[f], (unsigned long long)v);
+}
+__device__ __forceinline__ void stat_max(const Work &w, int f, uint64_t v) {
+  for (int d = 32; d > 0; d >>= 1) v = max(v, (uint64_t)__shfl_xor(v, d));
+  if (__lane_id() == 0 && v) atomicMax((unsigned long long *)&stat_line(w)->v[f], (unsigned long long)v);
 }
 
 __device__ __forceinline__ bool bit_get(const uint32_t *bm, int i) { return (bm[i >> 5] >> (i & 31)) & 1u; }
@@ -209,11 +202,68 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int v) {
 // base0 + stride, ...  A grid kernel spreads the items over all workgroups;
 // the single-workgroup engine takes them all.  The loops are uniform over a
 // workgroup, as the wave-wide operations require.
+// blk: every thread of the workgroup runs the loop (grid kernels), so list
+// space can be taken once per workgroup; otherwise once per wave (the
+// engine, whose waves share one compute unit and see no contention).
 struct Lanes {
-  int base0, stride;
+  int base0, stride, blk;
 };
-__device__ __forceinline__ Lanes grid_lanes() { return {(int)(blockIdx.x * blockDim.x), (int)(gridDim.x * blockDim.x)}; }
-__device__ __forceinline__ Lanes block_lanes() { return {0, (int)blockDim.x}; }
+__device__ __forceinline__ Lanes grid_lanes() {
+  return {(int)(blockIdx.x * blockDim.x), (int)(gridDim.x * blockDim.x), 1};
+}
+__device__ __forceinline__ Lanes block_lanes() { return {0, (int)blockDim.x, 0}; }
+
+// n entries per lane from a shared counter: returns this lane's first offset.
+// One atomic per workgroup (L.blk) or per wave; the loops that call it are
+// uniform over the workgroup.
+constexpr int kMaxWaves = 16;
+__device__ __forceinline__ int group_alloc(int *counter, int n, const Lanes &L) {
+  if (!L.blk) return wave_alloc(counter, n);
+  __shared__ int s_part[kMaxWaves];
+  __shared__ int s_base;
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  int x = n;
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_part[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) {
+      int t = s_part[i];
+      s_part[i] = acc;
+      acc += t;
+    }
+    s_base = acc ? atomicAdd(counter, acc) : 0;
+  }
+  __syncthreads();
+  const int r = s_base + s_part[wid] + x - n;
+  __syncthreads();
+  return r;
+}
+
+// The midpoint entries a lane flagged (up to 4), appended together (kept in
+// named registers: an indexed array would go to scratch memory).
+struct MidFlags {
+  int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+  int n = 0;
+  __device__ __forceinline__ void push(int k) {
+    k3 = n == 3 ? k : k3;
+    k2 = n == 2 ? k : k2;
+    k1 = n == 1 ? k : k1;
+    k0 = n == 0 ? k : k0;
+    n++;
+  }
+};
+__device__ __forceinline__ void push_mids(const Work &w, const MidFlags &f, const Lanes &L) {
+  const int off = group_alloc(&w.cnt->nmk, f.n, L);
+  if (f.n > 0) put_mid(w, off, f.k0);
+  if (f.n > 1) put_mid(w, off + 1, f.k1);
+  if (f.n > 2) put_mid(w, off + 2, f.k2);
+  if (f.n > 3) put_mid(w, off + 3, f.k3);
+}
 // the first lane of the whole distribution (single writes)
 __device__ __forceinline__ bool first_lane(const Lanes &L) { return L.base0 == 0 && threadIdx.x == 0; }
 
@@ -222,7 +272,7 @@ __device__ __forceinline__ bool first_lane(const Lanes &L) { return L.base0 == 0
 // ---------------------------------------------------------------------------
 // Tests one triangle: subsegment sides + encroaching apex, and badness.
 __device__ __forceinline__ bool scan_triangle(const DevMesh &m, const Work &w, int i, double B2, int pm,
-                                              SplitPt &r) {
+                                              SplitPt &r, MidFlags &fl) {
   int4 tri = m.tv[i];
   if (tri.w) {
     int4 s = m.ts[i];
@@ -233,15 +283,15 @@ __device__ __forceinline__ bool scan_triangle(const DevMesh &m, const Work &w, i
       int side = (u == m.sv[k].x) ? 0 : 1;
       w.sadj[2 * k + side] = i * 4 + e;
       double2 U = m.vxy[u], V = m.vxy[v], Cc = m.vxy[c];
-      if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0) flag_mid(w, k);
+      if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0 && atomicOr(&w.mflag[k], 1u) == 0u) fl.push(k);
     }
   }
   r = tri_split(m, i, tri, B2, pm);
   return r.bad != 0;
 }
 
-__device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const SplitPt &r) {
-  int idx = wave_append(&w.cnt->ncc, bad);
+__device__ __forceinline__ void append_cc(const Work &w, bool bad, int t, const SplitPt &r, const Lanes &L) {
+  int idx = group_alloc(&w.cnt->ncc, bad ? 1 : 0, L);
   if (bad) {
     w.cc.elem[idx] = t;
     w.cc.key[idx] = r.key;
@@ -258,9 +308,11 @@ __device__ __forceinline__ void scan_part(const DevMesh &m, const Work &w, doubl
     int i = base + threadIdx.x;
     bool bad = false;
     SplitPt r;
-    if (i < nT) bad = scan_triangle(m, w, i, B2, pm, r);
-    append_cc(w, bad, i, r);
-    if (i < nS && m.spend[i]) flag_mid(w, i);
+    MidFlags fl;
+    if (i < nT) bad = scan_triangle(m, w, i, B2, pm, r, fl);
+    append_cc(w, bad, i, r, L);
+    if (i < nS && m.spend[i] && atomicOr(&w.mflag[i], 1u) == 0u) fl.push(i);
+    push_mids(w, fl, L);
   }
 }
 
@@ -285,7 +337,7 @@ __device__ __forceinline__ void carry_part(const Work &w, const Lanes &L) {
       t = w.prev_cc_elem[c];
       keep = w.tstamp[t] != prev_serial;
     }
-    int idx = wave_append(&w.cnt->ncc, keep);
+    int idx = group_alloc(&w.cnt->ncc, keep ? 1 : 0, L);
     if (keep) {
       w.cc.elem[idx] = t;
       w.cc.key[idx] = w.prev_cc_key[c];
@@ -304,12 +356,14 @@ __device__ __forceinline__ void dirty_part(const DevMesh &m, const Work &w, doub
     int c = base + threadIdx.x;
     bool bad = false;
     SplitPt r;
+    MidFlags fl;
     int t = 0;
     if (c < n_dirty) {
       t = w.fan[c].slot;
-      bad = scan_triangle(m, w, t, B2, pm, r);
+      bad = scan_triangle(m, w, t, B2, pm, r, fl);
     }
-    append_cc(w, bad, t, r);
+    append_cc(w, bad, t, r, L);
+    push_mids(w, fl, L);
   }
 }
 
@@ -317,29 +371,30 @@ __device__ __forceinline__ void dirty_part(const DevMesh &m, const Work &w, doub
 // apex still inside the diametric circle (a flagged subsegment the candidate
 // cap left out is not pending, and its sides may be unchanged).  The side
 // slots are current: rewritten sides were re-scanned just before.
-__device__ __forceinline__ void pending_one(const DevMesh &m, const Work &w, int k) {
-  if (m.spend[k]) {
-    flag_mid(w, k);
-    return;
-  }
+// Returns true if subsegment k is flagged anew.
+__device__ __forceinline__ bool pending_one(const DevMesh &m, const Work &w, int k) {
+  if (m.spend[k]) return atomicOr(&w.mflag[k], 1u) == 0u;
   for (int side = 0; side < 2; side++) {
     int a = w.sadj[2 * k + side];
     if (a < 0) continue;
     int t = a >> 2, e = a & 3;
     int4 tri = m.tv[t];
     double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)], C = m.vxy[comp(tri, (e + 2) % 3)];
-    if (indiametral(U.x, U.y, V.x, V.y, C.x, C.y) > 0) {
-      flag_mid(w, k);
-      return;
-    }
+    if (indiametral(U.x, U.y, V.x, V.y, C.x, C.y) > 0) return atomicOr(&w.mflag[k], 1u) == 0u;
   }
+  return false;
 }
 
 __device__ __forceinline__ void pending_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int n_prev = w.st->prev_nmk;
   for (int base = L.base0; base < n_prev; base += L.stride) {
     int c = base + threadIdx.x;
-    if (c < n_prev) pending_one(m, w, w.prev_mid_elem[c]);
+    MidFlags fl;
+    if (c < n_prev) {
+      const int k = w.prev_mid_elem[c];
+      if (pending_one(m, w, k)) fl.push(k);
+    }
+    push_mids(w, fl, L);
   }
 }
 
@@ -487,15 +542,16 @@ __global__ void k_apply_cap(Work w) {
 // R4: locate circumcenters by a visibility walk (Line 6); a walk stopped only
 // by subsegments turns into the midpoint candidate of the first one.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void locate_one(const DevMesh &m, const Work &w, int c, int nS) {
-  if (w.cc.state[c] & kStSkip) return;
+// Returns 1 for a coincident point, 2 for a walk blocked by a subsegment.
+__device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c, int nS) {
+  if (w.cc.state[c] & kStSkip) return 0;
   int cur = w.cc.elem[c];
   double2 p = w.cc.p[c];
   for (int steps = 1;; steps++) {
     if (steps > (1 << 20)) {
       atomicOr(&w.cnt->err, kErrWalk);
       w.cc.state[c] = kStDone;
-      return;
+      return 0;
     }
     int4 tri = m.tv[cur];
     double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
@@ -503,13 +559,12 @@ __device__ __forceinline__ void locate_one(const DevMesh &m, const Work &w, int 
     if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
       int nz = (s0 == 0) + (s1 == 0) + (s2 == 0);
       if (nz >= 2) {
-        atomicAdd(&w.cnt->n_coincident, 1);
         w.cc.state[c] = kStDone;
-        return;
+        return 1;
       }
       w.cc.loc[c] = cur;
       w.cc.state[c] = kStFound;
-      return;
+      return 0;
     }
     int4 nb = m.tn[cur];
     int s[3] = {s0, s1, s2};
@@ -525,12 +580,11 @@ __device__ __forceinline__ void locate_one(const DevMesh &m, const Work &w, int 
       if (k < 0 || k >= nS) {  // a hull edge that is not a subsegment
         atomicOr(&w.cnt->err, kErrInput);
         w.cc.state[c] = kStDone;
-        return;
+        return 0;
       }
       flag_mid(w, k);
-      atomicAdd(&w.cnt->n_blocked, 1);
       w.cc.state[c] = kStDone;
-      return;
+      return 2;
     }
     cur = next;
   }
@@ -538,10 +592,17 @@ __device__ __forceinline__ void locate_one(const DevMesh &m, const Work &w, int 
 
 __device__ __forceinline__ void locate_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, nS = w.st->nS;
+  int n_coin = 0, n_blk = 0;
   for (int base = L.base0; base < ncc; base += L.stride) {
     int c = base + threadIdx.x;
-    if (c < ncc) locate_one(m, w, c, nS);
+    if (c < ncc) {
+      const int r = locate_one(m, w, c, nS);
+      n_coin += r == 1;
+      n_blk += r == 2;
+    }
   }
+  stat_add(w, kStCoincident, n_coin);
+  stat_add(w, kStBlocked, n_blk);
 }
 
 __global__ void k_locate(DevMesh m, Work w) {
@@ -686,7 +747,7 @@ __device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, in
 }
 
 constexpr int kCap = 24;      // per-thread cavity capacity of the grid kernel
-constexpr int kCavBlock = 128;
+constexpr int kCavBlock = kCavBlockSize;
 
 // Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
 // cap entries).  Returns the size, or -1 if it exceeds cap (the cavity then
@@ -841,7 +902,7 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
     int ci = base + tid;
     CavRes r{0, 0, 0, 0, 0, 0, 0};
     if (ci < n) r = cavity_one(m, w, lds, ls, cap, tid, ci, is_cc);
-    int off = wave_alloc(&w.cnt->pool_used, r.alive ? r.len : 0);
+    int off = group_alloc(&w.cnt->pool_used, r.alive ? r.len : 0, L);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
     if (r.alive) {
       if (off + r.len > w.pool_cap) {
@@ -861,19 +922,15 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
         counted = true;
       }
     }
-    int lsum = wave_sum(counted ? r.len : 0);
-    int lmax = wave_max(counted ? r.len : 0);
-    int glen = wave_sum(r.len), gbnd = wave_sum(r.bnd);
-    if (__lane_id() == 0) {
-      if (lsum) atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)lsum);
-      if (lmax) atomicMax(&w.cnt->cav_max, lmax);
-      if (glen) atomicAdd((unsigned long long *)&w.cnt->cav_len[is_cc], (unsigned long long)glen);
-      if (gbnd) atomicAdd((unsigned long long *)&w.cnt->cav_bnd[is_cc], (unsigned long long)gbnd);
-    }
-    wave_add(&w.cnt->n_enc_reject, r.enc_reject);
-    wave_add(&w.cnt->n_fan_invalid, r.fan_invalid);
-    wave_add(&w.cnt->n_unsplittable, r.unsplittable);
-    wave_add(&w.cnt->n_mid_cand, r.mid_cand);
+    // (summed per iteration: nothing stays live across the cavity work)
+    stat_add(w, kStCavTri, counted ? r.len : 0);
+    stat_max(w, kStCavMax, counted ? r.len : 0);
+    stat_add(w, is_cc ? kStCavLen1 : kStCavLen0, r.len);
+    stat_add(w, is_cc ? kStCavBnd1 : kStCavBnd0, r.bnd);
+    stat_add(w, kStEncReject, r.enc_reject);
+    stat_add(w, kStFanInvalid, r.fan_invalid);
+    stat_add(w, kStUnsplittable, r.unsplittable);
+    stat_add(w, kStMidCand, r.mid_cand);
   }
 }
 
@@ -1090,11 +1147,13 @@ __device__ __forceinline__ void own_one(const Work &w, int c, int ncc, int &lost
 
 __device__ __forceinline__ void own_part(const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  int n_lost = 0;
   for (int base = L.base0; base < n; base += L.stride) {
     int c = base + threadIdx.x, lost = 0;
     if (c < n) own_one(w, c, ncc, lost);
-    wave_add(&w.cnt->n_lost_mark, lost);
+    n_lost += lost;
   }
+  stat_add(w, kStLostMark, n_lost);
 }
 
 __global__ void k_own(Work w) {
@@ -1103,12 +1162,13 @@ __global__ void k_own(Work w) {
 }
 
 // R9: Delaunay dependency across a shared non-subsegment cavity edge.
-__device__ __forceinline__ void dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
+// Returns true if the candidate is dropped.
+__device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
   int st = S.state[ci];
-  if (!(st & kStW0)) return;
+  if (!(st & kStW0)) return false;
   uint64_t key = S.key[ci];
   double2 p = S.p[ci];
   int off = S.off[ci], len = S.len[ci];
@@ -1136,20 +1196,21 @@ __device__ __forceinline__ void dep_one(const DevMesh &m, const Work &w, int c, 
     }
   }
   (void)skip_k;
-  if (drop) {
-    atomicAdd(&w.cnt->n_dep_drop, 1);
-  } else {
+  if (!drop) {
     S.state[ci] = st | kStWin;
     bit_set(is_cc ? w.win_t : w.win_s, S.elem[ci]);
   }
+  return drop;
 }
 
 __device__ __forceinline__ void dep_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  int n_drop = 0;
   for (int base = L.base0; base < n; base += L.stride) {
     int c = base + threadIdx.x;
-    if (c < n) dep_one(m, w, c, ncc);
+    if (c < n) n_drop += dep_one(m, w, c, ncc);
   }
+  stat_add(w, kStDepDrop, n_drop);
 }
 
 __global__ void k_dep(DevMesh m, Work w) {
@@ -1387,7 +1448,7 @@ __device__ __forceinline__ void record_part(const DevMesh &m, const Work &w, con
   for (int base = L.base0; base < nwin; base += L.stride) {
     int r = base + threadIdx.x;
     int b = r < nwin ? fan_size(w, r) : 0;
-    int foff = wave_alloc(&w.cnt->fan_used, b);
+    int foff = group_alloc(&w.cnt->fan_used, b, L);
     if (r < nwin) record_one(m, w, r, foff);
   }
 }
@@ -1505,8 +1566,38 @@ __device__ __forceinline__ void finish_one(const DevMesh &m, const Work &w, int 
 // halts instead (the counters stay for the host to read).
 __device__ __forceinline__ void round_end(const Work &w) {
   __shared__ int s_go, s_slot;
+  __shared__ uint64_t s_fold[kStFields];
   DevState *st = w.st;
   DevCounters *c = w.cnt;
+  // fold the stat lines into the counters and clear them (read-and-clear
+  // atomics: the lines were written by atomics)
+  if (threadIdx.x < kStFields) {
+    const int f = threadIdx.x;
+    uint64_t acc = 0;
+    for (int i = 0; i < kStatStripes; i++) {
+      uint64_t x = atomicExch((unsigned long long *)&w.stat[i].v[f], 0ull);
+      acc = f == kStCavMax ? max(acc, x) : acc + x;
+    }
+    s_fold[f] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->cav_tri_total += (int64_t)s_fold[kStCavTri];
+    c->cav_len[0] += (int64_t)s_fold[kStCavLen0];
+    c->cav_len[1] += (int64_t)s_fold[kStCavLen1];
+    c->cav_bnd[0] += (int64_t)s_fold[kStCavBnd0];
+    c->cav_bnd[1] += (int64_t)s_fold[kStCavBnd1];
+    c->n_enc_reject += (int32_t)s_fold[kStEncReject];
+    c->n_fan_invalid += (int32_t)s_fold[kStFanInvalid];
+    c->n_unsplittable += (int32_t)s_fold[kStUnsplittable];
+    c->n_mid_cand += (int32_t)s_fold[kStMidCand];
+    c->n_lost_mark += (int32_t)s_fold[kStLostMark];
+    c->n_dep_drop += (int32_t)s_fold[kStDepDrop];
+    c->n_blocked += (int32_t)s_fold[kStBlocked];
+    c->n_coincident += (int32_t)s_fold[kStCoincident];
+    c->cav_max = max(c->cav_max, (int32_t)s_fold[kStCavMax]);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     s_go = 0;
     s_slot = -1;
@@ -1773,7 +1864,7 @@ __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
       }
     // R5/R6 cavities with their marks
     BigShared &sh = *reinterpret_cast<BigShared *>(lds);
-    const Lanes LC{0, kEngCavThreads};
+    const Lanes LC{0, kEngCavThreads, 0};
     if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 1, lds, kEngCavThreads, kEngCap, LC);
     phase_sync();
     engine_big(m, w, sh, 0);
