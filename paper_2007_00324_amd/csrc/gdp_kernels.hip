@@ -702,58 +702,26 @@ struct CavCheck {
   bool enc;
 };
 
-// Boundary checks of a sorted cavity: encroached boundary subsegments (for
-// circumcenters; all are flagged), fan orientation, boundary count.
-template <typename GetCav>
-__device__ CavCheck check_cavity(const DevMesh &m, const Work &w, GetCav cav, int len, int skip_k,
-                                 bool is_cc, double2 p) {
-  CavCheck r{0, false, false};
-  for (int j = 0; j < len; j++) {
-    const int t = cav(j);
-    const int4 tri = m.tv[t];
-    const int4 nb = m.tn[t];
-    const int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
-    bool bnd[3];
-    int sid[3];
-    for (int e = 0; e < 3; e++) {
-      sid[e] = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
-      bnd[e] = !(skip_k >= 0 && sid[e] == skip_k);
-      const int o = comp(nb, e);
-      if (bnd[e] && sid[e] < 0 && o >= 0) {
-        // internal iff o is in the cavity (binary search on the sorted list)
-        int lo = 0, hi = len - 1;
-        while (lo <= hi) {
-          int mid = (lo + hi) >> 1;
-          int x = cav(mid);
-          if (x == o) { bnd[e] = false; break; }
-          if (x < o) lo = mid + 1; else hi = mid - 1;
-        }
-      }
-    }
-    if (!(bnd[0] || bnd[1] || bnd[2])) continue;
-    const double2 P[3] = {m.vxy[tri.x], m.vxy[tri.y], m.vxy[tri.z]};
-    for (int e = 0; e < 3; e++) {
-      if (!bnd[e]) continue;
-      r.nbnd++;
-      const double2 U = P[e], V = P[(e + 1) % 3];
-      if (is_cc && sid[e] >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
-        flag_mid(w, sid[e]);
-        r.enc = true;
-      }
-      if (orient_pts(U, V, p) <= 0) r.fan_bad = true;
-    }
-  }
-  return r;
-}
-
 constexpr int kCap = 24;      // per-thread cavity capacity of the grid kernel
 constexpr int kCavBlock = kCavBlockSize;
 
 // Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
 // cap entries).  Returns the size, or -1 if it exceeds cap (the cavity then
 // goes to the cooperative path; the set of triangles is the same).
-__device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls, int cap, int tid, const int *seeds,
-                                          int nseeds, double2 p) {
+//
+// The boundary checks are made on the way: an edge of a cavity triangle is
+// internal iff its neighbour is in the cavity, and that is decided when the
+// triangle is taken from the list (a neighbour already listed is internal;
+// one that fails the circle test never enters).  For each boundary edge:
+// the count, the fan orientation (p strictly left of it), and for
+// circumcenters an encroached boundary subsegment (all are flagged; a
+// cavity that overflows flags a subset of what the cooperative path flags
+// for the same cavity).  The split subsegment of a midpoint (skip_k) is
+// not a boundary edge.
+__device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
+                                          const int *seeds, int nseeds, double2 p, int skip_k, bool is_cc,
+                                          CavCheck &ck) {
+  ck = CavCheck{0, false, false};
   int len = 0;
   for (int s = 0; s < nseeds; s++) {
     bool dup = false;
@@ -767,22 +735,31 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls
     // the three neighbours are distinct triangles, so they can be screened
     // against the list together and then tested in edge order
     int o[3];
-    bool c[3];
+    bool c[3], in[3];
     for (int e = 0; e < 3; e++) {
       o[e] = comp(nb, e);
-      c[e] = !((tri.w >> e) & 1) && o[e] >= 0;
+      in[e] = false;
     }
     for (int q = 0; q < len; q++) {
       const int x = lds[q * ls + tid];
-      c[0] = c[0] && x != o[0];
-      c[1] = c[1] && x != o[1];
-      c[2] = c[2] && x != o[2];
+      in[0] = in[0] || x == o[0];
+      in[1] = in[1] || x == o[1];
+      in[2] = in[2] || x == o[2];
     }
-    if (!(c[0] || c[1] || c[2])) continue;
-    // independent loads: the neighbours' records and this triangle's
-    // vertices; then only the far vertex of each neighbour
+    // in: internal (a listed neighbour across a non-subsegment edge);
+    // c: to be tested by the circle test; the rest (subsegment and hull
+    // edges) are boundary
+    for (int e = 0; e < 3; e++) {
+      const bool sub = (tri.w >> e) & 1;
+      in[e] = in[e] && !sub;
+      c[e] = !sub && o[e] >= 0 && !in[e];
+    }
+    if (in[0] && in[1] && in[2]) continue;
+    // independent loads: the neighbours' records, this triangle's vertices
+    // and subsegments; then only the far vertex of each neighbour
     int4 to[3];
     for (int e = 0; e < 3; e++) to[e] = c[e] ? m.tv[o[e]] : make_int4(0, 0, 0, 0);
+    const int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
     const double2 P[3] = {m.vxy[tri.x], m.vxy[tri.y], m.vxy[tri.z]};
     double2 F[3];
     int fv[3];
@@ -794,18 +771,30 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, int32_t *lds, int ls
       F[e] = m.vxy[fv[e]];
     }
     for (int e = 0; e < 3; e++) {
-      if (!c[e]) continue;
-      const int u = comp(tri, e);
+      if (in[e]) continue;
       const double2 Pu = P[e], Pv = P[(e + 1) % 3];
-      // the neighbour's vertices in its own order (the same arguments as a
-      // direct evaluation on its record)
-      const double2 A = to[e].x == fv[e] ? F[e] : (to[e].x == u ? Pu : Pv);
-      const double2 B = to[e].y == fv[e] ? F[e] : (to[e].y == u ? Pu : Pv);
-      const double2 C = to[e].z == fv[e] ? F[e] : (to[e].z == u ? Pu : Pv);
-      if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y) > 0) {
-        if (len == cap) return -1;
-        lds[(len++) * ls + tid] = o[e];
+      if (c[e]) {
+        const int u = comp(tri, e);
+        // the neighbour's vertices in its own order (the same arguments as
+        // a direct evaluation on its record)
+        const double2 A = to[e].x == fv[e] ? F[e] : (to[e].x == u ? Pu : Pv);
+        const double2 B = to[e].y == fv[e] ? F[e] : (to[e].y == u ? Pu : Pv);
+        const double2 C = to[e].z == fv[e] ? F[e] : (to[e].z == u ? Pu : Pv);
+        if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y) > 0) {
+          if (len == cap) return -1;
+          lds[(len++) * ls + tid] = o[e];
+          continue;
+        }
       }
+      // a boundary edge
+      const int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (skip_k >= 0 && sid == skip_k) continue;
+      ck.nbnd++;
+      if (is_cc && sid >= 0 && indiametral(Pu.x, Pu.y, Pv.x, Pv.y, p.x, p.y) > 0) {
+        flag_mid(w, sid);
+        ck.enc = true;
+      }
+      if (orient_pts(Pu, Pv, p) <= 0) ck.fan_bad = true;
     }
   }
   // insertion sort (ascending slots)
@@ -863,7 +852,8 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
     expect = nseeds == 2 ? 2 : 1;
     S.state[ci] = st | kStFound;
   }
-  int len = grow_local(m, lds, ls, cap, tid, seeds, nseeds, p);
+  CavCheck ck;
+  int len = grow_local(m, w, lds, ls, cap, tid, seeds, nseeds, p, skip_k, is_cc != 0, ck);
   if (len < 0) {
     S.state[ci] = st | kStBig | kStFound;
     int q = atomicAdd(&w.cnt->nbig, 1);
@@ -871,8 +861,6 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
     else atomicOr(&w.cnt->err, kErrCavity);
     return res;
   }
-  auto cav = [&](int j) { return lds[j * ls + tid]; };
-  CavCheck ck = check_cavity(m, w, cav, len, skip_k, is_cc != 0, p);
   res.len = len;
   res.bnd = ck.nbnd;
   if (is_cc && ck.enc) {
@@ -1122,6 +1110,12 @@ __global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int
 // ---------------------------------------------------------------------------
 // R8: priority marks and ownership
 // ---------------------------------------------------------------------------
+// Loop bodies that load a few records and then use them are written as
+// batches: all loads of a batch are issued before any result is needed
+// (the stores in between would otherwise keep the compiler from hoisting
+// them), which turns a chain of dependent memory latencies into a few.
+constexpr int kIlp = 8;
+
 __device__ __forceinline__ bool cand_at(const Work &w, int c, int ncc, CandSet &S, int &ci, int &is_cc) {
   if (c < ncc) { S = w.cc; ci = c; is_cc = 1; return true; }
   S = w.mid; ci = c - ncc; is_cc = 0; return true;
@@ -1135,8 +1129,18 @@ __device__ __forceinline__ void own_one(const Work &w, int c, int ncc, int &lost
   if (!(st & kStAlive)) return;
   uint64_t key = S.key[ci];
   int off = S.off[ci], len = S.len[ci];
+  // independent loads, kIlp slots at a time (the marks are tested after)
   bool own = true;
-  for (int j = 0; j < len && own; j++) own = w.mark[w.pool[off + j]] == key;
+  for (int j0 = 0; j0 < len && own; j0 += kIlp) {
+    int t[kIlp];
+    uint64_t mk[kIlp];
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) t[i] = j0 + i < len ? w.pool[off + j0 + i] : -1;
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) mk[i] = t[i] >= 0 ? w.mark[t[i]] : key;
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) own = own && mk[i] == key;
+  }
   if (own) {
     S.state[ci] = st | kStW0;
     bit_set(is_cc ? w.w0_t : w.w0_s, S.elem[ci]);
@@ -1174,17 +1178,36 @@ __device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, 
   int off = S.off[ci], len = S.len[ci];
   int skip_k = is_cc ? -1 : S.elem[ci];
   bool drop = false;
-  for (int j = 0; j < len && !drop; j++) {
-    int t = w.pool[off + j];
-    int4 tri = m.tv[t];
-    int4 nb = m.tn[t];
-    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
-    for (int e = 0; e < 3 && !drop; e++) {
-      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
-      if (sid >= 0) continue;  // subsegment edges (incl. the split one) are not tested
-      int o = comp(nb, e);
-      if (o < 0) continue;
-      uint64_t mo = w.mark[o];
+  constexpr int B = 2;  // cavity triangles per batch
+  for (int j0 = 0; j0 < len && !drop; j0 += B) {
+    int tt[B];
+    int4 tri_[B], nb_[B], ts_[B];
+    uint64_t mo_[B][3];
+#pragma unroll
+    for (int i = 0; i < B; i++) tt[i] = j0 + i < len ? w.pool[off + j0 + i] : -1;
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      const bool v = tt[i] >= 0;
+      tri_[i] = v ? m.tv[tt[i]] : make_int4(0, 0, 0, 0);
+      nb_[i] = v ? m.tn[tt[i]] : make_int4(-1, -1, -1, 0);
+      ts_[i] = v ? m.ts[tt[i]] : make_int4(-1, -1, -1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; i++)
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        const int o = comp(nb_[i], e);
+        const bool sub = ((tri_[i].w >> e) & 1) && comp(ts_[i], e) >= 0;
+        mo_[i][e] = (!sub && o >= 0) ? w.mark[o] : 0ull;
+      }
+#pragma unroll
+    for (int i = 0; i < B; i++)
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+      if (drop || tt[i] < 0) continue;
+      const int4 tri = tri_[i];
+      // subsegment edges (incl. the split one) and hull edges were given mark 0
+      uint64_t mo = mo_[i][e];
       if (mo == key || mo == 0) continue;  // inside this cavity, or unclaimed
       int q_cc = (mo >> 63) ? 0 : 1;
       int qid = (int)perm32_inv((uint32_t)(mo & 0xffffffffu));
@@ -1379,21 +1402,44 @@ __device__ __forceinline__ void record_one(const DevMesh &m, const Work &w, int 
   int b = len + (fbase_at(w, r + 1) - fbase_at(w, r));
   w.fan_off[r] = foff;
   int j = 0;
-  for (int q = 0; q < len; q++) {
-    int t = w.pool[off + q];
-    int4 tri = m.tv[t];
-    int4 nb = m.tn[t];
-    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+  constexpr int B = 2;  // cavity triangles per batch
+  for (int q0 = 0; q0 < len; q0 += B) {
+    int tt[B];
+    int4 tri_[B], nb_[B], ts_[B], to_[B][3];
+    uint64_t mk_[B][3];
+#pragma unroll
+    for (int i = 0; i < B; i++) tt[i] = q0 + i < len ? w.pool[off + q0 + i] : -1;
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      const bool v = tt[i] >= 0;
+      tri_[i] = v ? m.tv[tt[i]] : make_int4(0, 0, 0, 0);
+      nb_[i] = v ? m.tn[tt[i]] : make_int4(-1, -1, -1, 0);
+      ts_[i] = v ? m.ts[tt[i]] : make_int4(-1, -1, -1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; i++)
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        const int o = comp(nb_[i], e);
+        mk_[i][e] = o >= 0 ? w.mark[o] : 0ull;
+        to_[i][e] = o >= 0 ? m.tv[o] : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < B; i++)
+#pragma unroll
     for (int e = 0; e < 3; e++) {
+      if (tt[i] < 0) continue;
+      const int t = tt[i];
+      const int4 tri = tri_[i], ts = ts_[i];
       int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
       if (skip_k >= 0 && sid == skip_k) continue;
-      int o = comp(nb, e);
-      if (sid < 0 && o >= 0 && w.mark[o] == key) continue;
+      int o = comp(nb_[i], e);
+      if (sid < 0 && o >= 0 && mk_[i][e] == key) continue;
       int slot = j < len ? w.pool[off + j] : fresh_base + (j - len);
       int u = comp(tri, e), v = comp(tri, (e + 1) % 3);
       int jn = -1;
       if (o >= 0) {
-        int4 to = m.tv[o];
+        int4 to = to_[i][e];
         if (to.x == v && to.y == u) jn = 0;
         else if (to.y == v && to.z == u) jn = 1;
         else jn = 2;
@@ -1476,6 +1522,53 @@ __device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r
     a = sk.x;
     bb = sk.y;
   }
+  if (b <= kIlp) {
+    // the whole fan in registers: records, then the outside marks, their
+    // owners' win bits and replacement slots, each a batch of loads
+    FanRec F[kIlp];
+    uint64_t mo[kIlp];
+    bool ow[kIlp];
+    int rp[kIlp];
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) F[i] = i < b ? w.fan[foff + i] : FanRec{-1, -2, -2, -1, 0, -1};
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) mo[i] = F[i].o >= 0 ? w.mark[F[i].o] : 0ull;
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) ow[i] = F[i].o >= 0 && owner_wins(w, mo[i]);
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) rp[i] = ow[i] ? w.repl[F[i].o * 4 + F[i].jn] : -1;
+#pragma unroll
+    for (int i = 0; i < kIlp; i++) {
+      if (i >= b) continue;
+      const FanRec f = F[i];
+      const int s = f.slot;
+      int n0;
+      if (f.o < 0) n0 = -1;
+      else if (ow[i]) n0 = rp[i];
+      else {
+        n0 = f.o;
+        ((int32_t *)m.tn)[f.o * 4 + f.jn] = s;
+      }
+      int n1 = -1, n2 = -1;
+#pragma unroll
+      for (int g = 0; g < kIlp; g++) {
+        if (g >= b) continue;
+        if (F[g].u == f.v) n1 = F[g].slot;
+        if (F[g].v == f.u) n2 = F[g].slot;
+      }
+      int s1 = -1, s2 = -1;
+      if (!is_cc) {
+        s1 = f.v == a ? k : (f.v == bb ? knew : -1);
+        s2 = f.u == a ? k : (f.u == bb ? knew : -1);
+      }
+      int mask = (f.ts >= 0 ? 1 : 0) | (s1 >= 0 ? 2 : 0) | (s2 >= 0 ? 4 : 0);
+      m.tv[s] = make_int4(f.u, f.v, pid, mask);
+      m.tn[s] = make_int4(n0, n1, n2, 0);
+      m.ts[s] = make_int4(f.ts, s1, s2, 0);
+      w.tstamp[s] = serial;
+    }
+    b = 0;  // done
+  }
   for (int j = 0; j < b; j++) {
     FanRec f = w.fan[foff + j];
     int s = f.slot;
@@ -1540,7 +1633,14 @@ __device__ __forceinline__ void finish_one(const DevMesh &m, const Work &w, int 
   int st = S.state[ci];
   if (st & kStAlive) {
     int off = S.off[ci], len = S.len[ci];
-    for (int j = 0; j < len; j++) w.mark[w.pool[off + j]] = 0ull;
+    for (int j0 = 0; j0 < len; j0 += kIlp) {
+      int t[kIlp];
+#pragma unroll
+      for (int i = 0; i < kIlp; i++) t[i] = j0 + i < len ? w.pool[off + j0 + i] : -1;
+#pragma unroll
+      for (int i = 0; i < kIlp; i++)
+        if (t[i] >= 0) w.mark[t[i]] = 0ull;
+    }
   }
   int e = S.elem[ci];
   uint32_t bit = 1u << (e & 31);
