@@ -1522,15 +1522,16 @@ __device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r
     a = sk.x;
     bb = sk.y;
   }
-  if (b <= kIlp) {
-    // the whole fan in registers: records, then the outside marks, their
-    // owners' win bits and replacement slots, each a batch of loads
+  // kIlp fan records at a time: the records, then the outside marks, their
+  // owners' win bits and replacement slots, each a batch of loads; a fan of
+  // at most kIlp records finds its neighbours in registers
+  for (int j0 = 0; j0 < b; j0 += kIlp) {
     FanRec F[kIlp];
     uint64_t mo[kIlp];
     bool ow[kIlp];
     int rp[kIlp];
 #pragma unroll
-    for (int i = 0; i < kIlp; i++) F[i] = i < b ? w.fan[foff + i] : FanRec{-1, -2, -2, -1, 0, -1};
+    for (int i = 0; i < kIlp; i++) F[i] = j0 + i < b ? w.fan[foff + j0 + i] : FanRec{-1, -2, -2, -1, 0, -1};
 #pragma unroll
     for (int i = 0; i < kIlp; i++) mo[i] = F[i].o >= 0 ? w.mark[F[i].o] : 0ull;
 #pragma unroll
@@ -1539,7 +1540,7 @@ __device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r
     for (int i = 0; i < kIlp; i++) rp[i] = ow[i] ? w.repl[F[i].o * 4 + F[i].jn] : -1;
 #pragma unroll
     for (int i = 0; i < kIlp; i++) {
-      if (i >= b) continue;
+      if (j0 + i >= b) continue;
       const FanRec f = F[i];
       const int s = f.slot;
       int n0;
@@ -1550,11 +1551,19 @@ __device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r
         ((int32_t *)m.tn)[f.o * 4 + f.jn] = s;
       }
       int n1 = -1, n2 = -1;
+      if (b <= kIlp) {
 #pragma unroll
-      for (int g = 0; g < kIlp; g++) {
-        if (g >= b) continue;
-        if (F[g].u == f.v) n1 = F[g].slot;
-        if (F[g].v == f.u) n2 = F[g].slot;
+        for (int g = 0; g < kIlp; g++) {
+          if (g >= b) continue;
+          if (F[g].u == f.v) n1 = F[g].slot;
+          if (F[g].v == f.u) n2 = F[g].slot;
+        }
+      } else {
+        for (int g = 0; g < b; g++) {
+          FanRec h = w.fan[foff + g];
+          if (h.u == f.v) n1 = h.slot;
+          if (h.v == f.u) n2 = h.slot;
+        }
       }
       int s1 = -1, s2 = -1;
       if (!is_cc) {
@@ -1567,34 +1576,6 @@ __device__ __forceinline__ void write_one(const DevMesh &m, const Work &w, int r
       m.ts[s] = make_int4(f.ts, s1, s2, 0);
       w.tstamp[s] = serial;
     }
-    b = 0;  // done
-  }
-  for (int j = 0; j < b; j++) {
-    FanRec f = w.fan[foff + j];
-    int s = f.slot;
-    int n0;
-    if (f.o < 0) n0 = -1;
-    else if (owner_wins(w, w.mark[f.o])) n0 = w.repl[f.o * 4 + f.jn];
-    else {
-      n0 = f.o;
-      ((int32_t *)m.tn)[f.o * 4 + f.jn] = s;
-    }
-    int n1 = -1, n2 = -1;
-    for (int g = 0; g < b; g++) {
-      FanRec h = w.fan[foff + g];
-      if (h.u == f.v) n1 = h.slot;
-      if (h.v == f.u) n2 = h.slot;
-    }
-    int s1 = -1, s2 = -1;
-    if (!is_cc) {
-      s1 = f.v == a ? k : (f.v == bb ? knew : -1);
-      s2 = f.u == a ? k : (f.u == bb ? knew : -1);
-    }
-    int mask = (f.ts >= 0 ? 1 : 0) | (s1 >= 0 ? 2 : 0) | (s2 >= 0 ? 4 : 0);
-    m.tv[s] = make_int4(f.u, f.v, pid, mask);
-    m.tn[s] = make_int4(n0, n1, n2, 0);
-    m.ts[s] = make_int4(f.ts, s1, s2, 0);
-    w.tstamp[s] = serial;
   }
   m.vxy[pid] = p;
   m.vkind[pid] = is_cc ? 2 : 1;
