@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     orient2d,
     incircle,
     indiametral,
+    encroaches,
     incircle_sos,
     perm32,
     exact_counts,

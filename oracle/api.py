@@ -28,7 +28,8 @@ class _Mesh(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
-                ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32)]
+                ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("encroach_mode", C.c_int32),
+                ("max_edge_len_sq", C.c_double)]
 
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident",
@@ -76,11 +77,17 @@ def load() -> C.CDLL:
     lib.orc_perm32.restype = C.c_uint32
     lib.orc_check_topology.argtypes = [C.POINTER(_Mesh), C.c_char_p, C.c_int32]
     lib.orc_check_topology.restype = C.c_int64
-    for name in ("orc_check_local_delaunay", "orc_check_encroached", "orc_check_cdt_bruteforce"):
+    for name in ("orc_check_local_delaunay", "orc_check_cdt_bruteforce"):
         getattr(lib, name).argtypes = [C.POINTER(_Mesh)]
         getattr(lib, name).restype = C.c_int64
-    lib.orc_check_quality.argtypes = [C.POINTER(_Mesh), C.c_double]
+    lib.orc_check_encroached.argtypes = [C.POINTER(_Mesh), C.c_int32]
+    lib.orc_check_encroached.restype = C.c_int64
+    lib.orc_check_quality.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_double]
     lib.orc_check_quality.restype = C.c_int64
+    lib.orc_mesh_quality.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_double, C.POINTER(C.c_int64), P2]
+    lib.orc_mesh_quality.restype = None
+    lib.orc_encroaches.argtypes = [C.c_int32, P2, P2, P2]
+    lib.orc_encroaches.restype = C.c_int
     lib.orc_check_subsegments.argtypes = [C.POINTER(_Mesh), P2, C.POINTER(C.c_int32), C.c_char_p, C.c_int32]
     lib.orc_check_subsegments.restype = C.c_int64
     lib.orc_area_sum.argtypes = [C.POINTER(_Mesh)]
@@ -109,6 +116,11 @@ def orient2d(a, b, c) -> int:
 
 def incircle(a, b, c, d) -> int:
     return load().orc_incircle(_pt(a), _pt(b), _pt(c), _pt(d))
+
+
+def encroaches(mode: int, a, b, p) -> int:
+    """Subsegment ab encroached by p: diametric circle (mode 0) or lens (mode 1)."""
+    return load().orc_encroaches(mode, _pt(a), _pt(b), _pt(p))
 
 
 def indiametral(a, b, c) -> int:
@@ -184,8 +196,14 @@ class OracleMesh:
         return n, buf.value.decode()
 
     def check_local_delaunay(self): return load().orc_check_local_delaunay(self._p)
-    def check_quality(self, B2): return load().orc_check_quality(self._p, B2)
-    def check_encroached(self): return load().orc_check_encroached(self._p)
+    def check_quality(self, B2, L2=0.0): return load().orc_check_quality(self._p, B2, L2)
+    def check_encroached(self, mode=0): return load().orc_check_encroached(self._p, mode)
+
+    def quality(self, B2, L2=0.0):
+        """(bad triangle count, area they cover) under the criteria."""
+        n, a = C.c_int64(0), C.c_double(0.0)
+        load().orc_mesh_quality(self._p, B2, L2, C.byref(n), C.byref(a))
+        return n.value, a.value
     def check_cdt_bruteforce(self): return load().orc_check_cdt_bruteforce(self._p)
     def area(self): return load().orc_area_sum(self._p)
     def hull_count(self): return load().orc_hull_vertex_count(self._p)
@@ -214,9 +232,11 @@ def build_cdt(xy: np.ndarray, seg: np.ndarray) -> OracleMesh:
 
 def refine(mesh: OracleMesh, ratio_bound_sq: float, cand_cap_K: int = 0, priority_mode: int = 0,
            max_rounds: int = 0, stats_cap: int = 1 << 16, raise_on_error: bool = True,
-           prefilter_f1: int = 0, cavity_approx_n: int = 0) -> int:
+           prefilter_f1: int = 0, cavity_approx_n: int = 0, encroach_mode: int = 0,
+           max_edge_len_sq: float = 0.0) -> int:
     lib = load()
-    prm = _Params(cand_cap_K, priority_mode, max_rounds, prefilter_f1, cavity_approx_n)
+    prm = _Params(cand_cap_K, priority_mode, max_rounds, prefilter_f1, cavity_approx_n, encroach_mode,
+                  float(max_edge_len_sq))
     st = (_Stats * stats_cap)()
     ns = C.c_int32(0)
     err = C.create_string_buffer(256)

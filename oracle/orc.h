@@ -65,6 +65,9 @@ typedef struct orc_params {
   int32_t prefilter_f1;   /* 1: keep one circumcenter per located triangle (max key) */
   int32_t cavity_approx_n;/* n > 0: drop circumcenters that lose a mark on the first
                              n triangles of their cavity growth order */
+  int32_t encroach_mode;  /* 0: diametric circle (Ruppert); 1: diametric lens (Chew) */
+  double max_edge_len_sq; /* 0 = off; else a triangle with an edge longer than l
+                             (squared length > l^2) is bad as well */
 } orc_params;
 
 typedef struct orc_round_stats {
@@ -93,6 +96,11 @@ void orc_mesh_free(orc_mesh *m);
 int orc_orient2d(const double *a, const double *b, const double *c);
 int orc_incircle(const double *a, const double *b, const double *c, const double *d);
 int orc_indiametral(const double *a, const double *b, const double *c);
+/* Does p encroach subsegment ab?  mode 0: strictly inside the diametric
+   circle (exact).  mode 1: strictly inside the diametric lens, the region
+   from which ab is seen under more than 120 degrees (exact circle test,
+   then a fixed-order FP64 test of the angle). */
+int orc_encroaches(int32_t mode, const double *a, const double *b, const double *p);
 /* incircle with the symbolic-perturbation tie-break (vertex ids ia..id). */
 int orc_incircle_sos(const double *a, const double *b, const double *c, const double *d,
                      int32_t ia, int32_t ib, int32_t ic, int32_t id);
@@ -101,7 +109,7 @@ void orc_exact_counts(int64_t *orient, int64_t *incircle, int64_t *indiam);
 
 /* Fixed-order FP64 formulas (refinement Line 5 / Line 6). */
 uint32_t orc_perm32(uint32_t x);
-void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq,
+void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq, double max_edge_len_sq,
                       double *px, double *py, int32_t *bad, uint64_t *key,
                       int32_t priority_mode);
 void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t *key,
@@ -110,8 +118,13 @@ void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t
 /* Checkers.  Each returns the number of violations found. */
 int64_t orc_check_topology(const orc_mesh *m, char *err, int32_t errlen);
 int64_t orc_check_local_delaunay(const orc_mesh *m);
-int64_t orc_check_quality(const orc_mesh *m, double ratio_bound_sq);
-int64_t orc_check_encroached(const orc_mesh *m);
+int64_t orc_check_quality(const orc_mesh *m, double ratio_bound_sq, double max_edge_len_sq);
+int64_t orc_check_encroached(const orc_mesh *m, int32_t encroach_mode);
+/* Bad triangles of a mesh under the criteria and the area they cover (the
+   bad-area measure of Table 1): each bad triangle adds half its fixed-order
+   FP64 doubled area, summed in slot order. */
+void orc_mesh_quality(const orc_mesh *m, double ratio_bound_sq, double max_edge_len_sq, int64_t *n_bad,
+                      double *bad_area);
 int64_t orc_check_cdt_bruteforce(const orc_mesh *m);
 int64_t orc_check_subsegments(const orc_mesh *m, const double *in_xy, const int32_t *in_seg,
                               char *err, int32_t errlen);

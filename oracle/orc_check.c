@@ -101,19 +101,44 @@ int64_t orc_check_local_delaunay(const orc_mesh *m) {
   return bad;
 }
 
-int64_t orc_check_quality(const orc_mesh *m, double B2) {
+int64_t orc_check_quality(const orc_mesh *m, double B2, double L2) {
   int64_t bad = 0;
   for (int32_t t = 0; t < m->nT; t++) {
     double px, py;
     int32_t b;
     uint64_t key;
-    orc_circumcenter(m, t, B2, &px, &py, &b, &key, 0);
+    orc_circumcenter(m, t, B2, L2, &px, &py, &b, &key, 0);
     bad += b;
   }
   return bad;
 }
 
-int64_t orc_check_encroached(const orc_mesh *m) {
+void orc_mesh_quality(const orc_mesh *m, double B2, double L2, int64_t *n_bad, double *bad_area) {
+  int64_t n = 0;
+  double area = 0.0;
+  for (int32_t t = 0; t < m->nT; t++) {
+    double px, py;
+    int32_t b;
+    uint64_t key;
+    orc_circumcenter(m, t, B2, L2, &px, &py, &b, &key, 0);
+    if (!b) continue;
+    /* doubled area with the circumcenter formula's operand order: vertices
+       rotated so that the smallest id comes first */
+    int32_t v0 = m->tv[3 * t], v1 = m->tv[3 * t + 1], v2 = m->tv[3 * t + 2], ia, ib, ic;
+    if (v0 < v1 && v0 < v2) { ia = v0; ib = v1; ic = v2; }
+    else if (v1 < v2) { ia = v1; ib = v2; ic = v0; }
+    else { ia = v2; ib = v0; ic = v1; }
+    double bx = m->x[ib] - m->x[ia], by = m->y[ib] - m->y[ia];
+    double cx = m->x[ic] - m->x[ia], cy = m->y[ic] - m->y[ia];
+    double d = bx * cy - by * cx;
+    n++;
+    area += d * 0.5;
+  }
+  *n_bad = n;
+  *bad_area = area;
+}
+
+int64_t orc_check_encroached(const orc_mesh *m, int32_t mode) {
   int64_t bad = 0;
   for (int32_t t = 0; t < m->nT; t++)
     for (int i = 0; i < 3; i++) {
@@ -122,7 +147,7 @@ int64_t orc_check_encroached(const orc_mesh *m) {
       vxy(m, m->tv[3 * t + i], a);
       vxy(m, m->tv[3 * t + NXT(i)], b);
       vxy(m, m->tv[3 * t + PRV(i)], c);
-      if (orc_indiametral(a, b, c) > 0) bad++;
+      if (orc_encroaches(mode, a, b, c)) bad++;
     }
   return bad;
 }

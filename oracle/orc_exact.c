@@ -378,7 +378,7 @@ void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t
    circumcenter lies outside |x|,|y| <= 2^20, the triangle is bad, its measure
    is 0 and its splitting point is the midpoint of its longest edge (first of
    ab, ac, bc on ties). */
-void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq,
+void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq, double max_edge_len_sq,
                       double *px, double *py, int32_t *bad, uint64_t *key,
                       int32_t priority_mode) {
   int32_t v0 = m->tv[3 * t], v1 = m->tv[3 * t + 1], v2 = m->tv[3 * t + 2];
@@ -410,6 +410,13 @@ void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq,
       if (c2 < lmin2) lmin2 = c2;
       if (e2 < lmin2) lmin2 = e2;
       *bad = r2 > ratio_bound_sq * lmin2 ? 1 : 0;
+      if (max_edge_len_sq > 0.0) {
+        /* edge-length criterion: the longest of the three edges against l^2 */
+        double lmax2 = b2;
+        if (c2 > lmax2) lmax2 = c2;
+        if (e2 > lmax2) lmax2 = e2;
+        if (lmax2 > max_edge_len_sq) *bad = 1;
+      }
       q = (uint64_t)q31(d);
     }
   }
@@ -426,4 +433,25 @@ void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq,
   }
   if (priority_mode == 1) q = 0;
   *key = (q << 32) | (uint64_t)orc_perm32((uint32_t)t);
+}
+
+/* Encroachment of subsegment ab by p (Section 4.1: inside the diametric
+   circle under Ruppert's algorithm, inside the diametric lens under Chew's).
+   The paper does not give the lens angle.  The lens here is bounded by two
+   circular arcs through a and b that meet ab at 60 degrees; its points see
+   ab under an angle above 120 degrees, i.e. (a-p).(b-p) < 0 and
+   4 ((a-p).(b-p))^2 > |a-p|^2 |b-p|^2.  (A flatter lens, arcs at 30 degrees,
+   lets free vertices sit close to a subsegment whose circumcenters lie behind
+   it; without vertex deletion the splits then feed each other.)  The lens
+   lies inside the circle, so the exact circle test comes first; the angle
+   test is the FP64 formula below in this order. */
+int orc_encroaches(int32_t mode, const double *a, const double *b, const double *p) {
+  if (orc_indiametral(a, b, p) <= 0) return 0;
+  if (mode == 0) return 1;
+  double dax = a[0] - p[0], day = a[1] - p[1];
+  double dbx = b[0] - p[0], dby = b[1] - p[1];
+  double dot = dax * dbx + day * dby;
+  double la = dax * dax + day * day;
+  double lb = dbx * dbx + dby * dby;
+  return (dot * dot) * 4.0 > la * lb ? 1 : 0;
 }

@@ -6,10 +6,13 @@
  *
  * One round, in the order of Algorithm 1:
  *   R1 (Line 3)  collect encroached subsegments (pending flag, or an adjacent
- *                apex strictly inside the diametric circle; Section 4.2
- *                definition of encroachment, Ruppert mode) and bad triangles
+ *                apex strictly inside the diametric circle, Ruppert mode, or
+ *                inside the diametric lens, Chew mode; Section 4.1/4.2
+ *                definition of encroachment) and bad triangles
  *                (circumradius^2 > B^2 * shortest edge^2, the radius-edge
- *                ratio of Section 5.1).  Stop when there are none.
+ *                form of the angle bound, or, when a length bound l is set,
+ *                an edge longer than l; Section 4.1).  Stop when there are
+ *                none.
  *   R2 (Line 5)  splitting points: midpoints of subsegments, circumcenters of
  *                triangles; priorities per Section 4.3 (midpoints first, then
  *                larger length / area first), made unique by a fixed
@@ -317,14 +320,14 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
       vxy(m, u, a);
       vxy(m, v, b);
       vxy(m, c, cc);
-      if (orc_indiametral(a, b, cc) > 0) enc[k] = 1;
+      if (orc_encroaches(prm->encroach_mode, a, b, cc)) enc[k] = 1;
     }
   }
   int64_t n_enc = 0, n_bad = 0;
   for (int32_t k = 0; k < nS; k++) n_enc += enc[k];
   for (int32_t t = 0; t < nT; t++) {
     int32_t b;
-    orc_circumcenter(m, t, B2, &tpx[t], &tpy[t], &b, &tkey[t], pm);
+    orc_circumcenter(m, t, B2, prm->max_edge_len_sq, &tpx[t], &tpy[t], &b, &tkey[t], pm);
     bad[t] = (uint8_t)b;
     n_bad += b;
   }
@@ -479,7 +482,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
       double a[2], b[2];
       vxy(m, bb[j].u, a);
       vxy(m, bb[j].v, b);
-      if (orc_indiametral(a, b, p) > 0) { mflag[bb[j].ts] = 1; encroaches = 1; }
+      if (orc_encroaches(prm->encroach_mode, a, b, p)) { mflag[bb[j].ts] = 1; encroaches = 1; }
     }
     if (st) {
       st->cav_tri_total += cd->ncav;
@@ -695,7 +698,8 @@ int orc_refine(orc_mesh *m, double B2, const orc_params *p, orc_round_stats *sta
   if (n_stats) *n_stats = 0;
   if (!m || !p || !(B2 > 0.0) || !isfinite(B2)) { set_err(err, errlen, "bad arguments"); return ORC_E_ARG; }
   if ((p->prefilter_f1 != 0 && p->prefilter_f1 != 1) || p->cavity_approx_n < 0 || p->cand_cap_K < 0 ||
-      (p->priority_mode != 0 && p->priority_mode != 1)) {
+      (p->priority_mode != 0 && p->priority_mode != 1) || (p->encroach_mode != 0 && p->encroach_mode != 1) ||
+      !(p->max_edge_len_sq >= 0.0) || !isfinite(p->max_edge_len_sq)) {
     set_err(err, errlen, "unsupported parameter");
     return ORC_E_ARG;
   }
