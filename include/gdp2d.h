@@ -98,7 +98,14 @@ typedef struct {
   int32_t tail_engine_max;  /* rounds whose previous round had at most this many
                                candidates run whole inside one workgroup (0 =
                                default 1024; negative = never) */
-  int32_t reserved[2];
+  /* semantic (quality criteria of Section 4.1) */
+  int32_t encroach_mode;    /* 0: a subsegment is encroached by a vertex or splitting
+                               point strictly inside its diametric circle (Ruppert);
+                               1: strictly inside its diametric lens, the points that
+                               see it under more than 120 degrees (Chew) */
+  int32_t reserved[1];
+  double max_edge_len_sq;   /* 0 = off; else l^2 for the edge-length bound l: a
+                               triangle with an edge longer than l is bad too */
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */
@@ -172,6 +179,17 @@ gdp_status gdp_refine(gdp_ctx *ctx, const gdp_pslg *pslg, double ratio_bound_sq,
                       const gdp_params *params, gdp_mesh **out);
 
 gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info);
+
+/* The quality of a mesh under the criteria of Section 4.1 (the same FP64
+   test as the refinement's scan, with bound ratio_bound_sq and, if
+   max_edge_len_sq > 0, the edge-length bound): *n_bad gets the number of bad
+   triangles and *bad_area the area they cover (the bad-area measure of
+   Table 1: half the FP64 doubled area of each, summed on the device in a
+   fixed order per launch shape).  Bad triangles remain near input angles
+   below 60 degrees.  Computed by kernels on the context stream; blocks until
+   done.  GDP_E_ARG for a bad bound or null output. */
+gdp_status gdp_mesh_quality(gdp_ctx *ctx, const gdp_mesh *mesh, double ratio_bound_sq, double max_edge_len_sq,
+                            int64_t *n_bad, double *bad_area);
 
 /* Copies the mesh to caller buffers sized from gdp_mesh_info_get (any pointer
    may be NULL to skip that array): xy[2V], vkind[V] (0 input, 1 midpoint,

@@ -307,9 +307,12 @@ constexpr int64_t kEngineDefaultMax = 1024;  // candidates per round run by the 
 
 // Workspace pointers of a round; the two list buffers swap roles with the
 // parity of the round's serial.
-Work make_work(gdp_mesh *M, int pm, int parity) {
+Work make_work(gdp_mesh *M, const gdp_params *P, int parity) {
+  const int pm = P->priority_mode;
   Work w;
   memset(&w, 0, sizeof w);  // no stray padding bytes (graph keys hash the struct)
+  w.L2 = P->max_edge_len_sq;
+  w.enc_mode = P->encroach_mode;
   w.st = M->d_st;
   w.cnt = M->d_cnt;
   w.stat = M->d_stat;
@@ -537,7 +540,7 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   const DevMesh &m = M->m;
   const int bs = P->block_size;
   const int pm = P->priority_mode;
-  Work w = make_work(M, pm, parity);
+  Work w = make_work(M, P, parity);
   est = std::max<int64_t>(est, 1);
   M->cur_round = group_index;
   // ---- R1 collection ----
@@ -722,7 +725,7 @@ gdp_status reserve_group(gdp_mesh *M, int64_t last_cand, int R) {
 uint64_t graph_key(gdp_mesh *M, double B2, const gdp_params *P, int64_t est) {
   DevMesh m = M->m;
   m.nV = m.nT = m.nS = m.rounds = 0;  // counts are read from device memory
-  Work w = make_work(M, P->priority_mode, 0);
+  Work w = make_work(M, P, 0);
   uint64_t h = 1469598103934665603ull;
   h = fnv(h, &m, sizeof m);
   h = fnv(h, &w, sizeof w);
@@ -795,8 +798,8 @@ gdp_status launch_engine(gdp_mesh *M, double B2, const gdp_params *P, int rounds
   EngDesc &d = *M->h_eng;
   memset(&d, 0, sizeof d);
   d.m = M->m;
-  d.w[0] = make_work(M, P->priority_mode, 0);
-  d.w[1] = make_work(M, P->priority_mode, 1);
+  d.w[0] = make_work(M, P, 0);
+  d.w[1] = make_work(M, P, 1);
   d.B2 = B2;
   d.pm = P->priority_mode;
   d.K = P->cand_cap_K;
@@ -1104,8 +1107,8 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
     EngDesc &d = desc[q];
     memset(&d, 0, sizeof d);
     d.m = mesh[k]->m;
-    d.w[0] = make_work(mesh[k], P->priority_mode, 0);
-    d.w[1] = make_work(mesh[k], P->priority_mode, 1);
+    d.w[0] = make_work(mesh[k], P, 0);
+    d.w[1] = make_work(mesh[k], P, 1);
     d.B2 = bsq[ok[k]];
     d.pm = P->priority_mode;
     d.K = P->cand_cap_K;
@@ -1749,6 +1752,9 @@ static gdp_status check_params(gdp_ctx *ctx, const gdp_params *params, gdp_param
   if (P.reserve_mode != 0 && P.reserve_mode != 1) return fail(ctx, GDP_E_ARG, "bad reserve mode");
   if (P.rounds_per_sync < 0 || P.rounds_per_sync > kHistCap)
     return fail(ctx, GDP_E_ARG, "rounds_per_sync must be in [0, 64]");
+  if (P.encroach_mode != 0 && P.encroach_mode != 1) return fail(ctx, GDP_E_ARG, "encroach_mode must be 0 or 1");
+  if (!(P.max_edge_len_sq >= 0.0) || !std::isfinite(P.max_edge_len_sq))
+    return fail(ctx, GDP_E_ARG, "max_edge_len_sq must be finite and >= 0");
   return GDP_OK;
 }
 
@@ -1800,6 +1806,37 @@ gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info) {
   info->n_input_vertices = mesh->m.n_input_v;
   info->n_input_segments = mesh->m.n_input_s;
   info->rounds = mesh->m.rounds;
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_quality(gdp_ctx *ctx, const gdp_mesh *mesh, double ratio_bound_sq, double max_edge_len_sq,
+                            int64_t *n_bad, double *bad_area) {
+  if (!ctx || !mesh || mesh->ctx != ctx || !n_bad || !bad_area) return GDP_E_ARG;
+  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq) || !(max_edge_len_sq >= 0.0) ||
+      !std::isfinite(max_edge_len_sq))
+    return fail(ctx, GDP_E_ARG, "bad quality bound");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = ctx->stream;
+  // partials [kQualBlocks] and the totals, then a copy back
+  const size_t bytes = (size_t)(kQualBlocks + 1) * (sizeof(unsigned long long) + sizeof(double));
+  char *buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(ctx, GDP_E_NOMEM, "allocation failed");
+  auto *n_part = (unsigned long long *)buf;
+  auto *a_part = (double *)(buf + sizeof(unsigned long long) * (kQualBlocks + 1));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kQualBlocks, ((int64_t)mesh->m.nT + 255) / 256));
+  hipLaunchKernelGGL(k_quality, dim3(g), dim3(256), 0, s, mesh->m, ratio_bound_sq, max_edge_len_sq, n_part, a_part);
+  hipLaunchKernelGGL(k_quality_sum, dim3(1), dim3(64), 0, s, (int)g, n_part, a_part, n_part + kQualBlocks,
+                     a_part + kQualBlocks);
+  unsigned long long hn = 0;
+  double ha = 0.0;
+  bool ok = hipGetLastError() == hipSuccess &&
+            hipMemcpyAsync(&hn, n_part + kQualBlocks, sizeof hn, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(&ha, a_part + kQualBlocks, sizeof ha, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(buf);
+  if (!ok) return fail(ctx, GDP_E_DEVICE, "quality kernels failed");
+  *n_bad = (int64_t)hn;
+  *bad_area = ha;
   return GDP_OK;
 }
 

@@ -47,6 +47,8 @@ struct Work {
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
   int32_t *rhist;      // [256] digit histogram of the radix select (zero between uses)
   StatLine *stat;      // [kStatStripes] statistics of the running round
+  double L2;           // edge-length bound l^2 (0: off)
+  int32_t enc_mode;    // 0: diametric circle, 1: diametric lens
   uint64_t *sel;       // [3] radix select: key prefix, prefix mask, keys still to take
   int32_t pm;
 };
@@ -85,6 +87,12 @@ __global__ void k_winners(Work w);
 __global__ void k_record(DevMesh m, Work w);
 __global__ void k_write(DevMesh m, Work w);
 __global__ void k_finish(DevMesh m, Work w);
+// Mesh quality: bad triangles and their area (per-block partials, then one
+// fixed-order sum).
+constexpr int kQualBlocks = 512;
+__global__ void k_quality(DevMesh m, double B2, double L2, unsigned long long *n_part, double *a_part);
+__global__ void k_quality_sum(int n_part, const unsigned long long *n_in, const double *a_in,
+                              unsigned long long *n_out, double *a_out);
 
 // One mesh of the single-workgroup engine.
 struct EngDesc {

@@ -47,13 +47,14 @@ struct SplitPt {
   double px, py;
   uint64_t key;
   int bad;
+  double d;  // doubled area by the fixed formula (triangles)
 };
 
 // Circumcenter / radius-edge test / key of triangle t, in one fixed FP64
 // operation order (vertices rotated so the smallest id comes first); a
 // needle (non-positive FP64 doubled area, or a circumcenter beyond 2^20)
 // is bad, has measure 0 and splits at the midpoint of its longest edge.
-__device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, int pm) {
+__device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, double L2, int pm) {
   int v0 = tri.x, v1 = tri.y, v2 = tri.z, ia, ib, ic;
   if (v0 < v1 && v0 < v2) { ia = v0; ib = v1; ic = v2; }
   else if (v1 < v2) { ia = v1; ib = v2; ic = v0; }
@@ -84,6 +85,13 @@ __device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, int p
       if (c2 < lmin2) lmin2 = c2;
       if (e2 < lmin2) lmin2 = e2;
       r.bad = r2 > B2 * lmin2 ? 1 : 0;
+      if (L2 > 0.0) {
+        // edge-length bound (Section 4.1): the longest edge against l^2
+        double lmax2 = b2;
+        if (c2 > lmax2) lmax2 = c2;
+        if (e2 > lmax2) lmax2 = e2;
+        if (lmax2 > L2) r.bad = 1;
+      }
       q = q31(d);
     }
   }
@@ -99,6 +107,7 @@ __device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, int p
   }
   if (pm == 1) q = 0;
   r.key = (q << 32) | (uint64_t)perm32((uint32_t)t);
+  r.d = d;
   return r;
 }
 
@@ -133,6 +142,24 @@ __device__ __forceinline__ int wave_alloc(int *counter, int n) {
   if (lane == 63 && total > 0) base = atomicAdd(counter, total);
   base = __shfl(base, 63);
   return base + x - n;
+}
+
+// Encroachment of subsegment ab by p (Section 4.1): strictly inside the
+// diametric circle (exact), or, in lens mode, strictly inside the diametric
+// lens: the points that see ab under more than 120 degrees, bounded by two
+// circular arcs through a and b meeting ab at 60 degrees.  The lens lies in
+// the circle; after the exact circle test the angle is tested by the FP64
+// formula (a-p).(b-p) < 0 and 4 ((a-p).(b-p))^2 > |a-p|^2 |b-p|^2 in this
+// operation order.
+__device__ __forceinline__ bool encroached(const Work &w, double2 a, double2 b, double2 p) {
+  if (indiametral(a.x, a.y, b.x, b.y, p.x, p.y) <= 0) return false;
+  if (w.enc_mode == 0) return true;
+  const double dax = a.x - p.x, day = a.y - p.y;
+  const double dbx = b.x - p.x, dby = b.y - p.y;
+  const double dot = dax * dbx + day * dby;
+  const double la = dax * dax + day * day;
+  const double lb = dbx * dbx + dby * dby;
+  return (dot * dot) * 4.0 > la * lb;
 }
 
 // Entry idx of the midpoint list: subsegment k.
@@ -283,10 +310,10 @@ __device__ __forceinline__ bool scan_triangle(const DevMesh &m, const Work &w, i
       int side = (u == m.sv[k].x) ? 0 : 1;
       w.sadj[2 * k + side] = i * 4 + e;
       double2 U = m.vxy[u], V = m.vxy[v], Cc = m.vxy[c];
-      if (indiametral(U.x, U.y, V.x, V.y, Cc.x, Cc.y) > 0 && atomicOr(&w.mflag[k], 1u) == 0u) fl.push(k);
+      if (encroached(w, U, V, Cc) && atomicOr(&w.mflag[k], 1u) == 0u) fl.push(k);
     }
   }
-  r = tri_split(m, i, tri, B2, pm);
+  r = tri_split(m, i, tri, B2, w.L2, pm);
   return r.bad != 0;
 }
 
@@ -380,7 +407,7 @@ __device__ __forceinline__ bool pending_one(const DevMesh &m, const Work &w, int
     int t = a >> 2, e = a & 3;
     int4 tri = m.tv[t];
     double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)], C = m.vxy[comp(tri, (e + 2) % 3)];
-    if (indiametral(U.x, U.y, V.x, V.y, C.x, C.y) > 0) return atomicOr(&w.mflag[k], 1u) == 0u;
+    if (encroached(w, U, V, C)) return atomicOr(&w.mflag[k], 1u) == 0u;
   }
   return false;
 }
@@ -790,7 +817,7 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32
       const int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
       if (skip_k >= 0 && sid == skip_k) continue;
       ck.nbnd++;
-      if (is_cc && sid >= 0 && indiametral(Pu.x, Pu.y, Pv.x, Pv.y, p.x, p.y) > 0) {
+      if (is_cc && sid >= 0 && encroached(w, Pu, Pv, p)) {
         flag_mid(w, sid);
         ck.enc = true;
       }
@@ -1050,7 +1077,7 @@ __device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShar
       if (sid < 0 && o >= 0 && in_sorted(cav, len, o)) continue;
       atomicAdd(&s_nbnd, 1);
       double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
-      if (is_cc && sid >= 0 && indiametral(U.x, U.y, V.x, V.y, p.x, p.y) > 0) {
+      if (is_cc && sid >= 0 && encroached(w, U, V, p)) {
         flag_mid(w, sid);
         s_enc = 1;
       }
@@ -1741,6 +1768,54 @@ __global__ void k_finish(DevMesh m, Work w) {
   __threadfence();
   if (threadIdx.x == 0) w.st->done_blocks = 0;
   round_end(w);
+}
+
+// ---------------------------------------------------------------------------
+// Mesh quality (the bad-area measure of Table 1): every triangle is tested
+// with the scan's formula; a bad one adds its doubled area / 2.  Each block
+// sums its lanes in a fixed tree order; the partials are summed in index
+// order by one thread, so the result depends only on the grid shape.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_quality(DevMesh m, double B2, double L2, unsigned long long *n_part,
+                                                 double *a_part) {
+  __shared__ unsigned long long s_n[256];
+  __shared__ double s_a[256];
+  unsigned long long n = 0;
+  double a = 0.0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m.nT; t += gridDim.x * blockDim.x) {
+    SplitPt r = tri_split(m, t, m.tv[t], B2, L2, 0);
+    if (r.bad) {
+      n++;
+      a += r.d * 0.5;
+    }
+  }
+  s_n[threadIdx.x] = n;
+  s_a[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_n[threadIdx.x] += s_n[threadIdx.x + h];
+      s_a[threadIdx.x] += s_a[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    n_part[blockIdx.x] = s_n[0];
+    a_part[blockIdx.x] = s_a[0];
+  }
+}
+
+__global__ void k_quality_sum(int n_part, const unsigned long long *n_in, const double *a_in,
+                              unsigned long long *n_out, double *a_out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  unsigned long long n = 0;
+  double a = 0.0;
+  for (int i = 0; i < n_part; i++) {
+    n += n_in[i];
+    a += a_in[i];
+  }
+  *n_out = n;
+  *a_out = a;
 }
 
 // ---------------------------------------------------------------------------

@@ -40,7 +40,8 @@ class gdp_params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
                 ("profile_kernels", C.c_int32), ("reserve_mode", C.c_int32), ("rounds_per_sync", C.c_int32),
-                ("tail_engine_max", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("tail_engine_max", C.c_int32), ("encroach_mode", C.c_int32), ("reserved", C.c_int32 * 1),
+                ("max_edge_len_sq", C.c_double)]
 
 
 class gdp_kernel_prof(C.Structure):
@@ -91,6 +92,7 @@ def load() -> C.CDLL:
         "gdp_mesh_refine": (S, [_VP, _VP, C.c_double, C.POINTER(gdp_params)]),
         "gdp_refine": (S, [_VP, C.POINTER(gdp_pslg), C.c_double, C.POINTER(gdp_params), C.POINTER(_VP)]),
         "gdp_mesh_info_get": (S, [_VP, C.POINTER(gdp_mesh_info)]),
+        "gdp_mesh_quality": (S, [_VP, _VP, C.c_double, C.c_double, C.POINTER(C.c_int64), _PD]),
         "gdp_mesh_download": (S, [_VP, _VP, _PD, _PI, _PI, _PI, _PI, _PI, _PI, C.POINTER(C.c_uint8)]),
         "gdp_mesh_round_stats": (S, [_VP, C.POINTER(gdp_round_stats), C.c_int32, _PI]),
         "gdp_mesh_last_refine_ms": (S, [_VP, C.POINTER(C.c_double)]),
@@ -119,7 +121,7 @@ def load() -> C.CDLL:
 def exported_symbols() -> list[str]:
     return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
             "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
-            "gdp_mesh_info_get", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
+            "gdp_mesh_info_get", "gdp_mesh_quality", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
             "gdp_server_wait", "gdp_server_destroy"]
@@ -138,9 +140,11 @@ def _pslg(xy, seg):
 
 def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
                 prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0,
-                tail_engine_max=0) -> gdp_params:
+                tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
+    p.encroach_mode = encroach_mode
+    p.max_edge_len_sq = float(max_edge_len_sq)
     p.reserve_mode = reserve_mode
     p.rounds_per_sync = rounds_per_sync
     p.tail_engine_max = tail_engine_max
@@ -225,6 +229,13 @@ class Mesh:
         i = gdp_mesh_info()
         self.ctx.check(load().gdp_mesh_info_get(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in gdp_mesh_info._fields_}
+
+    def quality(self, ratio_bound_sq: float, max_edge_len_sq: float = 0.0):
+        """(bad triangle count, area they cover) under the criteria, on the device."""
+        n, a = C.c_int64(0), C.c_double(0.0)
+        self.ctx.check(load().gdp_mesh_quality(self.ctx._h, self._h, float(ratio_bound_sq), float(max_edge_len_sq),
+                                               C.byref(n), C.byref(a)))
+        return n.value, a.value
 
     def arrays(self) -> dict:
         lib = load()

@@ -38,7 +38,7 @@ def test_batch_matches_oracle(ctx):
 
 
 @pytest.mark.parametrize("kw", [dict(cand_cap_K=5), dict(prefilter_f1=1, cavity_approx_n=2), dict(priority_mode=1),
-                                dict(max_rounds=5)])
+                                dict(max_rounds=5), dict(encroach_mode=1, max_edge_len_sq=0.004)])
 def test_batch_options_match_oracle(ctx, kw):
     ps = workloads.batch_config3(12, seed=12, n_min=100, n_max=1500)
     meshes, st, _ = _batch(ctx, ps, **kw)
