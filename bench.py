@@ -89,6 +89,47 @@ def cpu_baseline(p, n_points: int, n_segments: int) -> dict:
     }
 
 
+def criteria_leg(ctx, init, work, p) -> dict:
+    """The other quality criteria of Section 4.1 on the same resident initial CDT:
+    Chew's diametric lenses, an edge-length bound l, and the angle bound theta = 20
+    degrees of Table 1 (B^2 = 1 / (4 sin^2 theta)); each refinement timed alone
+    (one warmup, then the median of three), with the bad-area measure of the
+    result under its own criteria."""
+    import math
+
+    from paper_2007_00324_amd import gdp2d
+    theta20 = 1.0 / (4.0 * math.sin(math.radians(20.0)) ** 2)
+    modes = [
+        ("ruppert_B=sqrt2", p.ratio_bound_sq, dict()),
+        ("chew_lens_B=sqrt2", p.ratio_bound_sq, dict(encroach_mode=1)),
+        ("ruppert_B=sqrt2_l=0.001", p.ratio_bound_sq, dict(max_edge_len_sq=1e-6)),
+        ("ruppert_theta=20deg", theta20, dict()),
+        ("chew_lens_theta=20deg_l=0.001", theta20, dict(encroach_mode=1, max_edge_len_sq=1e-6)),
+    ]
+    rows = []
+    n_in = init.info()["n_vertices"]
+    for name, bsq, kw in modes:
+        prm = gdp2d.make_params(**kw)
+        ms = []
+        for rep in range(4):
+            work.assign_from(init)
+            gdp2d.gdp_mesh_refine(ctx, work, bsq, prm)
+            if rep:
+                ms.append(work.last_refine_ms())
+        ms.sort()
+        info = work.info()
+        steiner = info["n_vertices"] - n_in
+        n_bad, bad_area = work.quality(bsq, kw.get("max_edge_len_sq", 0.0))
+        row = {"mode": name, "ratio_bound_sq": bsq, **kw, "refine_ms": ms[1], "steiner_points": steiner,
+               "output_triangles": info["n_triangles"], "rounds": info["rounds"],
+               "steiner_per_s": steiner / (ms[1] / 1000.0), "bad_triangles": n_bad, "bad_area": bad_area}
+        log(f"criteria {name}: {ms[1]:.2f} ms, {steiner:,} Steiner points, {info['rounds']} rounds, "
+            f"{n_bad} bad triangles covering {bad_area:.3e}")
+        rows.append(row)
+    return {"workload": "the 1M-point PSLG above, same initial CDT", "timing": "device refine time, median of 3",
+            "modes": rows}
+
+
 def make_batch(count: int, workers: int):
     """The batched workload, generated by worker processes before this
     process touches the GPU."""
@@ -216,6 +257,7 @@ def main() -> int:
     ap.add_argument("--approx-n", type=int, default=0, help="Line 7 filter: n-triangle cavity approximation")
     ap.add_argument("--tail-engine-max", type=int, default=0,
                     help="candidates per round below which rounds run inside one workgroup (0 default, -1 never)")
+    ap.add_argument("--no-criteria", action="store_true", help="skip the lens / length-bound / theta legs")
     ap.add_argument("--batch", type=int, default=4096, help="jobs of the batched form (0: skip)")
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
@@ -349,6 +391,8 @@ def main() -> int:
             "kernel_ms": {k["name"]: round(k["total_ms"], 3) for k in prof if k["launches"]},
             "profiled_refine_ms": work.last_refine_ms(),
         }
+    if not args.no_criteria:
+        out["criteria"] = criteria_leg(ctx, init, work, p)
     if args.batch > 0:
         out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
     if serve_jobs:

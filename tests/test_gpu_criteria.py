@@ -87,3 +87,21 @@ def test_bad_area_initial_cdt(ctx):
         n_g, a_g = gm.quality(B2, l2)
         assert n_g == n_o and n_o > 0
         assert abs(a_g - a_o) <= 1e-12 * max(1.0, abs(a_o))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", ["lens", "lens_length"])
+def test_criteria_parity_200k(ctx, mode):
+    """The 1M-point generator scaled to 200k points: many tiles, both paths."""
+    p = workloads.scaled_config1(200_000, 10_000)
+    kw = dict(MODES[mode])
+    if "max_edge_len_sq" in kw:
+        kw["max_edge_len_sq"] = 1e-5
+    print(f"[criteria] {p.name} {mode} {kw}", flush=True)
+    om, orc_rc = oracle_run(p, **kw)
+    gm, gpu_rc = gpu_run(ctx, p, **kw)
+    assert orc_rc == gpu_rc == 0
+    bad = diff_arrays(om.arrays(), gm.arrays())
+    assert not bad, bad
+    n_o, a_o = om.quality(p.ratio_bound_sq, kw.get("max_edge_len_sq", 0.0))
+    assert gm.quality(p.ratio_bound_sq, kw.get("max_edge_len_sq", 0.0)) == (n_o, a_o) == (0, 0.0)
