@@ -130,6 +130,66 @@ def criteria_leg(ctx, init, work, p) -> dict:
             "modes": rows}
 
 
+def ablation_leg(ctx, init, work, p) -> dict:
+    """gDP2d's rules switched on and off on the 1M-point PSLG (the paper leaves this
+    study out for 2D).  Per setting: device refine time (median of 3), Steiner points,
+    rounds, and the Rule 2 quantities: alpha = insertions / candidates given to
+    threads (effective concurrency without a filter), beta = the same with it, and
+    l / L = the filter kernels' share of the profiled time.  Rule 2 predicts a gain
+    iff (L + l) / L < beta / alpha; the measured gain is the Steiner/s ratio."""
+    from paper_2007_00324_amd import gdp2d
+    settings = [
+        ("base", dict()),
+        ("K=65536", dict(cand_cap_K=65536)),
+        ("K=16384", dict(cand_cap_K=16384)),
+        ("F1", dict(prefilter_f1=1)),
+        ("F2_n=2", dict(cavity_approx_n=2)),
+        ("F2_n=4", dict(cavity_approx_n=4)),
+        ("F1+F2_n=4", dict(prefilter_f1=1, cavity_approx_n=4)),
+        ("no_single_workgroup_rounds", dict(tail_engine_max=-1)),
+    ]
+    filt_kernels = {"k_cap", "k_prefilter"}
+    n_in = init.info()["n_vertices"]
+    rows = []
+    base = None
+    for name, kw in settings:
+        work.assign_from(init)
+        gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, gdp2d.make_params(profile_kernels=1, **kw))
+        prof = {k["name"]: k["total_ms"] for k in work.kernel_profile() if k["launches"]}
+        rs = work.round_stats()
+        attempts = sum(r["n_kept_cc"] + r["n_kept_mid"] for r in rs)
+        useful = sum(r["n_ins_cc"] + r["n_ins_mid"] for r in rs)
+        big = sum(r["n_big_cavities"] for r in rs)
+        filt_ms = sum(v for k, v in prof.items() if k in filt_kernels)
+        tot_ms = sum(prof.values())
+        ms = []
+        prm = gdp2d.make_params(**kw)
+        for rep in range(4):
+            work.assign_from(init)
+            gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)
+            if rep:
+                ms.append(work.last_refine_ms())
+        ms.sort()
+        steiner = work.info()["n_vertices"] - n_in
+        row = {"setting": name, **kw, "refine_ms": ms[1], "steiner_points": steiner, "rounds": work.info()["rounds"],
+               "steiner_per_s": steiner / (ms[1] / 1000.0), "candidates": attempts, "insertions": useful,
+               "concurrency_fraction": useful / max(attempts, 1), "filter_ms": filt_ms,
+               "filter_share": filt_ms / max(tot_ms - filt_ms, 1e-9), "big_cavities": big}
+        if base is None:
+            base = row
+        else:
+            row["rule2_beta_over_alpha"] = row["concurrency_fraction"] / base["concurrency_fraction"]
+            row["rule2_latency_ratio"] = 1.0 + row["filter_share"]
+            row["rule2_predicts_gain"] = row["rule2_latency_ratio"] < row["rule2_beta_over_alpha"]
+            row["measured_gain"] = row["steiner_per_s"] / base["steiner_per_s"]
+        log(f"ablation {name}: {ms[1]:.2f} ms, {steiner:,} Steiner, {row['rounds']} rounds, "
+            f"alpha {row['concurrency_fraction']:.3f}, filter {filt_ms:.2f} ms"
+            + (f", gain {row['measured_gain']:.3f} (Rule 2 predicts {row['rule2_predicts_gain']})" if row is not base else ""))
+        rows.append(row)
+    return {"workload": "the 1M-point PSLG above, same initial CDT", "timing": "device refine time, median of 3",
+            "settings": rows}
+
+
 def make_batch(count: int, workers: int):
     """The batched workload, generated by worker processes before this
     process touches the GPU."""
@@ -258,6 +318,7 @@ def main() -> int:
     ap.add_argument("--tail-engine-max", type=int, default=0,
                     help="candidates per round below which rounds run inside one workgroup (0 default, -1 never)")
     ap.add_argument("--no-criteria", action="store_true", help="skip the lens / length-bound / theta legs")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the rule ablation leg")
     ap.add_argument("--batch", type=int, default=4096, help="jobs of the batched form (0: skip)")
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
@@ -393,6 +454,8 @@ def main() -> int:
         }
     if not args.no_criteria:
         out["criteria"] = criteria_leg(ctx, init, work, p)
+    if not args.no_ablation:
+        out["ablation"] = ablation_leg(ctx, init, work, p)
     if args.batch > 0:
         out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
     if serve_jobs:

@@ -110,11 +110,11 @@ struct gdp_mesh {
 
 namespace {
 enum ProfId {
-  P_SCAN = 0, P_CAP, P_LOCATE, P_CAV_CC, P_CAV_MID, P_CAV_BIG, P_MARK, P_OWN, P_DEP, P_PREFIX,
+  P_SCAN = 0, P_CAP, P_LOCATE, P_CAV_CC, P_CAV_MID, P_CAV_BIG, P_PREFILTER, P_OWN, P_DEP, P_PREFIX,
   P_WINNERS, P_RECORD, P_WRITE, P_FINISH, P_ENGINE, P_NUM
 };
 const char *kProfNames[P_NUM] = {"k_scan", "k_cap", "k_locate", "k_cavity_cc", "k_cavity_mid", "k_cavity_big",
-                                  "k_mark", "k_own", "k_dep", "k_prefix_sum", "k_winners", "k_record", "k_write",
+                                  "k_prefilter", "k_own", "k_dep", "k_prefix_sum", "k_winners", "k_record", "k_write",
                                   "k_finish", "k_engine"};
 // Records HIP events around the launches issued in its scope (if enabled);
 // items and algorithmic bytes are filled in once the round's counts are read.
@@ -572,13 +572,16 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
     hipLaunchKernelGGL(k_locate, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
   }
   // ---- optional prefilters F1 / F2 on located circumcenters ----
-  if (P->prefilter_f1)
-    for (int mode = 0; mode < 3; mode++)
-      hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode, 0);
-  if (P->cavity_approx_n > 0)
-    for (int mode = 3; mode < 6; mode++)
-      hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode,
-                         P->cavity_approx_n);
+  if (P->prefilter_f1 || P->cavity_approx_n > 0) {
+    Prof pr(M, P_PREFILTER);
+    if (P->prefilter_f1)
+      for (int mode = 0; mode < 3; mode++)
+        hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode, 0);
+    if (P->cavity_approx_n > 0)
+      for (int mode = 3; mode < 6; mode++)
+        hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode,
+                           P->cavity_approx_n);
+  }
   // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
   {
     Prof pr(M, P_CAV_CC);
