@@ -246,7 +246,7 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     }
 
 
-def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int) -> dict:
+def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int, engine_max_v=None) -> dict:
     """Serving form: the same job set replayed as a Poisson stream at each
     rate; latency = completion - arrival (Line 1 runs before arrival)."""
     import threading
@@ -258,9 +258,10 @@ def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int
                         "of the points, B^2 drawn from {2.0, 2.56, 4.0}; Poisson arrivals, the same jobs at every "
                         "rate; Line 1 on the host before arrival"),
            "jobs": n, "input_vertices": sum(p.n_vertices for p in jobs), "budget_gb": budget_gb, "slots": slots,
+           "engine_max_vertices": engine_max_v if engine_max_v is not None else 0,
            "rates": []}
     for lam in rates:
-        srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots)
+        srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v)
         with ThreadPoolExecutor(16) as ex:  # Line 1 of every job, in parallel, before the stream starts
             ids = list(ex.map(lambda p: srv.prepare(p.xy, p.seg, p.ratio_bound_sq), jobs))
         gaps = np.random.default_rng(7).exponential(1.0 / lam, size=n)
@@ -326,6 +327,8 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=str, default="50,200,1000", help="arrival rates, jobs/s")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-engine-max", type=int, default=None,
+                    help="jobs up to this many input vertices run in batched launches (default: the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration) and exit")
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
@@ -460,7 +463,8 @@ def main() -> int:
         out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
     if serve_jobs:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
-        out["serving"] = serving_leg(ctx, serve_jobs, rates, args.serve_budget_gb, args.serve_slots, 8)
+        out["serving"] = serving_leg(ctx, serve_jobs, rates, args.serve_budget_gb, args.serve_slots, 8,
+                                     args.serve_engine_max)
     if not args.no_cpu_baseline:
         n = args.cpu_sample
         log(f"cpu baseline: oracle on {n:,} points")

@@ -247,8 +247,16 @@ typedef struct {
 } gdp_job_times;
 
 /* hbm_budget: bytes of device memory for job regions; max_slots: jobs on the
-   device at once.  A worker thread of the library drives the device. */
+   device at once on their own streams (one library thread each).  Optionally
+   (gdp_server_engine_jobs; off by default) small jobs do not use a slot: the
+   arrived ones are refined together in one launch of the single-workgroup
+   engine (one workgroup per job, largest first), driven by one more library
+   thread.  Every job's mesh is the same on either path. */
 gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out);
+/* Jobs with at most max_input_vertices input vertices go to the batched
+   launches (0: every job takes a slot).  Applies to jobs admitted afterwards.
+   GDP_E_ARG for a negative value. */
+gdp_status gdp_server_engine_jobs(gdp_server *srv, int32_t max_input_vertices);
 /* Line 1 for a job (host) without letting it arrive; *job identifies it. */
 gdp_status gdp_server_prepare(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq,
                               const gdp_params *params, uint64_t *job);

@@ -1262,6 +1262,7 @@ struct Job {
   enum { PREPARED, QUEUED, ACTIVE, DONE } state = PREPARED;
   gdp_status status = GDP_OK;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  bool grid_only = false;  // outgrew its region in a batched launch: the slots refine it
 };
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -1272,11 +1273,39 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 // One worker per slot: its own stream (so that the jobs of different slots
 // overlap on the device) and pinned mirrors lent to the mesh it refines.
+// A slot's own stream, pinned mirrors and engine descriptor, lent to each job
+// it runs: nothing is allocated or freed per job (hipFree and hipHostFree
+// wait for the whole device, which would stall every other slot).
 struct ServerWorker {
   gdp_ctx ctx;
   DevCounters *h_cnt = nullptr;
   DevState *h_st = nullptr;
   DevCounters *h_hist = nullptr;
+  EngDesc *d_eng = nullptr;
+  int32_t *d_head = nullptr;
+  EngDesc *h_eng = nullptr;
+  std::thread th;
+};
+
+// Batched launches for small jobs: every arrived job with at most
+// engine_max_v input vertices is refined in one launch of the
+// single-workgroup engine together with the other such jobs (one workgroup
+// per job, largest first), so that a small job costs one workgroup for its
+// whole refinement instead of ~17 launches per round on a slot's stream.
+constexpr int kSrvEngMax = 512;  // jobs per batched launch
+// Off by default: measured on mixed job streams, a batched launch (as long as
+// its slowest job on one compute unit) holds one of the few hardware queues
+// that the slots' streams share, which delays their rounds more than the
+// launches it saves.
+constexpr int32_t kSrvEngineDefaultMaxV = 0;
+struct ServerEngine {
+  gdp_ctx ctx;
+  EngDesc *d_desc = nullptr, *h_desc = nullptr;  // [kSrvEngMax]
+  int32_t *d_head = nullptr;
+  DevState *h_st = nullptr;                      // [kSrvEngMax]
+  DevCounters *h_cnt = nullptr;                  // [kSrvEngMax]
+  DevCounters *h_hist = nullptr;                 // [kSrvEngMax * kHistCap]
+  int cus = 256;
   std::thread th;
 };
 
@@ -1284,6 +1313,8 @@ struct gdp_server {
   gdp_ctx *user = nullptr;  // the caller's context: finished meshes are handed over to it
   ServerMem *mem = nullptr;
   int max_slots = 0;
+  int32_t engine_max_v = 0;  // 0: every job on the slots
+  ServerEngine *eng = nullptr;
   std::mutex mu;
   std::condition_variable cv;
   std::map<uint64_t, Job *> jobs;
@@ -1360,6 +1391,168 @@ void complete_job(gdp_server *S, Job *J, gdp_status st) {
 // A worker: takes the oldest arrived job once its region fits, uploads it,
 // refines it to the end on its own stream (the plain refinement, whose
 // small final rounds run in the single-workgroup engine), hands it over.
+void free_server_engine(ServerEngine *E) {
+  if (!E) return;
+  if (E->ctx.stream) (void)hipStreamDestroy(E->ctx.stream);
+  if (E->d_desc) (void)hipFree(E->d_desc);
+  if (E->d_head) (void)hipFree(E->d_head);
+  if (E->h_desc) (void)hipHostFree(E->h_desc);
+  if (E->h_st) (void)hipHostFree(E->h_st);
+  if (E->h_cnt) (void)hipHostFree(E->h_cnt);
+  if (E->h_hist) (void)hipHostFree(E->h_hist);
+  delete E;
+}
+
+bool for_engine(const gdp_server *S, const Job *J) {
+  return S->engine_max_v > 0 && !J->grid_only && J->hm.nV <= S->engine_max_v;
+}
+
+// One batched launch over jobs already taken from the queue (regions held).
+void engine_batch(gdp_server *S, ServerEngine *E, std::vector<Job *> &B) {
+  hipStream_t s = E->ctx.stream;
+  std::vector<Job *> run;
+  for (Job *J : B) {
+    gdp_status st = admit_job(S, J, &E->ctx);
+    if (st != GDP_OK) {
+      if (J->mesh) gdp_mesh_free(J->mesh);
+      J->mesh = nullptr;
+      complete_job(S, J, st);
+      continue;
+    }
+    run.push_back(J);
+  }
+  if (run.empty()) return;
+  std::stable_sort(run.begin(), run.end(), [](const Job *a, const Job *b) { return a->hm.nT > b->hm.nT; });
+  const int n = (int)run.size();
+  for (int q = 0; q < n; q++) {
+    gdp_mesh *M = run[q]->mesh;
+    const gdp_params *P = &run[q]->P;
+    EngDesc &d = E->h_desc[q];
+    memset(&d, 0, sizeof d);
+    d.m = M->m;
+    d.w[0] = make_work(M, P, 0);
+    d.w[1] = make_work(M, P, 1);
+    d.B2 = run[q]->B2;
+    d.pm = P->priority_mode;
+    d.K = P->cand_cap_K;
+    d.f1 = P->prefilter_f1;
+    d.approx_n = P->cavity_approx_n;
+    d.max_rounds = P->max_rounds;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+            hipMemcpyAsync(E->d_desc, E->h_desc, sizeof(EngDesc) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemsetAsync(E->d_head, 0, sizeof(int32_t), s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(k_engine, dim3((unsigned)std::min(n, E->cus)), dim3(kEngBlock), 0, s, E->d_desc, n,
+                       E->d_head, 1 << 30);
+    ok = hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess;
+  }
+  for (int q = 0; ok && q < n; q++) {
+    gdp_mesh *M = run[q]->mesh;
+    ok = hipMemcpyAsync(&E->h_st[q], M->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s) == hipSuccess &&
+         hipMemcpyAsync(&E->h_cnt[q], M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s) == hipSuccess &&
+         hipMemcpyAsync(&E->h_hist[(size_t)q * kHistCap], M->d_hist, sizeof(DevCounters) * kHistCap,
+                        hipMemcpyDeviceToHost, s) == hipSuccess;
+  }
+  ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  float ms = 0.f;
+  if (ok) (void)hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (int q = 0; q < n; q++) {
+    Job *J = run[q];
+    gdp_mesh *M = J->mesh;
+    if (!ok) {
+      gdp_mesh_free(M);
+      J->mesh = nullptr;
+      complete_job(S, J, fail(&E->ctx, GDP_E_DEVICE, "batched launch failed"));
+      continue;
+    }
+    const DevState &d = E->h_st[q];
+    M->m.nV = d.nV; M->m.nT = d.nT; M->m.nS = d.nS; M->m.rounds = d.rounds;
+    M->serial = d.serial;
+    M->last_ms = ms;
+    const DevCounters *h = &E->h_hist[(size_t)q * kHistCap];
+    for (int r = 0; r < std::min(d.nhist, kHistCap); r++) M->stats.push_back(round_stats_of(h[r], &J->P));
+    if (d.halt == kHaltAbort) {
+      // out of its region's room: a slot refines it from the start
+      gdp_mesh_free(M);
+      J->mesh = nullptr;
+      std::lock_guard<std::mutex> g(S->mu);
+      J->grid_only = true;
+      J->state = Job::QUEUED;
+      S->running--;
+      S->queue.push_front(J);
+      S->cv.notify_all();
+      continue;
+    }
+    gdp_status st = status_of_halt(&E->ctx, d, E->h_cnt[q]);
+    if (st != GDP_OK && st != GDP_E_NOTERM) {
+      gdp_mesh_free(M);
+      J->mesh = nullptr;
+    }
+    complete_job(S, J, st);
+  }
+}
+
+// Takes every arrived small job whose region fits (first come, first
+// served), up to kSrvEngMax, and runs them in one batched launch.
+void engine_dispatcher(gdp_server *S, ServerEngine *E) {
+  (void)hipSetDevice(E->ctx.device);
+  for (;;) {
+    std::vector<Job *> B;
+    {
+      std::unique_lock<std::mutex> g(S->mu);
+      for (;;) {
+        for (auto it = S->queue.begin(); it != S->queue.end() && (int)B.size() < kSrvEngMax;) {
+          Job *Q = *it;
+          if (!for_engine(S, Q)) {
+            ++it;
+            continue;
+          }
+          size_t off;
+          bool got;
+          {
+            std::lock_guard<std::mutex> gm(S->mem->mu);
+            got = S->mem->take(Q->bytes, &off);
+          }
+          if (!got) break;
+          Q->off = off;
+          Q->state = Job::ACTIVE;
+          Q->t_admit = ms_since(S->t0);
+          S->running++;
+          B.push_back(Q);
+          it = S->queue.erase(it);
+        }
+        if (!B.empty()) break;
+        if (S->stop) {
+          bool any = false;
+          for (Job *Q : S->queue) any = any || for_engine(S, Q);
+          if (!any) return;  // what is left is the slots'
+          if (S->running == 0) {
+            // closing, and the room is held by meshes the caller owns
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
+              if (!for_engine(S, *it)) {
+                ++it;
+                continue;
+              }
+              (*it)->status = GDP_E_NOMEM;
+              (*it)->t_done = ms_since(S->t0);
+              (*it)->state = Job::DONE;
+              it = S->queue.erase(it);
+            }
+            S->cv.notify_all();
+            return;
+          }
+        }
+        S->cv.wait_for(g, std::chrono::milliseconds(1));
+      }
+    }
+    engine_batch(S, E, B);
+  }
+}
+
 void server_worker(gdp_server *S, ServerWorker *W) {
   (void)hipSetDevice(W->ctx.device);
   for (;;) {
@@ -1367,8 +1560,10 @@ void server_worker(gdp_server *S, ServerWorker *W) {
     {
       std::unique_lock<std::mutex> g(S->mu);
       for (;;) {
-        if (!S->queue.empty()) {
-          Job *Q = S->queue.front();
+        auto it = S->queue.begin();
+        while (it != S->queue.end() && for_engine(S, *it)) ++it;
+        if (it != S->queue.end()) {
+          Job *Q = *it;
           size_t off;
           bool got;
           {
@@ -1377,7 +1572,7 @@ void server_worker(gdp_server *S, ServerWorker *W) {
           }
           if (got) {
             Q->off = off;
-            S->queue.pop_front();
+            S->queue.erase(it);
             Q->state = Job::ACTIVE;
             Q->t_admit = ms_since(S->t0);
             S->running++;
@@ -1406,10 +1601,16 @@ void server_worker(gdp_server *S, ServerWorker *W) {
       M->h_cnt = W->h_cnt;
       M->h_st = W->h_st;
       M->h_hist = W->h_hist;
+      M->d_eng = W->d_eng;
+      M->d_head = W->d_head;
+      M->h_eng = W->h_eng;
       st = refine_loop(M, J->B2, &J->P);
-      M->h_cnt = nullptr;  // give the lent mirrors back; a mesh that left its region gets its own
+      M->h_cnt = nullptr;  // give the lent buffers back; a mesh that left its region gets its own mirrors
       M->h_st = nullptr;
       M->h_hist = nullptr;
+      M->d_eng = nullptr;
+      M->d_head = nullptr;
+      M->h_eng = nullptr;
       if (!M->arena && st == GDP_OK) st = alloc_host_mirrors(M);
     }
     if (st != GDP_OK && st != GDP_E_NOTERM && M) {
@@ -2014,7 +2215,9 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
     ok = hipStreamCreateWithFlags(&W->ctx.stream, hipStreamNonBlocking) == hipSuccess &&
          hipHostMalloc((void **)&W->h_cnt, sizeof(DevCounters)) == hipSuccess &&
          hipHostMalloc((void **)&W->h_st, sizeof(DevState)) == hipSuccess &&
-         hipHostMalloc((void **)&W->h_hist, sizeof(DevCounters) * kHistCap) == hipSuccess;
+         hipHostMalloc((void **)&W->h_hist, sizeof(DevCounters) * kHistCap) == hipSuccess &&
+         dalloc(&W->d_eng, 1) == hipSuccess && dalloc(&W->d_head, 1) == hipSuccess &&
+         hipHostMalloc((void **)&W->h_eng, sizeof(EngDesc)) == hipSuccess;
   }
   if (!ok) {
     for (ServerWorker *W : S->workers) {
@@ -2022,6 +2225,9 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
       if (W->h_cnt) (void)hipHostFree(W->h_cnt);
       if (W->h_st) (void)hipHostFree(W->h_st);
       if (W->h_hist) (void)hipHostFree(W->h_hist);
+      if (W->d_eng) (void)hipFree(W->d_eng);
+      if (W->d_head) (void)hipFree(W->d_head);
+      if (W->h_eng) (void)hipHostFree(W->h_eng);
       delete W;
     }
     if (S->mem->base) (void)hipFree(S->mem->base);
@@ -2029,8 +2235,49 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
     delete S;
     return fail(ctx, GDP_E_NOMEM, "server allocation failed");
   }
+  ServerEngine *E = ok ? new ServerEngine() : nullptr;
+  if (E) {
+    S->eng = E;
+    E->ctx.device = ctx->device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+      E->cus = prop.multiProcessorCount;
+    ok = hipStreamCreateWithFlags(&E->ctx.stream, hipStreamNonBlocking) == hipSuccess &&
+         dalloc(&E->d_desc, kSrvEngMax) == hipSuccess && dalloc(&E->d_head, 1) == hipSuccess &&
+         hipHostMalloc((void **)&E->h_desc, sizeof(EngDesc) * kSrvEngMax) == hipSuccess &&
+         hipHostMalloc((void **)&E->h_st, sizeof(DevState) * kSrvEngMax) == hipSuccess &&
+         hipHostMalloc((void **)&E->h_cnt, sizeof(DevCounters) * kSrvEngMax) == hipSuccess &&
+         hipHostMalloc((void **)&E->h_hist, sizeof(DevCounters) * kHistCap * kSrvEngMax) == hipSuccess;
+  }
+  if (!ok) {
+    free_server_engine(E);
+    for (ServerWorker *W : S->workers) {
+      (void)hipStreamDestroy(W->ctx.stream);
+      (void)hipHostFree(W->h_cnt);
+      (void)hipHostFree(W->h_st);
+      (void)hipHostFree(W->h_hist);
+      (void)hipFree(W->d_eng);
+      (void)hipFree(W->d_head);
+      (void)hipHostFree(W->h_eng);
+      delete W;
+    }
+    (void)hipFree(S->mem->base);
+    delete S->mem;
+    delete S;
+    return fail(ctx, GDP_E_NOMEM, "server allocation failed");
+  }
+  S->engine_max_v = kSrvEngineDefaultMaxV;
   for (ServerWorker *W : S->workers) W->th = std::thread(server_worker, S, W);
+  E->th = std::thread(engine_dispatcher, S, E);
   *out = S;
+  return GDP_OK;
+}
+
+gdp_status gdp_server_engine_jobs(gdp_server *srv, int32_t max_input_vertices) {
+  if (!srv || max_input_vertices < 0) return GDP_E_ARG;
+  std::lock_guard<std::mutex> g(srv->mu);
+  srv->engine_max_v = max_input_vertices;
+  srv->cv.notify_all();
   return GDP_OK;
 }
 
@@ -2114,6 +2361,8 @@ void gdp_server_destroy(gdp_server *srv) {
     srv->cv.notify_all();
   }
   for (ServerWorker *W : srv->workers) W->th.join();
+  if (srv->eng) srv->eng->th.join();
+  free_server_engine(srv->eng);
   for (auto &kv : srv->jobs) {
     if (kv.second->mesh) gdp_mesh_free(kv.second->mesh);
     delete kv.second;
@@ -2123,6 +2372,9 @@ void gdp_server_destroy(gdp_server *srv) {
     (void)hipHostFree(W->h_cnt);
     (void)hipHostFree(W->h_st);
     (void)hipHostFree(W->h_hist);
+    (void)hipFree(W->d_eng);
+    (void)hipFree(W->d_head);
+    (void)hipHostFree(W->h_eng);
     delete W;
   }
   ServerMem *sm = srv->mem;

@@ -109,6 +109,7 @@ def load() -> C.CDLL:
         "gdp_server_poll": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
         "gdp_server_wait": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
         "gdp_server_destroy": (None, [_VP]),
+        "gdp_server_engine_jobs": (S, [_VP, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -124,7 +125,7 @@ def exported_symbols() -> list[str]:
             "gdp_mesh_info_get", "gdp_mesh_quality", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
-            "gdp_server_wait", "gdp_server_destroy"]
+            "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -346,10 +347,16 @@ class Server:
     """Serving form: jobs arrive while others run; each finished job yields a
     device-resident Mesh."""
 
-    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int):
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, engine_max_vertices: int | None = None):
         self.ctx = ctx
         self._h = _VP()
         ctx.check(load().gdp_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(self._h)))
+        if engine_max_vertices is not None:
+            self.engine_jobs(engine_max_vertices)
+
+    def engine_jobs(self, max_input_vertices: int) -> None:
+        """Jobs up to this many input vertices run in batched single-workgroup launches (0: never)."""
+        self.ctx.check(load().gdp_server_engine_jobs(self._h, int(max_input_vertices)))
 
     def prepare(self, xy, seg, ratio_bound_sq: float, params: gdp_params | None = None) -> int:
         p, keep = _pslg(xy, seg)

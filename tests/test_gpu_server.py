@@ -22,10 +22,14 @@ def _jobs(count, seed, n_min=200, n_max=3000):
     return workloads.batch_config3(count, seed=seed, n_min=n_min, n_max=n_max)
 
 
-def test_server_matches_oracle(ctx):
+ENGINE_PATHS = {"slots": 0, "batched": 1 << 30, "split": 1500}
+
+
+@pytest.mark.parametrize("path", list(ENGINE_PATHS))
+def test_server_matches_oracle(ctx, path):
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(20, seed=21)
-    srv = gdp2d.Server(ctx, 2 << 30, 8)
+    srv = gdp2d.Server(ctx, 2 << 30, 8, engine_max_vertices=ENGINE_PATHS[path])
     ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     print(f"[server] {len(ids)} jobs submitted", flush=True)
     for p, j in zip(ps, ids):
@@ -38,14 +42,15 @@ def test_server_matches_oracle(ctx):
     srv.close()
 
 
-def test_server_alone_equals_mix(ctx):
+@pytest.mark.parametrize("path", list(ENGINE_PATHS))
+def test_server_alone_equals_mix(ctx, path):
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(30, seed=22, n_max=8000)
     x = ps[7]
-    alone_srv = gdp2d.Server(ctx, 1 << 30, 4)
+    alone_srv = gdp2d.Server(ctx, 1 << 30, 4, engine_max_vertices=0)
     m_alone, rc, _ = alone_srv.wait(alone_srv.submit(x.xy, x.seg, x.ratio_bound_sq))
     assert rc == 0
-    mix = gdp2d.Server(ctx, 4 << 30, 12)
+    mix = gdp2d.Server(ctx, 4 << 30, 12, engine_max_vertices=ENGINE_PATHS[path])
     ids = [mix.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     got = [mix.wait(j) for j in ids]
     assert all(rc == 0 for _, rc, _ in got)
@@ -59,11 +64,12 @@ def test_server_alone_equals_mix(ctx):
     alone_srv.close()
 
 
-def test_server_tight_budget_and_slots(ctx):
+@pytest.mark.parametrize("path", ["slots", "batched"])
+def test_server_tight_budget_and_slots(ctx, path):
     """Room for about one job at a time: jobs wait for room, all finish."""
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(8, seed=23, n_min=1000, n_max=2000)
-    srv = gdp2d.Server(ctx, 8 << 20, 2)
+    srv = gdp2d.Server(ctx, 8 << 20, 2, engine_max_vertices=ENGINE_PATHS[path])
     ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     for p, j in zip(ps, ids):
         m, rc, _ = srv.wait(j)
