@@ -630,8 +630,9 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   }
   {
     Prof pr(M, P_FINISH);
-    // at most 1024 workgroups: each one arrives on one counter at its end
-    hipLaunchKernelGGL(k_finish, dim3(std::min(stride_grid(ncand, bs), 1024u)), dim3(bs), 0, s, m, w);
+    // at most 256 workgroups: each one arrives on one counter at its end
+    // (atomics on one address are serialised, ~12 ns each)
+    hipLaunchKernelGGL(k_finish, dim3(std::min(stride_grid(ncand, bs), 256u)), dim3(bs), 0, s, m, w);
   }
   HIPCHECK(hipGetLastError());
   return GDP_OK;

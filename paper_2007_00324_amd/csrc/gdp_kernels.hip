@@ -580,7 +580,9 @@ __device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c
       w.cc.state[c] = kStDone;
       return 0;
     }
+    // the neighbours are loaded with the vertices (needed unless p is found here)
     int4 tri = m.tv[cur];
+    const int4 nb = m.tn[cur];
     double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
     int s0 = orient_pts(A, B, p), s1 = orient_pts(B, C, p), s2 = orient_pts(C, A, p);
     if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
@@ -593,7 +595,6 @@ __device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c
       w.cc.state[c] = kStFound;
       return 0;
     }
-    int4 nb = m.tn[cur];
     int s[3] = {s0, s1, s2};
     int first_neg = -1, next = -1;
     for (int e = 0; e < 3; e++) {
@@ -861,6 +862,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
   } else {
     int k = S.elem[ci];
     res.mid_cand = 1;
+    const int a0 = w.sadj[2 * k], a1 = w.sadj[2 * k + 1];  // with the subsegment's record
     SplitPt r = seg_split(m, k, w.pm);
     S.key[ci] = r.key;
     p = make_double2(r.px, r.py);
@@ -872,7 +874,6 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
       S.state[ci] = st | kStDone;
       return res;
     }
-    int a0 = w.sadj[2 * k], a1 = w.sadj[2 * k + 1];
     if (a0 >= 0) seeds[nseeds++] = a0 >> 2;
     if (a1 >= 0) seeds[nseeds++] = a1 >> 2;
     skip_k = k;
@@ -1679,14 +1680,18 @@ __device__ __forceinline__ void round_end(const Work &w) {
   DevCounters *c = w.cnt;
   // fold the stat lines into the counters and clear them (read-and-clear
   // atomics: the lines were written by atomics)
-  if (threadIdx.x < kStFields) {
-    const int f = threadIdx.x;
-    uint64_t acc = 0;
-    for (int i = 0; i < kStatStripes; i++) {
-      uint64_t x = atomicExch((unsigned long long *)&w.stat[i].v[f], 0ull);
-      acc = f == kStCavMax ? max(acc, x) : acc + x;
+  if (threadIdx.x < kStFields) s_fold[threadIdx.x] = 0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 4 * kStatStripes; idx += blockDim.x) {
+    // one stripe, four of its fields (independent read-and-clear atomics),
+    // combined in LDS
+    const int i = idx >> 2, f0 = (idx & 3) * 4;
+    for (int f = f0; f < f0 + 4 && f < kStFields; f++) {
+      const uint64_t x = atomicExch((unsigned long long *)&w.stat[i].v[f], 0ull);
+      if (!x) continue;
+      if (f == kStCavMax) atomicMax((unsigned long long *)&s_fold[f], (unsigned long long)x);
+      else atomicAdd((unsigned long long *)&s_fold[f], (unsigned long long)x);
     }
-    s_fold[f] = acc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
