@@ -29,7 +29,7 @@ class _Mesh(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("encroach_mode", C.c_int32),
-                ("max_edge_len_sq", C.c_double)]
+                ("split_mode", C.c_int32), ("max_edge_len_sq", C.c_double)]
 
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident",
@@ -88,6 +88,8 @@ def load() -> C.CDLL:
     lib.orc_mesh_quality.restype = None
     lib.orc_encroaches.argtypes = [C.c_int32, P2, P2, P2]
     lib.orc_encroaches.restype = C.c_int
+    lib.orc_midpoint.argtypes = [C.POINTER(_Mesh), C.c_int32, P2, P2, C.POINTER(C.c_uint64), C.c_int32, C.c_int32]
+    lib.orc_midpoint.restype = None
     lib.orc_check_subsegments.argtypes = [C.POINTER(_Mesh), P2, C.POINTER(C.c_int32), C.c_char_p, C.c_int32]
     lib.orc_check_subsegments.restype = C.c_int64
     lib.orc_area_sum.argtypes = [C.POINTER(_Mesh)]
@@ -199,6 +201,12 @@ class OracleMesh:
     def check_quality(self, B2, L2=0.0): return load().orc_check_quality(self._p, B2, L2)
     def check_encroached(self, mode=0): return load().orc_check_encroached(self._p, mode)
 
+    def split_point(self, k: int, split_mode: int = 0):
+        """Splitting point and key of subsegment k (midpoint, or concentric shells)."""
+        x, y, key = C.c_double(0.0), C.c_double(0.0), C.c_uint64(0)
+        load().orc_midpoint(self._p, k, C.byref(x), C.byref(y), C.byref(key), 0, split_mode)
+        return x.value, y.value, key.value
+
     def quality(self, B2, L2=0.0):
         """(bad triangle count, area they cover) under the criteria."""
         n, a = C.c_int64(0), C.c_double(0.0)
@@ -233,10 +241,10 @@ def build_cdt(xy: np.ndarray, seg: np.ndarray) -> OracleMesh:
 def refine(mesh: OracleMesh, ratio_bound_sq: float, cand_cap_K: int = 0, priority_mode: int = 0,
            max_rounds: int = 0, stats_cap: int = 1 << 16, raise_on_error: bool = True,
            prefilter_f1: int = 0, cavity_approx_n: int = 0, encroach_mode: int = 0,
-           max_edge_len_sq: float = 0.0) -> int:
+           max_edge_len_sq: float = 0.0, split_mode: int = 0) -> int:
     lib = load()
     prm = _Params(cand_cap_K, priority_mode, max_rounds, prefilter_f1, cavity_approx_n, encroach_mode,
-                  float(max_edge_len_sq))
+                  split_mode, float(max_edge_len_sq))
     st = (_Stats * stats_cap)()
     ns = C.c_int32(0)
     err = C.create_string_buffer(256)

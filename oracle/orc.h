@@ -66,6 +66,8 @@ typedef struct orc_params {
   int32_t cavity_approx_n;/* n > 0: drop circumcenters that lose a mark on the first
                              n triangles of their cavity growth order */
   int32_t encroach_mode;  /* 0: diametric circle (Ruppert); 1: diametric lens (Chew) */
+  int32_t split_mode;     /* 0: subsegment midpoints; 1: concentric shells around input
+                             vertices (see orc_midpoint) */
   double max_edge_len_sq; /* 0 = off; else a triangle with an edge longer than l
                              (squared length > l^2) is bad as well */
 } orc_params;
@@ -113,7 +115,7 @@ void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq, doubl
                       double *px, double *py, int32_t *bad, uint64_t *key,
                       int32_t priority_mode);
 void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t *key,
-                  int32_t priority_mode);
+                  int32_t priority_mode, int32_t split_mode);
 
 /* Checkers.  Each returns the number of violations found. */
 int64_t orc_check_topology(const orc_mesh *m, char *err, int32_t errlen);

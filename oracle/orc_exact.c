@@ -360,14 +360,33 @@ static uint32_t q31(double x) {
   return (uint32_t)((b >> 32) & 0x7fffffffu);
 }
 
+/* Splitting point of subsegment k.  Midpoint, or with split_mode 1
+   (concentric shells): when exactly one endpoint c is an input vertex, the
+   point on the subsegment at distance 2^j from c, 2^j the power of two
+   nearest to half its length (2^e if len/2 = f 2^e with f > 3/4, else
+   2^(e-1)), so that subsegments meeting at a small input angle are cut on
+   common circles around c. */
 void orc_midpoint(const orc_mesh *m, int32_t k, double *mx, double *my, uint64_t *key,
-                  int32_t priority_mode) {
+                  int32_t priority_mode, int32_t split_mode) {
   int32_t ia = m->sv[2 * k], ib = m->sv[2 * k + 1];
   double ax = m->x[ia], ay = m->y[ia], bx = m->x[ib], by = m->y[ib];
-  *mx = (ax + bx) * 0.5;
-  *my = (ay + by) * 0.5;
   double dx = bx - ax, dy = by - ay;
   double len2 = dx * dx + dy * dy;
+  int ina = m->vkind[ia] == ORC_VK_INPUT, inb = m->vkind[ib] == ORC_VK_INPUT;
+  if (split_mode == 1 && ina != inb) {
+    double cx = ina ? ax : bx, cy = ina ? ay : by;
+    double ox = ina ? bx : ax, oy = ina ? by : ay;
+    double len = sqrt(len2);
+    int e;
+    double f = frexp(len * 0.5, &e);
+    double d = f > 0.75 ? ldexp(1.0, e) : ldexp(1.0, e - 1);
+    double t = d / len;
+    *mx = cx + (ox - cx) * t;
+    *my = cy + (oy - cy) * t;
+  } else {
+    *mx = (ax + bx) * 0.5;
+    *my = (ay + by) * 0.5;
+  }
   uint64_t q = priority_mode == 1 ? 0 : (uint64_t)q31(len2);
   *key = ((uint64_t)1 << 63) | (q << 32) | (uint64_t)orc_perm32((uint32_t)k);
 }

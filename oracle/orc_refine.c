@@ -345,7 +345,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
       if (enc[k]) {
         double mx, my;
         uint64_t key;
-        orc_midpoint(m, k, &mx, &my, &key, pm);
+        orc_midpoint(m, k, &mx, &my, &key, pm, prm->split_mode);
         keys[nk++] = key;
       }
     for (int32_t t = 0; t < nT; t++)
@@ -357,7 +357,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
     if (enc[k]) {
       double mx, my;
       uint64_t key;
-      orc_midpoint(m, k, &mx, &my, &key, pm);
+      orc_midpoint(m, k, &mx, &my, &key, pm, prm->split_mode);
       if (key >= thresh) { mflag[k] = 1; if (st) st->n_kept_mid++; }
     }
 
@@ -500,7 +500,7 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
     if (st) st->n_mid_cand++;
     double mx, my;
     uint64_t key;
-    orc_midpoint(m, k, &mx, &my, &key, pm);
+    orc_midpoint(m, k, &mx, &my, &key, pm, prm->split_mode);
     int32_t a = m->sv[2 * k], b = m->sv[2 * k + 1];
     if ((mx == m->x[a] && my == m->y[a]) || (mx == m->x[b] && my == m->y[b])) {
       if (st) st->n_unsplittable++;
@@ -699,6 +699,7 @@ int orc_refine(orc_mesh *m, double B2, const orc_params *p, orc_round_stats *sta
   if (!m || !p || !(B2 > 0.0) || !isfinite(B2)) { set_err(err, errlen, "bad arguments"); return ORC_E_ARG; }
   if ((p->prefilter_f1 != 0 && p->prefilter_f1 != 1) || p->cavity_approx_n < 0 || p->cand_cap_K < 0 ||
       (p->priority_mode != 0 && p->priority_mode != 1) || (p->encroach_mode != 0 && p->encroach_mode != 1) ||
+      (p->split_mode != 0 && p->split_mode != 1) ||
       !(p->max_edge_len_sq >= 0.0) || !isfinite(p->max_edge_len_sq)) {
     set_err(err, errlen, "unsupported parameter");
     return ORC_E_ARG;

@@ -171,3 +171,75 @@ def test_bad_area_refined():
         assert n == int(bad.sum())
         assert abs(a - area[bad].sum()) <= 1e-12 * max(1.0, abs(a))
     assert n > 0 and 0.0 < a < 1.0
+
+
+def spider(deg, n_spokes=4):
+    p = workloads.spokes(deg, n_spokes)
+    return p.xy, p.seg
+
+
+def test_concentric_shell_points():
+    """Concentric shells: a subsegment with exactly one input endpoint c is cut
+    at distance 2^j from c, 2^j the power of two nearest to half its length;
+    other subsegments at their midpoint."""
+    import oracle
+    xy, seg = spider(30)
+    m = oracle.build_cdt(xy, seg)
+    assert oracle.refine(m, 2.0, max_rounds=4, raise_on_error=False) == -5  # stopped with work left
+    arr = m.arrays()
+    vk, sv, pxy = arr["vkind"], arr["sv"], arr["xy"]
+    n_shell = 0
+    for k in range(sv.shape[0]):
+        a, b = sv[k]
+        x, y, _ = m.split_point(k, 1)
+        xm, ym, _ = m.split_point(k, 0)
+        assert (xm, ym) == ((pxy[a, 0] + pxy[b, 0]) * 0.5, (pxy[a, 1] + pxy[b, 1]) * 0.5)
+        if (vk[a] == 0) == (vk[b] == 0):
+            assert (x, y) == (xm, ym)
+            continue
+        c, o = (a, b) if vk[a] == 0 else (b, a)
+        C_, O_, P_ = [(F(float(q[0])), F(float(q[1]))) for q in (pxy[c], pxy[o], (x, y))]
+        L2 = (O_[0] - C_[0]) ** 2 + (O_[1] - C_[1]) ** 2
+        D2 = (P_[0] - C_[0]) ** 2 + (P_[1] - C_[1]) ** 2
+        half = math.sqrt(float(L2)) / 2
+        j = round(math.log2(float(D2)) / 2)
+        assert abs(float(D2) / 4.0 ** j - 1.0) < 1e-14  # distance 2^j up to rounding
+        # nearest power of two to len/2 (ties and near-ties excluded by the draw)
+        lo = 2.0 ** math.floor(math.log2(half))
+        want = 2 * lo if (2 * lo - half) < (half - lo) else lo
+        assert 2.0 ** j == want
+        # on the subsegment, strictly inside
+        cross = (O_[0] - C_[0]) * (P_[1] - C_[1]) - (O_[1] - C_[1]) * (P_[0] - C_[0])
+        assert abs(float(cross)) <= 1e-15 * math.sqrt(float(L2))  # within a few ulp of the line
+        assert 0 < float(D2) < float(L2)
+        n_shell += 1
+    assert n_shell > 0
+
+
+@pytest.mark.parametrize("deg", [30, 60])
+@pytest.mark.parametrize("split_mode", [0, 1])
+def test_small_angle_inputs(deg, split_mode):
+    """Spokes 30 and 60 degrees apart: both splitting rules terminate with a
+    valid mesh and no bad triangle at B = sqrt(2)."""
+    import oracle
+    xy, seg = spider(deg, n_spokes=4 if deg == 30 else 3)
+    m = oracle.build_cdt(xy, seg)
+    assert oracle.refine(m, 2.0, split_mode=split_mode) == 0
+    assert m.check_topology()[0] == 0
+    assert m.check_local_delaunay() == 0
+    assert m.check_quality(2.0) == 0
+    assert m.check_encroached() == 0
+    assert m.quality(2.0) == (0, 0.0)
+    assert abs(m.area() - 1.0) < 1e-12
+
+
+def test_shells_c0():
+    import oracle
+    p = workloads.config0()
+    m = oracle.build_cdt(p.xy, p.seg)
+    assert oracle.refine(m, p.ratio_bound_sq, split_mode=1) == 0
+    assert m.check_topology()[0] == 0
+    assert m.check_local_delaunay() == 0
+    assert m.check_quality(p.ratio_bound_sq) == 0
+    assert m.check_encroached() == 0
+    assert abs(m.area() - 1.0) < 1e-12

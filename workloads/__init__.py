@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     config2,
     scaled_config1,
     scaled_config2,
+    spokes,
     near_edge_point,
     random_small,
     manifest_hash,

@@ -448,3 +448,20 @@ def serving_jobs(count: int, seed: int = 4, n_min: int = 1_000, n_max: int = 200
         with mp.get_context("fork").Pool(workers) as pool:
             return pool.map(_serving_job_args, args, chunksize=2)
     return [serving_job(*a) for a in args]
+
+
+def spokes(deg: float, n_spokes: int = 4, n_free: int = 200, seed: int = 3, length: float = 0.45) -> PSLG:
+    """Small input angles: the square, n_free uniform points and n_spokes segments
+    of the given length from one input vertex at (0.31, 0.37), deg degrees apart
+    (the first at 10 degrees).  B = sqrt(2)."""
+    import math
+    rng = _rng(seed)
+    pts = CORNERS.tolist() + [[0.31, 0.37]]
+    seg = BOUNDARY.tolist()
+    for i in range(n_spokes):
+        a = math.radians(10.0 + deg * i)
+        pts.append([0.31 + length * math.cos(a), 0.37 + length * math.sin(a)])
+        seg.append([4, len(pts) - 1])
+    pts += rng.uniform(0.02, 0.98, size=(n_free, 2)).tolist()
+    return PSLG(f"spokes_{deg:g}deg", np.array(pts, dtype=np.float64), np.array(seg, dtype=np.int32), 2.0,
+                {"deg": deg, "n_spokes": n_spokes, "n_free": n_free, "seed": seed})
