@@ -91,7 +91,8 @@ def cpu_baseline(p, n_points: int, n_segments: int) -> dict:
 
 def criteria_leg(ctx, init, work, p) -> dict:
     """The other quality criteria of Section 4.1 on the same resident initial CDT:
-    Chew's diametric lenses, an edge-length bound l, and the angle bound theta = 20
+    Chew's diametric lenses, concentric-shell subsegment splitting, an edge-length
+    bound l, and the angle bound theta = 20
     degrees of Table 1 (B^2 = 1 / (4 sin^2 theta)); each refinement timed alone
     (one warmup, then the median of three), with the bad-area measure of the
     result under its own criteria."""
@@ -102,6 +103,7 @@ def criteria_leg(ctx, init, work, p) -> dict:
     modes = [
         ("ruppert_B=sqrt2", p.ratio_bound_sq, dict()),
         ("chew_lens_B=sqrt2", p.ratio_bound_sq, dict(encroach_mode=1)),
+        ("concentric_shells_B=sqrt2", p.ratio_bound_sq, dict(split_mode=1)),
         ("ruppert_B=sqrt2_l=0.001", p.ratio_bound_sq, dict(max_edge_len_sq=1e-6)),
         ("ruppert_theta=20deg", theta20, dict()),
         ("chew_lens_theta=20deg_l=0.001", theta20, dict(encroach_mode=1, max_edge_len_sq=1e-6)),

@@ -103,7 +103,10 @@ typedef struct {
                                point strictly inside its diametric circle (Ruppert);
                                1: strictly inside its diametric lens, the points that
                                see it under more than 120 degrees (Chew) */
-  int32_t reserved[1];
+  int32_t split_mode;       /* 0: subsegments split at their midpoint; 1: concentric
+                               shells: a subsegment with exactly one input-vertex
+                               endpoint c is split at distance 2^j from c, 2^j the
+                               power of two nearest to half its length */
   double max_edge_len_sq;   /* 0 = off; else l^2 for the edge-length bound l: a
                                triangle with an edge longer than l is bad too */
 } gdp_params;

@@ -313,6 +313,7 @@ Work make_work(gdp_mesh *M, const gdp_params *P, int parity) {
   memset(&w, 0, sizeof w);  // no stray padding bytes (graph keys hash the struct)
   w.L2 = P->max_edge_len_sq;
   w.enc_mode = P->encroach_mode;
+  w.split_mode = P->split_mode;
   w.st = M->d_st;
   w.cnt = M->d_cnt;
   w.stat = M->d_stat;
@@ -1958,6 +1959,7 @@ static gdp_status check_params(gdp_ctx *ctx, const gdp_params *params, gdp_param
   if (P.rounds_per_sync < 0 || P.rounds_per_sync > kHistCap)
     return fail(ctx, GDP_E_ARG, "rounds_per_sync must be in [0, 64]");
   if (P.encroach_mode != 0 && P.encroach_mode != 1) return fail(ctx, GDP_E_ARG, "encroach_mode must be 0 or 1");
+  if (P.split_mode != 0 && P.split_mode != 1) return fail(ctx, GDP_E_ARG, "split_mode must be 0 or 1");
   if (!(P.max_edge_len_sq >= 0.0) || !std::isfinite(P.max_edge_len_sq))
     return fail(ctx, GDP_E_ARG, "max_edge_len_sq must be finite and >= 0");
   return GDP_OK;

@@ -49,6 +49,7 @@ struct Work {
   StatLine *stat;      // [kStatStripes] statistics of the running round
   double L2;           // edge-length bound l^2 (0: off)
   int32_t enc_mode;    // 0: diametric circle, 1: diametric lens
+  int32_t split_mode;  // 0: midpoints, 1: concentric shells
   uint64_t *sel;       // [3] radix select: key prefix, prefix mask, keys still to take
   int32_t pm;
 };

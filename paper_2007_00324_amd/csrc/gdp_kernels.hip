@@ -111,14 +111,31 @@ __device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, doubl
   return r;
 }
 
-__device__ SplitPt seg_split(const DevMesh &m, int k, int pm) {
+// Splitting point of subsegment k: its midpoint, or with split_mode 1
+// (concentric shells) when exactly one endpoint c is an input vertex, the
+// point at distance 2^j from c, 2^j the power of two nearest to half the
+// length (2^e if len/2 = f 2^e with f > 3/4, else 2^(e-1)), so that
+// subsegments meeting at a small input angle are cut on common circles.
+__device__ SplitPt seg_split(const DevMesh &m, int k, int pm, int split_mode) {
   int2 s = m.sv[k];
   double2 A = m.vxy[s.x], B = m.vxy[s.y];
   SplitPt r;
-  r.px = (A.x + B.x) * 0.5;
-  r.py = (A.y + B.y) * 0.5;
   double dx = B.x - A.x, dy = B.y - A.y;
   double len2 = dx * dx + dy * dy;
+  const bool ina = split_mode == 1 && m.vkind[s.x] == 0, inb = split_mode == 1 && m.vkind[s.y] == 0;
+  if (ina != inb) {
+    const double2 C = ina ? A : B, O = ina ? B : A;
+    const double len = sqrt(len2);
+    int e;
+    const double f = frexp(len * 0.5, &e);
+    const double d = f > 0.75 ? ldexp(1.0, e) : ldexp(1.0, e - 1);
+    const double t = d / len;
+    r.px = C.x + (O.x - C.x) * t;
+    r.py = C.y + (O.y - C.y) * t;
+  } else {
+    r.px = (A.x + B.x) * 0.5;
+    r.py = (A.y + B.y) * 0.5;
+  }
   uint64_t q = pm == 1 ? 0 : (uint64_t)q31(len2);
   r.key = (1ull << 63) | (q << 32) | (uint64_t)perm32((uint32_t)k);
   r.bad = 1;
@@ -483,7 +500,7 @@ __device__ __forceinline__ void gather_part(const DevMesh &m, const Work &w, int
       w.keys[c] = w.cc.key[c];
     } else {
       int j = c - ncc;
-      SplitPt r = seg_split(m, w.mid.elem[j], pm);
+      SplitPt r = seg_split(m, w.mid.elem[j], pm, w.split_mode);
       w.mid.key[j] = r.key;
       w.mid.p[j] = make_double2(r.px, r.py);
       w.keys[c] = r.key;
@@ -863,7 +880,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
     int k = S.elem[ci];
     res.mid_cand = 1;
     const int a0 = w.sadj[2 * k], a1 = w.sadj[2 * k + 1];  // with the subsegment's record
-    SplitPt r = seg_split(m, k, w.pm);
+    SplitPt r = seg_split(m, k, w.pm, w.split_mode);
     S.key[ci] = r.key;
     p = make_double2(r.px, r.py);
     S.p[ci] = p;

@@ -40,7 +40,7 @@ class gdp_params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
                 ("profile_kernels", C.c_int32), ("reserve_mode", C.c_int32), ("rounds_per_sync", C.c_int32),
-                ("tail_engine_max", C.c_int32), ("encroach_mode", C.c_int32), ("reserved", C.c_int32 * 1),
+                ("tail_engine_max", C.c_int32), ("encroach_mode", C.c_int32), ("split_mode", C.c_int32),
                 ("max_edge_len_sq", C.c_double)]
 
 
@@ -141,10 +141,11 @@ def _pslg(xy, seg):
 
 def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
                 prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0,
-                tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0) -> gdp_params:
+                tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0, split_mode=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
     p.encroach_mode = encroach_mode
+    p.split_mode = split_mode
     p.max_edge_len_sq = float(max_edge_len_sq)
     p.reserve_mode = reserve_mode
     p.rounds_per_sync = rounds_per_sync

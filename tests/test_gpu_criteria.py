@@ -28,11 +28,14 @@ CASES = {
     "rand_300": lambda: workloads.random_small(32, 300, 20),
     "knn_2000": lambda: workloads.random_small(33, 2000, 100, pairing="knn"),
     "circles_small": lambda: workloads.scaled_config2(6, 40, 100, seed=5),
+    "spokes_30": lambda: workloads.spokes(30),
 }
 MODES = {
     "length": dict(max_edge_len_sq=0.004),
     "lens": dict(encroach_mode=1),
     "lens_length": dict(encroach_mode=1, max_edge_len_sq=0.002),
+    "shells": dict(split_mode=1),
+    "shells_lens_length": dict(split_mode=1, encroach_mode=1, max_edge_len_sq=0.002),
 }
 
 
