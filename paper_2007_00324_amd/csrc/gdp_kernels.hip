@@ -926,12 +926,14 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
 // only by the scan, the walk and the circumcenter cavities), so its length
 // is read from device memory.  The loop is uniform over the workgroup so
 // that pool space and statistics are handled once per wave.
+// Candidates [lo, hi) of the class (hi < 0: to the end of the list); tid is
+// the thread's index in the group that runs the loop (its LDS slice).
 __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int is_cc, int32_t *lds, int ls, int cap,
-                                            const Lanes &L) {
-  const int tid = threadIdx.x;
-  const int n = is_cc ? w.cnt->ncc : w.cnt->nmk;
+                                            const Lanes &L, int lo = 0, int hi = -1, int tid = -1) {
+  if (tid < 0) tid = threadIdx.x;
+  const int n = hi >= 0 ? hi : (is_cc ? w.cnt->ncc : w.cnt->nmk);
   CandSet S = is_cc ? w.cc : w.mid;
-  for (int base = L.base0; base < n; base += L.stride) {
+  for (int base = lo + L.base0; base < n; base += L.stride) {
     int ci = base + tid;
     CavRes r{0, 0, 0, 0, 0, 0, 0};
     if (ci < n) r = cavity_one(m, w, lds, ls, cap, tid, ci, is_cc);
@@ -1985,6 +1987,10 @@ __device__ void engine_big(const DevMesh &m, const Work &w, BigShared &sh, int p
 // clustered points, and the cooperative path runs them one at a time here).
 constexpr int kEngCavThreads = kEngBlock / 2;
 constexpr int kEngCap = 48;
+// midpoint cavities listed before the circumcenter cavities run on the other
+// half of the workgroup at the same time, in slices of their own
+constexpr int kEngMidCap = 24;
+constexpr int kEngMidLdsWords = kEngMidCap * kEngCavThreads;
 constexpr int kEngLdsWords = (kEngCap * kEngCavThreads > (int)(sizeof(BigShared) / 4)) ? kEngCap * kEngCavThreads
                                                                                      : (int)(sizeof(BigShared) / 4);
 static_assert(kApproxMax * kEngBlock <= kEngLdsWords, "prefilter slices fit in the engine's LDS");
@@ -1992,7 +1998,7 @@ static_assert(2 * kEngRankMax <= kEngLdsWords, "winner keys fit in the engine's 
 
 // Rounds of one mesh until it halts or round_limit rounds have completed.
 __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
-  __shared__ int s_ser, s_full, s_halt;
+  __shared__ int s_ser, s_full, s_halt, s_mid0;
   const DevMesh &m = d.m;
   DevState *st = d.w[0].st;
   const Lanes L = block_lanes();
@@ -2040,14 +2046,24 @@ __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
         prefilter_part(m, w, mode, d.approx_n, lds, L);
         phase_sync();
       }
-    // R5/R6 cavities with their marks
+    // R5/R6 cavities with their marks: the circumcenters on one half of the
+    // workgroup while the midpoints listed so far (collection and walks) run
+    // on the other; then the midpoints the circumcenter cavities flagged.
+    // (Marks are order free and a midpoint cavity depends on no other.)
     BigShared &sh = *reinterpret_cast<BigShared *>(lds);
     const Lanes LC{0, kEngCavThreads, 0};
-    if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 1, lds, kEngCavThreads, kEngCap, LC);
+    if (threadIdx.x == 0) s_mid0 = w.cnt->nmk;
+    __syncthreads();
+    const int mid0 = s_mid0;
+    if (threadIdx.x < kEngCavThreads)
+      cavity_part(m, w, 1, lds, kEngCavThreads, kEngCap, LC);
+    else
+      cavity_part(m, w, 0, lds + kEngLdsWords, kEngCavThreads, kEngMidCap, LC, 0, mid0,
+                  (int)threadIdx.x - kEngCavThreads);
     phase_sync();
     engine_big(m, w, sh, 0);
     phase_sync();
-    if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 0, lds, kEngCavThreads, kEngCap, LC);
+    if (threadIdx.x < kEngCavThreads) cavity_part(m, w, 0, lds, kEngCavThreads, kEngCap, LC, mid0);
     phase_sync();
     engine_big(m, w, sh, 1);
     phase_sync();
@@ -2084,7 +2100,7 @@ __device__ void engine_mesh(const EngDesc &d, int32_t *lds, int round_limit) {
 // runs each for at most round_limit rounds.
 __global__ __launch_bounds__(kEngBlock) void k_engine(const EngDesc *descs, int n_mesh, int32_t *head,
                                                       int round_limit) {
-  __shared__ int32_t lds[kEngLdsWords];
+  __shared__ int32_t lds[kEngLdsWords + kEngMidLdsWords];
   __shared__ int s_i;
   for (;;) {
     __syncthreads();
