@@ -1770,7 +1770,9 @@ __device__ __forceinline__ void round_end(const Work &w) {
 
 __device__ __forceinline__ void finish_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk, nV = w.st->nV;
-  bool aborted = w.cnt->abort != 0;
+  // an abandoned round, or one that inserts nothing (the refinement stops
+  // there), leaves the pending flags as they were
+  bool aborted = w.cnt->abort != 0 || w.cnt->nwin == 0;
   for (int base = L.base0; base < n; base += L.stride) {
     int c = base + threadIdx.x;
     if (c < n) finish_one(m, w, c, ncc, nV, aborted);

@@ -13,7 +13,7 @@ def oracle_run(pslg, cand_cap_K=0, priority_mode=0, max_rounds=0, prefilter_f1=0
                encroach_mode=0, max_edge_len_sq=0.0, split_mode=0):
     import oracle
     m = oracle.build_cdt(pslg.xy, pslg.seg)
-    rc = oracle.refine(m, pslg.ratio_bound_sq, cand_cap_K=cand_cap_K, priority_mode=priority_mode,
+    rc = oracle.refine(m, pslg.ratio_bound_sq, cand_cap_K=cand_cap_K, priority_mode=priority_mode, raise_on_error=False,
                        max_rounds=max_rounds, prefilter_f1=prefilter_f1, cavity_approx_n=cavity_approx_n,
                        encroach_mode=encroach_mode, max_edge_len_sq=max_edge_len_sq, split_mode=split_mode)
     return m, rc

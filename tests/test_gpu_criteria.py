@@ -108,3 +108,22 @@ def test_criteria_parity_200k(ctx, mode):
     assert not bad, bad
     n_o, a_o = om.quality(p.ratio_bound_sq, kw.get("max_edge_len_sq", 0.0))
     assert gm.quality(p.ratio_bound_sq, kw.get("max_edge_len_sq", 0.0)) == (n_o, a_o) == (0, 0.0)
+
+
+@pytest.mark.parametrize("engine", [0, -1])
+def test_small_angle_stall_parity(ctx, engine):
+    """Spokes 15 degrees apart: refinement runs until a round has candidates
+    but can insert nothing (GDP_E_STALL on both sides), with identical meshes
+    and round counters up to that point."""
+    from paper_2007_00324_amd import gdp2d
+    p = workloads.spokes(15)
+    om, orc_rc = oracle_run(p)
+    assert orc_rc == -6
+    gm = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg)
+    with pytest.raises(gdp2d.GdpError) as e:
+        gdp2d.gdp_mesh_refine(ctx, gm, p.ratio_bound_sq, gdp2d.make_params(tail_engine_max=engine))
+    assert e.value.code == -6
+    bad = diff_arrays(om.arrays(), gm.arrays())
+    assert not bad, bad
+    sd = diff_stats(om.stats, gm.round_stats())
+    assert not sd, sd
