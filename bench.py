@@ -339,7 +339,7 @@ def main() -> int:
     ap.add_argument("--serve", type=int, default=400, help="jobs of the serving stream (0: skip)")
     ap.add_argument("--serve-rates", type=str, default="50,200,1000", help="arrival rates, jobs/s")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-engine-max", type=int, default=None,
                     help="jobs up to this many input vertices run in batched launches (default: the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
