@@ -747,7 +747,10 @@ struct CavCheck {
   bool enc;
 };
 
-constexpr int kCap = 24;      // per-thread cavity capacity of the grid kernel
+// per-thread cavity capacity of the grid kernel: 39 slots x 128 threads (plus
+// a few bytes) is the most LDS that still lets 8 workgroups (16 waves) share a
+// compute unit's 160 KB; larger cavities go to the cooperative kernel
+constexpr int kCap = 39;
 constexpr int kCavBlock = kCavBlockSize;
 
 // Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
