@@ -153,6 +153,19 @@ const char *gdp_status_str(gdp_status s);
    to the device.  Subsegment k of the result is input segment k. */
 gdp_status gdp_mesh_create(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out);
 
+/* Line 1 of Algorithm 1 on the device (Section 4.3 names the initial CDT as
+   the first step; Section 7.1 builds it on the CPU): the same canonical CDT
+   as gdp_mesh_create, element for element, built by kernels on the context
+   stream from the host arrays of *pslg (copied to the device; the caller
+   keeps ownership).  Points are inserted by rounds of parallel
+   Bowyer-Watson insertion, missing segments recovered by rounds of
+   pseudo-polygon retriangulation.  Blocks until done.  Errors:
+   GDP_E_ARG (NULL, fewer than 3 vertices), GDP_E_INPUT (invalid PSLG: the
+   host builder's checks; its message may differ), GDP_E_CAVITY (a Delaunay
+   cavity above 16384 triangles), GDP_E_NOMEM, GDP_E_DEVICE.  On error
+   *out = NULL. */
+gdp_status gdp_mesh_create_device(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out);
+
 /* Same CDT, host only (no device needed).  Writes the counts to *n_tri and,
    when the pointers are non-NULL and cap_tri >= *n_tri, tri/nbr/seg
    (3 * n_tri int32 each: vertices, neighbour across edge i or -1, segment id

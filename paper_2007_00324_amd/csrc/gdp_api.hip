@@ -78,6 +78,7 @@ struct gdp_mesh {
   double2 *prev_cc_p = nullptr;
   int32_t *prev_mid_elem = nullptr;
   int32_t *tstamp = nullptr;
+  int32_t cdt_rounds[2] = {0, 0};  // rounds of the device CDT builder (points, segments)
   int32_t *cidx_t = nullptr, *cidx_s = nullptr;
   // cc.elem/key/p, mid.elem and the prev_* arrays form two list buffers; a
   // round with an odd serial uses them the other way round
@@ -432,12 +433,9 @@ void free_extras(gdp_mesh *M) {
   if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
 }
 
-// Allocates a device mesh with room for the given counts and uploads it.
-gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const int32_t *vkind,
-                  int32_t nT, const int32_t *tv, const int32_t *tn, const int32_t *ts, int32_t nS,
-                  int32_t nIS, const int32_t *sv, const int32_t *spar, const uint8_t *spend,
-                  int32_t rounds, gdp_mesh **out) {
-  hipStream_t s = ctx->stream;
+// Allocates a device mesh with room for the given counts (arrays not filled).
+gdp_status mesh_new(gdp_ctx *ctx, int32_t nV, int32_t nIV, int32_t nT, int32_t nS, int32_t nIS, int32_t rounds,
+                    gdp_mesh **out) {
   gdp_mesh *M = new gdp_mesh();
   M->ctx = ctx;
   auto bail = [&](gdp_status st) {
@@ -453,8 +451,36 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
   const int64_t cV = std::max<int64_t>(3 * (int64_t)nV + 1024, nV);
   const int64_t cT = std::max<int64_t>(2 * cV + 2048, nT);
   const int64_t cS = std::max<int64_t>(16 * (int64_t)nS + 1024, nS);
-  if (cT > (1 << 29) || cS > (1 << 28)) return fail(ctx, GDP_E_NOMEM, "mesh too large");
-  int32_t capV = (int32_t)cV, capT = (int32_t)cT, capS = (int32_t)cS;
+  if (cT > (1 << 29) || cS > (1 << 28)) return bail(fail(ctx, GDP_E_NOMEM, "mesh too large"));
+  M->m.capV = 0; M->m.capT = 0; M->m.capS = 0;
+  gdp_status st;
+  if ((st = grow_vtx(M, (int32_t)cV)) != GDP_OK) return bail(st);
+  if ((st = grow_tri(M, (int32_t)cT)) != GDP_OK) return bail(st);
+  if ((st = grow_seg(M, (int32_t)cS)) != GDP_OK) return bail(st);
+  if ((st = grow_cand(M)) != GDP_OK) return bail(st);
+  if ((st = alloc_control(M)) != GDP_OK) return bail(st);
+  M->pool_cap = std::max(1 << 16, 2 * M->m.capT + 65536);
+  if (dalloc(&M->pool, M->pool_cap) != hipSuccess) return bail(fail(ctx, GDP_E_NOMEM, "allocation failed"));
+  M->fan_cap = std::max(1 << 16, 2 * M->m.capT);
+  if (dalloc(&M->fan, M->fan_cap) != hipSuccess) return bail(fail(ctx, GDP_E_NOMEM, "allocation failed"));
+  *out = M;
+  return GDP_OK;
+}
+
+void mesh_delete(gdp_mesh *M) {
+  free_mesh_arrays(M);
+  delete M;
+}
+
+// Allocates a device mesh with room for the given counts and uploads it.
+gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const int32_t *vkind,
+                  int32_t nT, const int32_t *tv, const int32_t *tn, const int32_t *ts, int32_t nS,
+                  int32_t nIS, const int32_t *sv, const int32_t *spar, const uint8_t *spend,
+                  int32_t rounds, gdp_mesh **out) {
+  hipStream_t s = ctx->stream;
+  gdp_mesh *M = nullptr;
+  gdp_status st = mesh_new(ctx, nV, nIV, nT, nS, nIS, rounds, &M);
+  if (st != GDP_OK) return st;
   std::vector<double2> hv(nV);
   for (int i = 0; i < nV; i++) hv[i] = make_double2(xy[2 * i], xy[2 * i + 1]);
   std::vector<int4> htv(nT), htn(nT), hts(nT);
@@ -473,12 +499,6 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
   }
   std::vector<int32_t> hk(nV, 0);
   if (vkind) hk.assign(vkind, vkind + nV);
-  M->m.capV = 0; M->m.capT = 0; M->m.capS = 0;
-  gdp_status st;
-  if ((st = grow_vtx(M, capV)) != GDP_OK) return bail(st);
-  if ((st = grow_tri(M, capT)) != GDP_OK) return bail(st);
-  if ((st = grow_seg(M, capS)) != GDP_OK) return bail(st);
-  if ((st = grow_cand(M)) != GDP_OK) return bail(st);
   auto chk = [&](hipError_t e, const char *what) {
     if (e != hipSuccess) { fail(ctx, GDP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)); return false; }
     return true;
@@ -490,14 +510,11 @@ gdp_status upload(gdp_ctx *ctx, int32_t nV, int32_t nIV, const double *xy, const
       !chk(hipMemcpyAsync(M->m.ts, hts.data(), sizeof(int4) * nT, hipMemcpyHostToDevice, s), "upload") ||
       !chk(hipMemcpyAsync(M->m.sv, hsv.data(), sizeof(int2) * nS, hipMemcpyHostToDevice, s), "upload") ||
       !chk(hipMemcpyAsync(M->m.spar, hsp.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload") ||
-      !chk(hipMemcpyAsync(M->m.spend, hpend.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload"))
-    return bail(GDP_E_DEVICE);
-  if ((st = alloc_control(M)) != GDP_OK) return bail(st);
-  M->pool_cap = std::max(1 << 16, 2 * capT + 65536);
-  if (!chk(dalloc(&M->pool, M->pool_cap), "alloc")) return bail(GDP_E_DEVICE);
-  M->fan_cap = std::max(1 << 16, 2 * capT);
-  if (!chk(dalloc(&M->fan, M->fan_cap), "alloc")) return bail(GDP_E_DEVICE);
-  if (!chk(hipStreamSynchronize(s), "sync")) return bail(GDP_E_DEVICE);
+      !chk(hipMemcpyAsync(M->m.spend, hpend.data(), sizeof(int32_t) * nS, hipMemcpyHostToDevice, s), "upload") ||
+      !chk(hipStreamSynchronize(s), "sync")) {
+    mesh_delete(M);
+    return GDP_E_DEVICE;
+  }
   *out = M;
   return GDP_OK;
 }
@@ -1934,6 +1951,56 @@ gdp_status gdp_mesh_create(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out) {
   std::vector<uint8_t> pend(hm.nS, 0);
   return upload(ctx, hm.nV, hm.nV, hm.xy.data(), nullptr, hm.nT, hm.tv.data(), hm.tn.data(), hm.ts.data(), hm.nS,
                 hm.nS, hm.sv.data(), hm.sparent.data(), pend.data(), 0, out);
+}
+
+gdp_status gdp_mesh_create_device(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out) {
+  if (!ctx || !pslg || !out) return GDP_E_ARG;
+  *out = nullptr;
+  const int32_t nv = pslg->n_vertices, ns = pslg->n_segments;
+  const double *xy = pslg->xy;
+  const int32_t *seg = pslg->seg;
+  if (nv < 3 || !xy || ns < 0 || (ns > 0 && !seg)) return fail(ctx, GDP_E_ARG, "bad arguments");
+  if (nv > (1 << 28) - 8) return fail(ctx, GDP_E_NOMEM, "mesh too large");
+  // the checks of the host builder that need no sort; duplicate points and
+  // repeated segments are found by the kernels
+  for (int64_t i = 0; i < 2 * (int64_t)nv; i++) {
+    const double a = std::fabs(xy[i]);
+    if (!std::isfinite(xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100))
+      return fail(ctx, GDP_E_INPUT, "coordinate not finite, or nonzero with magnitude outside [2^-100, 2^20]");
+  }
+  for (int32_t k = 0; k < ns; k++) {
+    const int32_t a = seg[2 * k], b = seg[2 * k + 1];
+    if (a < 0 || b < 0 || a >= nv || b >= nv || a == b)
+      return fail(ctx, GDP_E_INPUT, "segment endpoint out of range or zero length");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  gdp_mesh *M = nullptr;
+  gdp_status st = mesh_new(ctx, nv, nv, 0, ns, ns, 0, &M);
+  if (st != GDP_OK) return st;
+  hipStream_t s = ctx->stream;
+  std::vector<int32_t> spar(ns);
+  for (int32_t k = 0; k < ns; k++) spar[k] = k;
+  if (hipMemcpyAsync(M->m.vxy, xy, sizeof(double2) * nv, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(M->m.vkind, 0, sizeof(int32_t) * nv, s) != hipSuccess ||
+      (ns > 0 && hipMemcpyAsync(M->m.sv, seg, sizeof(int2) * ns, hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (ns > 0 && hipMemcpyAsync(M->m.spar, spar.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (ns > 0 && hipMemsetAsync(M->m.spend, 0, sizeof(int32_t) * ns, s) != hipSuccess)) {
+    mesh_delete(M);
+    return fail(ctx, GDP_E_DEVICE, "upload failed");
+  }
+  std::string e;
+  int32_t nt = 0;
+  DevCdtStats cs;
+  const int rc = dev_cdt_build(s, nv, M->m.vxy, ns, M->m.sv, M->m.tv, M->m.tn, M->m.ts, M->m.capT, &nt, &cs, e);
+  if (rc != GDP_OK) {
+    mesh_delete(M);
+    return fail(ctx, (gdp_status)rc, e);
+  }
+  M->m.nT = nt;
+  M->cdt_rounds[0] = cs.dt_rounds;
+  M->cdt_rounds[1] = cs.seg_rounds;
+  *out = M;
+  return GDP_OK;
 }
 
 gdp_status gdp_mesh_upload(gdp_ctx *ctx, int32_t n_v, int32_t n_input_v, const double *xy, const int32_t *vkind,

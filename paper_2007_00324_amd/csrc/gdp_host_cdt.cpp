@@ -257,13 +257,17 @@ struct Builder {
     }
     // outside neighbours of the region, keyed by directed edge
     std::unordered_map<long long, std::pair<int, int>> outside;
+    std::unordered_map<long long, int> slit;  // uncrossed edges between two crossed triangles
     auto key = [](int u, int v) { return ((long long)u << 32) | (unsigned)v; };
     for (int c : crossed) dead[c] = 2;
     for (int c : crossed)
       for (int q = 0; q < 3; q++) {
         int o = N[3 * c + q];
-        if (o >= 0 && dead[o] == 2) continue;
         int u = V[3 * c + q], v = V[3 * c + (q + 1) % 3];
+        if (o >= 0 && dead[o] == 2) {
+          slit[key(u, v)] = Cn[3 * c + q];
+          continue;
+        }
         outside[key(u, v)] = {o, Cn[3 * c + q]};
       }
     for (int c : crossed) kill(c);
@@ -280,7 +284,8 @@ struct Builder {
         auto it = inner.find(key(v, u));
         if (it != inner.end()) {
           N[3 * t2 + q] = it->second.first;
-          Cn[3 * t2 + q] = ((u == a && v == b) || (u == b && v == a)) ? s : -1;
+          auto sl = slit.find(key(u, v));
+          Cn[3 * t2 + q] = ((u == a && v == b) || (u == b && v == a)) ? s : (sl != slit.end() ? sl->second : -1);
         } else {
           auto ot = outside.find(key(u, v));
           if (ot == outside.end()) { err = "segment recovery left an unmatched edge"; return false; }

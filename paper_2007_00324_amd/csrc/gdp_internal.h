@@ -27,6 +27,15 @@ struct HostMesh {
 int host_cdt_build(int32_t nv, const double *xy, int32_t ns, const int32_t *seg, HostMesh &out,
                    std::string &err);
 
+// The same CDT built by kernels (gdp_cdt_dev.hip).  d_xy holds the nv input
+// points and room for three more; the canonical triangles go to otv / otn /
+// ots in the device mesh layout below.
+struct DevCdtStats {
+  int32_t dt_rounds = 0, seg_rounds = 0;
+};
+int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, const int2 *d_seg, int4 *otv,
+                  int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err);
+
 // ---- device mesh --------------------------------------------------------------
 // Triangle t: tv[t] = (v0, v1, v2, subsegment-edge mask), tn[t] = (n0, n1, n2, 0),
 // ts[t] = (s0, s1, s2, 0); edge i = (v_i, v_{i+1 mod 3}).

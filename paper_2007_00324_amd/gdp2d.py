@@ -86,6 +86,7 @@ def load() -> C.CDLL:
         "gdp_ctx_destroy": (None, [_VP]),
         "gdp_last_error": (C.c_char_p, [_VP]),
         "gdp_mesh_create": (S, [_VP, C.POINTER(gdp_pslg), C.POINTER(_VP)]),
+        "gdp_mesh_create_device": (S, [_VP, C.POINTER(gdp_pslg), C.POINTER(_VP)]),
         "gdp_cdt_host": (S, [C.POINTER(gdp_pslg), _PI, C.c_int32, _PI, _PI, _PI, C.c_char_p, C.c_int32]),
         "gdp_mesh_upload": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.c_int32, _PI, _PI, _PI, C.c_int32,
                                 C.c_int32, _PI, _PI, C.POINTER(C.c_uint8), C.c_int32, C.POINTER(_VP)]),
@@ -121,7 +122,7 @@ def load() -> C.CDLL:
 
 def exported_symbols() -> list[str]:
     return ["gdp_params_default", "gdp_status_str", "gdp_ctx_create", "gdp_ctx_destroy", "gdp_last_error",
-            "gdp_mesh_create", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
+            "gdp_mesh_create", "gdp_mesh_create_device", "gdp_cdt_host", "gdp_mesh_upload", "gdp_mesh_refine", "gdp_refine",
             "gdp_mesh_info_get", "gdp_mesh_quality", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
@@ -291,6 +292,14 @@ def gdp_mesh_create(ctx: Context, xy, seg) -> Mesh:
     p, keep = _pslg(xy, seg)
     h = _VP()
     ctx.check(load().gdp_mesh_create(ctx._h, C.byref(p), C.byref(h)))
+    return Mesh(ctx, h)
+
+
+def gdp_mesh_create_device(ctx: Context, xy, seg) -> Mesh:
+    """Line 1 on the GPU: the same canonical CDT as gdp_mesh_create, built by kernels."""
+    p, keep = _pslg(xy, seg)
+    h = _VP()
+    ctx.check(load().gdp_mesh_create_device(ctx._h, C.byref(p), C.byref(h)))
     return Mesh(ctx, h)
 
 
