@@ -124,6 +124,9 @@ typedef struct {
   int32_t n_vertices, n_triangles, n_subsegments;
   int32_t n_input_vertices, n_input_segments;
   int32_t rounds;
+  /* rounds of the device CDT builder that made the mesh (point insertion,
+     segment recovery); 0 for meshes built on the host or uploaded */
+  int32_t cdt_point_rounds, cdt_segment_rounds;
 } gdp_mesh_info;
 
 /* Per-round counters (device-side counts copied back after every round). */

@@ -2095,6 +2095,8 @@ gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info) {
   info->n_input_vertices = mesh->m.n_input_v;
   info->n_input_segments = mesh->m.n_input_s;
   info->rounds = mesh->m.rounds;
+  info->cdt_point_rounds = mesh->cdt_rounds[0];
+  info->cdt_segment_rounds = mesh->cdt_rounds[1];
   return GDP_OK;
 }
 

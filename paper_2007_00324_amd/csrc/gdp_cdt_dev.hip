@@ -86,7 +86,7 @@ struct Ctr {
   int err;     // first error code
   int nkeep;   // kept triangles (final stage)
   int nhull;   // boundary edges of the kept region
-  int pad;
+  int first;   // smallest list index of a pending point (rounds with one forced insertion)
 };
 
 struct Bld {
@@ -95,7 +95,8 @@ struct Bld {
   int4 *tv, *tn, *ts;  // triangle slots: vertices, neighbours, segment id per edge (-1 none)
   int capT;
   int *ntri;
-  uint64_t *pick, *mark;  // per slot: elected key, stamp of the region owner (round << 32 | key)
+  uint64_t *pick, *mark;  // per slot: elected key, largest cavity stamp (round << 32 | key)
+  uint64_t *ring;         // per slot: largest ring stamp of a point cavity
   int *hint, *state;      // per point: last triangle, -2 / -1 (LDS cavity) / big slot
   int *vt;                // per vertex: an incident triangle
   int *big;               // kBigSlots * kBigCap
@@ -217,16 +218,17 @@ __global__ void k_init(Bld b, int *pend) {
 // Walks each pending point to its triangle and elects, per triangle, the
 // point with the largest key (waves whose lanes share a triangle combine
 // their keys before the atomic).
-__global__ void k_locate(Bld b, const int *pend, int np, uint32_t round) {
+__global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int solo) {
   const int lane = __lane_id();
   const int stride = gridDim.x * blockDim.x;
   for (int base = blockIdx.x * blockDim.x; base < np; base += stride) {
     const int i = base + threadIdx.x;
-    bool act = i < np;
+    const int p = i < np ? pend[i] : -1;  // -1: an inserted point left in the list
+    bool act = p >= 0;
     int t = 0;
     uint64_t key = 0;
+    if (solo && act) atomicMin(&b.c->first, i);
     if (act) {
-      const int p = pend[i];
       t = b.hint[p];
       int from = -1;
       const double2 q = b.P[p];
@@ -257,12 +259,15 @@ __global__ void k_locate(Bld b, const int *pend, int np, uint32_t round) {
       b.hint[p] = t;
       key = ((uint64_t)round << 32) | mix32((uint32_t)p);
     }
+    // combine the keys of lanes that share a triangle while such groups are
+    // large (early rounds: few triangles, many points each)
     uint64_t left = __ballot(act);
-    for (int it = 0; it < 4 && left; it++) {
+    for (int it = 0; it < 64 && left; it++) {
       const int leader = __ffsll((unsigned long long)left) - 1;
       const int tl = __shfl(t, leader);
       const bool same = act && t == tl;
       const uint64_t m = __ballot(same);
+      if (it > 0 && __popcll(m) < 3) break;
       long long best = same ? (long long)key : 0;
       for (int d = 32; d >= 1; d >>= 1) {
         long long o = __shfl_xor(best, d);
@@ -277,12 +282,15 @@ __global__ void k_locate(Bld b, const int *pend, int np, uint32_t round) {
 }
 
 // Cavity of point p from triangle t0 into list L (cap entries).  mode 0:
-// stamp key on the cavity and its ring; mode 1: require key on every
-// triangle read (cavity and ring) before reading it.  Returns the cavity
-// size, -1 when it exceeds cap, -2 when a foreign stamp is met (mode 1).
+// stamp key on the cavity (mark) and on the ring around it (ring); mode 1:
+// rebuild the list from the stamps, requiring that no larger key holds a
+// cavity triangle in its cavity or ring, nor a ring triangle in its cavity.
+// Rings may overlap: a ring triangle only has one neighbour pointer per
+// cavity rewritten.  Returns the cavity size, -1 when it exceeds cap, -2
+// when a larger key holds the region (mode 1).
 __device__ int grow(const Bld &b, int p, int t0, List L, int cap, uint64_t key, int mode) {
   if (mode == 1) {
-    if (b.mark[t0] != key) return -2;
+    if (b.mark[t0] != key || b.ring[t0] > key) return -2;
   } else {
     atomicMax((unsigned long long *)&b.mark[t0], (unsigned long long)key);
   }
@@ -293,13 +301,18 @@ __device__ int grow(const Bld &b, int p, int t0, List L, int cap, uint64_t key, 
     for (int e = 0; e < 3; e++) {
       const int o = comp(nb, e);
       if (o < 0 || in_list(L, n, o)) continue;
+      bool inside;
       if (mode == 1) {
-        if (b.mark[o] != key) return -2;
+        const uint64_t m = b.mark[o];
+        if (m > key) return -2;
+        inside = m == key;
+        if (inside && b.ring[o] > key) return -2;
       } else {
-        atomicMax((unsigned long long *)&b.mark[o], (unsigned long long)key);
+        const int4 v = b.tv[o];
+        inside = incircle_sos(b.P, v.x, v.y, v.z, p) > 0;
+        atomicMax((unsigned long long *)(inside ? &b.mark[o] : &b.ring[o]), (unsigned long long)key);
       }
-      const int4 v = b.tv[o];
-      if (incircle_sos(b.P, v.x, v.y, v.z, p) > 0) {
+      if (inside) {
         if (n == cap) return -1;
         L[n++] = o;
       }
@@ -312,13 +325,15 @@ __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np
   __shared__ int s_list[kLdsCap * kCavBlk];
   const List lds{&s_list[threadIdx.x], kCavBlk};
   const int stride = gridDim.x * blockDim.x;
+  const int first = solo ? b.c->first : -1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
     const int p = pend[i];
+    if (p < 0) continue;
     const uint64_t key = ((uint64_t)round << 32) | mix32((uint32_t)p);
     const int t0 = b.hint[p];
     int st = -2;
     if (solo) {
-      if (i == 0) {
+      if (i == first) {
         st = 0;
         if (grow(b, p, t0, List{b.big, 1}, kBigCap, key, 0) < 0) { set_err(b.c, kECavity); st = -2; }
       }
@@ -341,17 +356,20 @@ __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np
 
 // Checks each elected point's stamps and, for the winners, replaces the
 // cavity by the fan; the others go to the next pending list.
-__global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, const int *pend, int np, uint32_t round, int *pend_out) {
+// compact = 1: the points not inserted go to pend_out; compact = 0: the
+// list stays and each inserted point leaves -1 in its entry.
+__global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, uint32_t round, int *pend_out,
+                                                    int compact) {
   __shared__ int s_list[kLdsCap * kCavBlk];
   const List lds{&s_list[threadIdx.x], kCavBlk};
   const int stride = gridDim.x * blockDim.x;
   for (int base = blockIdx.x * blockDim.x; base < np; base += stride) {
     const int i = base + threadIdx.x;
-    const bool act = i < np;
-    int p = -1, n = -2;
+    int p = i < np ? pend[i] : -1;
+    const bool act = p >= 0;
+    int n = -2;
     List L = lds;
     if (act) {
-      p = pend[i];
       const int st = b.state[p];
       if (st != -2) {
         const uint64_t key = ((uint64_t)round << 32) | mix32((uint32_t)p);
@@ -363,9 +381,12 @@ __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, const int *pend, int 
     const bool win = n > 0;
     const int fresh = wave_take(b.ntri, win ? 2 : 0);
     const int bo = wave_take(&b.c->pool, win ? 4 * (n + 2) : 0);
-    const int po = wave_take(&b.c->npend, act && !win ? 1 : 0);
-    if (act && !win) pend_out[po] = p;
+    if (compact) {
+      const int po = wave_take(&b.c->npend, act && !win ? 1 : 0);
+      if (act && !win) pend_out[po] = p;
+    }
     if (!win) continue;
+    if (!compact) pend[i] = -1;
     if (fresh + 2 > b.capT || bo + 4 * (n + 2) > b.pool_cap) { set_err(b.c, kEInternal + 1); continue; }
     int *B = b.pool + bo;
     int nb = 0;
@@ -819,7 +840,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
   const size_t o_tv = take(sizeof(int4) * capT), o_tn = take(sizeof(int4) * capT), o_ts = take(sizeof(int4) * capT);
-  const size_t o_pick = take(8 * (size_t)capT), o_mark = take(8 * (size_t)capT);
+  const size_t o_pick = take(8 * (size_t)capT), o_mark = take(8 * (size_t)capT), o_ring = take(8 * (size_t)capT);
   const size_t o_hint = take(4 * (size_t)nv), o_state = take(4 * (size_t)std::max(nv, ns));
   const size_t o_vt = take(4 * (size_t)(nv + 3)), o_big = take(4 * (size_t)kBigSlots * kBigCap);
   const size_t o_pool = take(4 * (size_t)pool_cap);
@@ -847,7 +868,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   b.tv = (int4 *)(base + o_tv); b.tn = (int4 *)(base + o_tn); b.ts = (int4 *)(base + o_ts);
   b.capT = capT;
   b.ntri = (int *)(base + o_ntri);
-  b.pick = (uint64_t *)(base + o_pick); b.mark = (uint64_t *)(base + o_mark);
+  b.pick = (uint64_t *)(base + o_pick); b.mark = (uint64_t *)(base + o_mark); b.ring = (uint64_t *)(base + o_ring);
   b.hint = (int *)(base + o_hint); b.state = (int *)(base + o_state);
   b.vt = (int *)(base + o_vt); b.big = (int *)(base + o_big);
   b.pool = (int *)(base + o_pool); b.pool_cap = pool_cap;
@@ -856,6 +877,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   if (hipMemcpyAsync(d_xy + nv, enc, sizeof(enc), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemsetAsync(b.pick, 0, 8 * (size_t)capT, stream) != hipSuccess ||
       hipMemsetAsync(b.mark, 0, 8 * (size_t)capT, stream) != hipSuccess ||
+      hipMemsetAsync(b.ring, 0, 8 * (size_t)capT, stream) != hipSuccess ||
       hipMemsetAsync(b.c, 0, sizeof(Ctr), stream) != hipSuccess)
     { err = "device call failed"; return done(GDP_E_DEVICE); }
   k_init<<<grid_for(nv, kBlk), kBlk, 0, stream>>>(b, pl[0]);
@@ -864,21 +886,28 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
     return hipStreamSynchronize(stream) == hipSuccess;
   };
   uint32_t round = 0;
-  int np = nv, cur = 0, solo = 0, dt_rounds = 0, seg_rounds = 0;
+  // np: points still to insert; nl: entries of the pending list (inserted
+  // points stay in it as -1 until more than an eighth of it is stale)
+  int np = nv, nl = nv, cur = 0, solo = 0, dt_rounds = 0, seg_rounds = 0;
   while (np > 0) {
     round++;
     dt_rounds++;
-    if (hipMemsetAsync(b.c, 0, 4 * sizeof(int), stream) != hipSuccess) { err = "device call failed"; return done(GDP_E_DEVICE); }
-    k_locate<<<grid_for(np, kBlk), kBlk, 0, stream>>>(b, pl[cur], np, round);
-    k_mark<<<grid_for(np, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], np, round, solo);
-    k_insert<<<grid_for(np, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], np, round, pl[cur ^ 1]);
+    const int compact = (nl - np) * 8 >= nl;
+    if (hipMemsetAsync(b.c, 0, 4 * sizeof(int), stream) != hipSuccess ||
+        hipMemsetAsync(&b.c->first, 0x7f, sizeof(int), stream) != hipSuccess) { err = "device call failed"; return done(GDP_E_DEVICE); }
+    k_locate<<<grid_for(nl, kBlk), kBlk, 0, stream>>>(b, pl[cur], nl, round, solo);
+    k_mark<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, solo);
+    k_insert<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, pl[cur ^ 1], compact);
     if (!round_trip()) { err = "device call failed"; return done(GDP_E_DEVICE); }
     if (hctr->err) { err = std::string("points (round " + std::to_string(dt_rounds) + "): ") + cdt_err_string(hctr->err); return done(hctr->err == kECavity ? GDP_E_CAVITY : (hctr->err >= kEInternal ? GDP_E_DEVICE : GDP_E_INPUT)); }
-    if (hctr->npend != np - hctr->nwin) { err = "device CDT builder: lost points"; return done(GDP_E_DEVICE); }
+    if (compact && hctr->npend != np - hctr->nwin) { err = "device CDT builder: lost points"; return done(GDP_E_DEVICE); }
     if (solo && hctr->nwin == 0) { err = "device CDT builder: no insertion progress"; return done(GDP_E_DEVICE); }
     solo = hctr->nwin == 0;
-    np = hctr->npend;
-    cur ^= 1;
+    np -= hctr->nwin;
+    if (compact) {
+      nl = np;
+      cur ^= 1;
+    }
   }
   int nt = 0;
   if (hipMemcpyAsync(&nt, b.ntri, 4, hipMemcpyDeviceToHost, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
@@ -887,7 +916,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   // segments
   k_vt<<<grid_for(nt, kBlk), kBlk, 0, stream>>>(b, nt);
   int *sstart = b.state;
-  int nl = ns;
+  nl = ns;
   cur = 0;
   if (ns > 0) k_iota<<<grid_for(ns, kBlk), kBlk, 0, stream>>>(ns, pl[0]);
   while (nl > 0) {

@@ -51,7 +51,8 @@ class gdp_kernel_prof(C.Structure):
 
 class gdp_mesh_info(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_subsegments", C.c_int32),
-                ("n_input_vertices", C.c_int32), ("n_input_segments", C.c_int32), ("rounds", C.c_int32)]
+                ("n_input_vertices", C.c_int32), ("n_input_segments", C.c_int32), ("rounds", C.c_int32),
+                ("cdt_point_rounds", C.c_int32), ("cdt_segment_rounds", C.c_int32)]
 
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident", "n_enc_reject",
