@@ -132,6 +132,43 @@ def criteria_leg(ctx, init, work, p) -> dict:
             "modes": rows}
 
 
+def cdt_leg(ctx, init, p) -> dict:
+    """Line 1 of Algorithm 1 on the GPU (gdp_mesh_create_device) against the host
+    builder (gdp_mesh_create) on the benchmark PSLG: wall time from the PSLG in host
+    memory to the initial CDT resident in device memory, both including the copy of
+    their inputs (host: the finished CDT; device: the points and segments); one warmup,
+    then the median of three.  The two meshes must be identical element by element."""
+    import numpy as np
+
+    from paper_2007_00324_amd import gdp2d
+    host_ms, dev_ms = [], []
+    info = None
+    for rep in range(4):
+        t0 = time.perf_counter()
+        h = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg)
+        t1 = time.perf_counter()
+        d = gdp2d.gdp_mesh_create_device(ctx, p.xy, p.seg)
+        t2 = time.perf_counter()
+        if rep:
+            host_ms.append(1e3 * (t1 - t0))
+            dev_ms.append(1e3 * (t2 - t1))
+        if rep == 3:
+            a, b = init.arrays(), d.arrays()
+            identical = all(np.array_equal(np.asarray(a[k]).view(np.uint8), np.asarray(b[k]).view(np.uint8))
+                            for k in ["xy", "vkind", "tv", "tn", "ts", "sv", "sparent", "spend"])
+            info = d.info()
+        del h, d
+    host_ms.sort()
+    dev_ms.sort()
+    log(f"initial CDT: host {host_ms[1]:.1f} ms, device {dev_ms[1]:.1f} ms, "
+        f"{info['cdt_point_rounds']} + {info['cdt_segment_rounds']} rounds, identical {identical}")
+    return {"workload": f"{p.name}: {p.n_vertices:,} vertices / {p.n_segments:,} segments",
+            "timing": "wall time, PSLG in host memory to CDT in device memory, median of 3",
+            "host_ms": host_ms[1], "device_ms": dev_ms[1], "speedup": host_ms[1] / dev_ms[1],
+            "point_rounds": info["cdt_point_rounds"], "segment_rounds": info["cdt_segment_rounds"],
+            "triangles": info["n_triangles"], "identical_to_host": identical}
+
+
 def ablation_leg(ctx, init, work, p) -> dict:
     """gDP2d's rules switched on and off on the 1M-point PSLG (the paper leaves this
     study out for 2D).  Per setting: device refine time (median of 3), Steiner points,
@@ -333,6 +370,7 @@ def main() -> int:
                     help="candidates per round below which rounds run inside one workgroup (0 default, -1 never)")
     ap.add_argument("--no-criteria", action="store_true", help="skip the lens / length-bound / theta legs")
     ap.add_argument("--no-ablation", action="store_true", help="skip the rule ablation leg")
+    ap.add_argument("--no-cdt", action="store_true", help="skip the device initial-CDT leg")
     ap.add_argument("--batch", type=int, default=4096, help="jobs of the batched form (0: skip)")
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
@@ -468,6 +506,8 @@ def main() -> int:
             "kernel_ms": {k["name"]: round(k["total_ms"], 3) for k in prof if k["launches"]},
             "profiled_refine_ms": work.last_refine_ms(),
         }
+    if not args.no_cdt:
+        out["initial_cdt"] = cdt_leg(ctx, init, p)
     if not args.no_criteria:
         out["criteria"] = criteria_leg(ctx, init, work, p)
     if not args.no_ablation:
