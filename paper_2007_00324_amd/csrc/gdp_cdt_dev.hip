@@ -122,6 +122,12 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return h;
 }
 
+// Pending points take part in a round's election only while a second mix of
+// their id is at most the round's threshold: a random sample of about four
+// points per triangle while the mesh is coarse, so the early rounds do not
+// walk every point.
+__device__ __forceinline__ bool sampled(int p, uint32_t thresh) { return mix32((uint32_t)p ^ 0x5bd1e995u) <= thresh; }
+
 __device__ __forceinline__ int orient_ids(const double2 *P, int a, int b, int c) {
   const double2 A = P[a], B = P[b], C = P[c];
   return orient2d(A.x, A.y, B.x, B.y, C.x, C.y);
@@ -218,7 +224,9 @@ __global__ void k_init(Bld b, int *pend) {
 // Walks each pending point to its triangle and elects, per triangle, the
 // point with the largest key (waves whose lanes share a triangle combine
 // their keys before the atomic).
-__global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int solo) {
+// relocate = 1: the points outside the sample walk too (their start
+// triangles are refreshed each time the mesh has doubled) but do not elect.
+__global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int solo, uint32_t thresh, int relocate) {
   const int lane = __lane_id();
   const int stride = gridDim.x * blockDim.x;
   for (int base = blockIdx.x * blockDim.x; base < np; base += stride) {
@@ -228,6 +236,8 @@ __global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int sol
     int t = 0;
     uint64_t key = 0;
     if (solo && act) atomicMin(&b.c->first, i);
+    const bool elect = act && sampled(p, thresh);
+    if (!elect && !relocate) act = false;
     if (act) {
       t = b.hint[p];
       int from = -1;
@@ -258,6 +268,7 @@ __global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int sol
       }
       b.hint[p] = t;
       key = ((uint64_t)round << 32) | mix32((uint32_t)p);
+      if (!elect) act = false;
     }
     // combine the keys of lanes that share a triangle while such groups are
     // large (early rounds: few triangles, many points each)
@@ -321,7 +332,8 @@ __device__ int grow(const Bld &b, int p, int t0, List L, int cap, uint64_t key, 
   return n;
 }
 
-__global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np, uint32_t round, int solo) {
+__global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np, uint32_t round, int solo,
+                                                  uint32_t thresh) {
   __shared__ int s_list[kLdsCap * kCavBlk];
   const List lds{&s_list[threadIdx.x], kCavBlk};
   const int stride = gridDim.x * blockDim.x;
@@ -337,7 +349,7 @@ __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np
         st = 0;
         if (grow(b, p, t0, List{b.big, 1}, kBigCap, key, 0) < 0) { set_err(b.c, kECavity); st = -2; }
       }
-    } else if (b.pick[t0] == key) {
+    } else if (sampled(p, thresh) && b.pick[t0] == key) {
       int n = grow(b, p, t0, lds, kLdsCap, key, 0);
       st = -1;
       if (n < 0) {
@@ -889,14 +901,20 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   // np: points still to insert; nl: entries of the pending list (inserted
   // points stay in it as -1 until more than an eighth of it is stale)
   int np = nv, nl = nv, cur = 0, solo = 0, dt_rounds = 0, seg_rounds = 0;
+  int64_t t_reloc = 1;  // triangles at the last refresh of every start triangle
   while (np > 0) {
     round++;
     dt_rounds++;
     const int compact = (nl - np) * 8 >= nl;
+    const int64_t ntri = 1 + 2 * (int64_t)(nv - np);
+    const double frac = solo ? 1.0 : 4.0 * (double)ntri / (double)np;
+    const uint32_t thresh = frac >= 1.0 ? 0xffffffffu : (uint32_t)(frac * 4294967296.0);
+    int relocate = 0;
+    if (thresh != 0xffffffffu && ntri >= 2 * t_reloc) { relocate = 1; t_reloc = ntri; }
     if (hipMemsetAsync(b.c, 0, 4 * sizeof(int), stream) != hipSuccess ||
         hipMemsetAsync(&b.c->first, 0x7f, sizeof(int), stream) != hipSuccess) { err = "device call failed"; return done(GDP_E_DEVICE); }
-    k_locate<<<grid_for(nl, kBlk), kBlk, 0, stream>>>(b, pl[cur], nl, round, solo);
-    k_mark<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, solo);
+    k_locate<<<grid_for(nl, kBlk), kBlk, 0, stream>>>(b, pl[cur], nl, round, solo, thresh, relocate);
+    k_mark<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, solo, thresh);
     k_insert<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, pl[cur ^ 1], compact);
     if (!round_trip()) { err = "device call failed"; return done(GDP_E_DEVICE); }
     if (hctr->err) { err = std::string("points (round " + std::to_string(dt_rounds) + "): ") + cdt_err_string(hctr->err); return done(hctr->err == kECavity ? GDP_E_CAVITY : (hctr->err >= kEInternal ? GDP_E_DEVICE : GDP_E_INPUT)); }
