@@ -198,12 +198,6 @@ struct List {
   __device__ __forceinline__ int &operator[](int i) const { return p[(size_t)i * stride]; }
 };
 
-__device__ __forceinline__ bool in_list(const List &L, int n, int t) {
-  for (int i = 0; i < n; i++)
-    if (L[i] == t) return true;
-  return false;
-}
-
 // ---------------------------------------------------------------------------
 // Stage 1: Delaunay triangulation by parallel Bowyer-Watson rounds
 // ---------------------------------------------------------------------------
@@ -292,44 +286,73 @@ __global__ void k_locate(Bld b, const int *pend, int np, uint32_t round, int sol
   }
 }
 
-// Cavity of point p from triangle t0 into list L (cap entries).  mode 0:
-// stamp key on the cavity (mark) and on the ring around it (ring); mode 1:
-// rebuild the list from the stamps, requiring that no larger key holds a
-// cavity triangle in its cavity or ring, nor a ring triangle in its cavity.
-// Rings may overlap: a ring triangle only has one neighbour pointer per
-// cavity rewritten.  Returns the cavity size, -1 when it exceeds cap, -2
-// when a larger key holds the region (mode 1).
-__device__ int grow(const Bld &b, int p, int t0, List L, int cap, uint64_t key, int mode) {
-  if (mode == 1) {
-    if (b.mark[t0] != key || b.ring[t0] > key) return -2;
-  } else {
-    atomicMax((unsigned long long *)&b.mark[t0], (unsigned long long)key);
-  }
-  L[0] = t0;
-  int n = 1;
-  for (int h = 0; h < n; h++) {
+// Cavity of point p, breadth first from the triangles already in L[0..n)
+// (the caller puts the start triangle there and stamps / checks it).
+// mode 0: stamp key on the cavity (mark) and on the ring around it (ring);
+// a triangle already stamped with key is already listed.  mode 1: rebuild
+// the list from the stamps (pick marks the listed triangles), requiring that
+// no larger key holds a cavity triangle in its cavity or ring, nor a ring
+// triangle in its cavity.  Rings may overlap: a ring triangle only has one
+// neighbour pointer per cavity rewritten.  Returns n when done, -1 when the
+// list is full (h and n then allow a resume with a larger list), -2 when a
+// larger key holds the region.
+__device__ int grow(const Bld &b, int p, List L, int cap, uint64_t key, int mode, int &h, int &n) {
+  for (; h < n; h++) {
     const int4 nb = b.tn[L[h]];
     for (int e = 0; e < 3; e++) {
       const int o = comp(nb, e);
-      if (o < 0 || in_list(L, n, o)) continue;
-      bool inside;
+      if (o < 0) continue;
       if (mode == 1) {
         const uint64_t m = b.mark[o];
         if (m > key) return -2;
-        inside = m == key;
-        if (inside && b.ring[o] > key) return -2;
-      } else {
-        const int4 v = b.tv[o];
-        inside = incircle_sos(b.P, v.x, v.y, v.z, p) > 0;
-        atomicMax((unsigned long long *)(inside ? &b.mark[o] : &b.ring[o]), (unsigned long long)key);
-      }
-      if (inside) {
+        if (m != key) continue;  // ring
+        if (b.ring[o] > key) return -2;
+        if (b.pick[o] == key) continue;  // listed
         if (n == cap) return -1;
-        L[n++] = o;
+        b.pick[o] = key;
+      } else {
+        if (b.mark[o] == key) continue;  // listed
+        const int4 v = b.tv[o];
+        if (incircle_sos(b.P, v.x, v.y, v.z, p) <= 0) {
+          atomicMax((unsigned long long *)&b.ring[o], (unsigned long long)key);
+          continue;
+        }
+        if (n == cap) return -1;
+        const uint64_t old = atomicMax((unsigned long long *)&b.mark[o], (unsigned long long)key);
+        if (old > key) return -2;
+        if (old == key) continue;
       }
+      L[n++] = o;
     }
   }
   return n;
+}
+
+// Stamps the start triangle and grows the cavity of p (mode 0) in L; on a
+// full list continues in a large list of the global pool when one is free.
+// Returns the state: -1 (cavity in LDS), a big-list slot, or -2 (none).
+__device__ int mark_cavity(const Bld &b, int p, int t0, uint64_t key, List L, int cap, bool big_only) {
+  const uint64_t old = atomicMax((unsigned long long *)&b.mark[t0], (unsigned long long)key);
+  if (old > key) return -2;
+  int h = 0, n = 1;
+  if (big_only) {
+    const List G{b.big, 1};
+    G[0] = t0;
+    const int r = grow(b, p, G, kBigCap, key, 0, h, n);
+    if (r == -1) set_err(b.c, kECavity);
+    return r > 0 ? 0 : -2;
+  }
+  L[0] = t0;
+  int r = grow(b, p, L, cap, key, 0, h, n);
+  if (r > 0) return -1;
+  if (r == -2) return -2;
+  const int slot = atomicAdd(&b.c->nbig, 1);
+  if (slot >= kBigSlots) return -2;
+  const List G{b.big + (size_t)slot * kBigCap, 1};
+  for (int k = 0; k < n; k++) G[k] = L[k];
+  r = grow(b, p, G, kBigCap, key, 0, h, n);
+  if (r == -1) set_err(b.c, kECavity);
+  return r > 0 ? slot : -2;
 }
 
 __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np, uint32_t round, int solo,
@@ -345,29 +368,14 @@ __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np
     const int t0 = b.hint[p];
     int st = -2;
     if (solo) {
-      if (i == first) {
-        st = 0;
-        if (grow(b, p, t0, List{b.big, 1}, kBigCap, key, 0) < 0) { set_err(b.c, kECavity); st = -2; }
-      }
+      if (i == first) st = mark_cavity(b, p, t0, key, lds, kLdsCap, true);
     } else if (sampled(p, thresh) && b.pick[t0] == key) {
-      int n = grow(b, p, t0, lds, kLdsCap, key, 0);
-      st = -1;
-      if (n < 0) {
-        st = -2;
-        const int slot = atomicAdd(&b.c->nbig, 1);
-        if (slot < kBigSlots) {
-          n = grow(b, p, t0, List{b.big + (size_t)slot * kBigCap, 1}, kBigCap, key, 0);
-          if (n < 0) set_err(b.c, kECavity);
-          else st = slot;
-        }
-      }
+      st = mark_cavity(b, p, t0, key, lds, kLdsCap, false);
     }
     b.state[p] = st;
   }
 }
 
-// Checks each elected point's stamps and, for the winners, replaces the
-// cavity by the fan; the others go to the next pending list.
 // compact = 1: the points not inserted go to pend_out; compact = 0: the
 // list stays and each inserted point leaves -1 in its entry.
 __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, uint32_t round, int *pend_out,
@@ -387,7 +395,13 @@ __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, ui
         const uint64_t key = ((uint64_t)round << 32) | mix32((uint32_t)p);
         int cap = kLdsCap;
         if (st >= 0) { L = List{b.big + (size_t)st * kBigCap, 1}; cap = kBigCap; }
-        n = grow(b, p, b.hint[p], L, cap, key, 1);
+        const int t0 = b.hint[p];
+        if (b.mark[t0] == key && b.ring[t0] <= key) {
+          b.pick[t0] = key;
+          L[0] = t0;
+          int h = 0, m = 1;
+          n = grow(b, p, L, cap, key, 1, h, m);
+        }
       }
     }
     const bool win = n > 0;
@@ -401,40 +415,50 @@ __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, ui
     if (!compact) pend[i] = -1;
     if (fresh + 2 > b.capT || bo + 4 * (n + 2) > b.pool_cap) { set_err(b.c, kEInternal + 1); continue; }
     int *B = b.pool + bo;
-    int nb = 0;
-    for (int h = 0; h < n; h++) {
-      const int t = L[h];
-      const int4 v = b.tv[t], nbv = b.tn[t];
+    const uint64_t key = ((uint64_t)round << 32) | mix32((uint32_t)p);
+    // the cavity boundary as a cycle: from a boundary edge (u, w), rotate
+    // around w inside the cavity to the next boundary edge
+    int ft = -1, fe = -1;
+    for (int h = 0; h < n && ft < 0; h++) {
+      const int4 nbv = b.tn[L[h]];
       for (int e = 0; e < 3; e++) {
         const int o = comp(nbv, e);
-        if (o >= 0 && in_list(L, n, o)) continue;
-        if (nb >= n + 2) { nb = n + 3; continue; }
-        const int u = comp(v, e), w = comp(v, (e + 1) % 3);
-        B[4 * nb] = u;
-        B[4 * nb + 1] = w;
-        B[4 * nb + 2] = o;
-        B[4 * nb + 3] = o >= 0 ? eidx(b.tv[o], w, u) : -1;
-        nb++;
+        if (o < 0 || b.mark[o] != key) { ft = L[h]; fe = e; break; }
       }
     }
-    bool linked = nb == n + 2;
-    for (int j = 0; j < nb && linked; j++) {
-      int cn = 0, cp = 0;
-      for (int q = 0; q < nb; q++) {
-        cn += B[4 * q] == B[4 * j + 1];
-        cp += B[4 * q + 1] == B[4 * j];
+    bool linked = ft >= 0;
+    int nb = 0, ct = ft, ce = fe;
+    while (linked) {
+      if (nb >= n + 2) { linked = false; break; }
+      const int4 v = b.tv[ct];
+      const int o = comp(b.tn[ct], ce);
+      const int u = comp(v, ce), w = comp(v, (ce + 1) % 3);
+      const int oe = o >= 0 ? eidx(b.tv[o], w, u) : -1;
+      if (o >= 0 && oe < 0) { linked = false; break; }
+      B[4 * nb] = u;
+      B[4 * nb + 1] = w;
+      B[4 * nb + 2] = o;
+      B[4 * nb + 3] = oe;
+      nb++;
+      int t2 = ct, e2 = (ce + 1) % 3;
+      for (int guard = 0;; guard++) {
+        const int n2 = comp(b.tn[t2], e2);
+        if (n2 < 0 || b.mark[n2] != key) break;
+        const int k = vidx(b.tv[n2], w);
+        if (k < 0 || guard > n) { linked = false; break; }
+        t2 = n2;
+        e2 = k;
       }
-      linked = cn == 1 && cp == 1 && (B[4 * j + 2] < 0 || B[4 * j + 3] >= 0);
+      ct = t2;
+      ce = e2;
+      if (ct == ft && ce == fe) break;
     }
+    linked = linked && nb == n + 2;
     if (!linked) { set_err(b.c, kEInternal + 2); continue; }
     atomicAdd(&b.c->nwin, 1);
     for (int j = 0; j < nb; j++) {
       const int u = B[4 * j], w = B[4 * j + 1], o = B[4 * j + 2], oe = B[4 * j + 3];
-      int jn = -1, jp = -1;
-      for (int q = 0; q < nb; q++) {
-        if (B[4 * q] == w) jn = q;
-        if (B[4 * q + 1] == u) jp = q;
-      }
+      const int jn = j + 1 == nb ? 0 : j + 1, jp = j == 0 ? nb - 1 : j - 1;
       const int s = j < n ? L[j] : fresh + (j - n);
       const int sn = jn < n ? L[jn] : fresh + (jn - n);
       const int sp = jp < n ? L[jp] : fresh + (jp - n);
