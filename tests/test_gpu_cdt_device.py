@@ -111,3 +111,51 @@ def test_device_cdt_full_configs(ctx, name):
     dev = _device_arrays(ctx, p.xy, p.seg)
     host = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg).arrays()
     assert not diff_arrays(host, dev), diff_arrays(host, dev)
+
+
+def circle_pslg(n: int, with_center: bool, seed: int):
+    """The square plus n points on a circle (rounded cocircular) and uniform
+    interior points inside it: large cavities under the perturbation."""
+    rng = np.random.default_rng(seed)
+    a = np.sort(rng.uniform(0, 2 * np.pi, n))
+    pts = np.stack([0.5 + 0.3 * np.cos(a), 0.5 + 0.3 * np.sin(a)], axis=1)
+    inner = rng.uniform(0.3, 0.7, (n // 10, 2))
+    inner = inner[((inner - 0.5) ** 2).sum(axis=1) < 0.25 ** 2]
+    extra = [[0.5, 0.5]] if with_center else []
+    xy = np.vstack([workloads.generators.CORNERS, pts, inner] + ([np.array(extra)] if extra else []))
+    k = np.arange(n)
+    seg = np.stack([4 + k, 4 + (k + 1) % n], axis=1)[::3]  # every third chord of the polygon
+    return xy, np.vstack([workloads.generators.BOUNDARY, seg]).astype(np.int32)
+
+
+def rows_pslg(k: int = 40):
+    """Exactly collinear rows of points (dyadic coordinates) with segments
+    between row neighbours two apart: collinear and cocircular ties."""
+    h = 1.0 / 64
+    pts = [(i * h, j * h) for j in range(8, 57, 8) for i in range(4, 4 + k)]
+    xy = np.vstack([workloads.generators.CORNERS, np.array(pts)])
+    seg = [[4 + r * k + i, 4 + r * k + i + 1] for r in range(7) for i in range(0, k - 1, 3)]
+    return xy, np.vstack([workloads.generators.BOUNDARY, np.array(seg)]).astype(np.int32)
+
+
+MORE = {
+    **{f"uniform_s{s}": (lambda s=s: (lambda p: (p.xy, p.seg))(workloads.random_small(100 + s, 3000, 60)))
+       for s in range(4)},
+    **{f"knn_s{s}": (lambda s=s: (lambda p: (p.xy, p.seg))(workloads.random_small(200 + s, 5000, 400, pairing="knn")))
+       for s in range(3)},
+    "circles_b": lambda: (lambda p: (p.xy, p.seg))(workloads.scaled_config2(20, 100, 500, seed=9)),
+    "spokes_60": lambda: (lambda p: (p.xy, p.seg))(workloads.spokes(60, n_spokes=3)),
+    "circle_2000": lambda: circle_pslg(2000, False, 3),
+    "circle_2000_center": lambda: circle_pslg(2000, True, 4),
+    "rows": lambda: rows_pslg(),
+}
+
+
+@pytest.mark.parametrize("name", list(MORE))
+def test_device_cdt_more_inputs(ctx, name):
+    import oracle
+    xy, seg = MORE[name]()
+    print(f"device CDT case {name}: {len(xy)} vertices, {len(seg)} segments", flush=True)
+    dev = _device_arrays(ctx, xy, seg)
+    orc = oracle.build_cdt(xy, seg).arrays()
+    assert not diff_arrays(orc, dev), diff_arrays(orc, dev)
