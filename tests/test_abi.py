@@ -43,6 +43,9 @@ CASES = {
     "knn_5k": lambda: workloads.random_small(61, 5000, 250, pairing="knn"),
     "c1_like_50k": lambda: workloads.scaled_config1(50_000, 2_500, seed=3),
     "c2_like": lambda: workloads.scaled_config2(16, 100, 2_000, seed=4),
+    # a segment whose crossed triangles wrap around a vertex, where the slit
+    # edge left between them is itself a segment (its id must survive)
+    "knn_constrained_slit": lambda: workloads.random_small(1243, 3000, 600, pairing="knn"),
 }
 
 

@@ -148,6 +148,7 @@ MORE = {
     "circle_2000": lambda: circle_pslg(2000, False, 3),
     "circle_2000_center": lambda: circle_pslg(2000, True, 4),
     "rows": lambda: rows_pslg(),
+    "knn_constrained_slit": lambda: (lambda p: (p.xy, p.seg))(workloads.random_small(1243, 3000, 600, pairing="knn")),
 }
 
 
