@@ -9,6 +9,8 @@ from .api import (  # noqa: F401
     OracleMesh,
     build_cdt,
     refine,
+    ruppert,
+    mesh_from_arrays,
     orient2d,
     incircle,
     indiametral,

@@ -92,6 +92,13 @@ def load() -> C.CDLL:
     lib.orc_midpoint.restype = None
     lib.orc_check_subsegments.argtypes = [C.POINTER(_Mesh), P2, C.POINTER(C.c_int32), C.c_char_p, C.c_int32]
     lib.orc_check_subsegments.restype = C.c_int64
+    PI = C.POINTER(C.c_int32)
+    lib.orc_mesh_from_arrays.argtypes = [C.c_int32, C.c_int32, P2, PI, C.c_int32, PI, PI, PI,
+                                         C.c_int32, C.c_int32, PI, PI, C.POINTER(C.c_uint8)]
+    lib.orc_mesh_from_arrays.restype = C.POINTER(_Mesh)
+    lib.orc_ruppert.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_int64, C.POINTER(C.c_int64),
+                                C.c_char_p, C.c_int32]
+    lib.orc_ruppert.restype = C.c_int
     lib.orc_area_sum.argtypes = [C.POINTER(_Mesh)]
     lib.orc_area_sum.restype = C.c_double
     lib.orc_hull_vertex_count.argtypes = [C.POINTER(_Mesh)]
@@ -236,6 +243,42 @@ def build_cdt(xy: np.ndarray, seg: np.ndarray) -> OracleMesh:
     if rc != ORC_OK:
         raise OracleError(rc, err.value.decode())
     return OracleMesh(out, xy.copy(), seg.copy())
+
+
+def mesh_from_arrays(arr: dict, n_input_v: int, n_input_s: int, in_xy=None, in_seg=None) -> OracleMesh:
+    """An oracle mesh holding the given arrays (the dict form of
+    ``OracleMesh.arrays()``), e.g. a deliberately damaged copy for checker
+    tests."""
+    lib = load()
+    xy = np.ascontiguousarray(arr["xy"], dtype=np.float64).reshape(-1, 2)
+    vk = np.ascontiguousarray(arr["vkind"], dtype=np.int32)
+    tv = np.ascontiguousarray(arr["tv"], dtype=np.int32).reshape(-1, 3)
+    tn = np.ascontiguousarray(arr["tn"], dtype=np.int32).reshape(-1, 3)
+    ts = np.ascontiguousarray(arr["ts"], dtype=np.int32).reshape(-1, 3)
+    sv = np.ascontiguousarray(arr["sv"], dtype=np.int32).reshape(-1, 2)
+    sp = np.ascontiguousarray(arr["sparent"], dtype=np.int32)
+    pe = np.ascontiguousarray(arr["spend"], dtype=np.uint8)
+    PI = C.POINTER(C.c_int32)
+    ptr = lib.orc_mesh_from_arrays(xy.shape[0], n_input_v, xy.ctypes.data_as(C.POINTER(C.c_double)),
+                                   vk.ctypes.data_as(PI), tv.shape[0], tv.ctypes.data_as(PI),
+                                   tn.ctypes.data_as(PI), ts.ctypes.data_as(PI), sv.shape[0], n_input_s,
+                                   sv.ctypes.data_as(PI), sp.ctypes.data_as(PI),
+                                   pe.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if not ptr:
+        raise OracleError(ORC_E_NOMEM, "mesh_from_arrays failed")
+    return OracleMesh(ptr, in_xy, in_seg)
+
+
+def ruppert(mesh: OracleMesh, ratio_bound_sq: float, max_insertions: int = 0) -> dict:
+    """Classic sequential Ruppert refinement of ``mesh`` in place (the
+    point-count reference).  Returns the status and counters."""
+    lib = load()
+    uns = C.c_int64(0)
+    err = C.create_string_buffer(256)
+    rc = lib.orc_ruppert(mesh._p, float(ratio_bound_sq), int(max_insertions), C.byref(uns), err, 256)
+    if rc not in (ORC_OK, ORC_E_NOTERM):
+        raise OracleError(rc, err.value.decode())
+    return {"rc": rc, "n_unsplittable": uns.value}
 
 
 def refine(mesh: OracleMesh, ratio_bound_sq: float, cand_cap_K: int = 0, priority_mode: int = 0,

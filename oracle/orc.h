@@ -92,6 +92,21 @@ int orc_refine(orc_mesh *m, double ratio_bound_sq, const orc_params *p,
                char *err, int32_t errlen);
 
 orc_mesh *orc_mesh_clone(const orc_mesh *m);
+/* A mesh from caller arrays (copied; no check): xy[2nv], vkind[nv],
+   tv/tn/ts[3nt], sv[2ns], sparent[ns], spend[ns].  NULL on failure. */
+orc_mesh *orc_mesh_from_arrays(int32_t nv, int32_t n_input_v, const double *xy, const int32_t *vkind,
+                               int32_t nt, const int32_t *tv, const int32_t *tn, const int32_t *ts,
+                               int32_t ns, int32_t n_input_s, const int32_t *sv, const int32_t *sparent,
+                               const uint8_t *spend);
+
+/* Classic sequential Ruppert refinement of a CDT in place (one insertion at
+   a time from a priority queue, insertion by Lawson flips; the sequential
+   point-count reference, Ruppert mode, midpoint splits).  max_insertions > 0
+   caps the Steiner points (ORC_E_NOTERM when reached).  The mesh keeps the
+   orc_mesh conventions (CCW triangles, neighbours, subsegment ids) but not
+   the round oracle's slot order. */
+int orc_ruppert(orc_mesh *m, double ratio_bound_sq, int64_t max_insertions, int64_t *n_unsplittable,
+                char *err, int32_t errlen);
 void orc_mesh_free(orc_mesh *m);
 
 /* Exact predicates on FP64 points (p = {x, y}); return -1, 0 or +1. */

@@ -451,6 +451,24 @@ void orc_mesh_free(orc_mesh *m) {
   free(m);
 }
 
+orc_mesh *orc_mesh_from_arrays(int32_t nv, int32_t n_input_v, const double *xy, const int32_t *vkind,
+                               int32_t nt, const int32_t *tv, const int32_t *tn, const int32_t *ts,
+                               int32_t ns, int32_t n_input_s, const int32_t *sv, const int32_t *sparent,
+                               const uint8_t *spend) {
+  if (nv < 0 || nt < 0 || ns < 0) return NULL;
+  orc_mesh *m = mesh_alloc(nv + 16, nt + 16, ns + 16);
+  if (!m) return NULL;
+  m->nV = nv; m->nT = nt; m->nS = ns; m->n_input_v = n_input_v; m->n_input_s = n_input_s;
+  for (int32_t i = 0; i < nv; i++) { m->x[i] = xy[2 * i]; m->y[i] = xy[2 * i + 1]; m->vkind[i] = vkind[i]; }
+  memcpy(m->tv, tv, sizeof(int32_t) * 3 * (size_t)nt);
+  memcpy(m->tn, tn, sizeof(int32_t) * 3 * (size_t)nt);
+  memcpy(m->ts, ts, sizeof(int32_t) * 3 * (size_t)nt);
+  memcpy(m->sv, sv, sizeof(int32_t) * 2 * (size_t)ns);
+  memcpy(m->sparent, sparent, sizeof(int32_t) * (size_t)ns);
+  memcpy(m->spend, spend, (size_t)ns);
+  return m;
+}
+
 orc_mesh *orc_mesh_clone(const orc_mesh *s) {
   orc_mesh *m = mesh_alloc(s->capV, s->capT, s->capS);
   if (!m) return NULL;
