@@ -62,6 +62,41 @@ def recorded_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def loop_alg_bytes(tot: dict) -> float:
+    """What a sequential Bowyer-Watson insertion of the same points must
+    touch, from the winners' sums: per cavity triangle its record (36 B) and
+    its mark (16 B); per fan edge the incircle test outside (28 B), the new
+    triangle (36 B), the outside neighbour's repair (16 B) and the next
+    round's quality test of the new triangle (60 B); per walk step 52 B; per
+    inserted vertex 20 B."""
+    ins = tot.get("n_ins_mid", 0) + tot.get("n_ins_cc", 0)
+    return (52.0 * tot.get("win_cav_tri", 0) + 140.0 * tot.get("win_fan_edges", 0)
+            + 52.0 * tot.get("win_walk_steps", 0) + 20.0 * ins)
+
+
+def atomic_peak(ctx) -> dict:
+    """Random-slot 64-bit atomicMax throughput on a table the size of the
+    1M-point mesh's mark array (the conflict step's pattern)."""
+    from paper_2007_00324_amd import gdp2d
+    slots, ops = 6_000_000, 256_000_000
+    ms = gdp2d.gdp_bench_atomic_max(ctx, slots, ops)
+    return {"bench": f"{ops:,} atomicMax on random slots of a {slots:,}-word table", "ms": ms,
+            "gatomic_per_s": ops / (ms / 1000.0) / 1e9}
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -86,6 +121,7 @@ def cpu_baseline(p, n_points: int, n_segments: int) -> dict:
         "sample": (f"oracle refinement (initial CDT excluded), one thread, of {p.name}: {p.n_vertices:,} vertices / "
                    f"{p.n_segments:,} segments -> {steiner:,} Steiner points, {m.nT:,} output triangles in {dt:.2f} s"),
         "output_triangles_per_s": m.nT / dt,
+        **host_cpu(),
     }
 
 
@@ -488,6 +524,11 @@ def main() -> int:
         traffic = recorded_traffic()
         scan = by["k_scan"]
         scan_avg_s = scan["total_ms"] / scan["launches"] / 1000.0
+        rs = work.round_stats()
+        tot = {k: sum(r[k] for r in rs) for k in rs[0]} if rs else {}
+        loop_bytes = loop_alg_bytes(tot)
+        marks_cc = tot.get("n_marks_cc", 0)
+        atomic = atomic_peak(ctx)
         out["roofline"] = {
             "bound": "hbm",
             "kernel": ROOFLINE_KERNEL,
@@ -499,8 +540,28 @@ def main() -> int:
             "avg_launch_us": avg_s * 1e6,
             "launches": rk["launches"],
             "alg_bytes_per_launch": bytes_per_launch,
-            "traffic_over_alg": (traffic / bytes_per_launch) if traffic else None,
+            "alg_bytes_rule": ("winners only: 52 B per cavity triangle (36 B record + 16 B mark read-modify-write "
+                               "and read) + 28 B per fan edge (incircle test of the outside triangle)"),
+            "waste_ratio": (traffic / bytes_per_launch) if traffic else None,
             "dominant_kernel_by_time": dom["name"],
+            "loop": {"alg_bytes_per_step": loop_bytes,
+                     "alg_bytes_rule": ("per inserted point: 52 B per cavity triangle + 140 B per fan edge (incircle "
+                                        "test, new triangle, outside repair, next-round quality test) + 52 B per walk "
+                                        "step + 20 B vertex"),
+                     "achieved_gbs": loop_bytes / (ms_per_step / 1000.0) / 1e9,
+                     "frac": loop_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS},
+            "fallbacks": {"incircle_tests": tot.get("n_incircle_tests", 0),
+                          "orient_tests": tot.get("n_orient_tests", 0),
+                          "exact_orient": tot.get("n_exact_orient", 0), "exact_dot": tot.get("n_exact_dot", 0),
+                          "exact_incircle_b": tot.get("n_exact_incircle_b", 0),
+                          "exact_incircle_c": tot.get("n_exact_incircle_c", 0),
+                          "incircle_rate": ((tot.get("n_exact_incircle_b", 0) + tot.get("n_exact_incircle_c", 0))
+                                            / max(1, tot.get("n_incircle_tests", 0))),
+                          "orient_rate": tot.get("n_exact_orient", 0) / max(1, tot.get("n_orient_tests", 0))},
+            "atomics": {**atomic,
+                        "k_cavity_cc_marks_per_launch": marks_cc / rk["launches"],
+                        "k_cavity_cc_gatomic_per_s": marks_cc / rk["launches"] / avg_s / 1e9,
+                        "k_cavity_cc_frac_of_peak": (marks_cc / rk["launches"] / avg_s / 1e9) / atomic["gatomic_per_s"]},
             "k_scan": {"achieved": scan["alg_bytes"] / scan["launches"] / scan_avg_s / 1e9,
                        "avg_launch_us": scan_avg_s * 1e6, "alg_bytes_per_launch": scan["alg_bytes"] / scan["launches"]},
             "kernel_ms": {k["name"]: round(k["total_ms"], 3) for k in prof if k["launches"]},

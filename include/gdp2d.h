@@ -55,7 +55,8 @@ typedef enum {
   GDP_E_STALL = -6,   /* a round had candidates but inserted nothing */
   GDP_E_BUSY = -7,    /* reserved */
   GDP_E_WALK = -8,    /* a point-location walk exceeded its step cap */
-  GDP_E_CAVITY = -9   /* a cavity exceeded the cooperative-path capacity */
+  GDP_E_CAVITY = -9   /* a cavity failed an internal consistency check (its fan did not
+                         match its boundary; not expected for valid input) */
 } gdp_status;
 
 typedef struct gdp_ctx gdp_ctx;
@@ -127,6 +128,11 @@ typedef struct {
   /* rounds of the device CDT builder that made the mesh (point insertion,
      segment recovery); 0 for meshes built on the host or uploaded */
   int32_t cdt_point_rounds, cdt_segment_rounds;
+  /* FP64 filter fallbacks of the last gdp_mesh_refine: predicate calls whose
+     floating-point filter could not decide the sign and that were evaluated
+     exactly (orient2d, diametral test, incircle; the per-stage split is in
+     gdp_round_stats) */
+  int64_t fallbacks;
 } gdp_mesh_info;
 
 /* Per-round counters (device-side counts copied back after every round). */
@@ -136,6 +142,24 @@ typedef struct {
   int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
   int64_t cav_tri_total, cav_max, n_big_cavities;
   int64_t n_f1_drop, n_f2_drop;
+  /* predicate calls: incircle tests of cavity growth and of the dependency
+     test; orient2d tests of the walk (three per step) and of the fan check */
+  int64_t n_incircle_tests, n_orient_tests;
+  /* of those, evaluated exactly after the FP64 filter failed, per stage:
+     orient2d, diametral dot product, incircle on exact coordinate
+     differences, incircle on raw coordinates */
+  int64_t n_exact_orient, n_exact_dot, n_exact_incircle_b, n_exact_incircle_c;
+  /* the inserted points (all classes): sum of cavity sizes |C|, of fan
+     (boundary) edges b, and of the walk steps of the circumcenters; then |C|
+     and b of the circumcenters alone.  With these the memory work of a
+     sequential insertion of the same points can be priced. */
+  int64_t win_cav_tri, win_fan_edges, win_walk_steps, win_cc_cav_tri, win_cc_fan_edges;
+  /* cooperative cavities that outgrew the workgroup's local list and were
+     finished in device memory */
+  int64_t n_huge_cavities;
+  /* priority marks placed (64-bit atomicMax, one per cavity triangle of a
+     valid cavity): midpoint cavities, circumcenter cavities */
+  int64_t n_marks_mid, n_marks_cc;
 } gdp_round_stats;
 
 /* Fills *p with the defaults (all zero, block_size 256). */
@@ -164,8 +188,9 @@ gdp_status gdp_mesh_create(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out);
    Bowyer-Watson insertion, missing segments recovered by rounds of
    pseudo-polygon retriangulation.  Blocks until done.  Errors:
    GDP_E_ARG (NULL, fewer than 3 vertices), GDP_E_INPUT (invalid PSLG: the
-   host builder's checks; its message may differ), GDP_E_CAVITY (a Delaunay
-   cavity above 16384 triangles), GDP_E_NOMEM, GDP_E_DEVICE.  On error
+   host builder's checks; its message may differ), GDP_E_NOMEM,
+   GDP_E_DEVICE.  Cavities of any size are handled (one larger than a
+   round's per-point lists waits for a round of its own).  On error
    *out = NULL. */
 gdp_status gdp_mesh_create_device(gdp_ctx *ctx, const gdp_pslg *pslg, gdp_mesh **out);
 
@@ -210,6 +235,67 @@ gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info);
 gdp_status gdp_mesh_quality(gdp_ctx *ctx, const gdp_mesh *mesh, double ratio_bound_sq, double max_edge_len_sq,
                             int64_t *n_bad, double *bad_area);
 
+/* Zero-copy view of a mesh in device memory (Section 4.1: the output is the
+   refined CDT with its Steiner vertices and subsegments).  Every pointer is a
+   device address on the mesh's context device; the arrays belong to the
+   library and stay valid until the mesh is freed or passed to a call that
+   modifies it (gdp_mesh_refine, gdp_mesh_assign), which may move them.  A
+   caller may wrap them (e.g. as torch tensors) without taking ownership.
+   Layout, counts as in gdp_mesh_info:
+     xy          : 2V doubles, x then y of each vertex;
+     vkind       : V int32 (0 input, 1 midpoint, 2 circumcenter);
+     tri         : 4T int32, (v0, v1, v2, m) per triangle, counter-clockwise,
+                   bit i of m set when edge i (v_i, v_{i+1 mod 3}) is a subsegment;
+     nbr         : 4T int32, (n0, n1, n2, 0): the triangle across edge i or -1;
+     sub_on_edge : 4T int32, (s0, s1, s2, 0): the subsegment on edge i or -1;
+     sub_v       : 2S int32 endpoints; sub_parent: S int32 input segment;
+     sub_pending : S int32 (0/1).
+   GDP_E_ARG for a NULL argument. */
+typedef struct {
+  int32_t n_vertices, n_triangles, n_subsegments;
+  int32_t tri_stride; /* int32 per triangle record: 4 */
+  const double *xy;
+  const int32_t *vkind;
+  const int32_t *tri;
+  const int32_t *nbr;
+  const int32_t *sub_on_edge;
+  const int32_t *sub_v;
+  const int32_t *sub_parent;
+  const int32_t *sub_pending;
+} gdp_device_views;
+gdp_status gdp_mesh_device_views(const gdp_mesh *mesh, gdp_device_views *out);
+
+/* The refinement's geometric predicates (Section 4.1 and Section 4.2:
+   circumcircle and diametral-circle tests; Section 7: exact arithmetic),
+   evaluated for testing on n queries of one kind, in the same code the
+   kernels run:
+     kind 0: orient2d(a, b, c)           pts: 6 doubles per query (ax ay bx by cx cy),
+             signs[i] = 1 counter-clockwise, -1 clockwise, 0 collinear;
+     kind 1: incircle(a, b, c, d)         8 doubles; 1 if d is strictly inside the
+             circle through a, b, c (counter-clockwise), -1 outside, 0 on it;
+     kind 2: indiametral(a, b, c)         6 doubles; 1 if c is strictly inside the
+             circle with diameter ab, -1 outside, 0 on it;
+     kind 3: lens encroachment of ab by c 6 doubles; 1 if c is strictly inside the
+             diametric lens of ab (the points seeing ab under more than 120
+             degrees), else 0.
+   ctx non-NULL: one thread per query on the context's device and stream
+   (blocks until done; host arrays are copied); ctx NULL: on the host.
+   stage_counts (optional, 4 entries) receives the exact evaluations made,
+   per stage: orient2d, diametral dot product, incircle on exact differences,
+   incircle on raw coordinates.  Coordinates must satisfy the range of
+   gdp_pslg.  GDP_E_ARG for a bad kind, n < 0 or NULL arrays with n > 0. */
+gdp_status gdp_predicates_eval(gdp_ctx *ctx, int32_t kind, int32_t n, const double *pts, int32_t *signs,
+                               int64_t *stage_counts);
+
+/* Measurement of the conflict step's memory pattern (Section 5.2: each
+   cavity triangle takes the largest priority of the cavities that hold it,
+   here a 64-bit atomicMax): n_ops atomicMax operations on random slots of a
+   table of n_slots 64-bit words in device memory, one thread per operation
+   in a grid-stride loop.  *ms gets the device time of the timed launch (a
+   first launch warms the table).  Blocks until done.  GDP_E_ARG for
+   non-positive sizes, GDP_E_NOMEM when the table does not fit. */
+gdp_status gdp_bench_atomic_max(gdp_ctx *ctx, int64_t n_slots, int64_t n_ops, double *ms);
+
 /* Copies the mesh to caller buffers sized from gdp_mesh_info_get (any pointer
    may be NULL to skip that array): xy[2V], vkind[V] (0 input, 1 midpoint,
    2 circumcenter), tri/nbr/sub_on_edge[3T], sub_v[2S], sub_parent[S] (input
@@ -252,11 +338,15 @@ gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *r
    A server refines meshing jobs as they arrive, with continuous batching:
    arrived jobs are admitted while there is a free slot and room in the
    server's device memory (each job's region is sized from its initial CDT),
-   every admitted job advances a few rounds per launch of the single-workgroup
-   engine alongside the others, and finished jobs leave, freeing their slot.
-   Each result is bit-identical to gdp_refine on the same input.  A job that
-   outgrows its region is refined again on its own.  Latency is measured from
-   arrival (after Line 1, which runs in the caller's thread at prepare). */
+   admitted jobs are refined at once, side by side on the device, and
+   finished jobs leave, freeing their slot and region for the next arrival.
+   By default each admitted job runs its rounds on a slot of its own (one
+   stream and one library thread per slot); with gdp_server_engine_jobs,
+   small jobs are instead refined together, one workgroup each, in launches
+   of the single-workgroup engine.  Each result is bit-identical to
+   gdp_refine on the same input.  A job that outgrows its region is refined
+   again on its own.  Latency is measured from arrival (after Line 1, which
+   runs in the caller's thread at prepare). */
 typedef struct gdp_server gdp_server;
 
 typedef struct {
@@ -266,11 +356,7 @@ typedef struct {
 } gdp_job_times;
 
 /* hbm_budget: bytes of device memory for job regions; max_slots: jobs on the
-   device at once on their own streams (one library thread each).  Optionally
-   (gdp_server_engine_jobs; off by default) small jobs do not use a slot: the
-   arrived ones are refined together in one launch of the single-workgroup
-   engine (one workgroup per job, largest first), driven by one more library
-   thread.  Every job's mesh is the same on either path. */
+   device at once on their own streams (one library thread each). */
 gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out);
 /* Jobs with at most max_input_vertices input vertices go to the batched
    launches (0: every job takes a slot).  Applies to jobs admitted afterwards.

@@ -73,6 +73,9 @@ struct gdp_mesh {
   FanRec *fan = nullptr;
   int32_t fan_cap = 0;
   int32_t *big = nullptr;
+  int32_t *hvis = nullptr, *hlist = nullptr;  // [capT] cavities beyond the LDS list (device-memory path)
+  bool huge_mode = false;  // launch the device-memory cavity path (set once a round needed it)
+  bool engine_off = false; // a single-workgroup engine round met a cavity beyond its LDS list
   int32_t *prev_cc_elem = nullptr;
   uint64_t *prev_cc_key = nullptr;
   double2 *prev_cc_p = nullptr;
@@ -219,6 +222,8 @@ gdp_status grow_tri(gdp_mesh *M, int32_t need) {
   HIPCHECK(dgrow(&M->prev_cc_p, oc, nc, oc, 0, s));
   HIPCHECK(dgrow(&M->tstamp, oc, nc, oc, 0xff, s));
   HIPCHECK(dgrow(&M->cidx_t, oc, nc, oc, 0, s));
+  HIPCHECK(dgrow(&M->hvis, oc, nc, 0, 0, s));
+  HIPCHECK(dgrow(&M->hlist, oc, nc, 0, 0, s));
   M->m.capT = nc;
   return GDP_OK;
 }
@@ -318,6 +323,7 @@ Work make_work(gdp_mesh *M, const gdp_params *P, int parity) {
   w.st = M->d_st;
   w.cnt = M->d_cnt;
   w.stat = M->d_stat;
+  w.tally = (uint64_t *)M->d_stat;
   w.hist = M->d_hist;
   w.hist_cap = kHistCap;
   w.mark = M->mark;
@@ -342,6 +348,8 @@ Work make_work(gdp_mesh *M, const gdp_params *P, int parity) {
   w.pool = M->pool; w.pool_cap = M->pool_cap;
   w.fan = M->fan; w.fan_cap = M->fan_cap;
   w.big = M->big; w.big_cap = M->wT;
+  w.hvis = M->hvis; w.hlist = M->hlist; w.hcap = M->m.capT;
+  w.huge_ok = M->huge_mode ? 1 : 0;
   w.tstamp = M->tstamp;
   w.cidx_t = M->cidx_t; w.cidx_s = M->cidx_s;
   w.keys = M->keys; w.rhist = M->rhist; w.sel = M->sel;
@@ -413,7 +421,7 @@ void free_mesh_arrays(gdp_mesh *M) {
                   M->w0_t, M->w0_s, M->win_t, M->win_s, M->rank_t, M->rank_s, M->win_ref, M->fbase,
                   M->fcount, M->fan_off, M->repl, M->pool, M->fan, M->big, M->keys, M->rhist, M->sel,
                   M->d_st, M->d_hist, M->tiles_t, M->tiles_s, M->tiles_f, M->prev_cc_elem, M->prev_cc_key, M->prev_cc_p, M->prev_mid_elem, M->tstamp,
-                  M->cidx_t, M->cidx_s};
+                  M->cidx_t, M->cidx_s, M->hvis, M->hlist};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_extras(M);
@@ -608,6 +616,7 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   {
     Prof pr(M, P_CAV_BIG);
     hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 0);
+    if (M->huge_mode) hipLaunchKernelGGL(k_cavity_huge, dim3(1), dim3(kHugeBlock), 0, s, m, w, 0);
   }
   {
     Prof pr(M, P_CAV_MID);
@@ -616,6 +625,7 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   {
     Prof pr(M, P_CAV_BIG);
     hipLaunchKernelGGL(k_cavity_big, dim3(256), dim3(kBigBlockSize), 0, s, m, w, 1);
+    if (M->huge_mode) hipLaunchKernelGGL(k_cavity_huge, dim3(1), dim3(kHugeBlock), 0, s, m, w, 1);
   }
   // ---- R8 ownership, R9 dependency ----
   {
@@ -678,6 +688,20 @@ gdp_round_stats round_stats_of(const DevCounters &c, const gdp_params *P) {
   rs.n_mid_cand = c.n_mid_cand;
   rs.n_f1_drop = c.n_f1_drop;
   rs.n_f2_drop = c.n_f2_drop;
+  rs.n_incircle_tests = c.n_in_tests;
+  rs.n_orient_tests = c.n_or_tests + c.cav_bnd[0] + c.cav_bnd[1];
+  rs.n_exact_orient = c.n_exact[kExOrient];
+  rs.n_exact_dot = c.n_exact[kExDot];
+  rs.n_exact_incircle_b = c.n_exact[kExInB];
+  rs.n_exact_incircle_c = c.n_exact[kExInC];
+  rs.win_cav_tri = c.win_cav;
+  rs.win_fan_edges = c.win_bnd;
+  rs.win_walk_steps = c.win_steps;
+  rs.win_cc_cav_tri = c.win_cc_cav;
+  rs.win_cc_fan_edges = c.win_cc_bnd;
+  rs.n_huge_cavities = c.nhuge;
+  rs.n_marks_mid = c.n_marks[0];
+  rs.n_marks_cc = c.n_marks[1];
   return rs;
 }
 
@@ -706,17 +730,18 @@ int64_t prof_items(int id, const DevCounters &c, int64_t nT, int64_t pc, int64_t
 //   written, stamp 4), each rewritten slot (fan slot 4 + record 16 + three
 //   vertices 48) and the previous flagged list (entry 4 + pending flag 4),
 //   plus the new records / flags.
-//   Circumcenter cavities: per candidate its state, located triangle, point
-//   and key (32 B) and state / offset / size written (12 B); per cavity
-//   triangle its tv, tn and ts records (48 B), one new vertex (16 B), the
-//   pool entry (4 B) and its mark (8 B); per boundary edge the outside
-//   triangle's tv record (16 B).
+//   Circumcenter cavities: what a sequential insertion of the same points
+//   touches for them, counted over the winners only (the cavities of points
+//   that lose are waste): per cavity triangle its record (36 B) and its
+//   priority mark (8 B read-modify-write + 8 B read), per boundary edge the
+//   incircle test of the triangle outside (12 B of vertex ids + 16 B for the
+//   far vertex).
 int64_t alg_bytes(int id, const DevCounters &c, int64_t nT, int64_t nV, int64_t nS, int64_t pc, int64_t pmk,
                   int64_t pf, bool full) {
   if (id == P_SCAN)
     return full ? 16 * nT + 16 * nV + 40 * nS + 4 * nS + 32LL * c.ncc + 12LL * c.nmk0
                 : 64 * pc + 68 * pf + 8 * pmk + 32LL * c.ncc + 12LL * c.nmk0;
-  if (id == P_CAV_CC) return 44LL * c.ncc + 76 * c.cav_len[1] + 16 * c.cav_bnd[1];
+  if (id == P_CAV_CC) return 52 * c.win_cc_cav + 28 * c.win_cc_bnd;
   return 0;
 }
 
@@ -890,6 +915,8 @@ void for_each_array(gdp_mesh *M, const Caps &c, F f) {
   f((void **)&M->repl, 4, 4 * c.T, 0xff);
   f((void **)&M->tstamp, 4, c.T, 0xff);
   f((void **)&M->cidx_t, 4, c.T, 0);
+  f((void **)&M->hvis, 4, c.T, 0);
+  f((void **)&M->hlist, 4, c.T, 0);
   f((void **)&M->cidx_s, 4, c.S, 0);
   f((void **)&M->win_ref, 4, c.W, 0);
   f((void **)&M->fbase, 4, c.W, 0);
@@ -1751,7 +1778,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   for (;;) {
     // small rounds run in the single-workgroup engine
     const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
-    const bool engine = !full && eng_max > 0 && last_cand <= eng_max;
+    const bool engine = !full && !M->engine_off && eng_max > 0 && last_cand <= eng_max;
     const int R = full ? 1 : rounds_for(P, last_cand, engine);
     gdp_status st;
     if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, engine ? 4 : R))) return st;
@@ -1837,13 +1864,17 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
         snprintf(buf, sizeof buf, "fan boundary mismatch (cc=%d elem=%d cavity=%d expected=%d found=%d state=%d)",
                  c.dbg[0], c.dbg[1], c.dbg[2], c.dbg[3], c.dbg[4], c.dbg[5]);
       else
-        snprintf(buf, sizeof buf, "cavity exceeded the cooperative-path capacity");
+        snprintf(buf, sizeof buf, "cavity step failed");
       result = fail(ctx, GDP_E_CAVITY, buf);
       break;
     }
     if (d.halt == kHaltStall) { result = fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing"); break; }
     // kHaltAbort: nothing was written; grow and run the same round again
     if (++aborts > 16) return fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
+    if (c.err & kErrHuge) {  // rerun with the device-memory cavity path, on the grid kernels
+      M->huge_mode = true;
+      if (engine) M->engine_off = true;
+    }
     if ((st = grow_after_abort(M, c, full ? 0 : d.prev_fan))) return st;
     HIPCHECK(hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s));
     HIPCHECK(hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s));
@@ -2097,6 +2128,115 @@ gdp_status gdp_mesh_info_get(const gdp_mesh *mesh, gdp_mesh_info *info) {
   info->rounds = mesh->m.rounds;
   info->cdt_point_rounds = mesh->cdt_rounds[0];
   info->cdt_segment_rounds = mesh->cdt_rounds[1];
+  int64_t fb = 0;
+  for (const gdp_round_stats &r : mesh->stats)
+    fb += r.n_exact_orient + r.n_exact_dot + r.n_exact_incircle_b + r.n_exact_incircle_c;
+  info->fallbacks = fb;
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_device_views(const gdp_mesh *mesh, gdp_device_views *out) {
+  if (!mesh || !out) return GDP_E_ARG;
+  const DevMesh &m = mesh->m;
+  out->n_vertices = m.nV;
+  out->n_triangles = m.nT;
+  out->n_subsegments = m.nS;
+  out->tri_stride = 4;
+  out->xy = (const double *)m.vxy;
+  out->vkind = m.vkind;
+  out->tri = (const int32_t *)m.tv;
+  out->nbr = (const int32_t *)m.tn;
+  out->sub_on_edge = (const int32_t *)m.ts;
+  out->sub_v = (const int32_t *)m.sv;
+  out->sub_parent = m.spar;
+  out->sub_pending = m.spend;
+  return GDP_OK;
+}
+
+gdp_status gdp_bench_atomic_max(gdp_ctx *ctx, int64_t n_slots, int64_t n_ops, double *ms) {
+  if (!ctx || n_slots <= 0 || n_ops <= 0 || !ms) return ctx ? fail(ctx, GDP_E_ARG, "bad atomic benchmark size") : GDP_E_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = ctx->stream;
+  uint64_t *table = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipMalloc((void **)&table, sizeof(uint64_t) * (size_t)n_slots) != hipSuccess)
+    return fail(ctx, GDP_E_NOMEM, "atomic benchmark table");
+  hipError_t e = hipMemsetAsync(table, 0, sizeof(uint64_t) * (size_t)n_slots, s);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  // one launch warms the table and the code object, the second is timed
+  const unsigned grid = 256 * 32;
+  for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+    if (rep == 1) e = hipEventRecord(a, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_atomic_max_bench, dim3(grid), dim3(256), 0, s, table, (uint64_t)n_slots, n_ops,
+                         (uint64_t)(rep + 1) * 0x2545f4914f6cdd1dull);
+      e = hipGetLastError();
+    }
+    if (rep == 1 && e == hipSuccess) e = hipEventRecord(b, s);
+  }
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(table);
+  if (e != hipSuccess) return fail(ctx, GDP_E_DEVICE, std::string("atomic benchmark: ") + hipGetErrorString(e));
+  *ms = t;
+  return GDP_OK;
+}
+
+gdp_status gdp_predicates_eval(gdp_ctx *ctx, int32_t kind, int32_t n, const double *pts, int32_t *signs,
+                               int64_t *stage_counts) {
+  if (kind < 0 || kind > 3 || n < 0 || (n > 0 && (!pts || !signs))) return ctx ? fail(ctx, GDP_E_ARG, "bad predicate query") : GDP_E_ARG;
+  const int w = kind == 1 ? 8 : 6;
+  if (!ctx) {
+    uint64_t tally[kTallyStride] = {};
+    for (int32_t i = 0; i < n; i++) {
+      const double *q = pts + (size_t)i * w;
+      int r;
+      if (kind == 0) r = orient2d(q[0], q[1], q[2], q[3], q[4], q[5], tally);
+      else if (kind == 1) r = incircle(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], tally);
+      else if (kind == 2) r = indiametral(q[0], q[1], q[2], q[3], q[4], q[5], tally);
+      else r = encroaches(1, q[0], q[1], q[2], q[3], q[4], q[5], tally) ? 1 : 0;
+      signs[i] = r;
+    }
+    if (stage_counts)
+      for (int e = 0; e < kExStages; e++) stage_counts[e] = (int64_t)tally[kTally0 + e];
+    return GDP_OK;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = ctx->stream;
+  const size_t tally_words = (size_t)kTallyStripes * kTallyStride;
+  double *d_pts = nullptr;
+  int32_t *d_out = nullptr;
+  uint64_t *d_tally = nullptr;
+  std::vector<uint64_t> h_tally(tally_words);
+  hipError_t e = hipMalloc((void **)&d_pts, sizeof(double) * std::max<size_t>(1, (size_t)n * w));
+  if (e == hipSuccess) e = hipMalloc((void **)&d_out, sizeof(int32_t) * std::max<int32_t>(1, n));
+  if (e == hipSuccess) e = hipMalloc((void **)&d_tally, sizeof(uint64_t) * tally_words);
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpyAsync(d_pts, pts, sizeof(double) * (size_t)n * w, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(d_tally, 0, sizeof(uint64_t) * tally_words, s);
+  if (e == hipSuccess && n > 0) {
+    hipLaunchKernelGGL(k_predicates, dim3((n + 255) / 256), dim3(256), 0, s, (int)kind, (int)n,
+                       (const double *)d_pts, d_out, d_tally);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(signs, d_out, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h_tally.data(), d_tally, sizeof(uint64_t) * tally_words, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_pts);
+  (void)hipFree(d_out);
+  (void)hipFree(d_tally);
+  if (e != hipSuccess) return fail(ctx, GDP_E_DEVICE, std::string("predicate evaluation: ") + hipGetErrorString(e));
+  if (stage_counts)
+    for (int x = 0; x < kExStages; x++) {
+      int64_t sum = 0;
+      for (int i = 0; i < kTallyStripes; i++) sum += (int64_t)h_tally[(size_t)i * kTallyStride + kTally0 + x];
+      stage_counts[x] = sum;
+    }
   return GDP_OK;
 }
 

@@ -29,10 +29,9 @@
 //      so the result is the one sequential insertion gives.
 //   3. Triangles with an enclosing vertex are dropped; every dropped/kept
 //      boundary must be a segment, every vertex used, the kept region a
-//      convex disk; the survivors are rotated, sorted by (v0, v1) and
-//      renumbered into the refinement's mesh layout.
-#include <hipcub/hipcub.hpp>
-
+//      convex disk; the survivors are rotated, sorted by (v0, v1) with a
+//      radix sort of this file and renumbered into the refinement's mesh
+//      layout.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -47,7 +46,7 @@ constexpr int kBlk = 256;        // block of the plain kernels
 constexpr int kCavBlk = 128;     // block of the cavity kernels
 constexpr int kLdsCap = 32;      // cavity triangles per thread kept in LDS
 constexpr int kBigSlots = 64;    // cavities above kLdsCap handled per round
-constexpr int kBigCap = 16384;   // triangles of one such cavity
+constexpr int kBigCap = 16384;   // triangles of one such cavity (a larger one waits, see mark_cavity)
 constexpr int kWalkCap = 1 << 20;   // steps of one walk or rotation
 
 enum CdtErr : int {
@@ -99,7 +98,8 @@ struct Bld {
   uint64_t *ring;         // per slot: largest ring stamp of a point cavity
   int *hint, *state;      // per point: last triangle, -2 / -1 (LDS cavity) / big slot
   int *vt;                // per vertex: an incident triangle
-  int *big;               // kBigSlots * kBigCap
+  int *big;               // kBigSlots * kBigCap, or the whole area for the one cavity of a solo round
+  int big_all;            // ints of the area (>= capT: room for any cavity)
   int *pool;              // per-round scratch
   int pool_cap;
   Ctr *c;
@@ -330,7 +330,11 @@ __device__ int grow(const Bld &b, int p, List L, int cap, uint64_t key, int mode
 
 // Stamps the start triangle and grows the cavity of p (mode 0) in L; on a
 // full list continues in a large list of the global pool when one is free.
-// Returns the state: -1 (cavity in LDS), a big-list slot, or -2 (none).
+// Returns the state: -1 (cavity in LDS), a big-list slot, or -2 (none).  A
+// cavity beyond a big list waits: the point stays pending, its cavity
+// shrinks as its neighbourhood fills in, and a round that inserts nothing
+// is followed by a solo round whose one point may use the whole area, which
+// holds any cavity (the triangles of a cavity are distinct live slots).
 __device__ int mark_cavity(const Bld &b, int p, int t0, uint64_t key, List L, int cap, bool big_only) {
   const uint64_t old = atomicMax((unsigned long long *)&b.mark[t0], (unsigned long long)key);
   if (old > key) return -2;
@@ -338,8 +342,8 @@ __device__ int mark_cavity(const Bld &b, int p, int t0, uint64_t key, List L, in
   if (big_only) {
     const List G{b.big, 1};
     G[0] = t0;
-    const int r = grow(b, p, G, kBigCap, key, 0, h, n);
-    if (r == -1) set_err(b.c, kECavity);
+    const int r = grow(b, p, G, b.big_all, key, 0, h, n);
+    if (r == -1) set_err(b.c, kEInternal + 3);
     return r > 0 ? 0 : -2;
   }
   L[0] = t0;
@@ -351,7 +355,6 @@ __device__ int mark_cavity(const Bld &b, int p, int t0, uint64_t key, List L, in
   const List G{b.big + (size_t)slot * kBigCap, 1};
   for (int k = 0; k < n; k++) G[k] = L[k];
   r = grow(b, p, G, kBigCap, key, 0, h, n);
-  if (r == -1) set_err(b.c, kECavity);
   return r > 0 ? slot : -2;
 }
 
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(kCavBlk) void k_mark(Bld b, const int *pend, int np
 // compact = 1: the points not inserted go to pend_out; compact = 0: the
 // list stays and each inserted point leaves -1 in its entry.
 __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, uint32_t round, int *pend_out,
-                                                    int compact) {
+                                                    int compact, int solo) {
   __shared__ int s_list[kLdsCap * kCavBlk];
   const List lds{&s_list[threadIdx.x], kCavBlk};
   const int stride = gridDim.x * blockDim.x;
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(kCavBlk) void k_insert(Bld b, int *pend, int np, ui
       if (st != -2) {
         const uint64_t key = ((uint64_t)round << 32) | mix32((uint32_t)p);
         int cap = kLdsCap;
-        if (st >= 0) { L = List{b.big + (size_t)st * kBigCap, 1}; cap = kBigCap; }
+        if (st >= 0) { L = List{b.big + (size_t)st * kBigCap, 1}; cap = solo ? b.big_all : kBigCap; }
         const int t0 = b.hint[p];
         if (b.mark[t0] == key && b.ring[t0] <= key) {
           b.pick[t0] = key;
@@ -843,6 +846,136 @@ __global__ void k_emit(Bld b, int nk, const int *vals, const int *newid, int4 *o
   }
 }
 
+// ---------------------------------------------------------------------------
+// Canonical order: least-significant-digit radix sort of (key, value) pairs
+// by 8-bit digits, one stable counting pass per digit that varies:
+//   1. tile histograms (a tile is kSortThreads x kSortItems keys), written
+//      digit-major, so that
+//   2. one exclusive scan gives every (digit, tile) its output offset;
+//   3. each tile scatters its keys in their input order: items are taken
+//      kSortThreads at a time; inside a wave, lanes with the same digit find
+//      each other by eight ballots (one per digit bit) and rank themselves by
+//      the lanes below; the waves' digit counts, taken in wave order, and the
+//      running count of the tile's earlier items complete the rank.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaves = kSortThreads / 64;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *keys, int n, int shift, int ntiles,
+                                                            int *hist) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int j = 0; j < kSortItems; j++) {
+    const int i = base + j * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of hist[0..m) in place by one workgroup of kSortScanThreads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS, then
+// each thread rewrites its chunk.
+constexpr int kSortScanThreads = 1024;
+__global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(int *hist, int m) {
+  __shared__ int part[kSortScanThreads];
+  const int chunk = (m + kSortScanThreads - 1) / kSortScanThreads;
+  const int lo = threadIdx.x * chunk, hi = min(m, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; i++) s += hist[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < kSortScanThreads; i++) {
+      const int x = part[i];
+      part[i] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int i = lo; i < hi; i++) {
+    const int x = hist[i];
+    hist[i] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t *keys, const int *vals,
+                                                               uint64_t *keys_out, int *vals_out, int n, int shift,
+                                                               int ntiles, const int *offs) {
+  __shared__ int run[256];       // items of the tile ranked so far, per digit
+  __shared__ int wcnt[kSortWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  run[threadIdx.x] = offs[threadIdx.x * ntiles + blockIdx.x];
+  for (int w = 0; w < kSortWaves; w++) wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int j = 0; j < kSortItems; j++) {
+    const int i = base + j * kSortThreads + threadIdx.x;
+    const bool act = i < n;
+    const uint64_t k = act ? keys[i] : 0ull;
+    const int v = act ? vals[i] : 0;
+    const int d = (int)((k >> shift) & 0xff);
+    uint64_t peers = __ballot(act);
+    for (int bit = 0; bit < 8; bit++) {
+      const uint64_t m = __ballot((d >> bit) & 1);
+      peers &= ((d >> bit) & 1) ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    if (act && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (act) {
+      int pos = run[d] + rank;
+      for (int w = 0; w < wave; w++) pos += wcnt[w][d];
+      keys_out[pos] = k;
+      vals_out[pos] = v;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < kSortWaves; w++) {
+      add += wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = 0;
+    }
+    run[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// Sorts n pairs by key bits [0, 32 + vbits) and [32, 32 + vbits) (a key is
+// (a << 32) | b with a, b < 2^vbits); the result ends in (k1, v1).  hist
+// holds 256 * ceil(n / kSortTile) ints.
+hipError_t radix_sort_pairs(hipStream_t stream, uint64_t *k0, int *v0, uint64_t *k1, int *v1, int n, int vbits,
+                            int *hist) {
+  if (n <= 0) return hipSuccess;
+  const int ntiles = (n + kSortTile - 1) / kSortTile;
+  int shifts[16], ns = 0;
+  for (int half = 0; half < 2; half++)
+    for (int b = 0; b < vbits; b += 8) shifts[ns++] = 32 * half + b;
+  uint64_t *kin = k0, *kout = k1;
+  int *vin = v0, *vout = v1;
+  for (int p = 0; p < ns; p++) {
+    k_sort_hist<<<ntiles, kSortThreads, 0, stream>>>(kin, n, shifts[p], ntiles, hist);
+    k_sort_scan<<<1, kSortScanThreads, 0, stream>>>(hist, 256 * ntiles);
+    k_sort_scatter<<<ntiles, kSortThreads, 0, stream>>>(kin, vin, kout, vout, n, shifts[p], ntiles, hist);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  // after an odd number of passes the result is in (k1, v1); else copy it there
+  if (kin != k1) {
+    hipError_t e = hipMemcpyAsync(k1, kin, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(v1, vin, sizeof(int) * n, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
 __global__ void k_iota(int n, int *a) {
   const int stride = gridDim.x * blockDim.x;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = i;
@@ -878,16 +1011,14 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   const size_t o_tv = take(sizeof(int4) * capT), o_tn = take(sizeof(int4) * capT), o_ts = take(sizeof(int4) * capT);
   const size_t o_pick = take(8 * (size_t)capT), o_mark = take(8 * (size_t)capT), o_ring = take(8 * (size_t)capT);
   const size_t o_hint = take(4 * (size_t)nv), o_state = take(4 * (size_t)std::max(nv, ns));
-  const size_t o_vt = take(4 * (size_t)(nv + 3)), o_big = take(4 * (size_t)kBigSlots * kBigCap);
+  const int big_all = std::max(kBigSlots * kBigCap, capT);
+  const size_t o_vt = take(4 * (size_t)(nv + 3)), o_big = take(4 * (size_t)big_all);
   const size_t o_pool = take(4 * (size_t)pool_cap);
   const size_t o_p0 = take(4 * (size_t)std::max(nv, ns)), o_p1 = take(4 * (size_t)std::max(nv, ns));
   const size_t o_ctr = take(sizeof(Ctr)), o_ntri = take(4), o_used = take(4 * (size_t)nv);
   const size_t o_keys = take(8 * (size_t)capT), o_keys2 = take(8 * (size_t)capT);
   const size_t o_vals = take(4 * (size_t)capT), o_vals2 = take(4 * (size_t)capT), o_newid = take(4 * (size_t)capT);
-  size_t sort_bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr, (int *)nullptr,
-                                     (int *)nullptr, capT, 0, 64, stream);
-  const size_t o_sort = take(sort_bytes + 256);
+  const size_t o_sort = take(4 * 256 * (size_t)((capT + kSortTile - 1) / kSortTile));
   if (hipMalloc(&mem, off) != hipSuccess) { err = "device allocation failed"; return GDP_E_NOMEM; }
   char *base = (char *)mem;
   Ctr *hctr = nullptr;
@@ -907,6 +1038,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   b.pick = (uint64_t *)(base + o_pick); b.mark = (uint64_t *)(base + o_mark); b.ring = (uint64_t *)(base + o_ring);
   b.hint = (int *)(base + o_hint); b.state = (int *)(base + o_state);
   b.vt = (int *)(base + o_vt); b.big = (int *)(base + o_big);
+  b.big_all = big_all;
   b.pool = (int *)(base + o_pool); b.pool_cap = pool_cap;
   b.c = (Ctr *)(base + o_ctr);
   int *pl[2] = {(int *)(base + o_p0), (int *)(base + o_p1)};
@@ -939,7 +1071,7 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
         hipMemsetAsync(&b.c->first, 0x7f, sizeof(int), stream) != hipSuccess) { err = "device call failed"; return done(GDP_E_DEVICE); }
     k_locate<<<grid_for(nl, kBlk), kBlk, 0, stream>>>(b, pl[cur], nl, round, solo, thresh, relocate);
     k_mark<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, solo, thresh);
-    k_insert<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, pl[cur ^ 1], compact);
+    k_insert<<<grid_for(nl, kCavBlk), kCavBlk, 0, stream>>>(b, pl[cur], nl, round, pl[cur ^ 1], compact, solo);
     if (!round_trip()) { err = "device call failed"; return done(GDP_E_DEVICE); }
     if (hctr->err) { err = std::string("points (round " + std::to_string(dt_rounds) + "): ") + cdt_err_string(hctr->err); return done(hctr->err == kECavity ? GDP_E_CAVITY : (hctr->err >= kEInternal ? GDP_E_DEVICE : GDP_E_INPUT)); }
     if (compact && hctr->npend != np - hctr->nwin) { err = "device CDT builder: lost points"; return done(GDP_E_DEVICE); }
@@ -986,8 +1118,9 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   const int nk = hctr->nkeep;
   if ((int64_t)nk != 2 * (int64_t)nv - hctr->nhull - 2) { err = "the kept region is not a disk"; return done(GDP_E_INPUT); }
   if (nk > cap_out) { err = "output capacity"; return done(GDP_E_NOMEM); }
-  size_t sb = sort_bytes;
-  if (hipcub::DeviceRadixSort::SortPairs(base + o_sort, sb, keys, keys2, vals, vals2, nk, 0, 64, stream) != hipSuccess)
+  int vbits = 1;
+  while (vbits < 31 && (1 << vbits) < nv + 3) vbits++;
+  if (radix_sort_pairs(stream, keys, vals, keys2, vals2, nk, vbits, (int *)(base + o_sort)) != hipSuccess)
     { err = "sort failed"; return done(GDP_E_DEVICE); }
   k_newid<<<grid_for(nk, kBlk), kBlk, 0, stream>>>(nk, vals2, newid);
   k_emit<<<grid_for(nk, kBlk), kBlk, 0, stream>>>(b, nk, vals2, newid, otv, otn, ots);

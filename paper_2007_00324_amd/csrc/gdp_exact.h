@@ -5,20 +5,19 @@
 // exact arithmetic and robust predicates).  Here each test runs in stages:
 //   A. an FP64 evaluation with a forward error bound (most calls end here);
 //   B. (incircle) if every coordinate difference is exact in FP64, the
-//      determinant of the differences is evaluated exactly with
-//      floating-point expansions;
+//      determinant of the differences is evaluated exactly;
 //   C. otherwise the determinant is expanded in raw coordinates (the lifted
-//      4x4 form for incircle) and evaluated exactly with expansions.
-// Expansion arithmetic follows J. R. Shewchuk, "Adaptive Precision
-// Floating-Point Arithmetic and Fast Robust Geometric Predicates" (1997):
-// error-free sum and product of two doubles, growing an expansion by a
-// double, scaling an expansion by a double, each with zero elimination; the
-// sign of a nonoverlapping expansion is the sign of its largest component.
+//      4x4 form for incircle) and evaluated exactly.
+// The exact stages split every product into doubles without error (the
+// error-free product of two doubles, with a fused multiply-add) and sum
+// them in a fixed-point long accumulator (below), whose frame is a few
+// hundred bytes: small enough that kernels calling these predicates need
+// little scratch memory per lane.
 //
 // Exactness needs every nonzero coordinate in [2^-100, 2^20] in magnitude
-// (the library validates its inputs and guards computed points), so no
-// product underflows or overflows.  Build with -ffp-contract=off: the filter
-// bounds assume separately rounded operations.
+// (the library validates its inputs and guards computed points).  Build
+// with -ffp-contract=off: the filter bounds assume separately rounded
+// operations.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,166 +45,191 @@ GDP_HD void two_prod(double a, double b, double &x, double &y) {
   y = fma(a, b, -x);
 }
 
-// h = e + b (e nonoverlapping, increasing magnitude).  h may alias e.
-GDP_HD int grow_exp(int elen, const double *e, double b, double *h) {
-  double q = b;
-  int n = 0;
-  for (int i = 0; i < elen; i++) {
-    double s, t;
-    two_sum(q, e[i], s, t);
-    q = s;
-    if (t != 0.0) h[n++] = t;
+// ---- exact slow paths: a fixed-point long accumulator ----------------------
+// Every exact evaluation below is a signed sum of products of two or four
+// coordinates (or of exact coordinate differences).  Each product is split
+// into doubles without error (two_prod, twice for four factors), and every
+// such double is added exactly into a fixed-point accumulator of 32-bit
+// digits: the long accumulator of exact dot products (U. Kulisch, "Computer
+// Arithmetic and Validity", 2008; one digit array wide enough for the whole
+// exponent range of the terms).  The sign of the sum is read after one carry
+// pass.  The digits are int64, so each can take more than 2^30 additions of
+// a value below 2^32 before a carry is needed; an evaluation adds at most 384.
+//
+// Range: with every nonzero coordinate in [2^-100, 2^20], a coordinate's
+// lowest set bit is at least 2^-152, so a product of four has no bit below
+// 2^-608 and no term reaches 2^90; digit 0 weighs 2^-640 and 24 digits reach
+// 2^128.  A term outside that window (an input that breaks the range
+// precondition) is clamped into it: the evaluation then stays in bounds but
+// may give a wrong sign, as expansion arithmetic would after an underflow.
+constexpr int kAccBase = -640;
+constexpr int kAccDigits = 24;
+
+// Stage counters of the exact paths (optional): t points to a stripe array
+// of kTallyStripes lines of kTallyStride 64-bit words; the evaluation adds 1
+// to word kTally0 + stage of the line of its wave.
+enum ExactStage { kExOrient = 0, kExDot = 1, kExInB = 2, kExInC = 3, kExStages = 4 };
+constexpr int kTallyStride = 32;
+constexpr int kTallyStripes = 64;
+constexpr int kTally0 = 16;
+
+struct LongAcc {
+  int64_t d[kAccDigits];
+};
+
+GDP_HD void acc_clear(LongAcc &a) {
+  for (int i = 0; i < kAccDigits; i++) a.d[i] = 0;
+}
+
+// a += v exactly (v a normal double inside the window above).
+GDP_HD void acc_add(LongAcc &a, double v) {
+  if (v == 0.0) return;
+  uint64_t bits;
+  __builtin_memcpy(&bits, &v, sizeof bits);
+  const int be = (int)((bits >> 52) & 0x7ff);
+  const uint64_t mant = (bits & 0xfffffffffffffull) | (be ? (1ull << 52) : 0ull);
+  int sh = (be ? be : 1) - 1075 - kAccBase;  // weight of mant's lowest bit, above digit 0
+  if (sh < 0) sh = 0;
+  if (sh > 32 * (kAccDigits - 3) + 31) sh = 32 * (kAccDigits - 3) + 31;
+  const int k = sh >> 5, r = sh & 31;
+  const int64_t d0 = (int64_t)((mant << r) & 0xffffffffull);
+  const uint64_t rest = (mant >> 1) >> (31 - r);  // mant * 2^r / 2^32, rounded down
+  const int64_t d1 = (int64_t)(rest & 0xffffffffull), d2 = (int64_t)(rest >> 32);
+  if (bits >> 63) {
+    a.d[k] -= d0; a.d[k + 1] -= d1; a.d[k + 2] -= d2;
+  } else {
+    a.d[k] += d0; a.d[k + 1] += d1; a.d[k + 2] += d2;
   }
-  if (q != 0.0 || n == 0) h[n++] = q;
-  return n;
 }
 
-// h = h + f, in place (h holds hlen terms and has room for hlen + flen).
-GDP_HD int add_exp(int hlen, double *h, int flen, const double *f) {
-  for (int i = 0; i < flen; i++) hlen = grow_exp(hlen, h, f[i], h);
-  return hlen;
-}
-
-// h = e * b.  h must not alias e; room for 2 * elen.
-GDP_HD int scale_exp(int elen, const double *e, double b, double *h) {
-  double q, hh;
-  two_prod(e[0], b, q, hh);
-  int n = 0;
-  if (hh != 0.0) h[n++] = hh;
-  for (int i = 1; i < elen; i++) {
-    double p1, p0, s, t, u;
-    two_prod(e[i], b, p1, p0);
-    two_sum(q, p0, s, t);
-    if (t != 0.0) h[n++] = t;
-    two_sum(p1, s, q, u);
-    if (u != 0.0) h[n++] = u;
+// Sign of the accumulated value: one carry pass from the lowest digit, after
+// which value = carry * 2^(32 kAccDigits) + (nonnegative digits).
+GDP_HD int acc_sign(const LongAcc &a) {
+  int64_t carry = 0;
+  bool nz = false;
+  for (int i = 0; i < kAccDigits; i++) {
+    const int64_t v = a.d[i] + carry;
+    nz = nz || (v & 0xffffffffll) != 0;
+    carry = v >> 32;  // arithmetic shift: floor division by 2^32
   }
-  if (q != 0.0 || n == 0) h[n++] = q;
-  return n;
+  if (carry != 0) return carry > 0 ? 1 : -1;
+  return nz ? 1 : 0;
 }
 
-GDP_HD int exp_sign(int n, const double *e) {
-  for (int i = n - 1; i >= 0; i--) {
-    if (e[i] > 0.0) return 1;
-    if (e[i] < 0.0) return -1;
-  }
-  return 0;
+// a += s * x * y (two factors), exactly.
+GDP_HD void acc_prod2(LongAcc &a, double x, double y, bool neg) {
+  double h, l;
+  two_prod(x, y, h, l);
+  acc_add(a, neg ? -h : h);
+  acc_add(a, neg ? -l : l);
 }
 
-// e = a*b (2 terms) appended into h via grow; helper for sums of products.
-GDP_HD int add_prod(int hlen, double *h, double a, double b, bool negate) {
-  double x, y;
-  two_prod(a, b, x, y);
-  if (negate) { x = -x; y = -y; }
-  hlen = grow_exp(hlen, h, y, h);
-  hlen = grow_exp(hlen, h, x, h);
-  return hlen;
+// a += s * (x1 * x2) * (y1 * y2) (four factors), exactly: each pair is split
+// without error, then the four cross products are split again.
+GDP_HD void acc_prod4(LongAcc &a, double x1, double x2, double y1, double y2, bool neg) {
+  double xh, xl, yh, yl;
+  two_prod(x1, x2, xh, xl);
+  two_prod(y1, y2, yh, yl);
+  acc_prod2(a, xh, yh, neg);
+  acc_prod2(a, xh, yl, neg);
+  acc_prod2(a, xl, yh, neg);
+  acc_prod2(a, xl, yl, neg);
 }
 
-// raw orient2d expansion: px*qy - py*qx + qx*ry - qy*rx + rx*py - ry*px
-GDP_HD int orient_raw(double px, double py, double qx, double qy, double rx, double ry, double *h) {
-  int n = 1;
-  h[0] = 0.0;
-  n = add_prod(n, h, px, qy, false);
-  n = add_prod(n, h, py, qx, true);
-  n = add_prod(n, h, qx, ry, false);
-  n = add_prod(n, h, qy, rx, true);
-  n = add_prod(n, h, rx, py, false);
-  n = add_prod(n, h, ry, px, true);
-  return n;
-}
-
-// ---- exact slow paths (kept out of line on the device) ---------------------
 #ifdef __HIP_DEVICE_COMPILE__
 #define GDP_SLOW __device__ __noinline__
+GDP_HD void tally(uint64_t *t, int stage) {
+  if (!t) return;
+  const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  atomicAdd((unsigned long long *)(t + (wave & (kTallyStripes - 1)) * kTallyStride + kTally0 + stage), 1ull);
+}
 #else
 #define GDP_SLOW __host__ inline
+inline void tally(uint64_t *t, int stage) {
+  if (t) t[kTally0 + stage]++;
+}
 #endif
 
-GDP_SLOW int orient_exact(double ax, double ay, double bx, double by, double cx, double cy) {
-  double h[16];
-  int n = orient_raw(ax, ay, bx, by, cx, cy, h);
-  return exp_sign(n, h);
+// orient2d, exact: px*qy - py*qx + qx*ry - qy*rx + rx*py - ry*px
+GDP_SLOW int orient_exact(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t) {
+  tally(t, kExOrient);
+  LongAcc a;
+  acc_clear(a);
+  acc_prod2(a, ax, by, false);
+  acc_prod2(a, ay, bx, true);
+  acc_prod2(a, bx, cy, false);
+  acc_prod2(a, by, cx, true);
+  acc_prod2(a, cx, ay, false);
+  acc_prod2(a, cy, ax, true);
+  return acc_sign(a);
 }
 
-// (a-c).(b-c) sign, raw: ax*bx - ax*cx - cx*bx + cx*cx + ay*by - ay*cy - cy*by + cy*cy
-GDP_SLOW int dot_exact(double ax, double ay, double bx, double by, double cx, double cy) {
-  double h[24];
-  int n = 1;
-  h[0] = 0.0;
-  n = add_prod(n, h, ax, bx, false);
-  n = add_prod(n, h, ax, cx, true);
-  n = add_prod(n, h, cx, bx, true);
-  n = add_prod(n, h, cx, cx, false);
-  n = add_prod(n, h, ay, by, false);
-  n = add_prod(n, h, ay, cy, true);
-  n = add_prod(n, h, cy, by, true);
-  n = add_prod(n, h, cy, cy, false);
-  return exp_sign(n, h);
+// (a-c).(b-c), exact: ax*bx - ax*cx - cx*bx + cx*cx + ay*by - ay*cy - cy*by + cy*cy
+GDP_SLOW int dot_exact(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t) {
+  tally(t, kExDot);
+  LongAcc a;
+  acc_clear(a);
+  acc_prod2(a, ax, bx, false);
+  acc_prod2(a, ax, cx, true);
+  acc_prod2(a, cx, bx, true);
+  acc_prod2(a, cx, cx, false);
+  acc_prod2(a, ay, by, false);
+  acc_prod2(a, ay, cy, true);
+  acc_prod2(a, cy, by, true);
+  acc_prod2(a, cy, cy, false);
+  return acc_sign(a);
 }
 
-// lift(x,y) * o  where lift = x^2 + y^2 (4 terms) and o has olen terms;
-// accumulated into acc (negated if neg).
-GDP_HD int add_lift_times(int alen, double *acc, double x, double y, int olen, const double *o,
-                          bool neg, double *tmp) {
-  double l[8];
-  int ln = 1;
-  l[0] = 0.0;
-  ln = add_prod(ln, l, x, x, false);
-  ln = add_prod(ln, l, y, y, false);
-  for (int i = 0; i < ln; i++) {
-    double c = neg ? -l[i] : l[i];
-    if (c == 0.0) continue;
-    int sn = scale_exp(olen, o, c, tmp);
-    alen = add_exp(alen, acc, sn, tmp);
+// a += s * (px^2 + py^2) * orient(q, r, u), expanded into four-factor terms.
+GDP_HD void acc_lift_orient(LongAcc &a, double px, double py, double qx, double qy, double rx, double ry,
+                            double ux, double uy, bool neg) {
+  const double L[2] = {px, py};
+  for (int i = 0; i < 2; i++) {
+    const double l = L[i];
+    acc_prod4(a, l, l, qx, ry, neg);
+    acc_prod4(a, l, l, qy, rx, !neg);
+    acc_prod4(a, l, l, rx, uy, neg);
+    acc_prod4(a, l, l, ry, ux, !neg);
+    acc_prod4(a, l, l, ux, qy, neg);
+    acc_prod4(a, l, l, uy, qx, !neg);
   }
-  return alen;
 }
 
-// incircle, stage C: lifted 4x4 determinant in raw coordinates,
-//   +|a|^2 orient(b,c,d) - |b|^2 orient(a,c,d) + |c|^2 orient(a,b,d) - |d|^2 orient(a,b,c)
+// incircle, stage C: the lifted 4x4 determinant in raw coordinates,
+//   |a|^2 orient(b,c,d) - |b|^2 orient(a,c,d) + |c|^2 orient(a,b,d) - |d|^2 orient(a,b,c)
 GDP_SLOW int incircle_exact_raw(double ax, double ay, double bx, double by, double cx, double cy,
-                                double dx, double dy) {
-  double acc[544];  // <= 1 + 4 lifts * 5 terms * 26
-  double o[16];
-  double tmp[40];
-  int alen = 1;
-  acc[0] = 0.0;
-  int on = orient_raw(bx, by, cx, cy, dx, dy, o);
-  alen = add_lift_times(alen, acc, ax, ay, on, o, false, tmp);
-  on = orient_raw(ax, ay, cx, cy, dx, dy, o);
-  alen = add_lift_times(alen, acc, bx, by, on, o, true, tmp);
-  on = orient_raw(ax, ay, bx, by, dx, dy, o);
-  alen = add_lift_times(alen, acc, cx, cy, on, o, false, tmp);
-  on = orient_raw(ax, ay, bx, by, cx, cy, o);
-  alen = add_lift_times(alen, acc, dx, dy, on, o, true, tmp);
-  return exp_sign(alen, acc);
+                                double dx, double dy, uint64_t *t) {
+  tally(t, kExInC);
+  LongAcc a;
+  acc_clear(a);
+  acc_lift_orient(a, ax, ay, bx, by, cx, cy, dx, dy, false);
+  acc_lift_orient(a, bx, by, ax, ay, cx, cy, dx, dy, true);
+  acc_lift_orient(a, cx, cy, ax, ay, bx, by, dx, dy, false);
+  acc_lift_orient(a, dx, dy, ax, ay, bx, by, cx, cy, true);
+  return acc_sign(a);
 }
 
 // incircle, stage B: all six differences are exact doubles.
 //   alift*(bdx*cdy - cdx*bdy) + blift*(cdx*ady - adx*cdy) + clift*(adx*bdy - bdx*ady)
 GDP_SLOW int incircle_exact_diff(double adx, double ady, double bdx, double bdy, double cdx,
-                                 double cdy) {
-  double acc[160];  // <= 1 + 3 lifts * 5 terms * 10
-  double m[8];
-  double tmp[24];
-  int alen = 1;
-  acc[0] = 0.0;
+                                 double cdy, uint64_t *t) {
+  tally(t, kExInB);
+  LongAcc a;
+  acc_clear(a);
   const double X[3] = {adx, bdx, cdx}, Y[3] = {ady, bdy, cdy};
   for (int r = 0; r < 3; r++) {
-    int i = (r + 1) % 3, j = (r + 2) % 3;
-    int mn = 1;
-    m[0] = 0.0;
-    mn = add_prod(mn, m, X[i], Y[j], false);
-    mn = add_prod(mn, m, X[j], Y[i], true);
-    alen = add_lift_times(alen, acc, X[r], Y[r], mn, m, false, tmp);
+    const int i = (r + 1) % 3, j = (r + 2) % 3;
+    acc_prod4(a, X[r], X[r], X[i], Y[j], false);
+    acc_prod4(a, X[r], X[r], X[j], Y[i], true);
+    acc_prod4(a, Y[r], Y[r], X[i], Y[j], false);
+    acc_prod4(a, Y[r], Y[r], X[j], Y[i], true);
   }
-  return exp_sign(alen, acc);
+  return acc_sign(a);
 }
 
 // ---- public predicates -------------------------------------------------------
 // orient2d > 0 iff a, b, c are in counter-clockwise order.
-GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, double cy) {
+GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
   double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
   double l = acx * bcy, r = acy * bcx;
   double det = l - r;
@@ -215,12 +239,12 @@ GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, doubl
     if (det > bound) return 1;
     if (-det > bound) return -1;
   }
-  return orient_exact(ax, ay, bx, by, cx, cy);
+  return orient_exact(ax, ay, bx, by, cx, cy, t);
 }
 
 // incircle > 0 iff d lies strictly inside the circle through CCW a, b, c.
 GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, double cy, double dx,
-                    double dy) {
+                    double dy, uint64_t *tl = nullptr) {
   double adx = ax - dx, ady = ay - dy, bdx = bx - dx, bdy = by - dy, cdx = cx - dx, cdy = cy - dy;
   double bc1 = bdx * cdy, bc2 = cdx * bdy;
   double ca1 = cdx * ady, ca2 = adx * cdy;
@@ -244,12 +268,12 @@ GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, doubl
   two_sum(by, -dy, s, t); exact &= (t == 0.0);
   two_sum(cx, -dx, s, t); exact &= (t == 0.0);
   two_sum(cy, -dy, s, t); exact &= (t == 0.0);
-  if (exact) return incircle_exact_diff(adx, ady, bdx, bdy, cdx, cdy);
-  return incircle_exact_raw(ax, ay, bx, by, cx, cy, dx, dy);
+  if (exact) return incircle_exact_diff(adx, ady, bdx, bdy, cdx, cdy, tl);
+  return incircle_exact_raw(ax, ay, bx, by, cx, cy, dx, dy, tl);
 }
 
 // indiametral > 0 iff c lies strictly inside the circle with diameter ab.
-GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, double cy) {
+GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
   double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
   double l = acx * bcx, r = acy * bcy;
   double dot = l + r;
@@ -259,7 +283,26 @@ GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, do
     if (dot > bound) return -1;
     if (-dot > bound) return 1;
   }
-  return -dot_exact(ax, ay, bx, by, cx, cy);
+  return -dot_exact(ax, ay, bx, by, cx, cy, t);
+}
+
+// Encroachment of subsegment ab by p (Section 4.1): strictly inside the
+// diametric circle (mode 0, exact), or strictly inside the diametric lens
+// (mode 1): the points that see ab under more than 120 degrees, bounded by
+// two circular arcs through a and b meeting ab at 60 degrees.  The lens lies
+// in the circle; after the exact circle test the angle is tested by the FP64
+// formula (a-p).(b-p) < 0 and 4 ((a-p).(b-p))^2 > |a-p|^2 |b-p|^2 in this
+// operation order.
+GDP_HD bool encroaches(int mode, double ax, double ay, double bx, double by, double px, double py,
+                       uint64_t *t = nullptr) {
+  if (indiametral(ax, ay, bx, by, px, py, t) <= 0) return false;
+  if (mode == 0) return true;
+  const double dax = ax - px, day = ay - py;
+  const double dbx = bx - px, dby = by - py;
+  const double dot = dax * dbx + day * dby;
+  const double la = dax * dax + day * day;
+  const double lb = dbx * dbx + dby * dby;
+  return (dot * dot) * 4.0 > la * lb;
 }
 
 }  // namespace gdp

@@ -79,9 +79,19 @@ struct DevCounters {
   int32_t abort;        // the round was abandoned before any mesh write (capacity)
   int32_t nmk0;         // midpoint candidates after the collection (R4/R5 add more)
   int32_t fan_total;    // total of the fresh-count scan (fbase[nwin] is what is used)
-  int32_t pad0;
+  int32_t nhuge;        // cavities continued in device memory (beyond the LDS list)
   int64_t cav_len[2];   // per-thread cavities [midpoints, circumcenters]: triangles grown
   int64_t cav_bnd[2];   // ... and their boundary edges
+  int64_t n_in_tests;   // incircle evaluations of cavity growth and the dependency test
+  int64_t n_or_tests;   // orient2d evaluations of the walk and the fan check
+  int64_t n_exact[4];   // exact-stage evaluations (ExactStage: orient, dot, incircle B, incircle C)
+  // winners of the round (what a sequential insertion of the same points touches)
+  int64_t win_cav;      // sum of cavity sizes |C|
+  int64_t win_bnd;      // sum of boundary (fan) edges b
+  int64_t win_steps;    // walk steps of the circumcenter winners
+  int64_t win_cc_cav;   // |C| and b of the circumcenter winners alone
+  int64_t win_cc_bnd;
+  int64_t n_marks[2];   // priority marks placed (atomicMax): midpoint, circumcenter cavities
 };
 static_assert(sizeof(DevCounters) % 8 == 0, "DevCounters is copied as 32-bit words");
 static_assert(offsetof(DevCounters, nmk) == 128, "the midpoint append counter starts the second line");
@@ -89,15 +99,21 @@ static_assert(offsetof(DevCounters, nmk) == 128, "the midpoint append counter st
 // Statistics of a round, summed per wave into one of kStatStripes lines (the
 // wave's global index picks the line) and folded into DevCounters at the end
 // of the round, which also clears the lines.
+// The exact predicates count their slow-path evaluations into words
+// kTally0.. of the same lines (gdp_exact.h).
 enum StatField {
   kStCavTri, kStCavLen0, kStCavLen1, kStCavBnd0, kStCavBnd1, kStEncReject, kStFanInvalid, kStUnsplittable,
-  kStMidCand, kStLostMark, kStDepDrop, kStBlocked, kStCoincident, kStCavMax, kStFields
+  kStMidCand, kStLostMark, kStDepDrop, kStBlocked, kStCoincident, kStCavMax, kStInTests, kStOrTests,
+  kStExact0, kStExact3 = kStExact0 + 3,
+  kStWinCav, kStWinBnd, kStWinSteps, kStWinCcCav, kStWinCcBnd, kStMarks0, kStMarks1, kStFields
 };
 struct StatLine {
-  uint64_t v[16];
+  uint64_t v[32];
 };
-static_assert(kStFields <= 16 && sizeof(StatLine) == 128, "one stat line per cache line");
 constexpr int kStatStripes = 64;
+static_assert(kStFields <= 32 && sizeof(StatLine) == 256, "one stat line: two cache lines");
+static_assert(kStExact0 == kTally0 && kTallyStride == 32 && kTallyStripes == kStatStripes,
+              "the exact predicates' counters live in the stat lines");
 
 // Mesh counts and round control in device memory, so that several rounds
 // can be queued without the host looking at any count in between.
@@ -123,6 +139,7 @@ constexpr int kHaltStall = 5;  // candidates but no winner
 constexpr int kErrWalk = 1;
 constexpr int kErrCavity = 2;
 constexpr int kErrPool = 4;
+constexpr int kErrHuge = 16;  // a cavity outgrew the LDS list in a round run without the device-memory path
 constexpr int kErrInput = 8;
 
 // Candidate state bits.
@@ -132,6 +149,7 @@ constexpr int kStW0 = 4;        // holds every mark of its cavity
 constexpr int kStWin = 8;       // survives the dependency test
 constexpr int kStBig = 16;      // cavity goes to the cooperative path
 constexpr int kStDone = 32;     // cavity step finished (alive or dropped)
+constexpr int kStHuge = 128;    // cavity continues in device memory (beyond the LDS list)
 
 struct CandSet {
   int32_t *elem;     // triangle slot (circumcenters) or subsegment id (midpoints)

@@ -36,6 +36,10 @@ struct Work {
   int32_t fan_cap;
   int32_t *big;
   int32_t big_cap;
+  int32_t *hvis;       // [hcap] visited flags of the device-memory cavity path (zero between uses)
+  int32_t *hlist;      // [hcap] its cavity list (from the bottom) and rejected slots (from the top)
+  int32_t hcap;        // >= capT
+  int32_t huge_ok;     // 1: cavities beyond the LDS list continue in device memory this round
   // previous round's lists (incremental collection) and slot stamps
   int32_t *prev_cc_elem;
   uint64_t *prev_cc_key;
@@ -47,6 +51,7 @@ struct Work {
   uint64_t *keys;      // [capT+capS] scratch for the candidate cap
   int32_t *rhist;      // [256] digit histogram of the radix select (zero between uses)
   StatLine *stat;      // [kStatStripes] statistics of the running round
+  uint64_t *tally;     // = stat as 64-bit words: exact-stage counters of the predicates
   double L2;           // edge-length bound l^2 (0: off)
   int32_t enc_mode;    // 0: diametric circle, 1: diametric lens
   int32_t split_mode;  // 0: midpoints, 1: concentric shells
@@ -80,6 +85,7 @@ constexpr int kApproxMaxN = 16;
 template <int IS_CC>
 __global__ void k_cavity(DevMesh m, Work w);
 __global__ void k_cavity_big(DevMesh m, Work w, int phase);
+__global__ void k_cavity_huge(DevMesh m, Work w, int phase);
 __global__ void k_own(Work w);
 __global__ void k_dep(DevMesh m, Work w);
 __global__ void k_scan_tiles(ScanJob a, ScanJob b, const int32_t *halt);
@@ -95,6 +101,13 @@ __global__ void k_quality(DevMesh m, double B2, double L2, unsigned long long *n
 __global__ void k_quality_sum(int n_part, const unsigned long long *n_in, const double *a_in,
                               unsigned long long *n_out, double *a_out);
 
+// The exact predicates on a list of queries (kind 0 orient2d, 1 incircle,
+// 2 indiametral, 3 lens encroachment; 6 or 8 doubles per query).
+__global__ void k_predicates(int kind, int n, const double *pts, int32_t *out, uint64_t *tally);
+
+// Random-slot 64-bit atomicMax throughput (the marks' access pattern).
+__global__ void k_atomic_max_bench(uint64_t *table, uint64_t n_slots, int64_t n_ops, uint64_t seed);
+
 // One mesh of the single-workgroup engine.
 struct EngDesc {
   DevMesh m;
@@ -107,6 +120,7 @@ __global__ void k_engine(const EngDesc *descs, int n_mesh, int32_t *head, int ro
 
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;
+constexpr int kHugeBlock = 1024;
 constexpr int kScanTileSize = 256 * 8;
 
 }  // namespace gdp

@@ -161,22 +161,9 @@ __device__ __forceinline__ int wave_alloc(int *counter, int n) {
   return base + x - n;
 }
 
-// Encroachment of subsegment ab by p (Section 4.1): strictly inside the
-// diametric circle (exact), or, in lens mode, strictly inside the diametric
-// lens: the points that see ab under more than 120 degrees, bounded by two
-// circular arcs through a and b meeting ab at 60 degrees.  The lens lies in
-// the circle; after the exact circle test the angle is tested by the FP64
-// formula (a-p).(b-p) < 0 and 4 ((a-p).(b-p))^2 > |a-p|^2 |b-p|^2 in this
-// operation order.
+// Encroachment of subsegment ab by p under the round's mode (circle or lens).
 __device__ __forceinline__ bool encroached(const Work &w, double2 a, double2 b, double2 p) {
-  if (indiametral(a.x, a.y, b.x, b.y, p.x, p.y) <= 0) return false;
-  if (w.enc_mode == 0) return true;
-  const double dax = a.x - p.x, day = a.y - p.y;
-  const double dbx = b.x - p.x, dby = b.y - p.y;
-  const double dot = dax * dbx + day * dby;
-  const double la = dax * dax + day * day;
-  const double lb = dbx * dbx + dby * dby;
-  return (dot * dot) * 4.0 > la * lb;
+  return encroaches(w.enc_mode, a.x, a.y, b.x, b.y, p.x, p.y, w.tally);
 }
 
 // Entry idx of the midpoint list: subsegment k.
@@ -222,13 +209,13 @@ __device__ __forceinline__ int bit_rank(const uint32_t *bm, const int32_t *words
 // Exclusive prefix of the fresh-slot counts at winner r.
 __device__ __forceinline__ int fbase_at(const Work &w, int r) { return w.fbase[r] + w.tiles_f[r / kScanTileSize]; }
 
-__device__ __forceinline__ int orient_pts(double2 a, double2 b, double2 c) {
-  return orient2d(a.x, a.y, b.x, b.y, c.x, c.y);
+__device__ __forceinline__ int orient_pts(const Work &w, double2 a, double2 b, double2 c) {
+  return orient2d(a.x, a.y, b.x, b.y, c.x, c.y, w.tally);
 }
 
-__device__ __forceinline__ int incircle_tri(const DevMesh &m, int4 tri, double2 p) {
+__device__ __forceinline__ int incircle_tri(const DevMesh &m, const Work &w, int4 tri, double2 p) {
   double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
-  return incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y);
+  return incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y, w.tally);
 }
 
 __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int v) {
@@ -587,11 +574,15 @@ __global__ void k_apply_cap(Work w) {
 // by subsegments turns into the midpoint candidate of the first one.
 // ---------------------------------------------------------------------------
 // Returns 1 for a coincident point, 2 for a walk blocked by a subsegment.
-__device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c, int nS) {
+// The walk length is kept in bits 16-30 of the state of a located point (at
+// most 0x7fff) and added to *nsteps.
+constexpr int kStepShift = 16;
+__device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c, int nS, int &nsteps) {
   if (w.cc.state[c] & kStSkip) return 0;
   int cur = w.cc.elem[c];
   double2 p = w.cc.p[c];
   for (int steps = 1;; steps++) {
+    nsteps++;
     if (steps > (1 << 20)) {
       atomicOr(&w.cnt->err, kErrWalk);
       w.cc.state[c] = kStDone;
@@ -601,7 +592,7 @@ __device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c
     int4 tri = m.tv[cur];
     const int4 nb = m.tn[cur];
     double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
-    int s0 = orient_pts(A, B, p), s1 = orient_pts(B, C, p), s2 = orient_pts(C, A, p);
+    int s0 = orient_pts(w, A, B, p), s1 = orient_pts(w, B, C, p), s2 = orient_pts(w, C, A, p);
     if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
       int nz = (s0 == 0) + (s1 == 0) + (s2 == 0);
       if (nz >= 2) {
@@ -609,7 +600,7 @@ __device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c
         return 1;
       }
       w.cc.loc[c] = cur;
-      w.cc.state[c] = kStFound;
+      w.cc.state[c] = kStFound | (min(steps, 0x7fff) << kStepShift);
       return 0;
     }
     int s[3] = {s0, s1, s2};
@@ -637,17 +628,18 @@ __device__ __forceinline__ int locate_one(const DevMesh &m, const Work &w, int c
 
 __device__ __forceinline__ void locate_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, nS = w.st->nS;
-  int n_coin = 0, n_blk = 0;
+  int n_coin = 0, n_blk = 0, n_steps = 0;
   for (int base = L.base0; base < ncc; base += L.stride) {
     int c = base + threadIdx.x;
     if (c < ncc) {
-      const int r = locate_one(m, w, c, nS);
+      const int r = locate_one(m, w, c, nS, n_steps);
       n_coin += r == 1;
       n_blk += r == 2;
     }
   }
   stat_add(w, kStCoincident, n_coin);
   stat_add(w, kStBlocked, n_blk);
+  stat_add(w, kStOrTests, 3 * (uint64_t)n_steps);
 }
 
 __global__ void k_locate(DevMesh m, Work w) {
@@ -704,7 +696,7 @@ __device__ __forceinline__ void prefilter_one(const DevMesh &m, const Work &w, i
       for (int q = 0; q < len; q++)
         if (lds[q * ls + tid] == o) { in = true; break; }
       if (in) continue;
-      if (incircle_tri(m, m.tv[o], p) > 0) lds[(len++) * ls + tid] = o;
+      if (incircle_tri(m, w, m.tv[o], p) > 0) lds[(len++) * ls + tid] = o;
     }
   }
   if (mode == 3) {
@@ -745,6 +737,7 @@ struct CavCheck {
   int nbnd;
   bool fan_bad;
   bool enc;
+  int ntest;  // incircle evaluations
 };
 
 // per-thread cavity capacity of the grid kernel: 39 slots x 128 threads (plus
@@ -769,7 +762,7 @@ constexpr int kCavBlock = kCavBlockSize;
 __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
                                           const int *seeds, int nseeds, double2 p, int skip_k, bool is_cc,
                                           CavCheck &ck) {
-  ck = CavCheck{0, false, false};
+  ck = CavCheck{0, false, false, 0};
   int len = 0;
   for (int s = 0; s < nseeds; s++) {
     bool dup = false;
@@ -828,7 +821,8 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32
         const double2 A = to[e].x == fv[e] ? F[e] : (to[e].x == u ? Pu : Pv);
         const double2 B = to[e].y == fv[e] ? F[e] : (to[e].y == u ? Pu : Pv);
         const double2 C = to[e].z == fv[e] ? F[e] : (to[e].z == u ? Pu : Pv);
-        if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y) > 0) {
+        ck.ntest++;
+        if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y, w.tally) > 0) {
           if (len == cap) return -1;
           lds[(len++) * ls + tid] = o[e];
           continue;
@@ -842,7 +836,7 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32
         flag_mid(w, sid);
         ck.enc = true;
       }
-      if (orient_pts(Pu, Pv, p) <= 0) ck.fan_bad = true;
+      if (orient_pts(w, Pu, Pv, p) <= 0) ck.fan_bad = true;
     }
   }
   // insertion sort (ascending slots)
@@ -865,11 +859,12 @@ struct CavRes {
   int bnd;        // its boundary edges
   int alive;
   int enc_reject, fan_invalid, unsplittable, mid_cand;
+  int ntest;      // incircle evaluations made while growing
 };
 
 __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
                                              int ci, int is_cc) {
-  CavRes res{0, 0, 0, 0, 0, 0, 0};
+  CavRes res{0, 0, 0, 0, 0, 0, 0, 0};
   CandSet S = is_cc ? w.cc : w.mid;
   int st = S.state[ci];
   if (st & (kStDone | kStSkip | kStBig)) return res;
@@ -902,6 +897,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
   }
   CavCheck ck;
   int len = grow_local(m, w, lds, ls, cap, tid, seeds, nseeds, p, skip_k, is_cc != 0, ck);
+  res.ntest = ck.ntest;
   if (len < 0) {
     S.state[ci] = st | kStBig | kStFound;
     int q = atomicAdd(&w.cnt->nbig, 1);
@@ -938,7 +934,7 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
   CandSet S = is_cc ? w.cc : w.mid;
   for (int base = lo + L.base0; base < n; base += L.stride) {
     int ci = base + tid;
-    CavRes r{0, 0, 0, 0, 0, 0, 0};
+    CavRes r{0, 0, 0, 0, 0, 0, 0, 0};
     if (ci < n) r = cavity_one(m, w, lds, ls, cap, tid, ci, is_cc);
     int off = group_alloc(&w.cnt->pool_used, r.alive ? r.len : 0, L);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
@@ -969,6 +965,8 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
     stat_add(w, kStFanInvalid, r.fan_invalid);
     stat_add(w, kStUnsplittable, r.unsplittable);
     stat_add(w, kStMidCand, r.mid_cand);
+    stat_add(w, kStInTests, r.ntest);
+    stat_add(w, is_cc ? kStMarks1 : kStMarks0, (r.alive && counted) ? r.len : 0);
   }
 }
 
@@ -1005,89 +1003,52 @@ __device__ __forceinline__ int hash_insert(int32_t *hs, int v, int *ovf) {
 struct BigShared {
   int32_t cav[kBigMax];
   int32_t hs[kHash];
-  int s_n, s_head, s_ovf, s_nbnd, s_fanbad, s_enc, s_off;
+  int s_n, s_head, s_ovf, s_nbnd, s_fanbad, s_enc, s_off, s_r;
 };
 
-// Grows queue entry b (uniform over the workgroup).
-__device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
-  int32_t *cav = sh.cav;
-  int32_t *hs = sh.hs;
-  int &s_n = sh.s_n, &s_head = sh.s_head, &s_ovf = sh.s_ovf, &s_nbnd = sh.s_nbnd, &s_fanbad = sh.s_fanbad,
-      &s_enc = sh.s_enc, &s_off = sh.s_off;
-  int tid = threadIdx.x;
-  int ref = w.big[b];
-  int is_cc = (ref & 0x80000000) ? 0 : 1;
-  int ci = ref & 0x7fffffff;
-  CandSet S = is_cc ? w.cc : w.mid;
-  if (!(S.state[ci] & kStBig) || (S.state[ci] & kStDone)) return;
-  double2 p = S.p[ci];
-  int skip_k = is_cc ? -1 : S.elem[ci];
-  for (int i = tid; i < kHash; i += blockDim.x) hs[i] = -1;
-  __syncthreads();
-  int expect = 2;
-  if (tid == 0) {
-    s_n = 0; s_head = 0; s_ovf = 0; s_nbnd = 0; s_fanbad = 0; s_enc = 0;
-    if (is_cc) {
-      int t = S.loc[ci];
-      hash_insert(hs, t, &s_ovf);
-      cav[s_n++] = t;
-    } else {
-      int a0 = w.sadj[2 * skip_k], a1 = w.sadj[2 * skip_k + 1];
-      if (a0 >= 0 && hash_insert(hs, a0 >> 2, &s_ovf)) cav[s_n++] = a0 >> 2;
-      if (a1 >= 0 && hash_insert(hs, a1 >> 2, &s_ovf)) cav[s_n++] = a1 >> 2;
-    }
-  }
-  if (!is_cc) expect = (w.sadj[2 * skip_k] >= 0 && w.sadj[2 * skip_k + 1] >= 0) ? 2 : 1;
-  __syncthreads();
-  for (;;) {
-    int lo = s_head, hi = s_n < kBigMax ? s_n : kBigMax;
-    int ovf = s_ovf;
-    __syncthreads();
-    if (lo >= hi || ovf) break;
-    if (tid == 0) s_head = hi;
-    for (int idx = lo + tid; idx < hi; idx += blockDim.x) {
-      int t = cav[idx];
-      int4 tri = m.tv[t];
-      int4 nb = m.tn[t];
-      for (int e = 0; e < 3; e++) {
-        if ((tri.w >> e) & 1) continue;
-        int o = comp(nb, e);
-        if (o < 0) continue;
-        if (!hash_insert(hs, o, &s_ovf)) continue;
-        if (incircle_tri(m, m.tv[o], p) > 0) {
-          int pos = atomicAdd(&s_n, 1);
-          if (pos < kBigMax) cav[pos] = o;
-          else s_ovf = 1;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (s_ovf) {
-    if (tid == 0) {
-      atomicOr(&w.cnt->err, kErrCavity);
-      S.state[ci] |= kStDone;
-    }
-    return;
-  }
-  int len = s_n;
+// Ascending sort of a[0..n) by one workgroup: the bitonic network in its
+// all-ascending form (each block of size k first compares mirrored pairs,
+// then half-cleaners of strides k/4 .. 1; every compare-exchange puts the
+// smaller value at the lower index).  Entries beyond n act as +infinity and
+// are never touched, so no padding is stored.
+__device__ __forceinline__ void block_sort_asc(int32_t *a, int n) {
   int P = 1;
-  while (P < len) P <<= 1;
-  for (int i = len + tid; i < P; i += blockDim.x) cav[i] = 0x7fffffff;
-  for (int size = 2; size <= P; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+  while (P < n) P <<= 1;
+  const int half = P >> 1;
+  for (int k = 2; k <= P; k <<= 1) {
+    const int hk = k >> 1;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < half; idx += blockDim.x) {
+      const int blk = idx / hk, o = idx - blk * hk;
+      const int i = blk * k + o, l = blk * k + (k - 1 - o);
+      if (l < n) {
+        const int x = a[i], y = a[l];
+        if (x > y) { a[i] = y; a[l] = x; }
+      }
+    }
+    for (int j = k >> 2; j > 0; j >>= 1) {
       __syncthreads();
-      for (int i = tid; i < P; i += blockDim.x) {
-        int j = i ^ stride;
-        if (j > i) {
-          bool up = (i & size) == 0;
-          int x = cav[i], y = cav[j];
-          if ((x > y) == up) { cav[i] = y; cav[j] = x; }
+      for (int idx = threadIdx.x; idx < half; idx += blockDim.x) {
+        const int i = (idx / j) * 2 * j + idx % j, l = i + j;
+        if (l < n) {
+          const int x = a[i], y = a[l];
+          if (x > y) { a[i] = y; a[l] = x; }
         }
       }
     }
+  }
   __syncthreads();
-  // boundary checks, in parallel over cavity triangles
+}
+
+// The rest of a cooperative cavity once its slots are known (cav[0..len),
+// any order; LDS or device memory): sort, boundary checks in parallel over
+// the cavity triangles, then drop it or take pool space and place its
+// marks.  Uniform over the workgroup; the shared scalars are reset here.
+__device__ __forceinline__ void coop_finish(const DevMesh &m, const Work &w, BigShared &sh, CandSet S, int ci,
+                                            int is_cc, int skip_k, int expect, double2 p, int32_t *cav, int len) {
+  const int tid = threadIdx.x;
+  if (tid == 0) { sh.s_nbnd = 0; sh.s_fanbad = 0; sh.s_enc = 0; sh.s_off = -1; }
+  block_sort_asc(cav, len);
   for (int j = tid; j < len; j += blockDim.x) {
     int t = cav[j];
     int4 tri = m.tv[t];
@@ -1098,36 +1059,36 @@ __device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShar
       if (skip_k >= 0 && sid == skip_k) continue;
       int o = comp(nb, e);
       if (sid < 0 && o >= 0 && in_sorted(cav, len, o)) continue;
-      atomicAdd(&s_nbnd, 1);
+      atomicAdd(&sh.s_nbnd, 1);
       double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
       if (is_cc && sid >= 0 && encroached(w, U, V, p)) {
         flag_mid(w, sid);
-        s_enc = 1;
+        sh.s_enc = 1;
       }
-      if (orient_pts(U, V, p) <= 0) s_fanbad = 1;
+      if (orient_pts(w, U, V, p) <= 0) sh.s_fanbad = 1;
     }
   }
   __syncthreads();
   if (tid == 0) {
-    s_off = -1;
-    bool drop = (is_cc && s_enc) || s_fanbad || s_nbnd - len != expect;
+    atomicAdd((unsigned long long *)&stat_line(w)->v[kStOrTests], (unsigned long long)sh.s_nbnd);
+    bool drop = (is_cc && sh.s_enc) || sh.s_fanbad || sh.s_nbnd - len != expect;
     if (drop) {
       atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
       atomicMax(&w.cnt->cav_max, len);
-      atomicAdd((is_cc && s_enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
+      atomicAdd((is_cc && sh.s_enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
       S.state[ci] |= kStDone;
     } else {
       int off = atomicAdd(&w.cnt->pool_used, len);
       if (off + len > w.pool_cap) atomicOr(&w.cnt->err, kErrPool);
       else {
-        s_off = off;
+        sh.s_off = off;
         atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
         atomicMax(&w.cnt->cav_max, len);
       }
     }
   }
   __syncthreads();
-  int off = s_off;
+  int off = sh.s_off;
   if (off >= 0) {
     uint64_t key = S.key[ci];
     for (int j = tid; j < len; j += blockDim.x) {
@@ -1135,11 +1096,156 @@ __device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShar
       atomicMax((unsigned long long *)&w.mark[cav[j]], (unsigned long long)key);
     }
     if (tid == 0) {
+      atomicAdd((unsigned long long *)&stat_line(w)->v[is_cc ? kStMarks1 : kStMarks0], (unsigned long long)len);
       S.off[ci] = off;
       S.len[ci] = len;
       S.state[ci] |= kStDone | kStAlive;
     }
   }
+  __syncthreads();
+}
+
+// Candidate of queue entry b and its growth parameters.
+struct CoopCand {
+  CandSet S;
+  int ci, is_cc, skip_k, expect;
+  double2 p;
+};
+__device__ __forceinline__ CoopCand coop_cand(const Work &w, int b) {
+  CoopCand c;
+  const int ref = w.big[b];
+  c.is_cc = (ref & 0x80000000) ? 0 : 1;
+  c.ci = ref & 0x7fffffff;
+  c.S = c.is_cc ? w.cc : w.mid;
+  c.p = c.S.p[c.ci];
+  c.skip_k = c.is_cc ? -1 : c.S.elem[c.ci];
+  c.expect = c.is_cc ? 2 : ((w.sadj[2 * c.skip_k] >= 0 && w.sadj[2 * c.skip_k + 1] >= 0) ? 2 : 1);
+  return c;
+}
+
+// Grows queue entry b (uniform over the workgroup) in LDS: the tuple-
+// parallel ExpandList of Section 5.3 (Algorithm 3): the frontier of
+// <point, triangle> tuples is expanded in parallel and new tuples are
+// reserved with an atomic counter.  A cavity beyond the LDS list (kBigMax
+// triangles) continues in device memory (huge_one); when the round was
+// started without that path, the round is abandoned and run again with it.
+__device__ __forceinline__ void big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
+  int32_t *cav = sh.cav;
+  int32_t *hs = sh.hs;
+  int tid = threadIdx.x;
+  const int ci0 = w.big[b] & 0x7fffffff;
+  const CandSet S0 = (w.big[b] & 0x80000000) ? w.mid : w.cc;
+  if (!(S0.state[ci0] & kStBig) || (S0.state[ci0] & (kStDone | kStHuge))) return;
+  const CoopCand c = coop_cand(w, b);
+  for (int i = tid; i < kHash; i += blockDim.x) hs[i] = -1;
+  __syncthreads();
+  if (tid == 0) {
+    sh.s_n = 0; sh.s_head = 0; sh.s_ovf = 0;
+    if (c.is_cc) {
+      int t = c.S.loc[c.ci];
+      hash_insert(hs, t, &sh.s_ovf);
+      cav[sh.s_n++] = t;
+    } else {
+      int a0 = w.sadj[2 * c.skip_k], a1 = w.sadj[2 * c.skip_k + 1];
+      if (a0 >= 0 && hash_insert(hs, a0 >> 2, &sh.s_ovf)) cav[sh.s_n++] = a0 >> 2;
+      if (a1 >= 0 && hash_insert(hs, a1 >> 2, &sh.s_ovf)) cav[sh.s_n++] = a1 >> 2;
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    int lo = sh.s_head, hi = sh.s_n < kBigMax ? sh.s_n : kBigMax;
+    int ovf = sh.s_ovf;
+    __syncthreads();
+    if (lo >= hi || ovf) break;
+    if (tid == 0) sh.s_head = hi;
+    for (int idx = lo + tid; idx < hi; idx += blockDim.x) {
+      int t = cav[idx];
+      int4 tri = m.tv[t];
+      int4 nb = m.tn[t];
+      for (int e = 0; e < 3; e++) {
+        if ((tri.w >> e) & 1) continue;
+        int o = comp(nb, e);
+        if (o < 0) continue;
+        if (!hash_insert(hs, o, &sh.s_ovf)) continue;
+        atomicAdd((unsigned long long *)&stat_line(w)->v[kStInTests], 1ull);
+        if (incircle_tri(m, w, m.tv[o], c.p) > 0) {
+          int pos = atomicAdd(&sh.s_n, 1);
+          if (pos < kBigMax) cav[pos] = o;
+          else sh.s_ovf = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (sh.s_ovf) {
+    if (tid == 0) {
+      if (w.huge_ok) {
+        c.S.state[c.ci] |= kStHuge;
+        atomicAdd(&w.cnt->nhuge, 1);
+      } else {
+        atomicOr(&w.cnt->err, kErrHuge);
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  coop_finish(m, w, sh, c.S, c.ci, c.is_cc, c.skip_k, c.expect, c.p, cav, sh.s_n);
+}
+
+// A cavity beyond the LDS list, grown by one workgroup in device memory
+// with no ceiling (the mesh's triangle count bounds it): the frontier and
+// the cavity list live in w.hlist (accepted slots from the bottom, slots
+// that failed the circle test from the top; every slot enters at most
+// once), visited slots are flagged in w.hvis and cleared again at the end.
+// Only one workgroup of a mesh runs this at a time (the flags are shared).
+__device__ __noinline__ void huge_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
+  const int tid = threadIdx.x;
+  const int ci0 = w.big[b] & 0x7fffffff;
+  const CandSet S0 = (w.big[b] & 0x80000000) ? w.mid : w.cc;
+  if (!(S0.state[ci0] & kStHuge) || (S0.state[ci0] & kStDone)) return;
+  const CoopCand c = coop_cand(w, b);
+  int32_t *list = w.hlist;
+  const int top = w.hcap - 1;
+  if (tid == 0) {
+    sh.s_n = 0; sh.s_head = 0; sh.s_r = 0;
+    if (c.is_cc) {
+      int t = c.S.loc[c.ci];
+      w.hvis[t] = 1;
+      list[sh.s_n++] = t;
+    } else {
+      int a0 = w.sadj[2 * c.skip_k], a1 = w.sadj[2 * c.skip_k + 1];
+      if (a0 >= 0 && atomicExch(&w.hvis[a0 >> 2], 1) == 0) list[sh.s_n++] = a0 >> 2;
+      if (a1 >= 0 && atomicExch(&w.hvis[a1 >> 2], 1) == 0) list[sh.s_n++] = a1 >> 2;
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    int lo = sh.s_head, hi = sh.s_n;
+    __syncthreads();
+    if (lo >= hi) break;
+    if (tid == 0) sh.s_head = hi;
+    for (int idx = lo + tid; idx < hi; idx += blockDim.x) {
+      int t = list[idx];
+      int4 tri = m.tv[t];
+      int4 nb = m.tn[t];
+      for (int e = 0; e < 3; e++) {
+        if ((tri.w >> e) & 1) continue;
+        int o = comp(nb, e);
+        if (o < 0) continue;
+        if (atomicExch(&w.hvis[o], 1) != 0) continue;
+        atomicAdd((unsigned long long *)&stat_line(w)->v[kStInTests], 1ull);
+        if (incircle_tri(m, w, m.tv[o], c.p) > 0) list[atomicAdd(&sh.s_n, 1)] = o;
+        else list[top - atomicAdd(&sh.s_r, 1)] = o;
+      }
+    }
+    __syncthreads();
+  }
+  const int len = sh.s_n, nrej = sh.s_r;
+  __syncthreads();
+  // every visited slot is flagged: clear the flags for the next cavity
+  for (int j = tid; j < len; j += blockDim.x) w.hvis[list[j]] = 0;
+  for (int j = tid; j < nrej; j += blockDim.x) w.hvis[list[top - j]] = 0;
+  coop_finish(m, w, sh, c.S, c.ci, c.is_cc, c.skip_k, c.expect, c.p, list, len);
 }
 
 // Large cavities of one class (phase 0: circumcenters, 1: midpoints); the
@@ -1154,6 +1260,20 @@ __global__ __launch_bounds__(kBigBlock) void k_cavity_big(DevMesh m, Work w, int
     if (is_cc != (phase == 0 ? 1 : 0)) continue;
     big_one(m, w, sh, b);
     __syncthreads();
+  }
+}
+
+// Cavities of one class that outgrew the LDS list, one after the other by
+// a single workgroup (launched only on meshes that have needed it).
+__global__ __launch_bounds__(kHugeBlock) void k_cavity_huge(DevMesh m, Work w, int phase) {
+  __shared__ BigShared sh;
+  if (w.st->halt || w.cnt->nhuge == 0) return;
+  int nbig = min(w.cnt->nbig, w.big_cap);
+  for (int b = 0; b < nbig; b++) {
+    int ref = w.big[b];
+    int is_cc = (ref & 0x80000000) ? 0 : 1;
+    if (is_cc != (phase == 0 ? 1 : 0)) continue;
+    huge_one(m, w, sh, b);
   }
 }
 
@@ -1217,7 +1337,7 @@ __global__ void k_own(Work w) {
 
 // R9: Delaunay dependency across a shared non-subsegment cavity edge.
 // Returns true if the candidate is dropped.
-__device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, int ncc) {
+__device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, int ncc, int &ntest) {
   CandSet S;
   int ci, is_cc;
   cand_at(w, c, ncc, S, ci, is_cc);
@@ -1265,7 +1385,8 @@ __device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, 
       if (!(key < mo)) continue;  // only the lower key of a dependent pair drops
       double2 q = q_cc ? w.cc.p[w.cidx_t[qid]] : w.mid.p[w.cidx_s[qid]];
       double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
-      if (incircle(U.x, U.y, V.x, V.y, p.x, p.y, q.x, q.y) > 0) drop = true;
+      ntest++;
+      if (incircle(U.x, U.y, V.x, V.y, p.x, p.y, q.x, q.y, w.tally) > 0) drop = true;
     }
   }
   (void)skip_k;
@@ -1278,12 +1399,13 @@ __device__ __forceinline__ bool dep_one(const DevMesh &m, const Work &w, int c, 
 
 __device__ __forceinline__ void dep_part(const DevMesh &m, const Work &w, const Lanes &L) {
   const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
-  int n_drop = 0;
+  int n_drop = 0, ntest = 0;
   for (int base = L.base0; base < n; base += L.stride) {
     int c = base + threadIdx.x;
-    if (c < n) n_drop += dep_one(m, w, c, ncc);
+    if (c < n) n_drop += dep_one(m, w, c, ncc, ntest);
   }
   stat_add(w, kStDepDrop, n_drop);
+  stat_add(w, kStInTests, ntest);
 }
 
 __global__ void k_dep(DevMesh m, Work w) {
@@ -1518,12 +1640,6 @@ __device__ __forceinline__ void record_one(const DevMesh &m, const Work &w, int 
   }
 }
 
-__device__ __forceinline__ int fan_size(const Work &w, int r) {
-  int ref = w.win_ref[r];
-  CandSet S = (ref & 0x80000000) ? w.mid : w.cc;
-  return S.len[ref & 0x7fffffff] + (fbase_at(w, r + 1) - fbase_at(w, r));
-}
-
 // The capacity check of the round comes first: every thread evaluates it on
 // the same counts; if anything would overflow, the round is abandoned before
 // the mesh is written and the host grows the buffers and runs it again.
@@ -1533,7 +1649,7 @@ __device__ __forceinline__ void record_part(const DevMesh &m, const Work &w, con
   const int nwin = c->nwin;
   const int fresh = fbase_at(w, nwin);
   const int64_t need_fan = (int64_t)c->pool_used + 2 * (int64_t)nwin;
-  const bool over = (c->err & kErrPool) || (int64_t)st->nV + nwin > m.capV ||
+  const bool over = (c->err & (kErrPool | kErrHuge)) || (int64_t)st->nV + nwin > m.capV ||
                     (int64_t)st->nT + fresh > m.capT || (int64_t)st->nS + c->nwin_mid > m.capS ||
                     need_fan > w.fan_cap || nwin + 1 > w.win_cap;
   if (first_lane(L)) {
@@ -1543,9 +1659,23 @@ __device__ __forceinline__ void record_part(const DevMesh &m, const Work &w, con
   if (over) return;
   for (int base = L.base0; base < nwin; base += L.stride) {
     int r = base + threadIdx.x;
-    int b = r < nwin ? fan_size(w, r) : 0;
+    int b = 0, len = 0, steps = 0, cc = 0;
+    if (r < nwin) {
+      const int ref = w.win_ref[r];
+      cc = (ref & 0x80000000) ? 0 : 1;
+      const CandSet S = cc ? w.cc : w.mid;
+      len = S.len[ref & 0x7fffffff];
+      b = len + (fbase_at(w, r + 1) - fbase_at(w, r));
+      if (cc) steps = (S.state[ref & 0x7fffffff] >> kStepShift) & 0x7fff;
+    }
     int foff = group_alloc(&w.cnt->fan_used, b, L);
     if (r < nwin) record_one(m, w, r, foff);
+    // the winners' share of the round's memory work
+    stat_add(w, kStWinCav, len);
+    stat_add(w, kStWinBnd, b);
+    stat_add(w, kStWinSteps, steps);
+    stat_add(w, kStWinCcCav, cc ? len : 0);
+    stat_add(w, kStWinCcBnd, cc ? b : 0);
   }
 }
 
@@ -1704,10 +1834,11 @@ __device__ __forceinline__ void round_end(const Work &w) {
   // atomics: the lines were written by atomics)
   if (threadIdx.x < kStFields) s_fold[threadIdx.x] = 0;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 4 * kStatStripes; idx += blockDim.x) {
+  constexpr int kGroups = (kStFields + 3) / 4;
+  for (int idx = threadIdx.x; idx < kGroups * kStatStripes; idx += blockDim.x) {
     // one stripe, four of its fields (independent read-and-clear atomics),
     // combined in LDS
-    const int i = idx >> 2, f0 = (idx & 3) * 4;
+    const int i = idx / kGroups, f0 = (idx % kGroups) * 4;
     for (int f = f0; f < f0 + 4 && f < kStFields; f++) {
       const uint64_t x = atomicExch((unsigned long long *)&w.stat[i].v[f], 0ull);
       if (!x) continue;
@@ -1731,6 +1862,16 @@ __device__ __forceinline__ void round_end(const Work &w) {
     c->n_blocked += (int32_t)s_fold[kStBlocked];
     c->n_coincident += (int32_t)s_fold[kStCoincident];
     c->cav_max = max(c->cav_max, (int32_t)s_fold[kStCavMax]);
+    c->n_in_tests += (int64_t)s_fold[kStInTests];
+    c->n_or_tests += (int64_t)s_fold[kStOrTests];
+    for (int e = 0; e < kExStages; e++) c->n_exact[e] += (int64_t)s_fold[kStExact0 + e];
+    c->win_cav += (int64_t)s_fold[kStWinCav];
+    c->win_bnd += (int64_t)s_fold[kStWinBnd];
+    c->win_steps += (int64_t)s_fold[kStWinSteps];
+    c->win_cc_cav += (int64_t)s_fold[kStWinCcCav];
+    c->win_cc_bnd += (int64_t)s_fold[kStWinCcBnd];
+    c->n_marks[0] += (int64_t)s_fold[kStMarks0];
+    c->n_marks[1] += (int64_t)s_fold[kStMarks1];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1975,6 +2116,141 @@ __device__ bool engine_rank(const Work &w, int32_t *lds) {
   return true;
 }
 
+// The single-workgroup engine's large cavities: growth, bitonic sort and
+// checks in LDS, as the cooperative kernel does, by the engine's own
+// workgroup.  A cavity beyond the LDS list makes the round abandon itself
+// (kErrHuge); the host then runs that mesh's rounds on the grid kernels,
+// which finish such cavities in device memory.
+__device__ __forceinline__ void engine_big_one(const DevMesh &m, const Work &w, BigShared &sh, int b) {
+  int32_t *cav = sh.cav;
+  int32_t *hs = sh.hs;
+  int &s_n = sh.s_n, &s_head = sh.s_head, &s_ovf = sh.s_ovf, &s_nbnd = sh.s_nbnd, &s_fanbad = sh.s_fanbad,
+      &s_enc = sh.s_enc, &s_off = sh.s_off;
+  int tid = threadIdx.x;
+  int ref = w.big[b];
+  int is_cc = (ref & 0x80000000) ? 0 : 1;
+  int ci = ref & 0x7fffffff;
+  CandSet S = is_cc ? w.cc : w.mid;
+  if (!(S.state[ci] & kStBig) || (S.state[ci] & kStDone)) return;
+  double2 p = S.p[ci];
+  int skip_k = is_cc ? -1 : S.elem[ci];
+  for (int i = tid; i < kHash; i += blockDim.x) hs[i] = -1;
+  __syncthreads();
+  int expect = 2;
+  if (tid == 0) {
+    s_n = 0; s_head = 0; s_ovf = 0; s_nbnd = 0; s_fanbad = 0; s_enc = 0;
+    if (is_cc) {
+      int t = S.loc[ci];
+      hash_insert(hs, t, &s_ovf);
+      cav[s_n++] = t;
+    } else {
+      int a0 = w.sadj[2 * skip_k], a1 = w.sadj[2 * skip_k + 1];
+      if (a0 >= 0 && hash_insert(hs, a0 >> 2, &s_ovf)) cav[s_n++] = a0 >> 2;
+      if (a1 >= 0 && hash_insert(hs, a1 >> 2, &s_ovf)) cav[s_n++] = a1 >> 2;
+    }
+  }
+  if (!is_cc) expect = (w.sadj[2 * skip_k] >= 0 && w.sadj[2 * skip_k + 1] >= 0) ? 2 : 1;
+  __syncthreads();
+  for (;;) {
+    int lo = s_head, hi = s_n < kBigMax ? s_n : kBigMax;
+    int ovf = s_ovf;
+    __syncthreads();
+    if (lo >= hi || ovf) break;
+    if (tid == 0) s_head = hi;
+    for (int idx = lo + tid; idx < hi; idx += blockDim.x) {
+      int t = cav[idx];
+      int4 tri = m.tv[t];
+      int4 nb = m.tn[t];
+      for (int e = 0; e < 3; e++) {
+        if ((tri.w >> e) & 1) continue;
+        int o = comp(nb, e);
+        if (o < 0) continue;
+        if (!hash_insert(hs, o, &s_ovf)) continue;
+        if (incircle_tri(m, w, m.tv[o], p) > 0) {
+          int pos = atomicAdd(&s_n, 1);
+          if (pos < kBigMax) cav[pos] = o;
+          else s_ovf = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (s_ovf) {
+    if (tid == 0) atomicOr(&w.cnt->err, kErrHuge);
+    return;
+  }
+  int len = s_n;
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int i = len + tid; i < P; i += blockDim.x) cav[i] = 0x7fffffff;
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = tid; i < P; i += blockDim.x) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool up = (i & size) == 0;
+          int x = cav[i], y = cav[j];
+          if ((x > y) == up) { cav[i] = y; cav[j] = x; }
+        }
+      }
+    }
+  __syncthreads();
+  // boundary checks, in parallel over cavity triangles
+  for (int j = tid; j < len; j += blockDim.x) {
+    int t = cav[j];
+    int4 tri = m.tv[t];
+    int4 nb = m.tn[t];
+    int4 ts = tri.w ? m.ts[t] : make_int4(-1, -1, -1, 0);
+    for (int e = 0; e < 3; e++) {
+      int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
+      if (skip_k >= 0 && sid == skip_k) continue;
+      int o = comp(nb, e);
+      if (sid < 0 && o >= 0 && in_sorted(cav, len, o)) continue;
+      atomicAdd(&s_nbnd, 1);
+      double2 U = m.vxy[comp(tri, e)], V = m.vxy[comp(tri, (e + 1) % 3)];
+      if (is_cc && sid >= 0 && encroached(w, U, V, p)) {
+        flag_mid(w, sid);
+        s_enc = 1;
+      }
+      if (orient_pts(w, U, V, p) <= 0) s_fanbad = 1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_off = -1;
+    bool drop = (is_cc && s_enc) || s_fanbad || s_nbnd - len != expect;
+    if (drop) {
+      atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+      atomicMax(&w.cnt->cav_max, len);
+      atomicAdd((is_cc && s_enc) ? &w.cnt->n_enc_reject : &w.cnt->n_fan_invalid, 1);
+      S.state[ci] |= kStDone;
+    } else {
+      int off = atomicAdd(&w.cnt->pool_used, len);
+      if (off + len > w.pool_cap) atomicOr(&w.cnt->err, kErrPool);
+      else {
+        s_off = off;
+        atomicAdd((unsigned long long *)&w.cnt->cav_tri_total, (unsigned long long)len);
+        atomicMax(&w.cnt->cav_max, len);
+      }
+    }
+  }
+  __syncthreads();
+  int off = s_off;
+  if (off >= 0) {
+    uint64_t key = S.key[ci];
+    for (int j = tid; j < len; j += blockDim.x) {
+      w.pool[off + j] = cav[j];
+      atomicMax((unsigned long long *)&w.mark[cav[j]], (unsigned long long)key);
+    }
+    if (tid == 0) {
+      S.off[ci] = off;
+      S.len[ci] = len;
+      S.state[ci] |= kStDone | kStAlive;
+    }
+  }
+}
+
 // Large cavities of one class, one after the other, by the whole workgroup.
 __device__ void engine_big(const DevMesh &m, const Work &w, BigShared &sh, int phase) {
   const int nbig = min(w.cnt->nbig, w.big_cap);
@@ -1982,7 +2258,7 @@ __device__ void engine_big(const DevMesh &m, const Work &w, BigShared &sh, int p
     int ref = w.big[b];
     int is_cc = (ref & 0x80000000) ? 0 : 1;
     if (is_cc != (phase == 0 ? 1 : 0)) continue;
-    big_one(m, w, sh, b);
+    engine_big_one(m, w, sh, b);
     __syncthreads();
   }
 }
@@ -2115,6 +2391,38 @@ __global__ __launch_bounds__(kEngBlock) void k_engine(const EngDesc *descs, int 
     if (i >= n_mesh) return;
     engine_mesh(descs[i], lds, round_limit);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Measurement: 64-bit atomicMax at random slots of a table in device memory,
+// the access pattern of the priority marks (random slot, one read-modify-
+// write each).  Slot and value of operation i come from a fixed mix of i.
+// ---------------------------------------------------------------------------
+__global__ void k_atomic_max_bench(uint64_t *table, uint64_t n_slots, int64_t n_ops, uint64_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_ops; i += stride) {
+    uint64_t h = (uint64_t)i * 0x9e3779b97f4a7c15ull + seed;
+    h ^= h >> 31;
+    h *= 0xbf58476d1ce4e5b9ull;
+    h ^= h >> 29;
+    atomicMax((unsigned long long *)&table[h % n_slots], (unsigned long long)(h | 1ull));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Test entry: the predicates above, one thread per query.
+// ---------------------------------------------------------------------------
+__global__ void k_predicates(int kind, int n, const double *pts, int32_t *out, uint64_t *tally) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int w = kind == 1 ? 8 : 6;
+  const double *q = pts + (size_t)i * w;
+  int r = 0;
+  if (kind == 0) r = orient2d(q[0], q[1], q[2], q[3], q[4], q[5], tally);
+  else if (kind == 1) r = incircle(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], tally);
+  else if (kind == 2) r = indiametral(q[0], q[1], q[2], q[3], q[4], q[5], tally);
+  else r = encroaches(1, q[0], q[1], q[2], q[3], q[4], q[5], tally) ? 1 : 0;
+  out[i] = r;
 }
 
 }  // namespace gdp

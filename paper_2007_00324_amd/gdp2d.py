@@ -52,12 +52,22 @@ class gdp_kernel_prof(C.Structure):
 class gdp_mesh_info(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_subsegments", C.c_int32),
                 ("n_input_vertices", C.c_int32), ("n_input_segments", C.c_int32), ("rounds", C.c_int32),
-                ("cdt_point_rounds", C.c_int32), ("cdt_segment_rounds", C.c_int32)]
+                ("cdt_point_rounds", C.c_int32), ("cdt_segment_rounds", C.c_int32), ("fallbacks", C.c_int64)]
+
+
+class gdp_device_views(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("n_subsegments", C.c_int32),
+                ("tri_stride", C.c_int32), ("xy", C.c_void_p), ("vkind", C.c_void_p), ("tri", C.c_void_p),
+                ("nbr", C.c_void_p), ("sub_on_edge", C.c_void_p), ("sub_v", C.c_void_p),
+                ("sub_parent", C.c_void_p), ("sub_pending", C.c_void_p)]
 
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident", "n_enc_reject",
                "n_mid_cand", "n_unsplittable", "n_fan_invalid", "n_lost_mark", "n_dep_drop", "n_ins_mid",
-               "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities", "n_f1_drop", "n_f2_drop"]
+               "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities", "n_f1_drop", "n_f2_drop",
+               "n_incircle_tests", "n_orient_tests", "n_exact_orient", "n_exact_dot", "n_exact_incircle_b",
+               "n_exact_incircle_c", "win_cav_tri", "win_fan_edges", "win_walk_steps", "win_cc_cav_tri",
+               "win_cc_fan_edges", "n_huge_cavities", "n_marks_mid", "n_marks_cc"]
 
 
 class gdp_round_stats(C.Structure):
@@ -112,6 +122,9 @@ def load() -> C.CDLL:
         "gdp_server_wait": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
         "gdp_server_destroy": (None, [_VP]),
         "gdp_server_engine_jobs": (S, [_VP, C.c_int32]),
+        "gdp_mesh_device_views": (S, [_VP, C.POINTER(gdp_device_views)]),
+        "gdp_predicates_eval": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.POINTER(C.c_int64)]),
+        "gdp_bench_atomic_max": (S, [_VP, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -127,7 +140,8 @@ def exported_symbols() -> list[str]:
             "gdp_mesh_info_get", "gdp_mesh_quality", "gdp_mesh_download", "gdp_mesh_round_stats", "gdp_mesh_last_refine_ms",
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
-            "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy"]
+            "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy", "gdp_mesh_device_views",
+            "gdp_predicates_eval", "gdp_bench_atomic_max"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -180,6 +194,34 @@ def gdp_cdt_host(xy, seg):
     if rc != GDP_OK:
         raise GdpError(rc, err.value.decode())
     return tri, nbr, sg
+
+
+PRED_KINDS = {"orient2d": 0, "incircle": 1, "indiametral": 2, "lens": 3}
+
+
+def gdp_predicates_eval(ctx, kind: str, pts: np.ndarray):
+    """The library's predicates on query rows (6 or 8 doubles each): on the
+    device of ctx, or on the host when ctx is None.  Returns (signs, stage
+    counts [orient, dot, incircle B, incircle C])."""
+    lib = load()
+    k = PRED_KINDS[kind]
+    w = 8 if k == 1 else 6
+    q = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, w)
+    n = q.shape[0]
+    out = np.empty(n, np.int32)
+    counts = (C.c_int64 * 4)()
+    h = ctx._h if ctx is not None else None
+    rc = lib.gdp_predicates_eval(h, k, n, _ptr(q, C.c_double), _ptr(out, C.c_int32), counts)
+    if rc != GDP_OK:
+        raise GdpError(rc, lib.gdp_last_error(h).decode() if h is not None else "bad predicate query")
+    return out, list(counts)
+
+
+def gdp_bench_atomic_max(ctx, n_slots: int, n_ops: int) -> float:
+    """Device ms of n_ops random-slot 64-bit atomicMax on a table of n_slots words."""
+    ms = C.c_double(0.0)
+    ctx.check(load().gdp_bench_atomic_max(ctx._h, int(n_slots), int(n_ops), C.byref(ms)))
+    return ms.value
 
 
 class Context:
@@ -240,6 +282,32 @@ class Mesh:
         self.ctx.check(load().gdp_mesh_quality(self.ctx._h, self._h, float(ratio_bound_sq), float(max_edge_len_sq),
                                                C.byref(n), C.byref(a)))
         return n.value, a.value
+
+    def device_views(self) -> dict:
+        """Zero-copy torch tensors over the mesh's device arrays (the library
+        keeps ownership; valid until the mesh is freed, refined or assigned)."""
+        import torch
+        v = gdp_device_views()
+        self.ctx.check(load().gdp_mesh_device_views(self._h, C.byref(v)))
+        V, T, S = v.n_vertices, v.n_triangles, v.n_subsegments
+        dev = torch.device("cuda", self.ctx.device)
+
+        def wrap(ptr, n, dtype, shape):
+            if n == 0:
+                return torch.empty(shape, dtype=dtype, device=dev)
+            iface = {"shape": (n,), "typestr": "<f8" if dtype == torch.float64 else "<i4",
+                     "data": (ptr, False), "version": 3, "strides": None}
+            holder = type("_View", (), {"__cuda_array_interface__": iface})()
+            return torch.as_tensor(holder, device=dev).view(shape)
+
+        return {"xy": wrap(v.xy, 2 * V, torch.float64, (V, 2)),
+                "vkind": wrap(v.vkind, V, torch.int32, (V,)),
+                "tri": wrap(v.tri, 4 * T, torch.int32, (T, 4)),
+                "nbr": wrap(v.nbr, 4 * T, torch.int32, (T, 4)),
+                "sub_on_edge": wrap(v.sub_on_edge, 4 * T, torch.int32, (T, 4)),
+                "sub_v": wrap(v.sub_v, 2 * S, torch.int32, (S, 2)),
+                "sub_parent": wrap(v.sub_parent, S, torch.int32, (S,)),
+                "sub_pending": wrap(v.sub_pending, S, torch.int32, (S,))}
 
     def arrays(self) -> dict:
         lib = load()

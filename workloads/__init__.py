@@ -23,3 +23,4 @@ from .generators import (  # noqa: F401
     serving_job,
     serving_jobs,
 )
+from .predicates import FAMILIES as PREDICATE_FAMILIES, predicate_corpus  # noqa: F401
