@@ -296,6 +296,20 @@ gdp_status gdp_predicates_eval(gdp_ctx *ctx, int32_t kind, int32_t n, const doub
    non-positive sizes, GDP_E_NOMEM when the table does not fit. */
 gdp_status gdp_bench_atomic_max(gdp_ctx *ctx, int64_t n_slots, int64_t n_ops, double *ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops that forbid allocation): gdp_mesh_quality without
+   any allocation and without blocking.  The two results go to caller device
+   memory (*d_n_bad, *d_bad_area) on the context stream, equal to
+   gdp_mesh_quality's; the per-workgroup partial sums live in a static
+   device array of the library (16 KB per device, resolved when a context is
+   created on the device).  Calls that overlap on one device share that
+   array and race: serialise them (e.g. one stream).  GDP_E_ARG for a bad
+   bound, NULL pointers, or partials beyond the array (not reachable with
+   the fixed grid of at most 512 workgroups); GDP_E_DEVICE if the array's
+   address could not be resolved or a launch failed. */
+gdp_status gdp_mesh_quality_noalloc(gdp_ctx *ctx, const gdp_mesh *mesh, double ratio_bound_sq,
+                                    double max_edge_len_sq, unsigned long long *d_n_bad, double *d_bad_area);
+
 /* Copies the mesh to caller buffers sized from gdp_mesh_info_get (any pointer
    may be NULL to skip that array): xy[2V], vkind[V] (0 input, 1 midpoint,
    2 circumcenter), tri/nbr/sub_on_edge[3T], sub_v[2S], sub_parent[S] (input

@@ -21,6 +21,38 @@
 
 using namespace gdp;
 
+// ---- static scratch of the allocation-free entry point ---------------------
+// gdp_mesh_quality_noalloc keeps its per-workgroup partial sums here instead
+// of in memory it allocates.  Each device holds its own copy, at its own
+// address, resolved once per device when a context is created on it; host
+// code uses only that resolved address (the symbol's host-side name is not a
+// device address).  Calls that overlap on one device share the array and race.
+namespace {
+constexpr size_t kScratchBytes = 16384;
+static_assert((size_t)kQualBlocks * (sizeof(unsigned long long) + sizeof(double)) <= kScratchBytes,
+              "the quality partials fit in the scratch array");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+// With `device` current: resolves the device address of the scratch array once.
+void resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = ptr;
+}
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct gdp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1940,6 +1972,7 @@ gdp_status gdp_ctx_create(int device, void *hip_stream, gdp_ctx **out) {
     g_noctx_err = "hipSetDevice failed";
     return GDP_E_DEVICE;
   }
+  resolve_scratch(device);
   gdp_ctx *c = new gdp_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -2237,6 +2270,28 @@ gdp_status gdp_predicates_eval(gdp_ctx *ctx, int32_t kind, int32_t n, const doub
       for (int i = 0; i < kTallyStripes; i++) sum += (int64_t)h_tally[(size_t)i * kTallyStride + kTally0 + x];
       stage_counts[x] = sum;
     }
+  return GDP_OK;
+}
+
+gdp_status gdp_mesh_quality_noalloc(gdp_ctx *ctx, const gdp_mesh *mesh, double ratio_bound_sq,
+                                    double max_edge_len_sq, unsigned long long *d_n_bad, double *d_bad_area) {
+  if (!ctx || !mesh || mesh->ctx != ctx || !d_n_bad || !d_bad_area) return GDP_E_ARG;
+  if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq) || !(max_edge_len_sq >= 0.0) ||
+      !std::isfinite(max_edge_len_sq))
+    return fail(ctx, GDP_E_ARG, "bad quality bound");
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kQualBlocks, ((int64_t)mesh->m.nT + 255) / 256));
+  const size_t need = (size_t)g * (sizeof(unsigned long long) + sizeof(double));
+  if (need > kScratchBytes) return fail(ctx, GDP_E_ARG, "quality partials exceed the static scratch buffer");
+  void *base = scratch_ptr(ctx->device);
+  if (!base) return fail(ctx, GDP_E_DEVICE, "static scratch buffer address not resolved for this device");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = ctx->stream;
+  // the partials are written by every workgroup before they are read: nothing to clear
+  auto *n_part = (unsigned long long *)base;
+  auto *a_part = (double *)((char *)base + sizeof(unsigned long long) * kQualBlocks);
+  hipLaunchKernelGGL(k_quality, dim3(g), dim3(256), 0, s, mesh->m, ratio_bound_sq, max_edge_len_sq, n_part, a_part);
+  hipLaunchKernelGGL(k_quality_sum, dim3(1), dim3(64), 0, s, (int)g, n_part, a_part, d_n_bad, d_bad_area);
+  if (hipGetLastError() != hipSuccess) return fail(ctx, GDP_E_DEVICE, "quality kernels failed to launch");
   return GDP_OK;
 }
 

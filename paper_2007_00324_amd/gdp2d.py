@@ -125,6 +125,7 @@ def load() -> C.CDLL:
         "gdp_mesh_device_views": (S, [_VP, C.POINTER(gdp_device_views)]),
         "gdp_predicates_eval": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.POINTER(C.c_int64)]),
         "gdp_bench_atomic_max": (S, [_VP, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
+        "gdp_mesh_quality_noalloc": (S, [_VP, _VP, C.c_double, C.c_double, _VP, _VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,7 +142,7 @@ def exported_symbols() -> list[str]:
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
             "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy", "gdp_mesh_device_views",
-            "gdp_predicates_eval", "gdp_bench_atomic_max"]
+            "gdp_predicates_eval", "gdp_bench_atomic_max", "gdp_mesh_quality_noalloc"]
 
 
 def _ptr(a: np.ndarray, ct):
