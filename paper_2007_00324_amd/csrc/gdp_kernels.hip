@@ -190,6 +190,31 @@ __device__ __forceinline__ void stat_add(const Work &w, int f, uint64_t v) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
   if (__lane_id() == 0 && v) atomicAdd((unsigned long long *)&stat_line(w)->v[f], (unsigned long long)v);
 }
+// Four small statistics summed at once: each lane's values must stay below
+// 2^10 (the per-thread cavity slices bound them), so a wave's sums fit the
+// 16-bit fields of one 64-bit word.
+__device__ __forceinline__ void stat_add4(const Work &w, const int f[4], uint32_t a, uint32_t b, uint32_t c,
+                                         uint32_t d) {
+  uint64_t v = (uint64_t)a | ((uint64_t)b << 16) | ((uint64_t)c << 32) | ((uint64_t)d << 48);
+  for (int k = 32; k > 0; k >>= 1) v += __shfl_xor(v, k);
+  if (__lane_id() == 0 && v) {
+    StatLine *l = stat_line(w);
+    for (int i = 0; i < 4; i++) {
+      const uint64_t x = (v >> (16 * i)) & 0xffffu;
+      if (x) atomicAdd((unsigned long long *)&l->v[f[i]], (unsigned long long)x);
+    }
+  }
+}
+// Two statistics summed at once whose wave sums fit 32 bits.
+__device__ __forceinline__ void stat_add2(const Work &w, int f0, int f1, uint32_t a, uint32_t b) {
+  uint64_t v = (uint64_t)a | ((uint64_t)b << 32);
+  for (int k = 32; k > 0; k >>= 1) v += __shfl_xor(v, k);
+  if (__lane_id() == 0 && v) {
+    StatLine *l = stat_line(w);
+    if (v & 0xffffffffu) atomicAdd((unsigned long long *)&l->v[f0], (unsigned long long)(v & 0xffffffffu));
+    if (v >> 32) atomicAdd((unsigned long long *)&l->v[f1], (unsigned long long)(v >> 32));
+  }
+}
 __device__ __forceinline__ void stat_max(const Work &w, int f, uint64_t v) {
   for (int d = 32; d > 0; d >>= 1) v = max(v, (uint64_t)__shfl_xor(v, d));
   if (__lane_id() == 0 && v) atomicMax((unsigned long long *)&stat_line(w)->v[f], (unsigned long long)v);
@@ -744,6 +769,10 @@ struct CavCheck {
 // a few bytes) is the most LDS that still lets 8 workgroups (16 waves) share a
 // compute unit's 160 KB; larger cavities go to the cooperative kernel
 constexpr int kCap = 39;
+// per-lane statistics of a per-thread cavity (size, boundary edges, circle
+// tests: at most three per slot) stay below 2^10 (see stat_add4)
+constexpr int kStat4Cap = 1023 / 3 - 2;
+static_assert(kCap <= kStat4Cap, "per-thread cavity statistics fit stat_add4");
 constexpr int kCavBlock = kCavBlockSize;
 
 // Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
@@ -957,16 +986,12 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
       }
     }
     // (summed per iteration: nothing stays live across the cavity work)
-    stat_add(w, kStCavTri, counted ? r.len : 0);
     stat_max(w, kStCavMax, counted ? r.len : 0);
-    stat_add(w, is_cc ? kStCavLen1 : kStCavLen0, r.len);
-    stat_add(w, is_cc ? kStCavBnd1 : kStCavBnd0, r.bnd);
-    stat_add(w, kStEncReject, r.enc_reject);
-    stat_add(w, kStFanInvalid, r.fan_invalid);
-    stat_add(w, kStUnsplittable, r.unsplittable);
+    const int f4a[4] = {kStCavTri, is_cc ? kStCavLen1 : kStCavLen0, is_cc ? kStCavBnd1 : kStCavBnd0, kStInTests};
+    const int f4b[4] = {is_cc ? kStMarks1 : kStMarks0, kStEncReject, kStFanInvalid, kStUnsplittable};
+    stat_add4(w, f4a, counted ? r.len : 0, r.len, r.bnd, r.ntest);
+    stat_add4(w, f4b, (r.alive && counted) ? r.len : 0, r.enc_reject, r.fan_invalid, r.unsplittable);
     stat_add(w, kStMidCand, r.mid_cand);
-    stat_add(w, kStInTests, r.ntest);
-    stat_add(w, is_cc ? kStMarks1 : kStMarks0, (r.alive && counted) ? r.len : 0);
   }
 }
 
@@ -1670,12 +1695,11 @@ __device__ __forceinline__ void record_part(const DevMesh &m, const Work &w, con
     }
     int foff = group_alloc(&w.cnt->fan_used, b, L);
     if (r < nwin) record_one(m, w, r, foff);
-    // the winners' share of the round's memory work
-    stat_add(w, kStWinCav, len);
-    stat_add(w, kStWinBnd, b);
+    // the winners' share of the round's memory work (winners' cavities are
+    // disjoint, so a wave's sums of sizes and fan edges stay below 2^32)
+    stat_add2(w, kStWinCav, kStWinBnd, len, b);
+    stat_add2(w, kStWinCcCav, kStWinCcBnd, cc ? len : 0, cc ? b : 0);
     stat_add(w, kStWinSteps, steps);
-    stat_add(w, kStWinCcCav, cc ? len : 0);
-    stat_add(w, kStWinCcBnd, cc ? b : 0);
   }
 }
 
@@ -2271,6 +2295,7 @@ constexpr int kEngCap = 48;
 // midpoint cavities listed before the circumcenter cavities run on the other
 // half of the workgroup at the same time, in slices of their own
 constexpr int kEngMidCap = 24;
+static_assert(kEngCap <= kStat4Cap && kEngMidCap <= kStat4Cap, "engine cavity statistics fit stat_add4");
 constexpr int kEngMidLdsWords = kEngMidCap * kEngCavThreads;
 constexpr int kEngLdsWords = (kEngCap * kEngCavThreads > (int)(sizeof(BigShared) / 4)) ? kEngCap * kEngCavThreads
                                                                                      : (int)(sizeof(BigShared) / 4);

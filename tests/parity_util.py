@@ -62,3 +62,30 @@ def diff_stats(orc_stats: list[dict], gpu_stats: list[dict]) -> list[str]:
         if len(out) > 20:
             break
     return out
+
+
+ARRAY_KEYS = ["xy", "vkind", "tv", "tn", "ts", "sv", "sparent", "spend"]
+
+
+def mesh_digest(a: dict) -> str:
+    """SHA-256 over the mesh arrays in a fixed order and dtype (coordinates as
+    their IEEE bit patterns), so two meshes compare bit for bit by digest."""
+    import hashlib
+    h = hashlib.sha256()
+    for k in ARRAY_KEYS:
+        x = np.asarray(a[k])
+        x = x.view(np.uint64) if k == "xy" else x.astype(np.int64)
+        h.update(k.encode())
+        h.update(np.asarray(x.shape, dtype=np.int64).tobytes())
+        h.update(np.ascontiguousarray(x).tobytes())
+    return h.hexdigest()
+
+
+def batch_instance_with_oracle(args):
+    """Worker (a spawned process that never touches the GPU): one instance of
+    the batched workload and the digest of the oracle's refined mesh."""
+    import workloads
+    n, bsq, seed = args
+    p = workloads.batch_instance(n, bsq, seed)
+    om, rc = oracle_run(p)
+    return p.xy, p.seg, p.ratio_bound_sq, rc, mesh_digest(om.arrays()), om.rounds
