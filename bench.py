@@ -321,51 +321,72 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     }
 
 
-def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int, engine_max_v=None) -> dict:
-    """Serving form: the same job set replayed as a Poisson stream at each
-    rate; latency = completion - arrival (Line 1 runs before arrival)."""
+def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode):
+    """One replay of the job set as a Poisson stream of rate lam (None: every
+    job arrives at once); returns latencies (ms), the achieved rate and the
+    count of failed jobs."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     from paper_2007_00324_amd import gdp2d
     n = len(jobs)
-    out = {"workload": (f"{n} jobs: the 1M-point generator scaled to log-uniform 1,000..200,000 points, segments 5% "
-                        "of the points, B^2 drawn from {2.0, 2.56, 4.0}; Poisson arrivals, the same jobs at every "
-                        "rate; Line 1 on the host before arrival"),
+    srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v, mode=mode)
+    with ThreadPoolExecutor(16) as ex:  # Line 1 of every job, in parallel, before the stream starts
+        ids = list(ex.map(lambda p: srv.prepare(p.xy, p.seg, p.ratio_bound_sq), jobs))
+    gaps = np.random.default_rng(7).exponential(1.0 / lam, size=n) if lam else np.zeros(n)
+    results = [None] * n
+
+    def collect():
+        for k, j in enumerate(ids):
+            m, rc, t = srv.wait(j)
+            results[k] = (rc, t)
+            if m is not None:
+                m.free()
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    due = 0.0
+    for k, j in enumerate(ids):
+        due += gaps[k]
+        while time.perf_counter() - t0 < due:
+            time.sleep(min(0.0005, max(0.0, due - (time.perf_counter() - t0))))
+        srv.arrive(j)
+    th.join()
+    srv.close()
+    lat = np.array([t["done_ms"] - t["submit_ms"] for _, t in results])
+    span = max(1e-9, (max(t["done_ms"] for _, t in results) - min(t["submit_ms"] for _, t in results)) / 1000.0)
+    return lat, n / span, sum(1 for rc, _ in results if rc != 0)
+
+
+def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int, engine_max_v=None,
+                mode: int = 0) -> dict:
+    """Serving form: the same job set replayed as a Poisson stream at each
+    rate; latency = completion - arrival (Line 1 runs before arrival).  The
+    capacity is measured first (every job arriving at once); rates given as
+    fractions ("0.5x") are taken of it."""
+    import numpy as np
+    from paper_2007_00324_amd import gdp2d
+    n = len(jobs)
+    out = {"workload": (f"{n} jobs (a reduced stream, not the 20,000-job set): the 1M-point generator scaled to "
+                        "log-uniform 1,000..200,000 points, segments 5% of the points, B^2 drawn from "
+                        "{2.0, 2.56, 4.0}; Poisson arrivals, the same jobs at every rate; Line 1 on the host before "
+                        "arrival"),
            "jobs": n, "input_vertices": sum(p.n_vertices for p in jobs), "budget_gb": budget_gb, "slots": slots,
+           "mode": ["shared rounds", "stream per slot"][mode],
            "engine_max_vertices": engine_max_v if engine_max_v is not None else 0,
            "rates": []}
-    for lam in rates:
-        srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v)
-        with ThreadPoolExecutor(16) as ex:  # Line 1 of every job, in parallel, before the stream starts
-            ids = list(ex.map(lambda p: srv.prepare(p.xy, p.seg, p.ratio_bound_sq), jobs))
-        gaps = np.random.default_rng(7).exponential(1.0 / lam, size=n)
-        results = [None] * n
-
-        def collect():
-            for k, j in enumerate(ids):
-                m, rc, t = srv.wait(j)
-                results[k] = (rc, t)
-                if m is not None:
-                    m.free()
-        th = threading.Thread(target=collect)
-        th.start()
-        t0 = time.perf_counter()
-        due = 0.0
-        for k, j in enumerate(ids):
-            due += gaps[k]
-            while time.perf_counter() - t0 < due:
-                time.sleep(min(0.0005, max(0.0, due - (time.perf_counter() - t0))))
-            srv.arrive(j)
-        th.join()
-        srv.close()
-        lat = np.array([t["done_ms"] - t["submit_ms"] for _, t in results])
-        span = max(1e-9, (max(t["done_ms"] for _, t in results) - min(t["submit_ms"] for _, t in results)) / 1000.0)
-        bad = sum(1 for rc, _ in results if rc != 0)
-        row = {"rate_jobs_per_s": lam, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-               "achieved_jobs_per_s": n / span, "failed": bad}
-        log(f"serving at {lam}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
-            f"{row['achieved_jobs_per_s']:.0f} jobs/s, {bad} not OK")
+    lat, cap, bad = serve_stream(ctx, jobs, None, budget_gb, slots, engine_max_v, mode)
+    out["capacity_jobs_per_s"] = cap
+    out["capacity_run"] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                           "failed": bad}
+    log(f"serving capacity ({out['mode']}): {cap:.0f} jobs/s with every job arriving at once, {bad} not OK")
+    for r in rates:
+        lam = cap * float(r[:-1]) if r.endswith("x") else float(r)
+        lat, ach, bad = serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode)
+        row = {"rate_jobs_per_s": lam, "rate_vs_capacity": lam / cap, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "achieved_jobs_per_s": ach, "failed": bad}
+        log(f"serving at {lam:.0f}/s ({lam / cap:.2f} of capacity): p50 {row['p50_ms']:.1f} ms, "
+            f"p99 {row['p99_ms']:.1f} ms, {ach:.0f} jobs/s, {bad} not OK")
         out["rates"].append(row)
     # the plain loop on a sample: Line 1 untimed (the server runs it before arrival),
     # then upload + refine one job after another (end to end), and the device
@@ -386,6 +407,7 @@ def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int
     out["plain_device_jobs_per_s"] = len(sample) / (plain_ms / 1000.0)
     out["plain_sample"] = (f"every {plain_every}th job ({len(sample)} jobs), one after another: upload + refine "
                            "wall time (plain_jobs_per_s) and device refine time alone (plain_device_jobs_per_s)")
+    out["capacity_vs_plain"] = out["capacity_jobs_per_s"] / out["plain_jobs_per_s"]
     log(f"serving: plain loop {out['plain_jobs_per_s']:.0f} jobs/s end to end, "
         f"{out['plain_device_jobs_per_s']:.0f} jobs/s of device refine time")
     return out
@@ -411,7 +433,9 @@ def main() -> int:
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
     ap.add_argument("--serve", type=int, default=400, help="jobs of the serving stream (0: skip)")
-    ap.add_argument("--serve-rates", type=str, default="50,200,1000", help="arrival rates, jobs/s")
+    ap.add_argument("--serve-rates", type=str, default="0.25x,0.5x,0.9x,1.5x",
+                    help="arrival rates, jobs/s, or fractions of the measured capacity (0.5x)")
+    ap.add_argument("--serve-mode", type=int, default=0, help="0: shared rounds, 1: a stream per slot")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-engine-max", type=int, default=None,
@@ -576,9 +600,9 @@ def main() -> int:
     if args.batch > 0:
         out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
     if serve_jobs:
-        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        rates = [r for r in args.serve_rates.split(",") if r]
         out["serving"] = serving_leg(ctx, serve_jobs, rates, args.serve_budget_gb, args.serve_slots, 8,
-                                     args.serve_engine_max)
+                                     args.serve_engine_max, args.serve_mode)
     if not args.no_cpu_baseline:
         n = args.cpu_sample
         log(f"cpu baseline: oracle on {n:,} points")

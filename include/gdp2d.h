@@ -354,11 +354,15 @@ gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *r
    server's device memory (each job's region is sized from its initial CDT),
    admitted jobs are refined at once, side by side on the device, and
    finished jobs leave, freeing their slot and region for the next arrival.
-   By default each admitted job runs its rounds on a slot of its own (one
-   stream and one library thread per slot); with gdp_server_engine_jobs,
-   small jobs are instead refined together, one workgroup each, in launches
-   of the single-workgroup engine.  Each result is bit-identical to
-   gdp_refine on the same input.  A job that outgrows its region is refined
+   By default (mode 0) the rounds are shared (Rule 4 of Section 2: groups of
+   work merged into one launch): one library thread runs the rounds of every
+   active job together, one kernel launch per phase of the round for all of
+   them, and jobs join and leave between groups of two rounds.  In mode 1
+   each admitted job runs its rounds on a slot of its own (one stream and one
+   library thread per slot).  With gdp_server_engine_jobs, small jobs are
+   instead refined together, one workgroup each, in launches of the
+   single-workgroup engine.  Each result is bit-identical to gdp_refine on
+   the same input.  A job that outgrows its region is refined
    again on its own.  Latency is measured from arrival (after Line 1, which
    runs in the caller's thread at prepare). */
 typedef struct gdp_server gdp_server;
@@ -369,9 +373,12 @@ typedef struct {
   double done_ms;    /* completion */
 } gdp_job_times;
 
-/* hbm_budget: bytes of device memory for job regions; max_slots: jobs on the
-   device at once on their own streams (one library thread each). */
+/* hbm_budget: bytes of device memory for job regions; max_slots: jobs active
+   at once (in the shared rounds, or on their own streams in mode 1). */
 gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out);
+/* 0: shared rounds (default); 1: a stream and a thread per slot.  Applies to
+   jobs admitted afterwards.  GDP_E_ARG for another value. */
+gdp_status gdp_server_mode(gdp_server *srv, int32_t mode);
 /* Jobs with at most max_input_vertices input vertices go to the batched
    launches (0: every job takes a slot).  Applies to jobs admitted afterwards.
    GDP_E_ARG for a negative value. */

@@ -1402,12 +1402,26 @@ struct ServerEngine {
   std::thread th;
 };
 
+// Shared rounds (Rule 4 of Section 2, the default mode): one driver thread
+// runs the rounds of every active job together, one launch per phase for all
+// of them; jobs join and leave between groups of rounds.
+constexpr int kGangRounds = 2;  // rounds between two host reads of the jobs' states
+struct ServerGang {
+  gdp_ctx ctx;                               // the driver's own stream
+  GangDesc *d_desc = nullptr, *h_desc = nullptr;  // [max_slots]
+  int32_t *d_status = nullptr, *h_status = nullptr;
+  int stride_words = 0;                      // words of one job's status record
+  std::thread th;
+};
+
 struct gdp_server {
   gdp_ctx *user = nullptr;  // the caller's context: finished meshes are handed over to it
   ServerMem *mem = nullptr;
   int max_slots = 0;
-  int32_t engine_max_v = 0;  // 0: every job on the slots
+  int32_t mode = 0;          // 0: shared rounds; 1: a stream and a thread per slot
+  int32_t engine_max_v = 0;  // 0: no job in the single-workgroup engine launches
   ServerEngine *eng = nullptr;
+  ServerGang *gang = nullptr;
   std::mutex mu;
   std::condition_variable cv;
   std::map<uint64_t, Job *> jobs;
@@ -1499,6 +1513,8 @@ void free_server_engine(ServerEngine *E) {
 bool for_engine(const gdp_server *S, const Job *J) {
   return S->engine_max_v > 0 && !J->grid_only && J->hm.nV <= S->engine_max_v;
 }
+bool for_slots(const gdp_server *S, const Job *J) { return S->mode == 1 && !for_engine(S, J); }
+bool for_gang(const gdp_server *S, const Job *J) { return S->mode == 0 && !for_engine(S, J); }
 
 // One batched launch over jobs already taken from the queue (regions held).
 void engine_batch(gdp_server *S, ServerEngine *E, std::vector<Job *> &B) {
@@ -1646,6 +1662,260 @@ void engine_dispatcher(gdp_server *S, ServerEngine *E) {
   }
 }
 
+
+// ---- serving form: shared rounds ------------------------------------------
+// Per active job: the host's view between two groups of rounds.
+struct GangJob {
+  Job *J;
+  int64_t last_cand;  // candidates of the last completed round (sizes the grids)
+  int aborts;         // consecutive abandoned rounds
+  bool full;          // its next round is its first (a full collection)
+};
+
+GangDesc gang_desc(gdp_mesh *M, const Job *J) {
+  GangDesc g;
+  memset(&g, 0, sizeof g);
+  EngDesc &d = g.e;
+  d.m = M->m;
+  d.w[0] = make_work(M, &J->P, 0);
+  d.w[1] = make_work(M, &J->P, 1);
+  // one workgroup runs the device-memory cavity path per mesh and launch
+  d.w[0].huge_ok = d.w[1].huge_ok = 1;
+  d.B2 = J->B2;
+  d.pm = J->P.priority_mode;
+  d.K = J->P.cand_cap_K;
+  d.f1 = J->P.prefilter_f1;
+  d.approx_n = J->P.cavity_approx_n;
+  d.max_rounds = J->P.max_rounds;
+  g.js = ScanJob{(const int32_t *)M->win_s, M->rank_s, &M->d_st->wS, M->tiles_s, &M->d_cnt->nwin_mid, 1};
+  g.jt = ScanJob{(const int32_t *)M->win_t, M->rank_t, &M->d_st->wT, M->tiles_t, &M->d_cnt->nwin_cc, 1};
+  g.jf = ScanJob{M->fcount, M->fbase, &M->d_cnt->nwin1, M->tiles_f, &M->d_cnt->fan_total, 0};
+  return g;
+}
+
+// One round of every job in the descriptors (grids sized for the largest).
+void gang_round(hipStream_t s, const GangDesc *D, unsigned n, int64_t max_full, int64_t max_est,
+                int64_t max_ncand, int64_t max_words, bool any_cap, bool any_pre) {
+  const int bs = 256;
+  const unsigned gc = std::max(stride_grid(max_full, bs), stride_grid(3 * max_est, bs));
+  hipLaunchKernelGGL(kg_collect, dim3(gc, n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_pending, dim3(stride_grid(max_est / 4, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_gate, dim3(1, n), dim3(256), 0, s, D);
+  if (any_cap) {
+    hipLaunchKernelGGL(kg_gather_keys, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+    const unsigned g = std::min<unsigned>(grid_for(max_ncand, 256), 1024);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(kg_radix_hist, dim3(g, n), dim3(256), 0, s, D, shift);
+      hipLaunchKernelGGL(kg_radix_pick, dim3(1, n), dim3(256), 0, s, D, shift);
+    }
+    hipLaunchKernelGGL(kg_apply_cap, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  }
+  hipLaunchKernelGGL(kg_locate, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  if (any_pre)
+    for (int mode = 0; mode < 6; mode++)
+      hipLaunchKernelGGL(kg_prefilter, dim3(stride_grid(max_ncand, 128), n), dim3(128), 0, s, D, mode);
+  hipLaunchKernelGGL(kg_cavity<1>, dim3(stride_grid(max_ncand, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
+  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_cavity<0>, dim3(stride_grid(max_ncand / 4, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
+  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_own, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_dep, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  const int64_t tiles_w = std::max<int64_t>(1, (max_words + kScanTileSize - 1) / kScanTileSize);
+  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(2 * tiles_w, 2048), n), dim3(256), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_scan_sums, dim3(2, n), dim3(256), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_winners, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  const int64_t tiles_f = std::max<int64_t>(1, (max_ncand + 1 + kScanTileSize - 1) / kScanTileSize);
+  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(tiles_f, 2048), n), dim3(256), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_scan_sums, dim3(1, n), dim3(256), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_record, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_write, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_finish, dim3(std::min(stride_grid(max_ncand, bs), 256u), n), dim3(bs), 0, s, D);
+}
+
+// The driver: admits arrived jobs (first come, first served) while a slot
+// and room are free, runs kGangRounds rounds of every active job, reads all
+// their states at once, and retires finished jobs.  A job whose round found
+// a buffer short has that buffer grown and runs the round again, as in the
+// plain loop; each job's mesh is therefore the plain loop's.
+void gang_driver(gdp_server *S, ServerGang *Gn) {
+  (void)hipSetDevice(Gn->ctx.device);
+  gdp_ctx *ctx = &Gn->ctx;
+  hipStream_t s = ctx->stream;
+  std::vector<GangJob> active;
+  const int ns = (int)(sizeof(DevState) / 4), nc = (int)(sizeof(DevCounters) / 4);
+  for (;;) {
+    std::vector<Job *> fresh;
+    {
+      std::unique_lock<std::mutex> g(S->mu);
+      for (;;) {
+        for (auto it = S->queue.begin();
+             it != S->queue.end() && (int)(active.size() + fresh.size()) < S->max_slots;) {
+          Job *Q = *it;
+          if (!for_gang(S, Q)) {
+            ++it;
+            continue;
+          }
+          size_t off;
+          bool got;
+          {
+            std::lock_guard<std::mutex> gm(S->mem->mu);
+            got = S->mem->take(Q->bytes, &off);
+          }
+          if (!got) break;  // first come, first served: wait for room
+          Q->off = off;
+          Q->state = Job::ACTIVE;
+          Q->t_admit = ms_since(S->t0);
+          S->running++;
+          fresh.push_back(Q);
+          it = S->queue.erase(it);
+        }
+        if (!fresh.empty() || !active.empty()) break;
+        bool mine = false;
+        for (Job *Q : S->queue) mine = mine || for_gang(S, Q);
+        if (S->stop && !mine) return;
+        if (S->stop && mine && S->running == 0) {
+          // closing, and the room is held by meshes the caller owns
+          for (auto q = S->queue.begin(); q != S->queue.end();) {
+            if (!for_gang(S, *q)) {
+              ++q;
+              continue;
+            }
+            (*q)->status = GDP_E_NOMEM;
+            (*q)->t_done = ms_since(S->t0);
+            (*q)->state = Job::DONE;
+            q = S->queue.erase(q);
+          }
+          S->cv.notify_all();
+          continue;
+        }
+        S->cv.wait_for(g, std::chrono::milliseconds(1));
+      }
+    }
+    for (Job *J : fresh) {
+      gdp_status st = admit_job(S, J, ctx);
+      if (st != GDP_OK) {
+        if (J->mesh) gdp_mesh_free(J->mesh);
+        J->mesh = nullptr;
+        complete_job(S, J, st);
+        continue;
+      }
+      active.push_back(GangJob{J, (int64_t)J->mesh->m.nT + J->mesh->m.nS, 0, true});
+    }
+    if (active.empty()) continue;
+    // room for this group of rounds, then the descriptors
+    int64_t max_full = 0, max_est = 1, max_ncand = 1, max_words = 1;
+    bool any_cap = false, any_pre = false;
+    for (size_t q = 0; q < active.size();) {
+      GangJob &A = active[q];
+      gdp_mesh *M = A.J->mesh;
+      gdp_status st = reserve_group(M, A.last_cand, kGangRounds);
+      if (st != GDP_OK) {
+        gdp_mesh_free(M);
+        A.J->mesh = nullptr;
+        complete_job(S, A.J, st);
+        active.erase(active.begin() + q);
+        continue;
+      }
+      const DevMesh &m = M->m;
+      if (A.full) max_full = std::max<int64_t>(max_full, std::max(m.nT, m.nS));
+      else max_est = std::max<int64_t>(max_est, A.last_cand);
+      max_ncand = std::max<int64_t>(max_ncand, std::max<int64_t>((int64_t)m.nT + m.nS, 2 * A.last_cand));
+      max_words = std::max<int64_t>(max_words, std::max(words(m.capS), words(m.capT)));
+      any_cap = any_cap || A.J->P.cand_cap_K > 0;
+      any_pre = any_pre || A.J->P.prefilter_f1 || A.J->P.cavity_approx_n > 0;
+      Gn->h_desc[q] = gang_desc(M, A.J);
+      q++;
+    }
+    const unsigned n = (unsigned)active.size();
+    if (n == 0) continue;
+    bool ok = hipMemcpyAsync(Gn->d_desc, Gn->h_desc, sizeof(GangDesc) * n, hipMemcpyHostToDevice, s) == hipSuccess;
+    for (int r = 0; ok && r < kGangRounds; r++)
+      gang_round(s, Gn->d_desc, n, max_full, max_est, max_ncand, max_words, any_cap, any_pre);
+    if (ok) {
+      hipLaunchKernelGGL(kg_status, dim3(1, n), dim3(256), 0, s, Gn->d_desc, kGangRounds, Gn->d_status,
+                         Gn->stride_words);
+      ok = hipGetLastError() == hipSuccess &&
+           hipMemcpyAsync(Gn->h_status, Gn->d_status, sizeof(int32_t) * Gn->stride_words * n, hipMemcpyDeviceToHost,
+                          s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+    }
+    std::vector<GangJob> keep;
+    for (unsigned q = 0; q < n; q++) {
+      GangJob A = active[q];
+      Job *J = A.J;
+      gdp_mesh *M = J->mesh;
+      if (!ok) {
+        gdp_mesh_free(M);
+        J->mesh = nullptr;
+        complete_job(S, J, fail(ctx, GDP_E_DEVICE, "shared round launch failed"));
+        continue;
+      }
+      const int32_t *rec = Gn->h_status + (size_t)q * Gn->stride_words;
+      DevState d;
+      DevCounters c;
+      memcpy(&d, rec, sizeof d);
+      memcpy(&c, rec + ns, sizeof c);
+      const DevCounters *h = (const DevCounters *)(rec + ns + nc);
+      const int done = std::min(d.nhist, kGangRounds);
+      for (int i = 0; i < done; i++) {
+        M->stats.push_back(round_stats_of(h[i], &J->P));
+        A.last_cand = (int64_t)h[i].ncc + h[i].nmk;
+      }
+      M->m.nV = d.nV; M->m.nT = d.nT; M->m.nS = d.nS; M->m.rounds = d.rounds;
+      M->serial = d.serial;
+      if (done > 0) {
+        A.aborts = 0;
+        A.full = false;
+      }
+      gdp_status st = GDP_OK;
+      bool finished = false;
+      if (d.halt == kHaltAbort) {
+        // nothing was written: grow and run the same round again
+        if (++A.aborts > 16) {
+          st = fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
+          finished = true;
+        } else if ((st = grow_after_abort(M, c, d.full ? 0 : d.prev_fan)) != GDP_OK) {
+          finished = true;
+        } else if (hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s) != hipSuccess ||
+                   hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s) != hipSuccess) {
+          st = fail(ctx, GDP_E_DEVICE, "reset after an abandoned round failed");
+          finished = true;
+        }
+      } else if (d.halt != 0) {
+        st = status_of_halt(ctx, d, c);
+        finished = true;
+      }
+      if (!finished && hipMemsetAsync(&M->d_st->halt, 0, 2 * sizeof(int32_t), s) != hipSuccess) {  // halt, nhist
+        st = fail(ctx, GDP_E_DEVICE, "round state reset failed");
+        finished = true;
+      }
+      if (!finished) {
+        keep.push_back(A);
+        continue;
+      }
+      if (st == GDP_OK && !M->arena) st = alloc_host_mirrors(M);
+      if (st != GDP_OK && st != GDP_E_NOTERM) {
+        gdp_mesh_free(M);
+        J->mesh = nullptr;
+      }
+      complete_job(S, J, st);
+    }
+    active.swap(keep);
+  }
+}
+
+void free_server_gang(ServerGang *Gn) {
+  if (!Gn) return;
+  if (Gn->ctx.stream) (void)hipStreamDestroy(Gn->ctx.stream);
+  if (Gn->d_desc) (void)hipFree(Gn->d_desc);
+  if (Gn->d_status) (void)hipFree(Gn->d_status);
+  if (Gn->h_desc) (void)hipHostFree(Gn->h_desc);
+  if (Gn->h_status) (void)hipHostFree(Gn->h_status);
+  delete Gn;
+}
+
 void server_worker(gdp_server *S, ServerWorker *W) {
   (void)hipSetDevice(W->ctx.device);
   for (;;) {
@@ -1654,7 +1924,7 @@ void server_worker(gdp_server *S, ServerWorker *W) {
       std::unique_lock<std::mutex> g(S->mu);
       for (;;) {
         auto it = S->queue.begin();
-        while (it != S->queue.end() && for_engine(S, *it)) ++it;
+        while (it != S->queue.end() && !for_slots(S, *it)) ++it;
         if (it != S->queue.end()) {
           Job *Q = *it;
           size_t off;
@@ -1674,16 +1944,22 @@ void server_worker(gdp_server *S, ServerWorker *W) {
           }
           if (S->stop && S->running == 0) {
             // closing, and the room is held by meshes the caller owns
-            for (Job *R : S->queue) {
-              R->status = GDP_E_NOMEM;
-              R->t_done = ms_since(S->t0);
-              R->state = Job::DONE;
+            for (auto q = S->queue.begin(); q != S->queue.end();) {
+              if (!for_slots(S, *q)) {
+                ++q;
+                continue;
+              }
+              (*q)->status = GDP_E_NOMEM;
+              (*q)->t_done = ms_since(S->t0);
+              (*q)->state = Job::DONE;
+              q = S->queue.erase(q);
             }
-            S->queue.clear();
             S->cv.notify_all();
           }
         }
-        if (S->stop && S->queue.empty()) return;
+        bool mine = false;
+        for (Job *Q : S->queue) mine = mine || for_slots(S, Q);
+        if (S->stop && !mine) return;
         // first come, first served: wait for an arrival or for room
         S->cv.wait_for(g, std::chrono::milliseconds(2));
       }
@@ -2548,10 +2824,46 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
     delete S;
     return fail(ctx, GDP_E_NOMEM, "server allocation failed");
   }
+  ServerGang *Gn = new ServerGang();
+  Gn->ctx.device = ctx->device;
+  Gn->stride_words = (int)((sizeof(DevState) + (1 + kGangRounds) * sizeof(DevCounters)) / 4);
+  ok = hipStreamCreateWithFlags(&Gn->ctx.stream, hipStreamNonBlocking) == hipSuccess &&
+       dalloc(&Gn->d_desc, max_slots) == hipSuccess &&
+       hipHostMalloc((void **)&Gn->h_desc, sizeof(GangDesc) * max_slots) == hipSuccess &&
+       dalloc(&Gn->d_status, (size_t)Gn->stride_words * max_slots) == hipSuccess &&
+       hipHostMalloc((void **)&Gn->h_status, sizeof(int32_t) * Gn->stride_words * max_slots) == hipSuccess;
+  if (!ok) {
+    free_server_gang(Gn);
+    free_server_engine(E);
+    for (ServerWorker *W : S->workers) {
+      (void)hipStreamDestroy(W->ctx.stream);
+      (void)hipHostFree(W->h_cnt);
+      (void)hipHostFree(W->h_st);
+      (void)hipHostFree(W->h_hist);
+      (void)hipFree(W->d_eng);
+      (void)hipFree(W->d_head);
+      (void)hipHostFree(W->h_eng);
+      delete W;
+    }
+    (void)hipFree(S->mem->base);
+    delete S->mem;
+    delete S;
+    return fail(ctx, GDP_E_NOMEM, "server allocation failed");
+  }
+  S->gang = Gn;
   S->engine_max_v = kSrvEngineDefaultMaxV;
   for (ServerWorker *W : S->workers) W->th = std::thread(server_worker, S, W);
   E->th = std::thread(engine_dispatcher, S, E);
+  Gn->th = std::thread(gang_driver, S, Gn);
   *out = S;
+  return GDP_OK;
+}
+
+gdp_status gdp_server_mode(gdp_server *srv, int32_t mode) {
+  if (!srv || mode < 0 || mode > 1) return GDP_E_ARG;
+  std::lock_guard<std::mutex> g(srv->mu);
+  srv->mode = mode;
+  srv->cv.notify_all();
   return GDP_OK;
 }
 
@@ -2644,7 +2956,9 @@ void gdp_server_destroy(gdp_server *srv) {
   }
   for (ServerWorker *W : srv->workers) W->th.join();
   if (srv->eng) srv->eng->th.join();
+  if (srv->gang) srv->gang->th.join();
   free_server_engine(srv->eng);
+  free_server_gang(srv->gang);
   for (auto &kv : srv->jobs) {
     if (kv.second->mesh) gdp_mesh_free(kv.second->mesh);
     delete kv.second;

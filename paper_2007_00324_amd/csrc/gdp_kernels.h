@@ -118,6 +118,41 @@ struct EngDesc {
 constexpr int kEngBlock = 1024;
 __global__ void k_engine(const EngDesc *descs, int n_mesh, int32_t *head, int round_limit);
 
+// Round-boundary batching (the serving form's shared rounds): one launch per
+// phase for a set of meshes.  Workgroup (x, y) works on mesh y, with the
+// grid-stride loops of the single-mesh kernels over x; each mesh takes its
+// round's workspace from its own serial, its halt code stops its part of
+// every launch, and the first round of a mesh (DevState.full) is a full
+// collection.  Semantic parameters come from each mesh's descriptor.
+struct GangDesc {
+  EngDesc e;
+  ScanJob js, jt, jf;  // the round's scans (subsegment and triangle winner bitmaps, fresh-slot counts)
+};
+__global__ void kg_collect(const GangDesc *G);
+__global__ void kg_pending(const GangDesc *G);
+__global__ void kg_gate(const GangDesc *G);
+__global__ void kg_gather_keys(const GangDesc *G);
+__global__ void kg_radix_hist(const GangDesc *G, int shift);
+__global__ void kg_radix_pick(const GangDesc *G, int shift);
+__global__ void kg_apply_cap(const GangDesc *G);
+__global__ void kg_locate(const GangDesc *G);
+__global__ void kg_prefilter(const GangDesc *G, int mode);
+template <int IS_CC>
+__global__ void kg_cavity(const GangDesc *G);
+__global__ void kg_cavity_big(const GangDesc *G, int phase);
+__global__ void kg_cavity_huge(const GangDesc *G, int phase);
+__global__ void kg_own(const GangDesc *G);
+__global__ void kg_dep(const GangDesc *G);
+__global__ void kg_scan_tiles(const GangDesc *G, int which);
+__global__ void kg_scan_sums(const GangDesc *G, int which);
+__global__ void kg_winners(const GangDesc *G);
+__global__ void kg_record(const GangDesc *G);
+__global__ void kg_write(const GangDesc *G);
+__global__ void kg_finish(const GangDesc *G);
+// Copies each mesh's DevState, running counters and first `rounds` history
+// records to out + y * stride_words (32-bit words), for one host read.
+__global__ void kg_status(const GangDesc *G, int rounds, int32_t *out, int stride_words);
+
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;
 constexpr int kHugeBlock = 1024;

@@ -546,8 +546,7 @@ __global__ void k_radix_hist(Work w, int shift) {
 // Picks the digit of the K-th largest key (keys are unique) and clears the
 // histogram for the next digit.  With no more than K keys the threshold is 0
 // and every key is kept.
-__global__ void k_radix_pick(Work w, int shift, int K) {
-  if (w.st->halt) return;
+__device__ __forceinline__ void radix_pick_part(const Work &w, int shift, int K) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int n = w.cnt->ncc + w.cnt->nmk;
     if (shift == 56) w.sel[2] = (uint64_t)K;
@@ -566,6 +565,11 @@ __global__ void k_radix_pick(Work w, int shift, int K) {
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 256; i += blockDim.x) w.rhist[i] = 0;
+}
+
+__global__ void k_radix_pick(Work w, int shift, int K) {
+  if (w.st->halt) return;
+  radix_pick_part(w, shift, K);
 }
 
 __device__ __forceinline__ void apply_part(const Work &w, const Lanes &L) {
@@ -2417,6 +2421,225 @@ __global__ __launch_bounds__(kEngBlock) void k_engine(const EngDesc *descs, int 
     engine_mesh(descs[i], lds, round_limit);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Round-boundary batching: the round's phases for a set of meshes, one
+// launch each (gridDim.y = meshes).  The bodies are the single-mesh phases;
+// each workgroup copies its mesh's descriptor (mesh arrays and the round's
+// workspace, chosen by the mesh's own serial) into registers first.
+// ---------------------------------------------------------------------------
+#define GANG_MESH                                           \
+  const GangDesc &g_ = G[blockIdx.y];                       \
+  const int par_ = g_.e.w[0].st->serial & 1;                \
+  const DevMesh m = g_.e.m;                                 \
+  const Work w = g_.e.w[par_];
+
+__global__ void kg_collect(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt) return;
+  if (w.st->full) {
+    scan_part(m, w, g_.e.B2, g_.e.pm, grid_lanes());
+  } else {
+    carry_part(w, grid_lanes());
+    dirty_part(m, w, g_.e.B2, g_.e.pm, grid_lanes());
+  }
+}
+
+__global__ void kg_pending(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt || w.st->full) return;
+  pending_part(m, w, grid_lanes());
+}
+
+__global__ void kg_gate(const GangDesc *G) {
+  GANG_MESH
+  (void)m;
+  (void)gate_part(w, g_.e.max_rounds);
+}
+
+__global__ void kg_gather_keys(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt || g_.e.K <= 0) return;
+  gather_part(m, w, g_.e.pm, grid_lanes());
+}
+
+__global__ void kg_radix_hist(const GangDesc *G, int shift) {
+  __shared__ int h[256];
+  GANG_MESH
+  (void)m;
+  if (w.st->halt || g_.e.K <= 0) return;
+  const int n = w.cnt->ncc + w.cnt->nmk;
+  const uint64_t prefix = w.sel[0], pmask = w.sel[1];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    uint64_t k = w.keys[c];
+    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (h[i]) atomicAdd(&w.rhist[i], h[i]);
+}
+
+__global__ void kg_radix_pick(const GangDesc *G, int shift) {
+  GANG_MESH
+  (void)m;
+  if (w.st->halt || g_.e.K <= 0) return;
+  radix_pick_part(w, shift, g_.e.K);
+}
+
+__global__ void kg_apply_cap(const GangDesc *G) {
+  GANG_MESH
+  (void)m;
+  if (w.st->halt || g_.e.K <= 0) return;
+  apply_part(w, grid_lanes());
+}
+
+__global__ void kg_locate(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt) return;
+  locate_part(m, w, grid_lanes());
+}
+
+__global__ __launch_bounds__(kPreBlock) void kg_prefilter(const GangDesc *G, int mode) {
+  __shared__ int32_t lds[kApproxMax * kPreBlock];
+  GANG_MESH
+  if (w.st->halt) return;
+  if (mode < 3 ? !g_.e.f1 : g_.e.approx_n <= 0) return;
+  prefilter_part(m, w, mode, mode < 3 ? 0 : g_.e.approx_n, lds, grid_lanes());
+}
+
+template <int IS_CC>
+__global__ __launch_bounds__(kCavBlock, 4) void kg_cavity(const GangDesc *G) {
+  __shared__ int32_t lds[kCap * kCavBlock];
+  GANG_MESH
+  if (w.st->halt) return;
+  cavity_part(m, w, IS_CC, lds, kCavBlock, kCap, grid_lanes());
+}
+template __global__ void kg_cavity<0>(const GangDesc *G);
+template __global__ void kg_cavity<1>(const GangDesc *G);
+
+__global__ __launch_bounds__(kBigBlock) void kg_cavity_big(const GangDesc *G, int phase) {
+  __shared__ BigShared sh;
+  GANG_MESH
+  if (w.st->halt) return;
+  int nbig = min(w.cnt->nbig, w.big_cap);
+  for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+    int ref = w.big[b];
+    int is_cc = (ref & 0x80000000) ? 0 : 1;
+    if (is_cc != (phase == 0 ? 1 : 0)) continue;
+    big_one(m, w, sh, b);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kHugeBlock) void kg_cavity_huge(const GangDesc *G, int phase) {
+  __shared__ BigShared sh;
+  GANG_MESH
+  if (w.st->halt || w.cnt->nhuge == 0) return;
+  int nbig = min(w.cnt->nbig, w.big_cap);
+  for (int b = 0; b < nbig; b++) {
+    int ref = w.big[b];
+    int is_cc = (ref & 0x80000000) ? 0 : 1;
+    if (is_cc != (phase == 0 ? 1 : 0)) continue;
+    huge_one(m, w, sh, b);
+  }
+}
+
+__global__ void kg_own(const GangDesc *G) {
+  GANG_MESH
+  (void)m;
+  if (w.st->halt) return;
+  own_part(w, grid_lanes());
+}
+
+__global__ void kg_dep(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt) return;
+  dep_part(m, w, grid_lanes());
+}
+
+// which = 0: the two winner bitmaps; 1: the fresh-slot counts.
+__global__ __launch_bounds__(kScanBlock) void kg_scan_tiles(const GangDesc *G, int which) {
+  const GangDesc &g = G[blockIdx.y];
+  if (g.e.w[0].st->halt) return;
+  const ScanJob a = which == 0 ? g.js : g.jf;
+  const ScanJob b = which == 0 ? g.jt : ScanJob{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+  const int na = *a.n_dev, nb = b.in ? *b.n_dev : 0;
+  const int ta = (na + kScanTile - 1) / kScanTile, tb = (nb + kScanTile - 1) / kScanTile;
+  for (int tile = blockIdx.x; tile < ta + tb; tile += gridDim.x) {
+    if (tile < ta) scan_tile(a, na, tile);
+    else scan_tile(b, nb, tile - ta);
+  }
+}
+
+// Launched with gridDim.x = 2 (both jobs of which = 0; one of which = 1).
+__global__ __launch_bounds__(kScanBlock) void kg_scan_sums(const GangDesc *G, int which) {
+  __shared__ int s_total;
+  const GangDesc &g = G[blockIdx.y];
+  if (g.e.w[0].st->halt) return;
+  if (which == 1 && blockIdx.x != 0) return;
+  const ScanJob j = which == 1 ? g.jf : (blockIdx.x == 0 ? g.js : g.jt);
+  const int ntiles = (*j.n_dev + kScanTile - 1) / kScanTile;
+  int carry = 0;
+  for (int start = 0; start < ntiles; start += kScanBlock) {
+    int idx = start + threadIdx.x;
+    int x = idx < ntiles ? j.tiles[idx] : 0;
+    int e = block_excl_scan(x, &s_total);
+    if (idx < ntiles) j.tiles[idx] = e + carry;
+    carry += s_total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *j.total = carry;
+}
+
+__global__ void kg_winners(const GangDesc *G) {
+  GANG_MESH
+  (void)m;
+  if (w.st->halt) return;
+  winners_part(w, grid_lanes());
+}
+
+__global__ void kg_record(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt) return;
+  record_part(m, w, grid_lanes());
+}
+
+__global__ void kg_write(const GangDesc *G) {
+  GANG_MESH
+  if (w.st->halt) return;
+  write_part(m, w, grid_lanes());
+}
+
+__global__ void kg_finish(const GangDesc *G) {
+  __shared__ int s_last;
+  GANG_MESH
+  if (w.st->halt) return;
+  finish_part(m, w, grid_lanes());
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&w.st->done_blocks, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) w.st->done_blocks = 0;
+  round_end(w);
+}
+
+__global__ void kg_status(const GangDesc *G, int rounds, int32_t *out, int stride_words) {
+  const GangDesc &g = G[blockIdx.y];
+  const Work &w = g.e.w[0];
+  int32_t *o = out + (size_t)blockIdx.y * stride_words;
+  const int ns = (int)(sizeof(DevState) / 4), nc = (int)(sizeof(DevCounters) / 4);
+  const int32_t *st = (const int32_t *)w.st, *cn = (const int32_t *)w.cnt, *hi = (const int32_t *)w.hist;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) o[i] = st[i];
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) o[ns + i] = cn[i];
+  for (int i = threadIdx.x; i < rounds * nc; i += blockDim.x) o[ns + nc + i] = hi[i];
+}
+#undef GANG_MESH
 
 // ---------------------------------------------------------------------------
 // Measurement: 64-bit atomicMax at random slots of a table in device memory,

@@ -122,6 +122,7 @@ def load() -> C.CDLL:
         "gdp_server_wait": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
         "gdp_server_destroy": (None, [_VP]),
         "gdp_server_engine_jobs": (S, [_VP, C.c_int32]),
+        "gdp_server_mode": (S, [_VP, C.c_int32]),
         "gdp_mesh_device_views": (S, [_VP, C.POINTER(gdp_device_views)]),
         "gdp_predicates_eval": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.POINTER(C.c_int64)]),
         "gdp_bench_atomic_max": (S, [_VP, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
@@ -142,7 +143,7 @@ def exported_symbols() -> list[str]:
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
             "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy", "gdp_mesh_device_views",
-            "gdp_predicates_eval", "gdp_bench_atomic_max", "gdp_mesh_quality_noalloc"]
+            "gdp_predicates_eval", "gdp_bench_atomic_max", "gdp_mesh_quality_noalloc", "gdp_server_mode"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -427,10 +428,13 @@ class Server:
     """Serving form: jobs arrive while others run; each finished job yields a
     device-resident Mesh."""
 
-    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, engine_max_vertices: int | None = None):
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, engine_max_vertices: int | None = None,
+                 mode: int = 0):
         self.ctx = ctx
         self._h = _VP()
         ctx.check(load().gdp_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(self._h)))
+        if mode:
+            self.ctx.check(load().gdp_server_mode(self._h, int(mode)))
         if engine_max_vertices is not None:
             self.engine_jobs(engine_max_vertices)
 

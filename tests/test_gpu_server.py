@@ -22,14 +22,17 @@ def _jobs(count, seed, n_min=200, n_max=3000):
     return workloads.batch_config3(count, seed=seed, n_min=n_min, n_max=n_max)
 
 
-ENGINE_PATHS = {"slots": 0, "batched": 1 << 30, "split": 1500}
+# shared rounds (the default), a stream per slot, every job in the batched
+# single-workgroup engine launches, and small jobs there with the rest shared
+PATHS = {"shared": dict(mode=0, engine_max_vertices=0), "slots": dict(mode=1, engine_max_vertices=0),
+         "batched": dict(mode=0, engine_max_vertices=1 << 30), "split": dict(mode=0, engine_max_vertices=1500)}
 
 
-@pytest.mark.parametrize("path", list(ENGINE_PATHS))
+@pytest.mark.parametrize("path", list(PATHS))
 def test_server_matches_oracle(ctx, path):
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(20, seed=21)
-    srv = gdp2d.Server(ctx, 2 << 30, 8, engine_max_vertices=ENGINE_PATHS[path])
+    srv = gdp2d.Server(ctx, 2 << 30, 8, **PATHS[path])
     ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     print(f"[server] {len(ids)} jobs submitted", flush=True)
     for p, j in zip(ps, ids):
@@ -42,7 +45,7 @@ def test_server_matches_oracle(ctx, path):
     srv.close()
 
 
-@pytest.mark.parametrize("path", list(ENGINE_PATHS))
+@pytest.mark.parametrize("path", list(PATHS))
 def test_server_alone_equals_mix(ctx, path):
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(30, seed=22, n_max=8000)
@@ -50,7 +53,7 @@ def test_server_alone_equals_mix(ctx, path):
     alone_srv = gdp2d.Server(ctx, 1 << 30, 4, engine_max_vertices=0)
     m_alone, rc, _ = alone_srv.wait(alone_srv.submit(x.xy, x.seg, x.ratio_bound_sq))
     assert rc == 0
-    mix = gdp2d.Server(ctx, 4 << 30, 12, engine_max_vertices=ENGINE_PATHS[path])
+    mix = gdp2d.Server(ctx, 4 << 30, 12, **PATHS[path])
     ids = [mix.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     got = [mix.wait(j) for j in ids]
     assert all(rc == 0 for _, rc, _ in got)
@@ -64,12 +67,12 @@ def test_server_alone_equals_mix(ctx, path):
     alone_srv.close()
 
 
-@pytest.mark.parametrize("path", ["slots", "batched"])
+@pytest.mark.parametrize("path", ["shared", "slots", "batched"])
 def test_server_tight_budget_and_slots(ctx, path):
     """Room for about one job at a time: jobs wait for room, all finish."""
     from paper_2007_00324_amd import gdp2d
     ps = _jobs(8, seed=23, n_min=1000, n_max=2000)
-    srv = gdp2d.Server(ctx, 8 << 20, 2, engine_max_vertices=ENGINE_PATHS[path])
+    srv = gdp2d.Server(ctx, 8 << 20, 2, **PATHS[path])
     ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
     for p, j in zip(ps, ids):
         m, rc, _ = srv.wait(j)
@@ -106,3 +109,45 @@ def test_server_prepared_job_and_close(ctx):
         small.prepare(big.xy, big.seg, 2.0)
     small.close()
     del j2
+
+
+@pytest.mark.parametrize("kw", [dict(cand_cap_K=5), dict(max_rounds=3), dict(prefilter_f1=1, cavity_approx_n=2),
+                                dict(encroach_mode=1, max_edge_len_sq=0.004)])
+def test_shared_rounds_options_match_oracle(ctx, kw):
+    """Semantic options per job in the shared rounds (each job's own
+    parameters in its descriptor), mixed with default jobs."""
+    from paper_2007_00324_amd import gdp2d
+    ps = _jobs(10, seed=25, n_min=300, n_max=4000)
+    srv = gdp2d.Server(ctx, 2 << 30, 6)
+    ids = []
+    for i, p in enumerate(ps):
+        opt = kw if i % 2 == 0 else {}
+        ids.append((p, opt, srv.submit(p.xy, p.seg, p.ratio_bound_sq, gdp2d.make_params(**opt))))
+    for p, opt, j in ids:
+        m, rc, _ = srv.wait(j)
+        om, orc = oracle_run(p, **opt)
+        assert rc == orc, (p.name, rc, orc)
+        assert not diff_arrays(om.arrays(), m.arrays()), (p.name, opt)
+    srv.close()
+
+
+def test_shared_rounds_large_cavity_and_growth(ctx):
+    """A polygon of 8,192 rounded cocircular vertices (a cavity far beyond a
+    workgroup's local list) beside ordinary jobs, in regions sized for the
+    inputs: the shared rounds finish the large cavity in device memory and
+    grow the jobs that outgrow their regions."""
+    from paper_2007_00324_amd import gdp2d
+    circle = workloads.scaled_config2(1, 8192, 0, seed=7, r_lo=0.40, r_hi=0.45)
+    dense = workloads.random_small(27, 300, 15)  # with l = 0.01: ~50 times its input vertices
+    ps = [circle, dense] + _jobs(5, seed=26, n_min=2000, n_max=20000)
+    opts = [dict(cand_cap_K=8, max_rounds=3), dict(max_edge_len_sq=1e-4)] + [{}] * 5
+    srv = gdp2d.Server(ctx, 2 << 30, 6)
+    ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq, gdp2d.make_params(**o)) for p, o in zip(ps, opts)]
+    for p, o, j in zip(ps, opts, ids):
+        m, rc, _ = srv.wait(j)
+        om, orc = oracle_run(p, **o)
+        assert rc == orc, (p.name, rc, orc)
+        assert not diff_arrays(om.arrays(), m.arrays()), p.name
+        if p is circle:
+            assert sum(r["n_huge_cavities"] for r in m.round_stats()) >= 1
+    srv.close()
