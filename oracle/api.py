@@ -29,13 +29,13 @@ class _Mesh(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("cand_cap_K", C.c_int32), ("priority_mode", C.c_int32), ("max_rounds", C.c_int32),
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("encroach_mode", C.c_int32),
-                ("split_mode", C.c_int32), ("max_edge_len_sq", C.c_double)]
+                ("split_mode", C.c_int32), ("max_edge_len_sq", C.c_double), ("insert_mode", C.c_int32)]
 
 
 STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coincident",
                "n_enc_reject", "n_mid_cand", "n_unsplittable", "n_fan_invalid", "n_lost_mark",
                "n_dep_drop", "n_ins_mid", "n_ins_cc", "cav_tri_total", "cav_max", "walk_steps",
-               "n_f1_drop", "n_f2_drop"]
+               "n_f1_drop", "n_f2_drop", "n_ff_points", "n_ff_iters"]
 
 
 class _Stats(C.Structure):
@@ -284,10 +284,10 @@ def ruppert(mesh: OracleMesh, ratio_bound_sq: float, max_insertions: int = 0) ->
 def refine(mesh: OracleMesh, ratio_bound_sq: float, cand_cap_K: int = 0, priority_mode: int = 0,
            max_rounds: int = 0, stats_cap: int = 1 << 16, raise_on_error: bool = True,
            prefilter_f1: int = 0, cavity_approx_n: int = 0, encroach_mode: int = 0,
-           max_edge_len_sq: float = 0.0, split_mode: int = 0) -> int:
+           max_edge_len_sq: float = 0.0, split_mode: int = 0, insert_mode: int = 0) -> int:
     lib = load()
     prm = _Params(cand_cap_K, priority_mode, max_rounds, prefilter_f1, cavity_approx_n, encroach_mode,
-                  split_mode, float(max_edge_len_sq))
+                  split_mode, float(max_edge_len_sq), insert_mode)
     st = (_Stats * stats_cap)()
     ns = C.c_int32(0)
     err = C.create_string_buffer(256)

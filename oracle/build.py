@@ -12,7 +12,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_exact.c", "orc_cdt.c", "orc_refine.c", "orc_check.c", "orc_ruppert.c"]
+SOURCES = ["orc_exact.c", "orc_cdt.c", "orc_refine.c", "orc_ff.c", "orc_check.c", "orc_ruppert.c"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

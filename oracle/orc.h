@@ -60,7 +60,11 @@ typedef struct orc_mesh {
 
 typedef struct orc_params {
   int32_t cand_cap_K;     /* 0 = unlimited; else keep the K largest keys per round */
-  int32_t priority_mode;  /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
+  int32_t priority_mode;  /* 0: class|q(measure)|perm32(id); 1: class|perm32(id);
+                             2: as 0 for subsegments, and for triangles
+                             q(measure) reduced to 19 bits | first two vertex
+                             ids of the triangle (smallest first), 22 bits
+                             each: a key that does not depend on the slot */
   int32_t max_rounds;     /* stop after this many rounds (ORC_E_NOTERM if work left) */
   int32_t prefilter_f1;   /* 1: keep one circumcenter per located triangle (max key) */
   int32_t cavity_approx_n;/* n > 0: drop circumcenters that lose a mark on the first
@@ -70,6 +74,9 @@ typedef struct orc_params {
                              vertices (see orc_midpoint) */
   double max_edge_len_sq; /* 0 = off; else a triangle with an edge longer than l
                              (squared length > l^2) is bad as well */
+  int32_t insert_mode;    /* 0: cavities, marks and the dependency test (Section 5.1);
+                             1: Flip-Flop (Section 4.3 Line 8, see orc_ff.c);
+                             needs priority_mode 2 */
 } orc_params;
 
 typedef struct orc_round_stats {
@@ -78,6 +85,7 @@ typedef struct orc_round_stats {
   int64_t n_fan_invalid, n_lost_mark, n_dep_drop, n_ins_mid, n_ins_cc;
   int64_t cav_tri_total, cav_max, walk_steps;
   int64_t n_f1_drop, n_f2_drop;
+  int64_t n_ff_points, n_ff_iters; /* Flip-Flop: points added in Line 8, CDTs examined */
 } orc_round_stats;
 
 /* Builds the canonical CDT of the PSLG.  xy: 2*nv doubles; seg: 2*ns vertex ids.

@@ -451,7 +451,10 @@ void orc_circumcenter(const orc_mesh *m, int32_t t, double ratio_bound_sq, doubl
     q = 0;
   }
   if (priority_mode == 1) q = 0;
-  *key = (q << 32) | (uint64_t)orc_perm32((uint32_t)t);
+  if (priority_mode == 2)
+    *key = ((q >> 12) << 44) | ((uint64_t)ia << 22) | (uint64_t)ib;
+  else
+    *key = (q << 32) | (uint64_t)orc_perm32((uint32_t)t);
 }
 
 /* Encroachment of subsegment ab by p (Section 4.1: inside the diametric

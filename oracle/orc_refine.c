@@ -41,6 +41,7 @@
  *   R11          pending flags and the round counter.
  */
 #include "orc.h"
+#include "orc_ff.h"
 
 #include <math.h>
 #include <stdio.h>
@@ -306,6 +307,11 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
   }
   for (int32_t t = 0; t < nT; t++) stamp[t] = -1;
   for (int64_t k = 0; k < 2 * (int64_t)nS; k++) sadj[k] = -1;
+  if (pm == 2 && nV >= (1 << 22)) {
+    set_err(err, errlen, "priority mode 2 keys hold vertex ids below 2^22");
+    rc = ORC_E_INPUT;
+    goto out;
+  }
 
   /* ---- R1: collect ---- */
   for (int32_t k = 0; k < nS; k++) enc[k] = m->spend[k] ? 1 : 0;
@@ -458,6 +464,13 @@ static int one_round(orc_mesh *m, double B2, const orc_params *prm, orc_round_st
     }
     for (int32_t t = 0; t < nT; t++)
       if (tloc[t] == -2) tloc[t] = -1;
+  }
+
+  /* ---- Line 8 by Flip-Flop (orc_ff.c) in place of R5-R10 ---- */
+  if (prm->insert_mode == 1) {
+    rc = orc_ff_round(m, prm, tloc, tpx, tpy, tkey, mflag, sadj, st, err, errlen);
+    if (rc == 0) m->rounds++;
+    goto out;
   }
 
   /* ---- R5: circumcenter cavities ---- */
@@ -698,7 +711,8 @@ int orc_refine(orc_mesh *m, double B2, const orc_params *p, orc_round_stats *sta
   if (n_stats) *n_stats = 0;
   if (!m || !p || !(B2 > 0.0) || !isfinite(B2)) { set_err(err, errlen, "bad arguments"); return ORC_E_ARG; }
   if ((p->prefilter_f1 != 0 && p->prefilter_f1 != 1) || p->cavity_approx_n < 0 || p->cand_cap_K < 0 ||
-      (p->priority_mode != 0 && p->priority_mode != 1) || (p->encroach_mode != 0 && p->encroach_mode != 1) ||
+      p->priority_mode < 0 || p->priority_mode > 2 || (p->encroach_mode != 0 && p->encroach_mode != 1) ||
+      (p->insert_mode != 0 && p->insert_mode != 1) || (p->insert_mode == 1 && p->priority_mode != 2) ||
       (p->split_mode != 0 && p->split_mode != 1) ||
       !(p->max_edge_len_sq >= 0.0) || !isfinite(p->max_edge_len_sq)) {
     set_err(err, errlen, "unsupported parameter");
@@ -706,6 +720,11 @@ int orc_refine(orc_mesh *m, double B2, const orc_params *p, orc_round_stats *sta
   }
   int32_t max_rounds = p->max_rounds > 0 ? p->max_rounds : (1 << 20);
   int32_t ns = 0;
+  if (p->insert_mode == 1) {
+    /* Flip-Flop rounds keep the canonical CDT (see orc_ff.c) */
+    int r = orc_ff_canonical(m, err, errlen);
+    if (r) return r;
+  }
   for (;;) {
     orc_round_stats rs;
     int only_check = m->rounds >= max_rounds;
