@@ -59,7 +59,82 @@ typedef struct {
   int32_t cls;   /* 1 midpoint, 0 circumcenter */
   int32_t id;    /* subsegment k, or the bad triangle's slot */
   int32_t c0, c1; /* claimed triangles (c1 = -1: one) */
+  int32_t edge;   /* circumcenter on edge `edge` of c0 (-1: inside) */
 } ffpt;
+
+/* The points S of the last Flip-Flop round, in key order, with what Line 6
+   decided for them (kept for tests that drive other implementations of
+   Line 8 from the same S). */
+static struct {
+  int64_t n, cap;
+  double *xy;
+  int32_t *cls, *id, *c0, *c1, *edge;
+  uint64_t *key;
+  int64_t nflag, capflag;
+  int32_t *flagged; /* subsegments flagged for their midpoint when Line 8 starts */
+} g_last;
+
+static void record_last(const ffpt *pts, int64_t np, const int32_t *edge_of) {
+  if (np > g_last.cap) {
+    int64_t cap = np + 64;
+    double *xy = realloc(g_last.xy, sizeof(double) * 2 * (size_t)cap);
+    if (xy) g_last.xy = xy;
+    int32_t *a = realloc(g_last.cls, sizeof(int32_t) * (size_t)cap);
+    if (a) g_last.cls = a;
+    int32_t *b = realloc(g_last.id, sizeof(int32_t) * (size_t)cap);
+    if (b) g_last.id = b;
+    int32_t *c = realloc(g_last.c0, sizeof(int32_t) * (size_t)cap);
+    if (c) g_last.c0 = c;
+    int32_t *d = realloc(g_last.c1, sizeof(int32_t) * (size_t)cap);
+    if (d) g_last.c1 = d;
+    int32_t *e = realloc(g_last.edge, sizeof(int32_t) * (size_t)cap);
+    if (e) g_last.edge = e;
+    uint64_t *k = realloc(g_last.key, sizeof(uint64_t) * (size_t)cap);
+    if (k) g_last.key = k;
+    if (!xy || !a || !b || !c || !d || !e || !k) { g_last.n = 0; return; }
+    g_last.cap = cap;
+  }
+  for (int64_t i = 0; i < np; i++) {
+    g_last.xy[2 * i] = pts[i].x; g_last.xy[2 * i + 1] = pts[i].y;
+    g_last.cls[i] = pts[i].cls; g_last.id[i] = pts[i].id;
+    g_last.c0[i] = pts[i].c0; g_last.c1[i] = pts[i].c1;
+    g_last.edge[i] = edge_of[i];
+    g_last.key[i] = pts[i].key;
+  }
+  g_last.n = np;
+}
+
+static void record_flagged(const uint8_t *mflag, int32_t nS) {
+  int64_t n = 0;
+  for (int32_t k = 0; k < nS; k++) n += mflag[k] != 0;
+  if (n > g_last.capflag) {
+    int32_t *a = realloc(g_last.flagged, sizeof(int32_t) * (size_t)(n + 64));
+    if (!a) { g_last.nflag = 0; return; }
+    g_last.flagged = a;
+    g_last.capflag = n + 64;
+  }
+  n = 0;
+  for (int32_t k = 0; k < nS; k++)
+    if (mflag[k]) g_last.flagged[n++] = k;
+  g_last.nflag = n;
+}
+
+int64_t orc_ff_last_flagged(int64_t cap, int32_t *ks) {
+  int64_t n = g_last.nflag < cap ? g_last.nflag : cap;
+  for (int64_t i = 0; i < n; i++) ks[i] = g_last.flagged[i];
+  return g_last.nflag;
+}
+
+int64_t orc_ff_last_points(int64_t cap, double *xy, int32_t *cls, int32_t *id, int32_t *c0, int32_t *c1,
+                           int32_t *edge, uint64_t *key) {
+  int64_t n = g_last.n < cap ? g_last.n : cap;
+  for (int64_t i = 0; i < n; i++) {
+    xy[2 * i] = g_last.xy[2 * i]; xy[2 * i + 1] = g_last.xy[2 * i + 1];
+    cls[i] = g_last.cls[i]; id[i] = g_last.id[i]; c0[i] = g_last.c0[i]; c1[i] = g_last.c1[i];
+    edge[i] = g_last.edge[i]; key[i] = g_last.key[i];
+  }
+  return g_last.n;
+}
 
 static void ff_err(char *err, int32_t errlen, const char *msg) {
   if (err && errlen > 0) {
@@ -142,7 +217,7 @@ int orc_ff_round(orc_mesh *m, const orc_params *prm, const int32_t *tloc, const 
     }
     int e = s[0] == 0 ? 0 : (s[1] == 0 ? 1 : (s[2] == 0 ? 2 : -1));
     ffpt *q = &pts[np];
-    q->key = tkey[t]; q->x = p[0]; q->y = p[1]; q->cls = 0; q->id = t; q->c0 = loc; q->c1 = -1;
+    q->key = tkey[t]; q->x = p[0]; q->y = p[1]; q->cls = 0; q->id = t; q->c0 = loc; q->c1 = -1; q->edge = e;
     if (e >= 0) {
       int32_t k = m->ts[3 * loc + e];
       if (k >= 0) {
@@ -166,7 +241,7 @@ int orc_ff_round(orc_mesh *m, const orc_params *prm, const int32_t *tloc, const 
       continue;
     }
     ffpt *q = &pts[np++];
-    q->key = key; q->x = mx; q->y = my; q->cls = 1; q->id = k;
+    q->key = key; q->x = mx; q->y = my; q->cls = 1; q->id = k; q->edge = -1;
     q->c0 = sadj[2 * k] >= 0 ? sadj[2 * k] / 3 : -1;
     q->c1 = sadj[2 * k + 1] >= 0 ? sadj[2 * k + 1] / 3 : -1;
     if (q->c0 < 0) { q->c0 = q->c1; q->c1 = -1; }
@@ -187,6 +262,15 @@ int orc_ff_round(orc_mesh *m, const orc_params *prm, const int32_t *tloc, const 
   }
   qsort(pts, (size_t)np, sizeof(ffpt), cmp_key_desc);
   if (st) st->n_ff_points = np;
+  {
+    int32_t *edge_of = malloc(sizeof(int32_t) * ((size_t)np + 1));
+    if (edge_of) {
+      for (int64_t i = 0; i < np; i++) edge_of[i] = pts[i].edge;
+      record_last(pts, np, edge_of);
+      free(edge_of);
+    }
+    record_flagged(mflag, nS);
+  }
 
   /* ---- Line 8: the CDT of the old vertices and S, until no point of S is
      redundant ---- */

@@ -19,4 +19,14 @@ int orc_ff_round(orc_mesh *m, const orc_params *prm, const int32_t *tloc, const 
 /* Replaces the triangles by the canonical CDT of the current vertices and
    subsegments (the state the Flip-Flop rounds keep). */
 int orc_ff_canonical(orc_mesh *m, char *err, int32_t errlen);
+
+/* The points S (after Line 6, in key order) of the last Flip-Flop round run
+   in this process: coordinates, class (1 midpoint), subsegment or bad
+   triangle, claimed triangles (slots before the round), edge of c0 a
+   circumcenter lies on (-1 inside), key.  Copies up to cap; returns the
+   count.  For tests only. */
+int64_t orc_ff_last_points(int64_t cap, double *xy, int32_t *cls, int32_t *id, int32_t *c0, int32_t *c1,
+                           int32_t *edge, uint64_t *key);
+/* ... and the subsegments flagged for their midpoint when its Line 8 began. */
+int64_t orc_ff_last_flagged(int64_t cap, int32_t *ks);
 #endif

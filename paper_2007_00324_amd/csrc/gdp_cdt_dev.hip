@@ -133,39 +133,12 @@ __device__ __forceinline__ int orient_ids(const double2 *P, int a, int b, int c)
   return orient2d(A.x, A.y, B.x, B.y, C.x, C.y);
 }
 
-// incircle with the symbolic perturbation: on an exact tie the cofactors of
-// the lifted determinant (+o(b,c,d), -o(a,c,d), +o(a,b,d), -o(a,b,c), one per
-// point) decide, in the order of increasing vertex id; equal ids (a chain
-// vertex repeated around a slit) keep their argument order.
+// incircle with the symbolic perturbation of the lifting map (gdp_exact.h)
+// on points given by their ids; equal ids (a chain vertex repeated around a
+// slit) keep their argument order.
 __device__ int incircle_sos(const double2 *P, int a, int b, int c, int d) {
   const double2 A = P[a], B = P[b], C = P[c], D = P[d];
-  int s = incircle(A.x, A.y, B.x, B.y, C.x, C.y, D.x, D.y);
-  if (s != 0) return s;
-  auto id = [&](int pos) { return pos == 0 ? a : (pos == 1 ? b : (pos == 2 ? c : d)); };
-  // stable insertion sort of the four argument positions by id
-  int o0 = 0, o1 = 1, o2 = 2, o3 = 3, x;
-  if (id(o1) < id(o0)) { x = o0; o0 = o1; o1 = x; }
-  if (id(o2) < id(o1)) {
-    x = o1; o1 = o2; o2 = x;
-    if (id(o1) < id(o0)) { x = o0; o0 = o1; o1 = x; }
-  }
-  if (id(o3) < id(o2)) {
-    x = o2; o2 = o3; o3 = x;
-    if (id(o2) < id(o1)) {
-      x = o1; o1 = o2; o2 = x;
-      if (id(o1) < id(o0)) { x = o0; o0 = o1; o1 = x; }
-    }
-  }
-  for (int r = 0; r < 4; r++) {
-    const int pos = r == 0 ? o0 : (r == 1 ? o1 : (r == 2 ? o2 : o3));
-    int cof;
-    if (pos == 0) cof = orient2d(B.x, B.y, C.x, C.y, D.x, D.y);
-    else if (pos == 1) cof = -orient2d(A.x, A.y, C.x, C.y, D.x, D.y);
-    else if (pos == 2) cof = orient2d(A.x, A.y, B.x, B.y, D.x, D.y);
-    else cof = -orient2d(A.x, A.y, B.x, B.y, C.x, C.y);
-    if (cof != 0) return cof;
-  }
-  return 0;
+  return gdp::incircle_sos(A.x, A.y, B.x, B.y, C.x, C.y, D.x, D.y, a, b, c, d);
 }
 
 __device__ __forceinline__ int eidx(const int4 &v, int u, int w) {

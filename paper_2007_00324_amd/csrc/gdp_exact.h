@@ -272,6 +272,42 @@ GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, doubl
   return incircle_exact_raw(ax, ay, bx, by, cx, cy, dx, dy, tl);
 }
 
+// incircle under the symbolic perturbation of the lifting map (Section 7's
+// simulation of simplicity): on an exact tie the cofactors of the lifted
+// determinant (+o(b,c,d), -o(a,c,d), +o(a,b,d), -o(a,b,c), one per point)
+// decide, taken in the order of increasing vertex id; equal ids keep their
+// argument order.  Nonzero for four distinct ids of points in general
+// position or on one circle.
+GDP_HD int incircle_sos(double ax, double ay, double bx, double by, double cx, double cy, double dx, double dy,
+                        int ia, int ib, int ic, int id, uint64_t *tl = nullptr) {
+  const int s = incircle(ax, ay, bx, by, cx, cy, dx, dy, tl);
+  if (s != 0) return s;
+  // argument positions ordered by id (a sorting network on scalars, so the
+  // tie path needs no indexed private array); equal ids keep argument order
+  int p0 = 0, p1 = 1, p2 = 2, p3 = 3;
+  int k0 = ia, k1 = ib, k2 = ic, k3 = id;
+#define GDP_SOS_SWAP(pa, ka, pb, kb) \
+  if (kb < ka) { int tp = pa; pa = pb; pb = tp; int tk = ka; ka = kb; kb = tk; }
+  GDP_SOS_SWAP(p0, k0, p1, k1)
+  GDP_SOS_SWAP(p2, k2, p3, k3)
+  GDP_SOS_SWAP(p1, k1, p2, k2)
+  GDP_SOS_SWAP(p0, k0, p1, k1)
+  GDP_SOS_SWAP(p2, k2, p3, k3)
+  GDP_SOS_SWAP(p1, k1, p2, k2)
+#undef GDP_SOS_SWAP
+  for (int r = 0; r < 4; r++) {
+    int cof;
+    switch (r == 0 ? p0 : (r == 1 ? p1 : (r == 2 ? p2 : p3))) {
+      case 0: cof = orient2d(bx, by, cx, cy, dx, dy, tl); break;
+      case 1: cof = -orient2d(ax, ay, cx, cy, dx, dy, tl); break;
+      case 2: cof = orient2d(ax, ay, bx, by, dx, dy, tl); break;
+      default: cof = -orient2d(ax, ay, bx, by, cx, cy, tl); break;
+    }
+    if (cof != 0) return cof;
+  }
+  return 0;
+}
+
 // indiametral > 0 iff c lies strictly inside the circle with diameter ab.
 GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
   double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
