@@ -168,6 +168,46 @@ def criteria_leg(ctx, init, work, p) -> dict:
             "modes": rows}
 
 
+def flipflop_leg(ctx, init, work, p) -> dict:
+    """Line 8 by Flip-Flop insertion (Section 4.3, with the slot-independent keys
+    of priority mode 2) against cavity insertion (default keys) on the same
+    resident initial CDT: device refine time (median of 3 after a warmup), time per
+    round, and points kept per point added (Flip-Flop adds every point of S
+    and takes the redundant ones out again; cavity insertion decides before it
+    writes)."""
+    from paper_2007_00324_amd import gdp2d
+    rows = []
+    n_in = init.info()["n_vertices"]
+    for name, kw in [("cavity", dict()), ("flipflop", dict(priority_mode=2, insert_mode=1))]:
+        prm = gdp2d.make_params(**kw)
+        ms = []
+        for rep in range(4):
+            work.assign_from(init)
+            gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)
+            if rep:
+                ms.append(work.last_refine_ms())
+        ms.sort()
+        info = work.info()
+        st = work.round_stats()
+        steiner = info["n_vertices"] - n_in
+        row = {"insertion": name, "refine_ms": ms[1], "rounds": info["rounds"],
+               "ms_per_round": ms[1] / max(1, info["rounds"]), "steiner_points": steiner,
+               "steiner_per_s": steiner / (ms[1] / 1000.0), "output_triangles": info["n_triangles"]}
+        if name == "flipflop":
+            added = sum(r["n_ff_points"] for r in st)
+            row.update({"points_added": added, "kept_per_added": steiner / max(1, added),
+                        "flips": sum(r["n_flips"] for r in st), "flip_passes": sum(r["n_flip_passes"] for r in st),
+                        "removals": sum(r["n_removals"] for r in st),
+                        "cdts_examined": sum(r["n_ff_iters"] for r in st)})
+        else:
+            cands = sum(r["n_kept_cc"] + r["n_mid_cand"] for r in st)
+            row.update({"candidates": cands, "kept_per_candidate": steiner / max(1, cands)})
+        log(f"flip-flop leg {name}: {ms[1]:.2f} ms, {info['rounds']} rounds, {steiner:,} Steiner points")
+        rows.append(row)
+    return {"workload": "the 1M-point PSLG above, same initial CDT", "timing": "device refine time, median of 3",
+            "rows": rows}
+
+
 def cdt_leg(ctx, init, p) -> dict:
     """Line 1 of Algorithm 1 on the GPU (gdp_mesh_create_device) against the host
     builder (gdp_mesh_create) on the benchmark PSLG: wall time from the PSLG in host
@@ -205,64 +245,152 @@ def cdt_leg(ctx, init, p) -> dict:
             "triangles": info["n_triangles"], "identical_to_host": identical}
 
 
-def ablation_leg(ctx, init, work, p) -> dict:
+ABLATION_SETTINGS = [
+    ("base", dict()),
+    ("K=65536", dict(cand_cap_K=65536)),
+    ("K=16384", dict(cand_cap_K=16384)),
+    ("F1", dict(prefilter_f1=1)),
+    ("F2_n=2", dict(cavity_approx_n=2)),
+    ("F2_n=4", dict(cavity_approx_n=4)),
+    ("F1+F2_n=4", dict(prefilter_f1=1, cavity_approx_n=4)),
+    ("no_single_workgroup_rounds", dict(tail_engine_max=-1)),
+]
+# Rule 3 (the cooperative path for large cavities) on the circles input, whose
+# circle interiors make cavities of hundreds of triangles: per-thread slices of
+# 12, 24 or 39 (the default) slots before a cavity goes cooperative.
+COOP_SETTINGS = [("coop_cap_39", dict(cavity_thread_cap=39)), ("coop_cap_24", dict(cavity_thread_cap=24)),
+                 ("coop_cap_12", dict(cavity_thread_cap=12))]
+ABLATION_TRAFFIC_FILE = os.path.join(HERE, "profiles", "ablation_traffic.md")
+
+
+def recorded_setting_traffic() -> dict:
+    """HBM bytes per refine of each ablation setting from the committed counter
+    summary, if the kernel sources still hash to the recorded value."""
+    try:
+        with open(ABLATION_TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return {}
+    out, sha = {}, None
+    for line in text.splitlines():
+        line = line.strip().strip("`")
+        if line.startswith("kernel_sources_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("setting_traffic:"):
+            name, val = line.split(":", 1)[1].split("=")
+            out[name.strip()] = float(val)
+    return out if sha == kernel_source_hash() else {}
+
+
+def pmc_sum(fetch_dir: str, write_dir: str, fetch_scale: float, write_scale: float,
+            match: str = r"gdp::(k|kf|kg)_") -> dict:
+    """HBM bytes of the refinement's own kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the
+    counter reads for a plain copy of known size."""
+    import csv
+    import glob
+    import re
+    mine = re.compile(match)
+    tot = {}
+    for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        kib = 0.0
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row.get("Counter_Name") == name and mine.search(row.get("Kernel_Name", "")):
+                        kib += float(row["Counter_Value"])
+        tot[name] = kib
+    b = tot["FETCH_SIZE"] * 1024 * fetch_scale + tot["WRITE_SIZE"] * 1024 * write_scale
+    return {"fetch_kib": tot["FETCH_SIZE"], "write_kib": tot["WRITE_SIZE"], "bytes": b}
+
+
+def ablation_leg(ctx, init, work, p, init2=None, p2=None) -> dict:
     """gDP2d's rules switched on and off on the 1M-point PSLG (the paper leaves this
-    study out for 2D).  Per setting: device refine time (median of 3), Steiner points,
-    rounds, and the Rule 2 quantities: alpha = insertions / candidates given to
-    threads (effective concurrency without a filter), beta = the same with it, and
-    l / L = the filter kernels' share of the profiled time.  Rule 2 predicts a gain
-    iff (L + l) / L < beta / alpha; the measured gain is the Steiner/s ratio."""
+    study out for 2D), and the cooperative path's capacity on the circles input.
+    Per setting: device refine time (median of 3), Steiner points, rounds, and the
+    Rule 2 quantities: alpha = insertions / candidates given to threads (effective
+    concurrency without a filter), beta = the same with it, and l / L = the filter
+    kernels' share of the profiled time.  Rule 2 predicts a gain iff
+    (L + l) / L < beta / alpha.  The extended prediction adds the fixed cost of a
+    round (c, the time of a round of the single-workgroup tail, which is all
+    latency): T = rounds * c + (T_base - rounds_base * c) * candidates / candidates_base
+    + l.  The measured gain is the Steiner/s ratio.  The waste ratio is the measured
+    HBM traffic of a refine (rocprofv3, per setting) over its algorithmic bytes."""
     from paper_2007_00324_amd import gdp2d
-    settings = [
-        ("base", dict()),
-        ("K=65536", dict(cand_cap_K=65536)),
-        ("K=16384", dict(cand_cap_K=16384)),
-        ("F1", dict(prefilter_f1=1)),
-        ("F2_n=2", dict(cavity_approx_n=2)),
-        ("F2_n=4", dict(cavity_approx_n=4)),
-        ("F1+F2_n=4", dict(prefilter_f1=1, cavity_approx_n=4)),
-        ("no_single_workgroup_rounds", dict(tail_engine_max=-1)),
-    ]
+    traffic = recorded_setting_traffic()
+    rows = []
+    for name, kw in ABLATION_SETTINGS:
+        rows.append(_ablation_row(ctx, init, work, p, name, kw, traffic))
+    base = rows[0]
+    # fixed cost of a round: the single-workgroup tail's time per round (pure latency)
+    c = base.get("tail_ms_per_round") or 0.0
+    for row in rows[1:]:
+        row["rule2_beta_over_alpha"] = row["concurrency_fraction"] / base["concurrency_fraction"]
+        row["rule2_latency_ratio"] = 1.0 + row["filter_share"]
+        row["rule2_predicts_gain"] = row["rule2_latency_ratio"] < row["rule2_beta_over_alpha"]
+        work_ms = max(base["refine_ms"] - base["rounds"] * c, 1e-9)
+        pred_ms = row["rounds"] * c + work_ms * row["candidates"] / max(base["candidates"], 1) + row["filter_ms"]
+        row["rule2_extended_predicted_gain"] = base["refine_ms"] / pred_ms
+        row["measured_gain"] = row["steiner_per_s"] / base["steiner_per_s"]
+        log(f"ablation {row['setting']}: gain {row['measured_gain']:.3f} (Rule 2 predicts {row['rule2_predicts_gain']}, "
+            f"extended {row['rule2_extended_predicted_gain']:.3f})")
+    out = {"workload": "the 1M-point PSLG above, same initial CDT", "timing": "device refine time, median of 3",
+           "round_fixed_cost_ms": c, "settings": rows}
+    if init2 is not None:
+        w2 = init2.clone()
+        coop = [_ablation_row(ctx, init2, w2, p2, name, kw, traffic) for name, kw in COOP_SETTINGS]
+        for row in coop[1:]:
+            row["measured_gain"] = row["steiner_per_s"] / coop[0]["steiner_per_s"]
+        out["cooperative_path"] = {"workload": f"{p2.name}: {p2.n_vertices:,} vertices / {p2.n_segments:,} segments "
+                                               "(512 closed 1000-gons + 100,000 free points)",
+                                   "settings": coop}
+    return out
+
+
+def _ablation_row(ctx, init, work, p, name, kw, traffic) -> dict:
+    from paper_2007_00324_amd import gdp2d
     filt_kernels = {"k_cap", "k_prefilter"}
     n_in = init.info()["n_vertices"]
-    rows = []
-    base = None
-    for name, kw in settings:
+    work.assign_from(init)
+    gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, gdp2d.make_params(profile_kernels=1, **kw))
+    profs = [k for k in work.kernel_profile() if k["launches"]]
+    prof = {k["name"]: k["total_ms"] for k in profs}
+    eng = next((k for k in profs if k["name"] == "k_engine"), None)
+    rs = work.round_stats()
+    tot = {k: sum(r[k] for r in rs) for k in rs[0]} if rs else {}
+    attempts = sum(r["n_kept_cc"] + r["n_kept_mid"] for r in rs)
+    useful = sum(r["n_ins_cc"] + r["n_ins_mid"] for r in rs)
+    big = sum(r["n_big_cavities"] for r in rs)
+    filt_ms = sum(v for k, v in prof.items() if k in filt_kernels)
+    tot_ms = sum(prof.values())
+    ms = []
+    prm = gdp2d.make_params(**kw)
+    for rep in range(4):
         work.assign_from(init)
-        gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, gdp2d.make_params(profile_kernels=1, **kw))
-        prof = {k["name"]: k["total_ms"] for k in work.kernel_profile() if k["launches"]}
-        rs = work.round_stats()
-        attempts = sum(r["n_kept_cc"] + r["n_kept_mid"] for r in rs)
-        useful = sum(r["n_ins_cc"] + r["n_ins_mid"] for r in rs)
-        big = sum(r["n_big_cavities"] for r in rs)
-        filt_ms = sum(v for k, v in prof.items() if k in filt_kernels)
-        tot_ms = sum(prof.values())
-        ms = []
-        prm = gdp2d.make_params(**kw)
-        for rep in range(4):
-            work.assign_from(init)
-            gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)
-            if rep:
-                ms.append(work.last_refine_ms())
-        ms.sort()
-        steiner = work.info()["n_vertices"] - n_in
-        row = {"setting": name, **kw, "refine_ms": ms[1], "steiner_points": steiner, "rounds": work.info()["rounds"],
-               "steiner_per_s": steiner / (ms[1] / 1000.0), "candidates": attempts, "insertions": useful,
-               "concurrency_fraction": useful / max(attempts, 1), "filter_ms": filt_ms,
-               "filter_share": filt_ms / max(tot_ms - filt_ms, 1e-9), "big_cavities": big}
-        if base is None:
-            base = row
-        else:
-            row["rule2_beta_over_alpha"] = row["concurrency_fraction"] / base["concurrency_fraction"]
-            row["rule2_latency_ratio"] = 1.0 + row["filter_share"]
-            row["rule2_predicts_gain"] = row["rule2_latency_ratio"] < row["rule2_beta_over_alpha"]
-            row["measured_gain"] = row["steiner_per_s"] / base["steiner_per_s"]
-        log(f"ablation {name}: {ms[1]:.2f} ms, {steiner:,} Steiner, {row['rounds']} rounds, "
-            f"alpha {row['concurrency_fraction']:.3f}, filter {filt_ms:.2f} ms"
-            + (f", gain {row['measured_gain']:.3f} (Rule 2 predicts {row['rule2_predicts_gain']})" if row is not base else ""))
-        rows.append(row)
-    return {"workload": "the 1M-point PSLG above, same initial CDT", "timing": "device refine time, median of 3",
-            "settings": rows}
+        gdp2d.gdp_mesh_refine(ctx, work, p.ratio_bound_sq, prm)
+        if rep:
+            ms.append(work.last_refine_ms())
+    ms.sort()
+    steiner = work.info()["n_vertices"] - n_in
+    alg = loop_alg_bytes(tot)
+    row = {"setting": name, **kw, "refine_ms": ms[1], "steiner_points": steiner, "rounds": work.info()["rounds"],
+           "steiner_per_s": steiner / (ms[1] / 1000.0), "candidates": attempts, "insertions": useful,
+           "concurrency_fraction": useful / max(attempts, 1), "filter_ms": filt_ms,
+           "filter_share": filt_ms / max(tot_ms - filt_ms, 1e-9), "big_cavities": big,
+           "alg_bytes": alg, "traffic_bytes": traffic.get(name),
+           "waste_ratio": (traffic[name] / alg) if name in traffic and alg else None}
+    if eng is not None:
+        tail_rounds = max(1, len([r for r in rs]) - (prof_rounds_grid(profs)))
+        row["tail_ms_per_round"] = eng["total_ms"] / tail_rounds
+    log(f"ablation {name}: {ms[1]:.2f} ms, {steiner:,} Steiner, {row['rounds']} rounds, "
+        f"alpha {row['concurrency_fraction']:.3f}, filter {filt_ms:.2f} ms, {big} cooperative cavities")
+    return row
+
+
+def prof_rounds_grid(profs) -> int:
+    """Rounds that ran on the grid kernels (one k_locate launch each)."""
+    loc = next((k for k in profs if k["name"] == "k_locate"), None)
+    return loc["launches"] if loc else 0
 
 
 def make_batch(count: int, workers: int):
@@ -284,7 +412,10 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     nv = sum(p.n_vertices for p in ps)
     inputs = [(p.xy, p.seg) for p in ps]
     bsq = [p.ratio_bound_sq for p in ps]
-    prm = gdp2d.make_params()
+    from paper_2007_00324_amd import tune_batch
+    table = tune_batch.load_table()
+    prm = tune_batch.tuned_params(table)
+    default_prm = gdp2d.make_params()
     gdp2d.gdp_refine_batch(ctx, inputs[:8], bsq[:8], prm)  # warm-up (code objects, scratch)
     t = time.perf_counter()
     meshes, st, dev_ms = gdp2d.gdp_refine_batch(ctx, inputs, bsq, prm)
@@ -292,8 +423,11 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     bad = sum(1 for s_ in st if s_ != 0)
     steiner = sum(m.info()["n_vertices"] - p.n_vertices for m, p in zip(meshes, ps) if m is not None)
     del meshes
-    log(f"batched: {count:,} jobs, device {dev_ms:.1f} ms, call {wall:.2f} s (host CDT, upload, download), "
-        f"{bad} not OK")
+    log(f"batched (tuned: engine up to {prm.batch_engine_max_v or 'all'} input vertices, shared rounds above): "
+        f"{count:,} jobs, device {dev_ms:.1f} ms, call {wall:.2f} s (host CDT, upload, download), {bad} not OK")
+    m2, st2, default_ms = gdp2d.gdp_refine_batch(ctx, inputs, bsq, default_prm)
+    del m2
+    log(f"batched (default: every mesh in the engine): device {default_ms:.1f} ms")
     sample = ps[::plain_every]
     plain_ms = 0.0
     for p in sample:
@@ -313,6 +447,10 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
         "steiner_points": steiner,
         "jobs_per_s": jobs_s,
         "device_ms": dev_ms,
+        "tuned": {"batch_engine_max_v": prm.batch_engine_max_v, "rounds_per_group": prm.rounds_per_sync,
+                  "table": "paper_2007_00324_amd/tuning/batch.json" if table else None},
+        "default_jobs_per_s": count / (default_ms / 1000.0),
+        "tuned_vs_default": default_ms / dev_ms,
         "jobs_per_s_with_host_cdt": count / wall,
         "plain_jobs_per_s": plain_jobs_s,
         "plain_sample": f"every {plain_every}th job ({len(sample)} jobs), each gdp_mesh_refine timed alone",
@@ -321,7 +459,7 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     }
 
 
-def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode):
+def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode, rounds=0):
     """One replay of the job set as a Poisson stream of rate lam (None: every
     job arrives at once); returns latencies (ms), the achieved rate and the
     count of failed jobs."""
@@ -330,7 +468,8 @@ def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode):
     import numpy as np
     from paper_2007_00324_amd import gdp2d
     n = len(jobs)
-    srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v, mode=mode)
+    srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v, mode=mode,
+                       rounds_per_group=rounds)
     with ThreadPoolExecutor(16) as ex:  # Line 1 of every job, in parallel, before the stream starts
         ids = list(ex.map(lambda p: srv.prepare(p.xy, p.seg, p.ratio_bound_sq), jobs))
     gaps = np.random.default_rng(7).exponential(1.0 / lam, size=n) if lam else np.zeros(n)
@@ -429,6 +568,7 @@ def main() -> int:
     ap.add_argument("--no-criteria", action="store_true", help="skip the lens / length-bound / theta legs")
     ap.add_argument("--no-ablation", action="store_true", help="skip the rule ablation leg")
     ap.add_argument("--no-cdt", action="store_true", help="skip the device initial-CDT leg")
+    ap.add_argument("--no-flipflop", action="store_true", help="skip the Flip-Flop insertion leg")
     ap.add_argument("--batch", type=int, default=4096, help="jobs of the batched form (0: skip)")
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
@@ -436,10 +576,20 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=str, default="0.25x,0.5x,0.9x,1.5x",
                     help="arrival rates, jobs/s, or fractions of the measured capacity (0.5x)")
     ap.add_argument("--serve-mode", type=int, default=0, help="0: shared rounds, 1: a stream per slot")
+    ap.add_argument("--only-setting", type=str, default="",
+                    help="run one refine of the named ablation setting (on its workload) and exit, for counters")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="only measure the serving capacity for slots:rounds pairs (e.g. 16:2,32:4) and exit")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-engine-max", type=int, default=None,
                     help="jobs up to this many input vertices run in batched launches (default: the library's)")
+    ap.add_argument("--pmc-sum", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM bytes of the refinement kernels in two rocprofv3 --pmc output folders")
+    ap.add_argument("--pmc-scale", nargs=2, type=float, default=(1.0, 1.0), metavar=("FETCH", "WRITE"),
+                    help="copy-calibrated scale factors for --pmc-sum")
+    ap.add_argument("--pmc-match", type=str, default=r"gdp::(k|kf|kg)_",
+                    help="kernel-name regex for --pmc-sum (copyBuffer for the copy calibration)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration) and exit")
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
@@ -449,6 +599,10 @@ def main() -> int:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the refinement loop of one PSLG runs on a "
               "single device, it would shard by instance or by spatial blocks.", file=sys.stderr)
         return 2
+    if args.pmc_sum:
+        r = pmc_sum(args.pmc_sum[0], args.pmc_sum[1], args.pmc_scale[0], args.pmc_scale[1], args.pmc_match)
+        print(json.dumps(r), flush=True)
+        return 0
 
     batch = make_batch(args.batch, args.workers) if args.batch > 0 and not args.calibrate_copy else None
     serve_jobs = None
@@ -471,6 +625,16 @@ def main() -> int:
     from paper_2007_00324_amd import gdp2d
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.serve_sweep:
+        ctx = gdp2d.Context(0)
+        rows = []
+        for pair in args.serve_sweep.split(","):
+            slots, rounds = (int(x) for x in pair.split(":"))
+            lat, cap, bad = serve_stream(ctx, serve_jobs, None, args.serve_budget_gb, slots, 0, 0, rounds)
+            log(f"serving sweep: {slots} slots, {rounds} rounds per group: {cap:.1f} jobs/s, {bad} not OK")
+            rows.append({"slots": slots, "rounds_per_group": rounds, "capacity_jobs_per_s": cap, "failed": bad})
+        print(json.dumps({"serving_sweep": rows}), flush=True)
+        return 0
     t = time.perf_counter()
     if args.points == 1_000_000 and args.segments == 50_000:
         p = workloads.config1()
@@ -478,6 +642,22 @@ def main() -> int:
         p = workloads.scaled_config1(args.points, args.segments)
     log(f"generated {p.name}: {p.n_vertices:,} vertices, {p.n_segments:,} segments in {time.perf_counter() - t:.1f} s")
     ctx = gdp2d.Context(0)
+    if args.only_setting:
+        table = dict(ABLATION_SETTINGS + COOP_SETTINGS)
+        kw = table[args.only_setting]
+        q = workloads.config2() if args.only_setting.startswith("coop") else p
+        m0 = gdp2d.gdp_mesh_create(ctx, q.xy, q.seg)
+        m1 = m0.clone()
+        gdp2d.gdp_mesh_refine(ctx, m1, q.ratio_bound_sq, gdp2d.make_params(**kw))  # warm-up
+        m1.assign_from(m0)
+        torch.cuda.synchronize()
+        log(f"setting {args.only_setting}: timed refine begins")
+        gdp2d.gdp_mesh_refine(ctx, m1, q.ratio_bound_sq, gdp2d.make_params(**kw))
+        rs = m1.round_stats()
+        tot = {k: sum(r[k] for r in rs) for k in rs[0]}
+        print(json.dumps({"setting": args.only_setting, "workload": q.name, "refine_ms": m1.last_refine_ms(),
+                          "alg_bytes": loop_alg_bytes(tot), "rounds": m1.info()["rounds"]}), flush=True)
+        return 0
     t = time.perf_counter()
     init = gdp2d.gdp_mesh_create(ctx, p.xy, p.seg)
     log(f"initial CDT (host) + upload: {init.info()['n_triangles']:,} triangles in {time.perf_counter() - t:.1f} s")
@@ -595,8 +775,13 @@ def main() -> int:
         out["initial_cdt"] = cdt_leg(ctx, init, p)
     if not args.no_criteria:
         out["criteria"] = criteria_leg(ctx, init, work, p)
+    if not args.no_flipflop:
+        out["flipflop"] = flipflop_leg(ctx, init, work, p)
     if not args.no_ablation:
-        out["ablation"] = ablation_leg(ctx, init, work, p)
+        p2 = workloads.config2()
+        init2 = gdp2d.gdp_mesh_create(ctx, p2.xy, p2.seg)
+        out["ablation"] = ablation_leg(ctx, init, work, p, init2, p2)
+        del init2
     if args.batch > 0:
         out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
     if serve_jobs:

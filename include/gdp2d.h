@@ -78,7 +78,13 @@ typedef struct {
   /* semantic */
   int32_t cand_cap_K;       /* 0 = unlimited; else keep the K largest priorities per
                                round (Rule 2 filter as a candidate limit) */
-  int32_t priority_mode;    /* 0: class|q(measure)|perm32(id); 1: class|perm32(id) */
+  int32_t priority_mode;    /* 0: class|q(measure)|perm32(id); 1: class|perm32(id);
+                               2: as 0 for subsegments; a triangle's tie-break is
+                               its first two vertex ids from the smallest (22 bits
+                               each, over q(measure) cut to 19 bits), so no key
+                               depends on the slot a triangle occupies (needs
+                               fewer than 2^22 vertices; Flip-Flop insertion
+                               only, see insert_mode) */
   int32_t max_rounds;       /* 0 = no cap; else stop with GDP_E_NOTERM */
   int32_t prefilter_f1;     /* 1: keep one circumcenter per located triangle, the
                                largest key (Line 6 filter, Section 4.3) */
@@ -110,6 +116,32 @@ typedef struct {
                                power of two nearest to half its length */
   double max_edge_len_sq;   /* 0 = off; else l^2 for the edge-length bound l: a
                                triangle with an edge longer than l is bad too */
+  /* perf only (batched form) */
+  int32_t batch_engine_max_v; /* gdp_refine_batch: meshes with more input vertices
+                               run in shared rounds (each phase one launch for all
+                               of them, over the whole chip), the others one
+                               workgroup each in the single-workgroup engine;
+                               0 = every mesh in the engine */
+  /* perf only */
+  int32_t cavity_thread_cap;  /* per-thread cavity slots of the grid path (0 = 39;
+                               12, 24 or 39): larger cavities go to the cooperative
+                               path (Rule 3) */
+  /* semantic */
+  int32_t insert_mode;      /* Line 8 insertion.  0: Bowyer-Watson cavities with
+                               priority marks and the dependency test (Section 5.2);
+                               1: Flip-Flop (Section 4.3): every point kept by Line 6
+                               (one point per split triangle, its largest key) is
+                               added by splits, edges are flipped to the CDT, and
+                               points joined to a point of larger key, or
+                               circumcenters encroaching a subsegment opposite them
+                               (flagged pending), are removed by flips and a flop,
+                               until none is left.  Needs priority_mode 2 (triangles
+                               end in slots of the flips' choosing); each triangle
+                               is kept rotated so its smallest vertex comes first;
+                               gdp_mesh_refine only (not the batched or serving
+                               forms).  A refine call in this mode starts by
+                               flipping the mesh to the CDT under the symbolic
+                               perturbation of the lifting map. */
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */
@@ -160,6 +192,9 @@ typedef struct {
   /* priority marks placed (64-bit atomicMax, one per cavity triangle of a
      valid cavity): midpoint cavities, circumcenter cavities */
   int64_t n_marks_mid, n_marks_cc;
+  /* Flip-Flop rounds (insert_mode 1): points added in Line 8, CDTs examined
+     for redundant points, 2-2 flips, flip passes, points removed */
+  int64_t n_ff_points, n_ff_iters, n_flips, n_flip_passes, n_removals;
 } gdp_round_stats;
 
 /* Fills *p with the defaults (all zero, block_size 256). */
@@ -376,9 +411,11 @@ typedef struct {
 /* hbm_budget: bytes of device memory for job regions; max_slots: jobs active
    at once (in the shared rounds, or on their own streams in mode 1). */
 gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots, gdp_server **out);
-/* 0: shared rounds (default); 1: a stream and a thread per slot.  Applies to
-   jobs admitted afterwards.  GDP_E_ARG for another value. */
-gdp_status gdp_server_mode(gdp_server *srv, int32_t mode);
+/* mode 0: shared rounds (default); 1: a stream and a thread per slot.
+   Applies to jobs admitted afterwards.  rounds_per_group (perf only): shared
+   rounds run between two reads of the jobs' states, 1..8, 0 = default 2
+   (jobs join and leave only between groups).  GDP_E_ARG for other values. */
+gdp_status gdp_server_mode(gdp_server *srv, int32_t mode, int32_t rounds_per_group);
 /* Jobs with at most max_input_vertices input vertices go to the batched
    launches (0: every job takes a slot).  Applies to jobs admitted afterwards.
    GDP_E_ARG for a negative value. */

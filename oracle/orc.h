@@ -74,7 +74,7 @@ typedef struct orc_params {
                              vertices (see orc_midpoint) */
   double max_edge_len_sq; /* 0 = off; else a triangle with an edge longer than l
                              (squared length > l^2) is bad as well */
-  int32_t insert_mode;    /* 0: cavities, marks and the dependency test (Section 5.1);
+  int32_t insert_mode;    /* 0: cavities, marks and the dependency test (Section 5.2);
                              1: Flip-Flop (Section 4.3 Line 8, see orc_ff.c);
                              needs priority_mode 2 */
 } orc_params;

@@ -29,10 +29,10 @@
  *   R6           midpoint cavities, grown from both sides of the subsegment.
  *   R8           priority marks: every triangle keeps the largest key of the
  *                cavities that contain it; a point survives only if it holds
- *                every triangle of its cavity (Section 5.1 marking rule, taken
+ *                every triangle of its cavity (Section 5.2 marking rule, taken
  *                after all marks are placed so the result does not depend on
  *                timing).
- *   R9           Delaunay dependency (Section 5.1): for surviving p, q whose
+ *   R9           Delaunay dependency (Section 5.2): for surviving p, q whose
  *                cavities share a non-subsegment edge (u,v), if q lies strictly
  *                inside the circle (u,v,p) the lower priority is dropped.
  *   R10          insert: vertex ids, triangle slots and subsegment ids are

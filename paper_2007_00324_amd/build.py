@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgdp2d.so")
-SOURCES = ["gdp_kernels.hip", "gdp_cdt_dev.hip", "gdp_api.hip", "gdp_host_cdt.cpp"]
+SOURCES = ["gdp_kernels.hip", "gdp_ff.hip", "gdp_cdt_dev.hip", "gdp_api.hip", "gdp_host_cdt.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GDP_OFFLOAD_ARCH", "gfx950")
 

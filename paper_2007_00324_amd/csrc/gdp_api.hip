@@ -73,6 +73,30 @@ void arena_release(gdp_arena *a) {
   delete a;
 }
 
+// Device buffers of the Flip-Flop rounds (insert_mode 1), allocated by the
+// first such round and grown with the mesh.
+struct FfBufs {
+  int32_t capP = 0;   // points of S
+  int32_t capK = 0;   // candidates (sort input)
+  int32_t capT = 0, capV = 0, capS = 0;
+  int64_t pool_cap = 0;
+  uint64_t *skey0 = nullptr, *skey1 = nullptr;
+  int32_t *sref0 = nullptr, *sref1 = nullptr, *shist = nullptr;
+  double2 *pt = nullptr;
+  int4 *pinfo = nullptr, *pslots = nullptr;
+  int2 *pab = nullptr;
+  int32_t *alive = nullptr, *red = nullptr, *vtri = nullptr, *newid = nullptr;
+  int4 *grp = nullptr, *fc0 = nullptr, *fc1 = nullptr;
+  int32_t *sstamp = nullptr, *wstamp = nullptr, *tstamp = nullptr, *moved = nullptr;
+  uint64_t *claim = nullptr, *fprio = nullptr, *vmark = nullptr;
+  int32_t *list[2] = {nullptr, nullptr};
+  int32_t *touched = nullptr, *hole = nullptr, *mover = nullptr;
+  int32_t *sflag = nullptr, *mid_rank = nullptr, *pool = nullptr;
+  FfCount *d_c = nullptr, *h_c = nullptr;
+  int32_t stamp = 0;   // last slot stamp handed out (splits, worklists, touched list)
+  uint64_t pass = 0;   // last pass number (flip claims, removal marks)
+};
+
 struct gdp_mesh {
   gdp_ctx *ctx = nullptr;
   gdp_arena *arena = nullptr;  // non-null: the device arrays below live in a batch arena
@@ -142,6 +166,7 @@ struct gdp_mesh {
   std::vector<ProfRec> prof_pending;
   double prof_ms[16] = {};
   int64_t prof_launches[16] = {}, prof_items[16] = {}, prof_bytes[16] = {};
+  FfBufs *ff = nullptr;  // Flip-Flop rounds
 };
 
 namespace {
@@ -462,6 +487,18 @@ void free_mesh_arrays(gdp_mesh *M) {
 // Allocations a mesh owns even inside a batch arena: pinned host mirrors,
 // captured graphs, the engine descriptor.
 void free_extras(gdp_mesh *M) {
+  if (M->ff) {
+    FfBufs *F = M->ff;
+    void *ptrs[] = {F->skey0, F->skey1, F->sref0, F->sref1, F->shist, F->pt, F->pinfo, F->pslots, F->pab,
+                    F->alive, F->red, F->vtri, F->newid, F->grp, F->fc0, F->fc1, F->sstamp, F->wstamp,
+                    F->tstamp, F->moved, F->claim, F->fprio, F->vmark, F->list[0], F->list[1], F->touched,
+                    F->hole, F->mover, F->sflag, F->mid_rank, F->pool, F->d_c};
+    for (void *q : ptrs)
+      if (q) (void)hipFree(q);
+    if (F->h_c) (void)hipHostFree(F->h_c);
+    delete F;
+    M->ff = nullptr;
+  }
   if (M->h_cnt) (void)hipHostFree(M->h_cnt);
   if (M->h_st) (void)hipHostFree(M->h_st);
   if (M->h_hist) (void)hipHostFree(M->h_hist);
@@ -588,19 +625,14 @@ gdp_status grow_after_abort(gdp_mesh *M, const DevCounters &c, int keep_fan) {
   return GDP_OK;
 }
 
-// Queues one round (Algorithm 1, Lines 3-9) on the stream.  Every length
-// comes from device memory; `est` (an estimate of the candidates) only sizes
-// the grids.  `full` selects the full collection (first round of a call).
-gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full, int parity, int64_t est,
-                         int group_index) {
-  gdp_ctx *ctx = M->ctx;
-  hipStream_t s = ctx->stream;
+// Queues Lines 3-7 of a round (collection, gate, candidate cap, walk,
+// optional prefilters) with workspace w; returns the candidate bound that
+// sizes the later grids.
+int64_t enqueue_select(gdp_mesh *M, double B2, const gdp_params *P, bool full, int64_t est, const Work &w) {
+  hipStream_t s = M->ctx->stream;
   const DevMesh &m = M->m;
   const int bs = P->block_size;
   const int pm = P->priority_mode;
-  Work w = make_work(M, P, parity);
-  est = std::max<int64_t>(est, 1);
-  M->cur_round = group_index;
   // ---- R1 collection ----
   {
     Prof pr(M, P_SCAN);
@@ -640,10 +672,29 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
         hipLaunchKernelGGL(k_prefilter, dim3(stride_grid(ncand, 128)), dim3(128), 0, s, m, w, mode,
                            P->cavity_approx_n);
   }
+  return ncand;
+}
+
+// Queues one round (Algorithm 1, Lines 3-9) on the stream.  Every length
+// comes from device memory; `est` (an estimate of the candidates) only sizes
+// the grids.  `full` selects the full collection (first round of a call).
+gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full, int parity, int64_t est,
+                         int group_index) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  const DevMesh &m = M->m;
+  const int bs = P->block_size;
+  Work w = make_work(M, P, parity);
+  est = std::max<int64_t>(est, 1);
+  M->cur_round = group_index;
+  const int64_t ncand = enqueue_select(M, B2, P, full, est, w);
   // ---- R5/R6 cavities (marks placed as each valid cavity completes) ----
   {
     Prof pr(M, P_CAV_CC);
-    hipLaunchKernelGGL(k_cavity<1>, dim3(stride_grid(ncand, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w);
+    const unsigned g = stride_grid(ncand, kCavBlockSize);
+    if (P->cavity_thread_cap == 12) hipLaunchKernelGGL((k_cavity<1, 12>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
+    else if (P->cavity_thread_cap == 24) hipLaunchKernelGGL((k_cavity<1, 24>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
+    else hipLaunchKernelGGL((k_cavity<1, kCavCapDefault>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
   }
   {
     Prof pr(M, P_CAV_BIG);
@@ -652,7 +703,10 @@ gdp_status enqueue_round(gdp_mesh *M, double B2, const gdp_params *P, bool full,
   }
   {
     Prof pr(M, P_CAV_MID);
-    hipLaunchKernelGGL(k_cavity<0>, dim3(stride_grid(ncand / 4, kCavBlockSize)), dim3(kCavBlockSize), 0, s, m, w);
+    const unsigned g = stride_grid(ncand / 4, kCavBlockSize);
+    if (P->cavity_thread_cap == 12) hipLaunchKernelGGL((k_cavity<0, 12>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
+    else if (P->cavity_thread_cap == 24) hipLaunchKernelGGL((k_cavity<0, 24>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
+    else hipLaunchKernelGGL((k_cavity<0, kCavCapDefault>), dim3(g), dim3(kCavBlockSize), 0, s, m, w);
   }
   {
     Prof pr(M, P_CAV_BIG);
@@ -734,6 +788,11 @@ gdp_round_stats round_stats_of(const DevCounters &c, const gdp_params *P) {
   rs.n_huge_cavities = c.nhuge;
   rs.n_marks_mid = c.n_marks[0];
   rs.n_marks_cc = c.n_marks[1];
+  rs.n_ff_points = c.ff_points;
+  rs.n_ff_iters = c.ff_iters;
+  rs.n_flips = c.ff_flips;
+  rs.n_flip_passes = c.ff_passes;
+  rs.n_removals = c.ff_removals;
   return rs;
 }
 
@@ -1025,6 +1084,211 @@ gdp_status status_of_halt(gdp_ctx *ctx, const DevState &d, const DevCounters &c)
   }
 }
 
+// ---- shared rounds: the rounds of several meshes in one launch per phase ----
+// (Rule 4 of Section 2.)  Used by the serving form for its active jobs and
+// by the batched form for its largest meshes.
+struct GangItem {
+  gdp_mesh *M;
+  const gdp_params *P;
+  double B2;
+  int64_t last_cand;  // candidates of the last completed round (sizes the grids)
+  int aborts;         // consecutive abandoned rounds
+  bool full;          // its next round is its first (a full collection)
+  void *tag;          // the owner's handle
+};
+
+// Device and pinned buffers of a shared-rounds runner (up to cap meshes).
+struct GangBufs {
+  GangDesc *d_desc = nullptr, *h_desc = nullptr;
+  int32_t *d_status = nullptr, *h_status = nullptr;
+  int stride_words = 0;  // words of one mesh's status record
+  int cap = 0;
+};
+constexpr int kGangRounds = 2;     // default rounds between two host reads of the meshes' states
+constexpr int kGangRoundsMax = 8;
+
+bool gang_bufs_alloc(GangBufs &B, int cap) {
+  B.cap = cap;
+  B.stride_words = (int)((sizeof(DevState) + (1 + kGangRoundsMax) * sizeof(DevCounters)) / 4);
+  return dalloc(&B.d_desc, cap) == hipSuccess &&
+         hipHostMalloc((void **)&B.h_desc, sizeof(GangDesc) * cap) == hipSuccess &&
+         dalloc(&B.d_status, (size_t)B.stride_words * cap) == hipSuccess &&
+         hipHostMalloc((void **)&B.h_status, sizeof(int32_t) * B.stride_words * cap) == hipSuccess;
+}
+
+void gang_bufs_free(GangBufs &B) {
+  if (B.d_desc) (void)hipFree(B.d_desc);
+  if (B.d_status) (void)hipFree(B.d_status);
+  if (B.h_desc) (void)hipHostFree(B.h_desc);
+  if (B.h_status) (void)hipHostFree(B.h_status);
+  B = GangBufs();
+}
+
+GangItem gang_item(gdp_mesh *M, const gdp_params *P, double B2, void *tag) {
+  return GangItem{M, P, B2, (int64_t)M->m.nT + M->m.nS, 0, true, tag};
+}
+
+GangDesc gang_desc(gdp_mesh *M, const gdp_params *P, double B2) {
+  GangDesc g;
+  memset(&g, 0, sizeof g);
+  EngDesc &d = g.e;
+  d.m = M->m;
+  d.w[0] = make_work(M, P, 0);
+  d.w[1] = make_work(M, P, 1);
+  // one workgroup runs the device-memory cavity path per mesh and launch
+  d.w[0].huge_ok = d.w[1].huge_ok = 1;
+  d.B2 = B2;
+  d.pm = P->priority_mode;
+  d.K = P->cand_cap_K;
+  d.f1 = P->prefilter_f1;
+  d.approx_n = P->cavity_approx_n;
+  d.max_rounds = P->max_rounds;
+  g.js = ScanJob{(const int32_t *)M->win_s, M->rank_s, &M->d_st->wS, M->tiles_s, &M->d_cnt->nwin_mid, 1};
+  g.jt = ScanJob{(const int32_t *)M->win_t, M->rank_t, &M->d_st->wT, M->tiles_t, &M->d_cnt->nwin_cc, 1};
+  g.jf = ScanJob{M->fcount, M->fbase, &M->d_cnt->nwin1, M->tiles_f, &M->d_cnt->fan_total, 0};
+  return g;
+}
+
+// One round of every job in the descriptors (grids sized for the largest).
+void gang_round(hipStream_t s, const GangDesc *D, unsigned n, int64_t max_full, int64_t max_est,
+                int64_t max_ncand, int64_t max_words, bool any_cap, bool any_pre) {
+  const int bs = 256;
+  const unsigned gc = std::max(stride_grid(max_full, bs), stride_grid(3 * max_est, bs));
+  hipLaunchKernelGGL(kg_collect, dim3(gc, n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_pending, dim3(stride_grid(max_est / 4, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_gate, dim3(1, n), dim3(256), 0, s, D);
+  if (any_cap) {
+    hipLaunchKernelGGL(kg_gather_keys, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+    const unsigned g = std::min<unsigned>(grid_for(max_ncand, 256), 1024);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(kg_radix_hist, dim3(g, n), dim3(256), 0, s, D, shift);
+      hipLaunchKernelGGL(kg_radix_pick, dim3(1, n), dim3(256), 0, s, D, shift);
+    }
+    hipLaunchKernelGGL(kg_apply_cap, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  }
+  hipLaunchKernelGGL(kg_locate, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  if (any_pre)
+    for (int mode = 0; mode < 6; mode++)
+      hipLaunchKernelGGL(kg_prefilter, dim3(stride_grid(max_ncand, 128), n), dim3(128), 0, s, D, mode);
+  hipLaunchKernelGGL(kg_cavity<1>, dim3(stride_grid(max_ncand, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
+  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_cavity<0>, dim3(stride_grid(max_ncand / 4, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
+  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_own, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_dep, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  const int64_t tiles_w = std::max<int64_t>(1, (max_words + kScanTileSize - 1) / kScanTileSize);
+  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(2 * tiles_w, 2048), n), dim3(256), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_scan_sums, dim3(2, n), dim3(256), 0, s, D, 0);
+  hipLaunchKernelGGL(kg_winners, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  const int64_t tiles_f = std::max<int64_t>(1, (max_ncand + 1 + kScanTileSize - 1) / kScanTileSize);
+  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(tiles_f, 2048), n), dim3(256), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_scan_sums, dim3(1, n), dim3(256), 0, s, D, 1);
+  hipLaunchKernelGGL(kg_record, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_write, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
+  hipLaunchKernelGGL(kg_finish, dim3(std::min(stride_grid(max_ncand, bs), 256u), n), dim3(bs), 0, s, D);
+}
+
+// One group of R shared rounds of every active mesh (at most B.cap), then
+// one read of all their states.  Meshes whose refinement ended (done, round
+// cap, error) move to `finished` with their status; a mesh whose round found
+// a buffer short has that buffer grown and runs the round again, as in the
+// plain loop, so each mesh is the plain loop's.  Returns an error only if
+// the group itself could not run (then every mesh is finished with it).
+void gang_group(gdp_ctx *ctx, GangBufs &B, std::vector<GangItem> &active, int R,
+                std::vector<std::pair<GangItem, gdp_status>> &finished) {
+  hipStream_t s = ctx->stream;
+  const int ns = (int)(sizeof(DevState) / 4), nc = (int)(sizeof(DevCounters) / 4);
+  int64_t max_full = 0, max_est = 1, max_ncand = 1, max_words = 1;
+  bool any_cap = false, any_pre = false;
+  for (size_t q = 0; q < active.size();) {
+    GangItem &A = active[q];
+    gdp_mesh *M = A.M;
+    gdp_status st = reserve_group(M, A.last_cand, R);
+    if (st != GDP_OK) {
+      finished.push_back({A, st});
+      active.erase(active.begin() + q);
+      continue;
+    }
+    const DevMesh &m = M->m;
+    // grids sized for the largest mesh's work this round (a full collection
+    // for a mesh's first round, the candidate lists after it)
+    if (A.full) max_full = std::max<int64_t>(max_full, std::max(m.nT, m.nS));
+    else max_est = std::max<int64_t>(max_est, A.last_cand);
+    max_ncand = std::max<int64_t>(max_ncand, A.full ? (int64_t)m.nT + m.nS : 2 * A.last_cand);
+    max_words = std::max<int64_t>(max_words, std::max(words(m.capS), words(m.capT)));
+    any_cap = any_cap || A.P->cand_cap_K > 0;
+    any_pre = any_pre || A.P->prefilter_f1 || A.P->cavity_approx_n > 0;
+    B.h_desc[q] = gang_desc(M, A.P, A.B2);
+    q++;
+  }
+  const unsigned n = (unsigned)active.size();
+  if (n == 0) return;
+  bool ok = hipMemcpyAsync(B.d_desc, B.h_desc, sizeof(GangDesc) * n, hipMemcpyHostToDevice, s) == hipSuccess;
+  for (int r = 0; ok && r < R; r++)
+    gang_round(s, B.d_desc, n, max_full, max_est, max_ncand, max_words, any_cap, any_pre);
+  if (ok) {
+    hipLaunchKernelGGL(kg_status, dim3(1, n), dim3(256), 0, s, B.d_desc, R, B.d_status, B.stride_words);
+    ok = hipGetLastError() == hipSuccess &&
+         hipMemcpyAsync(B.h_status, B.d_status, sizeof(int32_t) * B.stride_words * n, hipMemcpyDeviceToHost, s) ==
+             hipSuccess &&
+         hipStreamSynchronize(s) == hipSuccess;
+  }
+  std::vector<GangItem> keep;
+  for (unsigned q = 0; q < n; q++) {
+    GangItem A = active[q];
+    gdp_mesh *M = A.M;
+    if (!ok) {
+      finished.push_back({A, fail(ctx, GDP_E_DEVICE, "shared round launch failed")});
+      continue;
+    }
+    const int32_t *rec = B.h_status + (size_t)q * B.stride_words;
+    DevState d;
+    DevCounters c;
+    memcpy(&d, rec, sizeof d);
+    memcpy(&c, rec + ns, sizeof c);
+    const DevCounters *h = (const DevCounters *)(rec + ns + nc);
+    const int done = std::min(d.nhist, R);
+    for (int i = 0; i < done; i++) {
+      M->stats.push_back(round_stats_of(h[i], A.P));
+      A.last_cand = (int64_t)h[i].ncc + h[i].nmk;
+    }
+    M->m.nV = d.nV; M->m.nT = d.nT; M->m.nS = d.nS; M->m.rounds = d.rounds;
+    M->serial = d.serial;
+    if (done > 0) {
+      A.aborts = 0;
+      A.full = false;
+    }
+    gdp_status st = GDP_OK;
+    bool over = false;
+    if (d.halt == kHaltAbort) {
+      // nothing was written: grow and run the same round again
+      if (++A.aborts > 16) {
+        st = fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
+        over = true;
+      } else if ((st = grow_after_abort(M, c, d.full ? 0 : d.prev_fan)) != GDP_OK) {
+        over = true;
+      } else if (hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s) != hipSuccess ||
+                 hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s) != hipSuccess) {
+        st = fail(ctx, GDP_E_DEVICE, "reset after an abandoned round failed");
+        over = true;
+      }
+    } else if (d.halt != 0) {
+      st = status_of_halt(ctx, d, c);
+      over = true;
+    }
+    if (!over && hipMemsetAsync(&M->d_st->halt, 0, 2 * sizeof(int32_t), s) != hipSuccess) {  // halt, nhist
+      st = fail(ctx, GDP_E_DEVICE, "round state reset failed");
+      over = true;
+    }
+    if (over) finished.push_back({A, st});
+    else keep.push_back(A);
+  }
+  active.swap(keep);
+}
+
+constexpr size_t kBatchGangMax = 256;  // batched meshes in one group of shared rounds, at most
 // The batched form (Algorithm 1 for many independent PSLGs): Line 1 on the
 // host for every input (in parallel), one arena holding every mesh and its
 // workspace, then all of Lines 2-9 in one launch of the single-workgroup
@@ -1178,15 +1442,22 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
     M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
     M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
   }
+  // Meshes with more input vertices than the split run in shared rounds
+  // (every phase one launch for all of them, the whole chip per round), the
+  // others one workgroup each in the engine launch.  Either way each mesh is
+  // the plain loop's.
+  const int64_t split = P->batch_engine_max_v > 0 ? P->batch_engine_max_v : (int64_t)1 << 40;
+  std::vector<int32_t> order, gang_k;
+  for (int32_t k = 0; k < n; k++) (hm[ok[k]].nV > split ? gang_k : order).push_back(k);
   // Queue order.  Largest first keeps the makespan short, but the engines on
   // one XCD share its 4 MB L2, and large meshes side by side evict each
   // other's working sets (measured: each runs many times slower than alone).
   // So the largest quarter, in size order, is spread out: every fourth entry,
   // the others (largest first) in between.  The order changes no mesh.
-  std::vector<int32_t> order(n);
-  for (int32_t k = 0; k < n; k++) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hm[ok[a]].nT > hm[ok[b]].nT; });
+  const int32_t ne = (int32_t)order.size();
   {
+    const int32_t n = ne;
     const int32_t nbig = (n + 3) / 4;
     std::vector<int32_t> spread;
     spread.reserve(n);
@@ -1197,8 +1468,8 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
     }
     order.swap(spread);
   }
-  std::vector<EngDesc> desc(n);
-  for (int32_t q = 0; q < n; q++) {
+  std::vector<EngDesc> desc(std::max(ne, 1));
+  for (int32_t q = 0; q < ne; q++) {
     const int32_t k = order[q];
     EngDesc &d = desc[q];
     memset(&d, 0, sizeof d);
@@ -1214,13 +1485,19 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   }
   EngDesc *d_desc = nullptr;
   int32_t *d_head = nullptr;
-  if (dalloc(&d_desc, n) != hipSuccess || dalloc(&d_head, 1) != hipSuccess) {
+  GangBufs gb;
+  const int gcap = (int)std::min<size_t>(gang_k.size(), kBatchGangMax);
+  if (dalloc(&d_desc, std::max(ne, 1)) != hipSuccess || dalloc(&d_head, 1) != hipSuccess ||
+      (gcap > 0 && !gang_bufs_alloc(gb, gcap))) {
     if (d_desc) (void)hipFree(d_desc);
+    if (d_head) (void)hipFree(d_head);
+    gang_bufs_free(gb);
     return bail(fail(ctx, GDP_E_NOMEM, "descriptor allocation failed"));
   }
   auto free_tmp = [&]() {
     (void)hipFree(d_desc);
     (void)hipFree(d_head);
+    gang_bufs_free(gb);
   };
   int cus = 256;
   {
@@ -1229,15 +1506,33 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
       cus = prop.multiProcessorCount;
   }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool ok_run = hipMemcpy(d_desc, desc.data(), sizeof(EngDesc) * n, hipMemcpyHostToDevice) == hipSuccess &&
+  bool ok_run = (ne == 0 || hipMemcpy(d_desc, desc.data(), sizeof(EngDesc) * ne, hipMemcpyHostToDevice) == hipSuccess) &&
                 hipMemsetAsync(d_head, 0, sizeof(int32_t), s) == hipSuccess && hipEventCreate(&ev0) == hipSuccess &&
                 hipEventCreate(&ev1) == hipSuccess && hipEventRecord(ev0, s) == hipSuccess;
-  if (ok_run) {
-    hipLaunchKernelGGL(k_engine, dim3((unsigned)std::min(n, cus)), dim3(kEngBlock), 0, s, d_desc, n, d_head,
-                       1 << 30);
-    ok_run = hipGetLastError() == hipSuccess && hipEventRecord(ev1, s) == hipSuccess &&
-             hipEventSynchronize(ev1) == hipSuccess;
+  // the large meshes first, in shared rounds over the whole chip (largest
+  // first, at most kBatchGangMax at a time), then the engine launch
+  std::vector<gdp_status> gang_st(n, GDP_OK);
+  if (ok_run && !gang_k.empty()) {
+    std::stable_sort(gang_k.begin(), gang_k.end(), [&](int32_t a, int32_t b) { return hm[ok[a]].nT > hm[ok[b]].nT; });
+    std::vector<GangItem> active;
+    size_t next = 0;
+    const int R = P->rounds_per_sync > 0 ? std::min(P->rounds_per_sync, kGangRoundsMax) : kGangRounds;
+    while (next < gang_k.size() || !active.empty()) {
+      while (next < gang_k.size() && (int)active.size() < gcap) {
+        const int32_t k = gang_k[next++];
+        active.push_back(gang_item(mesh[k], P, bsq[ok[k]], (void *)(intptr_t)k));
+      }
+      std::vector<std::pair<GangItem, gdp_status>> finished;
+      gang_group(ctx, gb, active, R, finished);
+      for (auto &f : finished) gang_st[(int32_t)(intptr_t)f.first.tag] = f.second;
+    }
   }
+  if (ok_run && ne > 0) {
+    hipLaunchKernelGGL(k_engine, dim3((unsigned)std::min(ne, cus)), dim3(kEngBlock), 0, s, d_desc, ne, d_head,
+                       1 << 30);
+    ok_run = hipGetLastError() == hipSuccess;
+  }
+  ok_run = ok_run && hipEventRecord(ev1, s) == hipSuccess && hipEventSynchronize(ev1) == hipSuccess;
   float ms = 0.f;
   if (ok_run) (void)hipEventElapsedTime(&ms, ev0, ev1);
   if (ev0) (void)hipEventDestroy(ev0);
@@ -1245,14 +1540,15 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   free_tmp();
   if (!ok_run) return bail(fail(ctx, GDP_E_DEVICE, "batch launch failed"));
   if (elapsed_ms) *elapsed_ms = ms;
-  // results: device states, counters and per-round histories
+  // the engine's: device states, counters and per-round histories
   const int R_CNT = R_ST - 1;  // d_cnt precedes d_st
   std::vector<char> hst(region[R_ST]), hcnt(region[R_CNT]), hhist(region[R_ST + 1]);
-  if (hipMemcpy(hst.data(), base + region_off[R_ST], region[R_ST], hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(hcnt.data(), base + region_off[R_CNT], region[R_CNT], hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(hhist.data(), base + region_off[R_ST + 1], region[R_ST + 1], hipMemcpyDeviceToHost) != hipSuccess)
+  if (ne > 0 &&
+      (hipMemcpy(hst.data(), base + region_off[R_ST], region[R_ST], hipMemcpyDeviceToHost) != hipSuccess ||
+       hipMemcpy(hcnt.data(), base + region_off[R_CNT], region[R_CNT], hipMemcpyDeviceToHost) != hipSuccess ||
+       hipMemcpy(hhist.data(), base + region_off[R_ST + 1], region[R_ST + 1], hipMemcpyDeviceToHost) != hipSuccess))
     return bail(fail(ctx, GDP_E_DEVICE, "batch download failed"));
-  for (int32_t k = 0; k < n; k++) {
+  for (int32_t k : order) {
     gdp_mesh *M = mesh[k];
     const int32_t i = ok[k];
     DevState d;
@@ -1277,6 +1573,24 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
     if (r == GDP_OK || r == GDP_E_NOTERM) {
       outs[i] = M;
     } else {
+      gdp_mesh_free(M);
+      mesh[k] = nullptr;
+    }
+  }
+  // the shared-rounds meshes are complete
+  for (int32_t k : gang_k) {
+    gdp_mesh *M = mesh[k];
+    const int32_t i = ok[k];
+    M->last_ms = ms;
+    gdp_status r = gang_st[k];
+    if (status) status[i] = r;
+    if (r == GDP_OK || r == GDP_E_NOTERM) {
+      if (r == GDP_OK && !M->arena && alloc_host_mirrors(M) != GDP_OK) r = GDP_E_NOMEM;
+    }
+    if (r == GDP_OK || r == GDP_E_NOTERM) {
+      outs[i] = M;
+    } else {
+      if (status) status[i] = r;
       gdp_mesh_free(M);
       mesh[k] = nullptr;
     }
@@ -1405,12 +1719,9 @@ struct ServerEngine {
 // Shared rounds (Rule 4 of Section 2, the default mode): one driver thread
 // runs the rounds of every active job together, one launch per phase for all
 // of them; jobs join and leave between groups of rounds.
-constexpr int kGangRounds = 2;  // rounds between two host reads of the jobs' states
 struct ServerGang {
-  gdp_ctx ctx;                               // the driver's own stream
-  GangDesc *d_desc = nullptr, *h_desc = nullptr;  // [max_slots]
-  int32_t *d_status = nullptr, *h_status = nullptr;
-  int stride_words = 0;                      // words of one job's status record
+  gdp_ctx ctx;     // the driver's own stream
+  GangBufs bufs;   // for max_slots jobs
   std::thread th;
 };
 
@@ -1419,6 +1730,7 @@ struct gdp_server {
   ServerMem *mem = nullptr;
   int max_slots = 0;
   int32_t mode = 0;          // 0: shared rounds; 1: a stream and a thread per slot
+  int32_t gang_rounds = kGangRounds;  // shared rounds between two host reads
   int32_t engine_max_v = 0;  // 0: no job in the single-workgroup engine launches
   ServerEngine *eng = nullptr;
   ServerGang *gang = nullptr;
@@ -1664,89 +1976,16 @@ void engine_dispatcher(gdp_server *S, ServerEngine *E) {
 
 
 // ---- serving form: shared rounds ------------------------------------------
-// Per active job: the host's view between two groups of rounds.
-struct GangJob {
-  Job *J;
-  int64_t last_cand;  // candidates of the last completed round (sizes the grids)
-  int aborts;         // consecutive abandoned rounds
-  bool full;          // its next round is its first (a full collection)
-};
-
-GangDesc gang_desc(gdp_mesh *M, const Job *J) {
-  GangDesc g;
-  memset(&g, 0, sizeof g);
-  EngDesc &d = g.e;
-  d.m = M->m;
-  d.w[0] = make_work(M, &J->P, 0);
-  d.w[1] = make_work(M, &J->P, 1);
-  // one workgroup runs the device-memory cavity path per mesh and launch
-  d.w[0].huge_ok = d.w[1].huge_ok = 1;
-  d.B2 = J->B2;
-  d.pm = J->P.priority_mode;
-  d.K = J->P.cand_cap_K;
-  d.f1 = J->P.prefilter_f1;
-  d.approx_n = J->P.cavity_approx_n;
-  d.max_rounds = J->P.max_rounds;
-  g.js = ScanJob{(const int32_t *)M->win_s, M->rank_s, &M->d_st->wS, M->tiles_s, &M->d_cnt->nwin_mid, 1};
-  g.jt = ScanJob{(const int32_t *)M->win_t, M->rank_t, &M->d_st->wT, M->tiles_t, &M->d_cnt->nwin_cc, 1};
-  g.jf = ScanJob{M->fcount, M->fbase, &M->d_cnt->nwin1, M->tiles_f, &M->d_cnt->fan_total, 0};
-  return g;
-}
-
-// One round of every job in the descriptors (grids sized for the largest).
-void gang_round(hipStream_t s, const GangDesc *D, unsigned n, int64_t max_full, int64_t max_est,
-                int64_t max_ncand, int64_t max_words, bool any_cap, bool any_pre) {
-  const int bs = 256;
-  const unsigned gc = std::max(stride_grid(max_full, bs), stride_grid(3 * max_est, bs));
-  hipLaunchKernelGGL(kg_collect, dim3(gc, n), dim3(bs), 0, s, D);
-  hipLaunchKernelGGL(kg_pending, dim3(stride_grid(max_est / 4, bs), n), dim3(bs), 0, s, D);
-  hipLaunchKernelGGL(kg_gate, dim3(1, n), dim3(256), 0, s, D);
-  if (any_cap) {
-    hipLaunchKernelGGL(kg_gather_keys, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-    const unsigned g = std::min<unsigned>(grid_for(max_ncand, 256), 1024);
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      hipLaunchKernelGGL(kg_radix_hist, dim3(g, n), dim3(256), 0, s, D, shift);
-      hipLaunchKernelGGL(kg_radix_pick, dim3(1, n), dim3(256), 0, s, D, shift);
-    }
-    hipLaunchKernelGGL(kg_apply_cap, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  }
-  hipLaunchKernelGGL(kg_locate, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  if (any_pre)
-    for (int mode = 0; mode < 6; mode++)
-      hipLaunchKernelGGL(kg_prefilter, dim3(stride_grid(max_ncand, 128), n), dim3(128), 0, s, D, mode);
-  hipLaunchKernelGGL(kg_cavity<1>, dim3(stride_grid(max_ncand, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
-  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 0);
-  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 0);
-  hipLaunchKernelGGL(kg_cavity<0>, dim3(stride_grid(max_ncand / 4, kCavBlockSize), n), dim3(kCavBlockSize), 0, s, D);
-  hipLaunchKernelGGL(kg_cavity_big, dim3(256, n), dim3(kBigBlockSize), 0, s, D, 1);
-  hipLaunchKernelGGL(kg_cavity_huge, dim3(1, n), dim3(kHugeBlock), 0, s, D, 1);
-  hipLaunchKernelGGL(kg_own, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  hipLaunchKernelGGL(kg_dep, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  const int64_t tiles_w = std::max<int64_t>(1, (max_words + kScanTileSize - 1) / kScanTileSize);
-  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(2 * tiles_w, 2048), n), dim3(256), 0, s, D, 0);
-  hipLaunchKernelGGL(kg_scan_sums, dim3(2, n), dim3(256), 0, s, D, 0);
-  hipLaunchKernelGGL(kg_winners, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  const int64_t tiles_f = std::max<int64_t>(1, (max_ncand + 1 + kScanTileSize - 1) / kScanTileSize);
-  hipLaunchKernelGGL(kg_scan_tiles, dim3((unsigned)std::min<int64_t>(tiles_f, 2048), n), dim3(256), 0, s, D, 1);
-  hipLaunchKernelGGL(kg_scan_sums, dim3(1, n), dim3(256), 0, s, D, 1);
-  hipLaunchKernelGGL(kg_record, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  hipLaunchKernelGGL(kg_write, dim3(stride_grid(max_ncand, bs), n), dim3(bs), 0, s, D);
-  hipLaunchKernelGGL(kg_finish, dim3(std::min(stride_grid(max_ncand, bs), 256u), n), dim3(bs), 0, s, D);
-}
-
 // The driver: admits arrived jobs (first come, first served) while a slot
-// and room are free, runs kGangRounds rounds of every active job, reads all
-// their states at once, and retires finished jobs.  A job whose round found
-// a buffer short has that buffer grown and runs the round again, as in the
-// plain loop; each job's mesh is therefore the plain loop's.
+// and room are free, runs a group of shared rounds of every active job,
+// and retires the jobs that finished.
 void gang_driver(gdp_server *S, ServerGang *Gn) {
   (void)hipSetDevice(Gn->ctx.device);
   gdp_ctx *ctx = &Gn->ctx;
-  hipStream_t s = ctx->stream;
-  std::vector<GangJob> active;
-  const int ns = (int)(sizeof(DevState) / 4), nc = (int)(sizeof(DevCounters) / 4);
+  std::vector<GangItem> active;
   for (;;) {
     std::vector<Job *> fresh;
+    int R = kGangRounds;
     {
       std::unique_lock<std::mutex> g(S->mu);
       for (;;) {
@@ -1792,6 +2031,7 @@ void gang_driver(gdp_server *S, ServerGang *Gn) {
         }
         S->cv.wait_for(g, std::chrono::milliseconds(1));
       }
+      R = S->gang_rounds;
     }
     for (Job *J : fresh) {
       gdp_status st = admit_job(S, J, ctx);
@@ -1801,100 +2041,15 @@ void gang_driver(gdp_server *S, ServerGang *Gn) {
         complete_job(S, J, st);
         continue;
       }
-      active.push_back(GangJob{J, (int64_t)J->mesh->m.nT + J->mesh->m.nS, 0, true});
+      active.push_back(gang_item(J->mesh, &J->P, J->B2, J));
     }
     if (active.empty()) continue;
-    // room for this group of rounds, then the descriptors
-    int64_t max_full = 0, max_est = 1, max_ncand = 1, max_words = 1;
-    bool any_cap = false, any_pre = false;
-    for (size_t q = 0; q < active.size();) {
-      GangJob &A = active[q];
-      gdp_mesh *M = A.J->mesh;
-      gdp_status st = reserve_group(M, A.last_cand, kGangRounds);
-      if (st != GDP_OK) {
-        gdp_mesh_free(M);
-        A.J->mesh = nullptr;
-        complete_job(S, A.J, st);
-        active.erase(active.begin() + q);
-        continue;
-      }
-      const DevMesh &m = M->m;
-      if (A.full) max_full = std::max<int64_t>(max_full, std::max(m.nT, m.nS));
-      else max_est = std::max<int64_t>(max_est, A.last_cand);
-      max_ncand = std::max<int64_t>(max_ncand, std::max<int64_t>((int64_t)m.nT + m.nS, 2 * A.last_cand));
-      max_words = std::max<int64_t>(max_words, std::max(words(m.capS), words(m.capT)));
-      any_cap = any_cap || A.J->P.cand_cap_K > 0;
-      any_pre = any_pre || A.J->P.prefilter_f1 || A.J->P.cavity_approx_n > 0;
-      Gn->h_desc[q] = gang_desc(M, A.J);
-      q++;
-    }
-    const unsigned n = (unsigned)active.size();
-    if (n == 0) continue;
-    bool ok = hipMemcpyAsync(Gn->d_desc, Gn->h_desc, sizeof(GangDesc) * n, hipMemcpyHostToDevice, s) == hipSuccess;
-    for (int r = 0; ok && r < kGangRounds; r++)
-      gang_round(s, Gn->d_desc, n, max_full, max_est, max_ncand, max_words, any_cap, any_pre);
-    if (ok) {
-      hipLaunchKernelGGL(kg_status, dim3(1, n), dim3(256), 0, s, Gn->d_desc, kGangRounds, Gn->d_status,
-                         Gn->stride_words);
-      ok = hipGetLastError() == hipSuccess &&
-           hipMemcpyAsync(Gn->h_status, Gn->d_status, sizeof(int32_t) * Gn->stride_words * n, hipMemcpyDeviceToHost,
-                          s) == hipSuccess &&
-           hipStreamSynchronize(s) == hipSuccess;
-    }
-    std::vector<GangJob> keep;
-    for (unsigned q = 0; q < n; q++) {
-      GangJob A = active[q];
-      Job *J = A.J;
+    std::vector<std::pair<GangItem, gdp_status>> finished;
+    gang_group(ctx, Gn->bufs, active, R, finished);
+    for (auto &f : finished) {
+      Job *J = (Job *)f.first.tag;
       gdp_mesh *M = J->mesh;
-      if (!ok) {
-        gdp_mesh_free(M);
-        J->mesh = nullptr;
-        complete_job(S, J, fail(ctx, GDP_E_DEVICE, "shared round launch failed"));
-        continue;
-      }
-      const int32_t *rec = Gn->h_status + (size_t)q * Gn->stride_words;
-      DevState d;
-      DevCounters c;
-      memcpy(&d, rec, sizeof d);
-      memcpy(&c, rec + ns, sizeof c);
-      const DevCounters *h = (const DevCounters *)(rec + ns + nc);
-      const int done = std::min(d.nhist, kGangRounds);
-      for (int i = 0; i < done; i++) {
-        M->stats.push_back(round_stats_of(h[i], &J->P));
-        A.last_cand = (int64_t)h[i].ncc + h[i].nmk;
-      }
-      M->m.nV = d.nV; M->m.nT = d.nT; M->m.nS = d.nS; M->m.rounds = d.rounds;
-      M->serial = d.serial;
-      if (done > 0) {
-        A.aborts = 0;
-        A.full = false;
-      }
-      gdp_status st = GDP_OK;
-      bool finished = false;
-      if (d.halt == kHaltAbort) {
-        // nothing was written: grow and run the same round again
-        if (++A.aborts > 16) {
-          st = fail(ctx, GDP_E_NOMEM, "round keeps exceeding its buffers");
-          finished = true;
-        } else if ((st = grow_after_abort(M, c, d.full ? 0 : d.prev_fan)) != GDP_OK) {
-          finished = true;
-        } else if (hipMemsetAsync(M->d_cnt, 0, sizeof(DevCounters), s) != hipSuccess ||
-                   hipMemsetAsync(M->d_stat, 0, sizeof(StatLine) * kStatStripes, s) != hipSuccess) {
-          st = fail(ctx, GDP_E_DEVICE, "reset after an abandoned round failed");
-          finished = true;
-        }
-      } else if (d.halt != 0) {
-        st = status_of_halt(ctx, d, c);
-        finished = true;
-      }
-      if (!finished && hipMemsetAsync(&M->d_st->halt, 0, 2 * sizeof(int32_t), s) != hipSuccess) {  // halt, nhist
-        st = fail(ctx, GDP_E_DEVICE, "round state reset failed");
-        finished = true;
-      }
-      if (!finished) {
-        keep.push_back(A);
-        continue;
-      }
+      gdp_status st = f.second;
       if (st == GDP_OK && !M->arena) st = alloc_host_mirrors(M);
       if (st != GDP_OK && st != GDP_E_NOTERM) {
         gdp_mesh_free(M);
@@ -1902,17 +2057,13 @@ void gang_driver(gdp_server *S, ServerGang *Gn) {
       }
       complete_job(S, J, st);
     }
-    active.swap(keep);
   }
 }
 
 void free_server_gang(ServerGang *Gn) {
   if (!Gn) return;
   if (Gn->ctx.stream) (void)hipStreamDestroy(Gn->ctx.stream);
-  if (Gn->d_desc) (void)hipFree(Gn->d_desc);
-  if (Gn->d_status) (void)hipFree(Gn->d_status);
-  if (Gn->h_desc) (void)hipHostFree(Gn->h_desc);
-  if (Gn->h_status) (void)hipHostFree(Gn->h_status);
+  gang_bufs_free(Gn->bufs);
   delete Gn;
 }
 
@@ -2054,6 +2205,348 @@ int rounds_for(const gdp_params *P, int64_t last_cand, bool engine) {
 // ... until L is empty").  Rounds are queued in groups; the host reads the
 // device state once per group.  A round that finds a buffer short writes
 // nothing and halts the group; the host grows the buffers and runs it again.
+// ---------------------------------------------------------------------------
+// Flip-Flop rounds (insert_mode 1; steps in gdp_ff_core.h, kernels in
+// gdp_ff.hip).  Every round: Lines 3-7 as in a cavity round (full
+// collection), the Line 6 claims, S sorted into decreasing key order, the
+// splits, flip passes to the CDT, then detection and removal of redundant
+// points until none is left, final ids, compaction, the round's record.
+// The host reads the device counters between the phases.
+// ---------------------------------------------------------------------------
+inline unsigned ff_grid(int64_t n) { return (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256)); }
+
+gdp_status ff_reserve(gdp_mesh *M, int32_t np) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  if (!M->ff) {
+    M->ff = new FfBufs();
+    HIPCHECK(dalloc(&M->ff->d_c, 1));
+    HIPCHECK(hipHostMalloc((void **)&M->ff->h_c, sizeof(FfCount)));
+  }
+  FfBufs &F = *M->ff;
+  const DevMesh &m = M->m;
+  const int64_t needK = (int64_t)m.capT + 2 * (int64_t)m.capS + 2;
+  if (needK > F.capK) {
+    // the claims' output (skey0, sref0) may already hold S: keep it
+    const size_t n = (size_t)needK, o = (size_t)F.capK;
+    HIPCHECK(dgrow(&F.skey0, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.skey1, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.sref0, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.sref1, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.shist, 0, 256 * ((n + kSortPairsTile - 1) / kSortPairsTile), 0, 0, s));
+    F.capK = (int32_t)needK;
+  }
+  if (np + 1 > F.capP) {
+    const size_t n = (size_t)std::max<int64_t>({(int64_t)np + 1, (int64_t)F.capP * 3 / 2, 1024});
+    HIPCHECK(dgrow(&F.pt, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.pinfo, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.pslots, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.pab, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.alive, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.red, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.vtri, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.newid, 0, n, 0, 0, s));
+    F.capP = (int32_t)n;
+  }
+  if (m.capT > F.capT) {
+    const size_t n = (size_t)m.capT, o = (size_t)F.capT;
+    // stamps and claims keep their values (they are compared with newer ones)
+    HIPCHECK(dgrow(&F.sstamp, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.wstamp, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.tstamp, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.claim, o, n, o, 0, s));
+    HIPCHECK(dgrow(&F.grp, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.moved, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.fc0, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.fc1, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.fprio, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.list[0], 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.list[1], 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.touched, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.hole, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.mover, 0, n, 0, 0, s));
+    F.capT = (int32_t)n;
+  }
+  const int64_t need_pool = std::max<int64_t>(1 << 20, 4 * (int64_t)m.capT);
+  if (need_pool > F.pool_cap) {
+    HIPCHECK(dgrow(&F.pool, 0, (size_t)need_pool, 0, 0, s));
+    F.pool_cap = need_pool;
+  }
+  if (m.capV > F.capV) {
+    HIPCHECK(dgrow(&F.vmark, (size_t)F.capV, (size_t)m.capV, (size_t)F.capV, 0, s));
+    F.capV = m.capV;
+  }
+  if ((int64_t)m.capS + F.capP > F.capS) {
+    // cleared by every round's last kernels: no contents to keep
+    const size_t n = (size_t)m.capS + (size_t)F.capP;
+    HIPCHECK(dgrow(&F.sflag, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.mid_rank, 0, n, 0, 0, s));
+    F.capS = (int32_t)n;
+  }
+  return GDP_OK;
+}
+
+// A fresh slot stamp / pass number (the stamp arrays, claims and vertex
+// marks are cleared when the counters would overflow their fields).
+gdp_status ff_next_stamp(gdp_mesh *M, int &out) {
+  gdp_ctx *ctx = M->ctx;
+  FfBufs &F = *M->ff;
+  if (F.stamp >= (1 << 30)) {
+    HIPCHECK(hipMemsetAsync(F.sstamp, 0, sizeof(int32_t) * F.capT, ctx->stream));
+    HIPCHECK(hipMemsetAsync(F.wstamp, 0, sizeof(int32_t) * F.capT, ctx->stream));
+    HIPCHECK(hipMemsetAsync(F.tstamp, 0, sizeof(int32_t) * F.capT, ctx->stream));
+    F.stamp = 0;
+  }
+  out = ++F.stamp;
+  return GDP_OK;
+}
+gdp_status ff_next_pass(gdp_mesh *M, uint64_t &out) {
+  gdp_ctx *ctx = M->ctx;
+  FfBufs &F = *M->ff;
+  if (F.pass >= (1ull << 23)) {
+    HIPCHECK(hipMemsetAsync(F.claim, 0, sizeof(uint64_t) * F.capT, ctx->stream));
+    HIPCHECK(hipMemsetAsync(F.vmark, 0, sizeof(uint64_t) * F.capV, ctx->stream));
+    F.pass = 0;
+  }
+  out = ++F.pass;
+  return GDP_OK;
+}
+
+FfView ff_view(gdp_mesh *M, const gdp_params *P, int32_t nmk) {
+  FfBufs &F = *M->ff;
+  const DevMesh &m = M->m;
+  FfView V;
+  memset(&V, 0, sizeof V);
+  V.vxy = m.vxy; V.vkind = m.vkind; V.tv = m.tv; V.tn = m.tn; V.ts = m.ts;
+  V.sv = m.sv; V.spar = m.spar; V.spend = m.spend; V.mflag = M->mflag;
+  V.nV = m.nV; V.nT = m.nT; V.nS = m.nS; V.enc_mode = P->encroach_mode;
+  V.pt = F.pt; V.pinfo = F.pinfo; V.pab = F.pab; V.pslots = F.pslots;
+  V.alive = F.alive; V.red = F.red; V.vtri = F.vtri; V.newid = F.newid;
+  V.grp = F.grp; V.sstamp = F.sstamp; V.wstamp = F.wstamp; V.tstamp = F.tstamp; V.moved = F.moved;
+  V.claim = F.claim;
+  V.list_in = F.list[1]; V.list_out = F.list[0];
+  V.touched = F.touched; V.hole = F.hole; V.mover = F.mover;
+  V.fc0 = F.fc0; V.fc1 = F.fc1; V.fprio = F.fprio; V.cand_cap = F.capT;
+  V.vmark = F.vmark; V.sflag = F.sflag; V.mid_rank = F.mid_rank;
+  V.mid_elem = M->mid.elem; V.mid_state = M->mid.state; V.nmk = nmk;
+  V.pool = F.pool; V.pool_cap = F.pool_cap;
+  V.c = F.d_c;
+  return V;
+}
+
+gdp_status ff_read(gdp_mesh *M, FfCount &c) {
+  gdp_ctx *ctx = M->ctx;
+  FfBufs &F = *M->ff;
+  HIPCHECK(hipMemcpyAsync(F.h_c, F.d_c, sizeof(FfCount), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  c = *F.h_c;
+  if (c.err) {
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "Flip-Flop step found an inconsistent mesh (site %d; round %d, |S| %d of which %d midpoints, "
+             "%lld CDTs, %lld flips in %lld passes, %lld removals, %d slots allocated, %d freed)",
+             c.err, M->m.rounds + 1, c.np, c.nmid, (long long)c.iters, (long long)c.flips, (long long)c.passes,
+             (long long)c.removals, c.n_alloc, c.n_dead);
+    return fail(ctx, GDP_E_CAVITY, buf);
+  }
+  return GDP_OK;
+}
+
+// Flip passes until no edge is left to check.  The first input list is
+// F.list[cur], written with stamp in_stamp; est sizes the grids.
+gdp_status ff_lawson(gdp_mesh *M, FfView &V, int &cur, int &in_stamp, int tst, int64_t est) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  FfBufs &F = *M->ff;
+  gdp_status st;
+  int batch = 4;
+  for (int64_t done = 0; done < (1 << 15);) {
+    for (int q = 0; q < batch; q++, done++) {
+      V.list_in = F.list[cur];
+      V.list_out = F.list[cur ^ 1];
+      int wst;
+      uint64_t pass;
+      if ((st = ff_next_stamp(M, wst)) || (st = ff_next_pass(M, pass))) return st;
+      hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 0);
+      hipLaunchKernelGGL(kf_flip_check, dim3(ff_grid(est)), dim3(256), 0, s, V, in_stamp, pass);
+      hipLaunchKernelGGL(kf_flip_apply, dim3(ff_grid(est)), dim3(256), 0, s, V, wst, tst);
+      in_stamp = wst;
+      cur ^= 1;
+    }
+    FfCount c;
+    if ((st = ff_read(M, c))) return st;
+    if (c.n_out == 0) return GDP_OK;
+    est = c.n_out;
+    batch = std::min(batch * 2, 16);
+  }
+  return fail(ctx, GDP_E_CAVITY, "flip passes did not converge");
+}
+
+// Resets the round counters of the Flip-Flop steps (slot allocation from nT).
+gdp_status ff_reset(gdp_mesh *M) {
+  gdp_ctx *ctx = M->ctx;
+  FfBufs &F = *M->ff;
+  memset(F.h_c, 0, sizeof(FfCount));
+  F.h_c->n_alloc = M->m.nT;
+  HIPCHECK(hipMemcpyAsync(F.d_c, F.h_c, sizeof(FfCount), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  return GDP_OK;
+}
+
+// The mesh as the CDT under the symbolic perturbation, each triangle rotated
+// so its smallest vertex comes first (the state Flip-Flop rounds keep).
+gdp_status ff_canonical(gdp_mesh *M, const gdp_params *P) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  gdp_status st;
+  if ((st = ff_reserve(M, 0)) || (st = ff_reset(M))) return st;
+  FfBufs &F = *M->ff;
+  FfView V = ff_view(M, P, 0);
+  const int nT = M->m.nT;
+  hipLaunchKernelGGL(kf_rotate, dim3(ff_grid(nT)), dim3(256), 0, s, V, nT);
+  int wst, tst;
+  if ((st = ff_next_stamp(M, wst)) || (st = ff_next_stamp(M, tst))) return st;
+  V.list_out = F.list[0];
+  hipLaunchKernelGGL(kf_all_slots, dim3(ff_grid(nT)), dim3(256), 0, s, V, nT, wst);
+  int cur = 0, in_stamp = wst;
+  if ((st = ff_lawson(M, V, cur, in_stamp, tst, nT))) return st;
+  return ff_reset(M);
+}
+
+// One Flip-Flop round after the Line 3-7 kernels and the claims have run and
+// the host has read the counts.  *recorded: the round was completed and
+// recorded; *stall: it inserted nothing and flagged nothing.
+gdp_status ff_line8(gdp_mesh *M, const gdp_params *P, int32_t np, int32_t nmid, int32_t nmk, bool *stall) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  FfBufs &F = *M->ff;
+  gdp_status st;
+  *stall = false;
+  const DevMesh &m = M->m;
+  // room: np vertices, 2 np slots, nmid subsegments (provisional second halves)
+  if ((st = grow_vtx(M, m.nV + np + 16)) || (st = grow_tri(M, m.nT + 2 * np + 16)) ||
+      (st = grow_seg(M, m.nS + nmid + 16)) || (st = grow_cand(M)) || (st = ff_reserve(M, np)))
+    return st;
+  Work w = make_work(M, P, 0);
+  FfView V = ff_view(M, P, nmk);
+  // S in decreasing key order (the keys were stored complemented)
+  if (np > 0) HIPCHECK(sort_pairs_u64(s, F.skey0, F.sref0, F.skey1, F.sref1, np, F.shist));
+  hipLaunchKernelGGL(kf_gather, dim3(ff_grid(np)), dim3(256), 0, s, M->m, w, V, (const int32_t *)F.sref1);
+  int wst, tst, split_stamp;
+  if ((st = ff_next_stamp(M, wst)) || (st = ff_next_stamp(M, tst)) || (st = ff_next_stamp(M, split_stamp)))
+    return st;
+  V.list_out = F.list[0];
+  hipLaunchKernelGGL(kf_split, dim3(ff_grid(np)), dim3(256), 0, s, V, split_stamp, wst, tst);
+  hipLaunchKernelGGL(kf_split_fix, dim3(ff_grid(np)), dim3(256), 0, s, V, split_stamp);
+  int cur = 0, in_stamp = wst;
+  if ((st = ff_lawson(M, V, cur, in_stamp, tst, 3 * (int64_t)np))) return st;
+  FfCount c;
+  for (int it = 0;; it++) {
+    if (it > (1 << 16)) return fail(ctx, GDP_E_CAVITY, "redundant points keep appearing");
+    if ((st = ff_read(M, c))) return st;
+    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 2);
+    hipLaunchKernelGGL(kf_vtri, dim3(ff_grid(c.n_touched)), dim3(256), 0, s, V);
+    hipLaunchKernelGGL(kf_detect, dim3(ff_grid(np)), dim3(256), 0, s, V);
+    if ((st = ff_read(M, c))) return st;
+    if (c.n_red == 0) break;
+    // removal passes; their triangles form the next flip worklist
+    if ((st = ff_next_stamp(M, wst))) return st;
+    V.list_out = F.list[cur];
+    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 3);
+    for (int pass_i = 0;; pass_i++) {
+      if (pass_i > (1 << 16)) return fail(ctx, GDP_E_CAVITY, "removal passes did not finish");
+      uint64_t pass;
+      if ((st = ff_next_pass(M, pass))) return st;
+      const uint64_t pbase = pass << 32;
+      hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 1);
+      hipLaunchKernelGGL(kf_rm_mark, dim3(ff_grid(np)), dim3(256), 0, s, V, pbase);
+      hipLaunchKernelGGL(kf_rm_decide, dim3(ff_grid(np)), dim3(256), 0, s, V, pbase);
+      hipLaunchKernelGGL(kf_rm_apply, dim3(ff_grid(np)), dim3(256), 0, s, V, wst, tst);
+      if ((st = ff_read(M, c))) return st;
+      if (c.n_left == 0) break;
+      if (c.pool_short) {
+        // a removal found no room in the pool: grow it (nothing is in flight)
+        const int64_t nc = F.pool_cap * 2;
+        HIPCHECK(dgrow(&F.pool, 0, (size_t)nc, 0, 0, s));
+        F.pool_cap = nc;
+        V.pool = F.pool;
+        V.pool_cap = nc;
+      }
+    }
+    in_stamp = wst;
+    if ((st = ff_lawson(M, V, cur, in_stamp, tst, c.n_out))) return st;
+  }
+  // final ids, renumbering, pending flags
+  hipLaunchKernelGGL(kf_newid, dim3(1), dim3(1024), 0, s, V);
+  hipLaunchKernelGGL(kf_final_point, dim3(ff_grid(np)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(kf_final_tri, dim3(ff_grid(c.n_touched)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(kf_final_mid, dim3(ff_grid(nmk)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(kf_final_flag, dim3(ff_grid(m.nS)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(kf_final_flag_clear, dim3(ff_grid(nmid)), dim3(256), 0, s, V);
+  if ((st = ff_read(M, c))) return st;
+  // compaction: live triangles above the final count fill the holes
+  const int n_alloc = c.n_alloc, n_live = c.n_alloc - c.n_dead;
+  hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 4);
+  hipLaunchKernelGGL(kf_compact_list, dim3(ff_grid(n_alloc)), dim3(256), 0, s, V, n_alloc, n_live);
+  hipLaunchKernelGGL(kf_compact_move, dim3(ff_grid(c.n_dead)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(kf_compact_fix, dim3(ff_grid(c.n_dead)), dim3(256), 0, s, V, n_live);
+  if (c.nwin == 0 && c.flags == 0) {
+    *stall = true;
+    return GDP_OK;
+  }
+  hipLaunchKernelGGL(kf_round_end, dim3(1), dim3(256), 0, s, w, (const FfCount *)F.d_c, n_live, c.nwin, c.nwin_mid);
+  HIPCHECK(hipGetLastError());
+  return GDP_OK;
+}
+
+gdp_status ff_loop(gdp_mesh *M, double B2, const gdp_params *P) {
+  gdp_ctx *ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  DevMesh &m = M->m;
+  gdp_status st;
+  if ((st = ff_canonical(M, P))) return st;
+  for (;;) {
+    if (m.nV >= (1 << 22)) return fail(ctx, GDP_E_INPUT, "priority mode 2 keys hold vertex ids below 2^22");
+    if ((st = ff_reserve(M, 0)) || (st = ff_reset(M))) return st;
+    FfBufs &F = *M->ff;
+    Work w = make_work(M, P, 0);
+    const int bs = P->block_size;
+    const int64_t ncand = enqueue_select(M, B2, P, true, m.nT, w);
+    hipLaunchKernelGGL(kf_claim_cc, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+    hipLaunchKernelGGL(kf_claim_mid, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, m, w);
+    hipLaunchKernelGGL(kf_own, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w, F.d_c, F.skey0, F.sref0);
+    hipLaunchKernelGGL(kf_clear_marks, dim3(stride_grid(ncand, bs)), dim3(bs), 0, s, w);
+    HIPCHECK(hipMemcpyAsync(M->h_st, M->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(M->h_cnt, M->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    FfCount c;
+    if ((st = ff_read(M, c))) return st;
+    const DevState d = *M->h_st;
+    const DevCounters &dc = *M->h_cnt;
+    if (d.halt == kHaltDone) return GDP_OK;
+    if (d.halt == kHaltCap) return fail(ctx, GDP_E_NOTERM, "round cap reached");
+    if (dc.err & kErrWalk) return fail(ctx, GDP_E_WALK, "locate walk exceeded its step cap");
+    if (dc.err & kErrInput)
+      return fail(ctx, GDP_E_INPUT, "a walk left the mesh through a hull edge that is not a subsegment");
+    if (c.np == 0) return fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing");
+    bool stall = false;
+    if ((st = ff_line8(M, P, c.np, c.nmid, dc.nmk, &stall))) return st;
+    if (stall) {
+      // the mesh is whole (the points were all taken out again); nothing
+      // was recorded
+      HIPCHECK(hipStreamSynchronize(s));
+      return fail(ctx, GDP_E_STALL, "round had candidates but inserted nothing");
+    }
+    HIPCHECK(hipMemcpyAsync(M->h_st, M->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(M->h_hist, M->d_hist, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const DevState e = *M->h_st;
+    M->stats.push_back(round_stats_of(M->h_hist[0], P));
+    m.nV = e.nV; m.nT = e.nT; m.nS = e.nS; m.rounds = e.rounds;
+    M->serial = e.serial;
+    HIPCHECK(hipMemsetAsync(&M->d_st->halt, 0, 2 * sizeof(int32_t), s));  // halt, nhist
+  }
+}
+
 gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
@@ -2083,7 +2576,8 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   int64_t last_cand = (int64_t)m.nT + m.nS;
   int64_t prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
   int aborts = 0;
-  for (;;) {
+  if (P->insert_mode == 1) result = ff_loop(M, B2, P);
+  else for (;;) {
     // small rounds run in the single-workgroup engine
     const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
     const bool engine = !full && !M->engine_off && eng_max > 0 && last_cand <= eng_max;
@@ -2374,8 +2868,15 @@ static gdp_status check_params(gdp_ctx *ctx, const gdp_params *params, gdp_param
   if (P.prefilter_f1 != 0 && P.prefilter_f1 != 1) return fail(ctx, GDP_E_ARG, "prefilter_f1 must be 0 or 1");
   if (P.cavity_approx_n < 0 || P.cavity_approx_n > kApproxMaxN)
     return fail(ctx, GDP_E_ARG, "cavity_approx_n must be in [0, 16]");
-  if (P.cand_cap_K < 0 || P.max_rounds < 0 || (P.priority_mode != 0 && P.priority_mode != 1))
+  if (P.cand_cap_K < 0 || P.max_rounds < 0 || P.priority_mode < 0 || P.priority_mode > 2)
     return fail(ctx, GDP_E_ARG, "bad parameter");
+  if (P.insert_mode != 0 && P.insert_mode != 1) return fail(ctx, GDP_E_ARG, "insert_mode must be 0 or 1");
+  if (P.insert_mode == 1 && P.priority_mode != 2)
+    return fail(ctx, GDP_E_ARG, "Flip-Flop insertion needs priority_mode 2 (keys independent of slots)");
+  // the cavity kernels recover a mark's owner from the perm32 tie-break in
+  // the low half of its key, which mode 2 keys do not carry
+  if (P.insert_mode == 0 && P.priority_mode == 2)
+    return fail(ctx, GDP_E_ARG, "priority_mode 2 is for Flip-Flop insertion (insert_mode 1)");
   if (P.block_size < 64 || P.block_size > 1024 || P.block_size % 64) return fail(ctx, GDP_E_ARG, "bad block size");
   if (P.reserve_mode != 0 && P.reserve_mode != 1) return fail(ctx, GDP_E_ARG, "bad reserve mode");
   if (P.rounds_per_sync < 0 || P.rounds_per_sync > kHistCap)
@@ -2384,6 +2885,10 @@ static gdp_status check_params(gdp_ctx *ctx, const gdp_params *params, gdp_param
   if (P.split_mode != 0 && P.split_mode != 1) return fail(ctx, GDP_E_ARG, "split_mode must be 0 or 1");
   if (!(P.max_edge_len_sq >= 0.0) || !std::isfinite(P.max_edge_len_sq))
     return fail(ctx, GDP_E_ARG, "max_edge_len_sq must be finite and >= 0");
+  if (P.batch_engine_max_v < 0) return fail(ctx, GDP_E_ARG, "batch_engine_max_v must be >= 0");
+  if (P.cavity_thread_cap != 0 && P.cavity_thread_cap != 12 && P.cavity_thread_cap != 24 &&
+      P.cavity_thread_cap != kCavCapDefault)
+    return fail(ctx, GDP_E_ARG, "cavity_thread_cap must be 0, 12, 24 or 39");
   return GDP_OK;
 }
 
@@ -2405,6 +2910,7 @@ gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *r
   gdp_params P;
   gdp_status st;
   if ((st = check_params(ctx, params, P))) return st;
+  if (P.insert_mode != 0) return fail(ctx, GDP_E_ARG, "the batched form runs cavity insertion only");
   for (int32_t i = 0; i < count; i++)
     if (!(ratio_bound_sq[i] > 0.0) || !std::isfinite(ratio_bound_sq[i])) return fail(ctx, GDP_E_ARG, "bad ratio bound");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, GDP_E_DEVICE, "hipSetDevice failed");
@@ -2826,12 +3332,8 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
   }
   ServerGang *Gn = new ServerGang();
   Gn->ctx.device = ctx->device;
-  Gn->stride_words = (int)((sizeof(DevState) + (1 + kGangRounds) * sizeof(DevCounters)) / 4);
   ok = hipStreamCreateWithFlags(&Gn->ctx.stream, hipStreamNonBlocking) == hipSuccess &&
-       dalloc(&Gn->d_desc, max_slots) == hipSuccess &&
-       hipHostMalloc((void **)&Gn->h_desc, sizeof(GangDesc) * max_slots) == hipSuccess &&
-       dalloc(&Gn->d_status, (size_t)Gn->stride_words * max_slots) == hipSuccess &&
-       hipHostMalloc((void **)&Gn->h_status, sizeof(int32_t) * Gn->stride_words * max_slots) == hipSuccess;
+       gang_bufs_alloc(Gn->bufs, max_slots);
   if (!ok) {
     free_server_gang(Gn);
     free_server_engine(E);
@@ -2859,10 +3361,11 @@ gdp_status gdp_server_create(gdp_ctx *ctx, size_t hbm_budget, int32_t max_slots,
   return GDP_OK;
 }
 
-gdp_status gdp_server_mode(gdp_server *srv, int32_t mode) {
-  if (!srv || mode < 0 || mode > 1) return GDP_E_ARG;
+gdp_status gdp_server_mode(gdp_server *srv, int32_t mode, int32_t rounds_per_group) {
+  if (!srv || mode < 0 || mode > 1 || rounds_per_group < 0 || rounds_per_group > kGangRoundsMax) return GDP_E_ARG;
   std::lock_guard<std::mutex> g(srv->mu);
   srv->mode = mode;
+  srv->gang_rounds = rounds_per_group ? rounds_per_group : kGangRounds;
   srv->cv.notify_all();
   return GDP_OK;
 }
@@ -2881,6 +3384,7 @@ gdp_status gdp_server_prepare(gdp_server *srv, const gdp_pslg *pslg, double rati
   gdp_params P;
   gdp_status st;
   if ((st = check_params(srv->user, params, P))) return st;
+  if (P.insert_mode != 0) return fail(srv->user, GDP_E_ARG, "the serving form runs cavity insertion only");
   if (!(ratio_bound_sq > 0.0) || !std::isfinite(ratio_bound_sq)) return fail(srv->user, GDP_E_ARG, "bad ratio bound");
   Job *J = new Job();
   if ((st = prepare_job(srv, pslg, ratio_bound_sq, &P, J))) {

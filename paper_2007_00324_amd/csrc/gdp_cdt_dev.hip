@@ -958,6 +958,13 @@ int grid_for(int n, int blk) { return std::max(1, std::min((n + blk - 1) / blk, 
 
 }  // namespace
 
+// Sorts n (64-bit key, int) pairs by the whole key (8 digit passes); the
+// result ends in (k1, v1).  hist holds 256 * ceil(n / 2048) ints.
+static_assert(kSortPairsTile == kSortTile, "the sort's tile as declared in gdp_internal.h");
+hipError_t sort_pairs_u64(hipStream_t stream, uint64_t *k0, int *v0, uint64_t *k1, int *v1, int n, int *hist) {
+  return radix_sort_pairs(stream, k0, v0, k1, v1, n, 32, hist);
+}
+
 // Builds the CDT of the PSLG whose vertices (nv, the first nv entries of
 // d_xy, which has room for nv + 3) and segments (d_seg) are on the device;
 // writes the canonical triangles to otv / otn / ots (capacity cap_out) and

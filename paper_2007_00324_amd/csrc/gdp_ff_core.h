@@ -46,6 +46,9 @@ struct FfCount {
   int32_t n_hole, n_mover;
   int32_t err;            // first inconsistency found (site number), 0 none
   int32_t flags;          // subsegments newly flagged by encroaching circumcenters
+  int32_t nwin, nwin_mid; // points of S kept, of which midpoints (after the last pass)
+  int32_t cand_over;      // a pass found more flip candidates than the list holds
+  int32_t pad;
   int64_t flips, removals, n_dep, n_enc, iters, passes;
 };
 
@@ -76,6 +79,7 @@ struct FfView {
   int32_t *list_in, *list_out, *touched, *hole, *mover;
   int4 *fc0, *fc1;        // flip candidates: (t, e, o, j), the four outer slots
   uint64_t *fprio;
+  int32_t cand_cap;
   // per vertex / subsegment
   uint64_t *vmark;
   int32_t *sflag;         // [nS + nmid] flagged by an encroaching circumcenter (provisional ids)
@@ -156,6 +160,13 @@ GDP_HD void ff_wrote(const FfView &V, int slot, int wstamp, int tstamp) {
   ff_push<O>(V.touched, &V.c->n_touched, V.tstamp, tstamp, slot);
 }
 
+// Every point of S starts in the mesh and not redundant.
+template <class O>
+GDP_HD void ff_init_point_one(const FfView &V, int r) {
+  V.alive[r] = 1;
+  V.red[r] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Insertion by splits (every claimed triangle is split by one point)
 // ---------------------------------------------------------------------------
@@ -220,6 +231,7 @@ GDP_HD void ff_split_one(const FfView &V, int r, int split_stamp, int wst, int t
     const int e0 = info.y;
     const int4 a0 = V.tv[t0];
     const int t1 = ffc(V.tn[t0], e0);
+    if (t1 < 0) { O::err(&V.c->err, 20); return; }
     const int e1 = ff_eidx(V.tv[t1], ffc(a0, (e0 + 1) % 3), ffc(a0, e0));
     if (e1 < 0) { O::err(&V.c->err, 1); return; }
     ff_split_edge<O>(V, r, p, t0, e0, t1, e1, -1, -1, split_stamp, wst, tst);
@@ -304,21 +316,36 @@ GDP_HD void ff_flip_check_one(const FfView &V, int i, int in_stamp, uint64_t pas
     const int n_vw = ffc(na, (e + 1) % 3), n_wu = ffc(na, (e + 2) % 3);
     const int n_ud = ffc(nb, (j + 1) % 3), n_dv = ffc(nb, (j + 2) % 3);
     const uint64_t prio = (pass << 40) | (uint64_t)(t < o ? 4 * (int64_t)t + e : 4 * (int64_t)o + j);
+    const int idx = O::add(&V.c->n_cand, 1);
+    if (idx >= V.cand_cap) {
+      // no room (and no claims, so the stored candidates still make
+      // progress): the whole input list goes to the next pass
+      O::or32(&V.c->cand_over, 1);
+      continue;
+    }
     O::max64(&V.claim[t], prio);
     O::max64(&V.claim[o], prio);
     if (n_vw >= 0) O::max64(&V.claim[n_vw], prio);
     if (n_wu >= 0) O::max64(&V.claim[n_wu], prio);
     if (n_ud >= 0) O::max64(&V.claim[n_ud], prio);
     if (n_dv >= 0) O::max64(&V.claim[n_dv], prio);
-    const int idx = O::add(&V.c->n_cand, 1);
     V.fc0[idx] = make_int4(t, e, o, j);
     V.fc1[idx] = make_int4(n_vw, n_wu, n_ud, n_dv);
     V.fprio[idx] = prio;
   }
 }
 
+// After a pass whose candidates overflowed their list: every triangle of the
+// input list is checked again in the next pass.
+template <class O>
+GDP_HD void ff_flip_requeue_one(const FfView &V, int i, int wst) {
+  const int t = V.list_in[i];
+  if (V.tv[t].x >= 0) ff_push<O>(V.list_out, &V.c->n_out, V.wstamp, wst, t);
+}
+
 template <class O>
 GDP_HD void ff_flip_apply_one(const FfView &V, int i, int wst, int tst) {
+  if (i >= V.cand_cap) return;
   const int4 f = V.fc0[i], g = V.fc1[i];
   const uint64_t prio = V.fprio[i];
   const int t = f.x, e = f.y, o = f.z, j = f.w;
@@ -496,18 +523,31 @@ GDP_HD int ff_clip(const FfView &V, int m, int *pv, int *info, int *sd, int *nx,
   return ne + 1;
 }
 
+// After all marks: a point that holds every mark of itself and its
+// neighbours is removed in this pass (bit 4 of red); the others wait.  This
+// reads the mesh only, so the removals of the pass start from whole stars.
 template <class O>
-GDP_HD void ff_rm_apply_one(const FfView &V, int r, uint64_t pbase, int wst, int tst) {
+GDP_HD void ff_rm_decide_one(const FfView &V, int r, uint64_t pbase) {
   if (!V.alive[r] || !V.red[r]) return;
   const int p = V.nV + r;
   const uint64_t prio = pbase | (uint64_t)(r + 1);
   bool own = V.vmark[p] == prio, open;
-  int k = ff_star(V, p, V.vtri[r], open, [&](int t, int i) {
+  const int k = ff_star(V, p, V.vtri[r], open, [&](int t, int i) {
     const int4 tri = V.tv[t];
     if (V.vmark[ffc(tri, (i + 1) % 3)] != prio || V.vmark[ffc(tri, (i + 2) % 3)] != prio) own = false;
   });
   if (k == 0) { O::err(&V.c->err, 9); return; }
-  if (!own) { O::add(&V.c->n_left, 1); return; }
+  if (own) V.red[r] |= 4;
+  else O::add(&V.c->n_left, 1);
+}
+
+template <class O>
+GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
+  if (!V.alive[r] || !(V.red[r] & 4)) return;
+  const int p = V.nV + r;
+  bool open;
+  const int k = ff_star(V, p, V.vtri[r], open, [&](int, int) {});
+  if (k == 0) { O::err(&V.c->err, 19); return; }
   // pool layout, k + 2 entries each: ring, star, outer neighbour, outer
   // subsegment; then the clipping arrays and up to k emitted triangles
   const int64_t L = k + 2;
@@ -516,6 +556,7 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, uint64_t pbase, int wst, int
   if (base + need > V.pool_cap) {
     O::or32(&V.c->pool_short, 1);
     O::add(&V.c->n_left, 1);
+    V.red[r] &= 3;  // tried again in the next pass
     return;
   }
   int *ring = V.pool + base, *star = ring + L, *onb = star + L, *osd = onb + L;

@@ -33,6 +33,10 @@ int host_cdt_build(int32_t nv, const double *xy, int32_t ns, const int32_t *seg,
 struct DevCdtStats {
   int32_t dt_rounds = 0, seg_rounds = 0;
 };
+// Radix sort of (64-bit key, int) pairs on the stream (gdp_cdt_dev.hip); the
+// sorted pairs end in (k1, v1); hist: 256 * ceil(n / kSortPairsTile) ints.
+constexpr int kSortPairsTile = 2048;
+hipError_t sort_pairs_u64(hipStream_t stream, uint64_t *k0, int *v0, uint64_t *k1, int *v1, int n, int *hist);
 int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, const int2 *d_seg, int4 *otv,
                   int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err);
 
@@ -92,6 +96,12 @@ struct DevCounters {
   int64_t win_cc_cav;   // |C| and b of the circumcenter winners alone
   int64_t win_cc_bnd;
   int64_t n_marks[2];   // priority marks placed (atomicMax): midpoint, circumcenter cavities
+  // Flip-Flop rounds (Section 4.3, Line 8)
+  int64_t ff_points;    // points of S added
+  int64_t ff_iters;     // CDTs examined for redundant points
+  int64_t ff_flips;     // 2-2 flips
+  int64_t ff_passes;    // flip passes
+  int64_t ff_removals;  // redundant points taken out
 };
 static_assert(sizeof(DevCounters) % 8 == 0, "DevCounters is copied as 32-bit words");
 static_assert(offsetof(DevCounters, nmk) == 128, "the midpoint append counter starts the second line");

@@ -1,6 +1,7 @@
 // gdp_kernels.h -- kernel interface of one refinement round.
 #pragma once
 
+#include "gdp_ff_core.h"
 #include "gdp_internal.h"
 
 namespace gdp {
@@ -82,7 +83,8 @@ __global__ void k_apply_cap(Work w);
 __global__ void k_locate(DevMesh m, Work w);
 __global__ void k_prefilter(DevMesh m, Work w, int mode, int n);
 constexpr int kApproxMaxN = 16;
-template <int IS_CC>
+constexpr int kCavCapDefault = 39;  // per-thread cavity slots of the grid kernel (LDS per 128-thread block)
+template <int IS_CC, int CAP>
 __global__ void k_cavity(DevMesh m, Work w);
 __global__ void k_cavity_big(DevMesh m, Work w, int phase);
 __global__ void k_cavity_huge(DevMesh m, Work w, int phase);
@@ -152,6 +154,42 @@ __global__ void kg_finish(const GangDesc *G);
 // Copies each mesh's DevState, running counters and first `rounds` history
 // records to out + y * stride_words (32-bit words), for one host read.
 __global__ void kg_status(const GangDesc *G, int rounds, int32_t *out, int stride_words);
+
+// Flip-Flop insertion (Section 4.3, Line 8; gdp_ff_core.h).  Line 6 of such
+// a round: every located circumcenter and midpoint claims the triangles it
+// would split with atomicMax of its key (a circumcenter on a subsegment
+// flags it instead); a point that holds all its claims goes to S as the pair
+// (~key, reference) for the sort into decreasing key order; kf_gather then
+// lays S out by rank.  The round ends with kf_round_end (one workgroup).
+__global__ void kf_claim_cc(DevMesh m, Work w);
+__global__ void kf_claim_mid(DevMesh m, Work w);
+__global__ void kf_own(Work w, FfCount *f, uint64_t *skey, int32_t *sref);
+__global__ void kf_clear_marks(Work w);
+__global__ void kf_gather(DevMesh m, Work w, FfView V, const int32_t *sref);
+__global__ void kf_round_end(Work w, const FfCount *f, int32_t nT_new, int32_t nwin, int32_t nwin_mid);
+// ... and the steps themselves (gdp_ff.hip): grid-stride loops over the
+// elements, counts read from device memory where they change on the device.
+__global__ void kf_split(FfView V, int split_stamp, int wst, int tst);
+__global__ void kf_split_fix(FfView V, int split_stamp);
+__global__ void kf_ctl(FfCount *c, int op);
+__global__ void kf_flip_check(FfView V, int in_stamp, uint64_t pass);
+__global__ void kf_flip_apply(FfView V, int wst, int tst);
+__global__ void kf_vtri(FfView V);
+__global__ void kf_detect(FfView V);
+__global__ void kf_rm_mark(FfView V, uint64_t pbase);
+__global__ void kf_rm_decide(FfView V, uint64_t pbase);
+__global__ void kf_rm_apply(FfView V, int wst, int tst);
+__global__ void kf_newid(FfView V);  // one workgroup: exclusive scan of alive -> newid
+__global__ void kf_final_point(FfView V);
+__global__ void kf_final_tri(FfView V);
+__global__ void kf_final_mid(FfView V);
+__global__ void kf_final_flag(FfView V);
+__global__ void kf_final_flag_clear(FfView V);
+__global__ void kf_compact_list(FfView V, int n_alloc, int n_live);
+__global__ void kf_compact_move(FfView V);
+__global__ void kf_compact_fix(FfView V, int n_live);
+__global__ void kf_rotate(FfView V, int n);
+__global__ void kf_all_slots(FfView V, int n, int wst);  // every slot onto the worklist
 
 constexpr int kCavBlockSize = 128;
 constexpr int kBigBlockSize = 256;

@@ -1,5 +1,5 @@
 // gdp_kernels.hip -- gfx950 kernels of one refinement round (Algorithm 1,
-// Lines 3-8 of gDP2d, with cavity insertion as in Section 5.1).
+// Lines 3-8 of gDP2d, with cavity insertion as in Section 5.2).
 //
 // Every kernel works on a slot-indexed structure-of-arrays mesh in HBM.  The
 // round is deterministic: candidate lists are built with atomics in any
@@ -106,7 +106,11 @@ __device__ SplitPt tri_split(const DevMesh &m, int t, int4 tri, double B2, doubl
     q = 0;
   }
   if (pm == 1) q = 0;
-  r.key = (q << 32) | (uint64_t)perm32((uint32_t)t);
+  // mode 2: a tie-break that does not depend on the slot (the first two ids
+  // of the rotation that starts at the smallest id, 22 bits each), above it
+  // the measure reduced to 19 bits
+  if (pm == 2) r.key = ((q >> 12) << 44) | ((uint64_t)ia << 22) | (uint64_t)ib;
+  else r.key = (q << 32) | (uint64_t)perm32((uint32_t)t);
   r.d = d;
   return r;
 }
@@ -772,7 +776,7 @@ struct CavCheck {
 // per-thread cavity capacity of the grid kernel: 39 slots x 128 threads (plus
 // a few bytes) is the most LDS that still lets 8 workgroups (16 waves) share a
 // compute unit's 160 KB; larger cavities go to the cooperative kernel
-constexpr int kCap = 39;
+constexpr int kCap = kCavCapDefault;
 // per-lane statistics of a per-thread cavity (size, boundary edges, circle
 // tests: at most three per slot) stay below 2^10 (see stat_add4)
 constexpr int kStat4Cap = 1023 / 3 - 2;
@@ -1000,18 +1004,24 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
 }
 
 // One kernel symbol per class (circumcenters: IS_CC = 1), so that profiles
-// tell them apart.
-template <int IS_CC>
+// tell them apart, and per slice length CAP (the per-thread capacity; a
+// cavity beyond it goes to the cooperative path: perf only).
+template <int IS_CC, int CAP>
 __global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w) {
-  __shared__ int32_t lds[kCap * kCavBlock];
+  static_assert(CAP <= kStat4Cap, "per-thread cavity statistics fit stat_add4");
+  __shared__ int32_t lds[CAP * kCavBlock];
   if (w.st->halt) return;
-  cavity_part(m, w, IS_CC, lds, kCavBlock, kCap, grid_lanes());
+  cavity_part(m, w, IS_CC, lds, kCavBlock, CAP, grid_lanes());
 }
-template __global__ void k_cavity<0>(DevMesh m, Work w);
-template __global__ void k_cavity<1>(DevMesh m, Work w);
+template __global__ void k_cavity<0, kCap>(DevMesh m, Work w);
+template __global__ void k_cavity<1, kCap>(DevMesh m, Work w);
+template __global__ void k_cavity<0, 24>(DevMesh m, Work w);
+template __global__ void k_cavity<1, 24>(DevMesh m, Work w);
+template __global__ void k_cavity<0, 12>(DevMesh m, Work w);
+template __global__ void k_cavity<1, 12>(DevMesh m, Work w);
 
 // Cooperative growth of one large cavity per workgroup (the tuple-parallel
-// ExpandList idea of Section 5.2: the frontier of <point, triangle> tuples
+// ExpandList idea of Section 5.3: the frontier of <point, triangle> tuples
 // is processed in parallel, new tuples are reserved with atomics).
 constexpr int kBigMax = 4096;
 constexpr int kHash = 16384;
@@ -1853,10 +1863,10 @@ __device__ __forceinline__ void finish_one(const DevMesh &m, const Work &w, int 
 // round's lists become the previous ones and the counters are cleared for
 // the next round.  An error, an abandoned round or a round without winners
 // halts instead (the counters stay for the host to read).
-__device__ __forceinline__ void round_end(const Work &w) {
-  __shared__ int s_go, s_slot;
+// Folds the stat lines into the round counters and clears them (one
+// workgroup; ends with a barrier).
+__device__ __forceinline__ void round_fold(const Work &w) {
   __shared__ uint64_t s_fold[kStFields];
-  DevState *st = w.st;
   DevCounters *c = w.cnt;
   // fold the stat lines into the counters and clear them (read-and-clear
   // atomics: the lines were written by atomics)
@@ -1902,6 +1912,13 @@ __device__ __forceinline__ void round_end(const Work &w) {
     c->n_marks[1] += (int64_t)s_fold[kStMarks1];
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void round_end(const Work &w) {
+  __shared__ int s_go, s_slot;
+  DevState *st = w.st;
+  DevCounters *c = w.cnt;
+  round_fold(w);
   if (threadIdx.x == 0) {
     s_go = 0;
     s_slot = -1;
@@ -1966,6 +1983,209 @@ __global__ void k_finish(DevMesh m, Work w) {
   __threadfence();
   if (threadIdx.x == 0) w.st->done_blocks = 0;
   round_end(w);
+}
+
+// ---------------------------------------------------------------------------
+// Flip-Flop rounds (Section 4.3): Line 6 claims and the end of the round.
+// ---------------------------------------------------------------------------
+// Edge of the located triangle a circumcenter lies on, + 1, kept in bits 8-9
+// of its state (0: strictly inside).
+constexpr int kFfEdgeShift = 8;
+
+// A located circumcenter claims its triangle, or both triangles of the
+// interior edge it lies on; one on a subsegment encroaches it and flags it.
+__global__ void kf_claim_cc(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const Lanes L = grid_lanes();
+  const int ncc = w.cnt->ncc;
+  int n_rej = 0;
+  for (int base = L.base0; base < ncc; base += L.stride) {
+    const int c = base + threadIdx.x;
+    if (c >= ncc) continue;
+    const int st = w.cc.state[c];
+    if (!(st & kStFound) || (st & kStDone)) continue;
+    const int loc = w.cc.loc[c];
+    const int4 tri = m.tv[loc];
+    const double2 p = w.cc.p[c];
+    const double2 A = m.vxy[tri.x], B = m.vxy[tri.y], C = m.vxy[tri.z];
+    const int s0 = orient_pts(w, A, B, p), s1 = orient_pts(w, B, C, p), s2 = orient_pts(w, C, A, p);
+    const int e = s0 == 0 ? 0 : (s1 == 0 ? 1 : (s2 == 0 ? 2 : -1));
+    int c1 = -1;
+    if (e >= 0) {
+      if ((tri.w >> e) & 1) {
+        flag_mid(w, comp(m.ts[loc], e));
+        w.cc.state[c] = st | kStDone;
+        n_rej++;
+        continue;
+      }
+      c1 = comp(m.tn[loc], e);
+    }
+    const uint64_t key = w.cc.key[c];
+    w.cc.off[c] = loc;
+    w.cc.len[c] = c1;
+    w.cc.state[c] = (st & ~(3 << kFfEdgeShift)) | ((e + 1) << kFfEdgeShift);
+    atomicMax((unsigned long long *)&w.mark[loc], (unsigned long long)key);
+    if (c1 >= 0) atomicMax((unsigned long long *)&w.mark[c1], (unsigned long long)key);
+  }
+  stat_add(w, kStEncReject, n_rej);
+}
+
+// A flagged subsegment's split point claims the triangles on its sides
+// (4 * slot + edge of each, -1 none); an unsplittable one is dropped.
+__global__ void kf_claim_mid(DevMesh m, Work w) {
+  if (w.st->halt) return;
+  const Lanes L = grid_lanes();
+  const int nmk = w.cnt->nmk;
+  int n_cand = 0, n_uns = 0;
+  for (int base = L.base0; base < nmk; base += L.stride) {
+    const int i = base + threadIdx.x;
+    if (i >= nmk) continue;
+    const int st = w.mid.state[i];
+    if (st & kStSkip) continue;
+    const int k = w.mid.elem[i];
+    n_cand++;
+    const SplitPt sp = seg_split(m, k, w.pm, w.split_mode);
+    const int2 s = m.sv[k];
+    const double2 A = m.vxy[s.x], B = m.vxy[s.y];
+    if ((sp.px == A.x && sp.py == A.y) || (sp.px == B.x && sp.py == B.y)) {
+      w.mid.state[i] = st | kStDone;
+      n_uns++;
+      continue;
+    }
+    const int c0 = w.sadj[2 * k], c1 = w.sadj[2 * k + 1];
+    w.mid.key[i] = sp.key;
+    w.mid.p[i] = make_double2(sp.px, sp.py);
+    w.mid.off[i] = c0;
+    w.mid.len[i] = c1;
+    w.mid.state[i] = st | kStFound;
+    if (c0 >= 0) atomicMax((unsigned long long *)&w.mark[c0 >> 2], (unsigned long long)sp.key);
+    if (c1 >= 0) atomicMax((unsigned long long *)&w.mark[c1 >> 2], (unsigned long long)sp.key);
+  }
+  stat_add(w, kStMidCand, n_cand);
+  stat_add(w, kStUnsplittable, n_uns);
+}
+
+// Points that hold every claim go to S (midpoint references have bit 30).
+__global__ void kf_own(Work w, FfCount *f, uint64_t *skey, int32_t *sref) {
+  if (w.st->halt) return;
+  const Lanes L = grid_lanes();
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  int n_lost = 0;
+  for (int base = L.base0; base < n; base += L.stride) {
+    const int c = base + threadIdx.x;
+    if (c >= n) continue;
+    const bool is_cc = c < ncc;
+    const int ci = is_cc ? c : c - ncc;
+    const CandSet &S = is_cc ? w.cc : w.mid;
+    const int st = S.state[ci];
+    if (!(st & kStFound) || (st & (kStDone | kStSkip))) continue;
+    const uint64_t key = S.key[ci];
+    int c0 = S.off[ci], c1 = S.len[ci];
+    if (!is_cc) {
+      c0 = c0 >= 0 ? c0 >> 2 : -1;
+      c1 = c1 >= 0 ? c1 >> 2 : -1;
+    }
+    const bool own = (c0 < 0 || w.mark[c0] == key) && (c1 < 0 || w.mark[c1] == key);
+    if (!own) { n_lost++; continue; }
+    const int idx = atomicAdd(&f->np, 1);
+    skey[idx] = ~key;
+    sref[idx] = is_cc ? ci : (ci | (1 << 30));
+    if (!is_cc) atomicAdd(&f->nmid, 1);
+  }
+  stat_add(w, kStLostMark, n_lost);
+}
+
+__global__ void kf_clear_marks(Work w) {
+  if (w.st->halt) return;
+  const Lanes L = grid_lanes();
+  const int ncc = w.cnt->ncc, n = ncc + w.cnt->nmk;
+  for (int base = L.base0; base < n; base += L.stride) {
+    const int c = base + threadIdx.x;
+    if (c >= n) continue;
+    const bool is_cc = c < ncc;
+    const int ci = is_cc ? c : c - ncc;
+    const CandSet &S = is_cc ? w.cc : w.mid;
+    const int st = S.state[ci];
+    if (!(st & kStFound) || (st & kStSkip)) continue;
+    if (is_cc && (st & kStDone)) continue;  // dropped before claiming
+    int c0 = S.off[ci], c1 = S.len[ci];
+    if (!is_cc) {
+      if (st & kStDone) continue;
+      c0 = c0 >= 0 ? c0 >> 2 : -1;
+      c1 = c1 >= 0 ? c1 >> 2 : -1;
+    }
+    if (c0 >= 0) w.mark[c0] = 0ull;
+    if (c1 >= 0) w.mark[c1] = 0ull;
+  }
+}
+
+// S by rank (the sorted references): point, class, claims, a midpoint's
+// subsegment endpoints; every point starts in the mesh and not redundant.
+__global__ void kf_gather(DevMesh m, Work w, FfView V, const int32_t *sref) {
+  const int np = V.c->np;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
+    const int ref = sref[r];
+    ff_init_point_one<FfDevOps>(V, r);
+    if (ref & (1 << 30)) {
+      const int i = ref & ((1 << 30) - 1);
+      const int k = w.mid.elem[i];
+      V.pt[r] = w.mid.p[i];
+      V.pinfo[r] = make_int4(1, k, w.mid.off[i], w.mid.len[i]);
+      V.pab[r] = m.sv[k];
+    } else {
+      const int st = w.cc.state[ref];
+      V.pt[r] = w.cc.p[ref];
+      V.pinfo[r] = make_int4(0, ((st >> kFfEdgeShift) & 3) - 1, w.cc.off[ref], w.cc.len[ref]);
+      V.pab[r] = make_int2(-1, -1);
+    }
+  }
+}
+
+// End of a Flip-Flop round (one workgroup): statistics folded in, the counts
+// advanced to the compacted mesh, the round recorded, the counters cleared.
+// Every element of the round's candidate lists was consumed by the host-side
+// sequence, so the next round collects over the whole mesh again.
+__global__ void kf_round_end(Work w, const FfCount *f, int32_t nT_new, int32_t nwin, int32_t nwin_mid) {
+  __shared__ int s_slot;
+  DevState *st = w.st;
+  DevCounters *c = w.cnt;
+  round_fold(w);
+  if (threadIdx.x == 0) {
+    c->n_dep_drop += (int32_t)f->n_dep;
+    c->n_enc_reject += (int32_t)f->n_enc;
+    c->nwin = nwin;
+    c->nwin_mid = nwin_mid;
+    c->nwin_cc = nwin - nwin_mid;
+    c->fresh_total = nT_new - st->nT;
+    c->ff_points = f->np;
+    c->ff_iters = f->iters;
+    c->ff_flips = f->flips;
+    c->ff_passes = f->passes;
+    c->ff_removals = f->removals;
+    const int nh = st->nhist;
+    s_slot = nh < w.hist_cap ? nh : -1;
+    st->nhist = nh + 1;
+    st->nV = st->nV + nwin;
+    st->nT = nT_new;
+    st->nS = st->nS + nwin_mid;
+    st->wT = nT_new / 32 + 1;
+    st->wS = st->nS / 32 + 1;
+    st->rounds = st->rounds + 1;
+    st->serial = st->serial + 1;
+    st->prev_ncc = 0;
+    st->prev_nmk = 0;
+    st->prev_fan = 0;
+    st->full = 1;
+  }
+  __syncthreads();
+  const int nw = (int)(sizeof(DevCounters) / 4);
+  int32_t *src = (int32_t *)c;
+  if (s_slot >= 0) {
+    int32_t *dst = (int32_t *)&w.hist[s_slot];
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) src[i] = 0;
 }
 
 // ---------------------------------------------------------------------------

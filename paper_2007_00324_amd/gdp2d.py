@@ -41,7 +41,8 @@ class gdp_params(C.Structure):
                 ("prefilter_f1", C.c_int32), ("cavity_approx_n", C.c_int32), ("block_size", C.c_int32),
                 ("profile_kernels", C.c_int32), ("reserve_mode", C.c_int32), ("rounds_per_sync", C.c_int32),
                 ("tail_engine_max", C.c_int32), ("encroach_mode", C.c_int32), ("split_mode", C.c_int32),
-                ("max_edge_len_sq", C.c_double)]
+                ("max_edge_len_sq", C.c_double), ("batch_engine_max_v", C.c_int32),
+                ("cavity_thread_cap", C.c_int32), ("insert_mode", C.c_int32)]
 
 
 class gdp_kernel_prof(C.Structure):
@@ -67,7 +68,8 @@ STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coin
                "n_ins_cc", "cav_tri_total", "cav_max", "n_big_cavities", "n_f1_drop", "n_f2_drop",
                "n_incircle_tests", "n_orient_tests", "n_exact_orient", "n_exact_dot", "n_exact_incircle_b",
                "n_exact_incircle_c", "win_cav_tri", "win_fan_edges", "win_walk_steps", "win_cc_cav_tri",
-               "win_cc_fan_edges", "n_huge_cavities", "n_marks_mid", "n_marks_cc"]
+               "win_cc_fan_edges", "n_huge_cavities", "n_marks_mid", "n_marks_cc", "n_ff_points", "n_ff_iters",
+               "n_flips", "n_flip_passes", "n_removals"]
 
 
 class gdp_round_stats(C.Structure):
@@ -122,7 +124,7 @@ def load() -> C.CDLL:
         "gdp_server_wait": (S, [_VP, C.c_uint64, C.POINTER(_VP), C.POINTER(gdp_job_times)]),
         "gdp_server_destroy": (None, [_VP]),
         "gdp_server_engine_jobs": (S, [_VP, C.c_int32]),
-        "gdp_server_mode": (S, [_VP, C.c_int32]),
+        "gdp_server_mode": (S, [_VP, C.c_int32, C.c_int32]),
         "gdp_mesh_device_views": (S, [_VP, C.POINTER(gdp_device_views)]),
         "gdp_predicates_eval": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.POINTER(C.c_int64)]),
         "gdp_bench_atomic_max": (S, [_VP, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
@@ -159,9 +161,13 @@ def _pslg(xy, seg):
 
 def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
                 prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0,
-                tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0, split_mode=0) -> gdp_params:
+                tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0, split_mode=0,
+                batch_engine_max_v=0, cavity_thread_cap=0, insert_mode=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
+    p.insert_mode = insert_mode
+    p.batch_engine_max_v = batch_engine_max_v
+    p.cavity_thread_cap = cavity_thread_cap
     p.encroach_mode = encroach_mode
     p.split_mode = split_mode
     p.max_edge_len_sq = float(max_edge_len_sq)
@@ -429,12 +435,12 @@ class Server:
     device-resident Mesh."""
 
     def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, engine_max_vertices: int | None = None,
-                 mode: int = 0):
+                 mode: int = 0, rounds_per_group: int = 0):
         self.ctx = ctx
         self._h = _VP()
         ctx.check(load().gdp_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(self._h)))
-        if mode:
-            self.ctx.check(load().gdp_server_mode(self._h, int(mode)))
+        if mode or rounds_per_group:
+            self.ctx.check(load().gdp_server_mode(self._h, int(mode), int(rounds_per_group)))
         if engine_max_vertices is not None:
             self.engine_jobs(engine_max_vertices)
 

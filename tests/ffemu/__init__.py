@@ -17,10 +17,11 @@ _lib = None
 
 
 def build() -> str:
+    tmp = f"{LIB}.{os.getpid()}.tmp"  # test workers may build at the same time
     cmd = [os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "-O2", "-std=c++17", "-fPIC", "-shared",
-           "-ffp-contract=off", "-fno-fast-math", "-I", CORE, "-o", LIB + ".tmp", os.path.join(HERE, "ff_emu.cpp")]
+           "-ffp-contract=off", "-fno-fast-math", "-I", CORE, "-o", tmp, os.path.join(HERE, "ff_emu.cpp")]
     subprocess.run(cmd, check=True, capture_output=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 
@@ -35,7 +36,7 @@ def load():
         D = C.POINTER(C.c_double)
         _lib.ffemu_round.argtypes = [C.c_int32] * 4 + [D, I, C.c_int32, I, I, I, C.c_int32, I, I, I, C.c_int32,
                                                        C.c_int32, C.c_int32, D, I, I, C.c_int32, I, I,
-                                                       C.POINTER(C.c_int64)]
+                                                       C.POINTER(C.c_int64), C.c_int32, C.c_uint64]
         _lib.ffemu_round.restype = C.c_int32
     return _lib
 
@@ -63,7 +64,7 @@ def last_points(orc_lib):
                 flagged=ks[:nf])
 
 
-def round_from_points(arr: dict, n_input_v: int, S: dict, enc_mode: int = 0):
+def round_from_points(arr: dict, n_input_v: int, S: dict, enc_mode: int = 0, cand_cap: int = 0, order_seed: int = 0):
     """Runs Line 8 on mesh arrays `arr` (oracle layout) for the points S.
     Returns (arrays in oracle layout, counters)."""
     lib = load()
@@ -113,7 +114,7 @@ def round_from_points(arr: dict, n_input_v: int, S: dict, enc_mode: int = 0):
                          _ptr(SV, C.c_int32), _ptr(SP, C.c_int32), _ptr(SE, C.c_int32), capS,
                          np_, nmid, _ptr(pxy, C.c_double), _ptr(pinfo, C.c_int32), _ptr(pab, C.c_int32),
                          len(mid_elem), _ptr(mid_elem if len(mid_elem) else np.zeros(1, np.int32), C.c_int32),
-                         _ptr(mid_state, C.c_int32), _ptr(out, C.c_int64))
+                         _ptr(mid_state, C.c_int32), _ptr(out, C.c_int64), cand_cap, order_seed)
     nV2, nT2, nS2 = int(out[0]), int(out[1]), int(out[2])
     res = dict(xy=X[:nV2].copy(), vkind=K[:nV2].copy(), tv=TV[:nT2, :3].copy(), tn=TN[:nT2, :3].copy(),
                ts=TS[:nT2, :3].copy(), sv=SV[:nS2].copy(), sparent=SP[:nS2].copy(), spend=SE[:nS2].astype(np.uint8))

@@ -44,12 +44,31 @@ int validate(const Bufs &B, int n_alloc) {
   }
   return 0;
 }
+// Element order of one emulated launch: 0, 1, ... or, with a seed, a
+// pseudo-random permutation (another legal schedule of the same kernel).
+struct Order {
+  uint64_t seed;
+  std::vector<int> idx;
+  const std::vector<int> &of(int n) {
+    idx.resize(n);
+    for (int i = 0; i < n; i++) idx[i] = i;
+    if (seed) {
+      for (int i = n - 1; i > 0; i--) {
+        seed = seed * 6364136223846793005ull + 1442695040888963407ull;
+        const int j = (int)((seed >> 33) % (uint64_t)(i + 1));
+        std::swap(idx[i], idx[j]);
+      }
+    }
+    return idx;
+  }
+};
 }  // namespace
 
 extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int *vkind, int capV, int *tv, int *tn,
                            int *ts, int capT, int *sv, int *spar, int *spend, int capS, int np, int nmid,
                            const double *pxy, const int *pinfo, const int *pab, int nmk, const int *mid_elem,
-                           const int *mid_state, int64_t *out) {
+                           const int *mid_state, int64_t *out, int cand_cap, uint64_t order_seed) {
+  Order ord{order_seed, {}};
   using O = FfHostOps;
   Bufs B;
   B.vxy.resize(capV);
@@ -72,7 +91,7 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
     B.pinfo[r] = make_int4(pinfo[4 * r], pinfo[4 * r + 1], pinfo[4 * r + 2], pinfo[4 * r + 3]);
     B.pab[r] = make_int2(pab[2 * r], pab[2 * r + 1]);
   }
-  B.alive.assign(np + 1, 1); B.red.assign(np + 1, 0); B.vtri.assign(np + 1, -1); B.newid.assign(np + 1, 0);
+  B.alive.assign(np + 1, 7); B.red.assign(np + 1, 7); B.vtri.assign(np + 1, -1); B.newid.assign(np + 1, 0);
   B.sstamp.assign(capT, 0); B.wstamp.assign(capT, 0); B.tstamp.assign(capT, 0); B.moved.assign(capT, -1);
   B.grp.resize(capT); B.claim.assign(capT, 0);
   B.l0.resize(capT); B.l1.resize(capT); B.touched.resize(capT); B.hole.resize(capT); B.mover.resize(capT);
@@ -96,7 +115,7 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   V.grp = B.grp.data(); V.sstamp = B.sstamp.data(); V.wstamp = B.wstamp.data(); V.tstamp = B.tstamp.data();
   V.moved = B.moved.data(); V.claim = B.claim.data();
   V.touched = B.touched.data(); V.hole = B.hole.data(); V.mover = B.mover.data();
-  V.fc0 = B.fc0.data(); V.fc1 = B.fc1.data(); V.fprio = B.fprio.data();
+  V.fc0 = B.fc0.data(); V.fc1 = B.fc1.data(); V.fprio = B.fprio.data(); V.cand_cap = cand_cap > 0 ? cand_cap : 3 * capT;
   V.vmark = B.vmark.data(); V.sflag = B.sflag.data(); V.mid_rank = B.mid_rank.data();
   V.mid_elem = B.mid_elem.data(); V.mid_state = B.mid_state.data(); V.nmk = nmk;
   V.pool = B.pool.data(); V.pool_cap = (int64_t)B.pool.size();
@@ -113,8 +132,9 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   int wst = ++stamp;
   set_lists(1);  // list_out = lists[0]
   C.n_out = 0;
-  for (int r = 0; r < np; r++) ff_split_one<O>(V, r, 1, wst, tst);
-  for (int r = 0; r < np; r++) ff_split_fix_one<O>(V, r, 1);
+  for (int r : ord.of(np)) ff_init_point_one<O>(V, r);
+  for (int r : ord.of(np)) ff_split_one<O>(V, r, 1, wst, tst);
+  for (int r : ord.of(np)) ff_split_fix_one<O>(V, r, 1);
   int bad = validate(B, C.n_alloc);
   if (bad) { out[11] = 1000 + bad; return 200; }
   cur = 0;
@@ -129,10 +149,13 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
       C.n_cand = 0;
       pass++;
       C.passes++;
-      for (int i = 0; i < n_in; i++) ff_flip_check_one<O>(V, i, in_stamp, pass);
       wst = ++stamp;
-      const int nc = C.n_cand;
-      for (int i = 0; i < nc; i++) ff_flip_apply_one<O>(V, i, wst, tst);
+      C.cand_over = 0;
+      for (int i : ord.of(n_in)) ff_flip_check_one<O>(V, i, in_stamp, pass);
+      const int nc = std::min(C.n_cand, V.cand_cap);
+      for (int i : ord.of(nc)) ff_flip_apply_one<O>(V, i, wst, tst);
+      if (C.cand_over)
+        for (int i = 0; i < n_in; i++) ff_flip_requeue_one<O>(V, i, wst);
       in_stamp = wst;
       cur ^= 1;
       const int bad2 = validate(B, C.n_alloc);
@@ -142,9 +165,9 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   lawson();
   for (int it = 0; it < 1000 && !C.err; it++) {
     C.iters++;
-    for (int i = 0; i < C.n_touched; i++) ff_vtri_one<O>(V, i, np);
+    for (int i : ord.of(C.n_touched)) ff_vtri_one<O>(V, i, np);
     C.n_red = 0;
-    for (int r = 0; r < np; r++) ff_detect_one<O>(V, r);
+    for (int r : ord.of(np)) ff_detect_one<O>(V, r);
     if (C.n_red == 0 || C.err) break;
     // removals write the next worklist
     wst = ++stamp;
@@ -156,8 +179,9 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
       const uint64_t pbase = pass << 32;
       C.n_left = 0;
       C.pool_used = 0;
-      for (int r = 0; r < np; r++) ff_rm_mark_one<O>(V, r, pbase);
-      for (int r = 0; r < np; r++) ff_rm_apply_one<O>(V, r, pbase, wst, tst);
+      for (int r : ord.of(np)) ff_rm_mark_one<O>(V, r, pbase);
+      for (int r : ord.of(np)) ff_rm_decide_one<O>(V, r, pbase);
+      for (int r : ord.of(np)) ff_rm_apply_one<O>(V, r, wst, tst);
       const int bad3 = validate(B, C.n_alloc);
       if (bad3) { out[11] = 3000 + bad3; C.err = 202; break; }
       if (C.n_left == 0 || C.err) break;

@@ -10,25 +10,27 @@ COMMON_STATS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coi
 
 
 def oracle_run(pslg, cand_cap_K=0, priority_mode=0, max_rounds=0, prefilter_f1=0, cavity_approx_n=0,
-               encroach_mode=0, max_edge_len_sq=0.0, split_mode=0):
+               encroach_mode=0, max_edge_len_sq=0.0, split_mode=0, insert_mode=0):
     import oracle
     m = oracle.build_cdt(pslg.xy, pslg.seg)
     rc = oracle.refine(m, pslg.ratio_bound_sq, cand_cap_K=cand_cap_K, priority_mode=priority_mode, raise_on_error=False,
                        max_rounds=max_rounds, prefilter_f1=prefilter_f1, cavity_approx_n=cavity_approx_n,
-                       encroach_mode=encroach_mode, max_edge_len_sq=max_edge_len_sq, split_mode=split_mode)
+                       encroach_mode=encroach_mode, max_edge_len_sq=max_edge_len_sq, split_mode=split_mode,
+                       insert_mode=insert_mode)
     return m, rc
 
 
 def gpu_run(ctx, pslg, cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, prefilter_f1=0,
             cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0, tail_engine_max=0, encroach_mode=0,
-            max_edge_len_sq=0.0, split_mode=0):
+            max_edge_len_sq=0.0, split_mode=0, cavity_thread_cap=0, insert_mode=0):
     from paper_2007_00324_amd import gdp2d
     mesh = gdp2d.gdp_mesh_create(ctx, pslg.xy, pslg.seg)
     prm = gdp2d.make_params(cand_cap_K=cand_cap_K, priority_mode=priority_mode, max_rounds=max_rounds,
                             block_size=block_size, prefilter_f1=prefilter_f1, cavity_approx_n=cavity_approx_n,
                             reserve_mode=reserve_mode, rounds_per_sync=rounds_per_sync,
                             tail_engine_max=tail_engine_max, encroach_mode=encroach_mode,
-                            max_edge_len_sq=max_edge_len_sq, split_mode=split_mode)
+                            max_edge_len_sq=max_edge_len_sq, split_mode=split_mode,
+                            cavity_thread_cap=cavity_thread_cap, insert_mode=insert_mode)
     rc = gdp2d.gdp_mesh_refine(ctx, mesh, pslg.ratio_bound_sq, prm, allow_noterm=True)
     return mesh, rc
 

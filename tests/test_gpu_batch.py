@@ -88,3 +88,20 @@ def test_batch_invalid_member(ctx):
     for p, g in zip(ps, meshes[:-1]):
         om, _ = oracle_run(p)
         assert not diff_arrays(om.arrays(), g.arrays())
+
+
+@pytest.mark.parametrize("split", [1500, 200])
+def test_batch_split_between_engine_and_shared_rounds(ctx, split):
+    """Meshes above the split run in shared rounds, the rest in the engine:
+    every mesh is still the oracle's (the split is perf only)."""
+    from paper_2007_00324_amd import gdp2d
+    ps = workloads.batch_config3(24, seed=16, n_min=100, n_max=6000)
+    print(f"[batch] split at {split} input vertices", flush=True)
+    meshes, st, _ = _batch(ctx, ps, batch_engine_max_v=split)
+    assert all(s == 0 for s in st), st
+    assert any(p.n_vertices > split for p in ps) and any(p.n_vertices <= split for p in ps)
+    for p, g in zip(ps, meshes):
+        om, rc = oracle_run(p)
+        assert not diff_arrays(om.arrays(), g.arrays()), p.name
+        assert g.info()["rounds"] == om.rounds
+        assert not diff_stats(om.stats[:64], g.round_stats()), p.name

@@ -32,8 +32,12 @@ def test_batch_config3_every_instance_matches_oracle():
                 print(f"[batch_all] oracle {i + 1}/{len(args)} ({time.time() - t:.0f} s)", flush=True)
     assert all(r[3] == 0 for r in res), [i for i, r in enumerate(res) if r[3] != 0][:10]
     ctx = gdp2d.Context(0)
-    print(f"[batch_all] GPU batch of {len(res)} instances", flush=True)
-    meshes, st, ms = gdp2d.gdp_refine_batch(ctx, [(r[0], r[1]) for r in res], [r[2] for r in res])
+    from paper_2007_00324_amd import tune_batch
+    # the tuned launch shapes (perf only), or a split that uses both paths
+    prm = tune_batch.tuned_params() if tune_batch.load_table() else gdp2d.make_params(batch_engine_max_v=10_000)
+    print(f"[batch_all] GPU batch of {len(res)} instances (engine up to {prm.batch_engine_max_v or 'all'} input "
+          f"vertices, shared rounds above)", flush=True)
+    meshes, st, ms = gdp2d.gdp_refine_batch(ctx, [(r[0], r[1]) for r in res], [r[2] for r in res], prm)
     assert all(s == 0 for s in st), [i for i, s in enumerate(st) if s != 0][:10]
     bad = []
     for i, (m, r) in enumerate(zip(meshes, res)):

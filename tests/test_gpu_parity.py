@@ -19,7 +19,7 @@ def ctx():
     return gdp2d.Context(0)
 
 
-PERF_ONLY = ("reserve_mode", "rounds_per_sync", "block_size", "tail_engine_max")
+PERF_ONLY = ("reserve_mode", "rounds_per_sync", "block_size", "tail_engine_max", "cavity_thread_cap")
 
 
 def _check(ctx, p, **kw):
@@ -67,6 +67,14 @@ ENGINE_ALL = 1 << 30  # every round after the first in the single-workgroup engi
 def test_parity_engine(ctx, case, kw):
     """Rounds run whole inside one workgroup give the same mesh and counters."""
     _check(ctx, SMALL[case](), tail_engine_max=ENGINE_ALL, **kw)
+
+
+@pytest.mark.parametrize("cap", [12, 24, 39])
+@pytest.mark.parametrize("case", ["circles_small", "knn_2000", "rand_300"])
+def test_parity_cavity_thread_cap(ctx, case, cap):
+    """The per-thread cavity capacity only moves cavities between the
+    per-thread and the cooperative kernels; the mesh must not change."""
+    _check(ctx, SMALL[case](), tail_engine_max=-1, cavity_thread_cap=cap)
 
 
 @pytest.mark.parametrize("B2", [1.6 * 1.6, 4.0])

@@ -9,7 +9,7 @@ pinned against things other than itself:
 * an independent insertion: with one point per round (K = 1) nothing can be
   redundant except by encroachment, so from the same canonical state a
   Flip-Flop round and a cavity round (Bowyer-Watson growth, fan write;
-  Section 5.1 insertion, separate code) must give the same triangulation
+  Section 5.2 insertion, separate code) must give the same triangulation
   whenever the cavity round rejected nothing;
 * what Line 8 promises for every round: no two points added in a round are
   joined by an edge, and no circumcenter added in a round encroaches a

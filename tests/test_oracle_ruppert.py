@@ -2,7 +2,7 @@
 
 The round oracle inserts many points per round, with priority marks and a
 dependency test deciding which ones go in (Algorithm 1, Lines 2-9; the
-marking and dependency rules of Section 5.1).  A sequential refiner inserts
+marking and dependency rules of Section 5.2).  A sequential refiner inserts
 one point at a time from a priority queue (Ruppert's algorithm with the
 encroachment and termination rules of Section 4.2).  Both must satisfy every
 post-condition, and they must agree on the number of Steiner points within
