@@ -174,11 +174,15 @@ def flipflop_leg(ctx, init, work, p) -> dict:
     resident initial CDT: device refine time (median of 3 after a warmup), time per
     round, and points kept per point added (Flip-Flop adds every point of S
     and takes the redundant ones out again; cavity insertion decides before it
-    writes)."""
+    writes).  The Line 7 filter (n-triangle approximate cavities, Section 4.3)
+    runs before Line 8 in two of the rows: it exists to keep dependent points
+    from being added only to be removed again."""
     from paper_2007_00324_amd import gdp2d
     rows = []
     n_in = init.info()["n_vertices"]
-    for name, kw in [("cavity", dict()), ("flipflop", dict(priority_mode=2, insert_mode=1))]:
+    ff = dict(priority_mode=2, insert_mode=1)
+    for name, kw in [("cavity", dict()), ("flipflop", ff), ("flipflop+F2_n=4", dict(ff, cavity_approx_n=4)),
+                     ("flipflop+F2_n=8", dict(ff, cavity_approx_n=8))]:
         prm = gdp2d.make_params(**kw)
         ms = []
         for rep in range(4):
@@ -193,11 +197,13 @@ def flipflop_leg(ctx, init, work, p) -> dict:
         row = {"insertion": name, "refine_ms": ms[1], "rounds": info["rounds"],
                "ms_per_round": ms[1] / max(1, info["rounds"]), "steiner_points": steiner,
                "steiner_per_s": steiner / (ms[1] / 1000.0), "output_triangles": info["n_triangles"]}
-        if name == "flipflop":
+        if name.startswith("flipflop"):
             added = sum(r["n_ff_points"] for r in st)
             row.update({"points_added": added, "kept_per_added": steiner / max(1, added),
                         "flips": sum(r["n_flips"] for r in st), "flip_passes": sum(r["n_flip_passes"] for r in st),
                         "removals": sum(r["n_removals"] for r in st),
+                        "removal_passes": sum(r["n_removal_passes"] for r in st),
+                        "f2_dropped": sum(r["n_f2_drop"] for r in st),
                         "cdts_examined": sum(r["n_ff_iters"] for r in st)})
         else:
             cands = sum(r["n_kept_cc"] + r["n_mid_cand"] for r in st)

@@ -193,8 +193,9 @@ typedef struct {
      valid cavity): midpoint cavities, circumcenter cavities */
   int64_t n_marks_mid, n_marks_cc;
   /* Flip-Flop rounds (insert_mode 1): points added in Line 8, CDTs examined
-     for redundant points, 2-2 flips, flip passes, points removed */
-  int64_t n_ff_points, n_ff_iters, n_flips, n_flip_passes, n_removals;
+     for redundant points, 2-2 flips, flip passes, points removed, removal
+     passes */
+  int64_t n_ff_points, n_ff_iters, n_flips, n_flip_passes, n_removals, n_removal_passes;
 } gdp_round_stats;
 
 /* Fills *p with the defaults (all zero, block_size 256). */

@@ -90,7 +90,8 @@ struct FfBufs {
   int32_t *sstamp = nullptr, *wstamp = nullptr, *tstamp = nullptr, *moved = nullptr;
   uint64_t *claim = nullptr, *fprio = nullptr, *vmark = nullptr;
   int32_t *list[2] = {nullptr, nullptr};
-  int32_t *touched = nullptr, *hole = nullptr, *mover = nullptr;
+  int32_t *touched = nullptr, *dead = nullptr, *hole = nullptr, *mover = nullptr;
+  int32_t *ntiles = nullptr;  // tile totals of the rank scan
   int32_t *sflag = nullptr, *mid_rank = nullptr, *pool = nullptr;
   FfCount *d_c = nullptr, *h_c = nullptr;
   int32_t stamp = 0;   // last slot stamp handed out (splits, worklists, touched list)
@@ -492,7 +493,7 @@ void free_extras(gdp_mesh *M) {
     void *ptrs[] = {F->skey0, F->skey1, F->sref0, F->sref1, F->shist, F->pt, F->pinfo, F->pslots, F->pab,
                     F->alive, F->red, F->vtri, F->newid, F->grp, F->fc0, F->fc1, F->sstamp, F->wstamp,
                     F->tstamp, F->moved, F->claim, F->fprio, F->vmark, F->list[0], F->list[1], F->touched,
-                    F->hole, F->mover, F->sflag, F->mid_rank, F->pool, F->d_c};
+                    F->dead, F->hole, F->mover, F->ntiles, F->sflag, F->mid_rank, F->pool, F->d_c};
     for (void *q : ptrs)
       if (q) (void)hipFree(q);
     if (F->h_c) (void)hipHostFree(F->h_c);
@@ -793,6 +794,7 @@ gdp_round_stats round_stats_of(const DevCounters &c, const gdp_params *P) {
   rs.n_flips = c.ff_flips;
   rs.n_flip_passes = c.ff_passes;
   rs.n_removals = c.ff_removals;
+  rs.n_removal_passes = c.ff_rm_passes;
   return rs;
 }
 
@@ -2246,6 +2248,7 @@ gdp_status ff_reserve(gdp_mesh *M, int32_t np) {
     HIPCHECK(dgrow(&F.red, 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.vtri, 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.newid, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.ntiles, 0, n / kFfScanTile + 2, 0, 0, s));
     F.capP = (int32_t)n;
   }
   if (m.capT > F.capT) {
@@ -2263,6 +2266,7 @@ gdp_status ff_reserve(gdp_mesh *M, int32_t np) {
     HIPCHECK(dgrow(&F.list[0], 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.list[1], 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.touched, 0, n, 0, 0, s));
+    HIPCHECK(dgrow(&F.dead, 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.hole, 0, n, 0, 0, s));
     HIPCHECK(dgrow(&F.mover, 0, n, 0, 0, s));
     F.capT = (int32_t)n;
@@ -2325,13 +2329,21 @@ FfView ff_view(gdp_mesh *M, const gdp_params *P, int32_t nmk) {
   V.grp = F.grp; V.sstamp = F.sstamp; V.wstamp = F.wstamp; V.tstamp = F.tstamp; V.moved = F.moved;
   V.claim = F.claim;
   V.list_in = F.list[1]; V.list_out = F.list[0];
-  V.touched = F.touched; V.hole = F.hole; V.mover = F.mover;
+  V.touched = F.touched; V.dead = F.dead; V.hole = F.hole; V.mover = F.mover;
+  V.newid_tiles = F.ntiles;
   V.fc0 = F.fc0; V.fc1 = F.fc1; V.fprio = F.fprio; V.cand_cap = F.capT;
   V.vmark = F.vmark; V.sflag = F.sflag; V.mid_rank = F.mid_rank;
   V.mid_elem = M->mid.elem; V.mid_state = M->mid.state; V.nmk = nmk;
   V.pool = F.pool; V.pool_cap = F.pool_cap;
   V.c = F.d_c;
   return V;
+}
+
+// Writers of the next flip worklist (splits, removals) append to list[out].
+void ff_target(gdp_mesh *M, FfView &V, int out) {
+  FfBufs &F = *M->ff;
+  V.list_out = F.list[out];
+  V.n_out = &F.d_c->n_list[out];
 }
 
 gdp_status ff_read(gdp_mesh *M, FfCount &c) {
@@ -2353,21 +2365,27 @@ gdp_status ff_read(gdp_mesh *M, FfCount &c) {
 }
 
 // Flip passes until no edge is left to check.  The first input list is
-// F.list[cur], written with stamp in_stamp; est sizes the grids.
+// F.list[cur] (length n_list[cur]), written with stamp in_stamp; est sizes
+// the grids.  A pass is two launches; the host reads the counters after
+// batches of 4, 8, then 16 passes.
 gdp_status ff_lawson(gdp_mesh *M, FfView &V, int &cur, int &in_stamp, int tst, int64_t est) {
   gdp_ctx *ctx = M->ctx;
   hipStream_t s = ctx->stream;
   FfBufs &F = *M->ff;
   gdp_status st;
   int batch = 4;
+  hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 0, cur ^ 1);  // candidate counts start at 0
   for (int64_t done = 0; done < (1 << 15);) {
     for (int q = 0; q < batch; q++, done++) {
-      V.list_in = F.list[cur];
-      V.list_out = F.list[cur ^ 1];
       int wst;
       uint64_t pass;
       if ((st = ff_next_stamp(M, wst)) || (st = ff_next_pass(M, pass))) return st;
-      hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 0);
+      V.list_in = F.list[cur];
+      V.list_out = F.list[cur ^ 1];
+      V.n_in = &F.d_c->n_list[cur];
+      V.n_out = &F.d_c->n_list[cur ^ 1];
+      V.n_cand = &F.d_c->n_cnd[pass & 1];
+      V.n_cand_next = &F.d_c->n_cnd[(pass + 1) & 1];
       hipLaunchKernelGGL(kf_flip_check, dim3(ff_grid(est)), dim3(256), 0, s, V, in_stamp, pass);
       hipLaunchKernelGGL(kf_flip_apply, dim3(ff_grid(est)), dim3(256), 0, s, V, wst, tst);
       in_stamp = wst;
@@ -2375,8 +2393,8 @@ gdp_status ff_lawson(gdp_mesh *M, FfView &V, int &cur, int &in_stamp, int tst, i
     }
     FfCount c;
     if ((st = ff_read(M, c))) return st;
-    if (c.n_out == 0) return GDP_OK;
-    est = c.n_out;
+    if (c.n_list[cur] == 0) return GDP_OK;
+    est = c.n_list[cur];
     batch = std::min(batch * 2, 16);
   }
   return fail(ctx, GDP_E_CAVITY, "flip passes did not converge");
@@ -2406,7 +2424,7 @@ gdp_status ff_canonical(gdp_mesh *M, const gdp_params *P) {
   hipLaunchKernelGGL(kf_rotate, dim3(ff_grid(nT)), dim3(256), 0, s, V, nT);
   int wst, tst;
   if ((st = ff_next_stamp(M, wst)) || (st = ff_next_stamp(M, tst))) return st;
-  V.list_out = F.list[0];
+  ff_target(M, V, 0);
   hipLaunchKernelGGL(kf_all_slots, dim3(ff_grid(nT)), dim3(256), 0, s, V, nT, wst);
   int cur = 0, in_stamp = wst;
   if ((st = ff_lawson(M, V, cur, in_stamp, tst, nT))) return st;
@@ -2435,7 +2453,7 @@ gdp_status ff_line8(gdp_mesh *M, const gdp_params *P, int32_t np, int32_t nmid, 
   int wst, tst, split_stamp;
   if ((st = ff_next_stamp(M, wst)) || (st = ff_next_stamp(M, tst)) || (st = ff_next_stamp(M, split_stamp)))
     return st;
-  V.list_out = F.list[0];
+  ff_target(M, V, 0);
   hipLaunchKernelGGL(kf_split, dim3(ff_grid(np)), dim3(256), 0, s, V, split_stamp, wst, tst);
   hipLaunchKernelGGL(kf_split_fix, dim3(ff_grid(np)), dim3(256), 0, s, V, split_stamp);
   int cur = 0, in_stamp = wst;
@@ -2444,21 +2462,21 @@ gdp_status ff_line8(gdp_mesh *M, const gdp_params *P, int32_t np, int32_t nmid, 
   for (int it = 0;; it++) {
     if (it > (1 << 16)) return fail(ctx, GDP_E_CAVITY, "redundant points keep appearing");
     if ((st = ff_read(M, c))) return st;
-    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 2);
+    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 2, 0);
     hipLaunchKernelGGL(kf_vtri, dim3(ff_grid(c.n_touched)), dim3(256), 0, s, V);
     hipLaunchKernelGGL(kf_detect, dim3(ff_grid(np)), dim3(256), 0, s, V);
     if ((st = ff_read(M, c))) return st;
     if (c.n_red == 0) break;
     // removal passes; their triangles form the next flip worklist
     if ((st = ff_next_stamp(M, wst))) return st;
-    V.list_out = F.list[cur];
-    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 3);
+    ff_target(M, V, cur);
+    hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 0, cur);
     for (int pass_i = 0;; pass_i++) {
       if (pass_i > (1 << 16)) return fail(ctx, GDP_E_CAVITY, "removal passes did not finish");
       uint64_t pass;
       if ((st = ff_next_pass(M, pass))) return st;
       const uint64_t pbase = pass << 32;
-      hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 1);
+      hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 1, 0);
       hipLaunchKernelGGL(kf_rm_mark, dim3(ff_grid(np)), dim3(256), 0, s, V, pbase);
       hipLaunchKernelGGL(kf_rm_decide, dim3(ff_grid(np)), dim3(256), 0, s, V, pbase);
       hipLaunchKernelGGL(kf_rm_apply, dim3(ff_grid(np)), dim3(256), 0, s, V, wst, tst);
@@ -2474,10 +2492,20 @@ gdp_status ff_line8(gdp_mesh *M, const gdp_params *P, int32_t np, int32_t nmid, 
       }
     }
     in_stamp = wst;
-    if ((st = ff_lawson(M, V, cur, in_stamp, tst, c.n_out))) return st;
+    if ((st = ff_lawson(M, V, cur, in_stamp, tst, c.n_list[cur]))) return st;
   }
   // final ids, renumbering, pending flags
-  hipLaunchKernelGGL(kf_newid, dim3(1), dim3(1024), 0, s, V);
+  // ranks of the kept points: a tiled exclusive scan of alive (newid holds
+  // the in-tile prefix, ntiles the tile prefixes), then the kept midpoints
+  {
+    const int32_t *no_halt = &F.d_c->err;  // the scan kernels stop on a nonzero word; err is 0 here
+    const ScanJob j{V.alive, V.newid, &F.d_c->np, F.ntiles, &F.d_c->nwin, 0};
+    const ScanJob none{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (np + kFfScanTile - 1) / kFfScanTile), 2048);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(g), dim3(256), 0, s, j, none, no_halt);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, j, none, no_halt);
+    hipLaunchKernelGGL(kf_nwin_mid, dim3(1), dim3(64), 0, s, V);
+  }
   hipLaunchKernelGGL(kf_final_point, dim3(ff_grid(np)), dim3(256), 0, s, V);
   hipLaunchKernelGGL(kf_final_tri, dim3(ff_grid(c.n_touched)), dim3(256), 0, s, V);
   hipLaunchKernelGGL(kf_final_mid, dim3(ff_grid(nmk)), dim3(256), 0, s, V);
@@ -2486,8 +2514,8 @@ gdp_status ff_line8(gdp_mesh *M, const gdp_params *P, int32_t np, int32_t nmid, 
   if ((st = ff_read(M, c))) return st;
   // compaction: live triangles above the final count fill the holes
   const int n_alloc = c.n_alloc, n_live = c.n_alloc - c.n_dead;
-  hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 4);
-  hipLaunchKernelGGL(kf_compact_list, dim3(ff_grid(n_alloc)), dim3(256), 0, s, V, n_alloc, n_live);
+  hipLaunchKernelGGL(kf_ctl, dim3(1), dim3(64), 0, s, F.d_c, 4, 0);
+  hipLaunchKernelGGL(kf_compact_list, dim3(ff_grid(c.n_dead)), dim3(256), 0, s, V, n_alloc, n_live);
   hipLaunchKernelGGL(kf_compact_move, dim3(ff_grid(c.n_dead)), dim3(256), 0, s, V);
   hipLaunchKernelGGL(kf_compact_fix, dim3(ff_grid(c.n_dead)), dim3(256), 0, s, V, n_live);
   if (c.nwin == 0 && c.flags == 0) {

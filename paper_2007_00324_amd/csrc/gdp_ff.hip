@@ -8,6 +8,7 @@
 namespace gdp {
 
 using DO = FfDevOps;
+static_assert(kFfScanTile == kScanTileSize, "the ranks are scanned with the refinement's tile");
 
 #define FF_LOOP(i, n) \
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
@@ -22,31 +23,26 @@ __global__ void kf_split_fix(FfView V, int split_stamp) {
   FF_LOOP(r, np) ff_split_fix_one<DO>(V, r, split_stamp);
 }
 
-// The control words of a pass are moved by one thread before the pass:
-// op 0 starts a flip pass (the last output list becomes the input), op 1 a
-// removal pass, op 2 a detection, op 3 empties the output list, op 4 the
-// compaction lists.
-__global__ void kf_ctl(FfCount *c, int op) {
+// Control words moved by one thread: op 0 empties worklist count `arg` and
+// both candidate counts, op 1 starts a removal pass, op 2 a detection, op 4
+// the compaction lists.
+__global__ void kf_ctl(FfCount *c, int op, int arg) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   switch (op) {
     case 0:
-      c->n_in = c->n_out;
-      c->n_out = 0;
-      c->n_cand = 0;
-      c->cand_over = 0;
-      if (c->n_in > 0) c->passes++;
+      c->n_list[arg] = 0;
+      c->n_cnd[0] = 0;
+      c->n_cnd[1] = 0;
       break;
     case 1:
       c->n_left = 0;
       c->pool_used = 0;
       c->pool_short = 0;
+      c->rm_passes++;
       break;
     case 2:
       c->n_red = 0;
       c->iters++;
-      break;
-    case 3:
-      c->n_out = 0;
       break;
     default:
       c->n_hole = 0;
@@ -55,16 +51,21 @@ __global__ void kf_ctl(FfCount *c, int op) {
   }
 }
 
+// A flip pass is these two launches: the list lengths and candidate counts
+// are entries of FfCount chosen by the host (two lists and two candidate
+// counts alternate), so no launch is needed between passes.
 __global__ void kf_flip_check(FfView V, int in_stamp, uint64_t pass) {
-  const int n = V.c->n_in;
+  const int n = *V.n_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ff_check_begin<DO>(V);
   FF_LOOP(i, n) ff_flip_check_one<DO>(V, i, in_stamp, pass);
 }
 
 __global__ void kf_flip_apply(FfView V, int wst, int tst) {
-  const int n = min(V.c->n_cand, V.cand_cap);
-  FF_LOOP(i, n) ff_flip_apply_one<DO>(V, i, wst, tst);
-  if (V.c->cand_over) {
-    const int n_in = V.c->n_in;
+  const int nc = *V.n_cand;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ff_apply_begin<DO>(V);
+  FF_LOOP(i, min(nc, V.cand_cap)) ff_flip_apply_one<DO>(V, i, wst, tst);
+  if (nc > V.cand_cap) {
+    const int n_in = *V.n_in;
     FF_LOOP(i, n_in) ff_flip_requeue_one<DO>(V, i, wst);
   }
 }
@@ -94,41 +95,12 @@ __global__ void kf_rm_apply(FfView V, int wst, int tst) {
   FF_LOOP(r, np) ff_rm_apply_one<DO>(V, r, wst, tst);
 }
 
-// One workgroup: newid = exclusive prefix of alive over the ranks; the
-// totals (kept points, kept midpoints) go to the counters.  Each thread
-// sums a contiguous chunk, the chunk sums are scanned in LDS, then each
-// thread writes its chunk.
-constexpr int kFfScanThreads = 1024;
-__global__ __launch_bounds__(kFfScanThreads) void kf_newid(FfView V) {
-  __shared__ int part[kFfScanThreads];
-  __shared__ int s_total;
+// The number of kept midpoints (the midpoints are ranks 0..nmid-1), once
+// the ranks are scanned (one thread).
+__global__ void kf_nwin_mid(FfView V) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int np = V.c->np, nmid = V.c->nmid;
-  const int chunk = (np + kFfScanThreads - 1) / kFfScanThreads;
-  const int lo = threadIdx.x * chunk, hi = min(np, lo + chunk);
-  int s = 0;
-  for (int r = lo; r < hi; r++) s += V.alive[r];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int i = 0; i < kFfScanThreads; i++) {
-      const int x = part[i];
-      part[i] = run;
-      run += x;
-    }
-    s_total = run;
-  }
-  __syncthreads();
-  int run = part[threadIdx.x];
-  for (int r = lo; r < hi; r++) {
-    V.newid[r] = run;
-    if (r == nmid) V.c->nwin_mid = run;
-    run += V.alive[r];
-  }
-  if (threadIdx.x == 0) {
-    V.c->nwin = s_total;
-    if (nmid >= np) V.c->nwin_mid = s_total;
-  }
+  V.c->nwin_mid = nmid < np ? ff_newid(V, nmid) : V.c->nwin;
 }
 
 __global__ void kf_final_point(FfView V) {
@@ -156,7 +128,9 @@ __global__ void kf_final_flag_clear(FfView V) {
 }
 
 __global__ void kf_compact_list(FfView V, int n_alloc, int n_live) {
-  FF_LOOP(s, n_alloc) ff_compact_list_one<DO>(V, s, n_live);
+  const int nd = V.c->n_dead;
+  FF_LOOP(i, nd) ff_compact_hole_one<DO>(V, i, n_live);
+  FF_LOOP(j, n_alloc - n_live) ff_compact_mover_one<DO>(V, n_live + j);
 }
 
 __global__ void kf_compact_move(FfView V) {
@@ -178,7 +152,7 @@ __global__ void kf_all_slots(FfView V, int n, int wst) {
     V.wstamp[s] = wst;
     V.list_out[s] = s;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) V.c->n_out = n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *V.n_out = n;
 }
 
 #undef FF_LOOP

@@ -36,8 +36,8 @@ namespace gdp {
 struct FfCount {
   int32_t np, nmid;       // points of S (midpoints first in rank order)
   int32_t n_alloc;        // next fresh triangle slot
-  int32_t n_in, n_out;    // lengths of the worklist being read / being built
-  int32_t n_cand;         // flip candidates of the running pass
+  int32_t n_list[2];      // lengths of the two worklists (one read, one built per pass)
+  int32_t n_cnd[2];       // flip candidates of a pass (by the parity of the pass)
   int32_t n_touched;      // slots written this round (each once)
   int32_t n_red;          // redundant points found by the last detection
   int32_t n_left;         // redundant points a removal pass left for the next one
@@ -47,9 +47,7 @@ struct FfCount {
   int32_t err;            // first inconsistency found (site number), 0 none
   int32_t flags;          // subsegments newly flagged by encroaching circumcenters
   int32_t nwin, nwin_mid; // points of S kept, of which midpoints (after the last pass)
-  int32_t cand_over;      // a pass found more flip candidates than the list holds
-  int32_t pad;
-  int64_t flips, removals, n_dep, n_enc, iters, passes;
+  int64_t flips, removals, n_dep, n_enc, iters, passes, rm_passes;
 };
 
 // Everything the steps read and write.
@@ -71,15 +69,19 @@ struct FfView {
   int2 *pab;              // a midpoint's subsegment endpoints (a, b) as the round started
   int4 *pslots;           // slots written by the point's split
   int32_t *alive, *red, *vtri, *newid;
+  int32_t *newid_tiles;   // final rank of r = newid[r] + newid_tiles[r / kFfScanTile] (a tiled scan)
   // per slot
   int4 *grp;              // slots that replaced a triangle split this round
   int32_t *sstamp, *wstamp, *tstamp, *moved;
   uint64_t *claim;
   // lists
-  int32_t *list_in, *list_out, *touched, *hole, *mover;
+  int32_t *list_in, *list_out, *touched, *dead, *hole, *mover;
   int4 *fc0, *fc1;        // flip candidates: (t, e, o, j), the four outer slots
   uint64_t *fprio;
   int32_t cand_cap;
+  // counters of the running pass (entries of FfCount): input and output list
+  // lengths, this pass's candidates and the next pass's
+  int32_t *n_in, *n_out, *n_cand, *n_cand_next;
   // per vertex / subsegment
   uint64_t *vmark;
   int32_t *sflag;         // [nS + nmid] flagged by an encroaching circumcenter (provisional ids)
@@ -93,13 +95,45 @@ struct FfView {
 
 // Candidate state bit of the refinement round (a cap-skipped entry).
 constexpr int kFfStSkip = 64;
+// Tile of the scan that ranks the kept points (the refinement's scan tile).
+constexpr int kFfScanTile = 2048;
 constexpr int kFfWalkCap = 1 << 20;
 
-// Atomic operations of the kernels.
+// Atomic operations of the kernels.  Additions to a shared counter are
+// combined per wave first (one atomic for the active lanes of the wave, each
+// lane getting its own offset): a pass appends thousands of entries to the
+// same few counters, and atomics on one address are serialised.
 struct FfDevOps {
-  __device__ static int add(int32_t *p, int v) { return atomicAdd(p, v); }
+  // returns the counter's value before this lane's share (lanes ordered by id)
+  __device__ static int add(int32_t *p, int v) {
+    const uint64_t mask = __ballot(1);
+    const int lane = __lane_id();
+    int prefix = 0, total = 0;
+    for (uint64_t m = mask; m; m &= m - 1) {
+      const int b = __ffsll((unsigned long long)m) - 1;
+      const int vb = __shfl(v, b);
+      prefix += b < lane ? vb : 0;
+      total += vb;
+    }
+    int base = 0;
+    if (lane == __ffsll((unsigned long long)mask) - 1) base = atomicAdd(p, total);
+    return __builtin_amdgcn_readfirstlane(base) + prefix;
+  }
+  // add(p, 1)
+  __device__ static int append(int32_t *p) {
+    const uint64_t mask = __ballot(1);
+    const int rank = __popcll(mask & ((1ull << __lane_id()) - 1));
+    int base = 0;
+    if (rank == 0) base = atomicAdd(p, __popcll(mask));
+    return __builtin_amdgcn_readfirstlane(base) + rank;
+  }
   __device__ static void add64(int64_t *p, int64_t v) {
-    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    const uint64_t mask = __ballot(1);
+    const int lane = __lane_id();
+    long long total = 0;
+    for (uint64_t m = mask; m; m &= m - 1) total += __shfl((long long)v, __ffsll((unsigned long long)m) - 1);
+    if (lane == __ffsll((unsigned long long)mask) - 1 && total)
+      atomicAdd((unsigned long long *)p, (unsigned long long)total);
   }
   __device__ static int exch(int32_t *p, int v) { return atomicExch(p, v); }
   __device__ static int or32(int32_t *p, int v) { return atomicOr(p, v); }
@@ -112,6 +146,7 @@ struct FfDevOps {
 // ... and of a sequential run on the host.
 struct FfHostOps {
   static int add(int32_t *p, int v) { const int o = *p; *p += v; return o; }
+  static int append(int32_t *p) { return (*p)++; }
   static void add64(int64_t *p, int64_t v) { *p += v; }
   static int exch(int32_t *p, int v) { const int o = *p; *p = v; return o; }
   static int or32(int32_t *p, int v) { const int o = *p; *p |= v; return o; }
@@ -150,13 +185,13 @@ GDP_HD void ff_store(const FfView &V, int slot, int a, int b, int c, int na, int
 
 template <class O>
 GDP_HD void ff_push(int32_t *list, int32_t *cnt, int32_t *stamps, int stamp, int slot) {
-  if (O::exch(&stamps[slot], stamp) != stamp) list[O::add(cnt, 1)] = slot;
+  if (O::exch(&stamps[slot], stamp) != stamp) list[O::append(cnt)] = slot;
 }
 
 // Both lists a written slot goes to: the flip worklist and the touched list.
 template <class O>
 GDP_HD void ff_wrote(const FfView &V, int slot, int wstamp, int tstamp) {
-  ff_push<O>(V.list_out, &V.c->n_out, V.wstamp, wstamp, slot);
+  ff_push<O>(V.list_out, V.n_out, V.wstamp, wstamp, slot);
   ff_push<O>(V.touched, &V.c->n_touched, V.tstamp, tstamp, slot);
 }
 
@@ -316,13 +351,8 @@ GDP_HD void ff_flip_check_one(const FfView &V, int i, int in_stamp, uint64_t pas
     const int n_vw = ffc(na, (e + 1) % 3), n_wu = ffc(na, (e + 2) % 3);
     const int n_ud = ffc(nb, (j + 1) % 3), n_dv = ffc(nb, (j + 2) % 3);
     const uint64_t prio = (pass << 40) | (uint64_t)(t < o ? 4 * (int64_t)t + e : 4 * (int64_t)o + j);
-    const int idx = O::add(&V.c->n_cand, 1);
-    if (idx >= V.cand_cap) {
-      // no room (and no claims, so the stored candidates still make
-      // progress): the whole input list goes to the next pass
-      O::or32(&V.c->cand_over, 1);
-      continue;
-    }
+    const int idx = O::append(V.n_cand);
+    if (idx >= V.cand_cap) continue;  // no room and no claims: ff_flip_requeue_one
     O::max64(&V.claim[t], prio);
     O::max64(&V.claim[o], prio);
     if (n_vw >= 0) O::max64(&V.claim[n_vw], prio);
@@ -335,12 +365,24 @@ GDP_HD void ff_flip_check_one(const FfView &V, int i, int in_stamp, uint64_t pas
   }
 }
 
-// After a pass whose candidates overflowed their list: every triangle of the
+// Duties of one thread of a pass's check launch: the output list starts
+// empty (nothing writes it during the check), and a pass is counted; of its
+// apply launch: the next pass's candidate count starts at zero.
+template <class O>
+GDP_HD void ff_check_begin(const FfView &V) {
+  *V.n_out = 0;
+  if (*V.n_in > 0) V.c->passes++;
+}
+template <class O>
+GDP_HD void ff_apply_begin(const FfView &V) { *V.n_cand_next = 0; }
+
+// After a pass whose candidates overflowed their list (more candidates than
+// room, and those without room placed no claims): every triangle of the
 // input list is checked again in the next pass.
 template <class O>
 GDP_HD void ff_flip_requeue_one(const FfView &V, int i, int wst) {
   const int t = V.list_in[i];
-  if (V.tv[t].x >= 0) ff_push<O>(V.list_out, &V.c->n_out, V.wstamp, wst, t);
+  if (V.tv[t].x >= 0) ff_push<O>(V.list_out, V.n_out, V.wstamp, wst, t);
 }
 
 template <class O>
@@ -356,7 +398,7 @@ GDP_HD void ff_flip_apply_one(const FfView &V, int i, int wst, int tst) {
     if (x >= 0 && V.claim[x] != prio) win = false;
   }
   if (!win) {
-    ff_push<O>(V.list_out, &V.c->n_out, V.wstamp, wst, t);  // the edge is checked again
+    ff_push<O>(V.list_out, V.n_out, V.wstamp, wst, t);  // the edge is checked again
     return;
   }
   // t = (u, v, w) with edge e = (u, v); o = (v, u, d) with edge j = (v, u).
@@ -447,14 +489,14 @@ GDP_HD void ff_detect_one(const FfView &V, int r) {
       if (encroaches(V.enc_mode, A.x, A.y, B.x, B.y, P.x, P.y)) {
         enc = true;
         const int sid = ffc(V.ts[t], (i + 1) % 3);
-        if (O::or32(&V.sflag[sid], 1) == 0) O::add(&V.c->flags, 1);
+        if (O::or32(&V.sflag[sid], 1) == 0) O::append(&V.c->flags);
       }
     }
   });
   if (n == 0) { O::err(&V.c->err, 7); return; }
   if (enc || dep) {
     V.red[r] = enc ? 2 : 1;
-    O::add(&V.c->n_red, 1);
+    O::append(&V.c->n_red);
     if (enc) O::add64(&V.c->n_enc, 1);
     else O::add64(&V.c->n_dep, 1);
   }
@@ -484,23 +526,39 @@ GDP_HD void ff_rm_mark_one(const FfView &V, int r, uint64_t pbase) {
 // (>= 0 a slot, -1 none, -2 matched later), sd[q] its subsegment id.  Emits
 // triangles into ev (3 ids each) and en / es (neighbour code and subsegment
 // per edge).  Returns the number emitted, -1 if no ear was found.
-GDP_HD int ff_clip(const FfView &V, int m, int *pv, int *info, int *sd, int *nx, int *pr, int *ev, int *en, int *es,
-                   int ne) {
+//
+// The polygon is the link of the removed point P, so it is star-shaped from
+// P (P inside it, or on its closing edge): a convex corner b between a and c
+// with P strictly on the other side of the chord a-c is an ear (the triangle
+// lies in the wedge a-P-c, which holds no other link vertex) -- that is a
+// flip of the edge P-b.  Only when no such corner is left (P on every
+// remaining chord) is a corner tested against all remaining vertices.
+GDP_HD int ff_clip(const FfView &V, double2 P, int m, int *pv, int *info, int *sd, int *nx, int *pr, int *ev,
+                   int *en, int *es, int ne) {
   for (int q = 0; q < m; q++) { nx[q] = (q + 1) % m; pr[q] = (q + m - 1) % m; }
   int left = m, cur = 0, tries = 0;
+  bool general = false;  // the slow ear test, once the fast one found nothing in a full turn
   while (left > 3) {
     const int a = pr[cur], b = cur, c = nx[cur];
     const double2 A = V.vxy[pv[a]], B = V.vxy[pv[b]], C = V.vxy[pv[c]];
     bool ear = orient2d(A.x, A.y, B.x, B.y, C.x, C.y) > 0;
-    for (int q = nx[c]; ear && q != a; q = nx[q]) {
-      const double2 Q = V.vxy[pv[q]];
-      if (orient2d(A.x, A.y, B.x, B.y, Q.x, Q.y) >= 0 && orient2d(B.x, B.y, C.x, C.y, Q.x, Q.y) >= 0 &&
-          orient2d(C.x, C.y, A.x, A.y, Q.x, Q.y) >= 0)
-        ear = false;
+    if (ear && !general) {
+      ear = orient2d(A.x, A.y, C.x, C.y, P.x, P.y) > 0;
+    } else if (ear) {
+      for (int q = nx[c]; ear && q != a; q = nx[q]) {
+        const double2 Q = V.vxy[pv[q]];
+        if (orient2d(A.x, A.y, B.x, B.y, Q.x, Q.y) >= 0 && orient2d(B.x, B.y, C.x, C.y, Q.x, Q.y) >= 0 &&
+            orient2d(C.x, C.y, A.x, A.y, Q.x, Q.y) >= 0)
+          ear = false;
+      }
     }
     if (!ear) {
       cur = nx[cur];
-      if (++tries > left) return -1;
+      if (++tries > left) {
+        if (general) return -1;
+        general = true;
+        tries = 0;
+      }
       continue;
     }
     // triangle (a, b, c): edges (a,b), (b,c) from the polygon; (c,a) new
@@ -515,6 +573,7 @@ GDP_HD int ff_clip(const FfView &V, int m, int *pv, int *info, int *sd, int *nx,
     left--;
     cur = a;
     tries = 0;
+    general = false;
   }
   const int a = pr[cur], b = cur, c = nx[cur];
   ev[3 * ne] = pv[a]; ev[3 * ne + 1] = pv[b]; ev[3 * ne + 2] = pv[c];
@@ -523,9 +582,6 @@ GDP_HD int ff_clip(const FfView &V, int m, int *pv, int *info, int *sd, int *nx,
   return ne + 1;
 }
 
-// After all marks: a point that holds every mark of itself and its
-// neighbours is removed in this pass (bit 4 of red); the others wait.  This
-// reads the mesh only, so the removals of the pass start from whole stars.
 template <class O>
 GDP_HD void ff_rm_decide_one(const FfView &V, int r, uint64_t pbase) {
   if (!V.alive[r] || !V.red[r]) return;
@@ -538,7 +594,7 @@ GDP_HD void ff_rm_decide_one(const FfView &V, int r, uint64_t pbase) {
   });
   if (k == 0) { O::err(&V.c->err, 9); return; }
   if (own) V.red[r] |= 4;
-  else O::add(&V.c->n_left, 1);
+  else O::append(&V.c->n_left);
 }
 
 template <class O>
@@ -555,7 +611,7 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
   const int64_t base = O::add(&V.c->pool_used, (int)need);
   if (base + need > V.pool_cap) {
     O::or32(&V.c->pool_short, 1);
-    O::add(&V.c->n_left, 1);
+    O::append(&V.c->n_left);
     V.red[r] &= 3;  // tried again in the next pass
     return;
   }
@@ -584,7 +640,7 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
   if (info4.x == 0) {
     // circumcenter: one closed polygon, the link
     for (int q = 0; q < k; q++) { pv[q] = ring[q]; info[q] = onb[q]; sd[q] = osd[q]; }
-    ne = ff_clip(V, k, pv, info, sd, nx, pr, ev, en, es, 0);
+    ne = ff_clip(V, V.vxy[p], k, pv, info, sd, nx, pr, ev, en, es, 0);
   } else {
     const int2 ab = V.pab[r];
     const int kseg = info4.y;
@@ -595,7 +651,7 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
       } else {
         for (int q = 0; q < k; q++) { pv[q] = ring[q]; info[q] = onb[q]; sd[q] = osd[q]; }
         pv[k] = ring[k]; info[k] = -1; sd[k] = kseg;
-        ne = ff_clip(V, k + 1, pv, info, sd, nx, pr, ev, en, es, 0);
+        ne = ff_clip(V, V.vxy[p], k + 1, pv, info, sd, nx, pr, ev, en, es, 0);
       }
     } else {
       int ia = -1, ib = -1;
@@ -615,7 +671,7 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
         int m = 0;
         for (int q = from; q != to; q = (q + 1) % k) { pv[m] = ring[q]; info[m] = onb[q]; sd[m] = osd[q]; m++; }
         pv[m] = ring[to]; info[m] = -2; sd[m] = kseg; m++;
-        ne = ff_clip(V, m, pv, info, sd, nx, pr, ev, en, es, ne);
+        ne = ff_clip(V, V.vxy[p], m, pv, info, sd, nx, pr, ev, en, es, ne);
       }
     }
   }
@@ -674,8 +730,8 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
   for (int q = ne; q < k; q++) {
     V.tv[star[q]] = make_int4(-1, -1, -1, 0);
     V.tn[star[q]] = make_int4(-1, -1, -1, 0);
+    V.dead[O::append(&V.c->n_dead)] = star[q];
   }
-  O::add(&V.c->n_dead, k - ne);
   V.alive[r] = 0;
   V.red[r] = 0;
   O::add64(&V.c->removals, 1);
@@ -684,16 +740,18 @@ GDP_HD void ff_rm_apply_one(const FfView &V, int r, int wst, int tst) {
 // ---------------------------------------------------------------------------
 // End of the round
 // ---------------------------------------------------------------------------
+GDP_HD int ff_newid(const FfView &V, int r) { return V.newid[r] + V.newid_tiles[r / kFfScanTile]; }
+
 // Final ids: newid[r] = rank of r among the live points (an exclusive scan).
 template <class O>
 GDP_HD void ff_final_point_one(const FfView &V, int r) {
   if (!V.alive[r]) return;
   const int4 info = V.pinfo[r];
-  const int id = V.nV + V.newid[r];
+  const int id = V.nV + ff_newid(V, r);
   V.vxy[id] = V.pt[r];
   V.vkind[id] = info.x ? 1 : 2;
   if (info.x) {
-    const int k = info.y, knew = V.nS + V.newid[r];  // midpoints come first in rank order
+    const int k = info.y, knew = V.nS + ff_newid(V, r);  // midpoints come first in rank order
     const int2 ab = V.pab[r];
     V.sv[k] = make_int2(ab.x, id);
     V.sv[knew] = make_int2(id, ab.y);
@@ -715,12 +773,12 @@ GDP_HD void ff_final_tri_one(const FfView &V, int i) {
     if (v[q] >= V.nV) {
       const int r = v[q] - V.nV;
       if (!V.alive[r]) O::err(&V.c->err, 15);
-      v[q] = V.nV + V.newid[r];
+      v[q] = V.nV + ff_newid(V, r);
     }
     if (((t.w >> q) & 1) && sid[q] >= V.nS) {
       const int r = sid[q] - V.nS;
       if (!V.alive[r]) O::err(&V.c->err, 16);
-      sid[q] = V.nS + V.newid[r];
+      sid[q] = V.nS + ff_newid(V, r);
     }
   }
   V.tv[s] = make_int4(v[0], v[1], v[2], t.w);
@@ -759,12 +817,17 @@ GDP_HD void ff_final_flag_one(const FfView &V, int k, int nmid) {
 template <class O>
 GDP_HD void ff_final_flag_clear_one(const FfView &V, int r) { V.sflag[V.nS + r] = 0; }
 
-// Compaction: live triangles above the final count move into the holes below.
+// Compaction: live triangles above the final count move into the holes
+// below it.  Holes are the freed slots below the count (from the list of
+// freed slots); movers are the live slots from the count up.
 template <class O>
-GDP_HD void ff_compact_list_one(const FfView &V, int s, int n_live) {
-  const bool dead = V.tv[s].x < 0;
-  if (s < n_live && dead) V.hole[O::add(&V.c->n_hole, 1)] = s;
-  if (s >= n_live && !dead) V.mover[O::add(&V.c->n_mover, 1)] = s;
+GDP_HD void ff_compact_hole_one(const FfView &V, int i, int n_live) {
+  const int s = V.dead[i];
+  if (s < n_live) V.hole[O::append(&V.c->n_hole)] = s;
+}
+template <class O>
+GDP_HD void ff_compact_mover_one(const FfView &V, int s) {
+  if (V.tv[s].x >= 0) V.mover[O::append(&V.c->n_mover)] = s;
 }
 template <class O>
 GDP_HD void ff_compact_move_one(const FfView &V, int i) {

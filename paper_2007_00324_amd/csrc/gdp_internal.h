@@ -102,6 +102,7 @@ struct DevCounters {
   int64_t ff_flips;     // 2-2 flips
   int64_t ff_passes;    // flip passes
   int64_t ff_removals;  // redundant points taken out
+  int64_t ff_rm_passes; // removal passes
 };
 static_assert(sizeof(DevCounters) % 8 == 0, "DevCounters is copied as 32-bit words");
 static_assert(offsetof(DevCounters, nmk) == 128, "the midpoint append counter starts the second line");

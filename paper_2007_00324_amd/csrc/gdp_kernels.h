@@ -171,7 +171,7 @@ __global__ void kf_round_end(Work w, const FfCount *f, int32_t nT_new, int32_t n
 // elements, counts read from device memory where they change on the device.
 __global__ void kf_split(FfView V, int split_stamp, int wst, int tst);
 __global__ void kf_split_fix(FfView V, int split_stamp);
-__global__ void kf_ctl(FfCount *c, int op);
+__global__ void kf_ctl(FfCount *c, int op, int arg);
 __global__ void kf_flip_check(FfView V, int in_stamp, uint64_t pass);
 __global__ void kf_flip_apply(FfView V, int wst, int tst);
 __global__ void kf_vtri(FfView V);
@@ -179,7 +179,7 @@ __global__ void kf_detect(FfView V);
 __global__ void kf_rm_mark(FfView V, uint64_t pbase);
 __global__ void kf_rm_decide(FfView V, uint64_t pbase);
 __global__ void kf_rm_apply(FfView V, int wst, int tst);
-__global__ void kf_newid(FfView V);  // one workgroup: exclusive scan of alive -> newid
+__global__ void kf_nwin_mid(FfView V);  // after the scan of alive into newid
 __global__ void kf_final_point(FfView V);
 __global__ void kf_final_tri(FfView V);
 __global__ void kf_final_mid(FfView V);

@@ -2087,10 +2087,10 @@ __global__ void kf_own(Work w, FfCount *f, uint64_t *skey, int32_t *sref) {
     }
     const bool own = (c0 < 0 || w.mark[c0] == key) && (c1 < 0 || w.mark[c1] == key);
     if (!own) { n_lost++; continue; }
-    const int idx = atomicAdd(&f->np, 1);
+    const int idx = FfDevOps::append(&f->np);
     skey[idx] = ~key;
     sref[idx] = is_cc ? ci : (ci | (1 << 30));
-    if (!is_cc) atomicAdd(&f->nmid, 1);
+    if (!is_cc) FfDevOps::append(&f->nmid);
   }
   stat_add(w, kStLostMark, n_lost);
 }
@@ -2162,6 +2162,7 @@ __global__ void kf_round_end(Work w, const FfCount *f, int32_t nT_new, int32_t n
     c->ff_flips = f->flips;
     c->ff_passes = f->passes;
     c->ff_removals = f->removals;
+    c->ff_rm_passes = f->rm_passes;
     const int nh = st->nhist;
     s_slot = nh < w.hist_cap ? nh : -1;
     st->nhist = nh + 1;

@@ -69,7 +69,7 @@ STAT_FIELDS = ["n_enc", "n_bad", "n_kept_mid", "n_kept_cc", "n_blocked", "n_coin
                "n_incircle_tests", "n_orient_tests", "n_exact_orient", "n_exact_dot", "n_exact_incircle_b",
                "n_exact_incircle_c", "win_cav_tri", "win_fan_edges", "win_walk_steps", "win_cc_cav_tri",
                "win_cc_fan_edges", "n_huge_cavities", "n_marks_mid", "n_marks_cc", "n_ff_points", "n_ff_iters",
-               "n_flips", "n_flip_passes", "n_removals"]
+               "n_flips", "n_flip_passes", "n_removals", "n_removal_passes"]
 
 
 class gdp_round_stats(C.Structure):

@@ -17,7 +17,7 @@ namespace {
 struct Bufs {
   std::vector<double2> vxy, pt;
   std::vector<int32_t> vkind, spar, spend, alive, red, vtri, newid, sstamp, wstamp, tstamp, moved;
-  std::vector<int32_t> l0, l1, touched, hole, mover, sflag, mid_rank, mid_elem, mid_state, pool;
+  std::vector<int32_t> l0, l1, touched, dead, hole, mover, sflag, mid_rank, mid_elem, mid_state, pool, ntiles;
   std::vector<uint32_t> mflag;
   std::vector<int4> tv, tn, ts, pinfo, pslots, grp, fc0, fc1;
   std::vector<int2> sv, pab;
@@ -94,7 +94,9 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   B.alive.assign(np + 1, 7); B.red.assign(np + 1, 7); B.vtri.assign(np + 1, -1); B.newid.assign(np + 1, 0);
   B.sstamp.assign(capT, 0); B.wstamp.assign(capT, 0); B.tstamp.assign(capT, 0); B.moved.assign(capT, -1);
   B.grp.resize(capT); B.claim.assign(capT, 0);
-  B.l0.resize(capT); B.l1.resize(capT); B.touched.resize(capT); B.hole.resize(capT); B.mover.resize(capT);
+  B.l0.resize(capT); B.l1.resize(capT); B.touched.resize(capT); B.dead.resize(capT); B.hole.resize(capT);
+  B.mover.resize(capT);
+  B.ntiles.assign(np / kFfScanTile + 2, 0);  // the host run ranks in one tile
   B.fc0.resize(3 * (size_t)capT); B.fc1.resize(3 * (size_t)capT); B.fprio.resize(3 * (size_t)capT);
   B.vmark.assign(capV, 0);
   B.sflag.assign(capS + np + 1, 0);
@@ -114,7 +116,8 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   V.alive = B.alive.data(); V.red = B.red.data(); V.vtri = B.vtri.data(); V.newid = B.newid.data();
   V.grp = B.grp.data(); V.sstamp = B.sstamp.data(); V.wstamp = B.wstamp.data(); V.tstamp = B.tstamp.data();
   V.moved = B.moved.data(); V.claim = B.claim.data();
-  V.touched = B.touched.data(); V.hole = B.hole.data(); V.mover = B.mover.data();
+  V.touched = B.touched.data(); V.dead = B.dead.data(); V.hole = B.hole.data(); V.mover = B.mover.data();
+  V.newid_tiles = B.ntiles.data();
   V.fc0 = B.fc0.data(); V.fc1 = B.fc1.data(); V.fprio = B.fprio.data(); V.cand_cap = cand_cap > 0 ? cand_cap : 3 * capT;
   V.vmark = B.vmark.data(); V.sflag = B.sflag.data(); V.mid_rank = B.mid_rank.data();
   V.mid_elem = B.mid_elem.data(); V.mid_state = B.mid_state.data(); V.nmk = nmk;
@@ -123,15 +126,15 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   int32_t *lists[2] = {B.l0.data(), B.l1.data()};
   int cur = 0, stamp = 0;
   uint64_t pass = 0;
-  auto set_lists = [&](int in) {
-    V.list_in = lists[in];
-    V.list_out = lists[in ^ 1];
+  auto target = [&](int out) {  // writers of the next worklist
+    V.list_out = lists[out];
+    V.n_out = &C.n_list[out];
+    C.n_list[out] = 0;
   };
   const int tst = ++stamp;
   // splits write the first worklist
   int wst = ++stamp;
-  set_lists(1);  // list_out = lists[0]
-  C.n_out = 0;
+  target(0);
   for (int r : ord.of(np)) ff_init_point_one<O>(V, r);
   for (int r : ord.of(np)) ff_split_one<O>(V, r, 1, wst, tst);
   for (int r : ord.of(np)) ff_split_fix_one<O>(V, r, 1);
@@ -140,21 +143,24 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   cur = 0;
   int in_stamp = wst;
   auto lawson = [&]() {
+    C.n_cnd[0] = C.n_cnd[1] = 0;
     for (;;) {
-      const int n_in = C.n_out;
-      if (n_in == 0 || C.err) return;
-      set_lists(cur);
-      C.n_in = n_in;
-      C.n_out = 0;
-      C.n_cand = 0;
-      pass++;
-      C.passes++;
+      if (C.n_list[cur] == 0 || C.err) return;
       wst = ++stamp;
-      C.cand_over = 0;
+      pass++;
+      V.list_in = lists[cur];
+      V.list_out = lists[cur ^ 1];
+      V.n_in = &C.n_list[cur];
+      V.n_out = &C.n_list[cur ^ 1];
+      V.n_cand = &C.n_cnd[pass & 1];
+      V.n_cand_next = &C.n_cnd[(pass + 1) & 1];
+      ff_check_begin<O>(V);
+      const int n_in = *V.n_in;
       for (int i : ord.of(n_in)) ff_flip_check_one<O>(V, i, in_stamp, pass);
-      const int nc = std::min(C.n_cand, V.cand_cap);
-      for (int i : ord.of(nc)) ff_flip_apply_one<O>(V, i, wst, tst);
-      if (C.cand_over)
+      const int nc = *V.n_cand;
+      ff_apply_begin<O>(V);
+      for (int i : ord.of(std::min(nc, V.cand_cap))) ff_flip_apply_one<O>(V, i, wst, tst);
+      if (nc > V.cand_cap)
         for (int i = 0; i < n_in; i++) ff_flip_requeue_one<O>(V, i, wst);
       in_stamp = wst;
       cur ^= 1;
@@ -171,8 +177,7 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
     if (C.n_red == 0 || C.err) break;
     // removals write the next worklist
     wst = ++stamp;
-    set_lists(cur ^ 1);  // list_out = lists[cur]
-    C.n_out = 0;
+    target(cur);
     for (int guard = 0;; guard++) {
       if (guard > 100000) { C.err = 99; break; }
       pass++;
@@ -202,7 +207,8 @@ extern "C" int ffemu_round(int nV, int nT, int nS, int enc_mode, double *xy, int
   for (int k = 0; k < nS; k++) ff_final_flag_one<O>(V, k, nmid);
   for (int r = 0; r < nmid; r++) ff_final_flag_clear_one<O>(V, r);
   const int n_live = C.n_alloc - C.n_dead;
-  for (int s = 0; s < C.n_alloc; s++) ff_compact_list_one<O>(V, s, n_live);
+  for (int i : ord.of(C.n_dead)) ff_compact_hole_one<O>(V, i, n_live);
+  for (int j : ord.of(C.n_alloc - n_live)) ff_compact_mover_one<O>(V, n_live + j);
   if (C.n_hole != C.n_mover) C.err = C.err ? C.err : 98;
   for (int i = 0; i < C.n_hole; i++) ff_compact_move_one<O>(V, i);
   for (int i = 0; i < C.n_hole; i++) ff_compact_fix_one<O>(V, i, n_live);
