@@ -283,7 +283,7 @@ def recorded_setting_traffic() -> dict:
         if line.startswith("kernel_sources_sha256:"):
             sha = line.split(":", 1)[1].strip()
         elif line.startswith("setting_traffic:"):
-            name, val = line.split(":", 1)[1].split("=")
+            name, val = line.split(":", 1)[1].rsplit("=", 1)
             out[name.strip()] = float(val)
     return out if sha == kernel_source_hash() else {}
 
