@@ -108,3 +108,12 @@ def test_ff_rejects_slot_dependent_keys_and_other_forms(ctx):
         gdp2d.gdp_mesh_refine(ctx, m, p.ratio_bound_sq, gdp2d.make_params(priority_mode=2))
     with pytest.raises(gdp2d.GdpError):
         gdp2d.gdp_refine_batch(ctx, [(p.xy, p.seg)], [p.ratio_bound_sq], gdp2d.make_params(**FF))
+
+
+def test_ff_parity_rounded_cocircular_polygon(ctx):
+    """8,192 rounded cocircular vertices: every interior triangle's circle holds
+    the centre, so the first point added there ends with a link of thousands of
+    vertices (thousands of flip passes, ties decided by the symbolic
+    perturbation)."""
+    p = workloads.scaled_config2(1, 8192, 0, seed=7, r_lo=0.40, r_hi=0.45)
+    _check(ctx, p, cand_cap_K=8, max_rounds=4)
