@@ -227,9 +227,13 @@ GDP_SLOW int incircle_exact_diff(double adx, double ady, double bdx, double bdy,
   return acc_sign(a);
 }
 
-// ---- public predicates -------------------------------------------------------
-// orient2d > 0 iff a, b, c are in counter-clockwise order.
-GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
+// ---- stage A alone ------------------------------------------------------------
+// The FP64 filters by themselves: the sign when the forward error bound
+// decides it, else kUndecided.  Kernels whose register budget matters call
+// these and hand the rare undecided case to a path that evaluates exactly.
+constexpr int kUndecided = 2;
+
+GDP_HD int orient2d_filter(double ax, double ay, double bx, double by, double cx, double cy) {
   double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
   double l = acx * bcy, r = acy * bcx;
   double det = l - r;
@@ -239,12 +243,11 @@ GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, doubl
     if (det > bound) return 1;
     if (-det > bound) return -1;
   }
-  return orient_exact(ax, ay, bx, by, cx, cy, t);
+  return kUndecided;
 }
 
-// incircle > 0 iff d lies strictly inside the circle through CCW a, b, c.
-GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, double cy, double dx,
-                    double dy, uint64_t *tl = nullptr) {
+GDP_HD int incircle_filter(double ax, double ay, double bx, double by, double cx, double cy, double dx,
+                           double dy) {
   double adx = ax - dx, ady = ay - dy, bdx = bx - dx, bdy = by - dy, cdx = cx - dx, cdy = cy - dy;
   double bc1 = bdx * cdy, bc2 = cdx * bdy;
   double ca1 = cdx * ady, ca2 = adx * cdy;
@@ -259,6 +262,36 @@ GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, doubl
     if (det > bound) return 1;
     if (-det > bound) return -1;
   }
+  return kUndecided;
+}
+
+// sign of -(a-c).(b-c): > 0 iff c lies strictly inside the circle with diameter ab
+GDP_HD int indiametral_filter(double ax, double ay, double bx, double by, double cx, double cy) {
+  double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
+  double l = acx * bcx, r = acy * bcy;
+  double dot = l + r;
+  double perm = fabs(l) + fabs(r);
+  double bound = 6.0 * kU * perm;
+  if (perm > kTiny) {
+    if (dot > bound) return -1;
+    if (-dot > bound) return 1;
+  }
+  return kUndecided;
+}
+
+// ---- public predicates -------------------------------------------------------
+// orient2d > 0 iff a, b, c are in counter-clockwise order.
+GDP_HD int orient2d(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
+  const int s = orient2d_filter(ax, ay, bx, by, cx, cy);
+  return s != kUndecided ? s : orient_exact(ax, ay, bx, by, cx, cy, t);
+}
+
+// incircle > 0 iff d lies strictly inside the circle through CCW a, b, c.
+GDP_HD int incircle(double ax, double ay, double bx, double by, double cx, double cy, double dx,
+                    double dy, uint64_t *tl = nullptr) {
+  const int f = incircle_filter(ax, ay, bx, by, cx, cy, dx, dy);
+  if (f != kUndecided) return f;
+  double adx = ax - dx, ady = ay - dy, bdx = bx - dx, bdy = by - dy, cdx = cx - dx, cdy = cy - dy;
   // Stage B applies when every difference is exact (zero tail).
   double s, t;
   bool exact = true;
@@ -310,16 +343,8 @@ GDP_HD int incircle_sos(double ax, double ay, double bx, double by, double cx, d
 
 // indiametral > 0 iff c lies strictly inside the circle with diameter ab.
 GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, double cy, uint64_t *t = nullptr) {
-  double acx = ax - cx, bcx = bx - cx, acy = ay - cy, bcy = by - cy;
-  double l = acx * bcx, r = acy * bcy;
-  double dot = l + r;
-  double perm = fabs(l) + fabs(r);
-  double bound = 6.0 * kU * perm;
-  if (perm > kTiny) {
-    if (dot > bound) return -1;
-    if (-dot > bound) return 1;
-  }
-  return -dot_exact(ax, ay, bx, by, cx, cy, t);
+  const int s = indiametral_filter(ax, ay, bx, by, cx, cy);
+  return s != kUndecided ? s : -dot_exact(ax, ay, bx, by, cx, cy, t);
 }
 
 // Encroachment of subsegment ab by p (Section 4.1): strictly inside the
@@ -329,16 +354,30 @@ GDP_HD int indiametral(double ax, double ay, double bx, double by, double cx, do
 // in the circle; after the exact circle test the angle is tested by the FP64
 // formula (a-p).(b-p) < 0 and 4 ((a-p).(b-p))^2 > |a-p|^2 |b-p|^2 in this
 // operation order.
-GDP_HD bool encroaches(int mode, double ax, double ay, double bx, double by, double px, double py,
-                       uint64_t *t = nullptr) {
-  if (indiametral(ax, ay, bx, by, px, py, t) <= 0) return false;
-  if (mode == 0) return true;
+GDP_HD bool in_lens_angle(double ax, double ay, double bx, double by, double px, double py) {
   const double dax = ax - px, day = ay - py;
   const double dbx = bx - px, dby = by - py;
   const double dot = dax * dbx + day * dby;
   const double la = dax * dax + day * day;
   const double lb = dbx * dbx + dby * dby;
   return (dot * dot) * 4.0 > la * lb;
+}
+
+GDP_HD bool encroaches(int mode, double ax, double ay, double bx, double by, double px, double py,
+                       uint64_t *t = nullptr) {
+  if (indiametral(ax, ay, bx, by, px, py, t) <= 0) return false;
+  if (mode == 0) return true;
+  return in_lens_angle(ax, ay, bx, by, px, py);
+}
+
+// encroaches() from the filter alone: 1 or 0, or kUndecided when the circle
+// test needs the exact evaluation.
+GDP_HD int encroaches_filter(int mode, double ax, double ay, double bx, double by, double px, double py) {
+  const int s = indiametral_filter(ax, ay, bx, by, px, py);
+  if (s == kUndecided) return kUndecided;
+  if (s <= 0) return 0;
+  if (mode == 0) return 1;
+  return in_lens_angle(ax, ay, bx, by, px, py) ? 1 : 0;
 }
 
 }  // namespace gdp

@@ -786,6 +786,10 @@ constexpr int kCavBlock = kCavBlockSize;
 // Grows the cavity of p from the seeds into lds[j * ls + tid] (a slice of
 // cap entries).  Returns the size, or -1 if it exceeds cap (the cavity then
 // goes to the cooperative path; the set of triangles is the same).
+// FILTER: the geometric tests use the FP64 filters alone, and a test they
+// cannot decide returns -2 (the cavity then goes to the cooperative path,
+// which evaluates exactly); this keeps the exact evaluations, and the
+// registers and scratch they need, out of the per-thread kernels.
 //
 // The boundary checks are made on the way: an edge of a cavity triangle is
 // internal iff its neighbour is in the cavity, and that is decided when the
@@ -795,7 +799,9 @@ constexpr int kCavBlock = kCavBlockSize;
 // circumcenters an encroached boundary subsegment (all are flagged; a
 // cavity that overflows flags a subset of what the cooperative path flags
 // for the same cavity).  The split subsegment of a midpoint (skip_k) is
-// not a boundary edge.
+// not a boundary edge.  A cavity left undecided by a filter (FILTER) has
+// flagged a subset too.
+template <bool FILTER>
 __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
                                           const int *seeds, int nseeds, double2 p, int skip_k, bool is_cc,
                                           CavCheck &ck) {
@@ -859,7 +865,14 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32
         const double2 B = to[e].y == fv[e] ? F[e] : (to[e].y == u ? Pu : Pv);
         const double2 C = to[e].z == fv[e] ? F[e] : (to[e].z == u ? Pu : Pv);
         ck.ntest++;
-        if (incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y, w.tally) > 0) {
+        int in;
+        if (FILTER) {
+          in = incircle_filter(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y);
+          if (in == kUndecided) return -2;
+        } else {
+          in = incircle(A.x, A.y, B.x, B.y, C.x, C.y, p.x, p.y, w.tally);
+        }
+        if (in > 0) {
           if (len == cap) return -1;
           lds[(len++) * ls + tid] = o[e];
           continue;
@@ -869,11 +882,27 @@ __device__ __forceinline__ int grow_local(const DevMesh &m, const Work &w, int32
       const int sid = ((tri.w >> e) & 1) ? comp(ts, e) : -1;
       if (skip_k >= 0 && sid == skip_k) continue;
       ck.nbnd++;
-      if (is_cc && sid >= 0 && encroached(w, Pu, Pv, p)) {
-        flag_mid(w, sid);
-        ck.enc = true;
+      if (is_cc && sid >= 0) {
+        int enc;
+        if (FILTER) {
+          enc = encroaches_filter(w.enc_mode, Pu.x, Pu.y, Pv.x, Pv.y, p.x, p.y);
+          if (enc == kUndecided) return -2;
+        } else {
+          enc = encroached(w, Pu, Pv, p) ? 1 : 0;
+        }
+        if (enc) {
+          flag_mid(w, sid);
+          ck.enc = true;
+        }
       }
-      if (orient_pts(w, Pu, Pv, p) <= 0) ck.fan_bad = true;
+      int o;
+      if (FILTER) {
+        o = orient2d_filter(Pu.x, Pu.y, Pv.x, Pv.y, p.x, p.y);
+        if (o == kUndecided) return -2;
+      } else {
+        o = orient_pts(w, Pu, Pv, p);
+      }
+      if (o <= 0) ck.fan_bad = true;
     }
   }
   // insertion sort (ascending slots)
@@ -899,6 +928,7 @@ struct CavRes {
   int ntest;      // incircle evaluations made while growing
 };
 
+template <bool FILTER>
 __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, int32_t *lds, int ls, int cap, int tid,
                                              int ci, int is_cc) {
   CavRes res{0, 0, 0, 0, 0, 0, 0, 0};
@@ -933,7 +963,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
     S.state[ci] = st | kStFound;
   }
   CavCheck ck;
-  int len = grow_local(m, w, lds, ls, cap, tid, seeds, nseeds, p, skip_k, is_cc != 0, ck);
+  int len = grow_local<FILTER>(m, w, lds, ls, cap, tid, seeds, nseeds, p, skip_k, is_cc != 0, ck);
   res.ntest = ck.ntest;
   if (len < 0) {
     S.state[ci] = st | kStBig | kStFound;
@@ -964,6 +994,7 @@ __device__ __forceinline__ CavRes cavity_one(const DevMesh &m, const Work &w, in
 // that pool space and statistics are handled once per wave.
 // Candidates [lo, hi) of the class (hi < 0: to the end of the list); tid is
 // the thread's index in the group that runs the loop (its LDS slice).
+template <bool FILTER = false>
 __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int is_cc, int32_t *lds, int ls, int cap,
                                             const Lanes &L, int lo = 0, int hi = -1, int tid = -1) {
   if (tid < 0) tid = threadIdx.x;
@@ -972,7 +1003,7 @@ __device__ __forceinline__ void cavity_part(const DevMesh &m, const Work &w, int
   for (int base = lo + L.base0; base < n; base += L.stride) {
     int ci = base + tid;
     CavRes r{0, 0, 0, 0, 0, 0, 0, 0};
-    if (ci < n) r = cavity_one(m, w, lds, ls, cap, tid, ci, is_cc);
+    if (ci < n) r = cavity_one<FILTER>(m, w, lds, ls, cap, tid, ci, is_cc);
     int off = group_alloc(&w.cnt->pool_used, r.alive ? r.len : 0, L);
     bool counted = r.len > 0 && !r.alive;  // dropped cavities count in the statistics now
     if (r.alive) {
@@ -1011,7 +1042,7 @@ __global__ __launch_bounds__(kCavBlock, 4) void k_cavity(DevMesh m, Work w) {
   static_assert(CAP <= kStat4Cap, "per-thread cavity statistics fit stat_add4");
   __shared__ int32_t lds[CAP * kCavBlock];
   if (w.st->halt) return;
-  cavity_part(m, w, IS_CC, lds, kCavBlock, CAP, grid_lanes());
+  cavity_part<true>(m, w, IS_CC, lds, kCavBlock, CAP, grid_lanes());
 }
 template __global__ void k_cavity<0, kCap>(DevMesh m, Work w);
 template __global__ void k_cavity<1, kCap>(DevMesh m, Work w);
@@ -2735,7 +2766,7 @@ __global__ __launch_bounds__(kCavBlock, 4) void kg_cavity(const GangDesc *G) {
   __shared__ int32_t lds[kCap * kCavBlock];
   GANG_MESH
   if (w.st->halt) return;
-  cavity_part(m, w, IS_CC, lds, kCavBlock, kCap, grid_lanes());
+  cavity_part<true>(m, w, IS_CC, lds, kCavBlock, kCap, grid_lanes());
 }
 template __global__ void kg_cavity<0>(const GangDesc *G);
 template __global__ void kg_cavity<1>(const GangDesc *G);
