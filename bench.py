@@ -465,18 +465,19 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     }
 
 
-def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode, rounds=0):
+def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode, rounds=0, line1=None, l1_out=None):
     """One replay of the job set as a Poisson stream of rate lam (None: every
     job arrives at once); returns latencies (ms), the achieved rate and the
-    count of failed jobs."""
+    count of failed jobs.  line1 = (host threads, device threshold): Line 1
+    runs in the server after arrival (l1_out receives each job's Line-1 ms)."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     from paper_2007_00324_amd import gdp2d
     n = len(jobs)
     srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=engine_max_v, mode=mode,
-                       rounds_per_group=rounds)
-    with ThreadPoolExecutor(16) as ex:  # Line 1 of every job, in parallel, before the stream starts
+                       rounds_per_group=rounds, line1=line1)
+    with ThreadPoolExecutor(16) as ex:  # Line 1 of every job (unless in the server) before the stream starts
         ids = list(ex.map(lambda p: srv.prepare(p.xy, p.seg, p.ratio_bound_sq), jobs))
     gaps = np.random.default_rng(7).exponential(1.0 / lam, size=n) if lam else np.zeros(n)
     results = [None] * n
@@ -499,8 +500,42 @@ def serve_stream(ctx, jobs, lam, budget_gb, slots, engine_max_v, mode, rounds=0)
     th.join()
     srv.close()
     lat = np.array([t["done_ms"] - t["submit_ms"] for _, t in results])
+    if l1_out is not None:
+        l1_out.extend(t["line1_ms"] - t["submit_ms"] for _, t in results)
     span = max(1e-9, (max(t["done_ms"] for _, t in results) - min(t["submit_ms"] for _, t in results)) / 1000.0)
     return lat, n / span, sum(1 for rc, _ in results if rc != 0)
+
+
+def serving_line1_leg(ctx, jobs, budget_gb: float, slots: int, dev_min_v: int, rate_frac: float = 0.5) -> dict:
+    """Serving with Line 1 inside the server (latency from the PSLG's arrival,
+    initial CDT included): host threads only, against the device builder for
+    jobs of at least dev_min_v input vertices.  Each setting: capacity (every
+    job at once), then a Poisson stream at rate_frac of the host setting's
+    capacity."""
+    import numpy as np
+    rows = []
+    lam = None
+    for name, l1 in (("host", (16, 0)), (f"device for jobs >= {dev_min_v:,} vertices", (16, dev_min_v))):
+        row = {"line1": name, "host_threads": l1[0], "device_min_vertices": l1[1]}
+        l1ms = []
+        lat, cap, bad = serve_stream(ctx, jobs, None, budget_gb, slots, 0, 0, line1=l1, l1_out=l1ms)
+        row["capacity_jobs_per_s"] = cap
+        row["capacity_run"] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                               "line1_mean_ms": float(np.mean(l1ms)), "failed": bad}
+        if lam is None:
+            lam = cap * rate_frac
+        l1ms = []
+        lat, ach, bad = serve_stream(ctx, jobs, lam, budget_gb, slots, 0, 0, line1=l1, l1_out=l1ms)
+        row["stream"] = {"rate_jobs_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "achieved_jobs_per_s": ach,
+                         "line1_mean_ms": float(np.mean(l1ms)), "line1_p99_ms": float(np.percentile(l1ms, 99)),
+                         "failed": bad}
+        log(f"serving, Line 1 in the server ({name}): capacity {cap:.0f} jobs/s; at {lam:.0f}/s p50 "
+            f"{row['stream']['p50_ms']:.1f} ms, p99 {row['stream']['p99_ms']:.1f} ms (Line 1 mean "
+            f"{row['stream']['line1_mean_ms']:.1f} ms), {bad} not OK")
+        rows.append(row)
+    return {"workload": "the serving job set; latency from the arrival of the PSLG (Line 1 included)",
+            "settings": rows}
 
 
 def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int, engine_max_v=None,
@@ -588,6 +623,8 @@ def main() -> int:
                     help="only measure the serving capacity for slots:rounds pairs (e.g. 16:2,32:4) and exit")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-line1-device-min", type=int, default=100000,
+                    help="serving with Line 1 in the server: device builder from this many input vertices (0: skip)")
     ap.add_argument("--serve-engine-max", type=int, default=None,
                     help="jobs up to this many input vertices run in batched launches (default: the library's)")
     ap.add_argument("--pmc-sum", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -794,6 +831,9 @@ def main() -> int:
         rates = [r for r in args.serve_rates.split(",") if r]
         out["serving"] = serving_leg(ctx, serve_jobs, rates, args.serve_budget_gb, args.serve_slots, 8,
                                      args.serve_engine_max, args.serve_mode)
+        if args.serve_line1_device_min > 0:
+            out["serving"]["line1_in_server"] = serving_line1_leg(ctx, serve_jobs, args.serve_budget_gb,
+                                                                  args.serve_slots, args.serve_line1_device_min)
     if not args.no_cpu_baseline:
         n = args.cpu_sample
         log(f"cpu baseline: oracle on {n:,} points")

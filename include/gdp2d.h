@@ -399,12 +399,16 @@ gdp_status gdp_refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *r
    instead refined together, one workgroup each, in launches of the
    single-workgroup engine.  Each result is bit-identical to gdp_refine on
    the same input.  A job that outgrows its region is refined
-   again on its own.  Latency is measured from arrival (after Line 1, which
-   runs in the caller's thread at prepare). */
+   again on its own.  Latency is measured from arrival.  Line 1 (the initial
+   CDT, Section 4.3) runs by default in the caller's thread at prepare, before
+   arrival; with gdp_server_line1 it runs in the server after arrival (and so
+   counts in the latency), on host threads or, for large jobs, by the device
+   builder of gdp_mesh_create_device. */
 typedef struct gdp_server gdp_server;
 
 typedef struct {
   double submit_ms;  /* arrival, ms since the server was created */
+  double line1_ms;   /* end of Line 1 in the server (0 when it ran at prepare) */
   double admit_ms;   /* admission into a slot */
   double done_ms;    /* completion */
 } gdp_job_times;
@@ -421,7 +425,20 @@ gdp_status gdp_server_mode(gdp_server *srv, int32_t mode, int32_t rounds_per_gro
    launches (0: every job takes a slot).  Applies to jobs admitted afterwards.
    GDP_E_ARG for a negative value. */
 gdp_status gdp_server_engine_jobs(gdp_server *srv, int32_t max_input_vertices);
-/* Line 1 for a job (host) without letting it arrive; *job identifies it. */
+/* Line 1 inside the server (Section 4.3 Line 1, the initial CDT): from now on
+   gdp_server_prepare only copies the job's input (checking its coordinates
+   and segment endpoints), and Line 1 runs after arrival: on one of
+   host_threads (1..64) library threads, or, for a job with at least
+   device_min_vertices input vertices (0: never), on the device by the kernels
+   of gdp_mesh_create_device (the same CDT), on a library thread and stream of
+   its own that takes the job's region first and builds the CDT inside it
+   (such jobs then run in the shared rounds whatever the mode).  A Line-1
+   failure ends the job with its status (GDP_E_INPUT for an invalid PSLG).
+   Must be called before the first job is prepared: GDP_E_BUSY otherwise;
+   GDP_E_ARG for values out of range. */
+gdp_status gdp_server_line1(gdp_server *srv, int32_t host_threads, int32_t device_min_vertices);
+/* Line 1 for a job (host) without letting it arrive, unless gdp_server_line1
+   moved it into the server; *job identifies it. */
 gdp_status gdp_server_prepare(gdp_server *srv, const gdp_pslg *pslg, double ratio_bound_sq,
                               const gdp_params *params, uint64_t *job);
 /* The prepared job arrives: it is queued for admission (first come, first served). */

@@ -1668,10 +1668,13 @@ struct Job {
   Caps caps;
   size_t bytes = 0, off = 0;
   gdp_mesh *mesh = nullptr;
-  enum { PREPARED, QUEUED, ACTIVE, DONE } state = PREPARED;
+  enum { PREPARED, LINE1, QUEUED, ACTIVE, DONE } state = PREPARED;
   gdp_status status = GDP_OK;
-  double t_submit = 0, t_admit = 0, t_done = 0;
+  double t_submit = 0, t_line1 = 0, t_admit = 0, t_done = 0;
   bool grid_only = false;  // outgrew its region in a batched launch: the slots refine it
+  int32_t nv_in = 0;       // input vertices
+  bool raw = false;        // Line 1 has not run: it runs in the server after arrival
+  bool resident = false;   // Line 1 ran on the device, into the job's region
 };
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -1727,6 +1730,15 @@ struct ServerGang {
   std::thread th;
 };
 
+// Line 1 in the server (gdp_server_line1): host threads build the CDTs of
+// arrived jobs; one more thread builds those of large jobs on the device, on
+// its own stream, directly into the job's region.
+struct ServerLine1Dev {
+  gdp_ctx ctx;
+  DevCdtWork ws;
+  std::thread th;
+};
+
 struct gdp_server {
   gdp_ctx *user = nullptr;  // the caller's context: finished meshes are handed over to it
   ServerMem *mem = nullptr;
@@ -1745,13 +1757,20 @@ struct gdp_server {
   bool stop = false;
   std::vector<ServerWorker *> workers;
   std::chrono::steady_clock::time_point t0;
+  int32_t l1_threads = 0;    // > 0: Line 1 runs in the server, after arrival
+  int32_t l1_dev_min_v = 0;  // jobs with at least this many input vertices build on the device (0: none)
+  std::deque<Job *> l1_host, l1_dev;
+  std::vector<std::thread> l1_workers;
+  ServerLine1Dev *l1dev = nullptr;
 };
 
 namespace {
 
-// Places a prepared job in its region and uploads its initial mesh.
-gdp_status admit_job(gdp_server *S, Job *J, gdp_ctx *ctx) {
-  hipStream_t st = ctx->stream;
+// The mesh of job J laid out in its region (J->off, J->bytes, J->caps), with
+// the byte ranges that must be filled before use (offset, (bytes, fill byte));
+// run receives the bytes used.
+gdp_mesh *region_mesh(gdp_server *S, Job *J, gdp_ctx *ctx, std::vector<std::pair<size_t, std::pair<size_t, int>>> &fills,
+                      size_t &run) {
   gdp_mesh *M = new gdp_mesh();
   M->ctx = ctx;
   gdp_arena *a = new gdp_arena();
@@ -1762,21 +1781,30 @@ gdp_status admit_job(gdp_server *S, Job *J, gdp_ctx *ctx) {
   a->release = [sm, off, n]() { server_mem_release(sm, off, n); };
   M->arena = a;
   char *p = (char *)a->base;
-  std::vector<std::pair<size_t, std::pair<size_t, int>>> fills;
-  size_t run = 0;
+  run = 0;
   for_each_array(M, J->caps, [&](void **pp, size_t es, int64_t len, int fill) {
     size_t b = align256(es * (size_t)std::max<int64_t>(len, 1));
     *pp = p + run;
     if (fill) fills.push_back({run, {b, fill}});
     run += b;
   });
-  const HostMesh &h = J->hm;
   const Caps &c = J->caps;
   M->m.capV = (int32_t)c.V; M->m.capT = (int32_t)c.T; M->m.capS = (int32_t)c.S;
-  M->m.nV = h.nV; M->m.nT = h.nT; M->m.nS = h.nS;
-  M->m.n_input_v = h.nV; M->m.n_input_s = h.nS;
   M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
   M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
+  return M;
+}
+
+// Places a prepared job in its region and uploads its initial mesh.
+gdp_status admit_job(gdp_server *S, Job *J, gdp_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  std::vector<std::pair<size_t, std::pair<size_t, int>>> fills;
+  size_t run = 0;
+  gdp_mesh *M = region_mesh(S, J, ctx, fills, run);
+  char *p = (char *)M->arena->base;
+  const HostMesh &h = J->hm;
+  M->m.nV = h.nV; M->m.nT = h.nT; M->m.nS = h.nS;
+  M->m.n_input_v = h.nV; M->m.n_input_s = h.nS;
   J->mesh = M;
   DevState ds;
   memset(&ds, 0, sizeof ds);
@@ -1825,10 +1853,11 @@ void free_server_engine(ServerEngine *E) {
 }
 
 bool for_engine(const gdp_server *S, const Job *J) {
-  return S->engine_max_v > 0 && !J->grid_only && J->hm.nV <= S->engine_max_v;
+  return S->engine_max_v > 0 && !J->grid_only && !J->resident && J->nv_in <= S->engine_max_v;
 }
-bool for_slots(const gdp_server *S, const Job *J) { return S->mode == 1 && !for_engine(S, J); }
-bool for_gang(const gdp_server *S, const Job *J) { return S->mode == 0 && !for_engine(S, J); }
+bool for_slots(const gdp_server *S, const Job *J) { return !J->resident && S->mode == 1 && !for_engine(S, J); }
+// (a job whose CDT was built in its region joins the shared rounds in any mode)
+bool for_gang(const gdp_server *S, const Job *J) { return J->resident || (S->mode == 0 && !for_engine(S, J)); }
 
 // One batched launch over jobs already taken from the queue (regions held).
 void engine_batch(gdp_server *S, ServerEngine *E, std::vector<Job *> &B) {
@@ -1998,14 +2027,16 @@ void gang_driver(gdp_server *S, ServerGang *Gn) {
             ++it;
             continue;
           }
-          size_t off;
-          bool got;
-          {
-            std::lock_guard<std::mutex> gm(S->mem->mu);
-            got = S->mem->take(Q->bytes, &off);
+          if (!Q->resident) {
+            size_t off;
+            bool got;
+            {
+              std::lock_guard<std::mutex> gm(S->mem->mu);
+              got = S->mem->take(Q->bytes, &off);
+            }
+            if (!got) break;  // first come, first served: wait for room
+            Q->off = off;
           }
-          if (!got) break;  // first come, first served: wait for room
-          Q->off = off;
           Q->state = Job::ACTIVE;
           Q->t_admit = ms_since(S->t0);
           S->running++;
@@ -2036,7 +2067,9 @@ void gang_driver(gdp_server *S, ServerGang *Gn) {
       R = S->gang_rounds;
     }
     for (Job *J : fresh) {
-      gdp_status st = admit_job(S, J, ctx);
+      gdp_status st = GDP_OK;
+      if (J->resident) J->mesh->ctx = ctx;  // built on the Line-1 thread's stream, which has finished
+      else st = admit_job(S, J, ctx);
       if (st != GDP_OK) {
         if (J->mesh) gdp_mesh_free(J->mesh);
         J->mesh = nullptr;
@@ -2143,18 +2176,28 @@ void server_worker(gdp_server *S, ServerWorker *W) {
   }
 }
 
-// Line 1 on the host and everything a job needs before it arrives.
-gdp_status prepare_job(gdp_server *S, const gdp_pslg *pslg, double B2, const gdp_params *P, Job *J) {
-  gdp_ctx *ctx = S->user;
-  J->B2 = B2;
-  J->P = *P;
-  // a host synchronisation per round: the other slots keep the device busy
-  if (J->P.rounds_per_sync == 0) J->P.rounds_per_sync = 1;
-  J->xy.assign(pslg->xy, pslg->xy + 2 * (size_t)pslg->n_vertices);
-  J->seg.assign(pslg->seg, pslg->seg + 2 * (size_t)pslg->n_segments);
-  std::string e;
-  int rc = host_cdt_build(pslg->n_vertices, pslg->xy, pslg->n_segments, pslg->seg, J->hm, e);
-  if (rc != GDP_OK) return fail(ctx, (gdp_status)rc, e);
+// Region sizes of a job from its initial CDT's counts.
+void job_caps(gdp_server *S, Job *J, int64_t nV, int64_t nT, int64_t nS) {
+  Caps c;
+  c.V = 3 * nV + 256;
+  c.T = std::max<int64_t>(2 * c.V + 256, nT);
+  c.S = 16 * nS + 64;
+  c.W = c.T + 2 * c.S + 2;
+  c.tiles = c.W / kScanTileSize + 2;
+  c.pool = 2 * c.T + 4096;
+  c.fan = 2 * c.T + 4096;
+  J->caps = c;
+  gdp_mesh tmp;
+  size_t b = 0;
+  for_each_array(&tmp, c, [&](void **, size_t es, int64_t len, int) { b += align256(es * (size_t)std::max<int64_t>(len, 1)); });
+  J->bytes = b;
+}
+
+// Line 1 of a job on the host, and the arrays and region size it needs.
+gdp_status job_line1_host(gdp_server *S, Job *J, std::string &e) {
+  int rc = host_cdt_build((int32_t)(J->xy.size() / 2), J->xy.data(), (int32_t)(J->seg.size() / 2), J->seg.data(),
+                          J->hm, e);
+  if (rc != GDP_OK) return (gdp_status)rc;
   const HostMesh &h = J->hm;
   J->tv.resize(h.nT);
   J->tn.resize(h.nT);
@@ -2165,21 +2208,158 @@ gdp_status prepare_job(gdp_server *S, const gdp_pslg *pslg, double B2, const gdp
     J->tn[t] = make_int4(h.tn[3 * t], h.tn[3 * t + 1], h.tn[3 * t + 2], 0);
     J->ts[t] = make_int4(h.ts[3 * t], h.ts[3 * t + 1], h.ts[3 * t + 2], 0);
   }
-  Caps c;
-  c.V = 3 * (int64_t)h.nV + 256;
-  c.T = std::max<int64_t>(2 * c.V + 256, h.nT);
-  c.S = 16 * (int64_t)h.nS + 64;
-  c.W = c.T + 2 * c.S + 2;
-  c.tiles = c.W / kScanTileSize + 2;
-  c.pool = 2 * c.T + 4096;
-  c.fan = 2 * c.T + 4096;
-  J->caps = c;
-  gdp_mesh tmp;
-  size_t b = 0;
-  for_each_array(&tmp, c, [&](void **, size_t es, int64_t len, int) { b += align256(es * (size_t)std::max<int64_t>(len, 1)); });
-  J->bytes = b;
-  if (b > S->mem->size) return fail(ctx, GDP_E_NOMEM, "job larger than the server's memory budget");
+  job_caps(S, J, h.nV, h.nT, h.nS);
+  if (J->bytes > S->mem->size) {
+    e = "job larger than the server's memory budget";
+    return GDP_E_NOMEM;
+  }
   return GDP_OK;
+}
+
+// The checks of the device builder's caller (gdp_mesh_create_device).
+gdp_status check_pslg_for_device(const gdp_pslg *pslg, std::string &e) {
+  const int32_t nv = pslg->n_vertices, ns = pslg->n_segments;
+  if (nv < 3 || !pslg->xy || ns < 0 || (ns > 0 && !pslg->seg)) { e = "bad arguments"; return GDP_E_ARG; }
+  if (nv > (1 << 28) - 8) { e = "mesh too large"; return GDP_E_NOMEM; }
+  for (int64_t i = 0; i < 2 * (int64_t)nv; i++) {
+    const double a = std::fabs(pslg->xy[i]);
+    if (!std::isfinite(pslg->xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100)) {
+      e = "coordinate not finite, or nonzero with magnitude outside [2^-100, 2^20]";
+      return GDP_E_INPUT;
+    }
+  }
+  for (int32_t k = 0; k < ns; k++) {
+    const int32_t a = pslg->seg[2 * k], b = pslg->seg[2 * k + 1];
+    if (a < 0 || b < 0 || a >= nv || b >= nv || a == b) {
+      e = "segment endpoint out of range or zero length";
+      return GDP_E_INPUT;
+    }
+  }
+  return GDP_OK;
+}
+
+// Everything a job needs before it arrives: its input and parameters, and
+// (unless Line 1 runs in the server) Line 1 on the host.
+gdp_status prepare_job(gdp_server *S, const gdp_pslg *pslg, double B2, const gdp_params *P, Job *J) {
+  gdp_ctx *ctx = S->user;
+  J->B2 = B2;
+  J->P = *P;
+  // a host synchronisation per round: the other slots keep the device busy
+  if (J->P.rounds_per_sync == 0) J->P.rounds_per_sync = 1;
+  std::string e;
+  gdp_status st;
+  if (S->l1_threads > 0 && (st = check_pslg_for_device(pslg, e))) return fail(ctx, st, e);
+  J->xy.assign(pslg->xy, pslg->xy + 2 * (size_t)pslg->n_vertices);
+  J->seg.assign(pslg->seg, pslg->seg + 2 * (size_t)pslg->n_segments);
+  J->nv_in = pslg->n_vertices;
+  if (S->l1_threads > 0) {
+    J->raw = true;
+    return GDP_OK;
+  }
+  if ((st = job_line1_host(S, J, e))) return fail(ctx, st, e);
+  return GDP_OK;
+}
+
+// Line 1 of job J has finished in the server with status st: the job joins
+// the admission queue, or ends.
+void line1_done(gdp_server *S, Job *J, gdp_status st) {
+  std::lock_guard<std::mutex> g(S->mu);
+  J->t_line1 = ms_since(S->t0);
+  if (st != GDP_OK) {
+    J->status = st;
+    J->t_done = J->t_line1;
+    J->state = Job::DONE;
+  } else {
+    J->state = Job::QUEUED;
+    S->queue.push_back(J);
+  }
+  S->cv.notify_all();
+}
+
+// Takes the next job of a Line-1 queue (nullptr once the server stops).
+Job *line1_next(gdp_server *S, std::deque<Job *> &q) {
+  std::unique_lock<std::mutex> g(S->mu);
+  S->cv.wait(g, [&] { return S->stop || !q.empty(); });
+  if (S->stop) return nullptr;
+  Job *J = q.front();
+  q.pop_front();
+  return J;
+}
+
+void line1_host_worker(gdp_server *S) {
+  for (;;) {
+    Job *J = line1_next(S, S->l1_host);
+    if (!J) return;
+    std::string e;
+    line1_done(S, J, job_line1_host(S, J, e));
+  }
+}
+
+// Line 1 of a large job by kernels, into its region: the region is taken
+// here (sized from the input: a CDT has at most 2 V triangles), the input
+// is uploaded and the device builder writes the canonical CDT in place.
+gdp_status job_line1_device(gdp_server *S, ServerLine1Dev *D, Job *J) {
+  const int32_t nv = J->nv_in, ns = (int32_t)(J->seg.size() / 2);
+  job_caps(S, J, nv, 2 * (int64_t)nv, ns);
+  if (J->bytes > S->mem->size) return GDP_E_NOMEM;
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> gm(S->mem->mu);
+      if (S->mem->take(J->bytes, &J->off)) break;
+    }
+    std::unique_lock<std::mutex> g(S->mu);
+    if (S->stop) return GDP_E_NOMEM;
+    S->cv.wait_for(g, std::chrono::milliseconds(1));
+  }
+  gdp_ctx *ctx = &D->ctx;
+  hipStream_t st = ctx->stream;
+  std::vector<std::pair<size_t, std::pair<size_t, int>>> fills;
+  size_t run = 0;
+  gdp_mesh *M = region_mesh(S, J, ctx, fills, run);
+  J->mesh = M;
+  char *p = (char *)M->arena->base;
+  std::vector<int32_t> spar(ns);
+  for (int32_t k = 0; k < ns; k++) spar[k] = k;
+  HIPCHECK(hipMemsetAsync(p, 0, run, st));
+  for (auto &f : fills) HIPCHECK(hipMemsetAsync(p + f.first, f.second.second, f.second.first, st));
+  HIPCHECK(hipMemcpyAsync(M->m.vxy, J->xy.data(), sizeof(double) * 2 * nv, hipMemcpyHostToDevice, st));
+  if (ns) {
+    HIPCHECK(hipMemcpyAsync(M->m.sv, J->seg.data(), sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(M->m.spar, spar.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+  }
+  std::string e;
+  int32_t nt = 0;
+  DevCdtStats cs;
+  const int rc = dev_cdt_build(st, nv, M->m.vxy, ns, M->m.sv, M->m.tv, M->m.tn, M->m.ts, M->m.capT, &nt, &cs, e,
+                               &D->ws);
+  if (rc != GDP_OK) return (gdp_status)rc;
+  M->m.nV = nv; M->m.nT = nt; M->m.nS = ns;
+  M->m.n_input_v = nv; M->m.n_input_s = ns;
+  M->cdt_rounds[0] = cs.dt_rounds;
+  M->cdt_rounds[1] = cs.seg_rounds;
+  DevState ds;
+  memset(&ds, 0, sizeof ds);
+  ds.nV = nv; ds.nT = nt; ds.nS = ns;
+  ds.wT = words(nt); ds.wS = words(ns);
+  ds.full = 1;
+  HIPCHECK(hipMemcpyAsync(M->d_st, &ds, sizeof ds, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));  // ds and spar are host locals
+  J->resident = true;
+  return GDP_OK;
+}
+
+void line1_dev_worker(gdp_server *S, ServerLine1Dev *D) {
+  (void)hipSetDevice(D->ctx.device);
+  for (;;) {
+    Job *J = line1_next(S, S->l1_dev);
+    if (!J) return;
+    gdp_status st = job_line1_device(S, D, J);
+    if (st != GDP_OK && J->mesh) {
+      gdp_mesh_free(J->mesh);
+      J->mesh = nullptr;
+    }
+    line1_done(S, J, st);
+  }
 }
 
 // Queues up to this many rounds before the next host synchronisation.
@@ -3432,10 +3612,38 @@ gdp_status gdp_server_arrive(gdp_server *srv, uint64_t job) {
   auto it = srv->jobs.find(job);
   if (it == srv->jobs.end() || it->second->state != Job::PREPARED) return GDP_E_ARG;
   Job *J = it->second;
-  J->state = Job::QUEUED;
   J->t_submit = ms_since(srv->t0);
-  srv->queue.push_back(J);
+  if (J->raw) {
+    J->state = Job::LINE1;
+    const bool dev = srv->l1dev && srv->l1_dev_min_v > 0 && J->nv_in >= srv->l1_dev_min_v && srv->mode == 0 &&
+                     !for_engine(srv, J);
+    (dev ? srv->l1_dev : srv->l1_host).push_back(J);
+  } else {
+    J->state = Job::QUEUED;
+    srv->queue.push_back(J);
+  }
   srv->cv.notify_all();
+  return GDP_OK;
+}
+
+gdp_status gdp_server_line1(gdp_server *srv, int32_t host_threads, int32_t device_min_vertices) {
+  if (!srv || host_threads < 1 || host_threads > 64 || device_min_vertices < 0) return GDP_E_ARG;
+  std::lock_guard<std::mutex> g(srv->mu);
+  if (srv->l1_threads > 0 || !srv->jobs.empty()) return fail(srv->user, GDP_E_BUSY, "Line 1 is set before the first job");
+  if (device_min_vertices > 0) {
+    ServerLine1Dev *D = new ServerLine1Dev();
+    D->ctx.device = srv->user->device;
+    if (hipSetDevice(D->ctx.device) != hipSuccess ||
+        hipStreamCreateWithFlags(&D->ctx.stream, hipStreamNonBlocking) != hipSuccess) {
+      delete D;
+      return fail(srv->user, GDP_E_DEVICE, "stream creation failed");
+    }
+    srv->l1dev = D;
+    srv->l1_dev_min_v = device_min_vertices;
+    D->th = std::thread(line1_dev_worker, srv, D);
+  }
+  srv->l1_threads = host_threads;
+  for (int i = 0; i < host_threads; i++) srv->l1_workers.emplace_back(line1_host_worker, srv);
   return GDP_OK;
 }
 
@@ -3456,6 +3664,7 @@ static gdp_status server_take(gdp_server *srv, uint64_t job, gdp_mesh **out, gdp
   if (wait) srv->cv.wait(g, [&] { return J->state == Job::DONE || srv->stop; });
   if (times) {
     times->submit_ms = J->t_submit;
+    times->line1_ms = J->t_line1;
     times->admit_ms = J->t_admit;
     times->done_ms = J->t_done;
   }
@@ -3485,6 +3694,13 @@ void gdp_server_destroy(gdp_server *srv) {
     std::lock_guard<std::mutex> g(srv->mu);
     srv->stop = true;
     srv->cv.notify_all();
+  }
+  for (std::thread &t : srv->l1_workers) t.join();
+  if (srv->l1dev) {
+    srv->l1dev->th.join();
+    (void)hipStreamDestroy(srv->l1dev->ctx.stream);
+    dev_cdt_work_free(srv->l1dev->ws);
+    delete srv->l1dev;
   }
   for (ServerWorker *W : srv->workers) W->th.join();
   if (srv->eng) srv->eng->th.join();

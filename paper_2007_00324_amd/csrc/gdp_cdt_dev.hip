@@ -971,8 +971,15 @@ hipError_t sort_pairs_u64(hipStream_t stream, uint64_t *k0, int *v0, uint64_t *k
 // their count to *n_tri.  Coordinates and segment endpoints are checked by
 // the caller.  Returns GDP_OK, GDP_E_INPUT (invalid PSLG, err set),
 // GDP_E_NOMEM or GDP_E_DEVICE.
+void dev_cdt_work_free(DevCdtWork &ws) {
+  if (ws.mem) (void)hipFree(ws.mem);
+  if (ws.hctr) (void)hipHostFree(ws.hctr);
+  ws = DevCdtWork();
+}
+
 int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, const int2 *d_seg, int4 *otv,
-                  int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err) {
+                  int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err,
+                  DevCdtWork *ws) {
   if (nv < 3) { err = "bad arguments"; return GDP_E_ARG; }
   // enclosing triangle, as the host builder places it
   std::vector<double2> hxy(nv);
@@ -999,14 +1006,31 @@ int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, con
   const size_t o_keys = take(8 * (size_t)capT), o_keys2 = take(8 * (size_t)capT);
   const size_t o_vals = take(4 * (size_t)capT), o_vals2 = take(4 * (size_t)capT), o_newid = take(4 * (size_t)capT);
   const size_t o_sort = take(4 * 256 * (size_t)((capT + kSortTile - 1) / kSortTile));
-  if (hipMalloc(&mem, off) != hipSuccess) { err = "device allocation failed"; return GDP_E_NOMEM; }
-  char *base = (char *)mem;
   Ctr *hctr = nullptr;
-  if (hipHostMalloc((void **)&hctr, sizeof(Ctr)) != hipSuccess) { (void)hipFree(mem); err = "host allocation failed"; return GDP_E_NOMEM; }
+  if (ws) {
+    // every earlier build on the workspace has finished (each one ends with
+    // a stream synchronisation), so its scratch can be replaced
+    if (ws->bytes < off) {
+      if (ws->mem) (void)hipFree(ws->mem);
+      ws->mem = nullptr;
+      ws->bytes = 0;
+      if (hipMalloc(&ws->mem, off) != hipSuccess) { ws->mem = nullptr; err = "device allocation failed"; return GDP_E_NOMEM; }
+      ws->bytes = off;
+    }
+    if (!ws->hctr && hipHostMalloc(&ws->hctr, sizeof(Ctr)) != hipSuccess) { ws->hctr = nullptr; err = "host allocation failed"; return GDP_E_NOMEM; }
+    mem = ws->mem;
+    hctr = (Ctr *)ws->hctr;
+  } else {
+    if (hipMalloc(&mem, off) != hipSuccess) { err = "device allocation failed"; return GDP_E_NOMEM; }
+    if (hipHostMalloc((void **)&hctr, sizeof(Ctr)) != hipSuccess) { (void)hipFree(mem); err = "host allocation failed"; return GDP_E_NOMEM; }
+  }
+  char *base = (char *)mem;
   auto done = [&](int rc) {
     (void)hipStreamSynchronize(stream);
-    (void)hipFree(mem);
-    (void)hipHostFree(hctr);
+    if (!ws) {
+      (void)hipFree(mem);
+      (void)hipHostFree(hctr);
+    }
     return rc;
   };
   Bld b;

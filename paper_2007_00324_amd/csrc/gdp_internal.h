@@ -37,8 +37,19 @@ struct DevCdtStats {
 // sorted pairs end in (k1, v1); hist: 256 * ceil(n / kSortPairsTile) ints.
 constexpr int kSortPairsTile = 2048;
 hipError_t sort_pairs_u64(hipStream_t stream, uint64_t *k0, int *v0, uint64_t *k1, int *v1, int n, int *hist);
+// A reusable workspace for repeated builds (a long-lived caller such as the
+// server's Line-1 thread): device scratch that grows to the largest build
+// seen, and one pinned counter block.  Without one, a build allocates and
+// frees its own.
+struct DevCdtWork {
+  void *mem = nullptr;
+  size_t bytes = 0;
+  void *hctr = nullptr;
+};
+void dev_cdt_work_free(DevCdtWork &ws);
 int dev_cdt_build(hipStream_t stream, int32_t nv, double2 *d_xy, int32_t ns, const int2 *d_seg, int4 *otv,
-                  int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err);
+                  int4 *otn, int4 *ots, int32_t cap_out, int32_t *n_tri, DevCdtStats *stats, std::string &err,
+                  DevCdtWork *ws = nullptr);
 
 // ---- device mesh --------------------------------------------------------------
 // Triangle t: tv[t] = (v0, v1, v2, subsegment-edge mask), tn[t] = (n0, n1, n2, 0),

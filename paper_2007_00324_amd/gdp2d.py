@@ -33,7 +33,8 @@ class gdp_pslg(C.Structure):
 
 
 class gdp_job_times(C.Structure):
-    _fields_ = [("submit_ms", C.c_double), ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+    _fields_ = [("submit_ms", C.c_double), ("line1_ms", C.c_double), ("admit_ms", C.c_double),
+                ("done_ms", C.c_double)]
 
 
 class gdp_params(C.Structure):
@@ -125,6 +126,7 @@ def load() -> C.CDLL:
         "gdp_server_destroy": (None, [_VP]),
         "gdp_server_engine_jobs": (S, [_VP, C.c_int32]),
         "gdp_server_mode": (S, [_VP, C.c_int32, C.c_int32]),
+        "gdp_server_line1": (S, [_VP, C.c_int32, C.c_int32]),
         "gdp_mesh_device_views": (S, [_VP, C.POINTER(gdp_device_views)]),
         "gdp_predicates_eval": (S, [_VP, C.c_int32, C.c_int32, _PD, _PI, C.POINTER(C.c_int64)]),
         "gdp_bench_atomic_max": (S, [_VP, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
@@ -145,7 +147,8 @@ def exported_symbols() -> list[str]:
             "gdp_mesh_kernel_profile", "gdp_mesh_assign", "gdp_mesh_clone", "gdp_mesh_free", "gdp_refine_batch",
             "gdp_server_create", "gdp_server_prepare", "gdp_server_arrive", "gdp_server_submit", "gdp_server_poll",
             "gdp_server_wait", "gdp_server_engine_jobs", "gdp_server_destroy", "gdp_mesh_device_views",
-            "gdp_predicates_eval", "gdp_bench_atomic_max", "gdp_mesh_quality_noalloc", "gdp_server_mode"]
+            "gdp_predicates_eval", "gdp_bench_atomic_max", "gdp_mesh_quality_noalloc", "gdp_server_mode",
+            "gdp_server_line1"]
 
 
 def _ptr(a: np.ndarray, ct):
@@ -435,7 +438,7 @@ class Server:
     device-resident Mesh."""
 
     def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, engine_max_vertices: int | None = None,
-                 mode: int = 0, rounds_per_group: int = 0):
+                 mode: int = 0, rounds_per_group: int = 0, line1: tuple[int, int] | None = None):
         self.ctx = ctx
         self._h = _VP()
         ctx.check(load().gdp_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(self._h)))
@@ -443,6 +446,13 @@ class Server:
             self.ctx.check(load().gdp_server_mode(self._h, int(mode), int(rounds_per_group)))
         if engine_max_vertices is not None:
             self.engine_jobs(engine_max_vertices)
+        if line1 is not None:
+            self.line1(*line1)
+
+    def line1(self, host_threads: int, device_min_vertices: int) -> None:
+        """Line 1 runs in the server after arrival: on host_threads library threads, or on the
+        device for jobs with at least device_min_vertices input vertices (0: never)."""
+        self.ctx.check(load().gdp_server_line1(self._h, int(host_threads), int(device_min_vertices)))
 
     def engine_jobs(self, max_input_vertices: int) -> None:
         """Jobs up to this many input vertices run in batched single-workgroup launches (0: never)."""
@@ -468,7 +478,7 @@ class Server:
         h = _VP()
         t = gdp_job_times()
         rc = fn(self._h, C.c_uint64(job), C.byref(h), C.byref(t))
-        times = {"submit_ms": t.submit_ms, "admit_ms": t.admit_ms, "done_ms": t.done_ms}
+        times = {"submit_ms": t.submit_ms, "line1_ms": t.line1_ms, "admit_ms": t.admit_ms, "done_ms": t.done_ms}
         if rc == GDP_E_BUSY:
             return None, rc, times
         return (Mesh(self.ctx, h) if h.value else None), rc, times
