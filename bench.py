@@ -410,7 +410,7 @@ def make_batch(count: int, workers: int):
     return ps
 
 
-def batched_leg(ctx, ps, plain_every: int) -> dict:
+def batched_leg(ctx, ps, plain_every: int, line1_dev_min: int = 0) -> dict:
     """Batched form: independent PSLGs refined in one persistent launch,
     against the plain per-instance loop on a sample of the same instances."""
     from paper_2007_00324_amd import gdp2d
@@ -434,6 +434,20 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
     m2, st2, default_ms = gdp2d.gdp_refine_batch(ctx, inputs, bsq, default_prm)
     del m2
     log(f"batched (default: every mesh in the engine): device {default_ms:.1f} ms")
+    line1_dev = None
+    if line1_dev_min > 0:
+        prm_dev = tune_batch.tuned_params(table)
+        prm_dev.batch_line1_device_min_v = line1_dev_min
+        t = time.perf_counter()
+        m3, st3, dev3_ms = gdp2d.gdp_refine_batch(ctx, inputs, bsq, prm_dev)
+        wall3 = time.perf_counter() - t
+        bad3 = sum(1 for s_ in st3 if s_ != 0)
+        del m3
+        n_dev = sum(1 for p in ps if p.n_vertices >= line1_dev_min)
+        line1_dev = {"device_min_vertices": line1_dev_min, "device_built": n_dev, "call_s": wall3,
+                     "jobs_per_s_with_line1": count / wall3, "device_ms": dev3_ms, "failed": bad3}
+        log(f"batched, Line 1 of the {n_dev} inputs with >= {line1_dev_min:,} vertices on the device: call "
+            f"{wall3:.2f} s ({count / wall3:,.0f} jobs/s with Line 1), {bad3} not OK")
     sample = ps[::plain_every]
     plain_ms = 0.0
     for p in sample:
@@ -458,6 +472,7 @@ def batched_leg(ctx, ps, plain_every: int) -> dict:
         "default_jobs_per_s": count / (default_ms / 1000.0),
         "tuned_vs_default": default_ms / dev_ms,
         "jobs_per_s_with_host_cdt": count / wall,
+        "line1_device": line1_dev,
         "plain_jobs_per_s": plain_jobs_s,
         "plain_sample": f"every {plain_every}th job ({len(sample)} jobs), each gdp_mesh_refine timed alone",
         "speedup_vs_plain": jobs_s / plain_jobs_s,
@@ -612,6 +627,8 @@ def main() -> int:
     ap.add_argument("--no-flipflop", action="store_true", help="skip the Flip-Flop insertion leg")
     ap.add_argument("--batch", type=int, default=4096, help="jobs of the batched form (0: skip)")
     ap.add_argument("--batch-plain-every", type=int, default=16, help="plain-loop sample: every k-th job")
+    ap.add_argument("--batch-line1-device-min", type=int, default=30000,
+                    help="batched form also run with Line 1 on the device from this many input vertices (0: skip)")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched inputs")
     ap.add_argument("--serve", type=int, default=400, help="jobs of the serving stream (0: skip)")
     ap.add_argument("--serve-rates", type=str, default="0.25x,0.5x,0.9x,1.5x",
@@ -826,7 +843,7 @@ def main() -> int:
         out["ablation"] = ablation_leg(ctx, init, work, p, init2, p2)
         del init2
     if args.batch > 0:
-        out["batched"] = batched_leg(ctx, batch, args.batch_plain_every)
+        out["batched"] = batched_leg(ctx, batch, args.batch_plain_every, args.batch_line1_device_min)
     if serve_jobs:
         rates = [r for r in args.serve_rates.split(",") if r]
         out["serving"] = serving_leg(ctx, serve_jobs, rates, args.serve_budget_gb, args.serve_slots, 8,

@@ -142,6 +142,13 @@ typedef struct {
                                forms).  A refine call in this mode starts by
                                flipping the mesh to the CDT under the symbolic
                                perturbation of the lifting map. */
+  /* perf only (batched form) */
+  int32_t batch_line1_device_min_v; /* gdp_refine_batch: inputs with at least this
+                               many vertices get their initial CDT (Line 1) from
+                               the device builder of gdp_mesh_create_device (the
+                               same CDT), on library threads with streams of their
+                               own, while host threads build the others; 0 = every
+                               input on the host */
 } gdp_params;
 
 /* Per-kernel totals of the last profiled gdp_mesh_refine. */

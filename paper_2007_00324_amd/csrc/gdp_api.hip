@@ -2,7 +2,9 @@
 // and the host loop that issues one refinement round after another
 // (Algorithm 1, "repeat ... until L is empty").
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <memory>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -1291,6 +1293,64 @@ void gang_group(gdp_ctx *ctx, GangBufs &B, std::vector<GangItem> &active, int R,
 }
 
 constexpr size_t kBatchGangMax = 256;  // batched meshes in one group of shared rounds, at most
+constexpr int32_t kBatchLine1DevThreads = 8;  // device Line-1 builders of a batch, each on its own stream
+
+// The checks of the device builder's caller (gdp_mesh_create_device).
+gdp_status check_pslg_for_device(const gdp_pslg *pslg, std::string &e) {
+  const int32_t nv = pslg->n_vertices, ns = pslg->n_segments;
+  if (nv < 3 || !pslg->xy || ns < 0 || (ns > 0 && !pslg->seg)) { e = "bad arguments"; return GDP_E_ARG; }
+  if (nv > (1 << 28) - 8) { e = "mesh too large"; return GDP_E_NOMEM; }
+  for (int64_t i = 0; i < 2 * (int64_t)nv; i++) {
+    const double a = std::fabs(pslg->xy[i]);
+    if (!std::isfinite(pslg->xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100)) {
+      e = "coordinate not finite, or nonzero with magnitude outside [2^-100, 2^20]";
+      return GDP_E_INPUT;
+    }
+  }
+  for (int32_t k = 0; k < ns; k++) {
+    const int32_t a = pslg->seg[2 * k], b = pslg->seg[2 * k + 1];
+    if (a < 0 || b < 0 || a >= nv || b >= nv || a == b) {
+      e = "segment endpoint out of range or zero length";
+      return GDP_E_INPUT;
+    }
+  }
+  return GDP_OK;
+}
+
+// Line 1 of one batched input by the device builder, into its arena slot M
+// (zeroed and filled beforehand): the input goes up, the canonical CDT is
+// written in place, then the mesh's device state.  nT receives the
+// triangle count.
+int batch_line1_device(hipStream_t st, DevCdtWork &ws, const gdp_pslg &q, gdp_mesh *M, int32_t &nT,
+                       std::string &err) {
+  const int32_t nv = q.n_vertices, ns = q.n_segments;
+  std::vector<int32_t> spar(ns);
+  for (int32_t k = 0; k < ns; k++) spar[k] = k;
+  if (hipMemcpyAsync(M->m.vxy, q.xy, sizeof(double) * 2 * nv, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (ns > 0 && hipMemcpyAsync(M->m.sv, q.seg, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, st) != hipSuccess) ||
+      (ns > 0 && hipMemcpyAsync(M->m.spar, spar.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st) != hipSuccess)) {
+    err = "upload failed";
+    return GDP_E_DEVICE;
+  }
+  DevCdtStats cs;
+  int32_t nt = 0;
+  const int rc = dev_cdt_build(st, nv, M->m.vxy, ns, M->m.sv, M->m.tv, M->m.tn, M->m.ts, M->m.capT, &nt, &cs, err, &ws);
+  if (rc != GDP_OK) return rc;
+  M->cdt_rounds[0] = cs.dt_rounds;
+  M->cdt_rounds[1] = cs.seg_rounds;
+  DevState ds;
+  memset(&ds, 0, sizeof ds);
+  ds.nV = nv; ds.nT = nt; ds.nS = ns;
+  ds.wT = words(nt); ds.wS = words(ns);
+  ds.full = 1;
+  if (hipMemcpyAsync(M->d_st, &ds, sizeof ds, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {  // ds and spar are locals
+    err = "upload failed";
+    return GDP_E_DEVICE;
+  }
+  nT = nt;
+  return GDP_OK;
+}
 // The batched form (Algorithm 1 for many independent PSLGs): Line 1 on the
 // host for every input (in parallel), one arena holding every mesh and its
 // workspace, then all of Lines 2-9 in one launch of the single-workgroup
@@ -1303,27 +1363,32 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
     outs[i] = nullptr;
     if (status) status[i] = GDP_OK;
   }
-  // Line 1 on the host
-  std::vector<HostMesh> hm(count);
+  // Line 1.  Inputs with at least batch_line1_device_min_v vertices are
+  // triangulated by the device builder (threads with a stream each, writing
+  // into the arena), the others on host threads, both at once.  The arena is
+  // sized before Line 1 from the input counts (a CDT of V vertices has at
+  // most 2V triangles and keeps the input segments), with the device-built
+  // meshes last in every array region so that the host-built ones are
+  // uploaded as one prefix of each region.
+  const int64_t dev_min = P->batch_line1_device_min_v;
   std::vector<int> rc(count, GDP_OK);
   std::vector<std::string> errs(count);
-  {
-    std::atomic<int32_t> next(0);
-    unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16));
-    nth = std::min<unsigned>(nth, (unsigned)std::max(count, 1));
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < nth; t++)
-      pool.emplace_back([&]() {
-        for (int32_t i; (i = next.fetch_add(1)) < count;)
-          rc[i] = host_cdt_build(pslgs[i].n_vertices, pslgs[i].xy, pslgs[i].n_segments, pslgs[i].seg, hm[i], errs[i]);
-      });
-    for (auto &th : pool) th.join();
-  }
-  std::vector<int32_t> ok;
+  std::vector<int32_t> ok, ok_dev;
   for (int32_t i = 0; i < count; i++) {
-    if (rc[i] == GDP_OK) ok.push_back(i);
-    else if (status) status[i] = (gdp_status)rc[i];
+    const gdp_pslg &q = pslgs[i];
+    if (q.n_vertices < 3 || !q.xy || q.n_segments < 0 || (q.n_segments > 0 && !q.seg)) {
+      rc[i] = GDP_E_ARG;
+      errs[i] = "bad arguments";
+    } else if (dev_min > 0 && q.n_vertices >= dev_min) {
+      rc[i] = check_pslg_for_device(&q, errs[i]);
+      if (rc[i] == GDP_OK) ok_dev.push_back(i);
+    } else {
+      ok.push_back(i);
+    }
+    if (rc[i] != GDP_OK && status) status[i] = (gdp_status)rc[i];
   }
+  const int32_t n_host = (int32_t)ok.size();
+  ok.insert(ok.end(), ok_dev.begin(), ok_dev.end());
   if (elapsed_ms) *elapsed_ms = 0.0;
   if (ok.empty()) return GDP_OK;
   // capacities: room for the refined mesh (about 2.5x the input vertices at
@@ -1331,13 +1396,14 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   const int32_t n = (int32_t)ok.size();
   std::vector<gdp_mesh *> mesh(n);
   std::vector<Caps> caps(n);
+  std::vector<int32_t> nT0(n, 0);  // triangles of each initial CDT
   gdp_arena *arena = new gdp_arena();
   for (int32_t k = 0; k < n; k++) {
-    const HostMesh &h = hm[ok[k]];
+    const int64_t nv = pslgs[ok[k]].n_vertices, ns = pslgs[ok[k]].n_segments;
     Caps c;
-    c.V = 3 * (int64_t)h.nV + 256;
-    c.T = std::max<int64_t>(2 * c.V + 256, h.nT);
-    c.S = 16 * (int64_t)h.nS + 64;
+    c.V = 3 * nv + 256;
+    c.T = std::max<int64_t>(2 * c.V + 256, 2 * nv);
+    c.S = 16 * ns + 64;
     c.W = c.T + 2 * c.S + 2;
     c.tiles = c.W / kScanTileSize + 2;
     c.pool = 2 * c.T + 4096;
@@ -1366,6 +1432,7 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   }
   auto bail = [&](gdp_status st) {
     for (gdp_mesh *M : mesh) {
+      if (!M) continue;
       M->arena = nullptr;
       delete M;
     }
@@ -1387,62 +1454,152 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
       run[j] += align256(es * (size_t)std::max<int64_t>(len, 1));
       j++;
     });
+    const Caps &c = caps[k];
+    gdp_mesh *M = mesh[k];
+    M->m.capV = (int32_t)c.V; M->m.capT = (int32_t)c.T; M->m.capS = (int32_t)c.S;
+    M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
+    M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
   }
   if (hipMemsetAsync(base, 0, total, s) != hipSuccess) return bail(fail(ctx, GDP_E_DEVICE, "arena fill failed"));
   for (size_t j = 0; j < region.size(); j++)
     if (fills[j] && hipMemsetAsync(base + region_off[j], fills[j], region[j], s) != hipSuccess)
       return bail(fail(ctx, GDP_E_DEVICE, "arena fill failed"));
-  // initial meshes and device states, staged per region (array indices as in for_each_array)
-  enum { R_VXY = 0, R_TV = 2, R_TN = 3, R_TS = 4, R_SV = 5, R_SPAR = 6 };
-  const int R_ST = (int)region.size() - 4;  // d_st (then d_hist, rhist, sel)
-  auto stage = [&](int j, auto fillfn) -> gdp_status {
-    std::vector<char> h(region[j], 0);
-    for (int32_t k = 0; k < n; k++) fillfn(k, h.data() + off[k][j]);
-    if (hipMemcpy(base + region_off[j], h.data(), region[j], hipMemcpyHostToDevice) != hipSuccess)
-      return fail(ctx, GDP_E_DEVICE, "batch upload failed");
-    return GDP_OK;
-  };
-  gdp_status st = GDP_OK;
-  if ((st = stage(R_VXY, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].xy.data(), sizeof(double) * 2 * hm[ok[k]].nV); })))
-    return bail(st);
-  for (int e = 0; e < 3; e++) {
-    const int j = e == 0 ? R_TV : (e == 1 ? R_TN : R_TS);
-    st = stage(j, [&](int32_t k, char *d) {
-      const HostMesh &h = hm[ok[k]];
-      int4 *q = (int4 *)d;
-      for (int32_t t = 0; t < h.nT; t++) {
-        const int32_t *a = e == 0 ? &h.tv[3 * t] : (e == 1 ? &h.tn[3 * t] : &h.ts[3 * t]);
-        int w = 0;
-        if (e == 0)
-          w = (h.ts[3 * t] >= 0 ? 1 : 0) | (h.ts[3 * t + 1] >= 0 ? 2 : 0) | (h.ts[3 * t + 2] >= 0 ? 4 : 0);
-        q[t] = make_int4(a[0], a[1], a[2], w);
-      }
-    });
-    if (st) return bail(st);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(ctx, GDP_E_DEVICE, "arena fill failed"));
+  // the host-built meshes go up packed: per mesh its points, the three
+  // triangle arrays (room for the 2V triangles a CDT can have), segments,
+  // segment parents and device state, each chunk 16-byte aligned, written by
+  // the thread that built the mesh; one copy, then a device scatter into the
+  // arena (the arena's room beyond each mesh is already zero)
+  enum { C_VXY, C_TV, C_TN, C_TS, C_SV, C_SPAR, C_ST, C_N };
+  std::vector<std::array<int64_t, C_N>> pk(n_host);
+  int64_t pk_total = 0;
+  for (int32_t k = 0; k < n_host; k++) {
+    const int64_t nv = pslgs[ok[k]].n_vertices, ns = pslgs[ok[k]].n_segments;
+    const int64_t sz[C_N] = {16 * nv, 32 * nv, 32 * nv, 32 * nv, 8 * ns, 4 * ns, (int64_t)sizeof(DevState)};
+    for (int c = 0; c < C_N; c++) {
+      pk[k][c] = pk_total;
+      pk_total += (sz[c] + 15) & ~(int64_t)15;
+    }
   }
-  if ((st = stage(R_SV, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].sv.data(), sizeof(int32_t) * 2 * hm[ok[k]].nS); })))
-    return bail(st);
-  if ((st = stage(R_SPAR, [&](int32_t k, char *d) { memcpy(d, hm[ok[k]].sparent.data(), sizeof(int32_t) * hm[ok[k]].nS); })))
-    return bail(st);
-  if ((st = stage(R_ST, [&](int32_t k, char *d) {
-         const HostMesh &h = hm[ok[k]];
-         DevState ds;
-         memset(&ds, 0, sizeof ds);
-         ds.nV = h.nV; ds.nT = h.nT; ds.nS = h.nS;
-         ds.wT = words(h.nT); ds.wS = words(h.nS);
-         ds.full = 1;
-         memcpy(d, &ds, sizeof ds);
-       })))
-    return bail(st);
+  std::unique_ptr<char[]> packed(new (std::nothrow) char[std::max<int64_t>(pk_total, 16)]);
+  if (!packed) return bail(fail(ctx, GDP_E_NOMEM, "batch staging allocation failed"));
+  auto pack = [&](int32_t k, const HostMesh &h) {
+    char *b = packed.get();
+    memcpy(b + pk[k][C_VXY], h.xy.data(), sizeof(double) * 2 * h.nV);
+    int4 *tv = (int4 *)(b + pk[k][C_TV]), *tn = (int4 *)(b + pk[k][C_TN]), *ts = (int4 *)(b + pk[k][C_TS]);
+    for (int32_t t = 0; t < h.nT; t++) {
+      const int w = (h.ts[3 * t] >= 0 ? 1 : 0) | (h.ts[3 * t + 1] >= 0 ? 2 : 0) | (h.ts[3 * t + 2] >= 0 ? 4 : 0);
+      tv[t] = make_int4(h.tv[3 * t], h.tv[3 * t + 1], h.tv[3 * t + 2], w);
+      tn[t] = make_int4(h.tn[3 * t], h.tn[3 * t + 1], h.tn[3 * t + 2], 0);
+      ts[t] = make_int4(h.ts[3 * t], h.ts[3 * t + 1], h.ts[3 * t + 2], 0);
+    }
+    if (h.nS) {
+      memcpy(b + pk[k][C_SV], h.sv.data(), sizeof(int32_t) * 2 * h.nS);
+      memcpy(b + pk[k][C_SPAR], h.sparent.data(), sizeof(int32_t) * h.nS);
+    }
+    DevState ds;
+    memset(&ds, 0, sizeof ds);
+    ds.nV = h.nV; ds.nT = h.nT; ds.nS = h.nS;
+    ds.wT = words(h.nT); ds.wS = words(h.nS);
+    ds.full = 1;
+    memcpy(b + pk[k][C_ST], &ds, sizeof ds);
+  };
+  {
+    std::atomic<int32_t> next_h(0), next_d(0);
+    const int32_t n_dev = n - n_host;
+    unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16));
+    nth = std::min<unsigned>(nth, (unsigned)std::max(n_host, 1));
+    const unsigned ndt = (unsigned)std::min<int32_t>(n_dev, kBatchLine1DevThreads);
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth && n_host > 0; t++)
+      pool.emplace_back([&]() {
+        for (int32_t k; (k = next_h.fetch_add(1)) < n_host;) {
+          const int32_t i = ok[k];
+          HostMesh h;
+          rc[i] = host_cdt_build(pslgs[i].n_vertices, pslgs[i].xy, pslgs[i].n_segments, pslgs[i].seg, h, errs[i]);
+          if (rc[i] == GDP_OK && (h.nV != pslgs[i].n_vertices || h.nS != pslgs[i].n_segments ||
+                                  (int64_t)h.nT > 2 * (int64_t)h.nV)) {
+            rc[i] = GDP_E_DEVICE;
+            errs[i] = "initial CDT outside the batch's room";
+          }
+          if (rc[i] == GDP_OK) {
+            nT0[k] = h.nT;
+            pack(k, h);
+          }
+        }
+      });
+    for (unsigned t = 0; t < ndt; t++)
+      pool.emplace_back([&]() {
+        (void)hipSetDevice(ctx->device);
+        hipStream_t ds = nullptr;
+        DevCdtWork ws;
+        if (hipStreamCreateWithFlags(&ds, hipStreamNonBlocking) != hipSuccess) ds = nullptr;
+        for (int32_t q; (q = next_d.fetch_add(1)) < n_dev;) {
+          const int32_t k = n_host + q, i = ok[k];
+          if (!ds) {
+            rc[i] = GDP_E_DEVICE;
+            errs[i] = "stream creation failed";
+            continue;
+          }
+          rc[i] = batch_line1_device(ds, ws, pslgs[i], mesh[k], nT0[k], errs[i]);
+        }
+        if (ds) {
+          (void)hipStreamSynchronize(ds);
+          (void)hipStreamDestroy(ds);
+        }
+        dev_cdt_work_free(ws);
+      });
+    for (auto &th : pool) th.join();
+  }
+  // meshes whose Line 1 failed leave the batch (their arena room stays unused)
+  std::vector<bool> live(n, true);
   for (int32_t k = 0; k < n; k++) {
+    const int32_t i = ok[k];
+    if (rc[i] == GDP_OK) continue;
+    live[k] = false;
+    if (status) status[i] = (gdp_status)rc[i];
+    arena->refs--;
+    mesh[k]->arena = nullptr;
+    delete mesh[k];
+    mesh[k] = nullptr;
+  }
+  {
+    std::vector<CopyEnt> ents;
+    for (int32_t k = 0; k < n_host; k++) {
+      if (!live[k]) continue;
+      const gdp_mesh *M = mesh[k];
+      const int64_t nv = pslgs[ok[k]].n_vertices, ns = pslgs[ok[k]].n_segments, nt = nT0[k];
+      int32_t *dst[C_N] = {(int32_t *)M->m.vxy, (int32_t *)M->m.tv, (int32_t *)M->m.tn, (int32_t *)M->m.ts,
+                           (int32_t *)M->m.sv, M->m.spar, (int32_t *)M->d_st};
+      const int64_t sz[C_N] = {16 * nv, 16 * nt, 16 * nt, 16 * nt, 8 * ns, 4 * ns, (int64_t)sizeof(DevState)};
+      for (int c = 0; c < C_N; c++)
+        if (sz[c] > 0) ents.push_back(CopyEnt{pk[k][c], dst[c], sz[c]});
+    }
+    if (!ents.empty()) {
+      int32_t *d_pk = nullptr;
+      CopyEnt *d_ents = nullptr;
+      bool up = hipMalloc(&d_pk, pk_total) == hipSuccess &&
+                hipMalloc(&d_ents, sizeof(CopyEnt) * ents.size()) == hipSuccess &&
+                hipMemcpy(d_pk, packed.get(), pk_total, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(d_ents, ents.data(), sizeof(CopyEnt) * ents.size(), hipMemcpyHostToDevice) == hipSuccess;
+      if (up) {
+        hipLaunchKernelGGL(k_scatter_copy, dim3((unsigned)std::min<size_t>(ents.size(), 8192)), dim3(256), 0, s,
+                           d_pk, d_ents, (int)ents.size());
+        up = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+      }
+      if (d_pk) (void)hipFree(d_pk);
+      if (d_ents) (void)hipFree(d_ents);
+      if (!up) return bail(fail(ctx, GDP_E_DEVICE, "batch upload failed"));
+    }
+    packed.reset();
+  }
+  const int R_ST = (int)region.size() - 4;  // d_st (then d_hist, rhist, sel)
+  for (int32_t k = 0; k < n; k++) {
+    if (!live[k]) continue;
     gdp_mesh *M = mesh[k];
-    const HostMesh &h = hm[ok[k]];
-    const Caps &c = caps[k];
-    M->m.capV = (int32_t)c.V; M->m.capT = (int32_t)c.T; M->m.capS = (int32_t)c.S;
-    M->m.nV = h.nV; M->m.nT = h.nT; M->m.nS = h.nS;
-    M->m.n_input_v = h.nV; M->m.n_input_s = h.nS; M->m.rounds = 0;
-    M->wT = (int32_t)c.W; M->tiles_cap = (int32_t)c.tiles;
-    M->pool_cap = (int32_t)c.pool; M->fan_cap = (int32_t)c.fan;
+    const int32_t nv = pslgs[ok[k]].n_vertices, ns = pslgs[ok[k]].n_segments;
+    M->m.nV = nv; M->m.nT = nT0[k]; M->m.nS = ns;
+    M->m.n_input_v = nv; M->m.n_input_s = ns; M->m.rounds = 0;
   }
   // Meshes with more input vertices than the split run in shared rounds
   // (every phase one launch for all of them, the whole chip per round), the
@@ -1450,13 +1607,14 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   // the plain loop's.
   const int64_t split = P->batch_engine_max_v > 0 ? P->batch_engine_max_v : (int64_t)1 << 40;
   std::vector<int32_t> order, gang_k;
-  for (int32_t k = 0; k < n; k++) (hm[ok[k]].nV > split ? gang_k : order).push_back(k);
+  for (int32_t k = 0; k < n; k++)
+    if (live[k]) (pslgs[ok[k]].n_vertices > split ? gang_k : order).push_back(k);
   // Queue order.  Largest first keeps the makespan short, but the engines on
   // one XCD share its 4 MB L2, and large meshes side by side evict each
   // other's working sets (measured: each runs many times slower than alone).
   // So the largest quarter, in size order, is spread out: every fourth entry,
   // the others (largest first) in between.  The order changes no mesh.
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hm[ok[a]].nT > hm[ok[b]].nT; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return nT0[a] > nT0[b]; });
   const int32_t ne = (int32_t)order.size();
   {
     const int32_t n = ne;
@@ -1515,7 +1673,7 @@ gdp_status refine_batch(gdp_ctx *ctx, const gdp_pslg *pslgs, const double *bsq, 
   // first, at most kBatchGangMax at a time), then the engine launch
   std::vector<gdp_status> gang_st(n, GDP_OK);
   if (ok_run && !gang_k.empty()) {
-    std::stable_sort(gang_k.begin(), gang_k.end(), [&](int32_t a, int32_t b) { return hm[ok[a]].nT > hm[ok[b]].nT; });
+    std::stable_sort(gang_k.begin(), gang_k.end(), [&](int32_t a, int32_t b) { return nT0[a] > nT0[b]; });
     std::vector<GangItem> active;
     size_t next = 0;
     const int R = P->rounds_per_sync > 0 ? std::min(P->rounds_per_sync, kGangRoundsMax) : kGangRounds;
@@ -2212,28 +2370,6 @@ gdp_status job_line1_host(gdp_server *S, Job *J, std::string &e) {
   if (J->bytes > S->mem->size) {
     e = "job larger than the server's memory budget";
     return GDP_E_NOMEM;
-  }
-  return GDP_OK;
-}
-
-// The checks of the device builder's caller (gdp_mesh_create_device).
-gdp_status check_pslg_for_device(const gdp_pslg *pslg, std::string &e) {
-  const int32_t nv = pslg->n_vertices, ns = pslg->n_segments;
-  if (nv < 3 || !pslg->xy || ns < 0 || (ns > 0 && !pslg->seg)) { e = "bad arguments"; return GDP_E_ARG; }
-  if (nv > (1 << 28) - 8) { e = "mesh too large"; return GDP_E_NOMEM; }
-  for (int64_t i = 0; i < 2 * (int64_t)nv; i++) {
-    const double a = std::fabs(pslg->xy[i]);
-    if (!std::isfinite(pslg->xy[i]) || a > 0x1p20 || (a != 0.0 && a < 0x1p-100)) {
-      e = "coordinate not finite, or nonzero with magnitude outside [2^-100, 2^20]";
-      return GDP_E_INPUT;
-    }
-  }
-  for (int32_t k = 0; k < ns; k++) {
-    const int32_t a = pslg->seg[2 * k], b = pslg->seg[2 * k + 1];
-    if (a < 0 || b < 0 || a >= nv || b >= nv || a == b) {
-      e = "segment endpoint out of range or zero length";
-      return GDP_E_INPUT;
-    }
   }
   return GDP_OK;
 }

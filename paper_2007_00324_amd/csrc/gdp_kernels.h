@@ -102,6 +102,14 @@ constexpr int kQualBlocks = 512;
 __global__ void k_quality(DevMesh m, double B2, double L2, unsigned long long *n_part, double *a_part);
 __global__ void k_quality_sum(int n_part, const unsigned long long *n_in, const double *a_in,
                               unsigned long long *n_out, double *a_out);
+// Scatter of packed uploads: entry e copies bytes[e] (a multiple of 4) from
+// src + src_off[e] to dst[e], one workgroup per entry (grid-stride).
+struct CopyEnt {
+  int64_t src_off;
+  int32_t *dst;
+  int64_t bytes;
+};
+__global__ void k_scatter_copy(const int32_t *src, const CopyEnt *ents, int n);
 
 // The exact predicates on a list of queries (kind 0 orient2d, 1 incircle,
 // 2 indiametral, 3 lens encroachment; 6 or 8 doubles per query).

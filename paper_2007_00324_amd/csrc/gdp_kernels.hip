@@ -2255,6 +2255,15 @@ __global__ __launch_bounds__(256) void k_quality(DevMesh m, double B2, double L2
   }
 }
 
+__global__ void k_scatter_copy(const int32_t *src, const CopyEnt *ents, int n) {
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const CopyEnt c = ents[e];
+    const int32_t *a = src + c.src_off / 4;
+    const int64_t words = c.bytes / 4;
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) c.dst[i] = a[i];
+  }
+}
+
 __global__ void k_quality_sum(int n_part, const unsigned long long *n_in, const double *a_in,
                               unsigned long long *n_out, double *a_out) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;

@@ -43,7 +43,8 @@ class gdp_params(C.Structure):
                 ("profile_kernels", C.c_int32), ("reserve_mode", C.c_int32), ("rounds_per_sync", C.c_int32),
                 ("tail_engine_max", C.c_int32), ("encroach_mode", C.c_int32), ("split_mode", C.c_int32),
                 ("max_edge_len_sq", C.c_double), ("batch_engine_max_v", C.c_int32),
-                ("cavity_thread_cap", C.c_int32), ("insert_mode", C.c_int32)]
+                ("cavity_thread_cap", C.c_int32), ("insert_mode", C.c_int32),
+                ("batch_line1_device_min_v", C.c_int32)]
 
 
 class gdp_kernel_prof(C.Structure):
@@ -165,9 +166,11 @@ def _pslg(xy, seg):
 def make_params(cand_cap_K=0, priority_mode=0, max_rounds=0, block_size=256, profile_kernels=0,
                 prefilter_f1=0, cavity_approx_n=0, reserve_mode=0, rounds_per_sync=0,
                 tail_engine_max=0, encroach_mode=0, max_edge_len_sq=0.0, split_mode=0,
-                batch_engine_max_v=0, cavity_thread_cap=0, insert_mode=0) -> gdp_params:
+                batch_engine_max_v=0, cavity_thread_cap=0, insert_mode=0,
+                batch_line1_device_min_v=0) -> gdp_params:
     p = gdp_params()
     load().gdp_params_default(C.byref(p))
+    p.batch_line1_device_min_v = batch_line1_device_min_v
     p.insert_mode = insert_mode
     p.batch_engine_max_v = batch_engine_max_v
     p.cavity_thread_cap = cavity_thread_cap

@@ -105,3 +105,36 @@ def test_batch_split_between_engine_and_shared_rounds(ctx, split):
         assert not diff_arrays(om.arrays(), g.arrays()), p.name
         assert g.info()["rounds"] == om.rounds
         assert not diff_stats(om.stats[:64], g.round_stats()), p.name
+
+
+@pytest.mark.parametrize("dev_min,split", [(1000, 0), (3, 0), (1500, 800)])
+def test_batch_line1_on_device(ctx, dev_min, split):
+    """Inputs of at least dev_min vertices get their initial CDT from the
+    device builder (into the batch's arena), the rest from host threads:
+    every mesh is still the oracle's, also with members in shared rounds."""
+    ps = workloads.batch_config3(24, seed=17, n_min=100, n_max=4000)
+    print(f"[batch] Line 1 on the device from {dev_min} vertices, split {split}", flush=True)
+    meshes, st, _ = _batch(ctx, ps, batch_line1_device_min_v=dev_min, batch_engine_max_v=split)
+    assert all(s == 0 for s in st), st
+    assert any(p.n_vertices >= dev_min for p in ps)
+    for p, g in zip(ps, meshes):
+        om, rc = oracle_run(p)
+        assert not diff_arrays(om.arrays(), g.arrays()), p.name
+        assert g.info()["rounds"] == om.rounds
+
+
+def test_batch_line1_on_device_invalid_member(ctx):
+    """An invalid PSLG among device-built members fails alone (GDP_E_INPUT)."""
+    from paper_2007_00324_amd import gdp2d
+    ps = workloads.batch_config3(4, seed=18, n_min=100, n_max=500)
+    sq = workloads.bare_square()
+    xy = np.vstack([sq.xy, [[0.25, 0.25], [0.75, 0.75], [0.25, 0.75], [0.75, 0.25]]])
+    seg = np.vstack([sq.seg, [[4, 5], [6, 7]]]).astype(np.int32)  # crossing segments
+    inputs = [(xy, seg)] + [(p.xy, p.seg) for p in ps]
+    meshes, st, _ = gdp2d.gdp_refine_batch(ctx, inputs, [2.0] + [p.ratio_bound_sq for p in ps],
+                                           gdp2d.make_params(batch_line1_device_min_v=3))
+    assert st[0] == -2 and meshes[0] is None
+    assert all(s == 0 for s in st[1:])
+    for p, g in zip(ps, meshes[1:]):
+        om, _ = oracle_run(p)
+        assert not diff_arrays(om.arrays(), g.arrays())
