@@ -553,6 +553,68 @@ def serving_line1_leg(ctx, jobs, budget_gb: float, slots: int, dev_min_v: int, r
             "settings": rows}
 
 
+def serving_full_leg(count: int, rates: list, budget_gb: float, slots: int, dev_min_v: int) -> dict:
+    """The serving workload at its full size: count jobs (the 20,000-job set by
+    default) replayed as one Poisson stream per rate, Line 1 in the server
+    (host threads, the device builder from dev_min_v input vertices), latency
+    from the PSLG's arrival.  Progress lines every 1,000 jobs."""
+    import multiprocessing as mp
+    import threading
+    import numpy as np
+    from workloads import generators as G
+    from paper_2007_00324_amd import gdp2d
+    t0 = time.perf_counter()
+    n, bsq, seeds = G.serving_plan(count, 4, 1_000, 200_000)
+    args = list(zip(n.tolist(), bsq.tolist(), seeds.tolist()))
+    jobs = []
+    with mp.get_context("fork").Pool(16) as pool:
+        for k, p in enumerate(pool.imap(G._serving_job_args, args, chunksize=4)):
+            jobs.append(p)
+            if (k + 1) % 1000 == 0:
+                log(f"serving (full): generated {k + 1:,} jobs in {time.perf_counter() - t0:.0f} s")
+    ctx = gdp2d.Context(0)
+    out = {"workload": (f"{count:,} jobs: the 1M-point generator scaled to log-uniform 1,000..200,000 points, "
+                        "segments 5% of the points, B^2 drawn from {2.0, 2.56, 4.0}; one Poisson stream per rate; "
+                        f"Line 1 in the server (16 host threads, the device builder from {dev_min_v:,} vertices); "
+                        "latency from the arrival of the PSLG"),
+           "jobs": count, "input_vertices": sum(p.n_vertices for p in jobs), "rates": []}
+    for rate in rates:
+        srv = gdp2d.Server(ctx, int(budget_gb * (1 << 30)), slots, engine_max_vertices=0, line1=(16, dev_min_v))
+        ids = [srv.prepare(p.xy, p.seg, p.ratio_bound_sq) for p in jobs]
+        gaps = np.random.default_rng(7).exponential(1.0 / rate, size=count)
+        res = [None] * count
+
+        def collect():
+            for k, j in enumerate(ids):
+                m, rc, t = srv.wait(j)
+                res[k] = (rc, t)
+                if m is not None:
+                    m.free()
+                if (k + 1) % 1000 == 0:
+                    log(f"serving (full) at {rate:g}/s: {k + 1:,} jobs done")
+        th = threading.Thread(target=collect)
+        th.start()
+        ts = time.perf_counter()
+        due = 0.0
+        for k, j in enumerate(ids):
+            due += gaps[k]
+            while time.perf_counter() - ts < due:
+                time.sleep(min(0.0005, max(0.0, due - (time.perf_counter() - ts))))
+            srv.arrive(j)
+        th.join()
+        srv.close()
+        lat = np.array([t["done_ms"] - t["submit_ms"] for _, t in res])
+        l1 = np.array([t["line1_ms"] - t["submit_ms"] for _, t in res])
+        span = (max(t["done_ms"] for _, t in res) - min(t["submit_ms"] for _, t in res)) / 1000.0
+        row = {"rate_jobs_per_s": rate, "achieved_jobs_per_s": count / span, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "line1_mean_ms": float(l1.mean()),
+               "failed": int(sum(1 for rc, _ in res if rc != 0))}
+        log(f"serving (full) at {rate:g}/s: p50 {row['p50_ms']:.0f} ms, p99 {row['p99_ms']:.0f} ms, "
+            f"{row['achieved_jobs_per_s']:.1f} jobs/s, {row['failed']} not OK")
+        out["rates"].append(row)
+    return out
+
+
 def serving_leg(ctx, jobs, rates, budget_gb: float, slots: int, plain_every: int, engine_max_v=None,
                 mode: int = 0) -> dict:
     """Serving form: the same job set replayed as a Poisson stream at each
@@ -640,6 +702,9 @@ def main() -> int:
                     help="only measure the serving capacity for slots:rounds pairs (e.g. 16:2,32:4) and exit")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-full-jobs", type=int, default=0,
+                    help="only run the serving workload at full size (e.g. 20000 jobs) at --serve-full-rates, and exit")
+    ap.add_argument("--serve-full-rates", type=str, default="50", help="arrival rates (jobs/s) of the full stream")
     ap.add_argument("--serve-line1-device-min", type=int, default=100000,
                     help="serving with Line 1 in the server: device builder from this many input vertices (0: skip)")
     ap.add_argument("--serve-engine-max", type=int, default=None,
@@ -655,6 +720,13 @@ def main() -> int:
     ap.add_argument("--points", type=int, default=1_000_000, help=argparse.SUPPRESS)
     ap.add_argument("--segments", type=int, default=50_000, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.serve_full_jobs > 0:
+        import torch  # noqa: F401
+        rates = [float(r) for r in args.serve_full_rates.split(",") if r]
+        r = serving_full_leg(args.serve_full_jobs, rates, args.serve_budget_gb, args.serve_slots,
+                             args.serve_line1_device_min)
+        print(json.dumps({"serving_full": r}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the refinement loop of one PSLG runs on a "
               "single device, it would shard by instance or by spatial blocks.", file=sys.stderr)
