@@ -138,3 +138,16 @@ def test_batch_line1_on_device_invalid_member(ctx):
     for p, g in zip(ps, meshes[1:]):
         om, _ = oracle_run(p)
         assert not diff_arrays(om.arrays(), g.arrays())
+
+
+def test_batch_line1_on_device_cocircular(ctx):
+    """Device Line 1 in the batch for a rounded-cocircular polygon (large
+    builder cavities) next to ordinary inputs built on the host."""
+    ps = [workloads.scaled_config2(1, 6000, 0, seed=7, r_lo=0.40, r_hi=0.45)]
+    ps += workloads.batch_config3(6, seed=19, n_min=100, n_max=2000)
+    meshes, st, _ = _batch(ctx, ps, batch_line1_device_min_v=5000)
+    assert all(s == 0 for s in st), st
+    for p, g in zip(ps, meshes):
+        om, rc = oracle_run(p)
+        assert rc == 0
+        assert not diff_arrays(om.arrays(), g.arrays()), p.name

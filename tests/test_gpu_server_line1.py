@@ -124,3 +124,23 @@ def test_line1_set_before_first_job(ctx):
     m, rc, _ = srv.wait(j)
     assert rc == 0
     srv.close()
+
+
+def test_line1_device_cocircular_jobs(ctx):
+    """Line 1 on the device inside the server for rounded-cocircular polygons
+    (cavities far beyond the builder's per-thread lists), two of them in a
+    row on the same builder workspace, among ordinary jobs."""
+    from paper_2007_00324_amd import gdp2d
+    ps = [workloads.scaled_config2(1, 6000, 0, seed=s, r_lo=0.40, r_hi=0.45) for s in (7, 8)]
+    ps += _jobs(4, seed=36)
+    srv = gdp2d.Server(ctx, 2 << 30, 4, engine_max_vertices=0, line1=(2, 5000))
+    ids = [srv.submit(p.xy, p.seg, p.ratio_bound_sq) for p in ps]
+    print(f"[line1 cocircular] {len(ids)} jobs submitted", flush=True)
+    for p, j in zip(ps, ids):
+        m, rc, _ = srv.wait(j)
+        assert rc == 0 and m is not None, (p.name, rc)
+        om, orc = oracle_run(p)
+        assert orc == 0
+        assert not diff_arrays(om.arrays(), m.arrays()), p.name
+        m.free()
+    srv.close()
