@@ -83,3 +83,14 @@ def test_host_cdt_rejects_invalid_input(kind):
     with pytest.raises(gdp2d.GdpError) as e:
         gdp2d.gdp_cdt_host(xy, seg)
     assert e.value.code == -2
+
+
+def test_server_calls_reject_a_missing_server():
+    """Argument checks that need no device: a NULL server is GDP_E_ARG."""
+    import ctypes as C
+    from paper_2007_00324_amd import gdp2d
+    lib = gdp2d.load()
+    assert lib.gdp_server_line1(None, 4, 0) == -1
+    assert lib.gdp_server_mode(None, 0, 0) == -1
+    assert lib.gdp_server_engine_jobs(None, 0) == -1
+    assert lib.gdp_server_arrive(None, C.c_uint64(1)) == -1
