@@ -370,6 +370,11 @@ gdp_status grow_cand(gdp_mesh *M) {
 
 constexpr int kHistCap = 64;  // rounds queued between two host synchronisations, at most
 constexpr int64_t kEngineDefaultMax = 1024;  // candidates per round run by the single-workgroup engine
+// The engine grows its large (cooperative) cavities one after the other, the
+// grid kernels side by side: a mesh whose last round had more of them stays
+// on the grid kernels for the next round (rounded-cocircular inputs give
+// hundreds per round; perf only, the rounds are the same either way).
+constexpr int64_t kEngineBigMax = 8;
 
 // Workspace pointers of a round; the two list buffers swap roles with the
 // parity of the round's serial.
@@ -2918,13 +2923,14 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
   // previous bad list over and re-test only the slots the last round wrote.
   bool full = true;
   int64_t last_cand = (int64_t)m.nT + m.nS;
+  int64_t last_big = 0;  // cooperative cavities of the last round
   int64_t prev_ncc = 0, prev_nmk = 0, prev_fan = 0;
   int aborts = 0;
   if (P->insert_mode == 1) result = ff_loop(M, B2, P);
   else for (;;) {
     // small rounds run in the single-workgroup engine
     const int64_t eng_max = P->tail_engine_max == 0 ? kEngineDefaultMax : P->tail_engine_max;
-    const bool engine = !full && !M->engine_off && eng_max > 0 && last_cand <= eng_max;
+    const bool engine = !full && !M->engine_off && eng_max > 0 && last_cand <= eng_max && last_big <= kEngineBigMax;
     const int R = full ? 1 : rounds_for(P, last_cand, engine);
     gdp_status st;
     if (P->reserve_mode == 0 && !full && (st = reserve_group(M, last_cand, engine ? 4 : R))) return st;
@@ -2972,6 +2978,7 @@ gdp_status refine_loop(gdp_mesh *M, double B2, const gdp_params *P) {
       const DevCounters &c = M->h_hist[i];
       M->stats.push_back(round_stats_of(c, P));
       last_cand = (int64_t)c.ncc + c.nmk;
+      last_big = c.nbig;
       prev_ncc = c.ncc;
       prev_nmk = c.nmk;
       prev_fan = c.fan_used;
